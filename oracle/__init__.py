@@ -1,0 +1,359 @@
+"""CPU oracle for the deviational phonon Monte Carlo tracer -- test infrastructure.
+
+The arithmetic lives in ``mcbte_oracle.c`` (plain FP64 C, one particle at a time,
+built with ``-ffp-contract=off``).  This module builds that file with gcc, marshals the
+workload descriptions of :mod:`workloads` into the oracle's own structs, runs particle
+ranges (optionally split over threads, each range with its own tally arrays, summed in
+range order) and normalises the raw sums into temperatures, fluxes and kappa.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mcbte_oracle.c")
+_HDR = os.path.join(_HERE, "mcbte_oracle.h")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+N_COUNTS = 16
+COUNT_NAMES = ["particles", "flights", "relaxations", "specular", "diffuse", "periodic", "absorbed",
+               "timeouts", "nscat_end", "cap_end", "escaped", "rejections"]
+EV_NAMES = {0: "emit+", 1: "relax", 2: "specular", 3: "diffuse", 4: "periodic", 5: "absorb",
+            6: "timeout", 7: "nscat_end", 8: "cap_end", 9: "emit-", 10: "escape"}
+
+
+class Mode(C.Structure):
+    _fields_ = [("omega", C.c_double), ("dos", C.c_double), ("v", C.c_double), ("domega", C.c_double),
+                ("tau", C.c_double), ("C", C.c_double), ("tau_imp", C.c_double),
+                ("bin", C.c_int32), ("branch", C.c_int32)]
+
+
+class Face(C.Structure):
+    _fields_ = [("type", C.c_int32), ("pad", C.c_int32), ("data", C.c_double * 3)]
+
+
+class Cyl(C.Structure):
+    _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("r", C.c_double), ("id", C.c_int32),
+                ("type", C.c_int32), ("spec", C.c_double)]
+
+
+class Geom(C.Structure):
+    _fields_ = [("L", C.c_double * 3), ("unbounded", C.c_int32 * 3), ("n_cyl", C.c_int32),
+                ("face", Face * 6), ("cyl", Cyl * 8), ("gradT", C.c_double * 3), ("volume", C.c_double)]
+
+
+class Det(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("n", C.c_int32 * 3), ("mask", C.c_int32)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("N", C.c_int64), ("max_events", C.c_int64), ("T_lin", C.c_double), ("t_max", C.c_double),
+                ("n_scat_max", C.c_int32), ("format", C.c_int32), ("transient", C.c_int32),
+                ("score_axis", C.c_int32), ("n_times", C.c_int32), ("ic_axis", C.c_int32),
+                ("n_ic", C.c_int32), ("pad", C.c_int32),
+                ("t_meas", C.POINTER(C.c_double)), ("ic_edges", C.POINTER(C.c_double)),
+                ("ic_dT", C.POINTER(C.c_double))]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain FP64: no contraction, no fast-math)."""
+    with _lock:
+        stale = (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)
+                 or os.path.getmtime(_LIB) < os.path.getmtime(_HDR))
+        if force or stale:
+            tmp = _LIB + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                                   "-shared", "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        p = C.c_void_p
+        L.orc_build.argtypes = [C.POINTER(Mode), C.c_int32, C.POINTER(Geom), C.POINTER(Det), C.POINTER(Problem),
+                                C.POINTER(p)]
+        L.orc_build.restype = C.c_int
+        L.orc_free.argtypes = [p]
+        L.orc_info.argtypes = [p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.orc_get.argtypes = [p, C.c_int32, p, C.c_int64]
+        L.orc_get.restype = C.c_int
+        L.orc_trace.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, p, p, p, p, C.c_int64, C.c_int32]
+        L.orc_trace.restype = C.c_int
+        L.orc_philox4x32_10.argtypes = [p, p, p]
+        L.orc_record.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_uint32, p]
+        L.orc_cdf_pick.argtypes = [p, C.c_int64, C.c_int64, C.c_uint64]
+        L.orc_cdf_pick.restype = C.c_int64
+        L.orc_cdf_build.argtypes = [p, C.c_int64, p, p]
+        L.orc_dir_iso.argtypes = [C.c_double, C.c_double, p]
+        L.orc_dir_cos.argtypes = [C.c_double, C.c_double, p, p]
+        L.orc_dedT.argtypes = [C.c_double, C.c_double]
+        L.orc_dedT.restype = C.c_double
+        L.orc_tally_segment.argtypes = [p, p, p, C.c_double, C.c_int32, C.c_double, p]
+        L.orc_next_boundary.argtypes = [p, p, p, p]
+        L.orc_next_boundary.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ----------------------------------------------------------------------------------------------
+# building blocks (exposed for the pins)
+# ----------------------------------------------------------------------------------------------
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def record(seed: int, instance: int, pid: int, rec: int) -> np.ndarray:
+    out = np.zeros(8, dtype=np.uint32)
+    lib().orc_record(seed, instance, pid, rec, _ptr(out))
+    return out
+
+
+def cdf_build(w) -> tuple[np.ndarray, int]:
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    thr = np.zeros(len(w), dtype=np.uint64)
+    last = np.zeros(1, dtype=np.int64)
+    lib().orc_cdf_build(_ptr(w), len(w), _ptr(thr), _ptr(last))
+    return thr, int(last[0])
+
+
+def cdf_pick(thr: np.ndarray, last: int, K: int) -> int:
+    thr = np.ascontiguousarray(thr, dtype=np.uint64)
+    return int(lib().orc_cdf_pick(_ptr(thr), len(thr), last, K))
+
+
+def dir_iso(u1: float, u2: float) -> np.ndarray:
+    out = np.zeros(3)
+    lib().orc_dir_iso(u1, u2, _ptr(out))
+    return out
+
+
+def dir_cos(u1: float, u2: float, n) -> np.ndarray:
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_dir_cos(u1, u2, _ptr(n), _ptr(out))
+    return out
+
+
+def dedT(omega: float, T: float) -> float:
+    return lib().orc_dedT(omega, T)
+
+
+# ----------------------------------------------------------------------------------------------
+# problem tables
+# ----------------------------------------------------------------------------------------------
+
+class Tables:
+    """The oracle's tables for one workload (see ``orc_build``)."""
+
+    def __init__(self, w: dict):
+        L = lib()
+        self.w = w
+        modes = np.ascontiguousarray(w["modes"])
+        self._modes = (Mode * len(modes))()
+        for i, r in enumerate(modes):
+            self._modes[i] = Mode(float(r["omega"]), float(r["dos"]), float(r["v"]), float(r["domega"]),
+                                  float(r["tau"]), float(r["C"]), float(r["tau_imp"]), int(r["bin"]),
+                                  int(r["branch"]))
+        g = w["geometry"]
+        G = Geom()
+        for a in range(3):
+            G.L[a] = g["L"][a]
+            G.unbounded[a] = int(g["unbounded"][a])
+            G.gradT[a] = g["gradT"][a]
+        for fid, (ty, d0, d1, d2) in g["faces"].items():
+            G.face[fid - 1].type = int(ty)
+            G.face[fid - 1].data[0], G.face[fid - 1].data[1], G.face[fid - 1].data[2] = d0, d1, d2
+        G.n_cyl = len(g["cylinders"])
+        for i, (cx, cy, r, cid, ty, spec) in enumerate(g["cylinders"]):
+            G.cyl[i] = Cyl(cx, cy, r, int(cid), int(ty), spec)
+        G.volume = g["volume"]
+        self._geom = G
+        d = w["detectors"]
+        D = Det()
+        for a in range(3):
+            D.lo[a], D.hi[a], D.n[a] = d["lo"][a], d["hi"][a], d["n"][a]
+        D.mask = d["mask"]
+        self._det = D
+        p = w["problem"]
+        self._t_meas = np.ascontiguousarray(p["t_meas"], dtype=np.float64)
+        self._ic_edges = np.ascontiguousarray(p["ic_edges"], dtype=np.float64)
+        self._ic_dT = np.ascontiguousarray(p["ic_dT"], dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        P = Problem(p["N"], p["max_events"], p["T_lin"], p["t_max"], p["n_scat_max"], p["format"],
+                    int(p["transient"]), p["score_axis"], len(self._t_meas) if p["transient"] else 0,
+                    p["ic_axis"], len(self._ic_dT), 0,
+                    self._t_meas.ctypes.data_as(dp), self._ic_edges.ctypes.data_as(dp),
+                    self._ic_dT.ctypes.data_as(dp))
+        self._prob = P
+        h = C.c_void_p()
+        rc = L.orc_build(self._modes, len(modes), C.byref(G), C.byref(D), C.byref(P), C.byref(h))
+        if rc != 0:
+            raise ValueError(f"oracle table build failed with status {rc}")
+        self.h = h
+        dd = (C.c_double * 6)()
+        ii = (C.c_int64 * 4)()
+        L.orc_info(h, dd, ii)
+        self.C_tot, self.Wv, self.e_eff, self.V_solid, self.E_tot, self.kappa_bulk = list(dd)
+        self.M, self.S, self.n_cells, self.n_cols = list(ii)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_free(self.h)
+            self.h = None
+
+    def get(self, which: str) -> np.ndarray:
+        code, n, dt = {"C": (0, self.M, np.float64), "thr_ic": (1, self.M, np.uint64),
+                       "thr_wall": (2, self.M, np.uint64), "thr_rel": (3, self.M, np.uint64),
+                       "src_E": (4, self.S, np.float64), "thr_src": (5, self.S, np.uint64),
+                       "src_sign": (6, self.S, np.int32), "last": (7, 4, np.int64)}[which]
+        out = np.zeros(n, dtype=dt)
+        if lib().orc_get(self.h, code, _ptr(out), n) != 0:
+            raise ValueError(which)
+        return out
+
+    @property
+    def raw_size(self) -> int:
+        return self.n_cells * self.n_cols * 4
+
+    def trace_range(self, seed: int, instance: int, first_pid: int, n: int, n_log: int = 0, log_stride: int = 64):
+        raw = np.zeros(self.raw_size)
+        counts = np.zeros(N_COUNTS, dtype=np.uint64)
+        mom = np.zeros(4)
+        log = np.zeros((max(n_log, 0), log_stride), dtype=np.uint32)
+        rc = lib().orc_trace(self.h, seed, instance, first_pid, n, _ptr(raw), _ptr(counts), _ptr(mom),
+                             _ptr(log) if n_log > 0 else None, n_log, log_stride)
+        if rc != 0:
+            raise ValueError(f"oracle trace failed with status {rc}")
+        return raw, counts, mom, log
+
+    def next_boundary(self, x, o) -> tuple[float, int]:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        o = np.ascontiguousarray(o, dtype=np.float64)
+        hit = np.zeros(1, dtype=np.int32)
+        d = lib().orc_next_boundary(self.h, _ptr(x), _ptr(o), _ptr(hit))
+        return d, int(hit[0])
+
+    def segment(self, x0, o, d, m, s=1.0) -> np.ndarray:
+        raw = np.zeros(self.raw_size)
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        o = np.ascontiguousarray(o, dtype=np.float64)
+        lib().orc_tally_segment(self.h, _ptr(x0), _ptr(o), float(d), int(m), float(s), _ptr(raw))
+        return raw
+
+
+def trace(w: dict, n: int | None = None, first_pid: int = 0, threads: int = 1, n_log: int = 0,
+          log_stride: int = 64, tables: Tables | None = None, instance: int | None = None) -> dict:
+    """Trace particles [first_pid, first_pid + n) of workload w; returns the raw sums."""
+    tb = tables or Tables(w)
+    n = w["problem"]["N"] if n is None else int(n)
+    inst = int(w.get("instance", 0) if instance is None else instance)
+    threads = max(1, min(int(threads), n)) if n > 0 else 1
+    bounds = [first_pid + (n * i) // threads for i in range(threads + 1)]
+
+    def one(i):
+        lo, hi = bounds[i], bounds[i + 1]
+        nl = max(0, min(n_log - (lo - first_pid), hi - lo))
+        return tb.trace_range(int(w["seed"]), inst, lo, hi - lo, nl, log_stride)
+
+    if threads == 1:
+        parts = [one(0)]
+    else:
+        with ThreadPoolExecutor(threads) as ex:
+            parts = list(ex.map(one, range(threads)))
+    raw = np.zeros(tb.raw_size)
+    counts = np.zeros(N_COUNTS, dtype=np.uint64)
+    mom = np.zeros(4)
+    logs = []
+    for r, c, m, lg in parts:        # fixed range order
+        raw += r
+        counts += c
+        mom += m
+        logs.append(lg)
+    log = np.concatenate(logs, axis=0) if logs else np.zeros((0, log_stride), np.uint32)
+    return {"raw": raw, "counts": counts, "moments": mom, "log": log[:max(n_log, 0)], "tables": tb}
+
+
+def finalize(res: dict) -> dict:
+    """Raw sums -> deviational temperature and heat flux per detector (section 3.4 for transient
+    snapshots, section 3.6 for steady track lengths), kappa and its standard error."""
+    tb: Tables = res["tables"]
+    w = tb.w
+    raw = res["raw"].reshape(tb.n_cells, tb.n_cols, 4)
+    n = int(res["counts"][0])
+    e = tb.E_tot / n                                  # effective energy (rate) per particle
+    det, g = w["detectors"], w["geometry"]
+    if all(k == 0 for k in det["n"]):
+        Vc = tb.V_solid
+    else:
+        Vc = 1.0
+        for a in range(3):
+            if det["n"][a] > 0:
+                Vc *= (det["hi"][a] - det["lo"][a]) / det["n"][a]
+            elif not g["unbounded"][a]:
+                Vc *= g["L"][a]
+    out = {"T": e / (tb.C_tot * Vc) * raw[..., 0], "q": e / Vc * raw[..., 1:], "e_eff": e, "V_cell": Vc,
+           "counts": dict(zip(COUNT_NAMES, [int(x) for x in res["counts"][:len(COUNT_NAMES)]]))}
+    if not w["problem"]["transient"] and n > 1:
+        m = res["moments"]
+        sa = w["problem"]["score_axis"]
+        var_q = max(m[3] - m[2] * m[2] / n, 0.0) / (n - 1)
+        var_T = max(m[1] - m[0] * m[0] / n, 0.0) / (n - 1)
+        out["q_score"] = tb.E_tot / tb.V_solid * m[2] / n
+        out["q_score_sigma"] = tb.E_tot / tb.V_solid * np.sqrt(var_q / n)
+        out["T_mean"] = tb.E_tot / (tb.C_tot * tb.V_solid) * m[0] / n
+        out["T_mean_sigma"] = tb.E_tot / (tb.C_tot * tb.V_solid) * np.sqrt(var_T / n)
+        gs = g["gradT"][sa]
+        if gs != 0.0:
+            out["kappa"] = -out["q_score"] / gs
+            out["kappa_sigma"] = out["q_score_sigma"] / abs(gs)
+            out["kappa_cell_avg"] = out["kappa"] * tb.V_solid / (np.prod([g["L"][a] if not g["unbounded"][a]
+                                                                          else 1.0 for a in range(3)]))
+    return out
+
+
+def run(w: dict, n: int | None = None, threads: int = 1, **kw) -> dict:
+    res = trace(w, n=n, threads=threads, **kw)
+    res.update(finalize(res))
+    return res
+
+
+def run_batches(w: dict, n_batches: int, n: int | None = None, threads: int = 8) -> list[dict]:
+    """Split particles [0, n) into n_batches contiguous ranges; finalize each range on its own
+    (batch means give the statistical error of binned tallies)."""
+    tb = Tables(w)
+    n = w["problem"]["N"] if n is None else int(n)
+    bounds = [(n * i) // n_batches for i in range(n_batches + 1)]
+    inst = int(w.get("instance", 0))
+
+    def one(i):
+        raw, counts, mom, _ = tb.trace_range(int(w["seed"]), inst, bounds[i], bounds[i + 1] - bounds[i])
+        res = {"raw": raw, "counts": counts, "moments": mom, "tables": tb}
+        res.update(finalize(res))
+        return res
+
+    with ThreadPoolExecutor(max(1, min(threads, n_batches))) as ex:
+        return list(ex.map(one, range(n_batches)))

@@ -1,0 +1,277 @@
+"""Whole-run pins of the CPU oracle against closed forms and exact invariants (no GPU).
+
+Statistical pins use 3-sigma bounds (sigma from per-particle moments or from batch means
+over contiguous particle ranges) plus, where a deterministic reference carries its own
+discretisation error, that error stated next to the bound.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+import oracle
+import workloads as W
+
+THREADS = 8
+NB = 64          # batch means for binned tallies
+
+
+def assert_bins_agree(batches_vals, ref, sys_err=0.0, family_alpha=1e-3):
+    """Batch-mean check of binned tallies against a reference.
+
+    z = |mean - ref| / (se + sys_err) follows Student-t with NB - 1 degrees of freedom; every
+    bin must lie below the two-sided quantile at family-wise level family_alpha, and the mean of
+    z^2 below its expectation nu/(nu-2) plus 4 standard errors.  Bins where no batch saw any
+    particle (se = 0) must match the reference to rounding."""
+    from scipy import stats
+    vals = np.asarray(batches_vals)
+    nb = vals.shape[0]
+    mean = vals.mean(0)
+    se = vals.std(0, ddof=1) / math.sqrt(nb)
+    ref = np.broadcast_to(ref, mean.shape)
+    ok = (se > 0)
+    assert np.all(np.abs(mean[~ok] - ref[~ok]) <= 1e-12 + sys_err), "empty bins disagree"
+    z = np.abs(mean - ref)[ok] / (se[ok] + sys_err)
+    nu = nb - 1
+    thr = stats.t.ppf(1.0 - family_alpha / (2.0 * max(z.size, 1)), nu)
+    assert np.all(z < thr), (z.max(), thr)
+    ez2 = nu / (nu - 2.0)
+    var_z2 = 2.0 * ez2 ** 2 * (nu - 1.0) / (nu - 4.0)
+    assert np.mean(z ** 2) < ez2 + 4.0 * math.sqrt(var_z2 / z.size), np.mean(z ** 2)
+
+
+def test_ballistic_slab_flux_is_deterministic():
+    """tau -> infinity: every wall particle crosses the slab once and contributes exactly L to
+    sum s l_z, so q_z = (|dT_hot| + |dT_cold|) C v / 4 to rounding (walls at 301 / 299 K)."""
+    w = W.gray_slab(N=20000)
+    w["modes"]["tau"][0] = 1.0
+    r = oracle.run(w, threads=THREADS)
+    C, v = 1e6, 6400.0
+    assert r["counts"]["relaxations"] == 0
+    assert r["counts"]["absorbed"] == 20000
+    assert r["q_score"] == pytest.approx(2.0 * C * v / 4.0, rel=1e-12)
+    assert r["q_score_sigma"] < 1e-10 * r["q_score"]
+    # per-bin: both walls superpose; the binned flux equals the same constant in every bin
+    qz = r["q"][:, 0, 2]
+    assert np.allclose(qz, 2.0 * C * v / 4.0, rtol=1e-11)
+
+
+def test_ballistic_single_wall_temperature_is_half():
+    """One emitting wall (the other held at T_lin): the ballistic steady temperature is dT/2
+    everywhere (linearised ballistic limit)."""
+    w = W.gray_slab(N=40000)
+    w["modes"]["tau"][0] = 1.0
+    w["geometry"]["faces"][6] = (W.ISOTHERMAL, 300.0, 0, 0)
+    batches = oracle.run_batches(w, NB, threads=THREADS)
+    assert_bins_agree([b["T"][:, 0] for b in batches], 0.5)
+
+
+@pytest.mark.parametrize("tau_L", [1.0, 0.25])
+def test_gray_slab_matches_integral_equation(tau_L):
+    """Gray slab between black walls (301 / 299 K): flux Psi and the temperature profile against
+    the product-integration solution of the E1-kernel integral equation."""
+    L = 100e-9
+    N = 100000
+    w = W.gray_slab(N=N, Lambda=L / tau_L)
+    t, phi, Psi = cf.gray_slab_integral_equation(tau_L, 2000)
+    _, _, Psi2 = cf.gray_slab_integral_equation(tau_L, 1000)
+    disc = abs(Psi - Psi2)                          # discretisation error of the reference
+    r = oracle.run(w, threads=THREADS)
+    q_ref = Psi * 1e6 * 6400.0 * 2.0 / 4.0
+    assert abs(r["q_score"] - q_ref) < 3.0 * r["q_score_sigma"] + disc * q_ref
+    # profile: T(z) = 2 phi(z / Lambda) - 1, averaged over the 50 detector bins
+    nb = w["detectors"]["n"][2]
+    ref = (2.0 * phi - 1.0).reshape(nb, -1).mean(1)
+    batches = oracle.run_batches(w, NB, n=N, threads=THREADS)
+    assert_bins_agree([b["T"][:, 0] for b in batches], ref, sys_err=1e-4)
+
+
+def test_gradient_source_gives_kinetic_bulk_kappa_gray():
+    """Unbounded gray bulk under the spatially varying control: kappa = C v^2 tau / 3 (this
+    pins the factor 1/2 of the gradient source and the sign convention of its particles)."""
+    for nsm in (1, 5):
+        w = W.bulk_gradient(N=200000, n_scat_max=nsm)
+        r = oracle.run(w, threads=THREADS)
+        k_ref = 1e6 * 6400.0 ** 2 * (100e-9 / 6400.0) / 3.0
+        assert abs(r["kappa"] - k_ref) < 3.0 * r["kappa_sigma"], (nsm, r["kappa"], r["kappa_sigma"])
+        # single flight: per-particle score c = l mu with l ~ Exp(Lambda), mu ~ 2 mu dmu
+        # -> coefficient of variation sqrt(5)/2
+        if nsm == 1:
+            cv = r["kappa_sigma"] * math.sqrt(200000) / r["kappa"]
+            assert cv == pytest.approx(math.sqrt(5) / 2, rel=0.03)
+
+
+def test_gradient_source_gives_kinetic_bulk_kappa_dispersive():
+    """Frequency-dependent bulk: kappa = (1/3) sum_m C_m v_m^2 tau_m."""
+    w = W.bulk_gradient(N=300000, n_scat_max=1, modes=W.silicon_like_modes(300.0))
+    r = oracle.run(w, threads=THREADS)
+    k_ref = r["tables"].kappa_bulk
+    assert abs(r["kappa"] - k_ref) < 3.0 * r["kappa_sigma"], (r["kappa"], r["kappa_sigma"], k_ref)
+
+
+def test_thin_film_matches_fuchs_sondheimer():
+    """Diffuse-walled film, in-plane gradient: kappa = sum_m kappa_m S(d / Lambda_m)."""
+    for d in (100e-9, 20e-9):
+        w = W.film(N=150000, d=d)
+        r = oracle.run(w, threads=THREADS)
+        tb = r["tables"]
+        C = tb.get("C")
+        m = w["modes"]
+        lam = m["v"] * m["tau"]
+        k_fs = sum(C[i] * m["v"][i] ** 2 * m["tau"][i] / 3.0 * cf.fs_suppression(d / lam[i]) for i in range(len(m)))
+        assert abs(r["kappa"] - k_fs) < 3.0 * r["kappa_sigma"], (d, r["kappa"], r["kappa_sigma"], k_fs)
+
+
+def test_partially_specular_film_matches_fuchs():
+    """Specularity p = 0.6 (drawn per hit against a 64-bit threshold): Fuchs' partially
+    specular suppression, gray medium at Kn = 1 and Kn = 4."""
+    for d in (100e-9, 25e-9):
+        w = W.film(N=200000, d=d, specularity=0.6, n_scat_max=2)
+        w["modes"] = W.gray_modes(6400.0, 100e-9 / 6400.0)
+        w["problem"]["format"] = 2
+        r = oracle.run(w, threads=THREADS)
+        k_ref = 1e6 * 6400.0 ** 2 * (100e-9 / 6400.0) / 3.0 * cf.fs_suppression(d / 100e-9, 0.6)
+        assert abs(r["kappa"] - k_ref) < 3.0 * r["kappa_sigma"], (d, r["kappa"], r["kappa_sigma"], k_ref)
+        c = r["counts"]
+        frac = c["specular"] / (c["specular"] + c["diffuse"])
+        assert abs(frac - 0.6) < 4 * math.sqrt(0.24 / (c["specular"] + c["diffuse"]))
+
+
+def test_specular_film_recovers_bulk():
+    """Fully specular walls do not resist in-plane flow: kappa -> kappa_bulk."""
+    w = W.film(N=100000, specularity=1.0, n_scat_max=1)
+    w["modes"] = W.gray_modes(6400.0, 100e-9 / 6400.0)
+    w["problem"]["format"] = 2
+    r = oracle.run(w, threads=THREADS)
+    k_ref = 1e6 * 6400.0 ** 2 * (100e-9 / 6400.0) / 3.0
+    assert abs(r["kappa"] - k_ref) < 3.0 * r["kappa_sigma"]
+    assert r["counts"]["specular"] > 0 and r["counts"]["diffuse"] == 0
+
+
+def test_ballistic_transient_matches_closed_form():
+    """The paper's ballistic benchmark (Eq. Analytical_T) on its own setup, per bin and time."""
+    w = W.ballistic_transient(N=240000)
+    p, det = w["problem"], w["detectors"]
+    L, v = w["geometry"]["L"][2], 12360.0
+    batches = oracle.run_batches(w, NB, threads=THREADS)
+    ref = np.stack([cf.bin_average(lambda z: cf.ballistic_transient_dT(z, tk, L, v, 3.0, -3.0), 0.0, L,
+                                   det["n"][2]) for tk in p["t_meas"]], axis=1)          # cell x time
+    assert_bins_agree([b["T"] for b in batches], ref)
+
+
+def test_transient_energy_is_conserved_exactly():
+    """Specular walls, positive initial bump, nothing absorbed: the detector energy
+    sum_c T_c C V_c equals the emitted energy at every measurement time."""
+    w = W.transient_bump(N=20000, n_times=40, dt_meas=50e-12)
+    r = oracle.run(w, threads=THREADS)
+    tb = r["tables"]
+    E = (r["T"] * tb.C_tot * r["V_cell"]).sum(0)
+    assert np.allclose(E, tb.E_tot, rtol=1e-12)
+    assert r["counts"]["timeouts"] == 20000
+    assert r["counts"]["absorbed"] == 0 and r["counts"]["escaped"] == 0
+    # the initial-condition energy is C A sum_c dT_c dz_c = C A sigma sqrt(2 pi) (1 K peak)
+    assert tb.E_tot == pytest.approx(tb.C_tot * 50e-9 * math.sqrt(2 * math.pi), rel=1e-9)
+
+
+def test_transient_first_snapshot_is_the_initial_condition():
+    w = W.transient_bump(N=200000, n_times=2, dt_meas=10e-12)
+    batches = oracle.run_batches(w, NB, threads=THREADS)
+    dT = w["problem"]["ic_dT"]
+    ref = (dT.reshape(100, 10)).mean(1)                       # 1 nm cells into 10 nm detector bins
+    # bins far in the tails see no particle; there the reference is below 1e-3 K
+    vals = np.array([b["T"][:, 0] for b in batches])
+    seen = vals.std(0) > 0
+    assert np.all(ref[~seen] < 1e-3)
+    assert_bins_agree(vals[:, seen], ref[seen])
+
+
+def test_gray_diffusive_bump_follows_fourier():
+    """Short mean free path (10 nm) in a 1 um slab: at ~1000 relaxation times the bump spreads
+    as the heat equation with D = v Lambda / 3 (insulated ends).  Bound: 3.5 sigma plus the
+    O(Kn^2) ~ 1e-3 relative non-Fourier correction."""
+    w = W.gray_diffusive_bump(N=64000, n_times=4)
+    p, det = w["problem"], w["detectors"]
+    L = 1e-6
+    D = 6400.0 * 10e-9 / 3.0
+    batches = oracle.run_batches(w, NB, threads=THREADS)
+    for k, tk in enumerate(p["t_meas"]):
+        if tk < 0.5e-9:
+            continue
+        ref = cf.bin_average(lambda z: cf.fourier_neumann_piecewise(z, tk, D, L, p["ic_edges"], p["ic_dT"]),
+                             0.0, L, det["n"][2], per_bin=8)
+        assert_bins_agree([b["T"][:, k] for b in batches], ref, sys_err=1e-3 * ref.max())
+
+
+def test_swapping_wall_temperatures_negates_tallies_exactly():
+    w = W.gray_slab(N=4000)
+    a = oracle.run(w)
+    w2 = W.with_(w, **{"geometry.faces": {5: (W.ISOTHERMAL, 299.0, 0, 0), 6: (W.ISOTHERMAL, 301.0, 0, 0)}})
+    b = oracle.run(w2)
+    assert np.array_equal(a["raw"], -b["raw"])
+    assert np.array_equal(a["counts"], b["counts"])
+
+
+def test_doubling_the_drive_doubles_results_exactly():
+    w = W.gray_slab(N=4000)
+    a = oracle.run(w)
+    w2 = W.with_(w, **{"geometry.faces": {5: (W.ISOTHERMAL, 302.0, 0, 0), 6: (W.ISOTHERMAL, 298.0, 0, 0)}})
+    b = oracle.run(w2)
+    assert np.array_equal(a["raw"], b["raw"])
+    assert np.array_equal(2.0 * a["T"], b["T"]) and np.array_equal(2.0 * a["q"], b["q"])
+
+
+def test_particle_range_partition_is_invisible():
+    """Particles are independent: [0, a) + [a, N) equals [0, N) (counts exact, sums to rounding)."""
+    w = W.film(N=6000, d=50e-9)
+    whole = oracle.trace(w)
+    parts = [oracle.trace(w, first_pid=lo, n=hi - lo) for lo, hi in ((0, 1234), (1234, 4000), (4000, 6000))]
+    assert np.array_equal(whole["counts"], sum(p["counts"] for p in parts))
+    raw = sum(p["raw"] for p in parts)
+    assert np.allclose(raw, whole["raw"], rtol=0, atol=1e-12 * np.abs(whole["raw"]).max())
+
+
+def test_periodic_faces_are_transparent():
+    """Linearised periodic condition (Eq. periodic_lin_final): reinsertion leaves the particle
+    unchanged, so a periodic box reproduces unbounded bulk trajectory by trajectory."""
+    w = W.bulk_gradient(N=20000, n_scat_max=6)
+    faces = {1: (W.PERIODIC, 0, 3e-8, 0), 3: (W.PERIODIC, 0, -3e-8, 0), 2: (W.PERIODIC, -2e-8, 0, 0),
+             4: (W.PERIODIC, 2e-8, 0, 0), 5: (W.PERIODIC, 0, 0, 5e-8), 6: (W.PERIODIC, 0, 0, -5e-8)}
+    wp = W.with_(w, **{"geometry.unbounded": (False, False, False), "geometry.L": (2e-8, 3e-8, 5e-8),
+                       "geometry.faces": faces, "geometry.volume": 1.0})
+    a = oracle.trace(w, n_log=200)
+    b = oracle.trace(wp, n_log=200)
+    assert b["counts"][5] > 10 * 20000               # many periodic transfers happened
+    for i in (0, 2, 8):                               # particles, relaxations, N_scat terminations
+        assert a["counts"][i] == b["counts"][i]
+    assert np.allclose(a["moments"], b["moments"], rtol=1e-11)
+    # the event logs agree once periodic transfers are removed
+    for ra, rb in zip(a["log"], b["log"]):
+        ea = [e for e in ra[1:1 + ra[0]] if (e >> 28) != 4]
+        eb = [e for e in rb[1:1 + min(rb[0], 63)] if (e >> 28) != 4]
+        n = min(len(ea), len(eb))
+        assert ea[:n] == eb[:n]
+
+
+def test_dispersive_diffusion_uses_post_scattering_distribution():
+    """Three short-mean-free-path modes: the late-time spreading of a bump follows Fourier with
+    D = sum_m C_m v_m^2 tau_m / (3 sum_m C_m), which holds only if relaxations redraw modes with
+    probability C_m / tau_m (Eq. norm_post_coll) -- a redraw proportional to C_m would give the
+    D of time-fractions C_m tau_m instead."""
+    modes = np.array([(1e13, 0.0, 6000.0, 0.0, 1.0e-12, 5.0e5, 0.0, 0, 1),
+                      (2e13, 0.0, 1000.0, 0.0, 1.0e-11, 5.0e5, 0.0, 1, 1),
+                      (3e13, 0.0, 3000.0, 0.0, 3.0e-12, 2.0e5, 0.0, 2, 2)], dtype=W.MODE_DTYPE)
+    L = 3e-6
+    w = W.transient_bump(N=48000, L=L, sigma=50e-9, n_cells=300, n_times=3, dt_meas=0.4e-9, bins=60,
+                         modes=modes, fmt=2)
+    w["problem"]["t_meas"] = np.array([0.4e-9, 0.8e-9, 1.19e-9])
+    C, v, tau = modes["C"], modes["v"], modes["tau"]
+    D = np.sum(C * v * v * tau) / (3 * C.sum())
+    D_wrong = np.sum(C * tau * v * v * tau) / (3 * np.sum(C * tau))
+    assert abs(D_wrong / D - 1) > 0.3
+    batches = oracle.run_batches(w, NB, threads=THREADS)
+    p = w["problem"]
+    for k, tk in enumerate(p["t_meas"]):
+        ref = cf.bin_average(lambda z: cf.fourier_neumann_piecewise(z, tk, D, L, p["ic_edges"], p["ic_dT"]),
+                             0.0, L, 60, per_bin=8)
+        assert_bins_agree([b["T"][:, k] for b in batches], ref, sys_err=3e-3 * ref.max())

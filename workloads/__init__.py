@@ -1,0 +1,278 @@
+"""Seeded synthetic workloads for the deviational phonon Monte Carlo tracer.
+
+This module only *describes problems*: material rows in the form of the
+paper's material-data file (section "MATLAB code I/O", material data), box
+geometry and boundary table (same section, geometry and boundary
+conditions), detector grids, run parameters and seeds.  It holds none of the
+method's arithmetic (no heat capacities from the Bose-Einstein derivative, no
+source energies, no distributions, no random draws).  Both the CPU oracle and
+the HIP library consume exactly these descriptions, each through its own
+binding.
+
+Units are SI throughout (m, s, rad/s, J, K).
+
+Face identifiers follow the paper's boundary-table order:
+    1: y = 0,  2: x = Lx,  3: y = Ly,  4: x = 0,  5: z = 0,  6: z = Lz,
+    7+: internal boundaries (here: z-axis cylindrical pores).
+Boundary types follow the same table: 1 isothermal (data0 = T_b),
+2 adiabatic (data0 = specularity d), 3 periodic (data = translation vector).
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+ISOTHERMAL, ADIABATIC, PERIODIC = 1, 2, 3
+FACE_AXIS_SIDE = {1: (1, 0), 2: (0, 1), 3: (1, 1), 4: (0, 0), 5: (2, 0), 6: (2, 1)}
+
+MODE_DTYPE = np.dtype([
+    ("omega", "f8"), ("dos", "f8"), ("v", "f8"), ("domega", "f8"),
+    ("tau", "f8"), ("C", "f8"), ("tau_imp", "f8"), ("bin", "i4"), ("branch", "i4"),
+])
+
+# Tally component mask bits: T (energy / temperature), q_x, q_y, q_z.
+MASK_T, MASK_QX, MASK_QY, MASK_QZ = 1, 2, 4, 8
+MASK_ALL = 15
+
+SEED_BASE = 0x4D43425445000000  # "MCBTE" followed by the config number
+
+# Synthetic silicon-like dispersion of the frequency-dependent workloads:
+# omega = omega_max * sin(k a / 2) per branch, zone edge k_max = 2 pi / a_Si,
+# a = pi / k_max so that omega(k_max) = omega_max.
+A_SI = 5.431e-10
+OMEGA_MAX_LA = 7.5e13
+OMEGA_MAX_TA = 3.0e13
+TAU_A = 1.3e-45      # s^3     (impurity-like  A omega^4)
+TAU_B = 1.7e-19      # s / K   (Umklapp-like   B omega^2 T exp(-C/T))
+TAU_C = 137.0        # K
+
+
+def silicon_like_modes(T: float, n_bins: int = 1000) -> np.ndarray:
+    """Material rows of the synthetic silicon-like crystal at temperature T.
+
+    Rows are in the paper's first material-data format (omega, DOS, V_g,
+    delta-omega, tau, polarization): one LA row per frequency bin and one TA
+    row (degeneracy 2 folded into the DOS) for every bin centre below the TA
+    zone-edge frequency.  Bin i has centre (i + 1/2) * delta-omega with
+    delta-omega = omega_max(LA) / n_bins.  The DOS of an isotropic branch is
+    g k^2 / (2 pi^2 V_g) per unit volume and unit angular frequency; the
+    relaxation time is 1 / (A omega^4 + B omega^2 T exp(-C/T)).  Heat
+    capacities are *not* computed here (the method derives them from the DOS).
+    """
+    k_max = 2.0 * math.pi / A_SI
+    a_eff = math.pi / k_max
+    dw = OMEGA_MAX_LA / n_bins
+    rows = []
+    for branch, (wmax, g) in enumerate(((OMEGA_MAX_LA, 1.0), (OMEGA_MAX_TA, 2.0))):
+        for i in range(n_bins):
+            w = (i + 0.5) * dw
+            if w >= wmax:
+                continue
+            k = (2.0 / a_eff) * math.asin(w / wmax)
+            v = 0.5 * a_eff * math.sqrt(wmax * wmax - w * w)
+            dos = g * k * k / (2.0 * math.pi ** 2 * v)
+            tau = 1.0 / (TAU_A * w ** 4 + TAU_B * w * w * T * math.exp(-TAU_C / T))
+            rows.append((w, dos, v, dw, tau, 0.0, 0.0, i, branch + 1))
+    return np.array(rows, dtype=MODE_DTYPE)
+
+
+def gray_modes(v: float, tau: float, C: float = 1.0e6) -> np.ndarray:
+    """One gray mode in the paper's second material-data format (omega, V_g, tau, C)."""
+    return np.array([(1.0e13, 0.0, v, 0.0, tau, C, 0.0, 0, 1)], dtype=MODE_DTYPE)
+
+
+def _geometry(L, unbounded=(False, False, False), faces=None, cylinders=(), gradT=(0.0, 0.0, 0.0),
+              volume=0.0):
+    return {
+        "L": tuple(float(x) for x in L),
+        "unbounded": tuple(bool(u) for u in unbounded),
+        "faces": {int(k): tuple(float(x) for x in v) for k, v in (faces or {}).items()},
+        "cylinders": [tuple(c) for c in cylinders],
+        "gradT": tuple(float(x) for x in gradT),
+        "volume": float(volume),
+    }
+
+
+def _problem(N, T_lin=300.0, n_scat_max=0, transient=False, t_max=0.0, t_meas=(), ic=None,
+             max_events=10_000_000, score_axis=2, fmt=1):
+    p = {
+        "N": int(N), "T_lin": float(T_lin), "n_scat_max": int(n_scat_max),
+        "transient": bool(transient), "t_max": float(t_max),
+        "t_meas": np.asarray(t_meas, dtype=np.float64),
+        "ic_axis": 2, "ic_edges": np.zeros(0), "ic_dT": np.zeros(0),
+        "max_events": int(max_events), "score_axis": int(score_axis), "format": int(fmt),
+    }
+    if ic is not None:
+        p["ic_axis"] = int(ic[0])
+        p["ic_edges"] = np.asarray(ic[1], dtype=np.float64)
+        p["ic_dT"] = np.asarray(ic[2], dtype=np.float64)
+    return p
+
+
+def _detectors(lo=(0.0, 0.0, 0.0), hi=(0.0, 0.0, 0.0), n=(0, 0, 0), mask=MASK_ALL):
+    return {"lo": tuple(float(x) for x in lo), "hi": tuple(float(x) for x in hi),
+            "n": tuple(int(x) for x in n), "mask": int(mask)}
+
+
+def gaussian_cell_average(edges: np.ndarray, centre: float, sigma: float, peak: float) -> np.ndarray:
+    """Cell averages of peak * exp(-(z - centre)^2 / (2 sigma^2)) over [edges[c], edges[c+1])."""
+    from scipy.special import erf
+    s2 = sigma * math.sqrt(2.0)
+    a, b = edges[:-1], edges[1:]
+    integral = peak * sigma * math.sqrt(math.pi / 2.0) * (erf((b - centre) / s2) - erf((a - centre) / s2))
+    return integral / (b - a)
+
+
+# --------------------------------------------------------------------------------------------
+# Named workloads.  Each returns a fresh dict; callers may override any field.
+# --------------------------------------------------------------------------------------------
+
+def gray_slab(N=100_000, Lambda=100e-9, L=100e-9, v=6400.0, T_hot=301.0, T_cold=299.0, bins=50,
+              seed=SEED_BASE + 1):
+    """Steady 1-D cross-plane slab between two black isothermal walls, gray medium."""
+    return {
+        "name": "gray_slab",
+        "modes": gray_modes(v, Lambda / v),
+        "geometry": _geometry((1.0, 1.0, L), (True, True, False),
+                              {5: (ISOTHERMAL, T_hot, 0, 0), 6: (ISOTHERMAL, T_cold, 0, 0)}),
+        "detectors": _detectors((0, 0, 0), (0, 0, L), (0, 0, bins)),
+        "problem": _problem(N, 300.0, 0, score_axis=2, fmt=2),
+        "seed": seed,
+    }
+
+
+def film(N=1_000_000, d=100e-9, T=300.0, gradT=-1.0e7, specularity=0.0, n_scat_max=10,
+         z_bins=0, seed=SEED_BASE + 2, modes=None):
+    """Steady in-plane thin film: diffuse (or partially specular) walls at z = 0, d; in-plane
+    axes unbounded; uniform gradient along y driving the spatially varying control."""
+    det = _detectors((0, 0, 0), (0, 0, d), (0, 0, z_bins), MASK_T | MASK_QY)
+    return {
+        "name": "film",
+        "modes": silicon_like_modes(T) if modes is None else modes,
+        "geometry": _geometry((1.0, 1.0, d), (True, True, False),
+                              {5: (ADIABATIC, specularity, 0, 0), 6: (ADIABATIC, specularity, 0, 0)},
+                              gradT=(0.0, gradT, 0.0)),
+        "detectors": det,
+        "problem": _problem(N, T, n_scat_max, score_axis=1, fmt=1),
+        "seed": seed,
+    }
+
+
+def transient_bump(N=10_000_000, L=1e-6, T=300.0, sigma=50e-9, peak=1.0, n_cells=1000,
+                   n_times=200, dt_meas=10e-12, bins=100, seed=SEED_BASE + 3, modes=None, fmt=1):
+    """Transient 1-D slab with specular walls, seeded by a Gaussian temperature bump."""
+    edges = np.linspace(0.0, L, n_cells + 1)
+    dT = gaussian_cell_average(edges, 0.5 * L, sigma, peak)
+    t_meas = np.arange(n_times, dtype=np.float64) * dt_meas
+    return {
+        "name": "transient_bump",
+        "modes": silicon_like_modes(T) if modes is None else modes,
+        "geometry": _geometry((1.0, 1.0, L), (True, True, False),
+                              {5: (ADIABATIC, 1.0, 0, 0), 6: (ADIABATIC, 1.0, 0, 0)}),
+        "detectors": _detectors((0, 0, 0), (0, 0, L), (0, 0, bins), MASK_T | MASK_QZ),
+        "problem": _problem(N, T, 0, transient=True, t_max=n_times * dt_meas, t_meas=t_meas,
+                            ic=(2, edges, dT), score_axis=2, fmt=fmt),
+        "seed": seed,
+    }
+
+
+def film_sweep(scale=1.0, seed=SEED_BASE + 4):
+    """The batched sweep: 16 log-spaced thicknesses (10 nm .. 10 um) x 4 temperatures.
+
+    Instance j (thickness index) carries round(10^(5 + log10(40) j / 15)) particles times
+    `scale`; instance id = 16 * t_index + j.
+    """
+    out = []
+    for ti, T in enumerate((100.0, 200.0, 300.0, 400.0)):
+        modes = silicon_like_modes(T)
+        for j in range(16):
+            d = 10.0 ** (-8.0 + 3.0 * j / 15.0)
+            N = max(1, int(round(scale * 10.0 ** (5.0 + math.log10(40.0) * j / 15.0))))
+            w = film(N=N, d=d, T=T, seed=seed, modes=modes)
+            w["name"] = f"film_sweep[T={T:.0f},d={d:.3e}]"
+            w["instance"] = 16 * ti + j
+            out.append(w)
+    return out
+
+
+def porous_cell(N=100_000_000, W=500e-9, porosity=0.25, T=300.0, gradT=-2.0e6, n_scat_max=10,
+                specularity=0.0, seed=SEED_BASE + 5, modes=None):
+    """3-D periodic cubic cell with a centred z-axis cylindrical pore (diffuse pore wall)."""
+    r = W * math.sqrt(porosity / math.pi)
+    faces = {1: (PERIODIC, 0, W, 0), 3: (PERIODIC, 0, -W, 0), 2: (PERIODIC, -W, 0, 0),
+             4: (PERIODIC, W, 0, 0), 5: (PERIODIC, 0, 0, W), 6: (PERIODIC, 0, 0, -W)}
+    return {
+        "name": "porous_cell",
+        "modes": silicon_like_modes(T) if modes is None else modes,
+        "geometry": _geometry((W, W, W), (False, False, False), faces,
+                              cylinders=[(0.5 * W, 0.5 * W, r, 7, ADIABATIC, specularity)],
+                              gradT=(0.0, gradT, 0.0)),
+        "detectors": _detectors(mask=MASK_T | MASK_QY),
+        "problem": _problem(N, T, n_scat_max, score_axis=1, fmt=1),
+        "seed": seed,
+    }
+
+
+def ballistic_transient(N=200_000, L=3000e-9, v=12360.0, tau=1.0, T_l=303.0, T_r=297.0,
+                        t_max=1.0e-9, t_meas=(5e-12, 50e-12, 100e-12, 200e-12, 300e-12, 900e-12),
+                        bins=60, seed=SEED_BASE + 6):
+    """The paper's ballistic benchmark: walls impulsively set to T_l / T_r at t = 0."""
+    return {
+        "name": "ballistic_transient",
+        "modes": gray_modes(v, tau),
+        "geometry": _geometry((1.0, 1.0, L), (True, True, False),
+                              {5: (ISOTHERMAL, T_l, 0, 0), 6: (ISOTHERMAL, T_r, 0, 0)}),
+        "detectors": _detectors((0, 0, 0), (0, 0, L), (0, 0, bins), MASK_T | MASK_QZ),
+        "problem": _problem(N, 300.0, 0, transient=True, t_max=t_max, t_meas=t_meas, score_axis=2,
+                            fmt=2),
+        "seed": seed,
+    }
+
+
+def bulk_gradient(N=200_000, v=6400.0, Lambda=100e-9, gradT=-1.0e7, n_scat_max=1, modes=None,
+                  seed=SEED_BASE + 7, T=300.0):
+    """Unbounded bulk driven only by the gradient source (no boundaries at all)."""
+    gray = modes is None
+    return {
+        "name": "bulk_gradient",
+        "modes": gray_modes(v, Lambda / v) if gray else modes,
+        "geometry": _geometry((1.0, 1.0, 1.0), (True, True, True), {}, gradT=(0.0, gradT, 0.0)),
+        "detectors": _detectors(mask=MASK_ALL),
+        "problem": _problem(N, T, n_scat_max, score_axis=1, fmt=2 if gray else 1),
+        "seed": seed,
+    }
+
+
+def gray_diffusive_bump(N=100_000, L=1e-6, v=6400.0, Lambda=10e-9, sigma=50e-9, peak=1.0,
+                        n_cells=1000, t_end=2e-9, n_times=5, bins=50, seed=SEED_BASE + 8):
+    """Gray analogue of the transient bump with a short mean free path (diffusive regime)."""
+    w = transient_bump(N=N, L=L, sigma=sigma, peak=peak, n_cells=n_cells, n_times=n_times,
+                       dt_meas=t_end / n_times, bins=bins, seed=seed, modes=gray_modes(v, Lambda / v),
+                       fmt=2)
+    w["name"] = "gray_diffusive_bump"
+    # measure at the end of each interval, the last exactly one interval before t_max
+    w["problem"]["t_meas"] = np.arange(1, n_times + 1) * (t_end / n_times) - 0.5 * (t_end / n_times)
+    w["problem"]["t_max"] = t_end
+    return w
+
+
+def with_(w: dict, **changes) -> dict:
+    """Deep copy of a workload with dotted-path overrides, e.g. with_(w, **{"problem.N": 10})."""
+    w = copy.deepcopy(w)
+    for key, val in changes.items():
+        node = w
+        parts = key.split(".")
+        for p in parts[:-1]:
+            node = node[p]
+        node[parts[-1]] = val
+    return w
+
+
+CONFIGS = {
+    "C1": gray_slab,
+    "C2": film,
+    "C3": transient_bump,
+    "C5": porous_cell,
+}
