@@ -1,0 +1,258 @@
+/*
+ * mcbte.h -- C ABI of the MI355X (gfx950) deviational phonon Monte Carlo tracer.
+ *
+ * The library runs the hot path of the linearized, deviational, energy-based
+ * Monte Carlo solution of the phonon Boltzmann transport equation of Pathak et
+ * al. ("MCBTE", Computer Physics Communications): deviational energy bundles are
+ * emitted from sources (section 3.2), fly exponential free paths (section 3.3),
+ * relax by redrawing frequency and direction (section 3.5.2), reflect, are
+ * absorbed or are reinserted at boundaries (sections 3.5.3-3.5.5), and are scored
+ * into temperature and heat-flux detectors (sections 3.4 and 3.6).
+ *
+ * Conventions of the whole interface:
+ *   - every function returns an int status: MCBTE_OK (0) or a negative MCBTE_E*
+ *     code; nothing throws across the ABI; mcbte_strerror() names the code;
+ *   - SI units (m, s, rad/s, J, K);
+ *   - "device pointer" = memory of the HIP device the tables were built for
+ *     (e.g. a torch.cuda tensor's data_ptr()); "host pointer" = CPU memory;
+ *   - "stream" = a hipStream_t passed as void* (NULL = the null stream); device
+ *     work is enqueued asynchronously unless a function says it synchronizes;
+ *   - tables are library-owned and opaque; particle-state, tally and event-log
+ *     buffers are caller-owned device memory; the library allocates nothing per
+ *     call (device memory is allocated only by mcbte_build_tables);
+ *   - calls on distinct table handles and distinct tally buffers are
+ *     thread-safe; calls sharing a tally buffer must be ordered on one stream.
+ */
+#ifndef MCBTE_H
+#define MCBTE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MCBTE_OK 0
+#define MCBTE_EINVAL (-1)   /* an argument is out of range or inconsistent            */
+#define MCBTE_ENOMEM (-2)   /* host or device allocation failed                       */
+#define MCBTE_EHIP (-3)     /* a HIP runtime call failed                              */
+#define MCBTE_ENODEV (-4)   /* host-only tables (device = -1) passed to a device call */
+#define MCBTE_ETABLE (-5)   /* a distribution or the source list has zero weight      */
+#define MCBTE_EGEOM (-6)    /* geometry not closed / periodic faces not paired / pore outside */
+#define MCBTE_ESIZE (-7)    /* a caller buffer is smaller than required               */
+
+/* boundary types (order of the paper's boundary table, section 4.3) */
+#define MCBTE_ISOTHERMAL 1  /* data[0] = wall temperature T_b                       */
+#define MCBTE_ADIABATIC 2   /* data[0] = specularity d in [0, 1]                    */
+#define MCBTE_PERIODIC 3    /* data = translation vector (must map the face onto its partner) */
+
+/* tally component mask bits */
+#define MCBTE_TALLY_T 1
+#define MCBTE_TALLY_QX 2
+#define MCBTE_TALLY_QY 4
+#define MCBTE_TALLY_QZ 8
+
+#define MCBTE_MAX_PORES 8
+#define MCBTE_N_COUNTS 16
+
+/* counters, indices into the counts array of the tally buffer (all uint64) */
+enum {
+    MCBTE_CNT_PARTICLES = 0, MCBTE_CNT_FLIGHTS = 1, MCBTE_CNT_RELAXATIONS = 2, MCBTE_CNT_SPECULAR = 3,
+    MCBTE_CNT_DIFFUSE = 4, MCBTE_CNT_PERIODIC = 5, MCBTE_CNT_ABSORBED = 6, MCBTE_CNT_TIMEOUT = 7,
+    MCBTE_CNT_NSCAT_END = 8, MCBTE_CNT_CAP_END = 9, MCBTE_CNT_ESCAPED = 10, MCBTE_CNT_REJECTIONS = 11
+};
+
+/* One material row (section 4.1).  First format: omega, dos (s rad^-1 m^-3), v, domega, tau;
+   the heat capacity is then dos * domega * de/dT(omega, T_lin) (Eq. BE_derivative with the
+   half argument, x = hbar omega / k_B T: k_B (x/2)^2 / sinh^2(x/2)).  Second format: omega, v,
+   tau and C (J m^-3 K^-1) given directly; dos / domega ignored.  tau_imp is reserved for the
+   separate two-phonon clock and must be 0.  bin: frequency-bin index (for per-bin outputs). */
+typedef struct {
+    double omega, dos, v, domega, tau, C, tau_imp;
+    int32_t bin, branch;
+} mcbte_mode;
+
+typedef struct {
+    int32_t type;               /* MCBTE_ISOTHERMAL / _ADIABATIC / _PERIODIC */
+    int32_t reserved;
+    double data[3];
+} mcbte_face;
+
+/* internal boundary: a cylindrical pore with axis along z through (cx, cy), adiabatic wall */
+typedef struct {
+    double cx, cy, r;
+    int32_t id;                 /* boundary id, >= 7, strictly increasing over the array */
+    int32_t type;               /* MCBTE_ADIABATIC */
+    double specularity;
+} mcbte_pore;
+
+/* Box [0, L0] x [0, L1] x [0, L2] (one corner at the origin, section 4.2).  face[id - 1] holds
+   boundary id 1..6 in the paper's order: 1 y=0, 2 x=L0, 3 y=L1, 4 x=0, 5 z=0, 6 z=L2.  An axis
+   with unbounded[a] != 0 has no faces (translation-invariant direction, lengths taken as 1 m
+   for areas and volumes; positions along it start at 0).  gradT is the uniform temperature
+   gradient of the spatially varying control (section 2.6); volume is the solid volume
+   (section 4.4; <= 0: box volume minus the pores). */
+typedef struct {
+    double L[3];
+    int32_t unbounded[3];
+    int32_t n_pores;
+    mcbte_face face[6];
+    mcbte_pore pore[MCBTE_MAX_PORES];
+    double gradT[3];
+    double volume;
+} mcbte_geometry;
+
+/* Detector grid (section 4.5): the cuboid [lo, hi] split into n[a] equal cells along each axis
+   with n[a] > 0; axes with n[a] == 0 are not binned.  mask selects the accumulated components
+   (MCBTE_TALLY_*).  Cells are numbered x-major: ((ix * ny) + iy) * nz + iz (n == 0 counts as 1). */
+typedef struct {
+    double lo[3], hi[3];
+    int32_t n[3];
+    int32_t mask;
+} mcbte_detectors;
+
+/* Run parameters (sections 4.4-4.5).  N: number of computational particles that share the
+   total deviational energy (effective energy E_tot / N).  transient: snapshot tallies at the
+   n_times sorted times t_meas (< t_max), particles end at t_max; wall and gradient sources
+   emit uniformly over [0, t_max).  Steady: track-length tallies, one column per mode.
+   Initial condition (transient only): n_ic cells along axis ic_axis with edges ic_edges[0..n_ic]
+   and cell-averaged temperature deviations ic_dT[0..n_ic-1].  n_scat_max: relaxations after
+   which a particle ends (0 = unlimited).  max_events: cap on segments per particle (counted in
+   MCBTE_CNT_CAP_END).  score_axis: flux component used for kappa and its standard error.
+   All pointers are host pointers, read during mcbte_build_tables only. */
+typedef struct {
+    int64_t N, max_events;
+    double T_lin, t_max;
+    int32_t n_scat_max, format, transient, score_axis;
+    int32_t n_times, ic_axis, n_ic, reserved;
+    const double* t_meas;
+    const double* ic_edges;
+    const double* ic_dT;
+} mcbte_problem;
+
+typedef struct mcbte_tables mcbte_tables;
+
+/* Derived quantities of a table set. */
+typedef struct {
+    double C_tot;        /* sum of the per-mode heat capacities (J m^-3 K^-1)              */
+    double sum_Cv;       /* sum_m C_m v_m                                                  */
+    double E_tot;        /* total deviational energy (transient, J) or energy rate (steady, W) */
+    double e_eff;        /* E_tot / N                                                      */
+    double V_solid;      /* solid volume (m^3)                                             */
+    double kappa_bulk;   /* sum_m C_m v_m^2 tau_m / 3                                      */
+    int64_t n_modes, n_sources, n_cells, n_cols;
+    int64_t tally_bytes; /* size of the tally buffer mcbte_trace needs                     */
+    int32_t device;      /* HIP device ordinal, -1 for host-only tables                    */
+    int32_t reserved;
+} mcbte_info;
+
+/* Trace options. */
+typedef struct {
+    uint64_t seed;        /* Philox key                                                     */
+    uint32_t instance;    /* fourth counter word of every Philox draw                       */
+    int32_t precision;    /* 64: FP64 trajectories; 32: FP32 trajectories, FP64 tables and sums */
+    int32_t block;        /* threads per workgroup (multiple of 64, <= 1024; 0 = default)   */
+    int32_t refill;       /* flights between refills of finished lanes (>= 1; 0 = default)  */
+    int32_t grid;         /* workgroups (0 = enough to fill every compute unit)             */
+    int32_t log_stride;   /* uint32 words per event-log row (>= 2)                          */
+    int64_t n_log;        /* particles logged (first_pid .. first_pid + n_log - 1)          */
+    uint32_t* event_log;  /* device pointer, n_log * log_stride uint32, or NULL             */
+} mcbte_run;
+
+/* Finalized results (mcbte_tally). */
+typedef struct {
+    uint64_t counts[MCBTE_N_COUNTS];
+    double moments[4];    /* sum c_T, sum c_T^2, sum c_q, sum c_q^2 over particles          */
+    double e_eff;         /* E_tot / particles traced                                        */
+    double V_cell;        /* detector cell volume used for the normalization                */
+    double T_mean, T_mean_sigma;     /* steady: solid-averaged temperature deviation (K)    */
+    double q_score, q_score_sigma;   /* steady: solid-averaged flux along score_axis (W/m^2) */
+    double kappa, kappa_sigma;       /* steady: -q_score / gradT[score_axis] (0 if no gradient) */
+    double kappa_cell_avg;           /* kappa * V_solid / box volume                         */
+} mcbte_result;
+
+/* Build the tables of one problem (section 3.1: source energies and effective energy; section
+   3.2: the cumulative distributions of Eq. cumul_freq for emission from initial conditions
+   (weight C_m), walls and the gradient source (weight C_m v_m, Eqs. iso_flux and grad_flux),
+   and relaxation (weight C_m / tau_m, Eqs. norm_post_coll and n_scatt)).  Host FP64; then, if
+   device >= 0, uploads the tables to that device (synchronous).  device = -1 builds host-only
+   tables for inspection (mcbte_table_info / mcbte_table_export).  All input pointers are host
+   pointers and are not retained.  Errors: MCBTE_EINVAL (bad row, detector or run parameter),
+   MCBTE_EGEOM, MCBTE_ETABLE, MCBTE_ENOMEM, MCBTE_EHIP.  *out is NULL on error. */
+int mcbte_build_tables(const mcbte_mode* modes, int32_t n_modes, const mcbte_geometry* geometry,
+                       const mcbte_detectors* detectors, const mcbte_problem* problem, int32_t device,
+                       mcbte_tables** out);
+
+/* Release tables and their device memory (NULL is ignored).  Synchronizes the device first. */
+void mcbte_free_tables(mcbte_tables* tables);
+
+/* Copy the derived quantities into *info (host). */
+int mcbte_table_info(const mcbte_tables* tables, mcbte_info* info);
+
+/* Copy one host-side table into host_out (n elements available): which = 0 C_m (double[M]),
+   1/2/3 initial-condition / wall / relaxation thresholds (uint64[M]), 4 source energies
+   (double[S]), 5 source thresholds (uint64[S]), 6 source signs (int32[S]).  Threshold j is
+   floor(F_j 2^64) saturated at 2^64 - 1; a 64-bit key K selects the first j with K < threshold. */
+int mcbte_table_export(const mcbte_tables* tables, int32_t which, void* host_out, int64_t n);
+
+/* Bytes of the particle-state buffer for `capacity` particles at `precision` (32 or 64); < 0 on
+   a bad argument.  Layout (structure of arrays, each array 256-byte aligned): x, y, z, ox, oy, oz,
+   t, dt_rem (real), then mode, sign, n_rel, segments, draws (int32 / uint32). */
+int64_t mcbte_state_bytes(int32_t precision, int64_t capacity);
+
+/* Emit particles first_pid .. first_pid + n - 1 (section 3.2: source chosen by deviational
+   energy, position, frequency, direction, sign, start time, first free flight of Eq.
+   time_to_scat) into the device state buffer `state` (mcbte_state_bytes(run->precision,
+   capacity) bytes, capacity >= n); slot i holds particle first_pid + i.  Async on `stream`.
+   Errors: MCBTE_EINVAL, MCBTE_ENODEV, MCBTE_EHIP. */
+int mcbte_emit(const mcbte_tables* tables, const mcbte_run* run, int64_t first_pid, int64_t n, void* state,
+               int64_t capacity, void* stream);
+
+/* Trace particles first_pid .. first_pid + n - 1 to termination and add their scores to the
+   device tally buffer `tally` (mcbte_table_info().tally_bytes bytes, zeroed by the caller before
+   the first trace; successive traces accumulate).  With state == NULL the particles are emitted
+   inside the trace kernel (same draws as mcbte_emit); otherwise `state` holds them as written by
+   mcbte_emit with the same run->precision and first_pid and with capacity == n (the layout of
+   the state buffer depends on its capacity).  Flight loop: section 3.3 (free flight,
+   boundary interruption of case iii), events of section 3.5, termination of section 3.5.6;
+   tallies: Eq. sampling (transient) or Eqs. temp_steady / flux_x_steady (steady).  Async on
+   `stream`.  Errors: MCBTE_EINVAL, MCBTE_ENODEV, MCBTE_EHIP.
+   Tally buffer layout (bytes): [0,128) counts uint64[16]; [128,160) moments double[4];
+   [192,200) library work counter; [256, ...) raw sums double[n_cells][n_cols][4] with
+   components (sum s l / v | sum s, sum s l Omega_x | sum s v Omega_x, ... y, ... z).
+   Event log rows (if run->event_log): word 0 = number of entries, then entries
+   (type << 28) | (min(boundary id or source index, 255) << 20) | mode, types 0 emit (sign +),
+   9 emit (sign -), 1 relaxation (new mode), 2 specular, 3 diffuse, 4 periodic, 5 absorbed,
+   6 time horizon, 7 N_scat^max reached, 8 segment cap, 10 escaped. */
+int mcbte_trace(const mcbte_tables* tables, const mcbte_run* run, int64_t first_pid, int64_t n,
+                const void* state, void* tally, void* stream);
+
+/* Batched form: instance i traces particles 0 .. n_particles[i] - 1 of tables[i] with Philox
+   instance word instance_ids[i] into tallies[i], all in one persistent launch whose workgroups
+   pull (instance, particle chunk) work items from a shared queue.  All tables must be built for
+   the same device with the same transient flag; run->instance is ignored; the event log is not
+   supported (run->event_log must be NULL).  `queue` is a caller-owned device buffer of at least
+   mcbte_batch_queue_bytes(n_inst) bytes (its contents are overwritten); the work table is
+   uploaded into it and `stream` is synchronized once before the launch, which is then async. */
+int64_t mcbte_batch_queue_bytes(int32_t n_inst);
+int mcbte_trace_batch(const mcbte_tables* const* tables, int32_t n_inst, const int64_t* n_particles,
+                      const uint32_t* instance_ids, void* const* tallies, const mcbte_run* run, void* queue,
+                      void* stream);
+
+/* Copy the device tally buffer to the host (synchronizes `stream`) and finalize it (Eqs.
+   sampling, temp_steady, flux_x_steady): host_out[n_cells][n_cols][4] receives the deviational
+   temperature T_dev = e (C_tot V_cell)^-1 raw_T and fluxes q_a = e V_cell^-1 raw_a with
+   e = E_tot / particles traced; V_cell = V_solid when no axis is binned.  host_out may be NULL
+   (n_out ignored); otherwise n_out must be >= n_cells * n_cols * 4.  *result (host) receives
+   counters, moments and, for steady runs, kappa with its standard error. */
+int mcbte_tally(const mcbte_tables* tables, const void* tally, double* host_out, int64_t n_out,
+                mcbte_result* result, void* stream);
+
+/* Static text for a status code. */
+const char* mcbte_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -104,6 +104,8 @@ def lib():
         L.orc_dedT.argtypes = [C.c_double, C.c_double]
         L.orc_dedT.restype = C.c_double
         L.orc_tally_segment.argtypes = [p, p, p, C.c_double, C.c_int32, C.c_double, p]
+        L.orc_emit_state.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, p, p]
+        L.orc_emit_state.restype = C.c_int
         L.orc_next_boundary.argtypes = [p, p, p, p]
         L.orc_next_boundary.restype = C.c_double
         _lib = L
@@ -249,6 +251,15 @@ class Tables:
         if rc != 0:
             raise ValueError(f"oracle trace failed with status {rc}")
         return raw, counts, mom, log
+
+    def emit_state(self, pid: int, seed: int | None = None, instance: int = 0):
+        """(x, o, t, dt_rem) as float64[8] and (mode, sign, source, rejections) as int32[4]."""
+        d8 = np.zeros(8)
+        i4 = np.zeros(4, dtype=np.int32)
+        sd = int(self.w["seed"]) if seed is None else int(seed)
+        if lib().orc_emit_state(self.h, sd, instance, pid, _ptr(d8), _ptr(i4)) != 0:
+            raise ValueError("emission failed")
+        return d8, i4
 
     def next_boundary(self, x, o) -> tuple[float, int]:
         x = np.ascontiguousarray(x, dtype=np.float64)

@@ -653,6 +653,19 @@ double orc_next_boundary(const orc_tables* t, const double x[3], const double o[
     return d;
 }
 
+int orc_emit_state(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t pid, double* d8, int32_t* i4)
+{
+    prt p;
+    int64_t src = 0;
+    uint64_t counts[ORC_N_COUNTS] = {0};
+    if (emit(t, seed, instance, pid, &p, counts, &src) != 0) return E_INVAL;
+    d8[0] = p.x[0]; d8[1] = p.x[1]; d8[2] = p.x[2];
+    d8[3] = p.o[0]; d8[4] = p.o[1]; d8[5] = p.o[2];
+    d8[6] = p.t; d8[7] = p.dtr;
+    i4[0] = p.m; i4[1] = p.s; i4[2] = (int32_t)src; i4[3] = (int32_t)counts[ORC_C_REJECT];
+    return E_OK;
+}
+
 static uint32_t pack_ev(int ev, int64_t bnd, int32_t m)
 {
     if (bnd > 255) bnd = 255;

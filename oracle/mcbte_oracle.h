@@ -77,6 +77,8 @@ void orc_cdf_build(const double* w, int64_t n, uint64_t* thr, int64_t* last);
 void orc_dir_iso(double u1, double u2, double out[3]);
 void orc_dir_cos(double u1, double u2, const double n[3], double out[3]);
 double orc_dedT(double omega, double T);
+/* emitted state of one particle: d8 = x, y, z, ox, oy, oz, t, dt_rem; i4 = mode, sign, source, rejections */
+int orc_emit_state(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t pid, double* d8, int32_t* i4);
 /* nearest boundary along a ray: distance and boundary id (0: none) */
 double orc_next_boundary(const orc_tables* t, const double x[3], const double o[3], int32_t* hit);
 /* tally one straight steady segment into raw (testing the detector clipping) */

@@ -1,0 +1,106 @@
+// Device-side view of one table set, shared by the host builder (mcbte_host.cpp) and the
+// kernels (mcbte_kernels.hip).  Library-internal: not part of the C ABI.
+#pragma once
+#include <stdint.h>
+
+#define MCBTE_DEV_MAX_PORES 8
+#define MCBTE_LDS_TABLE_BYTES (48 * 1024)   // mode tables staged in LDS (thresholds + v + tau)
+#define MCBTE_LDS_TALLY_BYTES (40 * 1024)   // per-workgroup tally privatisation budget
+#define MCBTE_TALLY_HEADER_BYTES 256
+#define MCBTE_TALLY_COUNTER_OFFSET 192
+
+namespace mcbte {
+
+enum SourceKind : int32_t { SRC_WALL = 0, SRC_GRAD = 1, SRC_IC = 2 };
+enum TallyKind : int32_t { TALLY_STEADY_ONE = 0, TALLY_STEADY_GRID = 1, TALLY_TRANSIENT = 2 };
+
+// Geometry in the form the flight loop reads it (uniform across a launch; scalar loads).
+struct DevGeom {
+    double L[3];
+    int32_t unb[3];              // axis without faces
+    int32_t n_pores;
+    int32_t face_type[6];        // by boundary id - 1
+    int32_t pad0;
+    double face_spec[6];         // adiabatic specularity
+    uint64_t face_thr[6];        // floor(d 2^64) for 0 < d < 1
+    double pore_cx[MCBTE_DEV_MAX_PORES], pore_cy[MCBTE_DEV_MAX_PORES], pore_r[MCBTE_DEV_MAX_PORES];
+    double pore_spec[MCBTE_DEV_MAX_PORES];
+    uint64_t pore_thr[MCBTE_DEV_MAX_PORES];
+    int32_t pore_id[MCBTE_DEV_MAX_PORES];
+    double ngrad[3];             // -gradT / |gradT| (0 if no gradient)
+    // single-precision copies for the FP32 trajectories
+    float L32[3];
+    float pore_cx32[MCBTE_DEV_MAX_PORES], pore_cy32[MCBTE_DEV_MAX_PORES], pore_r32[MCBTE_DEV_MAX_PORES];
+    float ngrad32[3];
+};
+
+struct DevDet {
+    double lo[3], hi[3], w[3];   // w = (hi - lo) / n on binned axes
+    float lo32[3], hi32[3], inv_w32[3];
+    int32_t n[3];
+    int32_t mask;
+    int32_t ncomp;               // number of components in the mask
+    int32_t slot[4];             // compact LDS slot of each component, -1 if masked out
+    int32_t comp[4];             // component of each compact slot
+    int32_t n_cols;
+    int64_t n_cells;
+};
+
+struct DevTab {
+    int32_t M, S;
+    int32_t transient, n_scat_max;
+    int32_t score_axis, n_times;
+    int32_t ic_axis, n_ic;
+    int32_t tally_kind;          // TallyKind
+    int32_t coop_axis;           // film axis for wave-cooperative diffuse bouncing (FP32), -1: off
+    double coop_min_path;        // remaining free path (m) above which a wall bounce turns cooperative
+    int64_t max_events;
+    double t_max;
+    int64_t last_ic, last_wall, last_rel, last_src;
+    // device arrays (inside the table allocation)
+    const double* v64;
+    const double* tau64;
+    const float* v32;
+    const float* tau32;
+    const uint64_t* thr_ic;
+    const uint64_t* thr_wall;
+    const uint64_t* thr_rel;
+    const uint64_t* thr_src;
+    const int32_t* src_kind;
+    const int32_t* src_ref;
+    const int32_t* src_sign;
+    const double* ic_edges;
+    const double* t_meas64;
+    const float* t_meas32;
+    DevGeom g;
+    DevDet det;
+};
+
+// launch description shared by the solo and batched trace kernels
+struct LaunchArgs {
+    const DevTab* tabs;          // device array, one per instance
+    int32_t n_inst;
+    int32_t refill;
+    uint64_t seed;
+    const uint32_t* inst_ids;    // device array (batched) or NULL (solo: inst0)
+    uint32_t inst0;
+    int32_t log_stride;
+    int64_t first_pid;
+    int64_t n;                   // solo: particle count
+    const void* state;           // solo: pre-emitted states or NULL
+    int64_t capacity;
+    unsigned char* tally;        // solo: tally buffer
+    uint32_t* event_log;
+    int64_t n_log;
+    // batched: per-instance tallies and particle counts plus the chunk table
+    unsigned char* const* tallies;
+    const int64_t* inst_n;
+    const int64_t* chunk_start;  // prefix sum of chunks per instance (n_inst + 1)
+    int64_t chunk_size;
+    unsigned long long* queue;   // [0]: next chunk
+    int64_t n_chunks;
+    int32_t tally_lds;           // tallies privatised in LDS
+    int32_t lds_tab_bytes;       // offset of the tally region in dynamic LDS
+};
+
+}  // namespace mcbte

@@ -1,0 +1,727 @@
+// Host side of the C ABI (include/mcbte.h): validation, the FP64 table build, device upload,
+// launch configuration and the finalization of the tallies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "mcbte.h"
+#include "mcbte_dev.h"
+
+namespace mcbte {
+hipError_t launch_emit(const DevTab* d_tab, int precision, uint64_t seed, uint32_t inst, int64_t first_pid, int64_t n,
+                       void* state, int64_t cap, hipStream_t s);
+hipError_t launch_trace(const LaunchArgs& a, bool batch, int precision, int tally_kind, int block, int grid, size_t lds,
+                        hipStream_t s);
+int trace_occupancy(bool batch, int precision, int tally_kind, int block, size_t lds);
+}  // namespace mcbte
+
+using namespace mcbte;
+
+namespace {
+
+const double kHbar = 1.054571817e-34;   // J s (CODATA 2018)
+const double kBoltzmann = 1.380649e-23; // J/K (exact, SI 2019)
+const double kPi = 3.141592653589793;
+const double kTwo64 = 18446744073709551616.0;
+
+// boundary id - 1 -> axis, side (1: the face at L, 0: the face at 0)
+const int kFaceAxis[6] = {1, 0, 1, 0, 2, 2};
+const int kFaceSide[6] = {0, 1, 1, 0, 0, 1};
+
+// cumulative distribution as 64-bit thresholds; returns the last positive-weight index (-1 if none)
+int64_t build_thresholds(const std::vector<double>& w, std::vector<uint64_t>& thr)
+{
+    const size_t n = w.size();
+    thr.assign(n, 0);
+    double total = 0.0;
+    int64_t last = -1;
+    for (size_t i = 0; i < n; ++i) {
+        total += w[i];
+        if (w[i] > 0.0) last = (int64_t)i;
+    }
+    if (last < 0) return -1;
+    double running = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        running += w[i];
+        const double F = running / total;
+        thr[i] = F >= 1.0 ? UINT64_MAX : (uint64_t)(F * kTwo64);
+    }
+    return last;
+}
+
+// d e_eq / dT of one mode: k_B (x/2)^2 / sinh^2(x/2) with x = hbar omega / (k_B T)
+double bose_einstein_dedT(double omega, double T)
+{
+    const double x = (kHbar * omega) / (kBoltzmann * T);
+    const double h = 0.5 * x;
+    const double sh = std::sinh(h);
+    return (kBoltzmann * (h * h)) / (sh * sh);
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct mcbte_tables {
+    int32_t device = -1;
+    mcbte_info info{};
+    mcbte_problem prob{};
+    mcbte_geometry geom{};
+    mcbte_detectors det{};
+    // host tables
+    std::vector<double> C, v, tau, src_E, ic_edges, ic_dT, t_meas;
+    std::vector<uint64_t> thr_ic, thr_wall, thr_rel, thr_src;
+    std::vector<int32_t> src_kind, src_ref, src_sign;
+    DevTab host_view{};   // device pointers once uploaded
+    void* d_mem = nullptr;
+    DevTab* d_tab = nullptr;
+    int n_cu = 0;
+    int max_lds = 0;
+};
+
+extern "C" {
+
+const char* mcbte_strerror(int status)
+{
+    switch (status) {
+    case MCBTE_OK: return "ok";
+    case MCBTE_EINVAL: return "invalid argument";
+    case MCBTE_ENOMEM: return "out of memory";
+    case MCBTE_EHIP: return "HIP runtime error";
+    case MCBTE_ENODEV: return "tables were built without a device";
+    case MCBTE_ETABLE: return "a distribution or the source list has zero total weight";
+    case MCBTE_EGEOM: return "invalid geometry";
+    case MCBTE_ESIZE: return "caller buffer too small";
+    default: return "unknown status";
+    }
+}
+
+void mcbte_free_tables(mcbte_tables* t)
+{
+    if (!t) return;
+    if (t->d_mem) {
+        DeviceGuard g(t->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(t->d_mem);
+    }
+    delete t;
+}
+
+int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry* geometry,
+                       const mcbte_detectors* detectors, const mcbte_problem* problem, int32_t device,
+                       mcbte_tables** out)
+{
+    if (!out) return MCBTE_EINVAL;
+    *out = nullptr;
+    if (!modes || !geometry || !detectors || !problem || M < 1 || device < -1) return MCBTE_EINVAL;
+    const mcbte_geometry& g = *geometry;
+    const mcbte_detectors& dt = *detectors;
+    const mcbte_problem& pr = *problem;
+    if (pr.N < 1 || !(pr.T_lin > 0.0) || (pr.format != 1 && pr.format != 2)) return MCBTE_EINVAL;
+    if (pr.score_axis < 0 || pr.score_axis > 2 || pr.max_events < 1 || pr.max_events > 0x3FFFFFF0LL) return MCBTE_EINVAL;
+    if (pr.n_scat_max < 0) return MCBTE_EINVAL;
+    // geometry
+    for (int a = 0; a < 3; ++a)
+        if (!g.unbounded[a] && !(g.L[a] > 0.0)) return MCBTE_EGEOM;
+    for (int i = 0; i < 6; ++i) {
+        if (g.unbounded[kFaceAxis[i]]) continue;
+        const int ty = g.face[i].type;
+        if (ty != MCBTE_ISOTHERMAL && ty != MCBTE_ADIABATIC && ty != MCBTE_PERIODIC) return MCBTE_EGEOM;
+        if (ty == MCBTE_ADIABATIC && !(g.face[i].data[0] >= 0.0 && g.face[i].data[0] <= 1.0)) return MCBTE_EGEOM;
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (g.unbounded[a]) continue;
+        int lo = -1, hi = -1;
+        for (int i = 0; i < 6; ++i)
+            if (kFaceAxis[i] == a) (kFaceSide[i] ? hi : lo) = i;
+        const bool plo = g.face[lo].type == MCBTE_PERIODIC, phi = g.face[hi].type == MCBTE_PERIODIC;
+        if (plo != phi) return MCBTE_EGEOM;
+        if (plo) {   // the translation must carry each face onto its partner
+            for (int b = 0; b < 3; ++b) {
+                const double want_lo = (b == a) ? g.L[a] : 0.0;
+                if (std::fabs(g.face[lo].data[b] - want_lo) > 1e-9 * g.L[a] ||
+                    std::fabs(g.face[hi].data[b] + want_lo) > 1e-9 * g.L[a])
+                    return MCBTE_EGEOM;
+            }
+        }
+    }
+    if (g.n_pores < 0 || g.n_pores > MCBTE_MAX_PORES) return MCBTE_EGEOM;
+    for (int c = 0; c < g.n_pores; ++c) {
+        const mcbte_pore& p = g.pore[c];
+        if (g.unbounded[0] || g.unbounded[1] || !(p.r > 0.0) || p.type != MCBTE_ADIABATIC) return MCBTE_EGEOM;
+        if (!(p.specularity >= 0.0 && p.specularity <= 1.0)) return MCBTE_EGEOM;
+        if (p.cx - p.r < 0.0 || p.cx + p.r > g.L[0] || p.cy - p.r < 0.0 || p.cy + p.r > g.L[1]) return MCBTE_EGEOM;
+        if (p.id < 7 || p.id > 255 || (c > 0 && p.id <= g.pore[c - 1].id)) return MCBTE_EGEOM;
+    }
+    // detectors
+    for (int a = 0; a < 3; ++a)
+        if (dt.n[a] < 0 || (dt.n[a] > 0 && !(dt.hi[a] > dt.lo[a]))) return MCBTE_EINVAL;
+    if (dt.mask < 1 || dt.mask > 15) return MCBTE_EINVAL;
+    // run
+    if (pr.transient) {
+        if (!(pr.t_max > 0.0) || pr.n_times < 1 || !pr.t_meas) return MCBTE_EINVAL;
+        for (int k = 0; k < pr.n_times; ++k)
+            if (!(pr.t_meas[k] >= 0.0) || (k > 0 && !(pr.t_meas[k] >= pr.t_meas[k - 1]))) return MCBTE_EINVAL;
+    } else if (pr.n_ic > 0) {
+        return MCBTE_EINVAL;
+    }
+    if (pr.n_ic < 0 || (pr.n_ic > 0 && (!pr.ic_edges || !pr.ic_dT || pr.ic_axis < 0 || pr.ic_axis > 2 || g.n_pores > 0)))
+        return MCBTE_EINVAL;
+
+    mcbte_tables* t = new (std::nothrow) mcbte_tables();
+    if (!t) return MCBTE_ENOMEM;
+    t->device = device;
+    t->prob = pr;
+    t->prob.t_meas = nullptr;
+    t->prob.ic_edges = nullptr;
+    t->prob.ic_dT = nullptr;
+    t->geom = g;
+    t->det = dt;
+
+    // per-mode heat capacity (first format: DOS x delta-omega x de/dT at T_lin)
+    t->C.resize(M);
+    t->v.resize(M);
+    t->tau.resize(M);
+    for (int m = 0; m < M; ++m) {
+        const mcbte_mode& r = modes[m];
+        if (!(r.v > 0.0) || !(r.tau > 0.0) || r.tau_imp != 0.0) { delete t; return MCBTE_EINVAL; }
+        t->v[m] = r.v;
+        t->tau[m] = r.tau;
+        if (pr.format == 1) {
+            if (!(r.dos >= 0.0) || !(r.domega >= 0.0) || !(r.omega > 0.0)) { delete t; return MCBTE_EINVAL; }
+            t->C[m] = (r.dos * r.domega) * bose_einstein_dedT(r.omega, pr.T_lin);
+        } else {
+            if (!(r.C >= 0.0)) { delete t; return MCBTE_EINVAL; }
+            t->C[m] = r.C;
+        }
+    }
+    double C_tot = 0.0, Wv = 0.0, kb = 0.0;
+    for (int m = 0; m < M; ++m) {
+        C_tot += t->C[m];
+        Wv += t->C[m] * t->v[m];
+        kb += ((t->C[m] * t->v[m]) * t->v[m]) * t->tau[m];
+    }
+    if (!(C_tot > 0.0)) { delete t; return MCBTE_ETABLE; }
+    std::vector<double> w(M);
+    for (int m = 0; m < M; ++m) w[m] = t->C[m];
+    const int64_t last_ic = build_thresholds(w, t->thr_ic);
+    for (int m = 0; m < M; ++m) w[m] = t->C[m] * t->v[m];
+    const int64_t last_wall = build_thresholds(w, t->thr_wall);
+    for (int m = 0; m < M; ++m) w[m] = t->C[m] / t->tau[m];
+    const int64_t last_rel = build_thresholds(w, t->thr_rel);
+    if (last_ic < 0 || last_wall < 0 || last_rel < 0) { delete t; return MCBTE_ETABLE; }
+
+    auto extent = [&](int a) { return g.unbounded[a] ? 1.0 : g.L[a]; };
+    double V = g.volume;
+    if (!(V > 0.0)) {
+        V = (extent(0) * extent(1)) * extent(2);
+        for (int c = 0; c < g.n_pores; ++c) V = V - (kPi * (g.pore[c].r * g.pore[c].r)) * extent(2);
+    }
+    const double gnorm = std::sqrt((g.gradT[0] * g.gradT[0] + g.gradT[1] * g.gradT[1]) + g.gradT[2] * g.gradT[2]);
+
+    if (pr.transient) t->t_meas.assign(pr.t_meas, pr.t_meas + pr.n_times);
+    if (pr.n_ic > 0) {
+        t->ic_edges.assign(pr.ic_edges, pr.ic_edges + pr.n_ic + 1);
+        t->ic_dT.assign(pr.ic_dT, pr.ic_dT + pr.n_ic);
+        for (int c = 0; c < pr.n_ic; ++c)
+            if (!(t->ic_edges[c + 1] > t->ic_edges[c])) { delete t; return MCBTE_EINVAL; }
+    }
+    // sources: isothermal faces by id, the gradient source, initial-condition cells
+    for (int i = 0; i < 6; ++i) {
+        const int a = kFaceAxis[i];
+        if (g.unbounded[a] || g.face[i].type != MCBTE_ISOTHERMAL) continue;
+        const double dT = g.face[i].data[0] - pr.T_lin;
+        if (dT == 0.0) continue;
+        const int b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
+        const double area = extent(b) * extent(c);
+        double E = ((area * std::fabs(dT)) * Wv) / 4.0;     // A |T_b - T_lin| sum C v / 4
+        if (pr.transient) E = E * pr.t_max;
+        t->src_kind.push_back(SRC_WALL);
+        t->src_ref.push_back(i + 1);
+        t->src_sign.push_back(dT > 0.0 ? 1 : -1);
+        t->src_E.push_back(E);
+    }
+    if (gnorm > 0.0) {
+        double E = ((V * gnorm) * Wv) / 2.0;                // V |grad T| sum C v / 2
+        if (pr.transient) E = E * pr.t_max;
+        t->src_kind.push_back(SRC_GRAD);
+        t->src_ref.push_back(0);
+        t->src_sign.push_back(0);
+        t->src_E.push_back(E);
+    }
+    for (int c = 0; c < pr.n_ic; ++c) {
+        const int a = pr.ic_axis;
+        const int b = (a == 0) ? 1 : 0, cc = (a == 2) ? 1 : 2;
+        const double Vc = ((t->ic_edges[c + 1] - t->ic_edges[c]) * extent(b)) * extent(cc);
+        const double E = (C_tot * std::fabs(t->ic_dT[c])) * Vc; // C_tot |dT_c| V_c
+        t->src_kind.push_back(SRC_IC);
+        t->src_ref.push_back(c);
+        t->src_sign.push_back(t->ic_dT[c] > 0.0 ? 1 : -1);
+        t->src_E.push_back(E);
+    }
+    const int S = (int)t->src_E.size();
+    if (S == 0) { delete t; return MCBTE_ETABLE; }
+    double E_tot = 0.0;
+    for (int s = 0; s < S; ++s) E_tot += t->src_E[s];
+    const int64_t last_src = build_thresholds(t->src_E, t->thr_src);
+    if (last_src < 0) { delete t; return MCBTE_ETABLE; }
+
+    int64_t n_cells = 1;
+    for (int a = 0; a < 3; ++a) n_cells *= dt.n[a] > 0 ? dt.n[a] : 1;
+    const int64_t n_cols = pr.transient ? pr.n_times : M;
+
+    mcbte_info& inf = t->info;
+    inf.C_tot = C_tot;
+    inf.sum_Cv = Wv;
+    inf.E_tot = E_tot;
+    inf.e_eff = E_tot / (double)pr.N;
+    inf.V_solid = V;
+    inf.kappa_bulk = kb / 3.0;
+    inf.n_modes = M;
+    inf.n_sources = S;
+    inf.n_cells = n_cells;
+    inf.n_cols = n_cols;
+    inf.tally_bytes = MCBTE_TALLY_HEADER_BYTES + n_cells * n_cols * 4 * (int64_t)sizeof(double);
+    inf.device = device;
+
+    // device view
+    DevTab& h = t->host_view;
+    std::memset(&h, 0, sizeof(h));
+    h.M = M;
+    h.S = S;
+    h.transient = pr.transient ? 1 : 0;
+    h.n_scat_max = pr.n_scat_max;
+    h.score_axis = pr.score_axis;
+    h.n_times = pr.transient ? pr.n_times : 0;
+    h.ic_axis = pr.ic_axis;
+    h.n_ic = pr.n_ic;
+    bool binned = false;
+    for (int a = 0; a < 3; ++a) binned = binned || dt.n[a] > 0;
+    h.tally_kind = pr.transient ? TALLY_TRANSIENT : (binned ? TALLY_STEADY_GRID : TALLY_STEADY_ONE);
+    // film-like problems (one bounded axis with fully diffuse faces, no pores, steady, one detector
+    // cell): a particle with a long free path bounces between the two walls many times in a row,
+    // which the FP32 kernel evaluates 64 bounces at a time with the whole wave
+    h.coop_axis = -1;
+    h.coop_min_path = 0.0;
+    {
+        int nb = 0, axis = -1;
+        for (int a = 0; a < 3; ++a)
+            if (!g.unbounded[a]) { ++nb; axis = a; }
+        if (nb == 1 && g.n_pores == 0 && !pr.transient && h.tally_kind == TALLY_STEADY_ONE) {
+            bool diffuse = true;
+            for (int i = 0; i < 6; ++i)
+                if (kFaceAxis[i] == axis && !(g.face[i].type == MCBTE_ADIABATIC && g.face[i].data[0] == 0.0))
+                    diffuse = false;
+            if (diffuse) {
+                h.coop_axis = axis;
+                h.coop_min_path = 16.0 * g.L[axis];
+            }
+        }
+    }
+    h.max_events = pr.max_events;
+    h.t_max = pr.transient ? pr.t_max : 0.0;
+    h.last_ic = last_ic;
+    h.last_wall = last_wall;
+    h.last_rel = last_rel;
+    h.last_src = last_src;
+    DevGeom& dg = h.g;
+    for (int a = 0; a < 3; ++a) {
+        dg.L[a] = g.unbounded[a] ? 1.0 : g.L[a];
+        dg.L32[a] = (float)dg.L[a];
+        dg.unb[a] = g.unbounded[a] ? 1 : 0;
+        dg.ngrad[a] = gnorm > 0.0 ? -g.gradT[a] / gnorm : 0.0;
+        dg.ngrad32[a] = (float)dg.ngrad[a];
+    }
+    for (int i = 0; i < 6; ++i) {
+        dg.face_type[i] = g.unbounded[kFaceAxis[i]] ? 0 : g.face[i].type;
+        const double d = g.face[i].type == MCBTE_ADIABATIC ? g.face[i].data[0] : 0.0;
+        dg.face_spec[i] = d;
+        dg.face_thr[i] = (d > 0.0 && d < 1.0) ? (uint64_t)(d * kTwo64) : 0;
+    }
+    dg.n_pores = g.n_pores;
+    for (int c = 0; c < g.n_pores; ++c) {
+        const mcbte_pore& p = g.pore[c];
+        dg.pore_cx[c] = p.cx;
+        dg.pore_cy[c] = p.cy;
+        dg.pore_r[c] = p.r;
+        dg.pore_cx32[c] = (float)p.cx;
+        dg.pore_cy32[c] = (float)p.cy;
+        dg.pore_r32[c] = (float)p.r;
+        dg.pore_spec[c] = p.specularity;
+        dg.pore_thr[c] = (p.specularity > 0.0 && p.specularity < 1.0) ? (uint64_t)(p.specularity * kTwo64) : 0;
+        dg.pore_id[c] = p.id;
+    }
+    DevDet& dd = h.det;
+    int nc = 0;
+    for (int q = 0; q < 4; ++q) {
+        dd.slot[q] = -1;
+        dd.comp[q] = 0;
+    }
+    for (int q = 0; q < 4; ++q)
+        if (dt.mask & (1 << q)) { dd.slot[q] = nc; dd.comp[nc] = q; ++nc; }
+    dd.ncomp = nc;
+    dd.mask = dt.mask;
+    dd.n_cols = (int32_t)n_cols;
+    dd.n_cells = n_cells;
+    for (int a = 0; a < 3; ++a) {
+        dd.n[a] = dt.n[a];
+        dd.lo[a] = dt.lo[a];
+        dd.hi[a] = dt.hi[a];
+        dd.w[a] = dt.n[a] > 0 ? (dt.hi[a] - dt.lo[a]) / (double)dt.n[a] : 1.0;
+        dd.lo32[a] = (float)dt.lo[a];
+        dd.hi32[a] = (float)dt.hi[a];
+        dd.inv_w32[a] = (float)(1.0 / dd.w[a]);
+    }
+
+    if (device >= 0) {
+        DeviceGuard guard(device);
+        if (!guard.ok) { delete t; return MCBTE_EHIP; }
+        if (hipDeviceGetAttribute(&t->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+            hipDeviceGetAttribute(&t->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
+            delete t;
+            return MCBTE_EHIP;
+        }
+        // one allocation, 256-byte aligned pieces
+        std::vector<std::pair<const void*, size_t>> parts;
+        auto add = [&](const void* src, size_t bytes) { parts.emplace_back(src, bytes); };
+        std::vector<float> v32(M), tau32(M), tm32(t->t_meas.size());
+        for (int m = 0; m < M; ++m) { v32[m] = (float)t->v[m]; tau32[m] = (float)t->tau[m]; }
+        for (size_t k = 0; k < t->t_meas.size(); ++k) tm32[k] = (float)t->t_meas[k];
+        add(nullptr, sizeof(DevTab));
+        add(t->v.data(), 8 * (size_t)M);
+        add(t->tau.data(), 8 * (size_t)M);
+        add(v32.data(), 4 * (size_t)M);
+        add(tau32.data(), 4 * (size_t)M);
+        add(t->thr_ic.data(), 8 * (size_t)M);
+        add(t->thr_wall.data(), 8 * (size_t)M);
+        add(t->thr_rel.data(), 8 * (size_t)M);
+        add(t->thr_src.data(), 8 * (size_t)S);
+        add(t->src_kind.data(), 4 * (size_t)S);
+        add(t->src_ref.data(), 4 * (size_t)S);
+        add(t->src_sign.data(), 4 * (size_t)S);
+        add(t->ic_edges.data(), 8 * t->ic_edges.size());
+        add(t->t_meas.data(), 8 * t->t_meas.size());
+        add(tm32.data(), 4 * tm32.size());
+        size_t total = 0;
+        std::vector<size_t> off;
+        for (auto& p : parts) {
+            off.push_back(total);
+            total += (p.second + 255) & ~size_t(255);
+        }
+        if (hipMalloc(&t->d_mem, total + 256) != hipSuccess) {
+            t->d_mem = nullptr;
+            delete t;
+            return MCBTE_ENOMEM;
+        }
+        unsigned char* base = (unsigned char*)t->d_mem;
+        auto dptr = [&](int i) { return (void*)(base + off[i]); };
+        h.v64 = (const double*)dptr(1);
+        h.tau64 = (const double*)dptr(2);
+        h.v32 = (const float*)dptr(3);
+        h.tau32 = (const float*)dptr(4);
+        h.thr_ic = (const uint64_t*)dptr(5);
+        h.thr_wall = (const uint64_t*)dptr(6);
+        h.thr_rel = (const uint64_t*)dptr(7);
+        h.thr_src = (const uint64_t*)dptr(8);
+        h.src_kind = (const int32_t*)dptr(9);
+        h.src_ref = (const int32_t*)dptr(10);
+        h.src_sign = (const int32_t*)dptr(11);
+        h.ic_edges = (const double*)dptr(12);
+        h.t_meas64 = (const double*)dptr(13);
+        h.t_meas32 = (const float*)dptr(14);
+        parts[0].first = &h;
+        for (size_t i = 0; i < parts.size(); ++i) {
+            if (parts[i].second == 0) continue;
+            if (hipMemcpy(dptr((int)i), parts[i].first, parts[i].second, hipMemcpyHostToDevice) != hipSuccess) {
+                mcbte_free_tables(t);
+                return MCBTE_EHIP;
+            }
+        }
+        t->d_tab = (DevTab*)dptr(0);
+    }
+    *out = t;
+    return MCBTE_OK;
+}
+
+int mcbte_table_info(const mcbte_tables* t, mcbte_info* info)
+{
+    if (!t || !info) return MCBTE_EINVAL;
+    *info = t->info;
+    return MCBTE_OK;
+}
+
+int mcbte_table_export(const mcbte_tables* t, int32_t which, void* out, int64_t n)
+{
+    if (!t || !out) return MCBTE_EINVAL;
+    auto put = [&](const void* src, int64_t count, size_t elem) {
+        if (n < count) return MCBTE_ESIZE;
+        std::memcpy(out, src, (size_t)count * elem);
+        return MCBTE_OK;
+    };
+    const int64_t M = t->info.n_modes, S = t->info.n_sources;
+    switch (which) {
+    case 0: return put(t->C.data(), M, 8);
+    case 1: return put(t->thr_ic.data(), M, 8);
+    case 2: return put(t->thr_wall.data(), M, 8);
+    case 3: return put(t->thr_rel.data(), M, 8);
+    case 4: return put(t->src_E.data(), S, 8);
+    case 5: return put(t->thr_src.data(), S, 8);
+    case 6: return put(t->src_sign.data(), S, 4);
+    default: return MCBTE_EINVAL;
+    }
+}
+
+int64_t mcbte_state_bytes(int32_t precision, int64_t cap)
+{
+    if ((precision != 32 && precision != 64) || cap < 0) return MCBTE_EINVAL;
+    const int64_t rb = precision / 8;
+    const int64_t fb = (cap * rb + 255) & ~int64_t(255);
+    const int64_t ib = (cap * 4 + 255) & ~int64_t(255);
+    return 8 * fb + 7 * ib;
+}
+
+int mcbte_emit(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, int64_t n, void* state,
+               int64_t capacity, void* stream)
+{
+    if (!t || !run || n < 0 || first_pid < 0 || capacity < n || (n > 0 && !state)) return MCBTE_EINVAL;
+    if (run->precision != 32 && run->precision != 64) return MCBTE_EINVAL;
+    if (t->device < 0 || !t->d_tab) return MCBTE_ENODEV;
+    DeviceGuard g(t->device);
+    if (!g.ok) return MCBTE_EHIP;
+    const hipError_t e = launch_emit(t->d_tab, run->precision, run->seed, run->instance, first_pid, n, state, capacity,
+                                     (hipStream_t)stream);
+    return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
+}
+
+namespace {
+
+struct LaunchPlan {
+    int block, grid, refill;
+    int tally_lds;
+    int64_t lds_tab;
+    size_t lds;
+};
+
+int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run, bool batch, LaunchPlan& lp)
+{
+    const mcbte_tables* t0 = ts[0];
+    const int prec = run->precision;
+    const int rb = prec / 8;
+    int64_t lds_tab = 0, lds_tally = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        const int64_t M = ts[i]->info.n_modes;
+        lds_tab = std::max<int64_t>(lds_tab, ((M * 8 + 15) & ~int64_t(15)) + 2 * ((M * rb + 15) & ~int64_t(15)));
+        lds_tally = std::max<int64_t>(lds_tally, ts[i]->info.n_cells * ts[i]->info.n_cols *
+                                                     (int64_t)ts[i]->host_view.det.ncomp * 8);
+    }
+    if (lds_tab > MCBTE_LDS_TABLE_BYTES || lds_tab > t0->max_lds) return MCBTE_EINVAL;
+    lp.lds_tab = lds_tab;
+    lp.tally_lds = (lds_tally <= MCBTE_LDS_TALLY_BYTES && lds_tab + lds_tally <= t0->max_lds) ? 1 : 0;
+    lp.lds = (size_t)(lds_tab + (lp.tally_lds ? lds_tally : 0));
+    lp.block = run->block > 0 ? run->block : 256;
+    if (lp.block % 64 != 0 || lp.block > 256) return MCBTE_EINVAL;
+    lp.refill = run->refill > 0 ? run->refill : 4;
+    if (run->grid > 0) {
+        lp.grid = run->grid;
+    } else {
+        const int occ = trace_occupancy(batch, prec, t0->host_view.tally_kind, lp.block, lp.lds);
+        lp.grid = std::max(1, occ) * std::max(1, t0->n_cu);
+    }
+    return MCBTE_OK;
+}
+
+}  // namespace
+
+int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, int64_t n, const void* state,
+                void* tally, void* stream)
+{
+    if (!t || !run || !tally || n < 0 || first_pid < 0) return MCBTE_EINVAL;
+    if (run->precision != 32 && run->precision != 64) return MCBTE_EINVAL;
+    if (run->event_log && (run->log_stride < 2 || run->n_log < 0)) return MCBTE_EINVAL;
+    if (t->device < 0 || !t->d_tab) return MCBTE_ENODEV;
+    if (n == 0) return MCBTE_OK;
+    DeviceGuard g(t->device);
+    if (!g.ok) return MCBTE_EHIP;
+    LaunchPlan lp;
+    const int rc = plan_launch(&t, 1, run, false, lp);
+    if (rc != MCBTE_OK) return rc;
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.tabs = t->d_tab;
+    a.n_inst = 1;
+    a.refill = lp.refill;
+    a.seed = run->seed;
+    a.inst0 = run->instance;
+    a.log_stride = run->event_log ? run->log_stride : 2;
+    a.first_pid = first_pid;
+    a.n = n;
+    a.state = state;
+    a.capacity = n;
+    a.tally = (unsigned char*)tally;
+    a.event_log = run->event_log;
+    a.n_log = run->event_log ? run->n_log : 0;
+    a.tally_lds = lp.tally_lds;
+    a.lds_tab_bytes = (int32_t)lp.lds_tab;
+    const hipError_t e = launch_trace(a, false, run->precision, t->host_view.tally_kind, lp.block, lp.grid, lp.lds,
+                                      (hipStream_t)stream);
+    return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
+}
+
+int64_t mcbte_batch_queue_bytes(int32_t n_inst)
+{
+    if (n_inst < 1) return MCBTE_EINVAL;
+    auto al = [](int64_t b) { return (b + 255) / 256 * 256; };
+    const int64_t n = n_inst;
+    // queue counter | tally pointers | particle counts | chunk starts | instance ids | tables
+    return 256 + al(8 * n) + al(8 * n) + al(8 * (n + 1)) + al(4 * n) + al((int64_t)sizeof(DevTab) * n);
+}
+
+int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64_t* n_particles,
+                      const uint32_t* instance_ids, void* const* tallies, const mcbte_run* run, void* queue,
+                      void* stream)
+{
+    if (!ts || n_inst < 1 || !n_particles || !instance_ids || !tallies || !run || !queue) return MCBTE_EINVAL;
+    if (run->precision != 32 && run->precision != 64) return MCBTE_EINVAL;
+    if (run->event_log) return MCBTE_EINVAL;
+    const mcbte_tables* t0 = ts[0];
+    if (!t0 || t0->device < 0) return MCBTE_ENODEV;
+    for (int i = 0; i < n_inst; ++i) {
+        if (!ts[i] || !tallies[i] || n_particles[i] < 0) return MCBTE_EINVAL;
+        if (ts[i]->device != t0->device || !ts[i]->d_tab) return MCBTE_ENODEV;
+        if (ts[i]->host_view.tally_kind != t0->host_view.tally_kind) return MCBTE_EINVAL;
+    }
+    DeviceGuard g(t0->device);
+    if (!g.ok) return MCBTE_EHIP;
+    LaunchPlan lp;
+    int rc = plan_launch(ts, n_inst, run, true, lp);
+    if (rc != MCBTE_OK) return rc;
+    // chunking: items of chunk_size particles, instance-major
+    const int64_t chunk = 8192;
+    std::vector<int64_t> cstart(n_inst + 1, 0);
+    for (int i = 0; i < n_inst; ++i) cstart[i + 1] = cstart[i] + (n_particles[i] + chunk - 1) / chunk;
+    // pack the small device-side arrays into the caller's queue buffer (one host->device copy)
+    const int64_t qbytes = mcbte_batch_queue_bytes(n_inst);
+    std::vector<unsigned char> host((size_t)qbytes, 0);
+    size_t off = 256;
+    auto place = [&](const void* src, size_t bytes) {
+        const size_t at = off;
+        std::memcpy(host.data() + at, src, bytes);
+        off = (off + bytes + 255) & ~size_t(255);
+        return at;
+    };
+    std::vector<unsigned char*> tp(n_inst);
+    for (int i = 0; i < n_inst; ++i) tp[i] = (unsigned char*)tallies[i];
+    const size_t o_tp = place(tp.data(), 8 * (size_t)n_inst);
+    const size_t o_n = place(n_particles, 8 * (size_t)n_inst);
+    const size_t o_cs = place(cstart.data(), 8 * (size_t)(n_inst + 1));
+    const size_t o_id = place(instance_ids, 4 * (size_t)n_inst);
+    std::vector<DevTab> tabs(n_inst);
+    for (int i = 0; i < n_inst; ++i) tabs[i] = ts[i]->host_view;
+    const size_t o_tab = place(tabs.data(), sizeof(DevTab) * (size_t)n_inst);
+    if ((int64_t)off > qbytes) return MCBTE_ESIZE;
+    unsigned char* qd = (unsigned char*)queue;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(qd, host.data(), (size_t)off, hipMemcpyHostToDevice, s) != hipSuccess) return MCBTE_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return MCBTE_EHIP;   // `host` is a local buffer
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.tabs = (const DevTab*)(qd + o_tab);
+    a.n_inst = n_inst;
+    a.refill = lp.refill;
+    a.seed = run->seed;
+    a.inst_ids = (const uint32_t*)(qd + o_id);
+    a.log_stride = 2;
+    a.tallies = (unsigned char* const*)(qd + o_tp);
+    a.inst_n = (const int64_t*)(qd + o_n);
+    a.chunk_start = (const int64_t*)(qd + o_cs);
+    a.chunk_size = chunk;
+    a.queue = (unsigned long long*)qd;
+    a.n_chunks = cstart[n_inst];
+    a.tally_lds = lp.tally_lds;
+    a.lds_tab_bytes = (int32_t)lp.lds_tab;
+    const hipError_t e = launch_trace(a, true, run->precision, t0->host_view.tally_kind, lp.block, lp.grid, lp.lds, s);
+    return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
+}
+
+int mcbte_tally(const mcbte_tables* t, const void* tally, double* host_out, int64_t n_out, mcbte_result* res,
+                void* stream)
+{
+    if (!t || !tally || !res) return MCBTE_EINVAL;
+    if (t->device < 0) return MCBTE_ENODEV;
+    const int64_t n_raw = t->info.n_cells * t->info.n_cols * 4;
+    if (host_out && n_out < n_raw) return MCBTE_ESIZE;
+    DeviceGuard g(t->device);
+    if (!g.ok) return MCBTE_EHIP;
+    std::vector<unsigned char> buf((size_t)t->info.tally_bytes);
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(buf.data(), tally, buf.size(), hipMemcpyDeviceToHost, s) != hipSuccess) return MCBTE_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return MCBTE_EHIP;
+    std::memset(res, 0, sizeof(*res));
+    std::memcpy(res->counts, buf.data(), sizeof(res->counts));
+    std::memcpy(res->moments, buf.data() + 128, sizeof(res->moments));
+    const double* raw = (const double*)(buf.data() + MCBTE_TALLY_HEADER_BYTES);
+    const double n = (double)res->counts[MCBTE_CNT_PARTICLES];
+    if (n <= 0.0) return MCBTE_OK;
+    const mcbte_info& inf = t->info;
+    const double e = inf.E_tot / n;
+    double Vc = 1.0;
+    bool binned = false;
+    for (int a = 0; a < 3; ++a) {
+        if (t->det.n[a] > 0) {
+            binned = true;
+            Vc *= (t->det.hi[a] - t->det.lo[a]) / (double)t->det.n[a];
+        } else if (!t->geom.unbounded[a]) {
+            Vc *= t->geom.L[a];
+        }
+    }
+    if (!binned) Vc = inf.V_solid;
+    res->e_eff = e;
+    res->V_cell = Vc;
+    if (host_out) {
+        const double sT = e / (inf.C_tot * Vc), sq = e / Vc;
+        for (int64_t i = 0; i < n_raw; i += 4) {
+            host_out[i] = sT * raw[i];
+            host_out[i + 1] = sq * raw[i + 1];
+            host_out[i + 2] = sq * raw[i + 2];
+            host_out[i + 3] = sq * raw[i + 3];
+        }
+    }
+    if (!t->prob.transient && n > 1.0) {
+        const double* m = res->moments;
+        const double var_T = std::max(m[1] - m[0] * m[0] / n, 0.0) / (n - 1.0);
+        const double var_q = std::max(m[3] - m[2] * m[2] / n, 0.0) / (n - 1.0);
+        res->T_mean = inf.E_tot / (inf.C_tot * inf.V_solid) * m[0] / n;
+        res->T_mean_sigma = inf.E_tot / (inf.C_tot * inf.V_solid) * std::sqrt(var_T / n);
+        res->q_score = inf.E_tot / inf.V_solid * m[2] / n;
+        res->q_score_sigma = inf.E_tot / inf.V_solid * std::sqrt(var_q / n);
+        const double gs = t->geom.gradT[t->prob.score_axis];
+        if (gs != 0.0) {
+            res->kappa = -res->q_score / gs;
+            res->kappa_sigma = res->q_score_sigma / std::fabs(gs);
+            double box = 1.0;
+            for (int a = 0; a < 3; ++a) box *= t->geom.unbounded[a] ? 1.0 : t->geom.L[a];
+            res->kappa_cell_avg = res->kappa * inf.V_solid / box;
+        }
+    }
+    return MCBTE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1240 @@
+// HIP kernels (gfx950) of the deviational phonon Monte Carlo tracer.
+//
+// One engine, templated on the trajectory precision R (double: FP64 form, bit-for-bit the
+// event sequence of the method's steps as spelled out in the design notes; float: FP32 form,
+// tables built and tallies summed in FP64), drives three kernels:
+//   k_emit        one lane per particle, writes the emitted state (section 3.2)
+//   k_trace_solo  persistent lanes; a lane whose particle ended is refilled every `refill`
+//                 flights from a global counter (wave ballot + prefix popcount, one atomic per
+//                 wave); relaxation table, velocities and relaxation times staged in LDS;
+//                 tallies privatised in LDS when they fit, then flushed with FP64 atomics
+//   k_trace_batch the same lanes over many problem instances: workgroups pull (instance,
+//                 particle-chunk) items from a queue, re-stage the tables when the instance
+//                 changes and flush that instance's tallies before moving on.
+// Nothing here is a dense contraction: the path is bound by plain vector ALU work (Philox,
+// transcendentals, divisions) and LDS traffic, not by MFMA or HBM.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <type_traits>
+
+#include "mcbte_dev.h"
+
+namespace mcbte {
+
+// ------------------------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------------------------
+
+// boundary id - 1 -> (axis, side) in the paper's boundary-table order
+__device__ __forceinline__ constexpr int face_axis(int i) { return (i == 1 || i == 3) ? 0 : (i == 0 || i == 2) ? 1 : 2; }
+__device__ __forceinline__ constexpr int face_side(int i) { return (i == 1 || i == 2 || i == 5) ? 1 : 0; }
+
+__host__ __device__ __forceinline__ int64_t align16(int64_t x) { return (x + 15) & ~int64_t(15); }
+
+struct W4 { uint32_t x, y, z, w; };
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64 products
+// (v_mad_u64_u32) and two three-way XORs; the key schedule is wave-uniform.
+__device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return W4{c0, c1, c2, c3};
+}
+
+// The random stream of one particle: counter = (block, pid_lo, pid_hi, instance), key = seed.
+// Record r is blocks 2r (words W0..W3) and 2r + 1 (W4..W7).
+struct Stream {
+    uint32_t k0, k1, plo, phi, inst;
+    __device__ __forceinline__ W4 block(uint32_t b) const { return philox10(b, plo, phi, inst, k0, k1); }
+};
+
+__device__ __forceinline__ uint64_t key64(uint32_t hi, uint32_t lo) { return ((uint64_t)hi << 32) | (uint64_t)lo; }
+
+template <typename R> __device__ __forceinline__ R unif(uint32_t hi, uint32_t lo);
+// FP64: 53 bits of the 64-bit key, u in [0, 1 - 2^-53]
+template <> __device__ __forceinline__ double unif<double>(uint32_t hi, uint32_t lo)
+{
+    return (double)(key64(hi, lo) >> 11) * 0x1p-53;
+}
+// FP32: the top 24 of those 53 bits (common random numbers with the FP64 form)
+template <> __device__ __forceinline__ float unif<float>(uint32_t hi, uint32_t)
+{
+    return (float)(hi >> 8) * 0x1p-24f;
+}
+
+// FP64: correctly rounded arithmetic and the device math library (the event sequence of the
+// method's spelled-out steps).  FP32: the hardware approximations (v_rcp_f32, v_sqrt_f32,
+// v_log_f32, v_sin_f32 / v_cos_f32, about 1 ulp each); the FP32 form is compared with the oracle
+// by tolerance, and its discrete choices still come from the same 64-bit keys.
+__device__ __forceinline__ double r_log(double x) { return log(x); }
+__device__ __forceinline__ float r_log(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+__device__ __forceinline__ double r_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float r_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double r_div(double a, double b) { return a / b; }
+__device__ __forceinline__ float r_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ void r_sincos_2pi(double u, double* s, double* c)
+{
+    const double phi = 6.283185307179586 * u;
+    *s = sin(phi);
+    *c = cos(phi);
+}
+// v_sin_f32 / v_cos_f32 take their argument in revolutions: sin(2 pi u) directly, u in [0, 1)
+__device__ __forceinline__ void r_sincos_2pi(float u, float* s, float* c)
+{
+    *s = __builtin_amdgcn_sinf(u);
+    *c = __builtin_amdgcn_cosf(u);
+}
+
+template <typename R> struct Geo;
+template <> struct Geo<double> {
+    static __device__ __forceinline__ double L(const DevGeom& g, int a) { return g.L[a]; }
+    static __device__ __forceinline__ double cx(const DevGeom& g, int i) { return g.pore_cx[i]; }
+    static __device__ __forceinline__ double cy(const DevGeom& g, int i) { return g.pore_cy[i]; }
+    static __device__ __forceinline__ double r(const DevGeom& g, int i) { return g.pore_r[i]; }
+    static __device__ __forceinline__ double ng(const DevGeom& g, int a) { return g.ngrad[a]; }
+    static __device__ __forceinline__ double dlo(const DevDet& d, int a) { return d.lo[a]; }
+    static __device__ __forceinline__ double dhi(const DevDet& d, int a) { return d.hi[a]; }
+    static __device__ __forceinline__ double dw(const DevDet& d, int a) { return d.w[a]; }
+    // cell index of a coordinate: floor((x - lo) / w), exactly as the method's detector binning
+    static __device__ __forceinline__ double cellf(const DevDet& d, int a, double x) { return floor((x - d.lo[a]) / d.w[a]); }
+    static __device__ __forceinline__ double tmeas(const DevTab& t, int k) { return t.t_meas64[k]; }
+    static __device__ __forceinline__ const double* v(const DevTab& t) { return t.v64; }
+    static __device__ __forceinline__ const double* tau(const DevTab& t) { return t.tau64; }
+};
+template <> struct Geo<float> {
+    static __device__ __forceinline__ float L(const DevGeom& g, int a) { return g.L32[a]; }
+    static __device__ __forceinline__ float cx(const DevGeom& g, int i) { return g.pore_cx32[i]; }
+    static __device__ __forceinline__ float cy(const DevGeom& g, int i) { return g.pore_cy32[i]; }
+    static __device__ __forceinline__ float r(const DevGeom& g, int i) { return g.pore_r32[i]; }
+    static __device__ __forceinline__ float ng(const DevGeom& g, int a) { return g.ngrad32[a]; }
+    static __device__ __forceinline__ float dlo(const DevDet& d, int a) { return d.lo32[a]; }
+    static __device__ __forceinline__ float dhi(const DevDet& d, int a) { return d.hi32[a]; }
+    static __device__ __forceinline__ float dw(const DevDet& d, int a) { return (float)d.w[a]; }
+    static __device__ __forceinline__ float cellf(const DevDet& d, int a, float x) { return floorf((x - d.lo32[a]) * d.inv_w32[a]); }
+    static __device__ __forceinline__ float tmeas(const DevTab& t, int k) { return t.t_meas32[k]; }
+    static __device__ __forceinline__ const float* v(const DevTab& t) { return t.v32; }
+    static __device__ __forceinline__ const float* tau(const DevTab& t) { return t.tau32; }
+};
+
+// first index j with K < thr[j] (thresholds non-decreasing), else `last`: a fixed number of
+// halving steps, so all lanes of a wave run the same instructions
+__device__ __forceinline__ int cdf_pick(const uint64_t* thr, int n, int64_t last, uint64_t K)
+{
+    int lo = 0;
+    int step = 1;
+    while (step * 2 <= n) step *= 2;
+    for (; step > 0; step >>= 1) {
+        const int probe = lo + step;
+        if (probe <= n && thr[probe - 1] <= K) lo = probe;
+    }
+    return lo < n ? lo : (int)last;
+}
+
+template <typename R> struct Part {
+    R x[3], o[3];
+    R t, dtr;            // time, remaining free-flight time
+    int32_t m, s, nrel;  // mode row, sign, relaxations so far
+    uint32_t k, j;       // segments so far, random-number-drawing events so far
+    int32_t src;         // source element (event log only)
+    double cT, cq;       // per-particle contributions (variance estimate)
+};
+
+// cosine-weighted direction about the unit normal n (Eq. wall_dir), frame t1 = e_j x n / |.|
+// with j the first axis of smallest |n_j|, t2 = n x t1
+template <typename R>
+__device__ __forceinline__ void dir_about(R mu, R a, R b, const R n[3], R o[3])
+{
+    int j = 0;
+    R m0 = fabs(n[0]);
+    if (fabs(n[1]) < m0) { j = 1; m0 = fabs(n[1]); }
+    if (fabs(n[2]) < m0) j = 2;
+    const R e0 = j == 0 ? R(1) : R(0), e1 = j == 1 ? R(1) : R(0), e2 = j == 2 ? R(1) : R(0);
+    R c0 = e1 * n[2] - e2 * n[1];
+    R c1 = e2 * n[0] - e0 * n[2];
+    R c2 = e0 * n[1] - e1 * n[0];
+    const R len = r_sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    const R t10 = r_div(c0, len), t11 = r_div(c1, len), t12 = r_div(c2, len);
+    const R t20 = n[1] * t12 - n[2] * t11;
+    const R t21 = n[2] * t10 - n[0] * t12;
+    const R t22 = n[0] * t11 - n[1] * t10;
+    o[0] = mu * n[0] + a * t10 + b * t20;
+    o[1] = mu * n[1] + a * t11 + b * t21;
+    o[2] = mu * n[2] + a * t12 + b * t22;
+}
+
+template <typename R>
+__device__ __forceinline__ void dir_cos(R u1, R u2, const R n[3], R o[3])
+{
+    const R mu = r_sqrt(u1);
+    const R st = r_sqrt(R(1) - u1);
+    R sn, cs;
+    r_sincos_2pi(u2, &sn, &cs);
+    dir_about(mu, st * cs, st * sn, n, o);
+}
+
+template <typename R>
+__device__ __forceinline__ void dir_iso(R u1, R u2, R o[3])
+{
+    const R mu = R(1) - R(2) * u1;
+    const R s2 = (R(1) - mu) * (R(1) + mu);
+    const R st = r_sqrt(s2 > R(0) ? s2 : R(0));
+    R sn, cs;
+    r_sincos_2pi(u2, &sn, &cs);
+    o[0] = st * cs;
+    o[1] = st * sn;
+    o[2] = mu;
+}
+
+// ------------------------------------------------------------------------------------------
+// emission (section 3.2)
+// ------------------------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st, Part<R>& p, uint32_t& rejections)
+{
+    const DevGeom& g = T.g;
+    const W4 r0a = st.block(0), r0b = st.block(1), r1a = st.block(2), r1b = st.block(3);
+    const int src = cdf_pick(T.thr_src, T.S, T.last_src, key64(r0a.x, r0a.y));
+    const int kind = T.src_kind[src];
+    R up[3] = {unif<R>(r1a.z, r1a.w), unif<R>(r1b.x, r1b.y), unif<R>(r1b.z, r1b.w)};
+    const R ud1 = unif<R>(r0b.x, r0b.y), ud2 = unif<R>(r0b.z, r0b.w);
+    W4 r2a = {0u, 0u, 0u, 0u};
+    if (kind == SRC_GRAD || (T.transient && kind != SRC_IC)) r2a = st.block(4);
+    p.src = src;
+    p.nrel = 0;
+    p.k = 0;
+    p.j = 0;
+    p.cT = 0.0;
+    p.cq = 0.0;
+    if (kind == SRC_WALL) {
+        const int fid = T.src_ref[src] - 1;
+        const int a = face_axis(fid), side = face_side(fid);
+        const int b = (a == 0) ? 1 : 0;
+        R n[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const R L = Geo<R>::L(g, ax);
+            const R u = (ax == b) ? up[0] : up[1];
+            p.x[ax] = (ax == a) ? (side ? L : R(0)) : (g.unb[ax] ? R(0) : u * L);
+            n[ax] = (ax == a) ? (side ? R(-1) : R(1)) : R(0);
+        }
+        dir_cos(ud1, ud2, n, p.o);
+        p.s = T.src_sign[src];
+        p.m = cdf_pick(T.thr_wall, T.M, T.last_wall, key64(r1a.x, r1a.y));
+    } else if (kind == SRC_GRAD) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) p.x[ax] = g.unb[ax] ? R(0) : up[ax] * Geo<R>::L(g, ax);
+        for (uint32_t attempt = 1; g.n_pores > 0; ++attempt) {   // positions inside pores are redrawn
+            bool inside = false;
+            for (int c = 0; c < g.n_pores; ++c) {
+                const R dx = p.x[0] - Geo<R>::cx(g, c), dy = p.x[1] - Geo<R>::cy(g, c);
+                const R r = Geo<R>::r(g, c);
+                if (dx * dx + dy * dy < r * r) inside = true;
+            }
+            if (!inside || attempt > 4096) break;
+            ++rejections;
+            const uint32_t blk = 2u * (0x40000000u + attempt);
+            const W4 qa = st.block(blk), qb = st.block(blk + 1u);
+            const R ua[3] = {unif<R>(qa.z, qa.w), unif<R>(qb.x, qb.y), unif<R>(qb.z, qb.w)};
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) p.x[ax] = g.unb[ax] ? R(0) : ua[ax] * Geo<R>::L(g, ax);
+        }
+        const R n[3] = {Geo<R>::ng(g, 0), Geo<R>::ng(g, 1), Geo<R>::ng(g, 2)};
+        dir_cos(ud1, ud2, n, p.o);
+        p.s = (r2a.x >> 31) ? -1 : 1;     // both signs equally likely; a negative particle travels reversed
+        if (p.s < 0) {
+            p.o[0] = -p.o[0];
+            p.o[1] = -p.o[1];
+            p.o[2] = -p.o[2];
+        }
+        p.m = cdf_pick(T.thr_wall, T.M, T.last_wall, key64(r1a.x, r1a.y));
+    } else {
+        const int c = T.src_ref[src];
+        const int ia = T.ic_axis;
+        const R e0 = (R)T.ic_edges[c];
+        const R width = (R)(T.ic_edges[c + 1] - T.ic_edges[c]);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+            p.x[ax] = (ax == ia) ? e0 + up[ax] * width : (g.unb[ax] ? R(0) : up[ax] * Geo<R>::L(g, ax));
+        dir_iso(ud1, ud2, p.o);
+        p.s = T.src_sign[src];
+        p.m = cdf_pick(T.thr_ic, T.M, T.last_ic, key64(r1a.x, r1a.y));
+    }
+    p.t = (T.transient && kind != SRC_IC) ? unif<R>(r2a.z, r2a.w) * (R)T.t_max : R(0);
+    const R tau = Geo<R>::tau(T)[p.m];
+    p.dtr = -tau * r_log(R(1) - unif<R>(r0a.z, r0a.w));
+}
+
+// ------------------------------------------------------------------------------------------
+// tallies
+// ------------------------------------------------------------------------------------------
+
+struct TallyCtx {
+    double* lds;     // compact per-workgroup copy (ncomp components per cell-column) or NULL
+    double* glob;    // raw sums in the tally buffer, 4 components per cell-column
+};
+
+__device__ __forceinline__ void tadd(const TallyCtx& tc, const DevDet& D, int64_t cc, int q, double val)
+{
+    if (tc.lds) atomicAdd(tc.lds + cc * D.ncomp + D.slot[q], val);
+    else atomicAdd(tc.glob + cc * 4 + q, val);
+}
+
+template <typename R>
+__device__ __forceinline__ void add4(const TallyCtx& tc, const DevDet& D, int64_t cc, R sg, R l, R vm, const R o[3])
+{
+    const int mask = D.mask;
+    if (mask & 1) tadd(tc, D, cc, 0, (double)(sg * r_div(l, vm)));
+    if (mask & 2) tadd(tc, D, cc, 1, (double)(sg * (l * o[0])));
+    if (mask & 4) tadd(tc, D, cc, 2, (double)(sg * (l * o[1])));
+    if (mask & 8) tadd(tc, D, cc, 3, (double)(sg * (l * o[2])));
+}
+
+// steady track-length estimator (Eqs. temp_steady, flux_x_steady) for the segment x0 + s o,
+// s in [0, d]: the pieces between consecutive detector-cell planes, each scored in the cell of
+// its midpoint; the plane parameters (lo + j w - x0) / o are the same numbers the method's
+// sorted-crossing description produces, visited in increasing order per axis
+template <typename R>
+__device__ __forceinline__ void tally_grid(const DevTab& T, const TallyCtx& tc, const R x0[3], const R o[3], R d,
+                                           int m, R sg, R vm)
+{
+    const DevDet& D = T.det;
+    if (!(d > R(0))) return;
+    R s_lo = R(0), s_hi = d;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (D.n[a] <= 0) continue;
+        const R lo = Geo<R>::dlo(D, a), hi = Geo<R>::dhi(D, a);
+        if (o[a] == R(0)) {
+            if (x0[a] < lo || x0[a] > hi) return;
+        } else {
+            R s1 = r_div(lo - x0[a], o[a]);
+            R s2 = r_div(hi - x0[a], o[a]);
+            if (s1 > s2) { const R tt = s1; s1 = s2; s2 = tt; }
+            if (s1 > s_lo) s_lo = s1;
+            if (s2 < s_hi) s_hi = s2;
+        }
+    }
+    if (!(s_hi > s_lo)) return;
+    const R INF = R(1) / R(0);
+    int jn[3];
+    R sn[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        jn[a] = 0;
+        sn[a] = INF;
+        const int n = D.n[a];
+        if (n <= 1 || o[a] == R(0)) continue;
+        const R lo = Geo<R>::dlo(D, a), w = Geo<R>::dw(D, a);
+        const int dir = o[a] > R(0) ? 1 : -1;
+        // guess from the entry point, then correct so that j is the first plane (in travel
+        // order) whose parameter exceeds s_lo
+        // entry cell (clamped: a segment may start exactly on the outer faces of the grid), then
+        // the plane ahead of it
+        const R xs = x0[a] + o[a] * s_lo;
+        int ic = (int)floor((double)((xs - lo) / w));
+        ic = ic < 0 ? 0 : (ic > n - 1 ? n - 1 : ic);
+        int j = ic + (dir > 0 ? 1 : 0);
+        for (int it = 0; it < 4; ++it) {
+            const int jb = j - dir;
+            if (jb >= 1 && jb <= n - 1 && r_div(lo + (R)jb * w - x0[a], o[a]) > s_lo) j = jb;
+            else break;
+        }
+        for (int it = 0; it < 4; ++it) {
+            if (j >= 1 && j <= n - 1 && !(r_div(lo + (R)j * w - x0[a], o[a]) > s_lo)) j += dir;
+            else break;
+        }
+        jn[a] = j;
+        if (j >= 1 && j <= n - 1) sn[a] = r_div(lo + (R)j * w - x0[a], o[a]);
+    }
+    R s_cur = s_lo;
+    for (int guard = 0; guard < 1 << 20; ++guard) {
+        R s_n = s_hi;
+        if (sn[0] < s_n) s_n = sn[0];
+        if (sn[1] < s_n) s_n = sn[1];
+        if (sn[2] < s_n) s_n = sn[2];
+        const R l = s_n - s_cur;
+        if (l > R(0)) {
+            const R mid = R(0.5) * (s_cur + s_n);
+            int64_t cell = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int n = D.n[a] > 0 ? D.n[a] : 1;
+                int64_t ci = 0;
+                if (D.n[a] > 0) {
+                    const R xa = x0[a] + o[a] * mid;
+                    const R f = Geo<R>::cellf(D, a, xa);
+                    ci = (int64_t)f;
+                    ci = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
+                }
+                cell = cell * n + ci;
+            }
+            add4(tc, D, cell * D.n_cols + m, sg, l, vm, o);
+        }
+        if (!(s_n < s_hi)) break;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (sn[a] == s_n) {
+                const int dir = o[a] > R(0) ? 1 : -1;
+                jn[a] += dir;
+                const int j = jn[a];
+                sn[a] = (j >= 1 && j <= D.n[a] - 1)
+                            ? r_div(Geo<R>::dlo(D, a) + (R)j * Geo<R>::dw(D, a) - x0[a], o[a]) : INF;
+            }
+        }
+        s_cur = s_n;
+    }
+}
+
+// transient snapshot estimator (Eq. sampling): every measurement time t_k in [t0, t1)
+template <typename R>
+__device__ __forceinline__ void tally_snap(const DevTab& T, const TallyCtx& tc, const R x0[3], const R o[3], R t0, R t1,
+                                           R vm, R sg)
+{
+    const DevDet& D = T.det;
+    const int nt = T.n_times;
+    int lo = 0, hi = nt;                       // first k with t_k >= t0
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (Geo<R>::tmeas(T, mid) < t0) lo = mid + 1;
+        else hi = mid;
+    }
+    for (int k = lo; k < nt; ++k) {
+        const R tk = Geo<R>::tmeas(T, k);
+        if (!(tk < t1)) break;
+        const R dist = vm * (tk - t0);
+        int64_t cell = 0;
+        bool inside = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int n = D.n[a] > 0 ? D.n[a] : 1;
+            int64_t ci = 0;
+            if (D.n[a] > 0) {
+                const R xa = x0[a] + o[a] * dist;
+                if (xa < Geo<R>::dlo(D, a) || xa > Geo<R>::dhi(D, a)) inside = false;
+                const R f = Geo<R>::cellf(D, a, xa);
+                ci = (int64_t)f;
+                ci = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
+            }
+            cell = cell * n + ci;
+        }
+        if (!inside) continue;
+        const int64_t cc = cell * D.n_cols + k;
+        const int mask = D.mask;
+        if (mask & 1) tadd(tc, D, cc, 0, (double)sg);
+        if (mask & 2) tadd(tc, D, cc, 1, (double)(sg * (vm * o[0])));
+        if (mask & 4) tadd(tc, D, cc, 2, (double)(sg * (vm * o[1])));
+        if (mask & 8) tadd(tc, D, cc, 3, (double)(sg * (vm * o[2])));
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// one flight (sections 3.3 and 3.5)
+// ------------------------------------------------------------------------------------------
+
+enum : uint32_t {
+    EV_EMIT_POS = 0, EV_RELAX = 1, EV_SPECULAR = 2, EV_DIFFUSE = 3, EV_PERIODIC = 4, EV_ABSORB = 5,
+    EV_TIMEOUT = 6, EV_NSCAT = 7, EV_CAP = 8, EV_EMIT_NEG = 9, EV_ESCAPE = 10
+};
+
+struct LaneCounts {
+    uint32_t c[12];
+};
+
+struct LogRow {
+    uint32_t* row;   // NULL: not logged
+    int32_t n;
+    int32_t stride;
+    __device__ __forceinline__ void put(uint32_t ev, int bnd, int m)
+    {
+        if (row) {
+            const uint32_t b = (uint32_t)(bnd > 255 ? 255 : bnd);
+            if (n + 1 < stride) row[1 + n] = (ev << 28) | (b << 20) | ((uint32_t)m & 0xFFFFFu);
+            ++n;
+        }
+    }
+};
+
+template <typename R>
+struct Tabs {
+    const uint64_t* thr_rel;   // LDS
+    const R* v;                // LDS
+    const R* tau;              // LDS
+};
+
+// Advance particle p by one segment; returns true when the particle has ended.
+template <typename R, int TK>
+__device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const TallyCtx& tc, const Stream& st,
+                                       Part<R>& p, LaneCounts& cnt, LogRow& lg, bool& coop)
+{
+    const DevGeom& g = T.g;
+    if ((int64_t)p.k >= T.max_events) {
+        ++cnt.c[9];
+        lg.put(EV_CAP, 0, p.m);
+        return true;
+    }
+    const R vm = tb.v[p.m];
+    const R ds = vm * p.dtr;
+    // nearest boundary along the ray: faces in id order, then pores; ties keep the lower id
+    R db = R(1) / R(0);
+    int hit = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const int a = face_axis(i), side = face_side(i);
+        if (g.unb[a]) continue;
+        const R oa = p.o[a];
+        const bool toward = side ? (oa > R(0)) : (oa < R(0));
+        if (toward) {
+            const R d = side ? r_div(Geo<R>::L(g, a) - p.x[a], oa) : r_div(R(0) - p.x[a], oa);
+            if (d < db) { db = d; hit = i + 1; }
+        }
+    }
+    for (int c = 0; c < g.n_pores; ++c) {
+        const R dx = p.x[0] - Geo<R>::cx(g, c), dy = p.x[1] - Geo<R>::cy(g, c);
+        const R qa = p.o[0] * p.o[0] + p.o[1] * p.o[1];
+        const R qb = dx * p.o[0] + dy * p.o[1];
+        const R rr = Geo<R>::r(g, c);
+        const R qc = dx * dx + dy * dy - rr * rr;
+        if (qb < R(0)) {
+            const R disc = qb * qb - qa * qc;
+            if (disc >= R(0)) {
+                const R d = (qc < R(0)) ? R(0) : r_div(qc, -qb + r_sqrt(disc));
+                if (d < db) { db = d; hit = g.pore_id[c]; }
+            }
+        }
+    }
+    // event: the time horizon first, then the boundary (segment (x0, x1]), then relaxation
+    const R dmin = db < ds ? db : ds;
+    const R tmax = (R)T.t_max;
+    int ev;             // 0 relax, 1 boundary, 2 time horizon
+    R d;
+    if (T.transient && vm * (tmax - p.t) <= dmin) { ev = 2; d = vm * (tmax - p.t); }
+    else if (db <= ds) { ev = 1; d = db; }
+    else { ev = 0; d = ds; }
+    const R dt = (ev == 0) ? p.dtr : (ev == 1 ? r_div(d, vm) : tmax - p.t);
+    const R t_end = (ev == 2) ? tmax : p.t + dt;
+    const R sg = (R)p.s;
+    if (TK == TALLY_TRANSIENT) {
+        tally_snap(T, tc, p.x, p.o, p.t, t_end, vm, sg);
+    } else {
+        if (TK == TALLY_STEADY_ONE) {
+            if (d > R(0)) add4(tc, T.det, (int64_t)p.m, sg, d, vm, p.o);
+        } else {
+            tally_grid(T, tc, p.x, p.o, d, p.m, sg, vm);
+        }
+        const int sa = T.score_axis;
+        const R os = sa == 0 ? p.o[0] : (sa == 1 ? p.o[1] : p.o[2]);
+        p.cT += (double)(sg * r_div(d, vm));
+        p.cq += (double)(sg * (d * os));
+    }
+    ++cnt.c[1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) p.x[a] = p.x[a] + d * p.o[a];
+    p.t = t_end;
+    if (ev == 1) {
+        const R r = p.dtr - dt;
+        p.dtr = r > R(0) ? r : R(0);
+    } else {
+        p.dtr = R(0);
+    }
+    p.k += 1;
+    if (ev == 2) {
+        ++cnt.c[7];
+        lg.put(EV_TIMEOUT, 0, p.m);
+        return true;
+    }
+    const bool on_face = (ev == 1) && hit <= 6;
+    const int fa = on_face ? face_axis(hit - 1) : -1;
+    const int fs = on_face ? face_side(hit - 1) : 0;
+    bool escaped = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R L = Geo<R>::L(g, a);
+        if (a == fa) p.x[a] = fs ? L : R(0);     // exactly on the wall
+        if (!g.unb[a] && (p.x[a] < R(-1e-9) * L || p.x[a] > L + R(1e-9) * L)) escaped = true;
+    }
+    if (escaped) {
+        ++cnt.c[10];
+        lg.put(EV_ESCAPE, 0, p.m);
+        return true;
+    }
+    // what the event needs
+    bool relax = (ev == 0);
+    if (relax) {
+        p.nrel += 1;
+        ++cnt.c[2];
+        if (T.n_scat_max > 0 && p.nrel >= T.n_scat_max) {
+            ++cnt.c[8];
+            lg.put(EV_NSCAT, 0, p.m);
+            return true;
+        }
+    }
+    int btype = 0;
+    R spec = R(0);
+    uint64_t sthr = 0;
+    int pore = -1;
+    if (ev == 1) {
+        if (hit <= 6) {
+            btype = g.face_type[hit - 1];
+            spec = (R)g.face_spec[hit - 1];
+            sthr = g.face_thr[hit - 1];
+        } else {
+            for (int c = 0; c < g.n_pores; ++c)
+                if (g.pore_id[c] == hit) pore = c;
+            btype = 2;
+            spec = (R)g.pore_spec[pore];
+            sthr = g.pore_thr[pore];
+        }
+        if (btype == 1) {
+            ++cnt.c[6];
+            lg.put(EV_ABSORB, hit, p.m);
+            return true;
+        }
+        if (btype == 3) {   // linearised periodic condition: reinsert unchanged at the partner face
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (a == fa) p.x[a] = fs ? R(0) : Geo<R>::L(g, a);
+            ++cnt.c[5];
+            lg.put(EV_PERIODIC, hit, p.m);
+            return false;
+        }
+    }
+    // FP32, film-like problem: a diffuse reflection off the film wall with a long free path left
+    // is handed to the whole wave (coop_bounces), which runs the coming bounces 64 at a time
+    if (std::is_same<R, float>::value && ev == 1 && T.coop_axis >= 0 && fa == T.coop_axis && !lg.row &&
+        vm * p.dtr > (R)T.coop_min_path) {
+        coop = true;
+        return false;
+    }
+    const bool adia = (ev == 1);
+    const bool partial = adia && spec > R(0) && spec < R(1);
+    const bool need_b0 = relax || partial;
+    const bool need_rec = need_b0 || (adia && !(spec > R(0)));
+    if (need_rec) p.j += 1;
+    const uint32_t blk = 2u * (2u + p.j);
+    W4 w0 = {0u, 0u, 0u, 0u};
+    if (need_b0) w0 = st.block(blk);
+    const bool specular = adia && (spec >= R(1) || (partial && key64(w0.x, w0.y) < sthr));
+    const bool diffuse = adia && !specular;
+    if (relax || diffuse) {
+        const W4 w1 = st.block(blk + 1u);
+        const R u1 = unif<R>(w1.x, w1.y), u2 = unif<R>(w1.z, w1.w);
+        if (relax) {
+            // three-phonon relaxation: frequency from the post-scattering distribution
+            // (weights C/tau), isotropic direction, new free flight, sign kept
+            p.m = cdf_pick(tb.thr_rel, T.M, T.last_rel, key64(w0.x, w0.y));
+            dir_iso(u1, u2, p.o);
+            p.dtr = -tb.tau[p.m] * r_log(R(1) - unif<R>(w0.z, w0.w));
+            lg.put(EV_RELAX, 0, p.m);
+        } else {
+            R n[3];
+            if (pore >= 0) {
+                const R rr = Geo<R>::r(g, pore);
+                n[0] = r_div(p.x[0] - Geo<R>::cx(g, pore), rr);
+                n[1] = r_div(p.x[1] - Geo<R>::cy(g, pore), rr);
+                n[2] = R(0);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) n[a] = (a == fa) ? (fs ? R(-1) : R(1)) : R(0);
+            }
+            dir_cos(u1, u2, n, p.o);
+            ++cnt.c[4];
+            lg.put(EV_DIFFUSE, hit, p.m);
+        }
+    } else if (specular) {
+        if (pore >= 0) {   // k' = k - 2 (k.n) n
+            const R rr = Geo<R>::r(g, pore);
+            const R n0 = r_div(p.x[0] - Geo<R>::cx(g, pore), rr);
+            const R n1 = r_div(p.x[1] - Geo<R>::cy(g, pore), rr);
+            const R k2 = R(2) * (p.o[0] * n0 + p.o[1] * n1 + p.o[2] * R(0));
+            p.o[0] = p.o[0] - k2 * n0;
+            p.o[1] = p.o[1] - k2 * n1;
+            p.o[2] = p.o[2] - k2 * R(0);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (a == fa) p.o[a] = -p.o[a];
+        }
+        ++cnt.c[3];
+        lg.put(EV_SPECULAR, hit, p.m);
+    }
+    return false;
+}
+
+__device__ __forceinline__ uint32_t wave_rank(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------------------------------
+// wave-cooperative bouncing in a film (FP32 form)
+// ------------------------------------------------------------------------------------------
+
+// The particle of lane `leader` sits on a wall of the film, about to be reflected diffusely, with
+// remaining free path lam = v dt_rem.  Its next reflections draw the records the sequential loop
+// would draw (record 2 + j + 1 + k for the k-th), and between two reflections it crosses the film
+// wall to wall (chord L / |Omega_axis|), so 64 lanes evaluate 64 consecutive bounces at once: each
+// lane draws its bounce's direction, a prefix sum of the chords finds the bounce during which the
+// free path runs out, and the completed segments are scored with one reduction.  The particle is
+// handed back at the start of its last (partial) segment; the sequential loop then ends that
+// segment with the relaxation.
+template <typename R>
+__device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb, const TallyCtx& tc, Part<R>& p,
+                                             const Stream& st_own, int leader, LaneCounts& cnt)
+{
+    const int lane = threadIdx.x & 63;
+    const int aw = T.coop_axis;
+    const R L = Geo<R>::L(T.g, aw);
+    const int m = __shfl(p.m, leader, 64);
+    const R sg = (R)__shfl(p.s, leader, 64);
+    // the owner's random stream (a lane that never started a particle holds no valid key)
+    const Stream st{(uint32_t)__shfl((int)st_own.k0, leader, 64), (uint32_t)__shfl((int)st_own.k1, leader, 64),
+                    (uint32_t)__shfl((int)st_own.plo, leader, 64), (uint32_t)__shfl((int)st_own.phi, leader, 64),
+                    (uint32_t)__shfl((int)st_own.inst, leader, 64)};
+    const R xw = __shfl(aw == 0 ? p.x[0] : (aw == 1 ? p.x[1] : p.x[2]), leader, 64);
+    const int side = xw > R(0.5) * L ? 1 : 0;
+    const uint32_t j0 = (uint32_t)__shfl((int)p.j, leader, 64);
+    const R vm = tb.v[m];
+    double lam = (double)vm * (double)__shfl(p.dtr, leader, 64);
+    const int sa = T.score_axis;
+    double aT = 0.0, aQ0 = 0.0, aQ1 = 0.0, aQ2 = 0.0, acq = 0.0;
+    R disp0 = R(0), disp1 = R(0), disp2 = R(0);
+    uint32_t j = j0;
+    uint32_t n_full = 0;       // this lane's completed segments
+    int kstar = 64;
+    R of0 = R(0), of1 = R(0), of2 = R(0);
+    double lam_end = 0.0;
+    for (int chunk = 0; chunk < (1 << 24); ++chunk) {
+        const int sk = side ^ (lane & 1);            // wall this lane's segment starts from
+        const uint32_t rec = 2u + j + 1u + (uint32_t)lane;
+        const W4 w1 = st.block(2u * rec + 1u);
+        const R u1 = unif<R>(w1.x, w1.y), u2 = unif<R>(w1.z, w1.w);
+        R n[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) n[a] = (a == aw) ? (sk ? R(-1) : R(1)) : R(0);
+        R o[3];
+        dir_cos(u1, u2, n, o);
+        const R oz = aw == 0 ? o[0] : (aw == 1 ? o[1] : o[2]);
+        const R len = oz != R(0) ? r_div(L, fabs(oz)) : R(1) / R(0);
+        R P = len;                                   // inclusive prefix sum of the chords
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const R t = __shfl_up(P, off, 64);
+            if (lane >= off) P += t;
+        }
+        const unsigned long long over = __ballot((double)P > lam);
+        kstar = over ? __ffsll((long long)over) - 1 : 64;
+        if (lane < kstar) {
+            const R os = sa == 0 ? o[0] : (sa == 1 ? o[1] : o[2]);
+            aT += (double)(sg * r_div(len, vm));
+            aQ0 += (double)(sg * (len * o[0]));
+            aQ1 += (double)(sg * (len * o[1]));
+            aQ2 += (double)(sg * (len * o[2]));
+            acq += (double)(sg * (len * os));
+            disp0 += len * o[0];
+            disp1 += len * o[1];
+            disp2 += len * o[2];
+            n_full += 1;
+        }
+        if (kstar < 64) {
+            const R Pprev = __shfl(P, kstar > 0 ? kstar - 1 : 0, 64);
+            lam_end = lam - (kstar > 0 ? (double)Pprev : 0.0);
+            of0 = __shfl(o[0], kstar, 64);
+            of1 = __shfl(o[1], kstar, 64);
+            of2 = __shfl(o[2], kstar, 64);
+            j += (uint32_t)kstar + 1u;
+            break;
+        }
+        lam -= (double)__shfl(P, 63, 64);
+        j += 64u;
+    }
+    const uint32_t full = wave_sum<uint32_t>(n_full);
+    const double sT = wave_sum<double>(aT), s0 = wave_sum<double>(aQ0), s1 = wave_sum<double>(aQ1),
+                 s2 = wave_sum<double>(aQ2), scq = wave_sum<double>(acq);
+    const R d0 = wave_sum<R>(disp0), d1 = wave_sum<R>(disp1), d2 = wave_sum<R>(disp2);
+    if (lane == leader) {
+        const DevDet& D = T.det;
+        const int mask = D.mask;
+        if (full > 0) {
+            if (mask & 1) tadd(tc, D, (int64_t)m, 0, sT);
+            if (mask & 2) tadd(tc, D, (int64_t)m, 1, s0);
+            if (mask & 4) tadd(tc, D, (int64_t)m, 2, s1);
+            if (mask & 8) tadd(tc, D, (int64_t)m, 3, s2);
+        }
+        p.cT += sT;
+        p.cq += scq;
+        const int side_end = side ^ (kstar & 1);
+        p.x[0] = p.x[0] + d0;
+        p.x[1] = p.x[1] + d1;
+        p.x[2] = p.x[2] + d2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (a == aw) p.x[a] = side_end ? L : R(0);
+        p.o[0] = of0;
+        p.o[1] = of1;
+        p.o[2] = of2;
+        p.dtr = (R)(lam_end / (double)vm);
+        p.j = j;
+        p.k += full;
+        cnt.c[1] += full;              // completed segments
+        cnt.c[4] += full + 1u;         // diffuse reflections
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// particle state buffer (structure of arrays)
+// ------------------------------------------------------------------------------------------
+
+template <typename R>
+struct StateView {
+    R* f[8];          // x, y, z, ox, oy, oz, t, dtr
+    int32_t* i[7];    // m, s, nrel, k, j, src, rejections
+    __device__ __host__ StateView(void* base, int64_t cap)
+    {
+        unsigned char* b = (unsigned char*)base;
+        const int64_t fb = (cap * (int64_t)sizeof(R) + 255) & ~int64_t(255);
+        const int64_t ib = (cap * 4 + 255) & ~int64_t(255);
+        for (int q = 0; q < 8; ++q) f[q] = (R*)(b + q * fb);
+        for (int q = 0; q < 7; ++q) i[q] = (int32_t*)(b + 8 * fb + q * ib);
+    }
+    __device__ void store(int64_t s, const Part<R>& p, uint32_t rej) const
+    {
+        f[0][s] = p.x[0]; f[1][s] = p.x[1]; f[2][s] = p.x[2];
+        f[3][s] = p.o[0]; f[4][s] = p.o[1]; f[5][s] = p.o[2];
+        f[6][s] = p.t; f[7][s] = p.dtr;
+        i[0][s] = p.m; i[1][s] = p.s; i[2][s] = p.nrel; i[3][s] = (int32_t)p.k; i[4][s] = (int32_t)p.j;
+        i[5][s] = p.src; i[6][s] = (int32_t)rej;
+    }
+    __device__ void load(int64_t s, Part<R>& p, uint32_t& rej) const
+    {
+        p.x[0] = f[0][s]; p.x[1] = f[1][s]; p.x[2] = f[2][s];
+        p.o[0] = f[3][s]; p.o[1] = f[4][s]; p.o[2] = f[5][s];
+        p.t = f[6][s]; p.dtr = f[7][s];
+        p.m = i[0][s]; p.s = i[1][s]; p.nrel = i[2][s]; p.k = (uint32_t)i[3][s]; p.j = (uint32_t)i[4][s];
+        p.src = i[5][s];
+        rej = (uint32_t)i[6][s];
+        p.cT = 0.0;
+        p.cq = 0.0;
+    }
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_emit(const DevTab* __restrict__ tabs, uint64_t seed, uint32_t inst,
+                                             int64_t first_pid, int64_t n, void* state, int64_t cap)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const DevTab& T = tabs[0];
+    const uint64_t pid = (uint64_t)(first_pid + i);
+    const Stream st{(uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)pid, (uint32_t)(pid >> 32), inst};
+    Part<R> p;
+    uint32_t rej = 0;
+    emit_particle<R>(T, st, p, rej);
+    StateView<R>(state, cap).store(i, p, rej);
+}
+
+// ------------------------------------------------------------------------------------------
+// persistent trace kernels
+// ------------------------------------------------------------------------------------------
+
+// stage the relaxation table, velocities and relaxation times of one instance into LDS
+template <typename R>
+__device__ __forceinline__ Tabs<R> stage_tables(const DevTab& T, unsigned char* smem)
+{
+    const int M = T.M;
+    uint64_t* s_thr = (uint64_t*)smem;
+    R* s_v = (R*)(smem + align16((int64_t)M * 8));
+    R* s_tau = (R*)(smem + align16((int64_t)M * 8) + align16((int64_t)M * sizeof(R)));
+    const R* gv = Geo<R>::v(T);
+    const R* gt = Geo<R>::tau(T);
+    for (int i = threadIdx.x; i < M; i += blockDim.x) {
+        s_thr[i] = T.thr_rel[i];
+        s_v[i] = gv[i];
+        s_tau[i] = gt[i];
+    }
+    return Tabs<R>{s_thr, s_v, s_tau};
+}
+
+__device__ __forceinline__ int64_t lds_tally_size(const DevTab& T) { return T.det.n_cells * T.det.n_cols * T.det.ncomp; }
+
+__device__ __forceinline__ void flush_lds_tally(const DevTab& T, double* s_tally, double* glob)
+{
+    const int64_t n = lds_tally_size(T);
+    const int nc = T.det.ncomp;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double v = s_tally[i];
+        if (v != 0.0) {
+            const int64_t cc = i / nc;
+            const int q = T.det.comp[i - cc * nc];
+            atomicAdd(glob + cc * 4 + q, v);
+        }
+        s_tally[i] = 0.0;
+    }
+}
+
+// per-lane counters and moments -> the tally-buffer header (one atomic per wave and counter)
+__device__ __forceinline__ void flush_lane_stats(unsigned char* tally, const LaneCounts& cnt, const double mom[4])
+{
+    unsigned long long* counts = (unsigned long long*)tally;
+    double* moments = (double*)(tally + 128);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const uint32_t s = wave_sum<uint32_t>(cnt.c[q]);
+        if (lane == 0 && s) atomicAdd(counts + q, (unsigned long long)s);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double s = wave_sum<double>(mom[q]);
+        if (lane == 0 && s != 0.0) atomicAdd(moments + q, s);
+    }
+}
+
+template <typename R, int TK>
+__device__ __forceinline__ void start_particle(const DevTab& T, const LaunchArgs& a, int64_t pid, uint32_t inst,
+                                               Part<R>& p, Stream& st, LaneCounts& cnt, LogRow& lg)
+{
+    st = Stream{(uint32_t)a.seed, (uint32_t)(a.seed >> 32), (uint32_t)(uint64_t)pid, (uint32_t)((uint64_t)pid >> 32),
+                inst};
+    uint32_t rej = 0;
+    if (a.state) StateView<R>((void*)a.state, a.capacity).load(pid - a.first_pid, p, rej);
+    else emit_particle<R>(T, st, p, rej);
+    cnt.c[0] += 1;
+    cnt.c[11] += rej;
+    lg.row = nullptr;
+    lg.n = 0;
+    lg.stride = a.log_stride;
+    if (a.event_log && pid - a.first_pid < a.n_log) {
+        lg.row = a.event_log + (pid - a.first_pid) * (int64_t)a.log_stride;
+        lg.put(p.s > 0 ? EV_EMIT_POS : EV_EMIT_NEG, p.src, p.m);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void end_particle(const Part<R>& p, int transient, double mom[4], LogRow& lg)
+{
+    if (!transient) {
+        mom[0] += p.cT;
+        mom[1] += p.cT * p.cT;
+        mom[2] += p.cq;
+        mom[3] += p.cq * p.cq;
+    }
+    if (lg.row) lg.row[0] = (uint32_t)lg.n;
+}
+
+template <typename R, int TK>
+__global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const DevTab& T = tabs[0];
+    const Tabs<R> tb = stage_tables<R>(T, smem);
+    double* s_tally = (double*)(smem + a.lds_tab_bytes);
+    if (a.tally_lds) {
+        const int64_t n = lds_tally_size(T);
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s_tally[i] = 0.0;
+    }
+    __syncthreads();
+    const TallyCtx tc{a.tally_lds ? s_tally : nullptr, (double*)(a.tally + MCBTE_TALLY_HEADER_BYTES)};
+    unsigned long long* counter = (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET);
+    const int lane = threadIdx.x & 63;
+    const unsigned long long n = (unsigned long long)a.n;
+
+    Part<R> p;
+    Stream st{0u, 0u, 0u, 0u, 0u};
+    LaneCounts cnt;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) cnt.c[q] = 0;
+    double mom[4] = {0.0, 0.0, 0.0, 0.0};
+    LogRow lg{nullptr, 0, a.log_stride};
+    bool alive = false;
+    bool exhausted = false;        // wave-uniform: the particle counter has run past n
+    int since_refill = 0;
+    for (;;) {
+        bool any_alive = __ballot(alive) != 0ull;
+        if (!exhausted && (!any_alive || since_refill >= a.refill)) {
+            since_refill = 0;
+            const unsigned long long need = __ballot(!alive);
+            if (need) {
+                const uint32_t cnt_need = (uint32_t)__popcll(need);
+                const int leader = __ffsll((long long)need) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(counter, (unsigned long long)cnt_need);
+                base = __shfl(base, leader, 64);
+                if (base + cnt_need >= n) exhausted = true;
+                if (!alive) {
+                    const unsigned long long idx = base + wave_rank(need);
+                    if (idx < n) {
+                        start_particle<R, TK>(T, a, a.first_pid + (int64_t)idx, a.inst0, p, st, cnt, lg);
+                        alive = true;
+                    }
+                }
+                any_alive = __ballot(alive) != 0ull;
+            }
+        }
+        if (!any_alive) {
+            if (exhausted) break;
+            continue;
+        }
+        ++since_refill;
+        bool coop = false;
+        if (alive) {
+            if (flight<R, TK>(T, tb, tc, st, p, cnt, lg, coop)) {
+                end_particle(p, T.transient, mom, lg);
+                alive = false;
+            }
+        }
+        if (std::is_same<R, float>::value && TK == TALLY_STEADY_ONE) {
+            for (unsigned long long pend = __ballot(coop); pend; pend &= pend - 1ull)
+                coop_bounces<R>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
+        }
+    }
+    flush_lane_stats(a.tally, cnt, mom);
+    if (a.tally_lds) {
+        __syncthreads();
+        flush_lds_tally(T, s_tally, (double*)(a.tally + MCBTE_TALLY_HEADER_BYTES));
+    }
+}
+
+// Batched form: the work items are (instance, chunk of chunk_size particles), numbered
+// instance-major; a workgroup takes one item at a time, its lanes refill from the item's
+// particle range through an LDS counter, and the workgroup moves on once every lane is idle.
+template <typename R, int TK>
+__global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ tabs, LaunchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ long long s_item;
+    __shared__ int s_inst;
+    __shared__ unsigned long long s_next;       // next particle of the current item
+    double* s_tally = (double*)(smem + a.lds_tab_bytes);
+    const int lane = threadIdx.x & 63;
+    int cur = -1;                                // instance whose tables are staged
+    Tabs<R> tb{nullptr, nullptr, nullptr};
+    LaneCounts cnt;
+    double mom[4];
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const unsigned long long it = atomicAdd(a.queue, 1ull);
+            s_item = (long long)it;
+            int inst = -1;
+            if ((long long)it < a.n_chunks) {
+                int lo = 0, hi = a.n_inst - 1;      // instance with chunk_start[i] <= it < chunk_start[i+1]
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (a.chunk_start[mid] <= (int64_t)it) lo = mid;
+                    else hi = mid - 1;
+                }
+                inst = lo;
+            }
+            s_inst = inst;
+            s_next = 0ull;
+        }
+        __syncthreads();
+        const long long item = s_item;
+        const int inst = s_inst;
+        if (cur >= 0 && inst != cur) {          // leaving an instance: flush its tallies
+            const DevTab& Tc = tabs[cur];
+            if (a.tally_lds) flush_lds_tally(Tc, s_tally, (double*)(a.tallies[cur] + MCBTE_TALLY_HEADER_BYTES));
+            flush_lane_stats(a.tallies[cur], cnt, mom);
+            __syncthreads();
+        }
+        if (inst < 0) break;
+        const DevTab& T = tabs[inst];
+        if (inst != cur) {
+            tb = stage_tables<R>(T, smem);
+            if (a.tally_lds) {
+                const int64_t n = lds_tally_size(T);
+                for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s_tally[i] = 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 12; ++q) cnt.c[q] = 0;
+            mom[0] = mom[1] = mom[2] = mom[3] = 0.0;
+            cur = inst;
+            __syncthreads();
+        }
+        const int64_t first = (item - a.chunk_start[inst]) * a.chunk_size;
+        int64_t last = first + a.chunk_size;
+        if (last > a.inst_n[inst]) last = a.inst_n[inst];
+        const unsigned long long n = (unsigned long long)(last - first);
+        const uint32_t inst_id = a.inst_ids[inst];
+        const TallyCtx tc{a.tally_lds ? s_tally : nullptr, (double*)(a.tallies[inst] + MCBTE_TALLY_HEADER_BYTES)};
+        Part<R> p;
+        Stream st{0u, 0u, 0u, 0u, 0u};
+        LogRow lg{nullptr, 0, 2};
+        bool alive = false;
+        bool exhausted = false;
+        int since_refill = 0;
+        for (;;) {
+            bool any_alive = __ballot(alive) != 0ull;
+            if (!exhausted && (!any_alive || since_refill >= a.refill)) {
+                since_refill = 0;
+                const unsigned long long need = __ballot(!alive);
+                if (need) {
+                    const uint32_t cnt_need = (uint32_t)__popcll(need);
+                    const int leader = __ffsll((long long)need) - 1;
+                    unsigned long long base = 0;
+                    if (lane == leader) base = atomicAdd(&s_next, (unsigned long long)cnt_need);
+                    base = __shfl(base, leader, 64);
+                    if (base + cnt_need >= n) exhausted = true;
+                    if (!alive) {
+                        const unsigned long long idx = base + wave_rank(need);
+                        if (idx < n) {
+                            const int64_t pid = first + (int64_t)idx;
+                            st = Stream{(uint32_t)a.seed, (uint32_t)(a.seed >> 32), (uint32_t)(uint64_t)pid,
+                                        (uint32_t)((uint64_t)pid >> 32), inst_id};
+                            uint32_t rej = 0;
+                            emit_particle<R>(T, st, p, rej);
+                            cnt.c[0] += 1;
+                            cnt.c[11] += rej;
+                            alive = true;
+                        }
+                    }
+                    any_alive = __ballot(alive) != 0ull;
+                }
+            }
+            if (!any_alive) {
+                if (exhausted) break;
+                continue;
+            }
+            ++since_refill;
+            bool coop = false;
+            if (alive) {
+                if (flight<R, TK>(T, tb, tc, st, p, cnt, lg, coop)) {
+                    end_particle(p, T.transient, mom, lg);
+                    alive = false;
+                }
+            }
+            if (std::is_same<R, float>::value && TK == TALLY_STEADY_ONE) {
+                for (unsigned long long pend = __ballot(coop); pend; pend &= pend - 1ull)
+                    coop_bounces<R>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers (called from the host side of the library)
+// ------------------------------------------------------------------------------------------
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+
+template <typename R>
+static hipError_t emit_t(const DevTab* d_tab, uint64_t seed, uint32_t inst, int64_t first_pid, int64_t n, void* state,
+                         int64_t cap, hipStream_t s)
+{
+    const int block = 256;
+    const int64_t grid = (n + block - 1) / block;
+    hipLaunchKernelGGL(k_emit<R>, dim3((unsigned)grid), dim3(block), 0, s, d_tab, seed, inst, first_pid, n, state, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const DevTab* d_tab, int precision, uint64_t seed, uint32_t inst, int64_t first_pid, int64_t n,
+                       void* state, int64_t cap, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    return precision == 64 ? emit_t<double>(d_tab, seed, inst, first_pid, n, state, cap, s)
+                           : emit_t<float>(d_tab, seed, inst, first_pid, n, state, cap, s);
+}
+
+// raise the dynamic-LDS limit of a kernel once per (kernel, size)
+static void ensure_lds_limit(const void* fn, size_t lds)
+{
+    static std::mutex mu;
+    static std::map<const void*, size_t> done;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = done.find(fn);
+    if (it != done.end() && it->second >= lds) return;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess) done[fn] = lds;
+}
+
+template <typename R, int TK>
+static hipError_t trace_t(const LaunchArgs& a, bool batch, int block, int grid, size_t lds, hipStream_t s)
+{
+    if (batch) {
+        auto fn = k_trace_batch<R, TK>;
+        ensure_lds_limit((const void*)fn, lds);
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a.tabs, a);
+    } else {
+        auto fn = k_trace_solo<R, TK>;
+        ensure_lds_limit((const void*)fn, lds);
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s,
+                           (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET));
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a.tabs, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(const LaunchArgs& a, bool batch, int precision, int tally_kind, int block, int grid, size_t lds,
+                        hipStream_t s)
+{
+    if (precision == 64) {
+        switch (tally_kind) {
+        case TALLY_STEADY_ONE: return trace_t<double, TALLY_STEADY_ONE>(a, batch, block, grid, lds, s);
+        case TALLY_STEADY_GRID: return trace_t<double, TALLY_STEADY_GRID>(a, batch, block, grid, lds, s);
+        default: return trace_t<double, TALLY_TRANSIENT>(a, batch, block, grid, lds, s);
+        }
+    }
+    switch (tally_kind) {
+    case TALLY_STEADY_ONE: return trace_t<float, TALLY_STEADY_ONE>(a, batch, block, grid, lds, s);
+    case TALLY_STEADY_GRID: return trace_t<float, TALLY_STEADY_GRID>(a, batch, block, grid, lds, s);
+    default: return trace_t<float, TALLY_TRANSIENT>(a, batch, block, grid, lds, s);
+    }
+}
+
+// occupancy of the trace kernel (workgroups per compute unit) for a block size and LDS size,
+// cached per (kernel, block, LDS)
+int trace_occupancy(bool batch, int precision, int tally_kind, int block, size_t lds)
+{
+    const void* fn = nullptr;
+#define MCBTE_PICK(RR, TKK) fn = batch ? (const void*)k_trace_batch<RR, TKK> : (const void*)k_trace_solo<RR, TKK>
+    if (precision == 64) {
+        if (tally_kind == TALLY_STEADY_ONE) MCBTE_PICK(double, TALLY_STEADY_ONE);
+        else if (tally_kind == TALLY_STEADY_GRID) MCBTE_PICK(double, TALLY_STEADY_GRID);
+        else MCBTE_PICK(double, TALLY_TRANSIENT);
+    } else {
+        if (tally_kind == TALLY_STEADY_ONE) MCBTE_PICK(float, TALLY_STEADY_ONE);
+        else if (tally_kind == TALLY_STEADY_GRID) MCBTE_PICK(float, TALLY_STEADY_GRID);
+        else MCBTE_PICK(float, TALLY_TRANSIENT);
+    }
+#undef MCBTE_PICK
+    static std::mutex mu;
+    static std::map<std::tuple<const void*, int, size_t>, int> cache;
+    const auto key = std::make_tuple(fn, block, lds);
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    ensure_lds_limit(fn, lds);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds) != hipSuccess || nb < 1) nb = 1;
+    std::lock_guard<std::mutex> lock(mu);
+    cache[key] = nb;
+    return nb;
+}
+
+}  // namespace mcbte

@@ -1,0 +1,329 @@
+"""ctypes binding of libmcbte.so (include/mcbte.h): argument marshalling only.
+
+Every step of the Monte Carlo path runs in the HIP kernels of the library; this module
+only converts workload descriptions into the ABI structs, hands device pointers of torch
+tensors and the current HIP stream to the library, and raises on error codes.  If the
+library is not built, loading fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmcbte.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENODEV, ETABLE, EGEOM, ESIZE = 0, -1, -2, -3, -4, -5, -6, -7
+N_COUNTS = 16
+COUNT_NAMES = ["particles", "flights", "relaxations", "specular", "diffuse", "periodic", "absorbed",
+               "timeouts", "nscat_end", "cap_end", "escaped", "rejections"]
+MAX_PORES = 8
+TALLY_HEADER_BYTES = 256
+
+
+class Mode(C.Structure):
+    _fields_ = [("omega", C.c_double), ("dos", C.c_double), ("v", C.c_double), ("domega", C.c_double),
+                ("tau", C.c_double), ("C", C.c_double), ("tau_imp", C.c_double),
+                ("bin", C.c_int32), ("branch", C.c_int32)]
+
+
+class Face(C.Structure):
+    _fields_ = [("type", C.c_int32), ("reserved", C.c_int32), ("data", C.c_double * 3)]
+
+
+class Pore(C.Structure):
+    _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("r", C.c_double), ("id", C.c_int32),
+                ("type", C.c_int32), ("specularity", C.c_double)]
+
+
+class Geometry(C.Structure):
+    _fields_ = [("L", C.c_double * 3), ("unbounded", C.c_int32 * 3), ("n_pores", C.c_int32),
+                ("face", Face * 6), ("pore", Pore * MAX_PORES), ("gradT", C.c_double * 3), ("volume", C.c_double)]
+
+
+class Detectors(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("n", C.c_int32 * 3), ("mask", C.c_int32)]
+
+
+class ProblemC(C.Structure):
+    _fields_ = [("N", C.c_int64), ("max_events", C.c_int64), ("T_lin", C.c_double), ("t_max", C.c_double),
+                ("n_scat_max", C.c_int32), ("format", C.c_int32), ("transient", C.c_int32),
+                ("score_axis", C.c_int32), ("n_times", C.c_int32), ("ic_axis", C.c_int32), ("n_ic", C.c_int32),
+                ("reserved", C.c_int32), ("t_meas", C.POINTER(C.c_double)), ("ic_edges", C.POINTER(C.c_double)),
+                ("ic_dT", C.POINTER(C.c_double))]
+
+
+class Info(C.Structure):
+    _fields_ = [("C_tot", C.c_double), ("sum_Cv", C.c_double), ("E_tot", C.c_double), ("e_eff", C.c_double),
+                ("V_solid", C.c_double), ("kappa_bulk", C.c_double), ("n_modes", C.c_int64),
+                ("n_sources", C.c_int64), ("n_cells", C.c_int64), ("n_cols", C.c_int64),
+                ("tally_bytes", C.c_int64), ("device", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Run(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("instance", C.c_uint32), ("precision", C.c_int32), ("block", C.c_int32),
+                ("refill", C.c_int32), ("grid", C.c_int32), ("log_stride", C.c_int32), ("n_log", C.c_int64),
+                ("event_log", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("counts", C.c_uint64 * N_COUNTS), ("moments", C.c_double * 4), ("e_eff", C.c_double),
+                ("V_cell", C.c_double), ("T_mean", C.c_double), ("T_mean_sigma", C.c_double),
+                ("q_score", C.c_double), ("q_score_sigma", C.c_double), ("kappa", C.c_double),
+                ("kappa_sigma", C.c_double), ("kappa_cell_avg", C.c_double)]
+
+
+EXPORTED = ["mcbte_build_tables", "mcbte_free_tables", "mcbte_table_info", "mcbte_table_export",
+            "mcbte_state_bytes", "mcbte_emit", "mcbte_trace", "mcbte_batch_queue_bytes", "mcbte_trace_batch",
+            "mcbte_tally", "mcbte_strerror"]
+
+_lib = None
+
+
+def lib():
+    """Load libmcbte.so (built by ``__graft_entry__.build()``); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                               "(there is no CPU fallback for the HIP path)")
+        L = C.CDLL(LIB_PATH)
+        p = C.c_void_p
+        L.mcbte_build_tables.argtypes = [C.POINTER(Mode), C.c_int32, C.POINTER(Geometry), C.POINTER(Detectors),
+                                         C.POINTER(ProblemC), C.c_int32, C.POINTER(p)]
+        L.mcbte_build_tables.restype = C.c_int
+        L.mcbte_free_tables.argtypes = [p]
+        L.mcbte_free_tables.restype = None
+        L.mcbte_table_info.argtypes = [p, C.POINTER(Info)]
+        L.mcbte_table_info.restype = C.c_int
+        L.mcbte_table_export.argtypes = [p, C.c_int32, p, C.c_int64]
+        L.mcbte_table_export.restype = C.c_int
+        L.mcbte_state_bytes.argtypes = [C.c_int32, C.c_int64]
+        L.mcbte_state_bytes.restype = C.c_int64
+        L.mcbte_emit.argtypes = [p, C.POINTER(Run), C.c_int64, C.c_int64, p, C.c_int64, p]
+        L.mcbte_emit.restype = C.c_int
+        L.mcbte_trace.argtypes = [p, C.POINTER(Run), C.c_int64, C.c_int64, p, p, p]
+        L.mcbte_trace.restype = C.c_int
+        L.mcbte_batch_queue_bytes.argtypes = [C.c_int32]
+        L.mcbte_batch_queue_bytes.restype = C.c_int64
+        L.mcbte_trace_batch.argtypes = [C.POINTER(p), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
+                                        C.POINTER(p), C.POINTER(Run), p, p]
+        L.mcbte_trace_batch.restype = C.c_int
+        L.mcbte_tally.argtypes = [p, p, C.POINTER(C.c_double), C.c_int64, C.POINTER(Result), p]
+        L.mcbte_tally.restype = C.c_int
+        L.mcbte_strerror.argtypes = [C.c_int]
+        L.mcbte_strerror.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+class MCBTEError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn}: {strerror(status)} ({status})")
+        self.status = status
+
+
+def strerror(status: int) -> str:
+    return lib().mcbte_strerror(status).decode()
+
+
+def _check(fn: str, status: int):
+    if status != OK:
+        raise MCBTEError(fn, status)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream)
+
+
+# ------------------------------------------------------------------------------------------
+# marshalling of workload descriptions
+# ------------------------------------------------------------------------------------------
+
+def structs_from_workload(w: dict):
+    """Workload dict (see the workloads package) -> (modes array, Geometry, Detectors, ProblemC, keepalive)."""
+    modes_np = np.ascontiguousarray(w["modes"])
+    modes = (Mode * len(modes_np))()
+    for i, r in enumerate(modes_np):
+        modes[i] = Mode(float(r["omega"]), float(r["dos"]), float(r["v"]), float(r["domega"]), float(r["tau"]),
+                        float(r["C"]), float(r["tau_imp"]), int(r["bin"]), int(r["branch"]))
+    g = w["geometry"]
+    G = Geometry()
+    for a in range(3):
+        G.L[a] = g["L"][a]
+        G.unbounded[a] = int(bool(g["unbounded"][a]))
+        G.gradT[a] = g["gradT"][a]
+    for fid, (ty, d0, d1, d2) in g["faces"].items():
+        G.face[fid - 1].type = int(ty)
+        G.face[fid - 1].data[0], G.face[fid - 1].data[1], G.face[fid - 1].data[2] = d0, d1, d2
+    G.n_pores = len(g["cylinders"])
+    for i, (cx, cy, r, cid, ty, spec) in enumerate(g["cylinders"]):
+        G.pore[i] = Pore(cx, cy, r, int(cid), int(ty), spec)
+    G.volume = g["volume"]
+    d = w["detectors"]
+    D = Detectors()
+    for a in range(3):
+        D.lo[a], D.hi[a], D.n[a] = d["lo"][a], d["hi"][a], d["n"][a]
+    D.mask = d["mask"]
+    p = w["problem"]
+    keep = [np.ascontiguousarray(p["t_meas"], dtype=np.float64),
+            np.ascontiguousarray(p["ic_edges"], dtype=np.float64),
+            np.ascontiguousarray(p["ic_dT"], dtype=np.float64)]
+    dp = C.POINTER(C.c_double)
+    P = ProblemC(p["N"], p["max_events"], p["T_lin"], p["t_max"], p["n_scat_max"], p["format"], int(p["transient"]),
+                 p["score_axis"], len(keep[0]) if p["transient"] else 0, p["ic_axis"], len(keep[2]), 0,
+                 keep[0].ctypes.data_as(dp), keep[1].ctypes.data_as(dp), keep[2].ctypes.data_as(dp))
+    return modes, G, D, P, keep
+
+
+# ------------------------------------------------------------------------------------------
+# the C ABI, one Python function per entry point
+# ------------------------------------------------------------------------------------------
+
+def build_tables(w: dict, device: int = 0) -> "Tables":
+    return Tables(w, device)
+
+
+def free_tables(t: "Tables"):
+    t.free()
+
+
+def table_info(t: "Tables") -> dict:
+    info = Info()
+    _check("mcbte_table_info", lib().mcbte_table_info(t.h, C.byref(info)))
+    return {k: getattr(info, k) for k, _ in Info._fields_ if k != "reserved"}
+
+
+def table_export(t: "Tables", which: str) -> np.ndarray:
+    code, dt = {"C": (0, np.float64), "thr_ic": (1, np.uint64), "thr_wall": (2, np.uint64),
+                "thr_rel": (3, np.uint64), "src_E": (4, np.float64), "thr_src": (5, np.uint64),
+                "src_sign": (6, np.int32)}[which]
+    n = t.info["n_modes"] if code <= 3 else t.info["n_sources"]
+    out = np.zeros(n, dtype=dt)
+    _check("mcbte_table_export", lib().mcbte_table_export(t.h, code, out.ctypes.data_as(C.c_void_p), n))
+    return out
+
+
+def state_bytes(precision: int, capacity: int) -> int:
+    n = lib().mcbte_state_bytes(precision, capacity)
+    if n < 0:
+        raise MCBTEError("mcbte_state_bytes", int(n))
+    return int(n)
+
+
+def make_run(seed: int, precision: int = 32, instance: int = 0, block: int = 0, refill: int = 0, grid: int = 0,
+             event_log=None, n_log: int = 0, log_stride: int = 64) -> Run:
+    return Run(seed & 0xFFFFFFFFFFFFFFFF, instance, precision, block, refill, grid, log_stride,
+               n_log if event_log is not None else 0,
+               C.c_void_p(event_log.data_ptr()) if event_log is not None else None)
+
+
+def emit(t: "Tables", run: Run, first_pid: int, n: int, state, capacity: int, stream=None):
+    _check("mcbte_emit", lib().mcbte_emit(t.h, C.byref(run), first_pid, n, C.c_void_p(state.data_ptr()), capacity,
+                                          _stream(stream)))
+
+
+def trace(t: "Tables", run: Run, first_pid: int, n: int, state, tally, stream=None):
+    st = C.c_void_p(state.data_ptr()) if state is not None else None
+    _check("mcbte_trace", lib().mcbte_trace(t.h, C.byref(run), first_pid, n, st, C.c_void_p(tally.data_ptr()),
+                                            _stream(stream)))
+
+
+def batch_queue_bytes(n_inst: int) -> int:
+    n = lib().mcbte_batch_queue_bytes(n_inst)
+    if n < 0:
+        raise MCBTEError("mcbte_batch_queue_bytes", int(n))
+    return int(n)
+
+
+def trace_batch(tables: list, n_particles, instance_ids, tallies: list, run: Run, queue, stream=None):
+    k = len(tables)
+    th = (C.c_void_p * k)(*[t.h for t in tables])
+    npart = (C.c_int64 * k)(*[int(x) for x in n_particles])
+    ids = (C.c_uint32 * k)(*[int(x) for x in instance_ids])
+    tp = (C.c_void_p * k)(*[tl.data_ptr() for tl in tallies])
+    _check("mcbte_trace_batch", lib().mcbte_trace_batch(th, k, npart, ids, tp, C.byref(run),
+                                                        C.c_void_p(queue.data_ptr()), _stream(stream)))
+
+
+def tally(t: "Tables", tally_buf, stream=None, with_arrays: bool = True) -> dict:
+    res = Result()
+    n = t.info["n_cells"] * t.info["n_cols"] * 4
+    out = np.zeros(n) if with_arrays else None
+    ptr = out.ctypes.data_as(C.POINTER(C.c_double)) if with_arrays else None
+    _check("mcbte_tally", lib().mcbte_tally(t.h, C.c_void_p(tally_buf.data_ptr()), ptr, n if with_arrays else 0,
+                                            C.byref(res), _stream(stream)))
+    r = {k: getattr(res, k) for k, _ in Result._fields_ if k not in ("counts", "moments")}
+    r["counts_raw"] = np.array(res.counts[:], dtype=np.uint64)
+    r["counts"] = dict(zip(COUNT_NAMES, [int(x) for x in res.counts[:len(COUNT_NAMES)]]))
+    r["moments"] = np.array(res.moments[:])
+    if with_arrays:
+        arr = out.reshape(t.info["n_cells"], t.info["n_cols"], 4)
+        r["T"] = arr[..., 0]
+        r["q"] = arr[..., 1:]
+    return r
+
+
+class Tables:
+    """Owner of one mcbte_tables handle."""
+
+    def __init__(self, w: dict, device: int = 0):
+        self.w = w
+        modes, G, D, P, keep = structs_from_workload(w)
+        h = C.c_void_p()
+        _check("mcbte_build_tables", lib().mcbte_build_tables(modes, len(modes), C.byref(G), C.byref(D), C.byref(P),
+                                                              device, C.byref(h)))
+        self.h = h
+        self.device = device
+        self.info = table_info(self)
+
+    def free(self):
+        if getattr(self, "h", None):
+            lib().mcbte_free_tables(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def new_tally(self):
+        import torch
+        return torch.zeros(self.info["tally_bytes"], dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def raw(self, tally_buf) -> np.ndarray:
+        """Raw sums of a tally buffer (n_cells, n_cols, 4), copied to the host."""
+        import torch
+        nbytes = self.info["n_cells"] * self.info["n_cols"] * 4 * 8
+        b = tally_buf[TALLY_HEADER_BYTES:TALLY_HEADER_BYTES + nbytes].view(torch.float64).cpu().numpy()
+        return b.reshape(self.info["n_cells"], self.info["n_cols"], 4)
+
+
+def run(w: dict, n: int | None = None, first_pid: int = 0, precision: int = 32, device: int = 0,
+        n_log: int = 0, log_stride: int = 64, emit_first: bool = False, tables: Tables | None = None,
+        **launch) -> dict:
+    """Build (or reuse) tables, trace particles [first_pid, first_pid + n) and finalize."""
+    import torch
+    t = tables or Tables(w, device)
+    n = w["problem"]["N"] if n is None else int(n)
+    tl = t.new_tally()
+    log = torch.zeros(max(n_log, 1) * log_stride, dtype=torch.int32, device=f"cuda:{device}") if n_log else None
+    r = make_run(int(w["seed"]), precision, int(w.get("instance", 0)), event_log=log, n_log=n_log,
+                 log_stride=log_stride, **launch)
+    state = None
+    if emit_first:
+        state = torch.zeros(state_bytes(precision, n), dtype=torch.uint8, device=f"cuda:{device}")
+        emit(t, r, first_pid, n, state, n)
+    trace(t, r, first_pid, n, state, tl)
+    out = tally(t, tl)
+    out["raw"] = t.raw(tl)
+    out["tables"] = t
+    if n_log:
+        out["log"] = log.view(n_log, log_stride).cpu().numpy().view(np.uint32)
+    return out

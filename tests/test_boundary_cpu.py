@@ -1,0 +1,118 @@
+"""The C-ABI library on the CPU: it loads, exports every declared entry point, builds host-side
+tables identical to the oracle's, and rejects bad input with the documented codes.  No kernel
+is launched here."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2104_03573_amd as M
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mcbte.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcbte_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 11
+    lib = M.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    dyn = subprocess.run(["nm", "-D", "--defined-only", M.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (mcbte_\w+)", dyn))
+    assert set(names) <= exported, set(names) - exported
+    assert set(M.EXPORTED) == set(names)
+
+
+@pytest.mark.parametrize("make", [lambda: W.gray_slab(N=1000), lambda: W.film(N=1000),
+                                  lambda: W.transient_bump(N=1000), lambda: W.porous_cell(N=1000),
+                                  lambda: W.ballistic_transient(N=100), lambda: W.bulk_gradient(N=10),
+                                  lambda: W.film(N=7, d=3e-8, T=100.0, specularity=0.3)])
+def test_host_tables_identical_to_oracle(make):
+    w = make()
+    t = M.Tables(w, device=-1)
+    o = oracle.Tables(w)
+    inf = t.info
+    assert inf["device"] == -1
+    for k, v in (("C_tot", o.C_tot), ("E_tot", o.E_tot), ("V_solid", o.V_solid), ("e_eff", o.e_eff),
+                 ("sum_Cv", o.Wv), ("kappa_bulk", o.kappa_bulk)):
+        assert inf[k] == v, k
+    assert (inf["n_modes"], inf["n_sources"], inf["n_cells"], inf["n_cols"]) == (o.M, o.S, o.n_cells, o.n_cols)
+    for k in ("C", "thr_ic", "thr_wall", "thr_rel", "src_E", "thr_src", "src_sign"):
+        assert np.array_equal(M.table_export(t, k), o.get(k)), k
+    assert inf["tally_bytes"] == 256 + o.n_cells * o.n_cols * 4 * 8
+
+
+def _status(w, device=-1):
+    try:
+        M.Tables(w, device)
+        return 0
+    except M.MCBTEError as e:
+        return e.status
+
+
+def test_invalid_inputs_are_rejected():
+    w = W.gray_slab(N=10)
+    bad = W.with_(w)
+    bad["modes"]["v"][0] = 0.0
+    assert _status(bad) == M.mcbte.EINVAL
+    assert _status(W.with_(w, **{"problem.N": 0})) == M.mcbte.EINVAL
+    assert _status(W.with_(w, **{"geometry.faces": {5: (W.PERIODIC, 0, 0, 1e-7), 6: (W.ISOTHERMAL, 299.0, 0, 0)}})) \
+        == M.mcbte.EGEOM
+    assert _status(W.with_(w, **{"geometry.faces": {5: (W.ISOTHERMAL, 300.0, 0, 0),
+                                                     6: (W.ISOTHERMAL, 300.0, 0, 0)}})) == M.mcbte.ETABLE
+    assert _status(W.with_(w, **{"detectors.mask": 0})) == M.mcbte.EINVAL
+    assert _status(W.with_(w, **{"detectors.n": (0, 0, 5), "detectors.hi": (0, 0, -1.0)})) == M.mcbte.EINVAL
+    p = W.porous_cell(N=10)
+    assert _status(W.with_(p, **{"geometry.cylinders": [(0.1e-7, 2.5e-7, 1.4e-7, 7, W.ADIABATIC, 0.0)]})) \
+        == M.mcbte.EGEOM
+    assert _status(W.with_(p, **{"geometry.faces": {**p["geometry"]["faces"], 1: (W.PERIODIC, 0, 1e-7, 0)}})) \
+        == M.mcbte.EGEOM
+    f = W.film(N=10)
+    assert _status(W.with_(f, **{"geometry.faces": {5: (W.ADIABATIC, 1.5, 0, 0), 6: (W.ADIABATIC, 0, 0, 0)}})) \
+        == M.mcbte.EGEOM
+    zero = W.with_(f)
+    zero["modes"]["dos"][:] = 0.0
+    assert _status(zero) == M.mcbte.ETABLE
+    tr = W.transient_bump(N=10)
+    assert _status(W.with_(tr, **{"problem.transient": False})) == M.mcbte.EINVAL   # IC needs a transient run
+    unsorted = W.with_(tr)
+    unsorted["problem"]["t_meas"] = unsorted["problem"]["t_meas"][::-1].copy()
+    assert _status(unsorted) == M.mcbte.EINVAL
+
+
+def test_device_calls_reject_host_only_tables():
+    t = M.Tables(W.gray_slab(N=10), device=-1)
+    run = M.make_run(1, 64)
+    L = M.lib()
+    dummy = C.c_void_p(1)
+    assert L.mcbte_trace(t.h, C.byref(run), 0, 10, None, dummy, None) == M.mcbte.ENODEV
+    assert L.mcbte_emit(t.h, C.byref(run), 0, 10, dummy, 10, None) == M.mcbte.ENODEV
+    res = M.mcbte.Result()
+    assert L.mcbte_tally(t.h, dummy, None, 0, C.byref(res), None) == M.mcbte.ENODEV
+    run.precision = 16
+    assert L.mcbte_trace(t.h, C.byref(run), 0, 10, None, dummy, None) == M.mcbte.EINVAL
+    assert L.mcbte_trace(None, C.byref(run), 0, 10, None, dummy, None) == M.mcbte.EINVAL
+
+
+def test_sizes_and_messages():
+    assert M.state_bytes(32, 1000) == 8 * 4096 + 7 * 4096
+    assert M.state_bytes(64, 1) == 15 * 256
+    with pytest.raises(M.MCBTEError):
+        M.state_bytes(16, 10)
+    assert M.batch_queue_bytes(64) > 64 * 8 * 3
+    assert M.strerror(0) == "ok"
+    assert "geometry" in M.strerror(-6)
+    tb = M.Tables(W.gray_slab(N=10), device=-1)
+    out = np.zeros(1)
+    assert M.lib().mcbte_table_export(tb.h, 3, out.ctypes.data_as(C.c_void_p), 0) == M.mcbte.ESIZE

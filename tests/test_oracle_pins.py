@@ -200,10 +200,15 @@ def test_steady_segment_clipping_matches_brute_force():
     rng = np.random.default_rng(5)
     for ww in (w, w3):
         tb = oracle.Tables(ww)
-        for _ in range(25):
+        det = ww["detectors"]
+        for k in range(40):
             x0 = rng.random(3) * np.array([4e-8, 3e-8, 1e-7]) - np.array([5e-9, 5e-9, 0])
             o = rng.normal(size=3)
             o /= np.linalg.norm(o)
+            if k % 2:   # start exactly on an outer face or an interior plane of the grid
+                a = int(rng.integers(0, 3))
+                nb = max(det["n"][a], 1)
+                x0[a] = det["lo"][a] + (det["hi"][a] - det["lo"][a]) * int(rng.integers(0, nb + 1)) / nb
             d = rng.random() * 8e-8
             got = tb.segment(x0, o, d, 0, -1.0)
             want = _brute_segment(tb, ww, x0, o, d, 0, -1.0)
