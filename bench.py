@@ -67,6 +67,24 @@ def algorithmic_lane_ops(counts: dict, info: dict, geom: dict, ncomp: int, trans
             + counts["rejections"] * 2 * OPS["philox_block"])
 
 
+def profiled_traffic(kernel_tag: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this
+    kernel and workload, or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2104_03573_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("mcbte_kernels.hip", "mcbte_dev.h"):
+        with open(os.path.join(src, f), "rb") as fh:
+            h.update(fh.read())
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+    if kv.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
 def workload(name: str, scale: float = 1.0):
     import workloads as W
     if name == "film":
@@ -122,6 +140,9 @@ def main():
     ap.add_argument("--streams", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -131,6 +152,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        nb = args.copy_calibration * 1024 * 1024
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": nb, "launches": 3}), flush=True)
+        return
 
     import paper_2104_03573_amd as M
 
@@ -213,7 +244,9 @@ def main():
                    "precision": args.precision, "tallies": "f64", "streams": S,
                    "parallelism": "single GPU" + (", batches overlapped on %d streams" % S if S > 1 else "")},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS,
+                     "traffic": (profiled_traffic("k_trace_solo_film_fp32")
+                                 if args.workload == "film" and args.precision == 32 and S == 1 else None),
                      "kernel": "k_trace_solo", "kernel_ms": sum(kernel_ms) / len(kernel_ms),
                      "lane_ops_per_launch": ops / args.steps},
         "kernel_ms_per_step": kernel_ms,
