@@ -12,6 +12,7 @@ import this package.  It shares no code with the HIP library.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 import threading
@@ -106,6 +107,8 @@ def lib():
         L.orc_tally_segment.argtypes = [p, p, p, C.c_double, C.c_int32, C.c_double, p]
         L.orc_emit_state.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, p, p]
         L.orc_emit_state.restype = C.c_int
+        L.orc_adjoint.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, p, p, p]
+        L.orc_adjoint.restype = C.c_int
         L.orc_next_boundary.argtypes = [p, p, p, p]
         L.orc_next_boundary.restype = C.c_double
         _lib = L
@@ -217,10 +220,10 @@ class Tables:
             raise ValueError(f"oracle table build failed with status {rc}")
         self.h = h
         dd = (C.c_double * 6)()
-        ii = (C.c_int64 * 4)()
+        ii = (C.c_int64 * 5)()
         L.orc_info(h, dd, ii)
         self.C_tot, self.Wv, self.e_eff, self.V_solid, self.E_tot, self.kappa_bulk = list(dd)
-        self.M, self.S, self.n_cells, self.n_cols = list(ii)
+        self.M, self.S, self.n_cells, self.n_cols, self.n_bins = list(ii)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -231,7 +234,8 @@ class Tables:
         code, n, dt = {"C": (0, self.M, np.float64), "thr_ic": (1, self.M, np.uint64),
                        "thr_wall": (2, self.M, np.uint64), "thr_rel": (3, self.M, np.uint64),
                        "src_E": (4, self.S, np.float64), "thr_src": (5, self.S, np.uint64),
-                       "src_sign": (6, self.S, np.int32), "last": (7, 4, np.int64)}[which]
+                       "src_sign": (6, self.S, np.int32), "last": (7, 4, np.int64),
+                       "P_bin": (8, self.n_bins, np.float64), "bin": (9, self.M, np.int32)}[which]
         out = np.zeros(n, dtype=dt)
         if lib().orc_get(self.h, code, _ptr(out), n) != 0:
             raise ValueError(which)
@@ -368,3 +372,47 @@ def run_batches(w: dict, n_batches: int, n: int | None = None, threads: int = 8)
 
     with ThreadPoolExecutor(max(1, min(threads, n_batches))) as ex:
         return list(ex.map(one, range(n_batches)))
+
+
+def adjoint(w: dict, n: int | None = None, first_pid: int = 0, threads: int = 1, n_batches: int = 1,
+            tables: Tables | None = None) -> dict:
+    """Score-function estimate of dkappa / dln tau_i (per frequency bin) over particles
+    [first_pid, first_pid + n), with batch-mean standard errors when n_batches > 1.
+
+    dkappa/dln tau_i = -E_tot / (V_solid gradT_s n) * (sparse_i + P_i B), the same normalisation
+    as kappa = -E_tot / (V_solid gradT_s n) * sum_p F_p (section 3.6, Eq. flux_x_steady)."""
+    tb = tables or Tables(w)
+    n = w["problem"]["N"] if n is None else int(n)
+    inst = int(w.get("instance", 0))
+    nb = max(1, int(n_batches))
+    bounds = [first_pid + (n * i) // nb for i in range(nb + 1)]
+
+    def one(i):
+        lo, hi = bounds[i], bounds[i + 1]
+        sp = np.zeros(tb.n_bins)
+        de = np.zeros(1)
+        F = np.zeros(hi - lo)
+        rc = lib().orc_adjoint(tb.h, int(w["seed"]), inst, lo, hi - lo, _ptr(sp), _ptr(de), _ptr(F))
+        if rc != 0:
+            raise ValueError(f"oracle adjoint failed with status {rc}")
+        return sp, float(de[0]), F
+
+    with ThreadPoolExecutor(max(1, min(threads, nb))) as ex:
+        parts = list(ex.map(one, range(nb)))
+    g = w["geometry"]["gradT"][w["problem"]["score_axis"]]
+    P = tb.get("P_bin")
+    per_batch = []
+    for (sp, de, F), lo, hi in zip(parts, bounds[:-1], bounds[1:]):
+        scale = -tb.E_tot / (tb.V_solid * g * (hi - lo))
+        per_batch.append(scale * (sp + P * de))
+    sp = sum(p[0] for p in parts)
+    de = sum(p[1] for p in parts)
+    F = np.concatenate([p[2] for p in parts])
+    scale = -tb.E_tot / (tb.V_solid * g * n)
+    out = {"dkappa_dlntau": scale * (sp + P * de), "sparse": sp, "dense": de, "F": F, "P_bin": P,
+           "kappa": scale * F.sum(), "tables": tb}
+    if nb > 1:
+        arr = np.array(per_batch)
+        out["dkappa_dlntau_sigma"] = arr.std(0, ddof=1) / math.sqrt(nb)
+        out["per_batch"] = arr
+    return out

@@ -55,6 +55,9 @@ struct orc_tables {
     double *t_meas, *ic_edges, *ic_dT;
     int64_t n_cells;
     int32_t n_cols;
+    int32_t n_bins;
+    int32_t* bin;        /* frequency bin of each mode row */
+    double* P_bin;       /* relaxation probability mass of each bin */
 };
 
 /* ------------------------------------------------------------------------------------------ */
@@ -201,6 +204,7 @@ void orc_free(orc_tables* t)
     free(t->thr_ic); free(t->thr_wall); free(t->thr_rel);
     free(t->src_kind); free(t->src_ref); free(t->src_sign); free(t->src_E); free(t->thr_src);
     free(t->t_meas); free(t->ic_edges); free(t->ic_dT);
+    free(t->bin); free(t->P_bin);
     free(t);
 }
 
@@ -378,6 +382,24 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
     t->n_cells = 1;
     for (int a = 0; a < 3; ++a) t->n_cells *= det->n[a] > 0 ? det->n[a] : 1;
     t->n_cols = pr->transient ? pr->n_times : M;
+
+    /* frequency bins (the parameters of the sensitivity dkappa / dln tau_i) and the share of the
+       relaxation distribution in each bin */
+    t->bin = (int32_t*)malloc(sizeof(int32_t) * M);
+    if (!t->bin) { orc_free(t); return E_NOMEM; }
+    t->n_bins = 0;
+    for (int m = 0; m < M; ++m) {
+        if (modes[m].bin < 0) { orc_free(t); return E_INVAL; }
+        t->bin[m] = modes[m].bin;
+        if (modes[m].bin + 1 > t->n_bins) t->n_bins = modes[m].bin + 1;
+    }
+    t->P_bin = (double*)calloc(t->n_bins, sizeof(double));
+    if (!t->P_bin) { orc_free(t); return E_NOMEM; }
+    {
+        double W = 0.0;
+        for (int m = 0; m < M; ++m) W += t->C[m] / t->tau[m];
+        for (int m = 0; m < M; ++m) t->P_bin[t->bin[m]] += (t->C[m] / t->tau[m]) / W;
+    }
     *out = t;
     return E_OK;
 }
@@ -386,7 +408,7 @@ void orc_info(const orc_tables* t, double* d6, int64_t* i4)
 {
     d6[0] = t->C_tot; d6[1] = t->Wv; d6[2] = t->e_eff; d6[3] = t->V_solid; d6[4] = t->E_tot;
     d6[5] = t->kappa_bulk;
-    i4[0] = t->M; i4[1] = t->S; i4[2] = t->n_cells; i4[3] = t->n_cols;
+    i4[0] = t->M; i4[1] = t->S; i4[2] = t->n_cells; i4[3] = t->n_cols; i4[4] = t->n_bins;
 }
 
 int orc_get(const orc_tables* t, int32_t which, void* out, int64_t n)
@@ -399,6 +421,8 @@ int orc_get(const orc_tables* t, int32_t which, void* out, int64_t n)
     case 4: if (n < t->S) return E_INVAL; memcpy(out, t->src_E, sizeof(double) * t->S); return 0;
     case 5: if (n < t->S) return E_INVAL; memcpy(out, t->thr_src, 8 * t->S); return 0;
     case 6: if (n < t->S) return E_INVAL; memcpy(out, t->src_sign, 4 * t->S); return 0;
+    case 8: if (n < t->n_bins) return E_INVAL; memcpy(out, t->P_bin, sizeof(double) * t->n_bins); return 0;
+    case 9: if (n < t->M) return E_INVAL; memcpy(out, t->bin, 4 * t->M); return 0;
     case 7: {
         if (n < 4) return E_INVAL;
         int64_t* o = (int64_t*)out;
@@ -666,6 +690,36 @@ int orc_emit_state(const orc_tables* t, uint64_t seed, uint32_t instance, int64_
     return E_OK;
 }
 
+/* Score-function (likelihood-ratio) terms of one particle, for the sensitivity of kappa to a
+   relative change of the relaxation times of one frequency bin, dkappa / dln tau_i.  Each
+   random quantity whose law depends on tau contributes its score times the part of the
+   particle's flux contribution F that comes after it (earlier parts cannot depend on it):
+     - a free flight of mode m (Eq. time_to_scat, time T ~ Exp(tau_m)) that ends in a relaxation:
+       d ln[(1/tau) e^{-T/tau}] / d ln tau = T/tau - 1, for bin(m), with F after the flight's start;
+       one cut short (absorbed, time horizon, segment cap) survives: d ln e^{-T/tau} / d ln tau = T/tau;
+     - a relaxation draw of row j from p_j = (C_j/tau_j) / sum_r (C_r/tau_r) (Eq. norm_post_coll):
+       d ln p_j / d ln tau_i = -[bin(j) = i] + P_i, with F after the draw; the P_i part is the same
+       for every draw and is summed into one number B per run. */
+typedef struct { int32_t bin, dense; double g, F_before; } adj_ev;
+typedef struct { adj_ev* ev; int64_t n, cap; int failed; } adj_list;
+
+static void adj_push(adj_list* al, int32_t bin, double g, double F_before, int dense)
+{
+    if (!al) return;
+    if (al->n == al->cap) {
+        int64_t cap = al->cap ? 2 * al->cap : 64;
+        adj_ev* e = (adj_ev*)realloc(al->ev, sizeof(adj_ev) * cap);
+        if (!e) { al->failed = 1; return; }
+        al->ev = e;
+        al->cap = cap;
+    }
+    adj_ev* e = &al->ev[al->n++];
+    e->bin = bin;
+    e->g = g;
+    e->F_before = F_before;
+    e->dense = dense;
+}
+
 static uint32_t pack_ev(int ev, int64_t bnd, int32_t m)
 {
     if (bnd > 255) bnd = 255;
@@ -673,7 +727,8 @@ static uint32_t pack_ev(int ev, int64_t bnd, int32_t m)
 }
 
 static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t pid, double* raw,
-                      uint64_t* counts, double* mom, uint32_t* logrow, int32_t stride, double* pts)
+                      uint64_t* counts, double* mom, uint32_t* logrow, int32_t stride, double* pts,
+                      adj_list* al, double* F_out)
 {
     const orc_geom* g = &t->g;
     const orc_problem* pr = &t->pr;
@@ -696,10 +751,14 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
     }
     LOG(p.s > 0 ? ORC_EV_EMIT_POS : ORC_EV_EMIT_NEG, src, p.m);
     const int sa = pr->score_axis;
+    double dtr0 = p.dtr;       /* free-flight time drawn for the current flight */
+    double F0 = 0.0;           /* flux contribution at the start of the current flight */
+#define CENSORED() adj_push(al, t->bin[p.m], (dtr0 - p.dtr) / t->tau[p.m], F0, 0)
     for (;;) {
         if ((int64_t)p.k >= pr->max_events) {
             counts[ORC_C_CAP_END] += 1;
             LOG(ORC_EV_CAP_END, 0, p.m);
+            CENSORED();
             break;
         }
         const double v = t->v[p.m];
@@ -742,6 +801,7 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
         if (ev == EV_TIME) {
             counts[ORC_C_TIMEOUT] += 1;
             LOG(ORC_EV_TIMEOUT, 0, p.m);
+            CENSORED();
             break;
         }
         int face_axis = -1, face_side = 0;
@@ -756,6 +816,7 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
         if (escaped) {
             counts[ORC_C_ESCAPED] += 1;
             LOG(ORC_EV_ESCAPE, 0, p.m);
+            CENSORED();
             break;
         }
         if (ev == EV_RELAX) {
@@ -763,6 +824,7 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
                distribution, isotropic direction, sign kept; termination after N_scat^max */
             p.nrel += 1;
             counts[ORC_C_RELAX] += 1;
+            adj_push(al, t->bin[p.m], dtr0 / t->tau[p.m] - 1.0, F0, 0);   /* the flight that ended */
             if (pr->n_scat_max > 0 && p.nrel >= pr->n_scat_max) {
                 counts[ORC_C_NSCAT_END] += 1;
                 LOG(ORC_EV_NSCAT_END, 0, p.m);
@@ -775,6 +837,9 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
             orc_dir_iso(unif(R, 4), unif(R, 6), p.o);
             p.dtr = -t->tau[p.m] * log(1.0 - unif(R, 2));
             LOG(ORC_EV_RELAX, 0, p.m);
+            adj_push(al, t->bin[p.m], -1.0, p.cq, 1);                        /* the draw of the new row */
+            dtr0 = p.dtr;
+            F0 = p.cq;
             continue;
         }
         /* boundary interaction (sections 3.5.3-3.5.5) */
@@ -793,6 +858,7 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
         if (type == B_ISO) {
             counts[ORC_C_ABSORBED] += 1;
             LOG(ORC_EV_ABSORB, hit, p.m);
+            CENSORED();
             break;
         }
         if (type == B_PERI) {
@@ -842,6 +908,8 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
         }
     }
 #undef LOG
+#undef CENSORED
+    if (F_out) *F_out = p.cq;
     if (!pr->transient) {
         mom[0] += p.cT;
         mom[1] += p.cT * p.cT;
@@ -861,8 +929,39 @@ int orc_trace(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t fir
     if (!pts) return E_NOMEM;
     for (int64_t i = 0; i < n; ++i) {
         uint32_t* row = (i < n_log) ? log + i * (int64_t)log_stride : NULL;
-        trace_one(t, seed, instance, first_pid + i, raw, counts, moments, row, log_stride, pts);
+        trace_one(t, seed, instance, first_pid + i, raw, counts, moments, row, log_stride, pts, NULL, NULL);
     }
     free(pts);
     return E_OK;
+}
+
+int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t first_pid, int64_t n,
+                double* sparse, double* dense, double* F_out)
+{
+    if (!t || n < 0 || first_pid < 0 || t->pr.transient) return E_INVAL;
+    int cap = 2;
+    for (int a = 0; a < 3; ++a) cap += t->det.n[a];
+    double* pts = (double*)malloc(sizeof(double) * cap);
+    double* raw = (double*)calloc((size_t)(t->n_cells * t->n_cols * 4), sizeof(double));
+    if (!pts || !raw) { free(pts); free(raw); return E_NOMEM; }
+    uint64_t counts[ORC_N_COUNTS] = {0};
+    double mom[ORC_N_MOMENTS] = {0};
+    adj_list al = {NULL, 0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        al.n = 0;
+        double F = 0.0;
+        trace_one(t, seed, instance, first_pid + i, raw, counts, mom, NULL, 0, pts, &al, &F);
+        if (al.failed) break;
+        for (int64_t e = 0; e < al.n; ++e) {
+            const double after = F - al.ev[e].F_before;
+            sparse[al.ev[e].bin] += al.ev[e].g * after;
+            if (al.ev[e].dense) *dense += after;
+        }
+        if (F_out) F_out[i] = F;
+    }
+    int failed = al.failed;
+    free(al.ev);
+    free(pts);
+    free(raw);
+    return failed ? E_NOMEM : E_OK;
 }

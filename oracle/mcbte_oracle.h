@@ -61,13 +61,20 @@ enum {
 int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det* det,
               const orc_problem* pr, orc_tables** out);
 void orc_free(orc_tables* t);
-/* doubles: C_tot, sum C v, e_eff, V_solid, E_tot, kappa_bulk; ints: M, S, n_cells, n_cols */
-void orc_info(const orc_tables* t, double* d6, int64_t* i4);
-/* which: 0 C, 1 thr_ic, 2 thr_wall, 3 thr_rel, 4 src_E, 5 thr_src, 6 src_sign, 7 last-index x4 */
+/* doubles: C_tot, sum C v, e_eff, V_solid, E_tot, kappa_bulk; ints: M, S, n_cells, n_cols, n_bins */
+void orc_info(const orc_tables* t, double* d6, int64_t* i5);
+/* which: 0 C, 1 thr_ic, 2 thr_wall, 3 thr_rel, 4 src_E, 5 thr_src, 6 src_sign, 7 last-index x4,
+   8 relaxation probability per bin, 9 bin of each mode */
 int orc_get(const orc_tables* t, int32_t which, void* out, int64_t n);
 int orc_trace(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t first_pid, int64_t n,
               double* raw, uint64_t* counts, double* moments,
               uint32_t* log, int64_t n_log, int32_t log_stride);
+
+/* likelihood-ratio sums for dkappa / dln tau_i over particles first_pid .. first_pid + n - 1 (steady
+   runs): sparse[n_bins] += sum_e g_e (F - F_before_e), *dense += sum over relaxation draws of
+   (F - F_before); F_out[i] (optional) = flux contribution of each particle */
+int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t first_pid, int64_t n,
+                double* sparse, double* dense, double* F_out);
 
 /* building blocks exposed for the pins */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

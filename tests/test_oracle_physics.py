@@ -275,3 +275,39 @@ def test_dispersive_diffusion_uses_post_scattering_distribution():
         ref = cf.bin_average(lambda z: cf.fourier_neumann_piecewise(z, tk, D, L, p["ic_edges"], p["ic_dT"]),
                              0.0, L, 60, per_bin=8)
         assert_bins_agree([b["T"][:, k] for b in batches], ref, sys_err=3e-3 * ref.max())
+
+
+def test_adjoint_gray_bulk_is_kappa():
+    """kappa = C v^2 tau / 3 for the gray bulk, so dkappa / dln tau = kappa."""
+    for nsm in (1, 4):
+        w = W.bulk_gradient(N=200000, n_scat_max=nsm)
+        a = oracle.adjoint(w, threads=THREADS, n_batches=NB)
+        k_ref = 1e6 * 6400.0 ** 2 * (100e-9 / 6400.0) / 3.0
+        assert_bins_agree(a["per_batch"], np.array([k_ref]))
+        # the flux itself comes out of the same replayed particles
+        assert abs(a["kappa"] - k_ref) < 4 * a["dkappa_dlntau_sigma"][0]
+
+
+def test_adjoint_film_matches_fuchs_sondheimer_derivative():
+    """Diffuse film: only the first flight carries mean flux, so dkappa/dln tau_i is the
+    derivative of sum_{m in bin i} kappa_m S(d / Lambda_m) (closed form differentiated); compared
+    in groups of 10 frequency bins (single low-frequency bins are too rarely emitted for a batch
+    error) and in total."""
+    d0 = 100e-9
+    w = W.film(N=400000, d=d0)
+    a = oracle.adjoint(w, threads=THREADS, n_batches=NB)
+    tb = a["tables"]
+    C = tb.get("C")
+    m = w["modes"]
+    bins = tb.get("bin")
+    lam = m["v"] * m["tau"]
+    ref = np.zeros(tb.n_bins)
+    for i in range(len(m)):
+        k = C[i] * m["v"][i] ** 2 * m["tau"][i] / 3.0
+        delta = d0 / lam[i]
+        e = 1e-5
+        dS = (cf.fs_suppression(delta * math.exp(-e)) - cf.fs_suppression(delta * math.exp(e))) / (2 * e)
+        ref[bins[i]] += k * cf.fs_suppression(delta) + k * dS
+    pb = a["per_batch"]
+    assert_bins_agree(pb.reshape(NB, -1, 10).sum(2), ref.reshape(-1, 10).sum(1))
+    assert_bins_agree(pb.sum(1)[:, None], np.array([ref.sum()]))
