@@ -143,6 +143,8 @@ typedef struct {
     double kappa_bulk;   /* sum_m C_m v_m^2 tau_m / 3                                      */
     int64_t n_modes, n_sources, n_cells, n_cols;
     int64_t tally_bytes; /* size of the tally buffer mcbte_trace needs                     */
+    int64_t n_bins;      /* frequency bins (1 + largest mcbte_mode.bin)                    */
+    int64_t adj_doubles; /* doubles of the buffer mcbte_adjoint needs (n_bins + 2)         */
     int32_t device;      /* HIP device ordinal, -1 for host-only tables                    */
     int32_t reserved;
 } mcbte_info;
@@ -158,6 +160,9 @@ typedef struct {
     int32_t log_stride;   /* uint32 words per event-log row (>= 2)                          */
     int64_t n_log;        /* particles logged (first_pid .. first_pid + n_log - 1)          */
     uint32_t* event_log;  /* device pointer, n_log * log_stride uint32, or NULL             */
+    double* particle_F;   /* device pointer, n doubles, or NULL: mcbte_trace writes each particle's
+                             flux score F (sum of s l Omega_score over its segments) at index
+                             pid - first_pid, the input of mcbte_adjoint                     */
 } mcbte_run;
 
 /* Finalized results (mcbte_tally). */
@@ -239,6 +244,26 @@ int64_t mcbte_batch_queue_bytes(int32_t n_inst);
 int mcbte_trace_batch(const mcbte_tables* const* tables, int32_t n_inst, const int64_t* n_particles,
                       const uint32_t* instance_ids, void* const* tallies, const mcbte_run* run, void* queue,
                       void* stream);
+
+/* Sensitivity of kappa to a relative change of the relaxation times of each frequency bin,
+   dkappa / dln tau_i (steady runs with a gradient).  Likelihood-ratio estimator: every random
+   quantity whose law depends on tau contributes its score times the part of the particle's flux
+   score that follows it -- a free flight (Eq. time_to_scat) that ends in a relaxation scores
+   T/tau - 1, one cut short (absorbed, segment cap) T/tau, both for the flying mode's bin; a
+   relaxation draw of row j (Eq. norm_post_coll) scores -[bin(j) = i] + P_i, P_i the bin's share of
+   the post-scattering distribution.  mcbte_adjoint replays particles first_pid .. first_pid + n - 1
+   with the same random streams (run->seed, run->instance, run->precision as the forward trace that
+   filled particle_F, a device array of n doubles) and adds the sums to `adj` (device, adj_doubles
+   doubles, zeroed by the caller; successive calls accumulate; the last word is library scratch).
+   Async on `stream`.  Errors: MCBTE_EINVAL (transient run, event log set), MCBTE_ENODEV, MCBTE_EHIP. */
+int mcbte_adjoint(const mcbte_tables* tables, const mcbte_run* run, int64_t first_pid, int64_t n,
+                  const double* particle_F, double* adj, void* stream);
+
+/* Copy `adj` to the host (synchronizes `stream`) and write dkappa / dln tau_i, i < n_bins, into
+   host_out (n_out >= n_bins) for n_particles traced particles, with the normalisation of kappa
+   (-E_tot / (V_solid gradT_score n_particles)).  dkappa / dtau_i = host_out[i] / tau_i. */
+int mcbte_adjoint_finalize(const mcbte_tables* tables, const double* adj, int64_t n_particles, double* host_out,
+                           int64_t n_out, void* stream);
 
 /* Copy the device tally buffer to the host (synchronizes `stream`) and finalize it (Eqs.
    sampling, temp_steady, flux_x_steady): host_out[n_cells][n_cols][4] receives the deviational

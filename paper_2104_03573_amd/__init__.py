@@ -1,12 +1,13 @@
 """MI355X-native deviational phonon Monte Carlo tracer (HIP kernels behind a C ABI).
 
 The public Python surface mirrors include/mcbte.h: build_tables, free_tables, table_info,
-table_export, state_bytes, emit, trace, batch_queue_bytes, trace_batch, tally, strerror.
+table_export, state_bytes, emit, trace, batch_queue_bytes, trace_batch, adjoint, adjoint_finalize, tally,
+strerror.
 """
-from .mcbte import (COUNT_NAMES, EXPORTED, LIB_PATH, MCBTEError, Tables, batch_queue_bytes, build_tables,
-                    emit, free_tables, lib, make_run, run, state_bytes, strerror, table_export, table_info,
-                    tally, trace, trace_batch)
+from .mcbte import (COUNT_NAMES, EXPORTED, LIB_PATH, MCBTEError, Tables, adjoint, adjoint_finalize,
+                    batch_queue_bytes, build_tables, emit, free_tables, lib, make_run, run, sensitivities,
+                    state_bytes, strerror, table_export, table_info, tally, trace, trace_batch)
 
-__all__ = ["COUNT_NAMES", "EXPORTED", "LIB_PATH", "MCBTEError", "Tables", "batch_queue_bytes", "build_tables",
-           "emit", "free_tables", "lib", "make_run", "run", "state_bytes", "strerror", "table_export",
-           "table_info", "tally", "trace", "trace_batch"]
+__all__ = ["COUNT_NAMES", "EXPORTED", "LIB_PATH", "MCBTEError", "Tables", "adjoint", "adjoint_finalize",
+           "batch_queue_bytes", "build_tables", "emit", "free_tables", "lib", "make_run", "run", "sensitivities",
+           "state_bytes", "strerror", "table_export", "table_info", "tally", "trace", "trace_batch"]

@@ -72,6 +72,9 @@ struct DevTab {
     const double* ic_edges;
     const double* t_meas64;
     const float* t_meas32;
+    const int32_t* bin_of;       // frequency bin of each mode (sensitivity parameters)
+    int32_t n_bins;
+    int32_t pad2;
     DevGeom g;
     DevDet det;
 };
@@ -101,6 +104,9 @@ struct LaunchArgs {
     int64_t n_chunks;
     int32_t tally_lds;           // tallies privatised in LDS
     int32_t lds_tab_bytes;       // offset of the tally region in dynamic LDS
+    // sensitivity replay
+    double* particle_F;          // per-particle flux score (written by the trace, read by the replay)
+    double* adj;                 // n_bins sums, the relaxation-draw sum B, then a work counter
 };
 
 }  // namespace mcbte

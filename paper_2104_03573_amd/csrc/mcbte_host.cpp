@@ -15,9 +15,10 @@
 namespace mcbte {
 hipError_t launch_emit(const DevTab* d_tab, int precision, uint64_t seed, uint32_t inst, int64_t first_pid, int64_t n,
                        void* state, int64_t cap, hipStream_t s);
-hipError_t launch_trace(const LaunchArgs& a, bool batch, int precision, int tally_kind, int block, int grid, size_t lds,
+hipError_t launch_trace(const LaunchArgs& a, int mode, int precision, int tally_kind, int block, int grid, size_t lds,
                         hipStream_t s);
-int trace_occupancy(bool batch, int precision, int tally_kind, int block, size_t lds);
+hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);
+int trace_occupancy(int mode, int precision, int tally_kind, int block, size_t lds);
 }  // namespace mcbte
 
 using namespace mcbte;
@@ -89,7 +90,8 @@ struct mcbte_tables {
     // host tables
     std::vector<double> C, v, tau, src_E, ic_edges, ic_dT, t_meas;
     std::vector<uint64_t> thr_ic, thr_wall, thr_rel, thr_src;
-    std::vector<int32_t> src_kind, src_ref, src_sign;
+    std::vector<int32_t> src_kind, src_ref, src_sign, bin_of;
+    std::vector<double> P_bin;   // relaxation probability mass per frequency bin
     DevTab host_view{};   // device pointers once uploaded
     void* d_mem = nullptr;
     DevTab* d_tab = nullptr;
@@ -228,6 +230,20 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     for (int m = 0; m < M; ++m) w[m] = t->C[m] / t->tau[m];
     const int64_t last_rel = build_thresholds(w, t->thr_rel);
     if (last_ic < 0 || last_wall < 0 || last_rel < 0) { delete t; return MCBTE_ETABLE; }
+    // frequency bins: the parameters of the sensitivities dkappa / dln tau_i
+    int32_t n_bins = 0;
+    t->bin_of.resize(M);
+    for (int m = 0; m < M; ++m) {
+        if (modes[m].bin < 0 || modes[m].bin >= (1 << 20)) { delete t; return MCBTE_EINVAL; }
+        t->bin_of[m] = modes[m].bin;
+        n_bins = std::max(n_bins, modes[m].bin + 1);
+    }
+    t->P_bin.assign(n_bins, 0.0);
+    {
+        double Wr = 0.0;
+        for (int m = 0; m < M; ++m) Wr += t->C[m] / t->tau[m];
+        for (int m = 0; m < M; ++m) t->P_bin[t->bin_of[m]] += (t->C[m] / t->tau[m]) / Wr;
+    }
 
     auto extent = [&](int a) { return g.unbounded[a] ? 1.0 : g.L[a]; };
     double V = g.volume;
@@ -300,6 +316,8 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     inf.n_cells = n_cells;
     inf.n_cols = n_cols;
     inf.tally_bytes = MCBTE_TALLY_HEADER_BYTES + n_cells * n_cols * 4 * (int64_t)sizeof(double);
+    inf.n_bins = n_bins;
+    inf.adj_doubles = (int64_t)n_bins + 2;
     inf.device = device;
 
     // device view
@@ -337,6 +355,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         }
     }
     h.max_events = pr.max_events;
+    h.n_bins = n_bins;
     h.t_max = pr.transient ? pr.t_max : 0.0;
     h.last_ic = last_ic;
     h.last_wall = last_wall;
@@ -420,6 +439,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         add(t->ic_edges.data(), 8 * t->ic_edges.size());
         add(t->t_meas.data(), 8 * t->t_meas.size());
         add(tm32.data(), 4 * tm32.size());
+        add(t->bin_of.data(), 4 * (size_t)M);
         size_t total = 0;
         std::vector<size_t> off;
         for (auto& p : parts) {
@@ -447,6 +467,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         h.ic_edges = (const double*)dptr(12);
         h.t_meas64 = (const double*)dptr(13);
         h.t_meas32 = (const float*)dptr(14);
+        h.bin_of = (const int32_t*)dptr(15);
         parts[0].first = &h;
         for (size_t i = 0; i < parts.size(); ++i) {
             if (parts[i].second == 0) continue;
@@ -520,7 +541,7 @@ struct LaunchPlan {
     size_t lds;
 };
 
-int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run, bool batch, LaunchPlan& lp)
+int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run, int mode, LaunchPlan& lp)
 {
     const mcbte_tables* t0 = ts[0];
     const int prec = run->precision;
@@ -534,15 +555,22 @@ int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run,
     }
     if (lds_tab > MCBTE_LDS_TABLE_BYTES || lds_tab > t0->max_lds) return MCBTE_EINVAL;
     lp.lds_tab = lds_tab;
-    lp.tally_lds = (lds_tally <= MCBTE_LDS_TALLY_BYTES && lds_tab + lds_tally <= t0->max_lds) ? 1 : 0;
-    lp.lds = (size_t)(lds_tab + (lp.tally_lds ? lds_tally : 0));
+    if (mode == 2) {   // sensitivity replay: the per-bin sums take the place of the tallies
+        const int64_t bins = 8 * t0->info.n_bins;
+        if (lds_tab + bins > t0->max_lds) return MCBTE_EINVAL;
+        lp.tally_lds = 0;
+        lp.lds = (size_t)(lds_tab + bins);
+    } else {
+        lp.tally_lds = (lds_tally <= MCBTE_LDS_TALLY_BYTES && lds_tab + lds_tally <= t0->max_lds) ? 1 : 0;
+        lp.lds = (size_t)(lds_tab + (lp.tally_lds ? lds_tally : 0));
+    }
     lp.block = run->block > 0 ? run->block : 256;
     if (lp.block % 64 != 0 || lp.block > 256) return MCBTE_EINVAL;
     lp.refill = run->refill > 0 ? run->refill : 4;
     if (run->grid > 0) {
         lp.grid = run->grid;
     } else {
-        const int occ = trace_occupancy(batch, prec, t0->host_view.tally_kind, lp.block, lp.lds);
+        const int occ = trace_occupancy(mode, prec, t0->host_view.tally_kind, lp.block, lp.lds);
         lp.grid = std::max(1, occ) * std::max(1, t0->n_cu);
     }
     return MCBTE_OK;
@@ -561,7 +589,7 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     DeviceGuard g(t->device);
     if (!g.ok) return MCBTE_EHIP;
     LaunchPlan lp;
-    const int rc = plan_launch(&t, 1, run, false, lp);
+    const int rc = plan_launch(&t, 1, run, 0, lp);
     if (rc != MCBTE_OK) return rc;
     LaunchArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -580,7 +608,8 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     a.n_log = run->event_log ? run->n_log : 0;
     a.tally_lds = lp.tally_lds;
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
-    const hipError_t e = launch_trace(a, false, run->precision, t->host_view.tally_kind, lp.block, lp.grid, lp.lds,
+    a.particle_F = run->particle_F;
+    const hipError_t e = launch_trace(a, 0, run->precision, t->host_view.tally_kind, lp.block, lp.grid, lp.lds,
                                       (hipStream_t)stream);
     return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
 }
@@ -611,7 +640,8 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     DeviceGuard g(t0->device);
     if (!g.ok) return MCBTE_EHIP;
     LaunchPlan lp;
-    int rc = plan_launch(ts, n_inst, run, true, lp);
+    if (run->particle_F) return MCBTE_EINVAL;
+    int rc = plan_launch(ts, n_inst, run, 1, lp);
     if (rc != MCBTE_OK) return rc;
     // chunking: items of chunk_size particles, instance-major
     const int64_t chunk = 8192;
@@ -657,8 +687,66 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     a.n_chunks = cstart[n_inst];
     a.tally_lds = lp.tally_lds;
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
-    const hipError_t e = launch_trace(a, true, run->precision, t0->host_view.tally_kind, lp.block, lp.grid, lp.lds, s);
+    const hipError_t e = launch_trace(a, 1, run->precision, t0->host_view.tally_kind, lp.block, lp.grid, lp.lds, s);
     return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
+}
+
+int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, int64_t n, const double* particle_F,
+                  double* adj, void* stream)
+{
+    if (!t || !run || !particle_F || !adj || n < 0 || first_pid < 0) return MCBTE_EINVAL;
+    if (run->precision != 32 && run->precision != 64) return MCBTE_EINVAL;
+    if (run->event_log) return MCBTE_EINVAL;
+    if (t->device < 0 || !t->d_tab) return MCBTE_ENODEV;
+    if (t->prob.transient) return MCBTE_EINVAL;
+    if (n == 0) return MCBTE_OK;
+    DeviceGuard g(t->device);
+    if (!g.ok) return MCBTE_EHIP;
+    LaunchPlan lp;
+    const int rc = plan_launch(&t, 1, run, 2, lp);
+    if (rc != MCBTE_OK) return rc;
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.tabs = t->d_tab;
+    a.n_inst = 1;
+    a.refill = lp.refill;
+    a.seed = run->seed;
+    a.inst0 = run->instance;
+    a.log_stride = 2;
+    a.first_pid = first_pid;
+    a.n = n;
+    a.capacity = n;
+    a.lds_tab_bytes = (int32_t)lp.lds_tab;
+    a.particle_F = const_cast<double*>(particle_F);
+    a.adj = adj;
+    hipStream_t s = (hipStream_t)stream;
+    // the work counter is the last word of the caller's buffer
+    if (launch_zero_u64((unsigned long long*)(adj + t->info.n_bins + 1), s) != hipSuccess) return MCBTE_EHIP;
+    const hipError_t e = launch_trace(a, 2, run->precision, t->host_view.tally_kind, lp.block, lp.grid, lp.lds, s);
+    return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
+}
+
+int mcbte_adjoint_finalize(const mcbte_tables* t, const double* adj, int64_t n_particles, double* out, int64_t n_out,
+                           void* stream)
+{
+    if (!t || !adj || !out || n_particles < 1) return MCBTE_EINVAL;
+    if (t->device < 0) return MCBTE_ENODEV;
+    const int64_t nb = t->info.n_bins;
+    if (n_out < nb) return MCBTE_ESIZE;
+    const double gs = t->geom.gradT[t->prob.score_axis];
+    if (gs == 0.0 || t->prob.transient) return MCBTE_EINVAL;
+    DeviceGuard g(t->device);
+    if (!g.ok) return MCBTE_EHIP;
+    std::vector<double> h((size_t)(nb + 1));
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(h.data(), adj, sizeof(double) * (size_t)(nb + 1), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return MCBTE_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return MCBTE_EHIP;
+    // same normalisation as kappa: -E_tot / (V_solid gradT_s N) times the summed scores
+    const double scale = -t->info.E_tot / (t->info.V_solid * gs * (double)n_particles);
+    const double B = h[(size_t)nb];
+    for (int64_t i = 0; i < nb; ++i) out[i] = scale * (h[(size_t)i] + t->P_bin[(size_t)i] * B);
+    return MCBTE_OK;
 }
 
 int mcbte_tally(const mcbte_tables* t, const void* tally, double* host_out, int64_t n_out, mcbte_result* res,

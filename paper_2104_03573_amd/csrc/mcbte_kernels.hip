@@ -152,7 +152,9 @@ template <typename R> struct Part {
     int32_t m, s, nrel;  // mode row, sign, relaxations so far
     uint32_t k, j;       // segments so far, random-number-drawing events so far
     int32_t src;         // source element (event log only)
-    double cT, cq;       // per-particle contributions (variance estimate)
+    double cT, cq;       // per-particle contributions (variance estimate); cq is the flux score F
+    R dtr0;              // free-flight time drawn for the current flight (sensitivity replay)
+    double F0;           // flux score at the start of the current flight (sensitivity replay)
 };
 
 // cosine-weighted direction about the unit normal n (Eq. wall_dir), frame t1 = e_j x n / |.|
@@ -279,6 +281,8 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
     p.t = (T.transient && kind != SRC_IC) ? unif<R>(r2a.z, r2a.w) * (R)T.t_max : R(0);
     const R tau = Geo<R>::tau(T)[p.m];
     p.dtr = -tau * r_log(R(1) - unif<R>(r0a.z, r0a.w));
+    p.dtr0 = p.dtr;
+    p.F0 = 0.0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -293,7 +297,7 @@ struct TallyCtx {
 __device__ __forceinline__ void tadd(const TallyCtx& tc, const DevDet& D, int64_t cc, int q, double val)
 {
     if (tc.lds) atomicAdd(tc.lds + cc * D.ncomp + D.slot[q], val);
-    else atomicAdd(tc.glob + cc * 4 + q, val);
+    else if (tc.glob) atomicAdd(tc.glob + cc * 4 + q, val);
 }
 
 template <typename R>
@@ -471,6 +475,17 @@ struct LogRow {
     }
 };
 
+// likelihood-ratio bookkeeping of the sensitivity replay (dkappa / dln tau per frequency bin):
+// a flight ended by a relaxation scores T/tau - 1, one cut short T/tau, a relaxation draw -1 for
+// the drawn row's bin (plus P_i for every bin, summed into `dense`); each score multiplies the
+// part of the particle's flux score F that follows it
+struct AdjCtx {
+    double* bins;            // LDS, n_bins sums
+    double F_total;          // this particle's F from the forward trace
+    double dense;            // per-lane sum of (F_total - F) over relaxation draws
+    __device__ __forceinline__ void add(int bin, double g, double after) { atomicAdd(bins + bin, g * after); }
+};
+
 template <typename R>
 struct Tabs {
     const uint64_t* thr_rel;   // LDS
@@ -479,14 +494,15 @@ struct Tabs {
 };
 
 // Advance particle p by one segment; returns true when the particle has ended.
-template <typename R, int TK>
+template <typename R, int TK, bool ADJ>
 __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const TallyCtx& tc, const Stream& st,
-                                       Part<R>& p, LaneCounts& cnt, LogRow& lg, bool& coop)
+                                       Part<R>& p, LaneCounts& cnt, LogRow& lg, bool& coop, AdjCtx& adj)
 {
     const DevGeom& g = T.g;
     if ((int64_t)p.k >= T.max_events) {
         ++cnt.c[9];
         lg.put(EV_CAP, 0, p.m);
+        if (ADJ) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
         return true;
     }
     const R vm = tb.v[p.m];
@@ -557,6 +573,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
     if (ev == 2) {
         ++cnt.c[7];
         lg.put(EV_TIMEOUT, 0, p.m);
+        if (ADJ) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
         return true;
     }
     const bool on_face = (ev == 1) && hit <= 6;
@@ -572,6 +589,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
     if (escaped) {
         ++cnt.c[10];
         lg.put(EV_ESCAPE, 0, p.m);
+        if (ADJ) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
         return true;
     }
     // what the event needs
@@ -579,6 +597,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
     if (relax) {
         p.nrel += 1;
         ++cnt.c[2];
+        if (ADJ) adj.add(T.bin_of[p.m], (double)p.dtr0 / T.tau64[p.m] - 1.0, adj.F_total - p.F0);
         if (T.n_scat_max > 0 && p.nrel >= T.n_scat_max) {
             ++cnt.c[8];
             lg.put(EV_NSCAT, 0, p.m);
@@ -604,6 +623,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
         if (btype == 1) {
             ++cnt.c[6];
             lg.put(EV_ABSORB, hit, p.m);
+            if (ADJ) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
             return true;
         }
         if (btype == 3) {   // linearised periodic condition: reinsert unchanged at the partner face
@@ -642,6 +662,12 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
             dir_iso(u1, u2, p.o);
             p.dtr = -tb.tau[p.m] * r_log(R(1) - unif<R>(w0.z, w0.w));
             lg.put(EV_RELAX, 0, p.m);
+            if (ADJ) {
+                adj.add(T.bin_of[p.m], -1.0, adj.F_total - p.cq);
+                adj.dense += adj.F_total - p.cq;
+            }
+            p.dtr0 = p.dtr;
+            p.F0 = p.cq;
         } else {
             R n[3];
             if (pore >= 0) {
@@ -839,6 +865,8 @@ struct StateView {
         rej = (uint32_t)i[6][s];
         p.cT = 0.0;
         p.cq = 0.0;
+        p.dtr0 = p.dtr;
+        p.F0 = 0.0;
     }
 };
 
@@ -946,20 +974,27 @@ __device__ __forceinline__ void end_particle(const Part<R>& p, int transient, do
     if (lg.row) lg.row[0] = (uint32_t)lg.n;
 }
 
-template <typename R, int TK>
+// ADJ = false: the forward trace (tallies, counters, moments, optional per-particle flux score F).
+// ADJ = true: the sensitivity replay of the same particles: no tallies; the likelihood-ratio sums
+// go to LDS bins and then to a.adj; the work counter lives after the sums.
+template <typename R, int TK, bool ADJ>
 __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const DevTab& T = tabs[0];
     const Tabs<R> tb = stage_tables<R>(T, smem);
     double* s_tally = (double*)(smem + a.lds_tab_bytes);
-    if (a.tally_lds) {
+    if (ADJ) {
+        for (int i = threadIdx.x; i < T.n_bins; i += blockDim.x) s_tally[i] = 0.0;
+    } else if (a.tally_lds) {
         const int64_t n = lds_tally_size(T);
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s_tally[i] = 0.0;
     }
     __syncthreads();
-    const TallyCtx tc{a.tally_lds ? s_tally : nullptr, (double*)(a.tally + MCBTE_TALLY_HEADER_BYTES)};
-    unsigned long long* counter = (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET);
+    const TallyCtx tc = ADJ ? TallyCtx{nullptr, nullptr}
+                            : TallyCtx{a.tally_lds ? s_tally : nullptr, (double*)(a.tally + MCBTE_TALLY_HEADER_BYTES)};
+    unsigned long long* counter = ADJ ? (unsigned long long*)(a.adj + T.n_bins + 1)
+                                      : (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET);
     const int lane = threadIdx.x & 63;
     const unsigned long long n = (unsigned long long)a.n;
 
@@ -970,6 +1005,8 @@ __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ t
     for (int q = 0; q < 12; ++q) cnt.c[q] = 0;
     double mom[4] = {0.0, 0.0, 0.0, 0.0};
     LogRow lg{nullptr, 0, a.log_stride};
+    AdjCtx adj{s_tally, 0.0, 0.0};
+    int64_t my_pid = 0;
     bool alive = false;
     bool exhausted = false;        // wave-uniform: the particle counter has run past n
     int since_refill = 0;
@@ -988,7 +1025,9 @@ __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ t
                 if (!alive) {
                     const unsigned long long idx = base + wave_rank(need);
                     if (idx < n) {
-                        start_particle<R, TK>(T, a, a.first_pid + (int64_t)idx, a.inst0, p, st, cnt, lg);
+                        my_pid = a.first_pid + (int64_t)idx;
+                        start_particle<R, TK>(T, a, my_pid, a.inst0, p, st, cnt, lg);
+                        if (ADJ) adj.F_total = a.particle_F[idx];
                         alive = true;
                     }
                 }
@@ -1002,8 +1041,9 @@ __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ t
         ++since_refill;
         bool coop = false;
         if (alive) {
-            if (flight<R, TK>(T, tb, tc, st, p, cnt, lg, coop)) {
+            if (flight<R, TK, ADJ>(T, tb, tc, st, p, cnt, lg, coop, adj)) {
                 end_particle(p, T.transient, mom, lg);
+                if (!ADJ && a.particle_F) a.particle_F[my_pid - a.first_pid] = p.cq;
                 alive = false;
             }
         }
@@ -1011,6 +1051,14 @@ __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ t
             for (unsigned long long pend = __ballot(coop); pend; pend &= pend - 1ull)
                 coop_bounces<R>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
         }
+    }
+    if (ADJ) {
+        const double d = wave_sum<double>(adj.dense);
+        if (lane == 0 && d != 0.0) atomicAdd(a.adj + T.n_bins, d);
+        __syncthreads();
+        for (int i = threadIdx.x; i < T.n_bins; i += blockDim.x)
+            if (s_tally[i] != 0.0) atomicAdd(a.adj + i, s_tally[i]);
+        return;
     }
     flush_lane_stats(a.tally, cnt, mom);
     if (a.tally_lds) {
@@ -1084,6 +1132,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
         Part<R> p;
         Stream st{0u, 0u, 0u, 0u, 0u};
         LogRow lg{nullptr, 0, 2};
+        AdjCtx adj{nullptr, 0.0, 0.0};
         bool alive = false;
         bool exhausted = false;
         int since_refill = 0;
@@ -1122,7 +1171,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
             ++since_refill;
             bool coop = false;
             if (alive) {
-                if (flight<R, TK>(T, tb, tc, st, p, cnt, lg, coop)) {
+                if (flight<R, TK, false>(T, tb, tc, st, p, cnt, lg, coop, adj)) {
                     end_particle(p, T.transient, mom, lg);
                     alive = false;
                 }
@@ -1172,14 +1221,19 @@ static void ensure_lds_limit(const void* fn, size_t lds)
 }
 
 template <typename R, int TK>
-static hipError_t trace_t(const LaunchArgs& a, bool batch, int block, int grid, size_t lds, hipStream_t s)
+static hipError_t trace_t(const LaunchArgs& a, int mode, int block, int grid, size_t lds, hipStream_t s)
 {
-    if (batch) {
+    // mode 0: solo trace, 1: batched trace, 2: sensitivity replay
+    if (mode == 1) {
         auto fn = k_trace_batch<R, TK>;
         ensure_lds_limit((const void*)fn, lds);
         hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a.tabs, a);
+    } else if (mode == 2) {
+        auto fn = k_trace_solo<R, TK, true>;
+        ensure_lds_limit((const void*)fn, lds);
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a.tabs, a);
     } else {
-        auto fn = k_trace_solo<R, TK>;
+        auto fn = k_trace_solo<R, TK, false>;
         ensure_lds_limit((const void*)fn, lds);
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s,
                            (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET));
@@ -1188,29 +1242,37 @@ static hipError_t trace_t(const LaunchArgs& a, bool batch, int block, int grid, 
     return hipGetLastError();
 }
 
-hipError_t launch_trace(const LaunchArgs& a, bool batch, int precision, int tally_kind, int block, int grid, size_t lds,
+hipError_t launch_trace(const LaunchArgs& a, int mode, int precision, int tally_kind, int block, int grid, size_t lds,
                         hipStream_t s)
 {
     if (precision == 64) {
         switch (tally_kind) {
-        case TALLY_STEADY_ONE: return trace_t<double, TALLY_STEADY_ONE>(a, batch, block, grid, lds, s);
-        case TALLY_STEADY_GRID: return trace_t<double, TALLY_STEADY_GRID>(a, batch, block, grid, lds, s);
-        default: return trace_t<double, TALLY_TRANSIENT>(a, batch, block, grid, lds, s);
+        case TALLY_STEADY_ONE: return trace_t<double, TALLY_STEADY_ONE>(a, mode, block, grid, lds, s);
+        case TALLY_STEADY_GRID: return trace_t<double, TALLY_STEADY_GRID>(a, mode, block, grid, lds, s);
+        default: return trace_t<double, TALLY_TRANSIENT>(a, mode, block, grid, lds, s);
         }
     }
     switch (tally_kind) {
-    case TALLY_STEADY_ONE: return trace_t<float, TALLY_STEADY_ONE>(a, batch, block, grid, lds, s);
-    case TALLY_STEADY_GRID: return trace_t<float, TALLY_STEADY_GRID>(a, batch, block, grid, lds, s);
-    default: return trace_t<float, TALLY_TRANSIENT>(a, batch, block, grid, lds, s);
+    case TALLY_STEADY_ONE: return trace_t<float, TALLY_STEADY_ONE>(a, mode, block, grid, lds, s);
+    case TALLY_STEADY_GRID: return trace_t<float, TALLY_STEADY_GRID>(a, mode, block, grid, lds, s);
+    default: return trace_t<float, TALLY_TRANSIENT>(a, mode, block, grid, lds, s);
     }
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p);
+    return hipGetLastError();
 }
 
 // occupancy of the trace kernel (workgroups per compute unit) for a block size and LDS size,
 // cached per (kernel, block, LDS)
-int trace_occupancy(bool batch, int precision, int tally_kind, int block, size_t lds)
+int trace_occupancy(int mode, int precision, int tally_kind, int block, size_t lds)
 {
     const void* fn = nullptr;
-#define MCBTE_PICK(RR, TKK) fn = batch ? (const void*)k_trace_batch<RR, TKK> : (const void*)k_trace_solo<RR, TKK>
+#define MCBTE_PICK(RR, TKK)                                                                    \
+    fn = mode == 1 ? (const void*)k_trace_batch<RR, TKK>                                        \
+                   : (mode == 2 ? (const void*)k_trace_solo<RR, TKK, true> : (const void*)k_trace_solo<RR, TKK, false>)
     if (precision == 64) {
         if (tally_kind == TALLY_STEADY_ONE) MCBTE_PICK(double, TALLY_STEADY_ONE);
         else if (tally_kind == TALLY_STEADY_GRID) MCBTE_PICK(double, TALLY_STEADY_GRID);

@@ -59,13 +59,14 @@ class Info(C.Structure):
     _fields_ = [("C_tot", C.c_double), ("sum_Cv", C.c_double), ("E_tot", C.c_double), ("e_eff", C.c_double),
                 ("V_solid", C.c_double), ("kappa_bulk", C.c_double), ("n_modes", C.c_int64),
                 ("n_sources", C.c_int64), ("n_cells", C.c_int64), ("n_cols", C.c_int64),
-                ("tally_bytes", C.c_int64), ("device", C.c_int32), ("reserved", C.c_int32)]
+                ("tally_bytes", C.c_int64), ("n_bins", C.c_int64), ("adj_doubles", C.c_int64),
+                ("device", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Run(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("instance", C.c_uint32), ("precision", C.c_int32), ("block", C.c_int32),
                 ("refill", C.c_int32), ("grid", C.c_int32), ("log_stride", C.c_int32), ("n_log", C.c_int64),
-                ("event_log", C.c_void_p)]
+                ("event_log", C.c_void_p), ("particle_F", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -77,7 +78,7 @@ class Result(C.Structure):
 
 EXPORTED = ["mcbte_build_tables", "mcbte_free_tables", "mcbte_table_info", "mcbte_table_export",
             "mcbte_state_bytes", "mcbte_emit", "mcbte_trace", "mcbte_batch_queue_bytes", "mcbte_trace_batch",
-            "mcbte_tally", "mcbte_strerror"]
+            "mcbte_adjoint", "mcbte_adjoint_finalize", "mcbte_tally", "mcbte_strerror"]
 
 _lib = None
 
@@ -111,6 +112,10 @@ def lib():
         L.mcbte_trace_batch.argtypes = [C.POINTER(p), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
                                         C.POINTER(p), C.POINTER(Run), p, p]
         L.mcbte_trace_batch.restype = C.c_int
+        L.mcbte_adjoint.argtypes = [p, C.POINTER(Run), C.c_int64, C.c_int64, p, p, p]
+        L.mcbte_adjoint.restype = C.c_int
+        L.mcbte_adjoint_finalize.argtypes = [p, p, C.c_int64, C.POINTER(C.c_double), C.c_int64, p]
+        L.mcbte_adjoint_finalize.restype = C.c_int
         L.mcbte_tally.argtypes = [p, p, C.POINTER(C.c_double), C.c_int64, C.POINTER(Result), p]
         L.mcbte_tally.restype = C.c_int
         L.mcbte_strerror.argtypes = [C.c_int]
@@ -217,10 +222,11 @@ def state_bytes(precision: int, capacity: int) -> int:
 
 
 def make_run(seed: int, precision: int = 32, instance: int = 0, block: int = 0, refill: int = 0, grid: int = 0,
-             event_log=None, n_log: int = 0, log_stride: int = 64) -> Run:
+             event_log=None, n_log: int = 0, log_stride: int = 64, particle_F=None) -> Run:
     return Run(seed & 0xFFFFFFFFFFFFFFFF, instance, precision, block, refill, grid, log_stride,
                n_log if event_log is not None else 0,
-               C.c_void_p(event_log.data_ptr()) if event_log is not None else None)
+               C.c_void_p(event_log.data_ptr()) if event_log is not None else None,
+               C.c_void_p(particle_F.data_ptr()) if particle_F is not None else None)
 
 
 def emit(t: "Tables", run: Run, first_pid: int, n: int, state, capacity: int, stream=None):
@@ -249,6 +255,19 @@ def trace_batch(tables: list, n_particles, instance_ids, tallies: list, run: Run
     tp = (C.c_void_p * k)(*[tl.data_ptr() for tl in tallies])
     _check("mcbte_trace_batch", lib().mcbte_trace_batch(th, k, npart, ids, tp, C.byref(run),
                                                         C.c_void_p(queue.data_ptr()), _stream(stream)))
+
+
+def adjoint(t: "Tables", run: Run, first_pid: int, n: int, particle_F, adj, stream=None):
+    _check("mcbte_adjoint", lib().mcbte_adjoint(t.h, C.byref(run), first_pid, n, C.c_void_p(particle_F.data_ptr()),
+                                                C.c_void_p(adj.data_ptr()), _stream(stream)))
+
+
+def adjoint_finalize(t: "Tables", adj, n_particles: int, stream=None) -> np.ndarray:
+    nb = t.info["n_bins"]
+    out = np.zeros(nb)
+    _check("mcbte_adjoint_finalize", lib().mcbte_adjoint_finalize(
+        t.h, C.c_void_p(adj.data_ptr()), n_particles, out.ctypes.data_as(C.POINTER(C.c_double)), nb, _stream(stream)))
+    return out
 
 
 def tally(t: "Tables", tally_buf, stream=None, with_arrays: bool = True) -> dict:
@@ -326,4 +345,27 @@ def run(w: dict, n: int | None = None, first_pid: int = 0, precision: int = 32, 
     out["tables"] = t
     if n_log:
         out["log"] = log.view(n_log, log_stride).cpu().numpy().view(np.uint32)
+    return out
+
+
+def sensitivities(w: dict, n: int | None = None, first_pid: int = 0, precision: int = 32, device: int = 0,
+                  tables: Tables | None = None, **launch) -> dict:
+    """Forward trace (recording each particle's flux score) then the replay that accumulates the
+    likelihood-ratio sums: kappa and dkappa / dln tau_i per frequency bin."""
+    import torch
+    t = tables or Tables(w, device)
+    n = w["problem"]["N"] if n is None else int(n)
+    dev = f"cuda:{device}"
+    F = torch.zeros(n, dtype=torch.float64, device=dev)
+    tl = t.new_tally()
+    r = make_run(int(w["seed"]), precision, int(w.get("instance", 0)), particle_F=F, **launch)
+    trace(t, r, first_pid, n, None, tl)
+    adj = torch.zeros(t.info["adj_doubles"], dtype=torch.float64, device=dev)
+    r2 = make_run(int(w["seed"]), precision, int(w.get("instance", 0)), **launch)
+    adjoint(t, r2, first_pid, n, F, adj)
+    out = tally(t, tl, with_arrays=False)
+    out["dkappa_dlntau"] = adjoint_finalize(t, adj, n)
+    out["F"] = F.cpu().numpy()
+    out["adj_raw"] = adj.cpu().numpy()
+    out["tables"] = t
     return out
