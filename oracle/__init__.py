@@ -107,7 +107,7 @@ def lib():
         L.orc_tally_segment.argtypes = [p, p, p, C.c_double, C.c_int32, C.c_double, p]
         L.orc_emit_state.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, p, p]
         L.orc_emit_state.restype = C.c_int
-        L.orc_adjoint.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, p, p, p]
+        L.orc_adjoint.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, C.c_int32, p, p, p, p]
         L.orc_adjoint.restype = C.c_int
         L.orc_next_boundary.argtypes = [p, p, p, p]
         L.orc_next_boundary.restype = C.c_double
@@ -375,12 +375,17 @@ def run_batches(w: dict, n_batches: int, n: int | None = None, threads: int = 8)
 
 
 def adjoint(w: dict, n: int | None = None, first_pid: int = 0, threads: int = 1, n_batches: int = 1,
-            tables: Tables | None = None) -> dict:
-    """Score-function estimate of dkappa / dln tau_i (per frequency bin) over particles
-    [first_pid, first_pid + n), with batch-mean standard errors when n_batches > 1.
+            tables: Tables | None = None, estimator: str = "score", per_particle: bool = False) -> dict:
+    """Estimate of dkappa / dln tau_i (per frequency bin) over particles [first_pid, first_pid + n),
+    with batch-mean standard errors when n_batches > 1.  estimator "score": likelihood ratios of
+    the free flights (Eq. time_to_scat) and of the relaxation draws (Eq. norm_post_coll);
+    "pathwise": the flights differentiated through their lengths (tangents carried along the
+    trajectory), the draws by their likelihood ratios.
 
     dkappa/dln tau_i = -E_tot / (V_solid gradT_s n) * (sparse_i + P_i B), the same normalisation
-    as kappa = -E_tot / (V_solid gradT_s n) * sum_p F_p (section 3.6, Eq. flux_x_steady)."""
+    as kappa = -E_tot / (V_solid gradT_s n) * sum_p F_p (section 3.6, Eq. flux_x_steady).
+    per_particle (pathwise only): also return each particle's tangent terms per bin, unscaled."""
+    kind = {"score": 0, "pathwise": 1}[estimator]
     tb = tables or Tables(w)
     n = w["problem"]["N"] if n is None else int(n)
     inst = int(w.get("instance", 0))
@@ -392,17 +397,19 @@ def adjoint(w: dict, n: int | None = None, first_pid: int = 0, threads: int = 1,
         sp = np.zeros(tb.n_bins)
         de = np.zeros(1)
         F = np.zeros(hi - lo)
-        rc = lib().orc_adjoint(tb.h, int(w["seed"]), inst, lo, hi - lo, _ptr(sp), _ptr(de), _ptr(F))
+        pp = np.zeros((hi - lo, tb.n_bins)) if per_particle else None
+        rc = lib().orc_adjoint(tb.h, int(w["seed"]), inst, lo, hi - lo, kind, _ptr(sp), _ptr(de), _ptr(F),
+                               _ptr(pp) if pp is not None else None)
         if rc != 0:
             raise ValueError(f"oracle adjoint failed with status {rc}")
-        return sp, float(de[0]), F
+        return sp, float(de[0]), F, pp
 
     with ThreadPoolExecutor(max(1, min(threads, nb))) as ex:
         parts = list(ex.map(one, range(nb)))
     g = w["geometry"]["gradT"][w["problem"]["score_axis"]]
     P = tb.get("P_bin")
     per_batch = []
-    for (sp, de, F), lo, hi in zip(parts, bounds[:-1], bounds[1:]):
+    for (sp, de, F, _), lo, hi in zip(parts, bounds[:-1], bounds[1:]):
         scale = -tb.E_tot / (tb.V_solid * g * (hi - lo))
         per_batch.append(scale * (sp + P * de))
     sp = sum(p[0] for p in parts)
@@ -410,7 +417,9 @@ def adjoint(w: dict, n: int | None = None, first_pid: int = 0, threads: int = 1,
     F = np.concatenate([p[2] for p in parts])
     scale = -tb.E_tot / (tb.V_solid * g * n)
     out = {"dkappa_dlntau": scale * (sp + P * de), "sparse": sp, "dense": de, "F": F, "P_bin": P,
-           "kappa": scale * F.sum(), "tables": tb}
+           "kappa": scale * F.sum(), "tables": tb, "scale": scale}
+    if per_particle:
+        out["per_particle"] = np.concatenate([p[3] for p in parts])
     if nb > 1:
         arr = np.array(per_batch)
         out["dkappa_dlntau_sigma"] = arr.std(0, ddof=1) / math.sqrt(nb)

@@ -701,11 +701,31 @@ int orc_emit_state(const orc_tables* t, uint64_t seed, uint32_t instance, int64_
        d ln p_j / d ln tau_i = -[bin(j) = i] + P_i, with F after the draw; the P_i part is the same
        for every draw and is summed into one number B per run. */
 typedef struct { int32_t bin, dense; double g, F_before; } adj_ev;
-typedef struct { adj_ev* ev; int64_t n, cap; int failed; } adj_list;
+
+/* Pathwise (reparametrisation) form: a free flight of mode m covers the distance
+   L = v_m tau_m E with E = -ln(1 - u) fixed by its random numbers, so dL / dln tau_m = L.  With
+   the sequence of events held fixed, the first-order change of the trajectory caused by that
+   stretch is a tangent (dx, dO, b): the shift of the current position and direction, and b, the
+   change of the distance left in the current flight.  It is born at the start of its flight with
+   b = L, carried through every later segment end (a boundary hit moves along the surface, a
+   reflection turns dO, a relaxation spends b and forgets dO because the new direction is drawn
+   independently of the position), and at the particle's end it changes F = s (x_end - x_start)_a
+   (the flux score is the net unwrapped displacement along the scored axis) by s dx_a.  The
+   relaxation draws still enter through their scores (-[bin(j) = i] + P_i) times the F that
+   follows them. */
+typedef struct { int32_t bin; double dx[3], dO[3], b; } tangent;
+
+typedef struct {
+    adj_ev* ev; int64_t n, cap; int failed;
+    int pathwise;               /* 1: tangents for the flights, scores only for the draws */
+    tangent* tg; int64_t nt, tcap;
+    int32_t sign;               /* the particle's sign s */
+} adj_list;
 
 static void adj_push(adj_list* al, int32_t bin, double g, double F_before, int dense)
 {
     if (!al) return;
+    if (al->pathwise && !dense) return;       /* flight scores: replaced by the tangents */
     if (al->n == al->cap) {
         int64_t cap = al->cap ? 2 * al->cap : 64;
         adj_ev* e = (adj_ev*)realloc(al->ev, sizeof(adj_ev) * cap);
@@ -718,6 +738,107 @@ static void adj_push(adj_list* al, int32_t bin, double g, double F_before, int d
     e->g = g;
     e->F_before = F_before;
     e->dense = dense;
+}
+
+/* a new flight of mode row m, distance L: its tangent; every earlier one has spent its b and
+   forgotten its direction shift at the relaxation that started this flight */
+static void tan_birth(adj_list* al, int32_t bin, double L)
+{
+    if (!al || !al->pathwise) return;
+    if (al->nt == al->tcap) {
+        int64_t cap = al->tcap ? 2 * al->tcap : 16;
+        tangent* e = (tangent*)realloc(al->tg, sizeof(tangent) * cap);
+        if (!e) { al->failed = 1; return; }
+        al->tg = e;
+        al->tcap = cap;
+    }
+    tangent* q = &al->tg[al->nt++];
+    memset(q, 0, sizeof(*q));
+    q->bin = bin;
+    q->b = L;
+}
+
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* the segment x -> x + d o ended on a surface with unit normal n at the hit point: the hit point
+   stays on the surface, n . (dx + dd o + d dO) = 0, and the flight has dd less distance left */
+static void tan_hit(adj_list* al, const double o[3], double d, const double n[3])
+{
+    if (!al || !al->pathwise) return;
+    const double on = dot3(o, n);
+    for (int64_t i = 0; i < al->nt; ++i) {
+        tangent* q = &al->tg[i];
+        const double dd = -(dot3(n, q->dx) + d * dot3(n, q->dO)) / on;
+        for (int a = 0; a < 3; ++a) q->dx[a] = q->dx[a] + dd * o[a] + d * q->dO[a];
+        q->b = q->b - dd;
+    }
+}
+
+/* the segment x -> x + d o ended in a relaxation: the end point moves with the distance left and
+   with the direction; the next direction is drawn afresh */
+static void tan_relax(adj_list* al, const double o[3], double d)
+{
+    if (!al || !al->pathwise) return;
+    for (int64_t i = 0; i < al->nt; ++i) {
+        tangent* q = &al->tg[i];
+        for (int a = 0; a < 3; ++a) q->dx[a] = q->dx[a] + q->b * o[a] + d * q->dO[a];
+        q->b = 0.0;
+        q->dO[0] = q->dO[1] = q->dO[2] = 0.0;
+    }
+}
+
+/* reflection off a plane with normal along axis fa: specular negates that direction component,
+   diffuse draws a direction that does not depend on the hit point */
+static void tan_plane(adj_list* al, int fa, int specular)
+{
+    if (!al || !al->pathwise) return;
+    for (int64_t i = 0; i < al->nt; ++i) {
+        tangent* q = &al->tg[i];
+        if (specular) q->dO[fa] = -q->dO[fa];
+        else q->dO[0] = q->dO[1] = q->dO[2] = 0.0;
+    }
+}
+
+/* reflection off the cylinder of radius r: the normal n = (x_h - c)_xy / r turns with the hit
+   point, dn = (dx_h)_xy / r.  Specular: o' = o - 2 (o.n) n (o before the reflection).  Diffuse:
+   o' = mu n + a t1 + c t2 with mu, a, c fixed by the random numbers and the frame of the
+   cosine-weighted draw, t1 = (e_j x n) / |e_j x n|, t2 = n x t1 (o = o' after the reflection). */
+static void tan_cyl(adj_list* al, const double o[3], const double n[3], double r, int specular)
+{
+    if (!al || !al->pathwise) return;
+    double e[3] = {0.0, 0.0, 0.0}, c[3], t1[3], t2[3];
+    double len = 0.0, mu = 0.0, ca = 0.0, cb = 0.0;
+    if (!specular) {
+        int j = 0;
+        if (fabs(n[1]) < fabs(n[j])) j = 1;
+        if (fabs(n[2]) < fabs(n[j])) j = 2;
+        e[j] = 1.0;
+        cross3(e, n, c);
+        len = sqrt(dot3(c, c));
+        for (int a = 0; a < 3; ++a) t1[a] = c[a] / len;
+        cross3(n, t1, t2);
+        mu = dot3(o, n);
+        ca = dot3(o, t1);
+        cb = dot3(o, t2);
+    }
+    for (int64_t i = 0; i < al->nt; ++i) {
+        tangent* q = &al->tg[i];
+        const double dn[3] = {q->dx[0] / r, q->dx[1] / r, 0.0};
+        if (specular) {
+            const double on = dot3(o, n);
+            const double don = dot3(q->dO, n) + dot3(o, dn);
+            for (int a = 0; a < 3; ++a) q->dO[a] = q->dO[a] - 2.0 * don * n[a] - 2.0 * on * dn[a];
+        } else {
+            double dc[3], dt1[3], dt2[3], u[3], w[3];
+            cross3(e, dn, dc);
+            const double p1 = dot3(t1, dc);
+            for (int a = 0; a < 3; ++a) dt1[a] = (dc[a] - p1 * t1[a]) / len;
+            cross3(dn, t1, u);
+            cross3(n, dt1, w);
+            for (int a = 0; a < 3; ++a) dt2[a] = u[a] + w[a];
+            for (int a = 0; a < 3; ++a) q->dO[a] = mu * dn[a] + ca * dt1[a] + cb * dt2[a];
+        }
+    }
 }
 
 static uint32_t pack_ev(int ev, int64_t bnd, int32_t m)
@@ -753,6 +874,8 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
     const int sa = pr->score_axis;
     double dtr0 = p.dtr;       /* free-flight time drawn for the current flight */
     double F0 = 0.0;           /* flux contribution at the start of the current flight */
+    if (al) al->sign = p.s;
+    tan_birth(al, t->bin[p.m], t->v[p.m] * p.dtr);
 #define CENSORED() adj_push(al, t->bin[p.m], (dtr0 - p.dtr) / t->tau[p.m], F0, 0)
     for (;;) {
         if ((int64_t)p.k >= pr->max_events) {
@@ -810,6 +933,23 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
             face_side = FACE_SIDE[hit - 1];
             p.x[face_axis] = face_side ? g->L[face_axis] : 0.0;      /* exactly on the wall */
         }
+        if (al && al->pathwise) {                  /* the segment's end, for the tangents */
+            if (ev == EV_RELAX) {
+                tan_relax(al, p.o, d);
+            } else {
+                double nh[3] = {0.0, 0.0, 0.0};
+                if (hit <= 6) {
+                    nh[face_axis] = face_side ? -1.0 : 1.0;
+                } else {
+                    for (int c = 0; c < g->n_cyl; ++c)
+                        if (g->cyl[c].id == hit) {
+                            nh[0] = (p.x[0] - g->cyl[c].cx) / g->cyl[c].r;
+                            nh[1] = (p.x[1] - g->cyl[c].cy) / g->cyl[c].r;
+                        }
+                }
+                tan_hit(al, p.o, d, nh);
+            }
+        }
         int escaped = 0;
         for (int a = 0; a < 3; ++a)
             if (!g->unbounded[a] && (p.x[a] < -1e-9 * g->L[a] || p.x[a] > g->L[a] + 1e-9 * g->L[a])) escaped = 1;
@@ -838,6 +978,7 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
             p.dtr = -t->tau[p.m] * log(1.0 - unif(R, 2));
             LOG(ORC_EV_RELAX, 0, p.m);
             adj_push(al, t->bin[p.m], -1.0, p.cq, 1);                        /* the draw of the new row */
+            tan_birth(al, t->bin[p.m], t->v[p.m] * p.dtr);
             dtr0 = p.dtr;
             F0 = p.cq;
             continue;
@@ -889,6 +1030,8 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
             n[face_axis] = face_side ? -1.0 : 1.0;
         }
         if (specular) {
+            if (cy) tan_cyl(al, p.o, n, cy->r, 1);
+            else tan_plane(al, face_axis, 1);
             if (cy) {                                 /* Eq. specular: k' = k - 2 (k.n) n */
                 double k2 = 2.0 * (p.o[0] * n[0] + p.o[1] * n[1] + p.o[2] * n[2]);
                 for (int a = 0; a < 3; ++a) p.o[a] = p.o[a] - k2 * n[a];
@@ -903,6 +1046,8 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
                 orc_record(seed, inst, pid, 2u + p.j, R);
             }
             orc_dir_cos(unif(R, 4), unif(R, 6), n, p.o);
+            if (cy) tan_cyl(al, p.o, n, cy->r, 0);
+            else tan_plane(al, face_axis, 0);
             counts[ORC_C_DIFFUSE] += 1;
             LOG(ORC_EV_DIFFUSE, hit, p.m);
         }
@@ -936,9 +1081,9 @@ int orc_trace(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t fir
 }
 
 int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t first_pid, int64_t n,
-                double* sparse, double* dense, double* F_out)
+                int32_t kind, double* sparse, double* dense, double* F_out, double* pp_out)
 {
-    if (!t || n < 0 || first_pid < 0 || t->pr.transient) return E_INVAL;
+    if (!t || n < 0 || first_pid < 0 || t->pr.transient || (kind != 0 && kind != 1)) return E_INVAL;
     int cap = 2;
     for (int a = 0; a < 3; ++a) cap += t->det.n[a];
     double* pts = (double*)malloc(sizeof(double) * cap);
@@ -946,9 +1091,13 @@ int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t f
     if (!pts || !raw) { free(pts); free(raw); return E_NOMEM; }
     uint64_t counts[ORC_N_COUNTS] = {0};
     double mom[ORC_N_MOMENTS] = {0};
-    adj_list al = {NULL, 0, 0, 0};
+    adj_list al;
+    memset(&al, 0, sizeof(al));
+    al.pathwise = kind;
+    const int sa = t->pr.score_axis;
     for (int64_t i = 0; i < n; ++i) {
         al.n = 0;
+        al.nt = 0;
         double F = 0.0;
         trace_one(t, seed, instance, first_pid + i, raw, counts, mom, NULL, 0, pts, &al, &F);
         if (al.failed) break;
@@ -957,10 +1106,16 @@ int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t f
             sparse[al.ev[e].bin] += al.ev[e].g * after;
             if (al.ev[e].dense) *dense += after;
         }
+        for (int64_t e = 0; e < al.nt; ++e) {
+            const double c = (double)al.sign * al.tg[e].dx[sa];
+            sparse[al.tg[e].bin] += c;
+            if (pp_out) pp_out[i * t->n_bins + al.tg[e].bin] += c;
+        }
         if (F_out) F_out[i] = F;
     }
     int failed = al.failed;
     free(al.ev);
+    free(al.tg);
     free(pts);
     free(raw);
     return failed ? E_NOMEM : E_OK;

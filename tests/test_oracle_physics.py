@@ -288,14 +288,122 @@ def test_adjoint_gray_bulk_is_kappa():
         assert abs(a["kappa"] - k_ref) < 4 * a["dkappa_dlntau_sigma"][0]
 
 
-def test_adjoint_film_matches_fuchs_sondheimer_derivative():
+def test_pathwise_gray_bulk_equals_kappa_per_particle():
+    """Gray bulk, periodic cell: stretching every flight by (1 + e) stretches the whole
+    trajectory, so each particle's pathwise term equals its own flux score F (the draw terms of a
+    single mode cancel: -1 + P = 0) and the estimate equals the kappa of the same particles."""
+    for nsm in (1, 4):
+        w = W.bulk_gradient(N=20000, n_scat_max=nsm)
+        a = oracle.adjoint(w, threads=THREADS, estimator="pathwise", per_particle=True)
+        assert np.allclose(a["per_particle"][:, 0], a["F"], rtol=1e-9, atol=1e-12 * np.abs(a["F"]).max())
+        assert a["dkappa_dlntau"][0] == pytest.approx(a["kappa"], rel=1e-10)
+
+
+def _tau_scaled(w, xi, eps):
+    w2 = W.with_(w)
+    w2["modes"]["tau"] = w2["modes"]["tau"] * (1.0 + eps * xi[w2["modes"]["bin"]])
+    return w2
+
+
+_GRAY = W.gray_modes(6400.0, 100e-9 / 6400.0)
+
+
+@pytest.mark.parametrize("name,make", [
+    ("gray_pore_diffuse", lambda: W.with_(W.porous_cell(N=300, modes=_GRAY), **{"problem.format": 2})),
+    ("gray_pore_specular", lambda: W.with_(W.porous_cell(N=300, modes=_GRAY, specularity=1.0),
+                                           **{"problem.format": 2})),
+    ("gray_pore_partial", lambda: W.with_(W.porous_cell(N=300, modes=_GRAY, specularity=0.5),
+                                          **{"problem.format": 2})),
+    ("film_partial", lambda: W.film(N=300, specularity=0.4)),
+    ("dispersive_pore", lambda: W.porous_cell(N=200)),
+    ("dispersive_film", lambda: W.film(N=300)),
+])
+def test_pathwise_tangents_match_per_particle_finite_differences(name, make):
+    """Brute force on single trajectories: scale tau_i by (1 +- e xi_i) with random signs xi over
+    all bins (e = 1e-7, same random numbers).  Wherever neither run changes the particle's event
+    sequence, the central difference of its flux score F is the pathwise part of its derivative,
+    sum_i xi_i (tangent terms)_i -- a check of the tangent transport through boundary hits, specular
+    and diffuse reflections off planes and the cylinder, periodic transfers and relaxations that
+    does not use that transport."""
+    w = make()
+    n = w["problem"]["N"]
+    tb = oracle.Tables(w)
+    xi = np.random.default_rng(11).choice([-1.0, 1.0], size=tb.n_bins)
+    eps = 1e-7
+    a = oracle.adjoint(w, threads=THREADS, estimator="pathwise", per_particle=True)
+    pred = a["per_particle"] @ xi
+    wp, wm = _tau_scaled(w, xi, eps), _tau_scaled(w, xi, -eps)
+    fp = oracle.adjoint(wp, threads=THREADS, estimator="pathwise")["F"]
+    fm = oracle.adjoint(wm, threads=THREADS, estimator="pathwise")["F"]
+    logs = [oracle.trace(x, n, n_log=n, log_stride=4096, threads=THREADS)["log"] for x in (w, wp, wm)]
+    same = np.all(logs[1] == logs[0], axis=1) & np.all(logs[2] == logs[0], axis=1)
+    assert same.mean() > 0.95
+    fd = (fp - fm) / (2 * eps)
+    scale = np.abs(pred[same]).max()
+    assert scale > 0
+    assert np.abs(fd - pred)[same].max() < 1e-7 * scale
+
+
+@pytest.mark.parametrize("estimator", ["score", "pathwise"])
+def test_adjoint_dispersive_bulk_per_bin(estimator):
+    """Dispersive bulk: after a relaxation the new direction is isotropic, so only the first
+    flight carries mean flux and dkappa / dln tau_i = sum over the rows of bin i of
+    C v^2 tau / 3 (groups of 25 bins and the total).  The relaxation times are capped at 1 ns
+    (mean free paths up to 10 um): with the uncapped 2e-5 s of the lowest bins a few particles
+    carry most of their sum and batch errors are unreliable; the relation holds for any table."""
+    modes = W.silicon_like_modes(300.0)
+    modes["tau"] = np.minimum(modes["tau"], 1e-9)
+    n = 300000
+    w = W.bulk_gradient(N=n, n_scat_max=3, modes=modes)
+    a = oracle.adjoint(w, threads=THREADS, n_batches=NB, estimator=estimator)
+    tb = a["tables"]
+    C = tb.get("C")
+    m = w["modes"]
+    bins = tb.get("bin")
+    ref = np.zeros(tb.n_bins)
+    np.add.at(ref, bins, C * m["v"] ** 2 * m["tau"] / 3.0)
+    # bins are grouped until each group expects >= 2000 emitted particles (emission ~ C v):
+    # bins that are hardly ever emitted have skewed batch means whose spread underestimates
+    # their error
+    p_emit = np.zeros(tb.n_bins)
+    np.add.at(p_emit, bins, C * m["v"])
+    group = _groups_by_count(n * p_emit / p_emit.sum(), 2000.0)
+    pb = a["per_batch"]
+    G = group.max() + 1
+    gb = np.zeros((NB, G))
+    for k in range(NB):
+        np.add.at(gb[k], group, pb[k])
+    gr = np.zeros(G)
+    np.add.at(gr, group, ref)
+    assert G >= 20
+    assert_bins_agree(gb, gr)
+    assert_bins_agree(pb.sum(1)[:, None], np.array([ref.sum()]))
+
+
+def _groups_by_count(expected, least):
+    """Consecutive bins merged into groups with at least `least` expected events each (the last
+    group absorbs a short remainder)."""
+    g = np.zeros(len(expected), dtype=np.int64)
+    k, acc = 0, 0.0
+    for i, e in enumerate(expected):
+        g[i] = k
+        acc += e
+        if acc >= least:
+            k, acc = k + 1, 0.0
+    if acc > 0.0 and k > 0:
+        g[g == k] = k - 1
+    return g
+
+
+@pytest.mark.parametrize("estimator", ["score", "pathwise"])
+def test_adjoint_film_matches_fuchs_sondheimer_derivative(estimator):
     """Diffuse film: only the first flight carries mean flux, so dkappa/dln tau_i is the
     derivative of sum_{m in bin i} kappa_m S(d / Lambda_m) (closed form differentiated); compared
     in groups of 10 frequency bins (single low-frequency bins are too rarely emitted for a batch
     error) and in total."""
     d0 = 100e-9
     w = W.film(N=400000, d=d0)
-    a = oracle.adjoint(w, threads=THREADS, n_batches=NB)
+    a = oracle.adjoint(w, threads=THREADS, n_batches=NB, estimator=estimator)
     tb = a["tables"]
     C = tb.get("C")
     m = w["modes"]
