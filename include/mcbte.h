@@ -41,6 +41,7 @@ extern "C" {
 #define MCBTE_ETABLE (-5)   /* a distribution or the source list has zero weight      */
 #define MCBTE_EGEOM (-6)    /* geometry not closed / periodic faces not paired / pore outside */
 #define MCBTE_ESIZE (-7)    /* a caller buffer is smaller than required               */
+#define MCBTE_ERANGE (-8)   /* a sensitivity term was not finite (mcbte_adjoint_finalize) */
 
 /* boundary types (order of the paper's boundary table, section 4.3) */
 #define MCBTE_ISOTHERMAL 1  /* data[0] = wall temperature T_b                       */
@@ -54,6 +55,11 @@ extern "C" {
 #define MCBTE_TALLY_QZ 8
 
 #define MCBTE_MAX_PORES 8
+
+/* Sensitivity estimators (mcbte_adjoint). */
+#define MCBTE_SENS_SCORE 0          /* likelihood ratio: any steady problem                     */
+#define MCBTE_SENS_PATHWISE 1       /* flight lengths differentiated along the trajectory       */
+#define MCBTE_PATHWISE_MAX_FLIGHTS 16 /* pathwise: n_scat_max must lie in [1, this]             */
 #define MCBTE_N_COUNTS 16
 
 /* counters, indices into the counts array of the tally buffer (all uint64) */
@@ -144,7 +150,7 @@ typedef struct {
     int64_t n_modes, n_sources, n_cells, n_cols;
     int64_t tally_bytes; /* size of the tally buffer mcbte_trace needs                     */
     int64_t n_bins;      /* frequency bins (1 + largest mcbte_mode.bin)                    */
-    int64_t adj_doubles; /* doubles of the buffer mcbte_adjoint needs (n_bins + 2)         */
+    int64_t adj_doubles; /* doubles of the buffer mcbte_adjoint needs (n_bins + 3)         */
     int32_t device;      /* HIP device ordinal, -1 for host-only tables                    */
     int32_t reserved;
 } mcbte_info;
@@ -246,22 +252,39 @@ int mcbte_trace_batch(const mcbte_tables* const* tables, int32_t n_inst, const i
                       void* stream);
 
 /* Sensitivity of kappa to a relative change of the relaxation times of each frequency bin,
-   dkappa / dln tau_i (steady runs with a gradient).  Likelihood-ratio estimator: every random
-   quantity whose law depends on tau contributes its score times the part of the particle's flux
-   score that follows it -- a free flight (Eq. time_to_scat) that ends in a relaxation scores
-   T/tau - 1, one cut short (absorbed, segment cap) T/tau, both for the flying mode's bin; a
-   relaxation draw of row j (Eq. norm_post_coll) scores -[bin(j) = i] + P_i, P_i the bin's share of
-   the post-scattering distribution.  mcbte_adjoint replays particles first_pid .. first_pid + n - 1
-   with the same random streams (run->seed, run->instance, run->precision as the forward trace that
-   filled particle_F, a device array of n doubles) and adds the sums to `adj` (device, adj_doubles
-   doubles, zeroed by the caller; successive calls accumulate; the last word is library scratch).
-   Async on `stream`.  Errors: MCBTE_EINVAL (transient run, event log set), MCBTE_ENODEV, MCBTE_EHIP. */
-int mcbte_adjoint(const mcbte_tables* tables, const mcbte_run* run, int64_t first_pid, int64_t n,
+   dkappa / dln tau_i (steady runs with a gradient), by one of two estimators.
+   MCBTE_SENS_SCORE (likelihood ratio): every random quantity whose law depends on tau contributes
+   its score times the part of the particle's flux score that follows it -- a free flight (Eq.
+   time_to_scat) that ends in a relaxation scores T/tau - 1, one cut short (absorbed, segment cap)
+   T/tau, both for the flying mode's bin; a relaxation draw of row j (Eq. norm_post_coll) scores
+   -[bin(j) = i] + P_i, P_i the bin's share of the post-scattering distribution.
+   MCBTE_SENS_PATHWISE: a flight's distance L = v tau E is stretched by dL / dln tau = L with its
+   random numbers E fixed, the change carried along the rest of the trajectory with the event
+   sequence held fixed (boundary hits slide along the surface, reflections off the cylinder turn
+   with its normal) into the change of the particle's net displacement along the scored axis; the
+   relaxation draws keep their likelihood-ratio terms.  Lower variance; unbiased where a
+   stretched flight cannot change the event sequence on average -- adiabatic walls and periodic
+   faces -- but not at isothermal walls (a flight ending just before or just after one changes
+   what follows).  Requires 1 <= n_scat_max <= MCBTE_PATHWISE_MAX_FLIGHTS.  Its variance grows with
+   the mean free path against the geometry: a stretch moves a flight's end by L Omega, and between
+   convex pores (a dispersing billiard) the shifts grow geometrically with the number of
+   reflections, so for mean free paths beyond the pore size the terms can overflow; a particle
+   term that is not finite is left out of the sums and counted, and mcbte_adjoint_finalize then
+   reports MCBTE_ERANGE.
+   mcbte_adjoint replays particles first_pid .. first_pid + n - 1 with the same random streams
+   (run->seed, run->instance, run->precision as the forward trace that filled particle_F, a
+   device array of n doubles) and adds the sums to `adj` (device, adj_doubles doubles, zeroed by
+   the caller; successive calls with one estimator accumulate): adj[0, n_bins) the per-bin sums,
+   adj[n_bins] the relaxation-draw sum B, adj[n_bins + 1] the count of terms left out as not
+   finite, adj[n_bins + 2] library scratch.  Async on `stream`.  Errors: MCBTE_EINVAL (transient run, event log set, unknown
+   estimator, n_scat_max outside the pathwise range), MCBTE_ENODEV, MCBTE_EHIP. */
+int mcbte_adjoint(const mcbte_tables* tables, const mcbte_run* run, int32_t estimator, int64_t first_pid, int64_t n,
                   const double* particle_F, double* adj, void* stream);
 
 /* Copy `adj` to the host (synchronizes `stream`) and write dkappa / dln tau_i, i < n_bins, into
    host_out (n_out >= n_bins) for n_particles traced particles, with the normalisation of kappa
-   (-E_tot / (V_solid gradT_score n_particles)).  dkappa / dtau_i = host_out[i] / tau_i. */
+   (-E_tot / (V_solid gradT_score n_particles)).  dkappa / dtau_i = host_out[i] / tau_i.  Returns
+   MCBTE_ERANGE (host_out still written) when terms were left out as not finite. */
 int mcbte_adjoint_finalize(const mcbte_tables* tables, const double* adj, int64_t n_particles, double* host_out,
                            int64_t n_out, void* stream);
 

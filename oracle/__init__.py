@@ -107,7 +107,7 @@ def lib():
         L.orc_tally_segment.argtypes = [p, p, p, C.c_double, C.c_int32, C.c_double, p]
         L.orc_emit_state.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, p, p]
         L.orc_emit_state.restype = C.c_int
-        L.orc_adjoint.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, C.c_int32, p, p, p, p]
+        L.orc_adjoint.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, C.c_int32, p, p, p, p, p]
         L.orc_adjoint.restype = C.c_int
         L.orc_next_boundary.argtypes = [p, p, p, p]
         L.orc_next_boundary.restype = C.c_double
@@ -398,18 +398,19 @@ def adjoint(w: dict, n: int | None = None, first_pid: int = 0, threads: int = 1,
         de = np.zeros(1)
         F = np.zeros(hi - lo)
         pp = np.zeros((hi - lo, tb.n_bins)) if per_particle else None
+        bad = np.zeros(1, dtype=np.int64)
         rc = lib().orc_adjoint(tb.h, int(w["seed"]), inst, lo, hi - lo, kind, _ptr(sp), _ptr(de), _ptr(F),
-                               _ptr(pp) if pp is not None else None)
+                               _ptr(pp) if pp is not None else None, _ptr(bad))
         if rc != 0:
             raise ValueError(f"oracle adjoint failed with status {rc}")
-        return sp, float(de[0]), F, pp
+        return sp, float(de[0]), F, pp, int(bad[0])
 
     with ThreadPoolExecutor(max(1, min(threads, nb))) as ex:
         parts = list(ex.map(one, range(nb)))
     g = w["geometry"]["gradT"][w["problem"]["score_axis"]]
     P = tb.get("P_bin")
     per_batch = []
-    for (sp, de, F, _), lo, hi in zip(parts, bounds[:-1], bounds[1:]):
+    for (sp, de, F, _, _), lo, hi in zip(parts, bounds[:-1], bounds[1:]):
         scale = -tb.E_tot / (tb.V_solid * g * (hi - lo))
         per_batch.append(scale * (sp + P * de))
     sp = sum(p[0] for p in parts)
@@ -417,7 +418,7 @@ def adjoint(w: dict, n: int | None = None, first_pid: int = 0, threads: int = 1,
     F = np.concatenate([p[2] for p in parts])
     scale = -tb.E_tot / (tb.V_solid * g * n)
     out = {"dkappa_dlntau": scale * (sp + P * de), "sparse": sp, "dense": de, "F": F, "P_bin": P,
-           "kappa": scale * F.sum(), "tables": tb, "scale": scale}
+           "kappa": scale * F.sum(), "tables": tb, "scale": scale, "n_nonfinite": sum(p[4] for p in parts)}
     if per_particle:
         out["per_particle"] = np.concatenate([p[3] for p in parts])
     if nb > 1:

@@ -720,6 +720,8 @@ typedef struct {
     int pathwise;               /* 1: tangents for the flights, scores only for the draws */
     tangent* tg; int64_t nt, tcap;
     int32_t sign;               /* the particle's sign s */
+    double dline;               /* straight distance since the last tangent update (periodic
+                                   transfers do not interrupt the line) */
 } adj_list;
 
 static void adj_push(adj_list* al, int32_t bin, double g, double F_before, int dense)
@@ -934,8 +936,13 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
             p.x[face_axis] = face_side ? g->L[face_axis] : 0.0;      /* exactly on the wall */
         }
         if (al && al->pathwise) {                  /* the segment's end, for the tangents */
+            const double dl = al->dline + d;       /* straight line since the last tangent update */
+            al->dline = 0.0;
             if (ev == EV_RELAX) {
-                tan_relax(al, p.o, d);
+                tan_relax(al, p.o, dl);
+            } else if (hit <= 6 && g->face[hit - 1].type == B_PERI) {
+                /* a periodic transfer is a translation: the line goes on unchanged */
+                al->dline = dl;
             } else {
                 double nh[3] = {0.0, 0.0, 0.0};
                 if (hit <= 6) {
@@ -947,7 +954,7 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
                             nh[1] = (p.x[1] - g->cyl[c].cy) / g->cyl[c].r;
                         }
                 }
-                tan_hit(al, p.o, d, nh);
+                tan_hit(al, p.o, dl, nh);
             }
         }
         int escaped = 0;
@@ -1081,7 +1088,7 @@ int orc_trace(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t fir
 }
 
 int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t first_pid, int64_t n,
-                int32_t kind, double* sparse, double* dense, double* F_out, double* pp_out)
+                int32_t kind, double* sparse, double* dense, double* F_out, double* pp_out, int64_t* n_bad)
 {
     if (!t || n < 0 || first_pid < 0 || t->pr.transient || (kind != 0 && kind != 1)) return E_INVAL;
     int cap = 2;
@@ -1098,6 +1105,7 @@ int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t f
     for (int64_t i = 0; i < n; ++i) {
         al.n = 0;
         al.nt = 0;
+        al.dline = 0.0;
         double F = 0.0;
         trace_one(t, seed, instance, first_pid + i, raw, counts, mom, NULL, 0, pts, &al, &F);
         if (al.failed) break;
@@ -1108,6 +1116,10 @@ int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t f
         }
         for (int64_t e = 0; e < al.nt; ++e) {
             const double c = (double)al.sign * al.tg[e].dx[sa];
+            if (!isfinite(c)) {             /* left out and counted */
+                if (n_bad) *n_bad += 1;
+                continue;
+            }
             sparse[al.tg[e].bin] += c;
             if (pp_out) pp_out[i * t->n_bins + al.tg[e].bin] += c;
         }

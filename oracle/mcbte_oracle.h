@@ -75,9 +75,10 @@ int orc_trace(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t fir
    relaxation draws; kind 1, pathwise: sparse[n_bins] += the tangent terms s dx_a of the flights plus
    the draw terms.  Both: *dense += sum over relaxation draws of (F - F_before).  F_out[i]
    (optional) = flux contribution of each particle; pp_out[i * n_bins + bin] (optional, kind 1)
-   += the tangent terms of particle i. */
+   += the tangent terms of particle i.  A tangent term that is not finite is left out of the sums
+   and counted in *n_bad (optional). */
 int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t first_pid, int64_t n,
-                int32_t kind, double* sparse, double* dense, double* F_out, double* pp_out);
+                int32_t kind, double* sparse, double* dense, double* F_out, double* pp_out, int64_t* n_bad);
 
 /* building blocks exposed for the pins */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

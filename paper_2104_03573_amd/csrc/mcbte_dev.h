@@ -8,6 +8,7 @@
 #define MCBTE_LDS_TALLY_BYTES (40 * 1024)   // per-workgroup tally privatisation budget
 #define MCBTE_TALLY_HEADER_BYTES 256
 #define MCBTE_TALLY_COUNTER_OFFSET 192
+#define MCBTE_PATH_MAX 16                    // flights per particle the pathwise replay holds
 
 namespace mcbte {
 

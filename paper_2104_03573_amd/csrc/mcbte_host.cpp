@@ -112,6 +112,7 @@ const char* mcbte_strerror(int status)
     case MCBTE_ETABLE: return "a distribution or the source list has zero total weight";
     case MCBTE_EGEOM: return "invalid geometry";
     case MCBTE_ESIZE: return "caller buffer too small";
+    case MCBTE_ERANGE: return "a sensitivity term was not finite (pathwise tangents grew without bound)";
     default: return "unknown status";
     }
 }
@@ -317,7 +318,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     inf.n_cols = n_cols;
     inf.tally_bytes = MCBTE_TALLY_HEADER_BYTES + n_cells * n_cols * 4 * (int64_t)sizeof(double);
     inf.n_bins = n_bins;
-    inf.adj_doubles = (int64_t)n_bins + 2;
+    inf.adj_doubles = (int64_t)n_bins + 3;
     inf.device = device;
 
     // device view
@@ -555,7 +556,7 @@ int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run,
     }
     if (lds_tab > MCBTE_LDS_TABLE_BYTES || lds_tab > t0->max_lds) return MCBTE_EINVAL;
     lp.lds_tab = lds_tab;
-    if (mode == 2) {   // sensitivity replay: the per-bin sums take the place of the tallies
+    if (mode >= 2) {   // sensitivity replay: the per-bin sums take the place of the tallies
         const int64_t bins = 8 * t0->info.n_bins;
         if (lds_tab + bins > t0->max_lds) return MCBTE_EINVAL;
         lp.tally_lds = 0;
@@ -691,19 +692,26 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
 }
 
-int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, int64_t n, const double* particle_F,
-                  double* adj, void* stream)
+static_assert(MCBTE_PATH_MAX == MCBTE_PATHWISE_MAX_FLIGHTS, "pathwise capacity");
+
+int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator, int64_t first_pid, int64_t n,
+                  const double* particle_F, double* adj, void* stream)
 {
     if (!t || !run || !particle_F || !adj || n < 0 || first_pid < 0) return MCBTE_EINVAL;
     if (run->precision != 32 && run->precision != 64) return MCBTE_EINVAL;
     if (run->event_log) return MCBTE_EINVAL;
+    if (estimator != MCBTE_SENS_SCORE && estimator != MCBTE_SENS_PATHWISE) return MCBTE_EINVAL;
     if (t->device < 0 || !t->d_tab) return MCBTE_ENODEV;
     if (t->prob.transient) return MCBTE_EINVAL;
+    if (estimator == MCBTE_SENS_PATHWISE &&
+        (t->prob.n_scat_max < 1 || t->prob.n_scat_max > MCBTE_PATHWISE_MAX_FLIGHTS))
+        return MCBTE_EINVAL;
     if (n == 0) return MCBTE_OK;
     DeviceGuard g(t->device);
     if (!g.ok) return MCBTE_EHIP;
+    const int mode = estimator == MCBTE_SENS_PATHWISE ? 3 : 2;
     LaunchPlan lp;
-    const int rc = plan_launch(&t, 1, run, 2, lp);
+    const int rc = plan_launch(&t, 1, run, mode, lp);
     if (rc != MCBTE_OK) return rc;
     LaunchArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -721,8 +729,8 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid
     a.adj = adj;
     hipStream_t s = (hipStream_t)stream;
     // the work counter is the last word of the caller's buffer
-    if (launch_zero_u64((unsigned long long*)(adj + t->info.n_bins + 1), s) != hipSuccess) return MCBTE_EHIP;
-    const hipError_t e = launch_trace(a, 2, run->precision, t->host_view.tally_kind, lp.block, lp.grid, lp.lds, s);
+    if (launch_zero_u64((unsigned long long*)(adj + t->info.n_bins + 2), s) != hipSuccess) return MCBTE_EHIP;
+    const hipError_t e = launch_trace(a, mode, run->precision, t->host_view.tally_kind, lp.block, lp.grid, lp.lds, s);
     return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
 }
 
@@ -737,16 +745,16 @@ int mcbte_adjoint_finalize(const mcbte_tables* t, const double* adj, int64_t n_p
     if (gs == 0.0 || t->prob.transient) return MCBTE_EINVAL;
     DeviceGuard g(t->device);
     if (!g.ok) return MCBTE_EHIP;
-    std::vector<double> h((size_t)(nb + 1));
+    std::vector<double> h((size_t)(nb + 2));
     hipStream_t s = (hipStream_t)stream;
-    if (hipMemcpyAsync(h.data(), adj, sizeof(double) * (size_t)(nb + 1), hipMemcpyDeviceToHost, s) != hipSuccess)
+    if (hipMemcpyAsync(h.data(), adj, sizeof(double) * (size_t)(nb + 2), hipMemcpyDeviceToHost, s) != hipSuccess)
         return MCBTE_EHIP;
     if (hipStreamSynchronize(s) != hipSuccess) return MCBTE_EHIP;
     // same normalisation as kappa: -E_tot / (V_solid gradT_s N) times the summed scores
     const double scale = -t->info.E_tot / (t->info.V_solid * gs * (double)n_particles);
     const double B = h[(size_t)nb];
     for (int64_t i = 0; i < nb; ++i) out[i] = scale * (h[(size_t)i] + t->P_bin[(size_t)i] * B);
-    return MCBTE_OK;
+    return h[(size_t)nb + 1] != 0.0 ? MCBTE_ERANGE : MCBTE_OK;
 }
 
 int mcbte_tally(const mcbte_tables* t, const void* tally, double* host_out, int64_t n_out, mcbte_result* res,

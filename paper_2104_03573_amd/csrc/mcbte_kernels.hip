@@ -483,6 +483,7 @@ struct AdjCtx {
     double* bins;            // LDS, n_bins sums
     double F_total;          // this particle's F from the forward trace
     double dense;            // per-lane sum of (F_total - F) over relaxation draws
+    uint32_t bad;            // pathwise terms that were not finite
     __device__ __forceinline__ void add(int bin, double g, double after) { atomicAdd(bins + bin, g * after); }
 };
 
@@ -493,16 +494,163 @@ struct Tabs {
     const R* tau;              // LDS
 };
 
+// Pathwise sensitivity state of one particle (replay form).  A free flight of mode m covers
+// the distance L = v_m tau_m E with E fixed by its random numbers, so dL / dln tau_m = L.  With the
+// sequence of events held fixed, stretching a flight shifts what follows it, linearly.  At the
+// start of a flight every earlier stretch has become a pure position shift (the relaxation that
+// began the flight drew a direction that does not depend on where it happened), so the flight
+// is described by its response g: how its position, direction and remaining distance (gx, go, gb)
+// follow a position shift at the flight's start.  g is updated at each boundary hit and
+// reflection (three columns, whatever the number of stored shifts); at the relaxation that ends
+// the flight it becomes the 3x3 map J = gx + o gb^T + d go, applied to every stored shift, and
+// the flight's own stretch joins them as L o.  The flux score F = s (x_end - x_start)_a changes by
+// s (gx tx)_a for each stored shift tx.
+template <typename R>
+struct PathCtx {
+    R gx[3][3], go[3][3], gb[3];      // [component][column]
+    R tx[MCBTE_PATH_MAX][3];          // stored shifts, one per finished flight
+    int tbin[MCBTE_PATH_MAX];         // frequency bin of each
+    int nt;
+    R dline;                          // straight distance since the last update (a periodic
+                                      // transfer is a translation: the line goes on unchanged)
+
+    __device__ __forceinline__ void begin_flight()
+    {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                gx[i][c] = i == c ? R(1) : R(0);
+                go[i][c] = R(0);
+            }
+            gb[i] = R(0);
+        }
+        dline = R(0);
+    }
+    // the segment x -> x + d o ended on a surface with unit normal n: the hit point stays on the
+    // surface, n . (dx + dd o + d dO) = 0, and the flight has dd less distance left
+    __device__ __forceinline__ void hit(const R o[3], R d, const R n[3])
+    {
+        const R on = o[0] * n[0] + o[1] * n[1] + o[2] * n[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R nx = n[0] * gx[0][c] + n[1] * gx[1][c] + n[2] * gx[2][c];
+            const R no = n[0] * go[0][c] + n[1] * go[1][c] + n[2] * go[2][c];
+            const R dd = -r_div(nx + d * no, on);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) gx[i][c] = gx[i][c] + dd * o[i] + d * go[i][c];
+            gb[c] = gb[c] - dd;
+        }
+    }
+    // the segment x -> x + d o ended in a relaxation: fold the flight into the stored shifts and
+    // store the flight's own stretch L o (its bin `bin`)
+    __device__ __forceinline__ void end_flight(const R o[3], R d, R L, int bin)
+    {
+        R J[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) J[i][c] = gx[i][c] + o[i] * gb[c] + d * go[i][c];
+#pragma unroll
+        for (int q = 0; q < MCBTE_PATH_MAX; ++q) {
+            if (q < nt) {
+                const R a0 = tx[q][0], a1 = tx[q][1], a2 = tx[q][2];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) tx[q][i] = J[i][0] * a0 + J[i][1] * a1 + J[i][2] * a2;
+            } else if (q == nt) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) tx[q][i] = L * o[i];
+                tbin[q] = bin;
+            }
+        }
+        if (nt < MCBTE_PATH_MAX) ++nt;
+        begin_flight();
+    }
+    // reflection off a plane normal to axis fa: specular negates that direction component,
+    // diffuse draws a direction that does not depend on the hit point
+    __device__ __forceinline__ void plane(int fa, bool specular)
+    {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) go[i][c] = specular ? (i == fa ? -go[i][c] : go[i][c]) : R(0);
+    }
+    // specular reflection off a cylinder of radius r (o before the reflection): the normal turns
+    // with the hit point, dn = (dx_h)_xy / r, and o' = o - 2 (o.n) n
+    __device__ __forceinline__ void cyl_specular(const R o[3], const R n[3], R r)
+    {
+        const R on = o[0] * n[0] + o[1] * n[1] + o[2] * n[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R dn0 = r_div(gx[0][c], r), dn1 = r_div(gx[1][c], r);
+            const R don = (go[0][c] * n[0] + go[1][c] * n[1] + go[2][c] * n[2]) + (o[0] * dn0 + o[1] * dn1);
+            go[0][c] = go[0][c] - R(2) * don * n[0] - R(2) * on * dn0;
+            go[1][c] = go[1][c] - R(2) * don * n[1] - R(2) * on * dn1;
+            go[2][c] = go[2][c] - R(2) * don * n[2];
+        }
+    }
+    // diffuse reflection off a cylinder (o after the reflection): o = mu n + a t1 + b t2 with the
+    // drawn (mu, a, b) and the frame of dir_about, t1 = e_j x n / |e_j x n|, t2 = n x t1
+    __device__ __forceinline__ void cyl_diffuse(const R o[3], const R n[3], R r)
+    {
+        int j = 0;
+        R m0 = fabs(n[0]);
+        if (fabs(n[1]) < m0) { j = 1; m0 = fabs(n[1]); }
+        if (fabs(n[2]) < m0) j = 2;
+        const R e0 = j == 0 ? R(1) : R(0), e1 = j == 1 ? R(1) : R(0), e2 = j == 2 ? R(1) : R(0);
+        const R c0 = e1 * n[2] - e2 * n[1], c1 = e2 * n[0] - e0 * n[2], c2 = e0 * n[1] - e1 * n[0];
+        const R len = r_sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+        const R t1[3] = {r_div(c0, len), r_div(c1, len), r_div(c2, len)};
+        const R t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+        const R mu = o[0] * n[0] + o[1] * n[1] + o[2] * n[2];
+        const R ca = o[0] * t1[0] + o[1] * t1[1] + o[2] * t1[2];
+        const R cb = o[0] * t2[0] + o[1] * t2[1] + o[2] * t2[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R dn[3] = {r_div(gx[0][c], r), r_div(gx[1][c], r), R(0)};
+            const R dc[3] = {e1 * dn[2] - e2 * dn[1], e2 * dn[0] - e0 * dn[2], e0 * dn[1] - e1 * dn[0]};
+            const R p1 = t1[0] * dc[0] + t1[1] * dc[1] + t1[2] * dc[2];
+            R dt1[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) dt1[i] = r_div(dc[i] - p1 * t1[i], len);
+            const R dt2[3] = {(dn[1] * t1[2] - dn[2] * t1[1]) + (n[1] * dt1[2] - n[2] * dt1[1]),
+                              (dn[2] * t1[0] - dn[0] * t1[2]) + (n[2] * dt1[0] - n[0] * dt1[2]),
+                              (dn[0] * t1[1] - dn[1] * t1[0]) + (n[0] * dt1[1] - n[1] * dt1[0])};
+#pragma unroll
+            for (int i = 0; i < 3; ++i) go[i][c] = mu * dn[i] + ca * dt1[i] + cb * dt2[i];
+        }
+    }
+    // the particle has ended: add s (gx tx)_a of every stored shift to its bin; a term that is not
+    // finite (tangents grown without bound) is counted in `bad` instead
+    __device__ __forceinline__ void flush(double* bins, int s, int a, uint32_t& bad)
+    {
+        const R r0 = a == 0 ? gx[0][0] : (a == 1 ? gx[1][0] : gx[2][0]);
+        const R r1 = a == 0 ? gx[0][1] : (a == 1 ? gx[1][1] : gx[2][1]);
+        const R r2 = a == 0 ? gx[0][2] : (a == 1 ? gx[1][2] : gx[2][2]);
+#pragma unroll
+        for (int q = 0; q < MCBTE_PATH_MAX; ++q) {
+            if (q < nt) {
+                const double c = (double)((R)s * (r0 * tx[q][0] + r1 * tx[q][1] + r2 * tx[q][2]));
+                if (isfinite(c)) atomicAdd(bins + tbin[q], c);
+                else ++bad;
+            }
+        }
+    }
+};
+
 // Advance particle p by one segment; returns true when the particle has ended.
-template <typename R, int TK, bool ADJ>
+// AK: 0 trace, 1 likelihood-ratio replay, 2 pathwise replay.
+template <typename R, int TK, int AK>
 __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const TallyCtx& tc, const Stream& st,
-                                       Part<R>& p, LaneCounts& cnt, LogRow& lg, bool& coop, AdjCtx& adj)
+                                       Part<R>& p, LaneCounts& cnt, LogRow& lg, bool& coop, AdjCtx& adj,
+                                       PathCtx<R>& pc)
 {
     const DevGeom& g = T.g;
     if ((int64_t)p.k >= T.max_events) {
         ++cnt.c[9];
         lg.put(EV_CAP, 0, p.m);
-        if (ADJ) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+        if (AK == 1) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+        if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
         return true;
     }
     const R vm = tb.v[p.m];
@@ -573,7 +721,8 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
     if (ev == 2) {
         ++cnt.c[7];
         lg.put(EV_TIMEOUT, 0, p.m);
-        if (ADJ) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+        if (AK == 1) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+        if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
         return true;
     }
     const bool on_face = (ev == 1) && hit <= 6;
@@ -586,10 +735,34 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
         if (a == fa) p.x[a] = fs ? L : R(0);     // exactly on the wall
         if (!g.unb[a] && (p.x[a] < R(-1e-9) * L || p.x[a] > L + R(1e-9) * L)) escaped = true;
     }
+    if (AK == 2) {   // the segment's end, for the pathwise state
+        const R dl = pc.dline + d;
+        pc.dline = R(0);
+        if (ev == 0) {
+            pc.end_flight(p.o, dl, vm * p.dtr0, T.bin_of[p.m]);
+        } else if (ev == 1 && hit <= 6 && g.face_type[hit - 1] == 3) {
+            pc.dline = dl;
+        } else if (ev == 1) {
+            R nh[3] = {R(0), R(0), R(0)};
+            if (hit <= 6) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) nh[a] = a == fa ? R(1) : R(0);
+            } else {
+                for (int c = 0; c < g.n_pores; ++c)
+                    if (g.pore_id[c] == hit) {
+                        const R rr = Geo<R>::r(g, c);
+                        nh[0] = r_div(p.x[0] - Geo<R>::cx(g, c), rr);
+                        nh[1] = r_div(p.x[1] - Geo<R>::cy(g, c), rr);
+                    }
+            }
+            pc.hit(p.o, dl, nh);
+        }
+    }
     if (escaped) {
         ++cnt.c[10];
         lg.put(EV_ESCAPE, 0, p.m);
-        if (ADJ) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+        if (AK == 1) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+        if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
         return true;
     }
     // what the event needs
@@ -597,10 +770,11 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
     if (relax) {
         p.nrel += 1;
         ++cnt.c[2];
-        if (ADJ) adj.add(T.bin_of[p.m], (double)p.dtr0 / T.tau64[p.m] - 1.0, adj.F_total - p.F0);
+        if (AK == 1) adj.add(T.bin_of[p.m], (double)p.dtr0 / T.tau64[p.m] - 1.0, adj.F_total - p.F0);
         if (T.n_scat_max > 0 && p.nrel >= T.n_scat_max) {
             ++cnt.c[8];
             lg.put(EV_NSCAT, 0, p.m);
+            if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
             return true;
         }
     }
@@ -623,7 +797,8 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
         if (btype == 1) {
             ++cnt.c[6];
             lg.put(EV_ABSORB, hit, p.m);
-            if (ADJ) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+            if (AK == 1) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+            if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
             return true;
         }
         if (btype == 3) {   // linearised periodic condition: reinsert unchanged at the partner face
@@ -639,6 +814,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
     // is handed to the whole wave (coop_bounces), which runs the coming bounces 64 at a time
     if (std::is_same<R, float>::value && ev == 1 && T.coop_axis >= 0 && fa == T.coop_axis && !lg.row &&
         vm * p.dtr > (R)T.coop_min_path) {
+        if (AK == 2) pc.plane(fa, false);    // the chain starts with a diffuse reflection
         coop = true;
         return false;
     }
@@ -662,7 +838,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
             dir_iso(u1, u2, p.o);
             p.dtr = -tb.tau[p.m] * r_log(R(1) - unif<R>(w0.z, w0.w));
             lg.put(EV_RELAX, 0, p.m);
-            if (ADJ) {
+            if (AK != 0) {
                 adj.add(T.bin_of[p.m], -1.0, adj.F_total - p.cq);
                 adj.dense += adj.F_total - p.cq;
             }
@@ -680,6 +856,10 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
                 for (int a = 0; a < 3; ++a) n[a] = (a == fa) ? (fs ? R(-1) : R(1)) : R(0);
             }
             dir_cos(u1, u2, n, p.o);
+            if (AK == 2) {
+                if (pore >= 0) pc.cyl_diffuse(p.o, n, Geo<R>::r(g, pore));
+                else pc.plane(fa, false);
+            }
             ++cnt.c[4];
             lg.put(EV_DIFFUSE, hit, p.m);
         }
@@ -688,11 +868,16 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
             const R rr = Geo<R>::r(g, pore);
             const R n0 = r_div(p.x[0] - Geo<R>::cx(g, pore), rr);
             const R n1 = r_div(p.x[1] - Geo<R>::cy(g, pore), rr);
+            if (AK == 2) {
+                const R nn[3] = {n0, n1, R(0)};
+                pc.cyl_specular(p.o, nn, rr);
+            }
             const R k2 = R(2) * (p.o[0] * n0 + p.o[1] * n1 + p.o[2] * R(0));
             p.o[0] = p.o[0] - k2 * n0;
             p.o[1] = p.o[1] - k2 * n1;
             p.o[2] = p.o[2] - k2 * R(0);
         } else {
+            if (AK == 2) pc.plane(fa, true);
 #pragma unroll
             for (int a = 0; a < 3; ++a)
                 if (a == fa) p.o[a] = -p.o[a];
@@ -974,16 +1159,17 @@ __device__ __forceinline__ void end_particle(const Part<R>& p, int transient, do
     if (lg.row) lg.row[0] = (uint32_t)lg.n;
 }
 
-// ADJ = false: the forward trace (tallies, counters, moments, optional per-particle flux score F).
-// ADJ = true: the sensitivity replay of the same particles: no tallies; the likelihood-ratio sums
-// go to LDS bins and then to a.adj; the work counter lives after the sums.
-template <typename R, int TK, bool ADJ>
+// AK = 0: the forward trace (tallies, counters, moments, optional per-particle flux score F).
+// AK = 1 (likelihood ratio) or 2 (pathwise): the sensitivity replay of the same particles: no
+// tallies; the per-bin sums go to LDS and then to a.adj; the work counter lives after the sums.
+template <typename R, int TK, int AK>
 __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const DevTab& T = tabs[0];
     const Tabs<R> tb = stage_tables<R>(T, smem);
     double* s_tally = (double*)(smem + a.lds_tab_bytes);
+    constexpr bool ADJ = AK != 0;
     if (ADJ) {
         for (int i = threadIdx.x; i < T.n_bins; i += blockDim.x) s_tally[i] = 0.0;
     } else if (a.tally_lds) {
@@ -993,7 +1179,7 @@ __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ t
     __syncthreads();
     const TallyCtx tc = ADJ ? TallyCtx{nullptr, nullptr}
                             : TallyCtx{a.tally_lds ? s_tally : nullptr, (double*)(a.tally + MCBTE_TALLY_HEADER_BYTES)};
-    unsigned long long* counter = ADJ ? (unsigned long long*)(a.adj + T.n_bins + 1)
+    unsigned long long* counter = ADJ ? (unsigned long long*)(a.adj + T.n_bins + 2)
                                       : (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET);
     const int lane = threadIdx.x & 63;
     const unsigned long long n = (unsigned long long)a.n;
@@ -1005,7 +1191,9 @@ __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ t
     for (int q = 0; q < 12; ++q) cnt.c[q] = 0;
     double mom[4] = {0.0, 0.0, 0.0, 0.0};
     LogRow lg{nullptr, 0, a.log_stride};
-    AdjCtx adj{s_tally, 0.0, 0.0};
+    AdjCtx adj{s_tally, 0.0, 0.0, 0u};
+    PathCtx<R> pc;
+    pc.nt = 0;
     int64_t my_pid = 0;
     bool alive = false;
     bool exhausted = false;        // wave-uniform: the particle counter has run past n
@@ -1028,6 +1216,10 @@ __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ t
                         my_pid = a.first_pid + (int64_t)idx;
                         start_particle<R, TK>(T, a, my_pid, a.inst0, p, st, cnt, lg);
                         if (ADJ) adj.F_total = a.particle_F[idx];
+                        if (AK == 2) {
+                            pc.nt = 0;
+                            pc.begin_flight();
+                        }
                         alive = true;
                     }
                 }
@@ -1041,7 +1233,7 @@ __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ t
         ++since_refill;
         bool coop = false;
         if (alive) {
-            if (flight<R, TK, ADJ>(T, tb, tc, st, p, cnt, lg, coop, adj)) {
+            if (flight<R, TK, AK>(T, tb, tc, st, p, cnt, lg, coop, adj, pc)) {
                 end_particle(p, T.transient, mom, lg);
                 if (!ADJ && a.particle_F) a.particle_F[my_pid - a.first_pid] = p.cq;
                 alive = false;
@@ -1055,6 +1247,8 @@ __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ t
     if (ADJ) {
         const double d = wave_sum<double>(adj.dense);
         if (lane == 0 && d != 0.0) atomicAdd(a.adj + T.n_bins, d);
+        const double nb = wave_sum<double>((double)adj.bad);
+        if (lane == 0 && nb != 0.0) atomicAdd(a.adj + T.n_bins + 1, nb);
         __syncthreads();
         for (int i = threadIdx.x; i < T.n_bins; i += blockDim.x)
             if (s_tally[i] != 0.0) atomicAdd(a.adj + i, s_tally[i]);
@@ -1132,7 +1326,9 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
         Part<R> p;
         Stream st{0u, 0u, 0u, 0u, 0u};
         LogRow lg{nullptr, 0, 2};
-        AdjCtx adj{nullptr, 0.0, 0.0};
+        AdjCtx adj{nullptr, 0.0, 0.0, 0u};
+        PathCtx<R> pc;            // unused by the trace
+        pc.nt = 0;
         bool alive = false;
         bool exhausted = false;
         int since_refill = 0;
@@ -1171,7 +1367,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
             ++since_refill;
             bool coop = false;
             if (alive) {
-                if (flight<R, TK, false>(T, tb, tc, st, p, cnt, lg, coop, adj)) {
+                if (flight<R, TK, 0>(T, tb, tc, st, p, cnt, lg, coop, adj, pc)) {
                     end_particle(p, T.transient, mom, lg);
                     alive = false;
                 }
@@ -1223,17 +1419,17 @@ static void ensure_lds_limit(const void* fn, size_t lds)
 template <typename R, int TK>
 static hipError_t trace_t(const LaunchArgs& a, int mode, int block, int grid, size_t lds, hipStream_t s)
 {
-    // mode 0: solo trace, 1: batched trace, 2: sensitivity replay
+    // mode 0: solo trace, 1: batched trace, 2: likelihood-ratio replay, 3: pathwise replay
     if (mode == 1) {
         auto fn = k_trace_batch<R, TK>;
         ensure_lds_limit((const void*)fn, lds);
         hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a.tabs, a);
-    } else if (mode == 2) {
-        auto fn = k_trace_solo<R, TK, true>;
+    } else if (mode == 2 || mode == 3) {
+        auto fn = mode == 2 ? k_trace_solo<R, TK, 1> : k_trace_solo<R, TK, 2>;
         ensure_lds_limit((const void*)fn, lds);
         hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a.tabs, a);
     } else {
-        auto fn = k_trace_solo<R, TK, false>;
+        auto fn = k_trace_solo<R, TK, 0>;
         ensure_lds_limit((const void*)fn, lds);
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s,
                            (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET));
@@ -1272,7 +1468,8 @@ int trace_occupancy(int mode, int precision, int tally_kind, int block, size_t l
     const void* fn = nullptr;
 #define MCBTE_PICK(RR, TKK)                                                                    \
     fn = mode == 1 ? (const void*)k_trace_batch<RR, TKK>                                        \
-                   : (mode == 2 ? (const void*)k_trace_solo<RR, TKK, true> : (const void*)k_trace_solo<RR, TKK, false>)
+       : mode == 2 ? (const void*)k_trace_solo<RR, TKK, 1>                                      \
+       : mode == 3 ? (const void*)k_trace_solo<RR, TKK, 2> : (const void*)k_trace_solo<RR, TKK, 0>
     if (precision == 64) {
         if (tally_kind == TALLY_STEADY_ONE) MCBTE_PICK(double, TALLY_STEADY_ONE);
         else if (tally_kind == TALLY_STEADY_GRID) MCBTE_PICK(double, TALLY_STEADY_GRID);

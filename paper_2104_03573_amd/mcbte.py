@@ -15,7 +15,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmcbte.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENODEV, ETABLE, EGEOM, ESIZE = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, EHIP, ENODEV, ETABLE, EGEOM, ESIZE, ERANGE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 N_COUNTS = 16
 COUNT_NAMES = ["particles", "flights", "relaxations", "specular", "diffuse", "periodic", "absorbed",
                "timeouts", "nscat_end", "cap_end", "escaped", "rejections"]
@@ -112,7 +112,7 @@ def lib():
         L.mcbte_trace_batch.argtypes = [C.POINTER(p), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
                                         C.POINTER(p), C.POINTER(Run), p, p]
         L.mcbte_trace_batch.restype = C.c_int
-        L.mcbte_adjoint.argtypes = [p, C.POINTER(Run), C.c_int64, C.c_int64, p, p, p]
+        L.mcbte_adjoint.argtypes = [p, C.POINTER(Run), C.c_int32, C.c_int64, C.c_int64, p, p, p]
         L.mcbte_adjoint.restype = C.c_int
         L.mcbte_adjoint_finalize.argtypes = [p, p, C.c_int64, C.POINTER(C.c_double), C.c_int64, p]
         L.mcbte_adjoint_finalize.restype = C.c_int
@@ -257,9 +257,15 @@ def trace_batch(tables: list, n_particles, instance_ids, tallies: list, run: Run
                                                         C.c_void_p(queue.data_ptr()), _stream(stream)))
 
 
-def adjoint(t: "Tables", run: Run, first_pid: int, n: int, particle_F, adj, stream=None):
-    _check("mcbte_adjoint", lib().mcbte_adjoint(t.h, C.byref(run), first_pid, n, C.c_void_p(particle_F.data_ptr()),
-                                                C.c_void_p(adj.data_ptr()), _stream(stream)))
+SENS_SCORE = 0
+SENS_PATHWISE = 1
+ESTIMATORS = {"score": SENS_SCORE, "pathwise": SENS_PATHWISE}
+
+
+def adjoint(t: "Tables", run: Run, estimator: int, first_pid: int, n: int, particle_F, adj, stream=None):
+    _check("mcbte_adjoint", lib().mcbte_adjoint(t.h, C.byref(run), estimator, first_pid, n,
+                                                C.c_void_p(particle_F.data_ptr()), C.c_void_p(adj.data_ptr()),
+                                                _stream(stream)))
 
 
 def adjoint_finalize(t: "Tables", adj, n_particles: int, stream=None) -> np.ndarray:
@@ -349,9 +355,10 @@ def run(w: dict, n: int | None = None, first_pid: int = 0, precision: int = 32, 
 
 
 def sensitivities(w: dict, n: int | None = None, first_pid: int = 0, precision: int = 32, device: int = 0,
-                  tables: Tables | None = None, **launch) -> dict:
+                  tables: Tables | None = None, estimator: str = "score", **launch) -> dict:
     """Forward trace (recording each particle's flux score) then the replay that accumulates the
-    likelihood-ratio sums: kappa and dkappa / dln tau_i per frequency bin."""
+    sensitivity sums of `estimator` ("score" or "pathwise"): kappa and dkappa / dln tau_i per
+    frequency bin."""
     import torch
     t = tables or Tables(w, device)
     n = w["problem"]["N"] if n is None else int(n)
@@ -362,7 +369,7 @@ def sensitivities(w: dict, n: int | None = None, first_pid: int = 0, precision: 
     trace(t, r, first_pid, n, None, tl)
     adj = torch.zeros(t.info["adj_doubles"], dtype=torch.float64, device=dev)
     r2 = make_run(int(w["seed"]), precision, int(w.get("instance", 0)), **launch)
-    adjoint(t, r2, first_pid, n, F, adj)
+    adjoint(t, r2, ESTIMATORS[estimator], first_pid, n, F, adj)
     out = tally(t, tl, with_arrays=False)
     out["dkappa_dlntau"] = adjoint_finalize(t, adj, n)
     out["F"] = F.cpu().numpy()
