@@ -203,3 +203,42 @@ def test_rademacher_projection_against_crn_finite_difference(case, estimator):
     _say(f"[projection] {case} {estimator}: {est.mean():.4f} +- {est.std(ddof=1) / 4:.4f}, FD {fd.mean():.4f} +- "
          f"{fd.std(ddof=1) / 4:.4f}")
     assert abs(est.mean() - fd.mean()) < 3.0 * se
+
+
+def test_autograd_function_backward_is_the_replay():
+    """kappa_of_tau: the forward value is the traced kappa, the gradient is the replay's
+    dkappa / dln tau_i divided by tau_i, and it composes with other torch operations."""
+    import torch
+    import paper_2104_03573_amd as M
+    w = W.film(N=20000)
+    t0 = M.tau_bins(w)
+    tau = torch.tensor(t0, dtype=torch.float64, requires_grad=True)
+    k = M.kappa_of_tau(tau, w, precision=64)
+    loss = (k - 40.0) ** 2
+    loss.backward()
+    ref = M.sensitivities(w, precision=64)
+    assert k.item() == pytest.approx(ref["kappa"], rel=1e-12)
+    expect = 2.0 * (ref["kappa"] - 40.0) * ref["dkappa_dlntau"] / t0
+    assert np.allclose(tau.grad.numpy(), expect, rtol=1e-9, atol=1e-12 * np.abs(expect).max())
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_autograd_gray_bulk_matches_finite_difference_exactly(precision):
+    """Gray unbounded bulk: scaling tau by (1 + e) scales every flight and so every particle's
+    flux score by (1 + e) with the same random numbers, so kappa(tau) is linear in tau along the
+    ray; the pathwise gradient through the Function must equal the central difference to rounding."""
+    import torch
+    import paper_2104_03573_amd as M
+    w = W.bulk_gradient(N=20000, n_scat_max=3)
+    t0 = M.tau_bins(w)
+    tau = torch.tensor(t0, dtype=torch.float64, requires_grad=True)
+    k = M.kappa_of_tau(tau, w, precision=precision, estimator="pathwise")
+    k.backward()
+    e = 1e-3
+    kp = M.kappa_of_tau(torch.tensor(t0 * (1 + e)), w, precision=precision).item()
+    km = M.kappa_of_tau(torch.tensor(t0 * (1 - e)), w, precision=precision).item()
+    fd = (kp - km) / (2 * e)
+    got = float(tau.grad.numpy() @ t0)
+    tol = 1e-9 if precision == 64 else 2e-4
+    assert got == pytest.approx(fd, rel=tol)
+    assert got == pytest.approx(k.item(), rel=tol)
