@@ -92,7 +92,7 @@ def workload(name: str, scale: float = 1.0):
     if name == "gray_slab":
         return W.gray_slab(N=int(100_000 * scale)), "gray_slab_L100nm_Kn1_N1e5_50bins"
     if name == "porous_cell":
-        return W.porous_cell(N=int(10_000_000 * scale)), "porous_cell_500nm_phi0.25_N1e7"
+        return W.porous_cell(N=int(100_000_000 * scale)), "porous_cell_500nm_phi0.25_N1e8"
     if name == "transient":
         return W.transient_bump(N=int(10_000_000 * scale)), "transient_bump_1um_200times_100bins_N1e7"
     if name == "sweep":
@@ -128,6 +128,170 @@ def cpu_baseline(w: dict, seconds: float, threads: int) -> dict:
                       f"{threads} threads over contiguous particle ranges)"}
 
 
+def launch_config(args, tabs, w, M, precision):
+    """Block and refill: the caller's, else the autotuner's (outside the timed region)."""
+    if args.block or args.refill or args.no_autotune:
+        return {"block": args.block or 256, "refill": args.refill or 4, "autotuned": False}
+    ws = w if isinstance(w, list) else [w]
+    total = sum(x["problem"]["N"] for x in ws)
+    t0 = time.perf_counter()
+    r = M.tune(w, precision=precision, n_probe=max(1, min(total // 4, 4_000_000)), reps=2, tables=tabs)
+    return {"block": r["block"], "refill": r["refill"], "autotuned": True,
+            "tune_s": round(time.perf_counter() - t0, 3),
+            "tune_candidates": M.TUNE_CANDIDATES}
+
+
+def measure(args, w, M, torch, precision: int, steps: int, warmup: int, streams: int = 1):
+    """Trace `steps` batches of workload w (a new seed per step) after `warmup` untimed ones;
+    HIP events bracket each trace launch on its stream."""
+    t0 = time.perf_counter()
+    tabs = M.Tables(w, 0)
+    t_tables = time.perf_counter() - t0
+    lc = launch_config(args, tabs, w, M, precision)
+    N = w["problem"]["N"]
+    ncomp = bin(w["detectors"]["mask"]).count("1")
+    S = max(1, streams)
+    strm = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)]
+    tallies = [tabs.new_tally() for _ in range(S)]
+    base_seed = int(w["seed"])
+
+    def launch(slot: int, seed: int, ev=None):
+        tl = tallies[slot]
+        tl.zero_()
+        run = M.make_run(seed, precision, block=lc["block"], refill=lc["refill"], grid=args.grid)
+        if ev is not None:
+            ev[0].record()
+        M.trace(tabs, run, 0, N, None, tl)
+        if ev is not None:
+            ev[1].record()
+
+    def run_steps(n_steps: int, seed0: int, timed: bool):
+        """batch i on stream i % S; a stream's previous batch is finalized before its next one."""
+        events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(n_steps)] if timed else [None] * n_steps
+        pending = [False] * S
+        results = []
+        for i in range(n_steps):
+            slot = i % S
+            with torch.cuda.stream(strm[slot]):
+                if pending[slot]:
+                    results.append(M.tally(tabs, tallies[slot], with_arrays=False))
+                launch(slot, seed0 + i, events[i])
+                pending[slot] = True
+        for k in range(n_steps, n_steps + S):
+            slot = k % S
+            if pending[slot]:
+                with torch.cuda.stream(strm[slot]):
+                    results.append(M.tally(tabs, tallies[slot], with_arrays=False))
+                pending[slot] = False
+        return results, events
+
+    run_steps(max(warmup, 1), base_seed + 100000, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results, events = run_steps(steps, base_seed, True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in events]
+    ops = sum(algorithmic_lane_ops(r["counts"], tabs.info, w["geometry"], ncomp, w["problem"]["transient"])
+              for r in results)
+    achieved = ops / (sum(kernel_ms) / 1e3)
+    flights = sum(r["counts"]["flights"] for r in results)
+    out = {"wall_s": wall, "flights_per_s": flights / wall, "ms_per_step": wall / steps * 1e3,
+           "kernel_ms": kernel_ms, "lane_ops_per_launch": ops / steps, "achieved": achieved,
+           "frac": achieved / PEAK_LANE_OPS, "flights_per_step": flights / steps,
+           "particles_per_s": N * steps / wall,
+           "relaxations_per_s": sum(r["counts"]["relaxations"] for r in results) / wall,
+           "table_build_s": t_tables, "launch": lc, "tables": tabs, "last": results[-1], "N": N}
+    last = results[-1]
+    if not w["problem"]["transient"] and last.get("kappa"):
+        sig = last["kappa_sigma"] / abs(last["kappa"])
+        out["kappa_eff"] = last["kappa"]
+        out["kappa_sigma"] = last["kappa_sigma"]
+        # time to a 0.5 % standard error at this rate: t_step (sigma_rel / 0.005)^2
+        out["time_to_sigma_0p5pct_s"] = (wall / steps) * (sig / 0.005) ** 2
+    return out
+
+
+def measure_batched(args, ws, M, torch, precision: int, steps: int, warmup: int):
+    """The batched form: every step traces all instances in one persistent launch."""
+    t0 = time.perf_counter()
+    tabs = [M.Tables(w, 0) for w in ws]
+    t_tables = time.perf_counter() - t0
+    lc = launch_config(args, tabs, ws, M, precision)
+    tallies = [t.new_tally() for t in tabs]
+    queue = torch.zeros(M.batch_queue_bytes(len(ws)), dtype=torch.uint8, device="cuda")
+    ns = [w["problem"]["N"] for w in ws]
+    ids = [w["instance"] for w in ws]
+    base_seed = int(ws[0]["seed"])
+
+    def step(seed, ev=None):
+        for tl in tallies:
+            tl.zero_()
+        run = M.make_run(seed, precision, block=lc["block"], refill=lc["refill"], grid=args.grid)
+        if ev is not None:
+            ev[0].record()
+        M.trace_batch(tabs, ns, ids, tallies, run, queue)
+        if ev is not None:
+            ev[1].record()
+        return [M.tally(t, tl, with_arrays=False) for t, tl in zip(tabs, tallies)]
+
+    for i in range(max(warmup, 1)):
+        step(base_seed + 100000 + i)
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    results = [step(base_seed + i, events[i]) for i in range(steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in events]
+    flights = sum(r["counts"]["flights"] for rs in results for r in rs)
+    ops = sum(algorithmic_lane_ops(r["counts"], t.info, w["geometry"], bin(w["detectors"]["mask"]).count("1"), False)
+              for rs in results for r, t, w in zip(rs, tabs, ws))
+    achieved = ops / (sum(kernel_ms) / 1e3)
+    last = results[-1]
+    return {"wall_s": wall, "flights_per_s": flights / wall, "ms_per_step": wall / steps * 1e3,
+            "kernel_ms": kernel_ms, "achieved": achieved, "frac": achieved / PEAK_LANE_OPS,
+            "lane_ops_per_launch": ops / steps, "flights_per_step": flights / steps, "particles_per_step": sum(ns),
+            "kappa_eff_per_instance": [r["kappa"] for r in last],
+            "worst_kappa_sigma_rel": max(r["kappa_sigma"] / abs(r["kappa"]) for r in last),
+            "table_build_s": t_tables, "launch": lc}
+
+
+def measure_sensitivity(args, w, M, torch, estimator: str, steps: int):
+    """Forward trace recording each particle's flux score, then the sensitivity replay (1000
+    frequency bins); both launches timed with HIP events."""
+    tabs = M.Tables(w, 0)
+    lc = launch_config(args, tabs, w, M, 32)
+    N = w["problem"]["N"]
+    F = torch.zeros(N, dtype=torch.float64, device="cuda")
+    tl = tabs.new_tally()
+    adj = torch.zeros(tabs.info["adj_doubles"], dtype=torch.float64, device="cuda")
+    fwd, rep, flights = [], [], 0
+    est = M.ESTIMATORS[estimator]
+    for i in range(steps + 1):
+        tl.zero_()
+        adj.zero_()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        seed = int(w["seed"]) + i
+        ev[0].record()
+        M.trace(tabs, M.make_run(seed, 32, block=lc["block"], refill=lc["refill"], particle_F=F), 0, N, None, tl)
+        ev[1].record()
+        M.adjoint(tabs, M.make_run(seed, 32, block=lc["block"], refill=lc["refill"]), est, 0, N, F, adj)
+        ev[2].record()
+        res = M.tally(tabs, tl, with_arrays=False)
+        M.adjoint_finalize(tabs, adj, N)
+        if i == 0:
+            continue                      # warm-up
+        fwd.append(ev[0].elapsed_time(ev[1]))
+        rep.append(ev[1].elapsed_time(ev[2]))
+        flights += res["counts"]["flights"]
+    return {"estimator": estimator, "forward_ms": fwd, "replay_ms": rep,
+            "flights_per_s_forward": flights / (sum(fwd) / 1e3),
+            "flights_per_s_with_sensitivities": flights / ((sum(fwd) + sum(rep)) / 1e3),
+            "bins": int(tabs.info["n_bins"]), "launch": lc}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +304,10 @@ def main():
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--streams", type=int, default=1)
+    ap.add_argument("--no-autotune", action="store_true", help="default launch shape (block 256, refill 4)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the other configurations (gray slab FP64, transient, batched sweep, porous cell "
+                         "with sensitivities) reported under 'forms'")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -152,7 +320,6 @@ def main():
               "(multi-GPU sharding is a design note, not a built path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.copy_calibration:
@@ -168,165 +335,79 @@ def main():
     import paper_2104_03573_amd as M
 
     w, wname = workload(args.workload, args.scale)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(torch.device("cuda:0"))
+    dtype = "f32" if args.precision == 32 else "f64"
+    common = {"metric": METRIC, "unit": "flights/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic"}
     if isinstance(w, list):
-        return bench_batched(args, w, wname, M, torch)
-    t0 = time.perf_counter()
-    tabs = M.Tables(w, 0)
-    t_tables = time.perf_counter() - t0
-    N = w["problem"]["N"]
-    ncomp = bin(w["detectors"]["mask"]).count("1")
+        m = measure_batched(args, w, M, torch, args.precision, args.steps, args.warmup)
+        out = dict(common, value=m["flights_per_s"], ms_per_step=m["ms_per_step"],
+                   config={"workload": wname, "instances": len(w), "particles_per_step": m["particles_per_step"],
+                           "precision": args.precision, "tallies": "f64", "launch": m["launch"],
+                           "parallelism": "single GPU, one batched launch"},
+                   roofline={"bound": "alu", "achieved": m["achieved"] / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                             "unit": "T lane-op/s", "frac": m["frac"], "traffic": None, "kernel": "k_trace_batch",
+                             "kernel_ms": sum(m["kernel_ms"]) / len(m["kernel_ms"])},
+                   kernel_ms_per_step=m["kernel_ms"], kappa_eff_per_instance=m["kappa_eff_per_instance"],
+                   worst_kappa_sigma_rel=m["worst_kappa_sigma_rel"], table_build_s=m["table_build_s"])
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(w[-1], args.cpu_seconds, min(16, os.cpu_count() or 1))
+        print(json.dumps(out), flush=True)
+        return
+    m = measure(args, w, M, torch, args.precision, args.steps, args.warmup, args.streams)
     S = max(1, args.streams)
-    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)]
-    tallies = [tabs.new_tally() for _ in range(S)]
-    base_seed = int(w["seed"])
-
-    def launch(slot: int, seed: int, ev=None):
-        tl = tallies[slot]
-        tl.zero_()
-        run = M.make_run(seed, args.precision, block=args.block, refill=args.refill, grid=args.grid)
-        if ev is not None:
-            ev[0].record()
-        M.trace(tabs, run, 0, N, None, tl)
-        if ev is not None:
-            ev[1].record()
-
-    def finish(slot: int):
-        return M.tally(tabs, tallies[slot], with_arrays=False)
-
-    def run_steps(n_steps: int, n_streams: int, seed0: int, timed: bool):
-        """n_steps batches; batch i on stream i % n_streams; a stream's previous batch is finalized
-        before the stream takes its next one."""
-        events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(n_steps)] if timed else [None] * n_steps
-        pending = [False] * n_streams
-        results = []
-        for i in range(n_steps):
-            slot = i % n_streams
-            with torch.cuda.stream(streams[slot]):
-                if pending[slot]:
-                    results.append(finish(slot))
-                launch(slot, seed0 + i, events[i])
-                pending[slot] = True
-        for k in range(n_steps, n_steps + n_streams):
-            slot = k % n_streams
-            if pending[slot]:
-                with torch.cuda.stream(streams[slot]):
-                    results.append(finish(slot))
-                pending[slot] = False
-        return results, events
-
-    # warmup, then the timed steps; the trace kernel of every step is bracketed by HIP events on
-    # its stream (the roofline uses their durations; with several streams the kernels overlap)
-    run_steps(max(args.warmup, 1), S, base_seed + 100000, False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results, events = run_steps(args.steps, S, base_seed, True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernel_ms = [a.elapsed_time(b) for a, b in events]
-    ops = sum(algorithmic_lane_ops(r["counts"], tabs.info, w["geometry"], ncomp, w["problem"]["transient"])
-              for r in results)
-    achieved = ops / (sum(kernel_ms) / 1e3)
-    flights = sum(r["counts"]["flights"] for r in results)
-    last = results[-1]
-    out = {
-        "metric": METRIC,
-        "value": flights / wall,
-        "unit": "flights/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if args.precision == 32 else "f64",
-        "data": "synthetic",
-        "config": {"workload": wname, "particles_per_step": N, "modes": int(tabs.info["n_modes"]),
-                   "precision": args.precision, "tallies": "f64", "streams": S,
-                   "parallelism": "single GPU" + (", batches overlapped on %d streams" % S if S > 1 else "")},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS,
-                     "traffic": (profiled_traffic("k_trace_solo_film_fp32")
-                                 if args.workload == "film" and args.precision == 32 and S == 1 else None),
-                     "kernel": "k_trace_solo", "kernel_ms": sum(kernel_ms) / len(kernel_ms),
-                     "lane_ops_per_launch": ops / args.steps},
-        "kernel_ms_per_step": kernel_ms,
-        "flights_per_step": flights / args.steps,
-        "particles_per_s": N * args.steps / wall,
-        "relaxations_per_s": sum(r["counts"]["relaxations"] for r in results) / wall,
-        "table_build_s": t_tables,
-    }
-    if not w["problem"]["transient"] and last.get("kappa"):
-        sig = last["kappa_sigma"] / abs(last["kappa"])
-        out["kappa_eff"] = last["kappa"]
-        out["kappa_sigma"] = last["kappa_sigma"]
-        # time to a 0.5% standard error at this rate: t_step (sigma_rel / 0.005)^2
-        out["time_to_sigma_0p5pct_s"] = (wall / args.steps) * (sig / 0.005) ** 2
+    out = dict(common, value=m["flights_per_s"], ms_per_step=m["ms_per_step"],
+               config={"workload": wname, "particles_per_step": m["N"], "modes": int(m["tables"].info["n_modes"]),
+                       "precision": args.precision, "tallies": "f64", "streams": S, "launch": m["launch"],
+                       "parallelism": "single GPU" + (", batches overlapped on %d streams" % S if S > 1 else "")},
+               roofline={"bound": "alu", "achieved": m["achieved"] / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                         "unit": "T lane-op/s", "frac": m["frac"],
+                         "traffic": (profiled_traffic("k_trace_solo_film_fp32")
+                                     if args.workload == "film" and args.precision == 32 and S == 1 else None),
+                         "kernel": "k_trace_solo", "kernel_ms": sum(m["kernel_ms"]) / len(m["kernel_ms"]),
+                         "lane_ops_per_launch": m["lane_ops_per_launch"]},
+               kernel_ms_per_step=m["kernel_ms"], flights_per_step=m["flights_per_step"],
+               particles_per_s=m["particles_per_s"], relaxations_per_s=m["relaxations_per_s"],
+               table_build_s=m["table_build_s"])
+    for k in ("kappa_eff", "kappa_sigma", "time_to_sigma_0p5pct_s"):
+        if k in m:
+            out[k] = m[k]
+    if not args.no_forms and args.workload == "film":
+        out["forms"] = other_forms(args, M, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, min(16, os.cpu_count() or 1))
     print(json.dumps(out), flush=True)
 
 
-def bench_batched(args, ws, wname, M, torch):
-    """The batched form: every step traces all instances of the sweep in one persistent launch."""
-    t0 = time.perf_counter()
-    tabs = [M.Tables(w, 0) for w in ws]
-    t_tables = time.perf_counter() - t0
-    tallies = [t.new_tally() for t in tabs]
-    queue = torch.zeros(M.batch_queue_bytes(len(ws)), dtype=torch.uint8, device="cuda")
-    ns = [w["problem"]["N"] for w in ws]
-    ids = [w["instance"] for w in ws]
-    base_seed = int(ws[0]["seed"])
+def _brief(m: dict, workload: str, precision: int) -> dict:
+    r = {"workload": workload, "precision": precision, "flights_per_s": m["flights_per_s"],
+         "ms_per_step": m["ms_per_step"], "kernel_ms": sum(m["kernel_ms"]) / len(m["kernel_ms"]),
+         "roofline_frac": m["frac"], "achieved_T_lane_ops": m["achieved"] / 1e12, "launch": m["launch"]}
+    for k in ("kappa_eff", "kappa_sigma", "time_to_sigma_0p5pct_s", "kappa_eff_per_instance",
+              "worst_kappa_sigma_rel", "particles_per_step"):
+        if k in m:
+            r[k] = m[k]
+    return r
 
-    def step(seed, ev=None):
-        for tl in tallies:
-            tl.zero_()
-        run = M.make_run(seed, args.precision, block=args.block, refill=args.refill, grid=args.grid)
-        if ev is not None:
-            ev[0].record()
-        M.trace_batch(tabs, ns, ids, tallies, run, queue)
-        if ev is not None:
-            ev[1].record()
-        return [M.tally(t, tl, with_arrays=False) for t, tl in zip(tabs, tallies)]
 
-    for i in range(max(args.warmup, 1)):
-        step(base_seed + 100000 + i)
-    torch.cuda.synchronize()
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    results = [step(base_seed + i, events[i]) for i in range(args.steps)]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernel_ms = [a.elapsed_time(b) for a, b in events]
-    flights = sum(r["counts"]["flights"] for rs in results for r in rs)
-    ops = sum(algorithmic_lane_ops(r["counts"], t.info, w["geometry"], bin(w["detectors"]["mask"]).count("1"), False)
-              for rs in results for r, t, w in zip(rs, tabs, ws))
-    achieved = ops / (sum(kernel_ms) / 1e3)
-    last = results[-1]
-    worst = max(r["kappa_sigma"] / abs(r["kappa"]) for r in last)
-    out = {
-        "metric": METRIC, "value": flights / wall, "unit": "flights/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == 32 else "f64",
-        "data": "synthetic",
-        "config": {"workload": wname, "instances": len(ws), "particles_per_step": sum(ns),
-                   "precision": args.precision, "tallies": "f64", "parallelism": "single GPU, one batched launch"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
-                     "kernel": "k_trace_batch", "kernel_ms": sum(kernel_ms) / len(kernel_ms)},
-        "kernel_ms_per_step": kernel_ms,
-        "kappa_eff_per_instance": [r["kappa"] for r in last],
-        "worst_kappa_sigma_rel": worst,
-        "table_build_s": t_tables,
-    }
-    if not args.no_cpu_baseline:
-        # the oracle on the most expensive instance alone (particles of every instance cost alike
-        # per flight); rate in flights/s
-        out["cpu_baseline"] = cpu_baseline(ws[-1], args.cpu_seconds, min(16, os.cpu_count() or 1))
-    print(json.dumps(out), flush=True)
+def other_forms(args, M, torch) -> dict:
+    """The remaining configurations, a few steps each, every one timed like the main line."""
+    forms = {}
+    plan = [("gray_slab_fp64", "gray_slab", 64, 10), ("film_fp64", "film", 64, 5),
+            ("transient_fp32", "transient", 32, 3), ("porous_cell_fp32", "porous_cell", 32, 3)]
+    for key, name, prec, steps in plan:
+        w, wname = workload(name, 1.0)
+        print(f"[bench] form {key}: {wname}", file=sys.stderr, flush=True)
+        forms[key] = _brief(measure(args, w, M, torch, prec, steps, 1), wname, prec)
+    ws, wname = workload("sweep", 1.0)
+    print(f"[bench] form batched_sweep_fp32: {wname}", file=sys.stderr, flush=True)
+    forms["batched_sweep_fp32"] = _brief(measure_batched(args, ws, M, torch, 32, 3, 1), wname, 32)
+    w, wname = workload("porous_cell", 1.0)
+    print(f"[bench] form sensitivities: {wname}", file=sys.stderr, flush=True)
+    sens = measure_sensitivity(args, w, M, torch, "score", 2)
+    sens["workload"] = wname
+    forms["porous_cell_sensitivities_fp32"] = sens
+    return forms
 
 
 if __name__ == "__main__":

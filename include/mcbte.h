@@ -251,6 +251,26 @@ int mcbte_trace_batch(const mcbte_tables* const* tables, int32_t n_inst, const i
                       const uint32_t* instance_ids, void* const* tallies, const mcbte_run* run, void* queue,
                       void* stream);
 
+/* Launch-shape autotuner.  The launch shape -- threads per workgroup and the refill period
+   (flights between refills of finished lanes) -- changes no result (every integer count and
+   trajectory is the same; only the order of floating-point tally sums moves), only the speed.
+   The candidates are block in {64, 128, 192, 256} x refill in {1, 2, 4, 8, 16, 32}, numbered
+   block-major (candidate c: block 64 (1 + c / 6), refill 2^(c % 6)).  Each is timed (HIP events on
+   `stream`) over `reps` launches after one warm-up launch, on a calibration run of the caller's
+   problem: n_inst == 1, particles 0 .. n_probe - 1 of tables[0] (mcbte_trace); n_inst > 1, the
+   batched form (mcbte_trace_batch) with every instance's particle count scaled by
+   n_probe / sum(n_particles) (at least one particle each), keeping the mix of instances.
+   *out = *base with the fastest block and refill (grid left as in *base).  timings (optional,
+   host, n_timings >= MCBTE_TUNE_CANDIDATES) receives the fastest time of each candidate in ms
+   (+inf for one that cannot launch).  tallies / queue: caller-owned device buffers as for
+   mcbte_trace / mcbte_trace_batch (instance_ids and queue are ignored when n_inst == 1); their
+   contents are meaningless afterwards.  base->event_log and base->particle_F must be NULL.
+   Synchronizes `stream`.  Errors: MCBTE_EINVAL, MCBTE_ENODEV, MCBTE_EHIP, MCBTE_ESIZE. */
+#define MCBTE_TUNE_CANDIDATES 24
+int mcbte_autotune(const mcbte_tables* const* tables, int32_t n_inst, const int64_t* n_particles,
+                   const uint32_t* instance_ids, void* const* tallies, void* queue, const mcbte_run* base,
+                   int64_t n_probe, int32_t reps, mcbte_run* out, double* timings, int32_t n_timings, void* stream);
+
 /* Sensitivity of kappa to a relative change of the relaxation times of each frequency bin,
    dkappa / dln tau_i (steady runs with a gradient), by one of two estimators.
    MCBTE_SENS_SCORE (likelihood ratio): every random quantity whose law depends on tau contributes

@@ -14,6 +14,8 @@ __all__ = ["COUNT_NAMES", "ESTIMATORS", "EXPORTED", "LIB_PATH", "SENS_PATHWISE",
            "batch_queue_bytes", "build_tables", "emit", "free_tables", "lib", "make_run", "run", "sensitivities",
            "state_bytes", "strerror", "table_export", "table_info", "tally", "trace", "trace_batch"]
 
+from .mcbte import TUNE_CANDIDATES, autotune, tune, tune_candidate  # noqa: E402
 from .autograd import KappaOfTau, kappa_of_tau, tau_bins, with_tau_bins  # noqa: E402
 
-__all__ += ["KappaOfTau", "kappa_of_tau", "tau_bins", "with_tau_bins"]
+__all__ += ["KappaOfTau", "kappa_of_tau", "tau_bins", "with_tau_bins", "TUNE_CANDIDATES", "autotune", "tune",
+            "tune_candidate"]

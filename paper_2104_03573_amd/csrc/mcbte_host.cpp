@@ -692,6 +692,80 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
 }
 
+int mcbte_autotune(const mcbte_tables* const* ts, int32_t n_inst, const int64_t* n_particles,
+                   const uint32_t* instance_ids, void* const* tallies, void* queue, const mcbte_run* base,
+                   int64_t n_probe, int32_t reps, mcbte_run* out, double* timings, int32_t n_timings, void* stream)
+{
+    if (!ts || n_inst < 1 || !n_particles || !tallies || !base || !out || n_probe < 1 || reps < 1) return MCBTE_EINVAL;
+    if (base->event_log || base->particle_F) return MCBTE_EINVAL;
+    if (n_inst > 1 && (!instance_ids || !queue)) return MCBTE_EINVAL;
+    if (timings && n_timings < MCBTE_TUNE_CANDIDATES) return MCBTE_ESIZE;
+    if (!ts[0] || ts[0]->device < 0) return MCBTE_ENODEV;
+    int64_t total = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        if (n_particles[i] < 0) return MCBTE_EINVAL;
+        total += n_particles[i];
+    }
+    if (total == 0) return MCBTE_EINVAL;
+    // the calibration problem: a prefix (one instance) or every count scaled alike (batched)
+    std::vector<int64_t> np((size_t)n_inst);
+    const double f = n_probe < total ? (double)n_probe / (double)total : 1.0;
+    for (int i = 0; i < n_inst; ++i)
+        np[(size_t)i] = n_particles[i] == 0 ? 0 : std::max<int64_t>(1, (int64_t)std::llround((double)n_particles[i] * f));
+    DeviceGuard g(ts[0]->device);
+    if (!g.ok) return MCBTE_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return MCBTE_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MCBTE_EHIP;
+    }
+    int status = MCBTE_OK;
+    int best = -1;
+    double best_ms = 0.0;
+    for (int c = 0; c < MCBTE_TUNE_CANDIDATES && status == MCBTE_OK; ++c) {
+        mcbte_run r = *base;
+        r.block = 64 * (1 + c / 6);
+        r.refill = 1 << (c % 6);
+        auto go = [&]() {
+            return n_inst == 1 ? mcbte_trace(ts[0], &r, 0, np[0], nullptr, tallies[0], stream)
+                               : mcbte_trace_batch(ts, n_inst, np.data(), instance_ids, tallies, &r, queue, stream);
+        };
+        double t_c = INFINITY;
+        int rc = go();                                   // warm-up
+        if (rc == MCBTE_OK) {
+            for (int k = 0; k < reps; ++k) {
+                if (hipEventRecord(e0, s) != hipSuccess) { status = MCBTE_EHIP; break; }
+                rc = go();
+                if (rc != MCBTE_OK) break;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    status = MCBTE_EHIP;
+                    break;
+                }
+                float ms = 0.0f;
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { status = MCBTE_EHIP; break; }
+                t_c = std::min(t_c, (double)ms);
+            }
+        }
+        if (rc == MCBTE_EHIP) status = MCBTE_EHIP;      // a launch failure ends the search
+        if (rc != MCBTE_OK) t_c = INFINITY;              // a shape this problem cannot use
+        if (timings) timings[c] = t_c;
+        if (t_c < INFINITY && (best < 0 || t_c < best_ms)) {
+            best = c;
+            best_ms = t_c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != MCBTE_OK) return status;
+    if (best < 0) return MCBTE_EINVAL;
+    *out = *base;
+    out->block = 64 * (1 + best / 6);
+    out->refill = 1 << (best % 6);
+    return MCBTE_OK;
+}
+
 static_assert(MCBTE_PATH_MAX == MCBTE_PATHWISE_MAX_FLIGHTS, "pathwise capacity");
 
 int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator, int64_t first_pid, int64_t n,

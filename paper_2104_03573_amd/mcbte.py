@@ -78,7 +78,7 @@ class Result(C.Structure):
 
 EXPORTED = ["mcbte_build_tables", "mcbte_free_tables", "mcbte_table_info", "mcbte_table_export",
             "mcbte_state_bytes", "mcbte_emit", "mcbte_trace", "mcbte_batch_queue_bytes", "mcbte_trace_batch",
-            "mcbte_adjoint", "mcbte_adjoint_finalize", "mcbte_tally", "mcbte_strerror"]
+            "mcbte_adjoint", "mcbte_adjoint_finalize", "mcbte_tally", "mcbte_strerror", "mcbte_autotune"]
 
 _lib = None
 
@@ -112,6 +112,10 @@ def lib():
         L.mcbte_trace_batch.argtypes = [C.POINTER(p), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
                                         C.POINTER(p), C.POINTER(Run), p, p]
         L.mcbte_trace_batch.restype = C.c_int
+        L.mcbte_autotune.argtypes = [C.POINTER(p), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
+                                     C.POINTER(p), p, C.POINTER(Run), C.c_int64, C.c_int32, C.POINTER(Run),
+                                     C.POINTER(C.c_double), C.c_int32, p]
+        L.mcbte_autotune.restype = C.c_int
         L.mcbte_adjoint.argtypes = [p, C.POINTER(Run), C.c_int32, C.c_int64, C.c_int64, p, p, p]
         L.mcbte_adjoint.restype = C.c_int
         L.mcbte_adjoint_finalize.argtypes = [p, p, C.c_int64, C.POINTER(C.c_double), C.c_int64, p]
@@ -255,6 +259,45 @@ def trace_batch(tables: list, n_particles, instance_ids, tallies: list, run: Run
     tp = (C.c_void_p * k)(*[tl.data_ptr() for tl in tallies])
     _check("mcbte_trace_batch", lib().mcbte_trace_batch(th, k, npart, ids, tp, C.byref(run),
                                                         C.c_void_p(queue.data_ptr()), _stream(stream)))
+
+
+TUNE_CANDIDATES = 24
+
+
+def tune_candidate(c: int) -> tuple[int, int]:
+    """(block, refill) of autotuner candidate c."""
+    return 64 * (1 + c // 6), 1 << (c % 6)
+
+
+def autotune(tables: list, n_particles, instance_ids, tallies: list, queue, base: Run, n_probe: int,
+             reps: int = 3, stream=None) -> tuple[Run, np.ndarray]:
+    k = len(tables)
+    th = (C.c_void_p * k)(*[t.h for t in tables])
+    npart = (C.c_int64 * k)(*[int(x) for x in n_particles])
+    ids = (C.c_uint32 * k)(*[int(x) for x in instance_ids])
+    tp = (C.c_void_p * k)(*[tl.data_ptr() for tl in tallies])
+    out = Run()
+    tim = (C.c_double * TUNE_CANDIDATES)()
+    _check("mcbte_autotune", lib().mcbte_autotune(th, k, npart, ids, tp,
+                                                  C.c_void_p(queue.data_ptr()) if queue is not None else None,
+                                                  C.byref(base), int(n_probe), int(reps), C.byref(out), tim,
+                                                  TUNE_CANDIDATES, _stream(stream)))
+    return out, np.array(tim[:])
+
+
+def tune(w, precision: int = 32, n_probe: int = 1 << 18, reps: int = 3, tables=None, device: int = 0) -> dict:
+    """Autotune the launch shape for a workload (dict) or a sweep (list of dicts, batched form)."""
+    import torch
+    ws = w if isinstance(w, list) else [w]
+    tabs = tables or [Tables(x, device) for x in ws]
+    tabs = tabs if isinstance(tabs, list) else [tabs]
+    tallies = [t.new_tally() for t in tabs]
+    queue = (torch.zeros(batch_queue_bytes(len(ws)), dtype=torch.uint8, device=f"cuda:{device}")
+             if len(ws) > 1 else None)
+    base = make_run(int(ws[0]["seed"]), precision)
+    run_, tim = autotune(tabs, [x["problem"]["N"] for x in ws], [int(x.get("instance", 0)) for x in ws], tallies,
+                         queue, base, n_probe, reps)
+    return {"block": run_.block, "refill": run_.refill, "timings_ms": tim, "tables": tabs}
 
 
 SENS_SCORE = 0
