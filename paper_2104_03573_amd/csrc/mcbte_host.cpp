@@ -556,7 +556,7 @@ int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run,
     }
     if (lds_tab > MCBTE_LDS_TABLE_BYTES || lds_tab > t0->max_lds) return MCBTE_EINVAL;
     lp.lds_tab = lds_tab;
-    if (mode >= 2) {   // sensitivity replay: the per-bin sums take the place of the tallies
+    if (mode == 2 || mode == 3) {   // sensitivity replay: the per-bin sums take the place of the tallies
         const int64_t bins = 8 * t0->info.n_bins;
         if (lds_tab + bins > t0->max_lds) return MCBTE_EINVAL;
         lp.tally_lds = 0;
@@ -590,7 +590,8 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     DeviceGuard g(t->device);
     if (!g.ok) return MCBTE_EHIP;
     LaunchPlan lp;
-    const int rc = plan_launch(&t, 1, run, 0, lp);
+    const int mode = (state || run->event_log) ? 4 : 0;   // the plain kernel has neither compiled in
+    const int rc = plan_launch(&t, 1, run, mode, lp);
     if (rc != MCBTE_OK) return rc;
     LaunchArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -610,7 +611,7 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     a.tally_lds = lp.tally_lds;
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
     a.particle_F = run->particle_F;
-    const hipError_t e = launch_trace(a, 0, run->precision, t->host_view.tally_kind, lp.block, lp.grid, lp.lds,
+    const hipError_t e = launch_trace(a, mode, run->precision, t->host_view.tally_kind, lp.block, lp.grid, lp.lds,
                                       (hipStream_t)stream);
     return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
 }

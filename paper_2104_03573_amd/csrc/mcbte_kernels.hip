@@ -1127,21 +1127,25 @@ __device__ __forceinline__ void flush_lane_stats(unsigned char* tally, const Lan
     }
 }
 
-template <typename R, int TK>
+// optional features of the trace kernel, compiled in only where used: particles loaded from a
+// state buffer written by k_emit, and the per-particle event log
+enum : int { FT_STATE = 1, FT_LOG = 2 };
+
+template <typename R, int TK, int FT>
 __device__ __forceinline__ void start_particle(const DevTab& T, const LaunchArgs& a, int64_t pid, uint32_t inst,
                                                Part<R>& p, Stream& st, LaneCounts& cnt, LogRow& lg)
 {
     st = Stream{(uint32_t)a.seed, (uint32_t)(a.seed >> 32), (uint32_t)(uint64_t)pid, (uint32_t)((uint64_t)pid >> 32),
                 inst};
     uint32_t rej = 0;
-    if (a.state) StateView<R>((void*)a.state, a.capacity).load(pid - a.first_pid, p, rej);
+    if ((FT & FT_STATE) && a.state) StateView<R>((void*)a.state, a.capacity).load(pid - a.first_pid, p, rej);
     else emit_particle<R>(T, st, p, rej);
     cnt.c[0] += 1;
     cnt.c[11] += rej;
     lg.row = nullptr;
     lg.n = 0;
     lg.stride = a.log_stride;
-    if (a.event_log && pid - a.first_pid < a.n_log) {
+    if ((FT & FT_LOG) && a.event_log && pid - a.first_pid < a.n_log) {
         lg.row = a.event_log + (pid - a.first_pid) * (int64_t)a.log_stride;
         lg.put(p.s > 0 ? EV_EMIT_POS : EV_EMIT_NEG, p.src, p.m);
     }
@@ -1162,7 +1166,7 @@ __device__ __forceinline__ void end_particle(const Part<R>& p, int transient, do
 // AK = 0: the forward trace (tallies, counters, moments, optional per-particle flux score F).
 // AK = 1 (likelihood ratio) or 2 (pathwise): the sensitivity replay of the same particles: no
 // tallies; the per-bin sums go to LDS and then to a.adj; the work counter lives after the sums.
-template <typename R, int TK, int AK>
+template <typename R, int TK, int AK, int FT>
 __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1214,7 +1218,7 @@ __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ t
                     const unsigned long long idx = base + wave_rank(need);
                     if (idx < n) {
                         my_pid = a.first_pid + (int64_t)idx;
-                        start_particle<R, TK>(T, a, my_pid, a.inst0, p, st, cnt, lg);
+                        start_particle<R, TK, FT>(T, a, my_pid, a.inst0, p, st, cnt, lg);
                         if (ADJ) adj.F_total = a.particle_F[idx];
                         if (AK == 2) {
                             pc.nt = 0;
@@ -1419,17 +1423,18 @@ static void ensure_lds_limit(const void* fn, size_t lds)
 template <typename R, int TK>
 static hipError_t trace_t(const LaunchArgs& a, int mode, int block, int grid, size_t lds, hipStream_t s)
 {
-    // mode 0: solo trace, 1: batched trace, 2: likelihood-ratio replay, 3: pathwise replay
+    // mode 0: solo trace, 1: batched trace, 2: likelihood-ratio replay, 3: pathwise replay,
+    // 4: solo trace with a state buffer and/or an event log
     if (mode == 1) {
         auto fn = k_trace_batch<R, TK>;
         ensure_lds_limit((const void*)fn, lds);
         hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a.tabs, a);
     } else if (mode == 2 || mode == 3) {
-        auto fn = mode == 2 ? k_trace_solo<R, TK, 1> : k_trace_solo<R, TK, 2>;
+        auto fn = mode == 2 ? k_trace_solo<R, TK, 1, 0> : k_trace_solo<R, TK, 2, 0>;
         ensure_lds_limit((const void*)fn, lds);
         hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a.tabs, a);
     } else {
-        auto fn = k_trace_solo<R, TK, 0>;
+        auto fn = mode == 4 ? k_trace_solo<R, TK, 0, FT_STATE | FT_LOG> : k_trace_solo<R, TK, 0, 0>;
         ensure_lds_limit((const void*)fn, lds);
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s,
                            (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET));
@@ -1468,8 +1473,10 @@ int trace_occupancy(int mode, int precision, int tally_kind, int block, size_t l
     const void* fn = nullptr;
 #define MCBTE_PICK(RR, TKK)                                                                    \
     fn = mode == 1 ? (const void*)k_trace_batch<RR, TKK>                                        \
-       : mode == 2 ? (const void*)k_trace_solo<RR, TKK, 1>                                      \
-       : mode == 3 ? (const void*)k_trace_solo<RR, TKK, 2> : (const void*)k_trace_solo<RR, TKK, 0>
+       : mode == 2 ? (const void*)k_trace_solo<RR, TKK, 1, 0>                                   \
+       : mode == 3 ? (const void*)k_trace_solo<RR, TKK, 2, 0>                                   \
+       : mode == 4 ? (const void*)k_trace_solo<RR, TKK, 0, FT_STATE | FT_LOG>                   \
+                   : (const void*)k_trace_solo<RR, TKK, 0, 0>
     if (precision == 64) {
         if (tally_kind == TALLY_STEADY_ONE) MCBTE_PICK(double, TALLY_STEADY_ONE);
         else if (tally_kind == TALLY_STEADY_GRID) MCBTE_PICK(double, TALLY_STEADY_GRID);
