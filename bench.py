@@ -135,7 +135,9 @@ def launch_config(args, tabs, w, M, precision):
     ws = w if isinstance(w, list) else [w]
     total = sum(x["problem"]["N"] for x in ws)
     t0 = time.perf_counter()
-    r = M.tune(w, precision=precision, n_probe=max(1, min(total // 4, 4_000_000)), reps=2, tables=tabs)
+    # the calibration runs the whole batch up to 4e6 particles: a smaller probe shifts the balance
+    # between the steady part and the tail of a launch, and with it the best shape
+    r = M.tune(w, precision=precision, n_probe=max(1, min(total, 4_000_000)), reps=3, tables=tabs)
     return {"block": r["block"], "refill": r["refill"], "autotuned": True,
             "tune_s": round(time.perf_counter() - t0, 3),
             "tune_candidates": M.TUNE_CANDIDATES}

@@ -15,6 +15,10 @@ namespace mcbte {
 enum SourceKind : int32_t { SRC_WALL = 0, SRC_GRAD = 1, SRC_IC = 2 };
 enum TallyKind : int32_t { TALLY_STEADY_ONE = 0, TALLY_STEADY_GRID = 1, TALLY_TRANSIENT = 2 };
 
+// optional features of the trace kernels, compiled in only where used: particles loaded from a
+// state buffer written by k_emit, and the per-particle event log
+enum : int { FT_STATE = 1, FT_LOG = 2 };
+
 // Geometry in the form the flight loop reads it (uniform across a launch; scalar loads).
 struct DevGeom {
     double L[3];

@@ -15,10 +15,10 @@
 namespace mcbte {
 hipError_t launch_emit(const DevTab* d_tab, int precision, uint64_t seed, uint32_t inst, int64_t first_pid, int64_t n,
                        void* state, int64_t cap, hipStream_t s);
-hipError_t launch_trace(const LaunchArgs& a, int mode, int precision, int tally_kind, int block, int grid, size_t lds,
+hipError_t launch_trace(const LaunchArgs& a, int mode, int precision, int tally_kind, int ft, int block, int grid, size_t lds,
                         hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);
-int trace_occupancy(int mode, int precision, int tally_kind, int block, size_t lds);
+int trace_occupancy(int mode, int precision, int tally_kind, int ft, int block, size_t lds);
 }  // namespace mcbte
 
 using namespace mcbte;
@@ -542,7 +542,7 @@ struct LaunchPlan {
     size_t lds;
 };
 
-int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run, int mode, LaunchPlan& lp)
+int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run, int mode, int ft, LaunchPlan& lp)
 {
     const mcbte_tables* t0 = ts[0];
     const int prec = run->precision;
@@ -571,7 +571,7 @@ int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run,
     if (run->grid > 0) {
         lp.grid = run->grid;
     } else {
-        const int occ = trace_occupancy(mode, prec, t0->host_view.tally_kind, lp.block, lp.lds);
+        const int occ = trace_occupancy(mode, prec, t0->host_view.tally_kind, ft, lp.block, lp.lds);
         lp.grid = std::max(1, occ) * std::max(1, t0->n_cu);
     }
     return MCBTE_OK;
@@ -590,8 +590,9 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     DeviceGuard g(t->device);
     if (!g.ok) return MCBTE_EHIP;
     LaunchPlan lp;
-    const int mode = (state || run->event_log) ? 4 : 0;   // the plain kernel has neither compiled in
-    const int rc = plan_launch(&t, 1, run, mode, lp);
+    // the plain kernel has neither a state buffer nor an event log compiled in
+    const int ft = (state || run->event_log) ? (FT_STATE | FT_LOG) : 0;
+    const int rc = plan_launch(&t, 1, run, 0, ft, lp);
     if (rc != MCBTE_OK) return rc;
     LaunchArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -611,7 +612,7 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     a.tally_lds = lp.tally_lds;
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
     a.particle_F = run->particle_F;
-    const hipError_t e = launch_trace(a, mode, run->precision, t->host_view.tally_kind, lp.block, lp.grid, lp.lds,
+    const hipError_t e = launch_trace(a, 0, run->precision, t->host_view.tally_kind, ft, lp.block, lp.grid, lp.lds,
                                       (hipStream_t)stream);
     return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
 }
@@ -643,7 +644,7 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     if (!g.ok) return MCBTE_EHIP;
     LaunchPlan lp;
     if (run->particle_F) return MCBTE_EINVAL;
-    int rc = plan_launch(ts, n_inst, run, 1, lp);
+    int rc = plan_launch(ts, n_inst, run, 1, 0, lp);
     if (rc != MCBTE_OK) return rc;
     // chunking: items of chunk_size particles, instance-major
     const int64_t chunk = 8192;
@@ -689,7 +690,7 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     a.n_chunks = cstart[n_inst];
     a.tally_lds = lp.tally_lds;
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
-    const hipError_t e = launch_trace(a, 1, run->precision, t0->host_view.tally_kind, lp.block, lp.grid, lp.lds, s);
+    const hipError_t e = launch_trace(a, 1, run->precision, t0->host_view.tally_kind, 0, lp.block, lp.grid, lp.lds, s);
     return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
 }
 
@@ -785,8 +786,9 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
     DeviceGuard g(t->device);
     if (!g.ok) return MCBTE_EHIP;
     const int mode = estimator == MCBTE_SENS_PATHWISE ? 3 : 2;
+    const int ft = 0;
     LaunchPlan lp;
-    const int rc = plan_launch(&t, 1, run, mode, lp);
+    const int rc = plan_launch(&t, 1, run, mode, ft, lp);
     if (rc != MCBTE_OK) return rc;
     LaunchArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -805,7 +807,7 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
     hipStream_t s = (hipStream_t)stream;
     // the work counter is the last word of the caller's buffer
     if (launch_zero_u64((unsigned long long*)(adj + t->info.n_bins + 2), s) != hipSuccess) return MCBTE_EHIP;
-    const hipError_t e = launch_trace(a, mode, run->precision, t->host_view.tally_kind, lp.block, lp.grid, lp.lds, s);
+    const hipError_t e = launch_trace(a, mode, run->precision, t->host_view.tally_kind, ft, lp.block, lp.grid, lp.lds, s);
     return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
 }
 

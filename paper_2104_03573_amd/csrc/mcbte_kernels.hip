@@ -640,7 +640,7 @@ struct PathCtx {
 
 // Advance particle p by one segment; returns true when the particle has ended.
 // AK: 0 trace, 1 likelihood-ratio replay, 2 pathwise replay.
-template <typename R, int TK, int AK>
+template <typename R, int TK, int AK, int FT>
 __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const TallyCtx& tc, const Stream& st,
                                        Part<R>& p, LaneCounts& cnt, LogRow& lg, bool& coop, AdjCtx& adj,
                                        PathCtx<R>& pc)
@@ -1127,10 +1127,6 @@ __device__ __forceinline__ void flush_lane_stats(unsigned char* tally, const Lan
     }
 }
 
-// optional features of the trace kernel, compiled in only where used: particles loaded from a
-// state buffer written by k_emit, and the per-particle event log
-enum : int { FT_STATE = 1, FT_LOG = 2 };
-
 template <typename R, int TK, int FT>
 __device__ __forceinline__ void start_particle(const DevTab& T, const LaunchArgs& a, int64_t pid, uint32_t inst,
                                                Part<R>& p, Stream& st, LaneCounts& cnt, LogRow& lg)
@@ -1237,7 +1233,7 @@ __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ t
         ++since_refill;
         bool coop = false;
         if (alive) {
-            if (flight<R, TK, AK>(T, tb, tc, st, p, cnt, lg, coop, adj, pc)) {
+            if (flight<R, TK, AK, FT>(T, tb, tc, st, p, cnt, lg, coop, adj, pc)) {
                 end_particle(p, T.transient, mom, lg);
                 if (!ADJ && a.particle_F) a.particle_F[my_pid - a.first_pid] = p.cq;
                 alive = false;
@@ -1371,7 +1367,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
             ++since_refill;
             bool coop = false;
             if (alive) {
-                if (flight<R, TK, 0>(T, tb, tc, st, p, cnt, lg, coop, adj, pc)) {
+                if (flight<R, TK, 0, 0>(T, tb, tc, st, p, cnt, lg, coop, adj, pc)) {
                     end_particle(p, T.transient, mom, lg);
                     alive = false;
                 }
@@ -1420,44 +1416,48 @@ static void ensure_lds_limit(const void* fn, size_t lds)
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess) done[fn] = lds;
 }
 
+// the kernel of a launch: mode 0 trace, 1 batched trace, 2 likelihood-ratio replay, 3 pathwise
+// replay; ft the optional features (FT_STATE | FT_LOG: a state buffer and/or an event log)
 template <typename R, int TK>
-static hipError_t trace_t(const LaunchArgs& a, int mode, int block, int grid, size_t lds, hipStream_t s)
+static const void* pick_kernel(int mode, int ft)
 {
-    // mode 0: solo trace, 1: batched trace, 2: likelihood-ratio replay, 3: pathwise replay,
-    // 4: solo trace with a state buffer and/or an event log
-    if (mode == 1) {
-        auto fn = k_trace_batch<R, TK>;
-        ensure_lds_limit((const void*)fn, lds);
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a.tabs, a);
-    } else if (mode == 2 || mode == 3) {
-        auto fn = mode == 2 ? k_trace_solo<R, TK, 1, 0> : k_trace_solo<R, TK, 2, 0>;
-        ensure_lds_limit((const void*)fn, lds);
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a.tabs, a);
-    } else {
-        auto fn = mode == 4 ? k_trace_solo<R, TK, 0, FT_STATE | FT_LOG> : k_trace_solo<R, TK, 0, 0>;
-        ensure_lds_limit((const void*)fn, lds);
-        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s,
-                           (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET));
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a.tabs, a);
-    }
-    return hipGetLastError();
+    if (mode == 1) return (const void*)k_trace_batch<R, TK>;
+    if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, 0>;
+    if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, 0>;
+    if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG>;
+    return (const void*)k_trace_solo<R, TK, 0, 0>;
 }
 
-hipError_t launch_trace(const LaunchArgs& a, int mode, int precision, int tally_kind, int block, int grid, size_t lds,
-                        hipStream_t s)
+static const void* kernel_for(int mode, int precision, int tally_kind, int ft)
 {
     if (precision == 64) {
         switch (tally_kind) {
-        case TALLY_STEADY_ONE: return trace_t<double, TALLY_STEADY_ONE>(a, mode, block, grid, lds, s);
-        case TALLY_STEADY_GRID: return trace_t<double, TALLY_STEADY_GRID>(a, mode, block, grid, lds, s);
-        default: return trace_t<double, TALLY_TRANSIENT>(a, mode, block, grid, lds, s);
+        case TALLY_STEADY_ONE: return pick_kernel<double, TALLY_STEADY_ONE>(mode, ft);
+        case TALLY_STEADY_GRID: return pick_kernel<double, TALLY_STEADY_GRID>(mode, ft);
+        default: return pick_kernel<double, TALLY_TRANSIENT>(mode, ft);
         }
     }
     switch (tally_kind) {
-    case TALLY_STEADY_ONE: return trace_t<float, TALLY_STEADY_ONE>(a, mode, block, grid, lds, s);
-    case TALLY_STEADY_GRID: return trace_t<float, TALLY_STEADY_GRID>(a, mode, block, grid, lds, s);
-    default: return trace_t<float, TALLY_TRANSIENT>(a, mode, block, grid, lds, s);
+    case TALLY_STEADY_ONE: return pick_kernel<float, TALLY_STEADY_ONE>(mode, ft);
+    case TALLY_STEADY_GRID: return pick_kernel<float, TALLY_STEADY_GRID>(mode, ft);
+    default: return pick_kernel<float, TALLY_TRANSIENT>(mode, ft);
     }
+}
+
+hipError_t launch_trace(const LaunchArgs& a, int mode, int precision, int tally_kind, int ft, int block, int grid,
+                        size_t lds, hipStream_t s)
+{
+    const void* fn = kernel_for(mode, precision, tally_kind, ft);
+    ensure_lds_limit(fn, lds);
+    if (mode == 0) {   // the work counter of a solo trace lives in the tally header
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s,
+                           (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET));
+    }
+    const DevTab* tabs = a.tabs;
+    LaunchArgs args = a;
+    void* kargs[] = {(void*)&tabs, (void*)&args};
+    const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(block), kargs, lds, s);
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s)
@@ -1468,25 +1468,9 @@ hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s)
 
 // occupancy of the trace kernel (workgroups per compute unit) for a block size and LDS size,
 // cached per (kernel, block, LDS)
-int trace_occupancy(int mode, int precision, int tally_kind, int block, size_t lds)
+int trace_occupancy(int mode, int precision, int tally_kind, int ft, int block, size_t lds)
 {
-    const void* fn = nullptr;
-#define MCBTE_PICK(RR, TKK)                                                                    \
-    fn = mode == 1 ? (const void*)k_trace_batch<RR, TKK>                                        \
-       : mode == 2 ? (const void*)k_trace_solo<RR, TKK, 1, 0>                                   \
-       : mode == 3 ? (const void*)k_trace_solo<RR, TKK, 2, 0>                                   \
-       : mode == 4 ? (const void*)k_trace_solo<RR, TKK, 0, FT_STATE | FT_LOG>                   \
-                   : (const void*)k_trace_solo<RR, TKK, 0, 0>
-    if (precision == 64) {
-        if (tally_kind == TALLY_STEADY_ONE) MCBTE_PICK(double, TALLY_STEADY_ONE);
-        else if (tally_kind == TALLY_STEADY_GRID) MCBTE_PICK(double, TALLY_STEADY_GRID);
-        else MCBTE_PICK(double, TALLY_TRANSIENT);
-    } else {
-        if (tally_kind == TALLY_STEADY_ONE) MCBTE_PICK(float, TALLY_STEADY_ONE);
-        else if (tally_kind == TALLY_STEADY_GRID) MCBTE_PICK(float, TALLY_STEADY_GRID);
-        else MCBTE_PICK(float, TALLY_TRANSIENT);
-    }
-#undef MCBTE_PICK
+    const void* fn = kernel_for(mode, precision, tally_kind, ft);
     static std::mutex mu;
     static std::map<std::tuple<const void*, int, size_t>, int> cache;
     const auto key = std::make_tuple(fn, block, lds);

@@ -233,3 +233,28 @@ def test_full_size_film_fp32_against_oracle():
     assert got["counts"]["particles"] == 1_000_000
     assert rel_k < 1e-4
     assert abs(got["counts"]["flights"] - ref["counts"]["flights"]) <= 1e-3 * ref["counts"]["flights"]
+
+
+@pytest.mark.parametrize("lam,spec", [(20e-6, 0.0), (20e-6, 1.0), (2e-6, 0.5)])
+def test_fp32_long_flights_in_pore_lattice_against_fp64_oracle(lam, spec):
+    """Gray medium in the porous cell with mean free paths of 2-20 um (4-40 cells per free
+    path on average, thousands for the long ones; diffuse, specular and partly specular pore):
+    every event count of the FP32 trajectories agrees with the FP64 oracle's on the same
+    particles within 1 %, and kappa within 3 oracle standard errors."""
+    M = _pkg()
+    gray = W.gray_modes(6400.0, lam / 6400.0)
+    w = W.with_(W.porous_cell(N=20000, modes=gray, specularity=spec, n_scat_max=4), **{"problem.format": 2})
+    got = M.run(w, precision=32)
+    ref = _oracle_full(w)
+    c, r = got["counts"], ref["counts"]
+    _say(f"[pore lattice] lam {lam:g} spec {spec}: kappa {got['kappa']:.5g} vs {ref['kappa']:.5g} "
+         f"(sigma {ref['kappa_sigma']:.3g}); periodic {c['periodic']} vs {r['periodic']}, "
+         f"pore hits {c['diffuse'] + c['specular']} vs {r['diffuse'] + r['specular']}")
+    for k in ("particles", "relaxations", "nscat_end", "rejections"):
+        assert c[k] == r[k], k
+    for k in ("flights", "periodic"):
+        assert abs(c[k] - r[k]) <= 0.01 * r[k], k
+    hits = c["diffuse"] + c["specular"], r["diffuse"] + r["specular"]
+    assert abs(hits[0] - hits[1]) <= 0.01 * hits[1] + 5
+    assert c["escaped"] == 0 and c["cap_end"] == 0
+    assert abs(got["kappa"] - ref["kappa"]) < 3.0 * ref["kappa_sigma"]
