@@ -160,7 +160,10 @@ typedef struct {
     uint64_t seed;        /* Philox key                                                     */
     uint32_t instance;    /* fourth counter word of every Philox draw                       */
     int32_t precision;    /* 64: FP64 trajectories; 32: FP32 trajectories, FP64 tables and sums */
-    int32_t block;        /* threads per workgroup (multiple of 64, <= 1024; 0 = default)   */
+    int32_t block;        /* threads per workgroup: multiple of 64, <= 256 (0 = 256); <= 1024
+                             (0 = 1024) for an FP32 trace whose FP64 tally is too large for a
+                             per-workgroup LDS copy while its FP32 tally fits the whole LDS: those
+                             run wide workgroups, the mode tables read from HBM */
     int32_t refill;       /* flights between refills of finished lanes (>= 1; 0 = default)  */
     int32_t grid;         /* workgroups (0 = enough to fill every compute unit)             */
     int32_t log_stride;   /* uint32 words per event-log row (>= 2)                          */
@@ -254,8 +257,10 @@ int mcbte_trace_batch(const mcbte_tables* const* tables, int32_t n_inst, const i
 /* Launch-shape autotuner.  The launch shape -- threads per workgroup and the refill period
    (flights between refills of finished lanes) -- changes no result (every integer count and
    trajectory is the same; only the order of floating-point tally sums moves), only the speed.
-   The candidates are block in {64, 128, 192, 256} x refill in {1, 2, 4, 8, 16, 32}, numbered
-   block-major (candidate c: block 64 (1 + c / 6), refill 2^(c % 6)).  Each is timed (HIP events on
+   The candidates are block in {64, 128, 192, 256, 512, 1024} x refill in {1, 2, 4, 8, 16, 32},
+   numbered block-major (candidate c: block {64, 128, 192, 256, 512, 1024}[c / 6], refill
+   2^(c % 6)); a block size the problem's kernel cannot take (above 256 except for the wide FP32
+   kernel, see mcbte_run) counts as +inf.  Each is timed (HIP events on
    `stream`) over `reps` launches after one warm-up launch, on a calibration run of the caller's
    problem: n_inst == 1, particles 0 .. n_probe - 1 of tables[0] (mcbte_trace); n_inst > 1, the
    batched form (mcbte_trace_batch) with every instance's particle count scaled by
@@ -266,7 +271,7 @@ int mcbte_trace_batch(const mcbte_tables* const* tables, int32_t n_inst, const i
    mcbte_trace / mcbte_trace_batch (instance_ids and queue are ignored when n_inst == 1); their
    contents are meaningless afterwards.  base->event_log and base->particle_F must be NULL.
    Synchronizes `stream`.  Errors: MCBTE_EINVAL, MCBTE_ENODEV, MCBTE_EHIP, MCBTE_ESIZE. */
-#define MCBTE_TUNE_CANDIDATES 24
+#define MCBTE_TUNE_CANDIDATES 36
 int mcbte_autotune(const mcbte_tables* const* tables, int32_t n_inst, const int64_t* n_particles,
                    const uint32_t* instance_ids, void* const* tallies, void* queue, const mcbte_run* base,
                    int64_t n_probe, int32_t reps, mcbte_run* out, double* timings, int32_t n_timings, void* stream);

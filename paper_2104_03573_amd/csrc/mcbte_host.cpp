@@ -419,6 +419,10 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
             delete t;
             return MCBTE_EHIP;
         }
+        int optin = 0;   // the LDS a kernel may use after raising its dynamic-LDS limit
+        if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, device) == hipSuccess &&
+            optin > t->max_lds)
+            t->max_lds = optin;
         // one allocation, 256-byte aligned pieces
         std::vector<std::pair<const void*, size_t>> parts;
         auto add = [&](const void* src, size_t bytes) { parts.emplace_back(src, bytes); };
@@ -556,7 +560,12 @@ int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run,
     }
     if (lds_tab > MCBTE_LDS_TABLE_BYTES || lds_tab > t0->max_lds) return MCBTE_EINVAL;
     lp.lds_tab = lds_tab;
-    if (mode == 2 || mode == 3) {   // sensitivity replay: the per-bin sums take the place of the tallies
+    if (ft & FT_WIDE) {             // wide workgroups: the FP32 tally fills the LDS, tables stay in HBM
+        lp.lds_tab = 0;
+        lp.tally_lds = 1;
+        lp.lds = (size_t)(lds_tally / 2);
+        if ((int64_t)lp.lds > t0->max_lds) return MCBTE_EINVAL;
+    } else if (mode == 2 || mode == 3) {   // sensitivity replay: the per-bin sums take the place of the tallies
         const int64_t bins = 8 * t0->info.n_bins;
         if (lds_tab + bins > t0->max_lds) return MCBTE_EINVAL;
         lp.tally_lds = 0;
@@ -565,8 +574,9 @@ int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run,
         lp.tally_lds = (lds_tally <= MCBTE_LDS_TALLY_BYTES && lds_tab + lds_tally <= t0->max_lds) ? 1 : 0;
         lp.lds = (size_t)(lds_tab + (lp.tally_lds ? lds_tally : 0));
     }
-    lp.block = run->block > 0 ? run->block : 256;
-    if (lp.block % 64 != 0 || lp.block > 256) return MCBTE_EINVAL;
+    const int max_block = (ft & FT_WIDE) ? 1024 : 256;
+    lp.block = run->block > 0 ? run->block : max_block;
+    if (lp.block % 64 != 0 || lp.block > max_block) return MCBTE_EINVAL;
     lp.refill = run->refill > 0 ? run->refill : 4;
     if (run->grid > 0) {
         lp.grid = run->grid;
@@ -590,8 +600,16 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     DeviceGuard g(t->device);
     if (!g.ok) return MCBTE_EHIP;
     LaunchPlan lp;
-    // the plain kernel has neither a state buffer nor an event log compiled in
-    const int ft = (state || run->event_log) ? (FT_STATE | FT_LOG) : 0;
+    // the plain kernel has neither a state buffer nor an event log compiled in; an FP32 trace whose
+    // FP64 tally is too large for the LDS copy but whose FP32 tally fits runs wide workgroups
+    int ft = (state || run->event_log) ? (FT_STATE | FT_LOG) : 0;
+    if (ft == 0 && run->precision == 32) {
+        const int64_t t64 = t->info.n_cells * t->info.n_cols * (int64_t)t->host_view.det.ncomp * 8;
+        const int64_t M = t->info.n_modes;
+        const int64_t tab = ((M * 8 + 15) & ~int64_t(15)) + 2 * ((M * 4 + 15) & ~int64_t(15));
+        const bool fits64 = t64 <= MCBTE_LDS_TALLY_BYTES && tab + t64 <= t->max_lds;
+        if (!fits64 && t64 / 2 <= t->max_lds) ft = FT_WIDE;
+    }
     const int rc = plan_launch(&t, 1, run, 0, ft, lp);
     if (rc != MCBTE_OK) return rc;
     LaunchArgs a;
@@ -726,9 +744,10 @@ int mcbte_autotune(const mcbte_tables* const* ts, int32_t n_inst, const int64_t*
     int status = MCBTE_OK;
     int best = -1;
     double best_ms = 0.0;
+    static const int kBlocks[6] = {64, 128, 192, 256, 512, 1024};
     for (int c = 0; c < MCBTE_TUNE_CANDIDATES && status == MCBTE_OK; ++c) {
         mcbte_run r = *base;
-        r.block = 64 * (1 + c / 6);
+        r.block = kBlocks[c / 6];
         r.refill = 1 << (c % 6);
         auto go = [&]() {
             return n_inst == 1 ? mcbte_trace(ts[0], &r, 0, np[0], nullptr, tallies[0], stream)
@@ -763,7 +782,7 @@ int mcbte_autotune(const mcbte_tables* const* ts, int32_t n_inst, const int64_t*
     if (status != MCBTE_OK) return status;
     if (best < 0) return MCBTE_EINVAL;
     *out = *base;
-    out->block = 64 * (1 + best / 6);
+    out->block = kBlocks[best / 6];
     out->refill = 1 << (best % 6);
     return MCBTE_OK;
 }

@@ -292,11 +292,13 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
 struct TallyCtx {
     double* lds;     // compact per-workgroup copy (ncomp components per cell-column) or NULL
     double* glob;    // raw sums in the tally buffer, 4 components per cell-column
+    float* lds32;    // compact per-workgroup FP32 copy (wide workgroups) or NULL
 };
 
 __device__ __forceinline__ void tadd(const TallyCtx& tc, const DevDet& D, int64_t cc, int q, double val)
 {
-    if (tc.lds) atomicAdd(tc.lds + cc * D.ncomp + D.slot[q], val);
+    if (tc.lds32) atomicAdd(tc.lds32 + cc * D.ncomp + D.slot[q], (float)val);
+    else if (tc.lds) atomicAdd(tc.lds + cc * D.ncomp + D.slot[q], val);
     else if (tc.glob) atomicAdd(tc.glob + cc * 4 + q, val);
 }
 
@@ -1094,6 +1096,20 @@ __device__ __forceinline__ Tabs<R> stage_tables(const DevTab& T, unsigned char* 
 
 __device__ __forceinline__ int64_t lds_tally_size(const DevTab& T) { return T.det.n_cells * T.det.n_cols * T.det.ncomp; }
 
+// the FP32 copy of a wide workgroup into the FP64 sums
+__device__ __forceinline__ void flush_lds_tally32(const DevTab& T, const float* s_tally, double* glob)
+{
+    const int64_t n = lds_tally_size(T);
+    const int nc = T.det.ncomp;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const float v = s_tally[i];
+        if (v != 0.0f) {
+            const int64_t cc = i / nc;
+            atomicAdd(glob + cc * 4 + T.det.comp[i - cc * nc], (double)v);
+        }
+    }
+}
+
 __device__ __forceinline__ void flush_lds_tally(const DevTab& T, double* s_tally, double* glob)
 {
     const int64_t n = lds_tally_size(T);
@@ -1163,22 +1179,29 @@ __device__ __forceinline__ void end_particle(const Part<R>& p, int transient, do
 // AK = 1 (likelihood ratio) or 2 (pathwise): the sensitivity replay of the same particles: no
 // tallies; the per-bin sums go to LDS and then to a.adj; the work counter lives after the sums.
 template <typename R, int TK, int AK, int FT>
-__global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
+__global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const DevTab& T = tabs[0];
-    const Tabs<R> tb = stage_tables<R>(T, smem);
+    constexpr bool WIDE = (FT & FT_WIDE) != 0;
+    const Tabs<R> tb = WIDE ? Tabs<R>{T.thr_rel, Geo<R>::v(T), Geo<R>::tau(T)} : stage_tables<R>(T, smem);
     double* s_tally = (double*)(smem + a.lds_tab_bytes);
+    float* s_tally32 = (float*)smem;
     constexpr bool ADJ = AK != 0;
     if (ADJ) {
         for (int i = threadIdx.x; i < T.n_bins; i += blockDim.x) s_tally[i] = 0.0;
+    } else if (WIDE) {
+        const int64_t n = lds_tally_size(T);
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s_tally32[i] = 0.0f;
     } else if (a.tally_lds) {
         const int64_t n = lds_tally_size(T);
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s_tally[i] = 0.0;
     }
     __syncthreads();
-    const TallyCtx tc = ADJ ? TallyCtx{nullptr, nullptr}
-                            : TallyCtx{a.tally_lds ? s_tally : nullptr, (double*)(a.tally + MCBTE_TALLY_HEADER_BYTES)};
+    double* const gsum = (double*)(a.tally + MCBTE_TALLY_HEADER_BYTES);
+    const TallyCtx tc = ADJ ? TallyCtx{nullptr, nullptr, nullptr}
+                            : (WIDE ? TallyCtx{nullptr, gsum, s_tally32}
+                                    : TallyCtx{a.tally_lds ? s_tally : nullptr, gsum, nullptr});
     unsigned long long* counter = ADJ ? (unsigned long long*)(a.adj + T.n_bins + 2)
                                       : (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET);
     const int lane = threadIdx.x & 63;
@@ -1255,9 +1278,12 @@ __global__ void __launch_bounds__(256) k_trace_solo(const DevTab* __restrict__ t
         return;
     }
     flush_lane_stats(a.tally, cnt, mom);
-    if (a.tally_lds) {
+    if (WIDE) {
         __syncthreads();
-        flush_lds_tally(T, s_tally, (double*)(a.tally + MCBTE_TALLY_HEADER_BYTES));
+        flush_lds_tally32(T, s_tally32, gsum);
+    } else if (a.tally_lds) {
+        __syncthreads();
+        flush_lds_tally(T, s_tally, gsum);
     }
 }
 
@@ -1322,7 +1348,8 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
         if (last > a.inst_n[inst]) last = a.inst_n[inst];
         const unsigned long long n = (unsigned long long)(last - first);
         const uint32_t inst_id = a.inst_ids[inst];
-        const TallyCtx tc{a.tally_lds ? s_tally : nullptr, (double*)(a.tallies[inst] + MCBTE_TALLY_HEADER_BYTES)};
+        const TallyCtx tc{a.tally_lds ? s_tally : nullptr, (double*)(a.tallies[inst] + MCBTE_TALLY_HEADER_BYTES),
+                          nullptr};
         Part<R> p;
         Stream st{0u, 0u, 0u, 0u, 0u};
         LogRow lg{nullptr, 0, 2};
@@ -1417,7 +1444,8 @@ static void ensure_lds_limit(const void* fn, size_t lds)
 }
 
 // the kernel of a launch: mode 0 trace, 1 batched trace, 2 likelihood-ratio replay, 3 pathwise
-// replay; ft the optional features (FT_STATE | FT_LOG: a state buffer and/or an event log)
+// replay; ft the optional features (FT_STATE | FT_LOG: a state buffer and/or an event log;
+// FT_WIDE: FP32 trace with the tally in LDS in FP32)
 template <typename R, int TK>
 static const void* pick_kernel(int mode, int ft)
 {
@@ -1425,6 +1453,9 @@ static const void* pick_kernel(int mode, int ft)
     if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, 0>;
     if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, 0>;
     if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG>;
+    if constexpr (std::is_same<R, float>::value) {
+        if (ft & FT_WIDE) return (const void*)k_trace_solo<R, TK, 0, FT_WIDE>;
+    }
     return (const void*)k_trace_solo<R, TK, 0, 0>;
 }
 

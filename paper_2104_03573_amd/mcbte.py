@@ -261,12 +261,13 @@ def trace_batch(tables: list, n_particles, instance_ids, tallies: list, run: Run
                                                         C.c_void_p(queue.data_ptr()), _stream(stream)))
 
 
-TUNE_CANDIDATES = 24
+TUNE_CANDIDATES = 36
+TUNE_BLOCKS = (64, 128, 192, 256, 512, 1024)
 
 
 def tune_candidate(c: int) -> tuple[int, int]:
     """(block, refill) of autotuner candidate c."""
-    return 64 * (1 + c // 6), 1 << (c % 6)
+    return TUNE_BLOCKS[c // 6], 1 << (c % 6)
 
 
 def autotune(tables: list, n_particles, instance_ids, tallies: list, queue, base: Run, n_probe: int,

@@ -258,3 +258,26 @@ def test_fp32_long_flights_in_pore_lattice_against_fp64_oracle(lam, spec):
     assert abs(hits[0] - hits[1]) <= 0.01 * hits[1] + 5
     assert c["escaped"] == 0 and c["cap_end"] == 0
     assert abs(got["kappa"] - ref["kappa"]) < 3.0 * ref["kappa_sigma"]
+
+
+def test_fp32_transient_wide_kernel_against_fp64_oracle():
+    """The transient bump with its full snapshot detector (100 bins x 200 times, too large for a
+    per-workgroup FP64 copy): the FP32 kernel sums it per workgroup in FP32 in LDS.  Each particle
+    adds its sign once per measurement time, so the total of every snapshot equals the oracle's
+    exactly, and every cell agrees within two particles moved to a neighbouring bin by FP32
+    rounding (a particle adds s to T and s v Omega_z to q_z of one bin per time)."""
+    M = _pkg()
+    w = W.transient_bump(N=20000)
+    got = M.run(w, precision=32)
+    ref = _oracle_full(w)
+    rg = np.asarray(got["raw"])
+    rr = np.asarray(ref["raw"]).reshape(rg.shape)          # (bins, times, components)
+    Tg, Tr = rg[..., 0], rr[..., 0]
+    qg, qr = rg[..., 3], rr[..., 3]
+    _say(f"[transient fp32] max |dT| {np.abs(Tg - Tr).max():.3g} of {np.abs(Tr).max():.3g}; "
+         f"max |dq| {np.abs(qg - qr).max():.3g} of {np.abs(qr).max():.3g}")
+    assert got["counts"]["particles"] == ref["counts"]["particles"]
+    assert np.array_equal(Tg.sum(axis=0), Tr.sum(axis=0))
+    vmax = float(np.max(w["modes"]["v"]))
+    assert np.abs(Tg - Tr).max() <= 4.0
+    assert np.abs(qg - qr).max() <= 4.0 * vmax
