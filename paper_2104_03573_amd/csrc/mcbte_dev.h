@@ -6,6 +6,7 @@
 #define MCBTE_DEV_MAX_PORES 8
 #define MCBTE_LDS_TABLE_BYTES (48 * 1024)   // mode tables staged in LDS (thresholds + v + tau)
 #define MCBTE_LDS_TALLY_BYTES (40 * 1024)   // per-workgroup tally privatisation budget
+#define MCBTE_LDS_GUIDE_BYTES 1024           // guide of the relaxation draw (256 packed bounds)
 #define MCBTE_TALLY_HEADER_BYTES 256
 #define MCBTE_TALLY_COUNTER_OFFSET 192
 #define MCBTE_PATH_MAX 16                    // flights per particle the pathwise replay holds
@@ -80,6 +81,7 @@ struct DevTab {
     const double* t_meas64;
     const float* t_meas32;
     const int32_t* bin_of;       // frequency bin of each mode (sensitivity parameters)
+    const uint32_t* rel_guide;   // 256 packed search bounds of the relaxation draw, or NULL
     int32_t n_bins;
     int32_t pad2;
     DevGeom g;

@@ -445,6 +445,22 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         add(t->t_meas.data(), 8 * t->t_meas.size());
         add(tm32.data(), 4 * tm32.size());
         add(t->bin_of.data(), 4 * (size_t)M);
+        // guide of the relaxation draw: entry b packs the number of thresholds <= b 2^56 (low 16
+        // bits) and <= (b + 1) 2^56 (high 16 bits), the bounds of the draw for keys K with top
+        // byte b (the threshold search then only runs between them); tables of more than 65535
+        // rows search the whole table
+        std::vector<uint32_t> guide(256, 0u);
+        if (M <= 65535) {
+            auto count_le = [&](uint64_t K) {
+                return (uint32_t)(std::upper_bound(t->thr_rel.begin(), t->thr_rel.end(), K) - t->thr_rel.begin());
+            };
+            for (int b = 0; b < 256; ++b) {
+                const uint32_t lo = count_le((uint64_t)b << 56);
+                const uint32_t hi = b == 255 ? (uint32_t)M : count_le((uint64_t)(b + 1) << 56);
+                guide[b] = lo | (hi << 16);
+            }
+        }
+        add(guide.data(), 4 * 256);
         size_t total = 0;
         std::vector<size_t> off;
         for (auto& p : parts) {
@@ -473,6 +489,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         h.t_meas64 = (const double*)dptr(13);
         h.t_meas32 = (const float*)dptr(14);
         h.bin_of = (const int32_t*)dptr(15);
+        h.rel_guide = M <= 65535 ? (const uint32_t*)dptr(16) : nullptr;
         parts[0].first = &h;
         for (size_t i = 0; i < parts.size(); ++i) {
             if (parts[i].second == 0) continue;
@@ -554,7 +571,8 @@ int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run,
     int64_t lds_tab = 0, lds_tally = 0;
     for (int i = 0; i < n_inst; ++i) {
         const int64_t M = ts[i]->info.n_modes;
-        lds_tab = std::max<int64_t>(lds_tab, ((M * 8 + 15) & ~int64_t(15)) + 2 * ((M * rb + 15) & ~int64_t(15)));
+        lds_tab = std::max<int64_t>(lds_tab, ((M * 8 + 15) & ~int64_t(15)) + 2 * ((M * rb + 15) & ~int64_t(15)) +
+                                                 MCBTE_LDS_GUIDE_BYTES);
         lds_tally = std::max<int64_t>(lds_tally, ts[i]->info.n_cells * ts[i]->info.n_cols *
                                                      (int64_t)ts[i]->host_view.det.ncomp * 8);
     }
@@ -606,7 +624,7 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     if (ft == 0 && run->precision == 32) {
         const int64_t t64 = t->info.n_cells * t->info.n_cols * (int64_t)t->host_view.det.ncomp * 8;
         const int64_t M = t->info.n_modes;
-        const int64_t tab = ((M * 8 + 15) & ~int64_t(15)) + 2 * ((M * 4 + 15) & ~int64_t(15));
+        const int64_t tab = ((M * 8 + 15) & ~int64_t(15)) + 2 * ((M * 4 + 15) & ~int64_t(15)) + MCBTE_LDS_GUIDE_BYTES;
         const bool fits64 = t64 <= MCBTE_LDS_TALLY_BYTES && tab + t64 <= t->max_lds;
         if (!fits64 && t64 / 2 <= t->max_lds) ft = FT_WIDE;
     }

@@ -146,6 +146,21 @@ __device__ __forceinline__ int cdf_pick(const uint64_t* thr, int n, int64_t last
     return lo < n ? lo : (int)last;
 }
 
+// the same choice as cdf_pick for a non-decreasing table, searching only between the bounds the
+// guide gives for the key's top byte (guide[b] = count(thr <= b 2^56) | count(thr <= (b+1) 2^56) << 16)
+__device__ __forceinline__ int cdf_pick_guided(const uint64_t* thr, const uint32_t* guide, int n, int64_t last,
+                                               uint64_t K)
+{
+    const uint32_t g = guide[(uint32_t)(K >> 56)];
+    int lo = (int)(g & 0xFFFFu), hi = (int)(g >> 16);          // count(thr <= K) lies in [lo, hi]
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (thr[mid] <= K) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < n ? lo : (int)last;
+}
+
 template <typename R> struct Part {
     R x[3], o[3];
     R t, dtr;            // time, remaining free-flight time
@@ -494,6 +509,7 @@ struct Tabs {
     const uint64_t* thr_rel;   // LDS
     const R* v;                // LDS
     const R* tau;              // LDS
+    const uint32_t* guide;     // LDS: bounds of the relaxation draw, or NULL (search the whole table)
 };
 
 // Pathwise sensitivity state of one particle (replay form).  A free flight of mode m covers
@@ -836,7 +852,8 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
         if (relax) {
             // three-phonon relaxation: frequency from the post-scattering distribution
             // (weights C/tau), isotropic direction, new free flight, sign kept
-            p.m = cdf_pick(tb.thr_rel, T.M, T.last_rel, key64(w0.x, w0.y));
+            p.m = tb.guide ? cdf_pick_guided(tb.thr_rel, tb.guide, T.M, T.last_rel, key64(w0.x, w0.y))
+                           : cdf_pick(tb.thr_rel, T.M, T.last_rel, key64(w0.x, w0.y));
             dir_iso(u1, u2, p.o);
             p.dtr = -tb.tau[p.m] * r_log(R(1) - unif<R>(w0.z, w0.w));
             lg.put(EV_RELAX, 0, p.m);
@@ -1084,6 +1101,7 @@ __device__ __forceinline__ Tabs<R> stage_tables(const DevTab& T, unsigned char* 
     uint64_t* s_thr = (uint64_t*)smem;
     R* s_v = (R*)(smem + align16((int64_t)M * 8));
     R* s_tau = (R*)(smem + align16((int64_t)M * 8) + align16((int64_t)M * sizeof(R)));
+    uint32_t* s_guide = (uint32_t*)(smem + align16((int64_t)M * 8) + 2 * align16((int64_t)M * sizeof(R)));
     const R* gv = Geo<R>::v(T);
     const R* gt = Geo<R>::tau(T);
     for (int i = threadIdx.x; i < M; i += blockDim.x) {
@@ -1091,7 +1109,9 @@ __device__ __forceinline__ Tabs<R> stage_tables(const DevTab& T, unsigned char* 
         s_v[i] = gv[i];
         s_tau[i] = gt[i];
     }
-    return Tabs<R>{s_thr, s_v, s_tau};
+    if (T.rel_guide)
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) s_guide[i] = T.rel_guide[i];
+    return Tabs<R>{s_thr, s_v, s_tau, T.rel_guide ? s_guide : nullptr};
 }
 
 __device__ __forceinline__ int64_t lds_tally_size(const DevTab& T) { return T.det.n_cells * T.det.n_cols * T.det.ncomp; }
@@ -1184,7 +1204,7 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
     extern __shared__ __align__(16) unsigned char smem[];
     const DevTab& T = tabs[0];
     constexpr bool WIDE = (FT & FT_WIDE) != 0;
-    const Tabs<R> tb = WIDE ? Tabs<R>{T.thr_rel, Geo<R>::v(T), Geo<R>::tau(T)} : stage_tables<R>(T, smem);
+    const Tabs<R> tb = WIDE ? Tabs<R>{T.thr_rel, Geo<R>::v(T), Geo<R>::tau(T), T.rel_guide} : stage_tables<R>(T, smem);
     double* s_tally = (double*)(smem + a.lds_tab_bytes);
     float* s_tally32 = (float*)smem;
     constexpr bool ADJ = AK != 0;
