@@ -281,3 +281,55 @@ def test_fp32_transient_wide_kernel_against_fp64_oracle():
     vmax = float(np.max(w["modes"]["v"]))
     assert np.abs(Tg - Tr).max() <= 4.0
     assert np.abs(qg - qr).max() <= 4.0 * vmax
+
+
+def test_fp64_parity_across_the_2_32_particle_id():
+    """Particle ids past 2^32 use the second counter word of every Philox draw: a range crossing
+    that boundary gives the oracle's event sequences bit for bit."""
+    M = _pkg()
+    first = (1 << 32) - 100
+    for w in (W.film(N=200), W.porous_cell(N=200)):
+        got = M.run(w, n=200, first_pid=first, precision=64, n_log=200, log_stride=96)
+        ref = oracle.trace(w, n=200, first_pid=first, n_log=200, log_stride=96, threads=THREADS)
+        assert _first_log_mismatch(got["log"], ref["log"]) is None
+        assert np.array_equal(got["counts_raw"], ref["counts"])
+        # and the two halves are different particles: ids below and above 2^32 do not repeat
+        low = M.run(w, n=100, first_pid=first, precision=64)
+        high = M.run(w, n=100, first_pid=first + 100, precision=64)
+        assert not np.array_equal(low["raw"], high["raw"])
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 65, 257])
+def test_fp64_ragged_and_empty_ranges(n):
+    """Empty, single-particle and wave-ragged launches: counts equal the oracle's exactly (an
+    empty launch leaves the tally untouched)."""
+    M = _pkg()
+    w = W.film(N=max(n, 1))
+    got = M.run(w, n=n, precision=64, block=64, refill=1)
+    if n == 0:
+        assert got["counts"]["particles"] == 0 and not np.any(got["raw"])
+        return
+    ref = oracle.trace(w, n=n, threads=1)
+    assert np.array_equal(got["counts_raw"], ref["counts"])
+    assert np.abs(got["raw"] - ref["raw"].reshape(got["raw"].shape)).max() <= 1e-10 * np.abs(ref["raw"]).max()
+
+
+def test_batched_launch_with_an_empty_instance():
+    """An instance with no particles inside a batch contributes nothing and disturbs no other."""
+    import torch
+    M = _pkg()
+    counts = (5000, 0, 7000)
+    ws = [W.film(N=max(n, 1), d=d) for n, d in zip(counts, (2e-8, 1e-7, 5e-7))]
+    for i, w in enumerate(ws):
+        w["instance"] = 11 + i
+    tabs = [M.Tables(w) for w in ws]
+    tallies = [t.new_tally() for t in tabs]
+    queue = torch.zeros(M.batch_queue_bytes(len(ws)), dtype=torch.uint8, device="cuda")
+    M.trace_batch(tabs, list(counts), [w["instance"] for w in ws], tallies, M.make_run(int(ws[0]["seed"]), 64), queue)
+    for n, w, t, tl in zip(counts, ws, tabs, tallies):
+        b = M.tally(t, tl)
+        if n == 0:
+            assert b["counts"]["particles"] == 0 and not np.any(t.raw(tl))
+            continue
+        s = M.run(w, precision=64, tables=t)
+        assert np.array_equal(b["counts_raw"], s["counts_raw"])
