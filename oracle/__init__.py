@@ -107,7 +107,7 @@ def lib():
         L.orc_tally_segment.argtypes = [p, p, p, C.c_double, C.c_int32, C.c_double, p]
         L.orc_emit_state.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, p, p]
         L.orc_emit_state.restype = C.c_int
-        L.orc_adjoint.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, C.c_int32, p, p, p, p, p]
+        L.orc_adjoint.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, C.c_int32, C.c_double, p, p, p, p, p]
         L.orc_adjoint.restype = C.c_int
         L.orc_next_boundary.argtypes = [p, p, p, p]
         L.orc_next_boundary.restype = C.c_double
@@ -374,18 +374,31 @@ def run_batches(w: dict, n_batches: int, n: int | None = None, threads: int = 8)
         return list(ex.map(one, range(n_batches)))
 
 
+def default_lambda_split(w: dict) -> float:
+    """The geometric length below which a mode's flights take the local pathwise form: the smallest
+    bounded extent of the cell or pore diameter (infinite for the unbounded bulk)."""
+    g = w["geometry"]
+    sizes = [float(L) for L, u in zip(g["L"], g["unbounded"]) if not u]
+    sizes += [2.0 * float(c[2]) for c in g["cylinders"]]
+    return min(sizes) if sizes else math.inf
+
+
 def adjoint(w: dict, n: int | None = None, first_pid: int = 0, threads: int = 1, n_batches: int = 1,
-            tables: Tables | None = None, estimator: str = "score", per_particle: bool = False) -> dict:
+            tables: Tables | None = None, estimator: str = "score", per_particle: bool = False,
+            lambda_split: float | None = None) -> dict:
     """Estimate of dkappa / dln tau_i (per frequency bin) over particles [first_pid, first_pid + n),
     with batch-mean standard errors when n_batches > 1.  estimator "score": likelihood ratios of
     the free flights (Eq. time_to_scat) and of the relaxation draws (Eq. norm_post_coll);
     "pathwise": the flights differentiated through their lengths (tangents carried along the
-    trajectory), the draws by their likelihood ratios.
+    trajectory), the draws by their likelihood ratios; "local": for modes with v tau <= lambda_split
+    (default: the smallest bounded extent or pore diameter) a flight's own flux through its length
+    and what follows by its likelihood ratio, other flights and the draws as for "score".
 
     dkappa/dln tau_i = -E_tot / (V_solid gradT_s n) * (sparse_i + P_i B), the same normalisation
     as kappa = -E_tot / (V_solid gradT_s n) * sum_p F_p (section 3.6, Eq. flux_x_steady).
     per_particle (pathwise only): also return each particle's tangent terms per bin, unscaled."""
-    kind = {"score": 0, "pathwise": 1}[estimator]
+    kind = {"score": 0, "pathwise": 1, "local": 2}[estimator]
+    split = default_lambda_split(w) if lambda_split is None else float(lambda_split)
     tb = tables or Tables(w)
     n = w["problem"]["N"] if n is None else int(n)
     inst = int(w.get("instance", 0))
@@ -399,7 +412,7 @@ def adjoint(w: dict, n: int | None = None, first_pid: int = 0, threads: int = 1,
         F = np.zeros(hi - lo)
         pp = np.zeros((hi - lo, tb.n_bins)) if per_particle else None
         bad = np.zeros(1, dtype=np.int64)
-        rc = lib().orc_adjoint(tb.h, int(w["seed"]), inst, lo, hi - lo, kind, _ptr(sp), _ptr(de), _ptr(F),
+        rc = lib().orc_adjoint(tb.h, int(w["seed"]), inst, lo, hi - lo, kind, split, _ptr(sp), _ptr(de), _ptr(F),
                                _ptr(pp) if pp is not None else None, _ptr(bad))
         if rc != 0:
             raise ValueError(f"oracle adjoint failed with status {rc}")

@@ -700,7 +700,7 @@ int orc_emit_state(const orc_tables* t, uint64_t seed, uint32_t instance, int64_
      - a relaxation draw of row j from p_j = (C_j/tau_j) / sum_r (C_r/tau_r) (Eq. norm_post_coll):
        d ln p_j / d ln tau_i = -[bin(j) = i] + P_i, with F after the draw; the P_i part is the same
        for every draw and is summed into one number B per run. */
-typedef struct { int32_t bin, dense; double g, F_before; } adj_ev;
+typedef struct { int32_t bin, dense; double g, F_before, c0; } adj_ev;   /* adds c0 + g (F - F_before) */
 
 /* Pathwise (reparametrisation) form: a free flight of mode m covers the distance
    L = v_m tau_m E with E = -ln(1 - u) fixed by its random numbers, so dL / dln tau_m = L.  With
@@ -722,6 +722,8 @@ typedef struct {
     int32_t sign;               /* the particle's sign s */
     double dline;               /* straight distance since the last tangent update (periodic
                                    transfers do not interrupt the line) */
+    int local;                  /* 1: local pathwise form for modes with v tau <= lambda_split */
+    double lambda_split;
 } adj_list;
 
 static void adj_push(adj_list* al, int32_t bin, double g, double F_before, int dense)
@@ -740,6 +742,25 @@ static void adj_push(adj_list* al, int32_t bin, double g, double F_before, int d
     e->g = g;
     e->F_before = F_before;
     e->dense = dense;
+    e->c0 = 0.0;
+}
+
+/* Local pathwise form, for a mode whose mean free path v tau is at most lambda_split: a flight's
+   own flux A(T) = s (x_end - x_start)_a is continuous in its time T and depends on tau only through
+   T = tau E, so its part is the pathwise s L Omega_a (L = v T, Omega the direction of its last
+   segment; zero for a flight cut short, whose end does not move); what follows the flight, B(T),
+   keeps the likelihood ratio (T/tau - 1) (F - F at the flight's end) of an uncensored flight (zero
+   after a cut-short one, which ends the particle).  A per-mode choice of the form keeps the sum
+   unbiased: each flight time is differentiated one way. */
+static int adj_local(const adj_list* al, const orc_tables* t, int32_t m)
+{
+    return al && al->local && t->v[m] * t->tau[m] <= al->lambda_split;
+}
+
+static void adj_push_local(adj_list* al, int32_t bin, double c0, double g, double F_before)
+{
+    adj_push(al, bin, g, F_before, 0);
+    if (al && !al->failed) al->ev[al->n - 1].c0 = c0;
 }
 
 /* a new flight of mode row m, distance L: its tangent; every earlier one has spent its b and
@@ -878,7 +899,10 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
     double F0 = 0.0;           /* flux contribution at the start of the current flight */
     if (al) al->sign = p.s;
     tan_birth(al, t->bin[p.m], t->v[p.m] * p.dtr);
-#define CENSORED() adj_push(al, t->bin[p.m], (dtr0 - p.dtr) / t->tau[p.m], F0, 0)
+#define CENSORED()                                                                                \
+    do {                                                                                          \
+        if (!adj_local(al, t, p.m)) adj_push(al, t->bin[p.m], (dtr0 - p.dtr) / t->tau[p.m], F0, 0); \
+    } while (0)
     for (;;) {
         if ((int64_t)p.k >= pr->max_events) {
             counts[ORC_C_CAP_END] += 1;
@@ -971,7 +995,11 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
                distribution, isotropic direction, sign kept; termination after N_scat^max */
             p.nrel += 1;
             counts[ORC_C_RELAX] += 1;
-            adj_push(al, t->bin[p.m], dtr0 / t->tau[p.m] - 1.0, F0, 0);   /* the flight that ended */
+            if (adj_local(al, t, p.m))                                         /* the flight that ended */
+                adj_push_local(al, t->bin[p.m], (double)p.s * (t->v[p.m] * dtr0) * p.o[sa],
+                               dtr0 / t->tau[p.m] - 1.0, p.cq);
+            else
+                adj_push(al, t->bin[p.m], dtr0 / t->tau[p.m] - 1.0, F0, 0);
             if (pr->n_scat_max > 0 && p.nrel >= pr->n_scat_max) {
                 counts[ORC_C_NSCAT_END] += 1;
                 LOG(ORC_EV_NSCAT_END, 0, p.m);
@@ -1088,9 +1116,10 @@ int orc_trace(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t fir
 }
 
 int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t first_pid, int64_t n,
-                int32_t kind, double* sparse, double* dense, double* F_out, double* pp_out, int64_t* n_bad)
+                int32_t kind, double lambda_split, double* sparse, double* dense, double* F_out, double* pp_out,
+                int64_t* n_bad)
 {
-    if (!t || n < 0 || first_pid < 0 || t->pr.transient || (kind != 0 && kind != 1)) return E_INVAL;
+    if (!t || n < 0 || first_pid < 0 || t->pr.transient || kind < 0 || kind > 2) return E_INVAL;
     int cap = 2;
     for (int a = 0; a < 3; ++a) cap += t->det.n[a];
     double* pts = (double*)malloc(sizeof(double) * cap);
@@ -1100,7 +1129,9 @@ int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t f
     double mom[ORC_N_MOMENTS] = {0};
     adj_list al;
     memset(&al, 0, sizeof(al));
-    al.pathwise = kind;
+    al.pathwise = kind == 1;
+    al.local = kind == 2;
+    al.lambda_split = lambda_split;
     const int sa = t->pr.score_axis;
     for (int64_t i = 0; i < n; ++i) {
         al.n = 0;
@@ -1111,7 +1142,7 @@ int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t f
         if (al.failed) break;
         for (int64_t e = 0; e < al.n; ++e) {
             const double after = F - al.ev[e].F_before;
-            sparse[al.ev[e].bin] += al.ev[e].g * after;
+            sparse[al.ev[e].bin] += al.ev[e].c0 + al.ev[e].g * after;
             if (al.ev[e].dense) *dense += after;
         }
         for (int64_t e = 0; e < al.nt; ++e) {

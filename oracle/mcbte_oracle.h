@@ -73,12 +73,15 @@ int orc_trace(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t fir
 /* sensitivity sums for dkappa / dln tau_i over particles first_pid .. first_pid + n - 1 (steady
    runs).  kind 0, score function: sparse[n_bins] += sum_e g_e (F - F_before_e) over the flights and
    relaxation draws; kind 1, pathwise: sparse[n_bins] += the tangent terms s dx_a of the flights plus
-   the draw terms.  Both: *dense += sum over relaxation draws of (F - F_before).  F_out[i]
-   (optional) = flux contribution of each particle; pp_out[i * n_bins + bin] (optional, kind 1)
-   += the tangent terms of particle i.  A tangent term that is not finite is left out of the sums
-   and counted in *n_bad (optional). */
+   the draw terms; kind 2, local pathwise: for modes with v tau <= lambda_split a flight ended by a
+   relaxation adds s L Omega_a + (T/tau - 1) (F - F at its end) and one cut short adds nothing,
+   other modes and the draws as for kind 0.  All: *dense += sum over relaxation draws of
+   (F - F_before).  F_out[i] (optional) = flux contribution of each particle; pp_out[i * n_bins +
+   bin] (optional, kind 1) += the tangent terms of particle i.  A tangent term that is not finite is
+   left out of the sums and counted in *n_bad (optional). */
 int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t first_pid, int64_t n,
-                int32_t kind, double* sparse, double* dense, double* F_out, double* pp_out, int64_t* n_bad);
+                int32_t kind, double lambda_split, double* sparse, double* dense, double* F_out, double* pp_out,
+                int64_t* n_bad);
 
 /* building blocks exposed for the pins */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
