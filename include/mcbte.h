@@ -59,6 +59,7 @@ extern "C" {
 /* Sensitivity estimators (mcbte_adjoint). */
 #define MCBTE_SENS_SCORE 0          /* likelihood ratio: any steady problem                     */
 #define MCBTE_SENS_PATHWISE 1       /* flight lengths differentiated along the trajectory       */
+#define MCBTE_SENS_LOCAL 2          /* a flight's own flux through its length, the rest scored   */
 #define MCBTE_PATHWISE_MAX_FLIGHTS 16 /* pathwise: n_scat_max must lie in [1, this]             */
 #define MCBTE_N_COUNTS 16
 
@@ -296,6 +297,13 @@ int mcbte_autotune(const mcbte_tables* const* tables, int32_t n_inst, const int6
    reflections, so for mean free paths beyond the pore size the terms can overflow; a particle
    term that is not finite is left out of the sums and counted, and mcbte_adjoint_finalize then
    reports MCBTE_ERANGE.
+   MCBTE_SENS_LOCAL: for modes whose mean free path v tau is at most lambda_split (<= 0: the
+   smallest bounded extent of the cell or pore diameter; every mode of the unbounded bulk), a
+   flight ended by a relaxation adds its own flux's change s L Omega_a (L = v tau E stretched with
+   E fixed, Omega its last direction) plus (T/tau - 1) times the flux score that follows it, a flight
+   cut short adds nothing; longer modes and the relaxation draws as for MCBTE_SENS_SCORE.  Unbiased
+   everywhere (the own flux is continuous in the flight time, what follows is scored), with lower
+   variance where short flights carry the flux; nothing is propagated, so no growth.
    mcbte_adjoint replays particles first_pid .. first_pid + n - 1 with the same random streams
    (run->seed, run->instance, run->precision as the forward trace that filled particle_F, a
    device array of n doubles) and adds the sums to `adj` (device, adj_doubles doubles, zeroed by
@@ -303,8 +311,8 @@ int mcbte_autotune(const mcbte_tables* const* tables, int32_t n_inst, const int6
    adj[n_bins] the relaxation-draw sum B, adj[n_bins + 1] the count of terms left out as not
    finite, adj[n_bins + 2] library scratch.  Async on `stream`.  Errors: MCBTE_EINVAL (transient run, event log set, unknown
    estimator, n_scat_max outside the pathwise range), MCBTE_ENODEV, MCBTE_EHIP. */
-int mcbte_adjoint(const mcbte_tables* tables, const mcbte_run* run, int32_t estimator, int64_t first_pid, int64_t n,
-                  const double* particle_F, double* adj, void* stream);
+int mcbte_adjoint(const mcbte_tables* tables, const mcbte_run* run, int32_t estimator, double lambda_split,
+                  int64_t first_pid, int64_t n, const double* particle_F, double* adj, void* stream);
 
 /* Copy `adj` to the host (synchronizes `stream`) and write dkappa / dln tau_i, i < n_bins, into
    host_out (n_out >= n_bins) for n_particles traced particles, with the normalisation of kappa

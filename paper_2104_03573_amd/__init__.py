@@ -4,12 +4,12 @@ The public Python surface mirrors include/mcbte.h: build_tables, free_tables, ta
 table_export, state_bytes, emit, trace, batch_queue_bytes, trace_batch, adjoint, adjoint_finalize, tally,
 strerror.
 """
-from .mcbte import (COUNT_NAMES, ESTIMATORS, EXPORTED, LIB_PATH, SENS_PATHWISE, SENS_SCORE, MCBTEError, Tables,
+from .mcbte import (COUNT_NAMES, ESTIMATORS, EXPORTED, LIB_PATH, SENS_LOCAL, SENS_PATHWISE, SENS_SCORE, MCBTEError, Tables,
                     adjoint, adjoint_finalize,
                     batch_queue_bytes, build_tables, emit, free_tables, lib, make_run, run, sensitivities,
                     state_bytes, strerror, table_export, table_info, tally, trace, trace_batch)
 
-__all__ = ["COUNT_NAMES", "ESTIMATORS", "EXPORTED", "LIB_PATH", "SENS_PATHWISE", "SENS_SCORE", "MCBTEError", "Tables",
+__all__ = ["COUNT_NAMES", "ESTIMATORS", "EXPORTED", "LIB_PATH", "SENS_LOCAL", "SENS_PATHWISE", "SENS_SCORE", "MCBTEError", "Tables",
            "adjoint", "adjoint_finalize",
            "batch_queue_bytes", "build_tables", "emit", "free_tables", "lib", "make_run", "run", "sensitivities",
            "state_bytes", "strerror", "table_export", "table_info", "tally", "trace", "trace_batch"]

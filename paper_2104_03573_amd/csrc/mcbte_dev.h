@@ -116,6 +116,7 @@ struct LaunchArgs {
     // sensitivity replay
     double* particle_F;          // per-particle flux score (written by the trace, read by the replay)
     double* adj;                 // n_bins sums, the relaxation-draw sum B, then a work counter
+    double lambda_split;         // local pathwise replay: modes with v tau <= this take that form
 };
 
 }  // namespace mcbte

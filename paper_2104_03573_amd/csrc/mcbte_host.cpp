@@ -583,7 +583,7 @@ int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run,
         lp.tally_lds = 1;
         lp.lds = (size_t)(lds_tally / 2);
         if ((int64_t)lp.lds > t0->max_lds) return MCBTE_EINVAL;
-    } else if (mode == 2 || mode == 3) {   // sensitivity replay: the per-bin sums take the place of the tallies
+    } else if (mode >= 2 && mode <= 4) {   // sensitivity replay: the per-bin sums take the place of the tallies
         const int64_t bins = 8 * t0->info.n_bins;
         if (lds_tab + bins > t0->max_lds) return MCBTE_EINVAL;
         lp.tally_lds = 0;
@@ -807,13 +807,14 @@ int mcbte_autotune(const mcbte_tables* const* ts, int32_t n_inst, const int64_t*
 
 static_assert(MCBTE_PATH_MAX == MCBTE_PATHWISE_MAX_FLIGHTS, "pathwise capacity");
 
-int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator, int64_t first_pid, int64_t n,
-                  const double* particle_F, double* adj, void* stream)
+int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator, double lambda_split,
+                  int64_t first_pid, int64_t n, const double* particle_F, double* adj, void* stream)
 {
     if (!t || !run || !particle_F || !adj || n < 0 || first_pid < 0) return MCBTE_EINVAL;
     if (run->precision != 32 && run->precision != 64) return MCBTE_EINVAL;
     if (run->event_log) return MCBTE_EINVAL;
-    if (estimator != MCBTE_SENS_SCORE && estimator != MCBTE_SENS_PATHWISE) return MCBTE_EINVAL;
+    if (estimator != MCBTE_SENS_SCORE && estimator != MCBTE_SENS_PATHWISE && estimator != MCBTE_SENS_LOCAL)
+        return MCBTE_EINVAL;
     if (t->device < 0 || !t->d_tab) return MCBTE_ENODEV;
     if (t->prob.transient) return MCBTE_EINVAL;
     if (estimator == MCBTE_SENS_PATHWISE &&
@@ -822,11 +823,13 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
     if (n == 0) return MCBTE_OK;
     DeviceGuard g(t->device);
     if (!g.ok) return MCBTE_EHIP;
-    const int mode = estimator == MCBTE_SENS_PATHWISE ? 3 : 2;
+    const int mode = estimator == MCBTE_SENS_PATHWISE ? 3 : (estimator == MCBTE_SENS_LOCAL ? 4 : 2);
     const int ft = 0;
     LaunchPlan lp;
     const int rc = plan_launch(&t, 1, run, mode, ft, lp);
     if (rc != MCBTE_OK) return rc;
+    // the replay keeps its per-bin sums in LDS after the tables
+    if ((int64_t)lp.lds < lp.lds_tab + 8 * t->info.n_bins) return MCBTE_EINVAL;
     LaunchArgs a;
     std::memset(&a, 0, sizeof(a));
     a.tabs = t->d_tab;
@@ -841,6 +844,16 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
     a.particle_F = const_cast<double*>(particle_F);
     a.adj = adj;
+    // local form: the split given, else the smallest bounded extent or pore diameter (every mode
+    // of the unbounded bulk)
+    double split = lambda_split;
+    if (!(split > 0.0)) {
+        split = INFINITY;
+        for (int ax = 0; ax < 3; ++ax)
+            if (!t->geom.unbounded[ax]) split = std::min(split, t->geom.L[ax]);
+        for (int c = 0; c < t->geom.n_pores; ++c) split = std::min(split, 2.0 * t->geom.pore[c].r);
+    }
+    a.lambda_split = split;
     hipStream_t s = (hipStream_t)stream;
     // the work counter is the last word of the caller's buffer
     if (launch_zero_u64((unsigned long long*)(adj + t->info.n_bins + 2), s) != hipSuccess) return MCBTE_EHIP;

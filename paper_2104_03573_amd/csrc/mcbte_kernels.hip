@@ -501,8 +501,20 @@ struct AdjCtx {
     double F_total;          // this particle's F from the forward trace
     double dense;            // per-lane sum of (F_total - F) over relaxation draws
     uint32_t bad;            // pathwise terms that were not finite
+    double split;            // local pathwise form: modes with v tau <= split
     __device__ __forceinline__ void add(int bin, double g, double after) { atomicAdd(bins + bin, g * after); }
 };
+
+// Local pathwise form (AK = 3), for a mode whose mean free path v tau is at most the split: a
+// flight's own flux depends on tau only through its length L = v tau E and changes by s L Omega_a
+// (Omega the direction of its last segment) if it ended in a relaxation, by nothing if it was cut
+// short; what follows it keeps the likelihood ratio (T/tau - 1) (F_total - F at the flight's end).
+// Longer modes take the likelihood-ratio form of AK = 1.
+template <int AK>
+__device__ __forceinline__ bool local_form(const DevTab& T, int m, const AdjCtx& adj)
+{
+    return AK == 3 && T.v64[m] * T.tau64[m] <= adj.split;
+}
 
 template <typename R>
 struct Tabs {
@@ -657,7 +669,7 @@ struct PathCtx {
 };
 
 // Advance particle p by one segment; returns true when the particle has ended.
-// AK: 0 trace, 1 likelihood-ratio replay, 2 pathwise replay.
+// AK: 0 trace, 1 likelihood-ratio replay, 2 pathwise replay, 3 local pathwise replay.
 template <typename R, int TK, int AK, int FT>
 __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const TallyCtx& tc, const Stream& st,
                                        Part<R>& p, LaneCounts& cnt, LogRow& lg, bool& coop, AdjCtx& adj,
@@ -667,7 +679,8 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
     if ((int64_t)p.k >= T.max_events) {
         ++cnt.c[9];
         lg.put(EV_CAP, 0, p.m);
-        if (AK == 1) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+        if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
+            adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
         if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
         return true;
     }
@@ -739,7 +752,8 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
     if (ev == 2) {
         ++cnt.c[7];
         lg.put(EV_TIMEOUT, 0, p.m);
-        if (AK == 1) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+        if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
+            adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
         if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
         return true;
     }
@@ -779,7 +793,8 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
     if (escaped) {
         ++cnt.c[10];
         lg.put(EV_ESCAPE, 0, p.m);
-        if (AK == 1) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+        if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
+            adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
         if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
         return true;
     }
@@ -788,7 +803,14 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
     if (relax) {
         p.nrel += 1;
         ++cnt.c[2];
-        if (AK == 1) adj.add(T.bin_of[p.m], (double)p.dtr0 / T.tau64[p.m] - 1.0, adj.F_total - p.F0);
+        if (AK == 3 && local_form<AK>(T, p.m, adj)) {
+            const int sa = T.score_axis;
+            const double os = (double)(sa == 0 ? p.o[0] : (sa == 1 ? p.o[1] : p.o[2]));
+            atomicAdd(adj.bins + T.bin_of[p.m], (double)p.s * (T.v64[p.m] * (double)p.dtr0) * os);
+            adj.add(T.bin_of[p.m], (double)p.dtr0 / T.tau64[p.m] - 1.0, adj.F_total - p.cq);
+        } else if (AK == 1 || AK == 3) {
+            adj.add(T.bin_of[p.m], (double)p.dtr0 / T.tau64[p.m] - 1.0, adj.F_total - p.F0);
+        }
         if (T.n_scat_max > 0 && p.nrel >= T.n_scat_max) {
             ++cnt.c[8];
             lg.put(EV_NSCAT, 0, p.m);
@@ -815,7 +837,8 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
         if (btype == 1) {
             ++cnt.c[6];
             lg.put(EV_ABSORB, hit, p.m);
-            if (AK == 1) adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+            if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
+            adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
             if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
             return true;
         }
@@ -1196,7 +1219,7 @@ __device__ __forceinline__ void end_particle(const Part<R>& p, int transient, do
 }
 
 // AK = 0: the forward trace (tallies, counters, moments, optional per-particle flux score F).
-// AK = 1 (likelihood ratio) or 2 (pathwise): the sensitivity replay of the same particles: no
+// AK = 1 (likelihood ratio), 2 (pathwise) or 3 (local pathwise): the sensitivity replay of the same particles: no
 // tallies; the per-bin sums go to LDS and then to a.adj; the work counter lives after the sums.
 template <typename R, int TK, int AK, int FT>
 __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
@@ -1234,7 +1257,7 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
     for (int q = 0; q < 12; ++q) cnt.c[q] = 0;
     double mom[4] = {0.0, 0.0, 0.0, 0.0};
     LogRow lg{nullptr, 0, a.log_stride};
-    AdjCtx adj{s_tally, 0.0, 0.0, 0u};
+    AdjCtx adj{s_tally, 0.0, 0.0, 0u, a.lambda_split};
     PathCtx<R> pc;
     pc.nt = 0;
     int64_t my_pid = 0;
@@ -1373,7 +1396,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
         Part<R> p;
         Stream st{0u, 0u, 0u, 0u, 0u};
         LogRow lg{nullptr, 0, 2};
-        AdjCtx adj{nullptr, 0.0, 0.0, 0u};
+        AdjCtx adj{nullptr, 0.0, 0.0, 0u, 0.0};
         PathCtx<R> pc;            // unused by the trace
         pc.nt = 0;
         bool alive = false;
@@ -1464,7 +1487,7 @@ static void ensure_lds_limit(const void* fn, size_t lds)
 }
 
 // the kernel of a launch: mode 0 trace, 1 batched trace, 2 likelihood-ratio replay, 3 pathwise
-// replay; ft the optional features (FT_STATE | FT_LOG: a state buffer and/or an event log;
+// replay, 4 local pathwise replay; ft the optional features (FT_STATE | FT_LOG: a state buffer and/or an event log;
 // FT_WIDE: FP32 trace with the tally in LDS in FP32)
 template <typename R, int TK>
 static const void* pick_kernel(int mode, int ft)
@@ -1472,6 +1495,7 @@ static const void* pick_kernel(int mode, int ft)
     if (mode == 1) return (const void*)k_trace_batch<R, TK>;
     if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, 0>;
     if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, 0>;
+    if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, 0>;
     if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG>;
     if constexpr (std::is_same<R, float>::value) {
         if (ft & FT_WIDE) return (const void*)k_trace_solo<R, TK, 0, FT_WIDE>;

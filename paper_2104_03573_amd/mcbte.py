@@ -116,7 +116,7 @@ def lib():
                                      C.POINTER(p), p, C.POINTER(Run), C.c_int64, C.c_int32, C.POINTER(Run),
                                      C.POINTER(C.c_double), C.c_int32, p]
         L.mcbte_autotune.restype = C.c_int
-        L.mcbte_adjoint.argtypes = [p, C.POINTER(Run), C.c_int32, C.c_int64, C.c_int64, p, p, p]
+        L.mcbte_adjoint.argtypes = [p, C.POINTER(Run), C.c_int32, C.c_double, C.c_int64, C.c_int64, p, p, p]
         L.mcbte_adjoint.restype = C.c_int
         L.mcbte_adjoint_finalize.argtypes = [p, p, C.c_int64, C.POINTER(C.c_double), C.c_int64, p]
         L.mcbte_adjoint_finalize.restype = C.c_int
@@ -303,11 +303,13 @@ def tune(w, precision: int = 32, n_probe: int = 1 << 18, reps: int = 3, tables=N
 
 SENS_SCORE = 0
 SENS_PATHWISE = 1
-ESTIMATORS = {"score": SENS_SCORE, "pathwise": SENS_PATHWISE}
+SENS_LOCAL = 2
+ESTIMATORS = {"score": SENS_SCORE, "pathwise": SENS_PATHWISE, "local": SENS_LOCAL}
 
 
-def adjoint(t: "Tables", run: Run, estimator: int, first_pid: int, n: int, particle_F, adj, stream=None):
-    _check("mcbte_adjoint", lib().mcbte_adjoint(t.h, C.byref(run), estimator, first_pid, n,
+def adjoint(t: "Tables", run: Run, estimator: int, first_pid: int, n: int, particle_F, adj, stream=None,
+            lambda_split: float = 0.0):
+    _check("mcbte_adjoint", lib().mcbte_adjoint(t.h, C.byref(run), estimator, float(lambda_split), first_pid, n,
                                                 C.c_void_p(particle_F.data_ptr()), C.c_void_p(adj.data_ptr()),
                                                 _stream(stream)))
 
@@ -399,10 +401,11 @@ def run(w: dict, n: int | None = None, first_pid: int = 0, precision: int = 32, 
 
 
 def sensitivities(w: dict, n: int | None = None, first_pid: int = 0, precision: int = 32, device: int = 0,
-                  tables: Tables | None = None, estimator: str = "score", **launch) -> dict:
+                  tables: Tables | None = None, estimator: str = "score", lambda_split: float = 0.0,
+                  **launch) -> dict:
     """Forward trace (recording each particle's flux score) then the replay that accumulates the
-    sensitivity sums of `estimator` ("score" or "pathwise"): kappa and dkappa / dln tau_i per
-    frequency bin."""
+    sensitivity sums of `estimator` ("score", "pathwise" or "local"; lambda_split <= 0: the
+    library's default split for "local"): kappa and dkappa / dln tau_i per frequency bin."""
     import torch
     t = tables or Tables(w, device)
     n = w["problem"]["N"] if n is None else int(n)
@@ -413,7 +416,7 @@ def sensitivities(w: dict, n: int | None = None, first_pid: int = 0, precision: 
     trace(t, r, first_pid, n, None, tl)
     adj = torch.zeros(t.info["adj_doubles"], dtype=torch.float64, device=dev)
     r2 = make_run(int(w["seed"]), precision, int(w.get("instance", 0)), **launch)
-    adjoint(t, r2, ESTIMATORS[estimator], first_pid, n, F, adj)
+    adjoint(t, r2, ESTIMATORS[estimator], first_pid, n, F, adj, lambda_split=lambda_split)
     out = tally(t, tl, with_arrays=False)
     out["dkappa_dlntau"] = adjoint_finalize(t, adj, n)
     out["F"] = F.cpu().numpy()

@@ -31,7 +31,8 @@ CASES = {
 PATHWISE_CASES = [k for k in CASES if k != "gray_slab"]
 
 
-@pytest.mark.parametrize("name,estimator", [(k, "score") for k in CASES] + [(k, "pathwise") for k in PATHWISE_CASES])
+@pytest.mark.parametrize("name,estimator", [(k, "score") for k in CASES] + [(k, "pathwise") for k in PATHWISE_CASES]
+                         + [(k, "local") for k in CASES])
 def test_fp64_sensitivities_match_oracle(name, estimator):
     """Same particles, same events: the per-particle flux scores agree to rounding (the device
     logarithm and trigonometric functions may differ from the host's in the last place) and the
@@ -61,7 +62,7 @@ def test_pathwise_rejects_unbounded_flights():
         M.sensitivities(w, precision=64, estimator="pathwise")
 
 
-@pytest.mark.parametrize("estimator", ["score", "pathwise"])
+@pytest.mark.parametrize("estimator", ["score", "pathwise", "local"])
 def test_fp32_sensitivities_match_oracle_statistically(estimator):
     """FP32 trajectories: the sensitivities of the film agree with the FP64 oracle's on the same
     particles within the oracle's batch errors (groups of 10 bins and the total).  The score form
@@ -81,7 +82,7 @@ def test_fp32_sensitivities_match_oracle_statistically(estimator):
     se_tot = pb.sum(1).std(ddof=1) / math.sqrt(32)
     _say(f"[adjoint fp32] film {estimator}: total {g.sum():.4f} / {r.sum():.4f} (se {se_tot:.4f}), "
          f"max |z| over groups {z.max():.3f}")
-    if estimator == "score":
+    if estimator != "pathwise":
         assert z.max() < 1.0
         assert abs(g.sum() - r.sum()) < 0.1 * se_tot + 1e-12
     else:
@@ -96,9 +97,10 @@ def _scaled(w, bins_set, factor):
     return w2
 
 
-def test_sensitivities_against_crn_finite_differences():
+@pytest.mark.parametrize("estimator", ["score", "local"])
+def test_sensitivities_against_crn_finite_differences(estimator):
     """The porous cell (25 % pore, diffuse pore wall, periodic cell): for groups of frequency
-    bins, the likelihood-ratio estimate agrees with central differences of kappa at
+    bins, the estimate (likelihood ratio, or local pathwise) agrees with central differences of kappa at
     tau (1 +- 0.05) computed with the same random numbers, within 3 combined standard errors
     (both from 16 batches). The central difference is biased by O(eps^2) of the second
     derivative, well below the tolerance; the test is only meaningful if the standard error is a
@@ -114,7 +116,7 @@ def test_sensitivities_against_crn_finite_differences():
     t0 = M.Tables(W.with_(base, **{"problem.N": n_per}))
     for b in range(nb_batches):
         w = W.with_(base, **{"problem.N": n_per, "seed": int(base["seed"]) + 7919 * b})
-        s = M.sensitivities(w, precision=32, tables=t0, estimator="score")
+        s = M.sensitivities(w, precision=32, tables=t0, estimator=estimator)
         for gi, grp in enumerate(groups):
             sf[b, gi] = s["dkappa_dlntau"][list(grp)].sum()
             kp = M.run(_scaled(w, grp, 1.0 + eps), precision=32)["kappa"]
@@ -122,7 +124,7 @@ def test_sensitivities_against_crn_finite_differences():
             fd[b, gi] = (kp - km) / (2.0 * eps)
     m_sf, m_fd = sf.mean(0), fd.mean(0)
     se = np.sqrt(sf.var(0, ddof=1) / nb_batches + fd.var(0, ddof=1) / nb_batches)
-    _say(f"[adjoint vs CRN FD] score: estimate {np.round(m_sf, 4)} FD {np.round(m_fd, 4)} "
+    _say(f"[adjoint vs CRN FD] {estimator}: estimate {np.round(m_sf, 4)} FD {np.round(m_fd, 4)} "
          f"se {np.round(se, 4)} (estimate alone {np.round(sf.std(0, ddof=1) / 4, 4)})")
     assert np.all(np.abs(m_sf - m_fd) < 3.0 * se)
     # the low-frequency group carries little of kappa: agreement only; the others must be resolved
@@ -134,7 +136,7 @@ def _gray_pore(lam, N, specularity=0.0):
                    **{"problem.format": 2})
 
 
-@pytest.mark.parametrize("estimator", ["score", "pathwise"])
+@pytest.mark.parametrize("estimator", ["score", "pathwise", "local"])
 def test_short_mean_free_path_pore_against_crn_finite_difference(estimator):
     """Gray medium with a 50 nm mean free path in the porous cell (pore radius 141 nm), where the
     pathwise form is well behaved: both estimates of dkappa / dln tau agree with the central
@@ -171,8 +173,8 @@ def test_pathwise_overflow_is_reported():
     assert e.value.status == M.mcbte.ERANGE
 
 
-@pytest.mark.parametrize("case,estimator", [("porous_cell", "score"), ("film_capped", "score"),
-                                            ("film_capped", "pathwise")])
+@pytest.mark.parametrize("case,estimator", [("porous_cell", "score"), ("porous_cell", "local"),
+                                            ("film_capped", "score"), ("film_capped", "pathwise")])
 def test_rademacher_projection_against_crn_finite_difference(case, estimator):
     """One +- pair over all bins at once: tau_i -> tau_i (1 +- e xi_i) with random signs xi_i gives
     (kappa+ - kappa-) / 2e = sum_i xi_i dkappa / dln tau_i + O(e^2), compared with the estimate on
