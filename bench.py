@@ -128,28 +128,29 @@ def cpu_baseline(w: dict, seconds: float, threads: int) -> dict:
                       f"{threads} threads over contiguous particle ranges)"}
 
 
-def launch_config(args, tabs, w, M, precision):
+def launch_config(args, tabs, w, M, precision, probe_cap: int = 4_000_000, reps: int = 3):
     """Block and refill: the caller's, else the autotuner's (outside the timed region)."""
     if args.block or args.refill or args.no_autotune:
-        return {"block": args.block or 256, "refill": args.refill or 4, "autotuned": False}
+        return {"block": args.block or 0, "refill": args.refill or 4, "autotuned": False}
     ws = w if isinstance(w, list) else [w]
     total = sum(x["problem"]["N"] for x in ws)
     t0 = time.perf_counter()
-    # the calibration runs the whole batch up to 4e6 particles: a smaller probe shifts the balance
-    # between the steady part and the tail of a launch, and with it the best shape
-    r = M.tune(w, precision=precision, n_probe=max(1, min(total, 4_000_000)), reps=3, tables=tabs)
+    # the calibration runs the whole batch up to probe_cap particles: a smaller probe shifts the
+    # balance between the steady part and the tail of a launch, and with it the best shape
+    r = M.tune(w, precision=precision, n_probe=max(1, min(total, probe_cap)), reps=reps, tables=tabs)
     return {"block": r["block"], "refill": r["refill"], "autotuned": True,
             "tune_s": round(time.perf_counter() - t0, 3),
             "tune_candidates": M.TUNE_CANDIDATES}
 
 
-def measure(args, w, M, torch, precision: int, steps: int, warmup: int, streams: int = 1):
+def measure(args, w, M, torch, precision: int, steps: int, warmup: int, streams: int = 1,
+            probe_cap: int = 4_000_000, reps: int = 3):
     """Trace `steps` batches of workload w (a new seed per step) after `warmup` untimed ones;
     HIP events bracket each trace launch on its stream."""
     t0 = time.perf_counter()
     tabs = M.Tables(w, 0)
     t_tables = time.perf_counter() - t0
-    lc = launch_config(args, tabs, w, M, precision)
+    lc = launch_config(args, tabs, w, M, precision, probe_cap, reps)
     N = w["problem"]["N"]
     ncomp = bin(w["detectors"]["mask"]).count("1")
     S = max(1, streams)
@@ -215,12 +216,13 @@ def measure(args, w, M, torch, precision: int, steps: int, warmup: int, streams:
     return out
 
 
-def measure_batched(args, ws, M, torch, precision: int, steps: int, warmup: int):
+def measure_batched(args, ws, M, torch, precision: int, steps: int, warmup: int, probe_cap: int = 4_000_000,
+                    reps: int = 3):
     """The batched form: every step traces all instances in one persistent launch."""
     t0 = time.perf_counter()
     tabs = [M.Tables(w, 0) for w in ws]
     t_tables = time.perf_counter() - t0
-    lc = launch_config(args, tabs, ws, M, precision)
+    lc = launch_config(args, tabs, ws, M, precision, probe_cap, reps)
     tallies = [t.new_tally() for t in tabs]
     queue = torch.zeros(M.batch_queue_bytes(len(ws)), dtype=torch.uint8, device="cuda")
     ns = [w["problem"]["N"] for w in ws]
@@ -260,38 +262,46 @@ def measure_batched(args, ws, M, torch, precision: int, steps: int, warmup: int)
             "table_build_s": t_tables, "launch": lc}
 
 
-def measure_sensitivity(args, w, M, torch, estimator: str, steps: int):
-    """Forward trace recording each particle's flux score, then the sensitivity replay (1000
-    frequency bins); both launches timed with HIP events."""
+def measure_sensitivity(args, w, M, torch, estimators, steps: int):
+    """Forward trace recording each particle's flux score, then the sensitivity replay of each
+    estimator (1000 frequency bins), every launch timed with HIP events; the spread of the summed
+    sensitivity over the steps is reported per estimator."""
     tabs = M.Tables(w, 0)
-    lc = launch_config(args, tabs, w, M, 32)
+    lc = launch_config(args, tabs, w, M, 32, 1_000_000, 1)
     N = w["problem"]["N"]
     F = torch.zeros(N, dtype=torch.float64, device="cuda")
     tl = tabs.new_tally()
     adj = torch.zeros(tabs.info["adj_doubles"], dtype=torch.float64, device="cuda")
-    fwd, rep, flights = [], [], 0
-    est = M.ESTIMATORS[estimator]
+    fwd, flights = [], 0
+    rep = {e: [] for e in estimators}
+    total = {e: [] for e in estimators}
     for i in range(steps + 1):
         tl.zero_()
-        adj.zero_()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         seed = int(w["seed"]) + i
-        ev[0].record()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         M.trace(tabs, M.make_run(seed, 32, block=lc["block"], refill=lc["refill"], particle_F=F), 0, N, None, tl)
-        ev[1].record()
-        M.adjoint(tabs, M.make_run(seed, 32, block=lc["block"], refill=lc["refill"]), est, 0, N, F, adj)
-        ev[2].record()
+        e1.record()
         res = M.tally(tabs, tl, with_arrays=False)
-        M.adjoint_finalize(tabs, adj, N)
-        if i == 0:
-            continue                      # warm-up
-        fwd.append(ev[0].elapsed_time(ev[1]))
-        rep.append(ev[1].elapsed_time(ev[2]))
-        flights += res["counts"]["flights"]
-    return {"estimator": estimator, "forward_ms": fwd, "replay_ms": rep,
-            "flights_per_s_forward": flights / (sum(fwd) / 1e3),
-            "flights_per_s_with_sensitivities": flights / ((sum(fwd) + sum(rep)) / 1e3),
-            "bins": int(tabs.info["n_bins"]), "launch": lc}
+        if i > 0:
+            fwd.append(e0.elapsed_time(e1))
+            flights += res["counts"]["flights"]
+        for est in estimators:
+            adj.zero_()
+            r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            r0.record()
+            M.adjoint(tabs, M.make_run(seed, 32, block=lc["block"], refill=lc["refill"]), M.ESTIMATORS[est], 0, N, F,
+                      adj)
+            r1.record()
+            d = M.adjoint_finalize(tabs, adj, N)
+            if i > 0:                                     # the first step warms up
+                rep[est].append(r0.elapsed_time(r1))
+                total[est].append(float(d.sum()))
+    out = {"forward_ms": fwd, "flights_per_s_forward": flights / (sum(fwd) / 1e3),
+           "bins": int(tabs.info["n_bins"]), "launch": lc}
+    for est in estimators:
+        out[est] = {"replay_ms": rep[est], "sum_dkappa_dlntau_per_step": total[est]}
+    return out
 
 
 def main():
@@ -397,16 +407,18 @@ def other_forms(args, M, torch) -> dict:
     forms = {}
     plan = [("gray_slab_fp64", "gray_slab", 64, 10), ("film_fp64", "film", 64, 5),
             ("transient_fp32", "transient", 32, 3), ("porous_cell_fp32", "porous_cell", 32, 3)]
+    # each configuration is tuned on at most 1e6 particles with one timed launch per candidate
+    # (the calibration stays outside the timed steps but inside the run's few minutes)
     for key, name, prec, steps in plan:
         w, wname = workload(name, 1.0)
         print(f"[bench] form {key}: {wname}", file=sys.stderr, flush=True)
-        forms[key] = _brief(measure(args, w, M, torch, prec, steps, 1), wname, prec)
+        forms[key] = _brief(measure(args, w, M, torch, prec, steps, 1, 1, 1_000_000, 1), wname, prec)
     ws, wname = workload("sweep", 1.0)
     print(f"[bench] form batched_sweep_fp32: {wname}", file=sys.stderr, flush=True)
-    forms["batched_sweep_fp32"] = _brief(measure_batched(args, ws, M, torch, 32, 3, 1), wname, 32)
+    forms["batched_sweep_fp32"] = _brief(measure_batched(args, ws, M, torch, 32, 3, 1, 8_000_000, 1), wname, 32)
     w, wname = workload("porous_cell", 1.0)
     print(f"[bench] form sensitivities: {wname}", file=sys.stderr, flush=True)
-    sens = measure_sensitivity(args, w, M, torch, "score", 2)
+    sens = measure_sensitivity(args, w, M, torch, ("score", "local"), 2)
     sens["workload"] = wname
     forms["porous_cell_sensitivities_fp32"] = sens
     return forms
