@@ -1,5 +1,9 @@
 """kappa_eff as a differentiable function of the relaxation times of the frequency bins.
 
+The gradient comes from the sensitivity replay; the default estimator is the local pathwise form
+(each flight's own flux differentiated through its length, what follows it by its likelihood ratio),
+"score" and "pathwise" are the alternatives (see mcbte_adjoint in include/mcbte.h).
+
 The forward pass traces the problem with the rows of bin i given relaxation time tau[i] (the
 relaxation time depends on the frequency only, so the rows of the branches that share a bin share
 it) and returns kappa_eff; it also runs the sensitivity replay of the same particles, and the
@@ -47,7 +51,7 @@ class KappaOfTau(torch.autograd.Function):
     tau's device."""
 
     @staticmethod
-    def forward(ctx, tau, w, n=None, precision=32, estimator="score", device=0):
+    def forward(ctx, tau, w, n=None, precision=32, estimator="local", device=0):
         t = tau.detach().to("cpu", torch.float64).numpy()
         out = sensitivities(with_tau_bins(w, t), n, precision=precision, device=device, estimator=estimator)
         grad = np.where(t > 0.0, out["dkappa_dlntau"] / np.where(t > 0.0, t, 1.0), 0.0)
@@ -62,5 +66,5 @@ class KappaOfTau(torch.autograd.Function):
 
 
 def kappa_of_tau(tau: torch.Tensor, w: dict, n: int | None = None, precision: int = 32,
-                 estimator: str = "score", device: int = 0) -> torch.Tensor:
+                 estimator: str = "local", device: int = 0) -> torch.Tensor:
     return KappaOfTau.apply(tau, w, n, precision, estimator, device)

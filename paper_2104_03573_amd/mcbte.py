@@ -401,7 +401,7 @@ def run(w: dict, n: int | None = None, first_pid: int = 0, precision: int = 32, 
 
 
 def sensitivities(w: dict, n: int | None = None, first_pid: int = 0, precision: int = 32, device: int = 0,
-                  tables: Tables | None = None, estimator: str = "score", lambda_split: float = 0.0,
+                  tables: Tables | None = None, estimator: str = "local", lambda_split: float = 0.0,
                   **launch) -> dict:
     """Forward trace (recording each particle's flux score) then the replay that accumulates the
     sensitivity sums of `estimator` ("score", "pathwise" or "local"; lambda_split <= 0: the
