@@ -413,6 +413,17 @@ def other_forms(args, M, torch) -> dict:
         w, wname = workload(name, 1.0)
         print(f"[bench] form {key}: {wname}", file=sys.stderr, flush=True)
         forms[key] = _brief(measure(args, w, M, torch, prec, steps, 1, 1, 1_000_000, 1), wname, prec)
+    # the pore cell's step ends with the few particles of the longest mean free paths walking
+    # through the lattice one segment at a time; a job of several batches overlaps one batch's
+    # tail with the next batch on a second stream (throughput by wall clock; the per-launch
+    # event times then include the overlap, so no roofline figure is given for it)
+    w, wname = workload("porous_cell", 1.0)
+    print(f"[bench] form porous_cell_fp32_two_streams: {wname}", file=sys.stderr, flush=True)
+    m2 = measure(args, w, M, torch, 32, 4, 2, 2, 1_000_000, 1)
+    forms["porous_cell_fp32_two_streams"] = {
+        "workload": wname, "precision": 32, "streams": 2, "steps": 4, "flights_per_s": m2["flights_per_s"],
+        "ms_per_step": m2["ms_per_step"], "launch": m2["launch"], "kappa_eff": m2.get("kappa_eff"),
+        "kappa_sigma": m2.get("kappa_sigma")}
     ws, wname = workload("sweep", 1.0)
     print(f"[bench] form batched_sweep_fp32: {wname}", file=sys.stderr, flush=True)
     forms["batched_sweep_fp32"] = _brief(measure_batched(args, ws, M, torch, 32, 3, 1, 8_000_000, 1), wname, 32)

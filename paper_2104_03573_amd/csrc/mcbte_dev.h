@@ -23,6 +23,14 @@ enum TallyKind : int32_t { TALLY_STEADY_ONE = 0, TALLY_STEADY_GRID = 1, TALLY_TR
 enum : int { FT_STATE = 1, FT_LOG = 2, FT_WIDE = 4 };
 
 // Geometry in the form the flight loop reads it (uniform across a launch; scalar loads).
+struct DevPore32 { float cx, cy, r; int32_t id; };
+struct DevPore64 { double cx, cy, r; int32_t id, pad; };
+
+// class of an adiabatic surface for the event choice: 0 diffuse (d <= 0), 1 specular (d >= 1),
+// 2 partly specular (0 < d < 1, decided by a key against the surface's threshold); each
+// precision classifies its own rounding of d
+enum : uint32_t { SURF_DIFFUSE = 0, SURF_SPECULAR = 1, SURF_PARTIAL = 2 };
+
 struct DevGeom {
     double L[3];
     int32_t unb[3];              // axis without faces
@@ -40,6 +48,14 @@ struct DevGeom {
     float L32[3];
     float pore_cx32[MCBTE_DEV_MAX_PORES], pore_cy32[MCBTE_DEV_MAX_PORES], pore_r32[MCBTE_DEV_MAX_PORES];
     float ngrad32[3];
+    // compact forms for the flight loop, read into registers once per launch: axis mask, and per
+    // precision ([0] FP32, [1] FP64) 4 bits per face id - 1 (type | class << 2) and 2 bits per
+    // pore (class); the pores again as one record each
+    uint32_t unb_mask;
+    uint32_t face_code[2];
+    uint32_t pore_cls[2];
+    DevPore32 pore32[MCBTE_DEV_MAX_PORES];
+    DevPore64 pore64[MCBTE_DEV_MAX_PORES];
 };
 
 struct DevDet {

@@ -34,6 +34,14 @@ const double kTwo64 = 18446744073709551616.0;
 const int kFaceAxis[6] = {1, 0, 1, 0, 2, 2};
 const int kFaceSide[6] = {0, 1, 1, 0, 0, 1};
 
+// event class of an adiabatic surface of specularity d, as the trajectories of precision R see d
+template <typename R>
+uint32_t surf_class(double d)
+{
+    const R r = (R)d;
+    return (r > R(0) && r < R(1)) ? SURF_PARTIAL : (r >= R(1) ? SURF_SPECULAR : SURF_DIFFUSE);
+}
+
 // cumulative distribution as 64-bit thresholds; returns the last positive-weight index (-1 if none)
 int64_t build_thresholds(const std::vector<double>& w, std::vector<uint64_t>& thr)
 {
@@ -375,7 +383,10 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         const double d = g.face[i].type == MCBTE_ADIABATIC ? g.face[i].data[0] : 0.0;
         dg.face_spec[i] = d;
         dg.face_thr[i] = (d > 0.0 && d < 1.0) ? (uint64_t)(d * kTwo64) : 0;
+        dg.face_code[0] |= ((uint32_t)dg.face_type[i] | surf_class<float>(d) << 2) << (4 * i);
+        dg.face_code[1] |= ((uint32_t)dg.face_type[i] | surf_class<double>(d) << 2) << (4 * i);
     }
+    for (int a = 0; a < 3; ++a) dg.unb_mask |= (uint32_t)dg.unb[a] << a;
     dg.n_pores = g.n_pores;
     for (int c = 0; c < g.n_pores; ++c) {
         const mcbte_pore& p = g.pore[c];
@@ -388,6 +399,10 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         dg.pore_spec[c] = p.specularity;
         dg.pore_thr[c] = (p.specularity > 0.0 && p.specularity < 1.0) ? (uint64_t)(p.specularity * kTwo64) : 0;
         dg.pore_id[c] = p.id;
+        dg.pore32[c] = DevPore32{(float)p.cx, (float)p.cy, (float)p.r, p.id};
+        dg.pore64[c] = DevPore64{p.cx, p.cy, p.r, p.id, 0};
+        dg.pore_cls[0] |= surf_class<float>(p.specularity) << (2 * c);
+        dg.pore_cls[1] |= surf_class<double>(p.specularity) << (2 * c);
     }
     DevDet& dd = h.det;
     int nc = 0;

@@ -116,6 +116,8 @@ template <> struct Geo<double> {
     static __device__ __forceinline__ double tmeas(const DevTab& t, int k) { return t.t_meas64[k]; }
     static __device__ __forceinline__ const double* v(const DevTab& t) { return t.v64; }
     static __device__ __forceinline__ const double* tau(const DevTab& t) { return t.tau64; }
+    static __device__ __forceinline__ const DevPore64& pore(const DevGeom& g, int i) { return g.pore64[i]; }
+    static constexpr int prec = 1;
 };
 template <> struct Geo<float> {
     static __device__ __forceinline__ float L(const DevGeom& g, int a) { return g.L32[a]; }
@@ -130,6 +132,8 @@ template <> struct Geo<float> {
     static __device__ __forceinline__ float tmeas(const DevTab& t, int k) { return t.t_meas32[k]; }
     static __device__ __forceinline__ const float* v(const DevTab& t) { return t.v32; }
     static __device__ __forceinline__ const float* tau(const DevTab& t) { return t.tau32; }
+    static __device__ __forceinline__ const DevPore32& pore(const DevGeom& g, int i) { return g.pore32[i]; }
+    static constexpr int prec = 0;
 };
 
 // first index j with K < thr[j] (thresholds non-decreasing), else `last`: a fixed number of
@@ -325,6 +329,24 @@ __device__ __forceinline__ void add4(const TallyCtx& tc, const DevDet& D, int64_
     if (mask & 2) tadd(tc, D, cc, 1, (double)(sg * (l * o[0])));
     if (mask & 4) tadd(tc, D, cc, 2, (double)(sg * (l * o[1])));
     if (mask & 8) tadd(tc, D, cc, 3, (double)(sg * (l * o[2])));
+}
+
+__device__ __forceinline__ void tadd_c(const TallyCtx& tc, int ncomp, uint32_t slots, int64_t cc, int q, double val)
+{
+    const int slot = (int)((slots >> (8 * q)) & 0xFFu);
+    if (tc.lds32) atomicAdd(tc.lds32 + cc * ncomp + slot, (float)val);
+    else if (tc.lds) atomicAdd(tc.lds + cc * ncomp + slot, val);
+    else if (tc.glob) atomicAdd(tc.glob + cc * 4 + q, val);
+}
+
+template <typename R>
+__device__ __forceinline__ void add4_c(const TallyCtx& tc, int mask, int ncomp, uint32_t slots, int64_t cc, R sg,
+                                       R l, R vm, const R o[3])
+{
+    if (mask & 1) tadd_c(tc, ncomp, slots, cc, 0, (double)(sg * r_div(l, vm)));
+    if (mask & 2) tadd_c(tc, ncomp, slots, cc, 1, (double)(sg * (l * o[0])));
+    if (mask & 4) tadd_c(tc, ncomp, slots, cc, 2, (double)(sg * (l * o[1])));
+    if (mask & 8) tadd_c(tc, ncomp, slots, cc, 3, (double)(sg * (l * o[2])));
 }
 
 // steady track-length estimator (Eqs. temp_steady, flux_x_steady) for the segment x0 + s o,
@@ -524,6 +546,50 @@ struct Tabs {
     const uint32_t* guide;     // LDS: bounds of the relaxation draw, or NULL (search the whole table)
 };
 
+// The launch-uniform values the flight loop reads, loaded once before it so that they stay in
+// registers instead of being fetched from the table block at every segment.
+template <typename R>
+struct Hot {
+    R L[3];
+    R t_max;
+    R coop_min;          // remaining free path above which a film-wall bounce turns cooperative
+    uint32_t unb;        // bit a: axis a has no faces
+    uint32_t face;       // 4 bits per face id - 1: type | class << 2
+    uint32_t pcls;       // 2 bits per pore: class
+    uint32_t det_slot;   // 8 bits per tally component: compact slot
+    int32_t det_mask, det_ncomp;
+    int32_t n_pores, max_events, n_scat_max, M, last_rel, transient, score_axis, coop_axis;
+};
+
+template <typename R>
+__device__ __forceinline__ Hot<R> load_hot(const DevTab& T)
+{
+    const DevGeom& g = T.g;
+    Hot<R> h;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) h.L[a] = Geo<R>::L(g, a);
+    h.t_max = (R)T.t_max;
+    h.coop_min = (R)T.coop_min_path;
+    h.unb = g.unb_mask;
+    h.face = g.face_code[Geo<R>::prec];
+    h.pcls = g.pore_cls[Geo<R>::prec];
+    uint32_t slots = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) slots |= ((uint32_t)T.det.slot[q] & 0xFFu) << (8 * q);
+    h.det_slot = slots;
+    h.det_mask = T.det.mask;
+    h.det_ncomp = T.det.ncomp;
+    h.n_pores = g.n_pores;
+    h.max_events = (int32_t)T.max_events;
+    h.n_scat_max = T.n_scat_max;
+    h.M = T.M;
+    h.last_rel = (int32_t)T.last_rel;
+    h.transient = T.transient;
+    h.score_axis = T.score_axis;
+    h.coop_axis = T.coop_axis;
+    return h;
+}
+
 // Pathwise sensitivity state of one particle (replay form).  A free flight of mode m covers
 // the distance L = v_m tau_m E with E fixed by its random numbers, so dL / dln tau_m = L.  With the
 // sequence of events held fixed, stretching a flight shifts what follows it, linearly.  At the
@@ -668,135 +734,156 @@ struct PathCtx {
     }
 };
 
-// Advance particle p by one segment; returns true when the particle has ended.
+// Advance particle p by one segment; returns true when the particle has ended.  With `chain`
+// set (the lane is the last one of its wave still tracing), segments that end in a transfer
+// through a periodic face, which leaves mode, direction and remaining flight as they were, are
+// followed by the next one in the same call, up to an event of another kind: the lone lane then
+// skips the wave-level work of the trace loop between them.  Lanes that share a wave take one
+// segment per call, so that a long chain of transfers in one lane does not hold up the others
+// (as do all lanes of the pathwise replay, whose state leaves no registers for the chain).
 // AK: 0 trace, 1 likelihood-ratio replay, 2 pathwise replay, 3 local pathwise replay.
 template <typename R, int TK, int AK, int FT>
-__device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const TallyCtx& tc, const Stream& st,
-                                       Part<R>& p, LaneCounts& cnt, LogRow& lg, bool& coop, AdjCtx& adj,
-                                       PathCtx<R>& pc)
+__device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const Tabs<R>& tb, const TallyCtx& tc,
+                                       const Stream& st, Part<R>& p, LaneCounts& cnt, LogRow& lg, bool& coop,
+                                       AdjCtx& adj, PathCtx<R>& pc, bool chain)
 {
     const DevGeom& g = T.g;
-    if ((int64_t)p.k >= T.max_events) {
-        ++cnt.c[9];
-        lg.put(EV_CAP, 0, p.m);
-        if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
-            adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
-        if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
-        return true;
-    }
     const R vm = tb.v[p.m];
-    const R ds = vm * p.dtr;
-    // nearest boundary along the ray: faces in id order, then pores; ties keep the lower id
-    R db = R(1) / R(0);
-    int hit = 0;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        const int a = face_axis(i), side = face_side(i);
-        if (g.unb[a]) continue;
-        const R oa = p.o[a];
-        const bool toward = side ? (oa > R(0)) : (oa < R(0));
-        if (toward) {
-            const R d = side ? r_div(Geo<R>::L(g, a) - p.x[a], oa) : r_div(R(0) - p.x[a], oa);
-            if (d < db) { db = d; hit = i + 1; }
-        }
-    }
-    for (int c = 0; c < g.n_pores; ++c) {
-        const R dx = p.x[0] - Geo<R>::cx(g, c), dy = p.x[1] - Geo<R>::cy(g, c);
-        const R qa = p.o[0] * p.o[0] + p.o[1] * p.o[1];
-        const R qb = dx * p.o[0] + dy * p.o[1];
-        const R rr = Geo<R>::r(g, c);
-        const R qc = dx * dx + dy * dy - rr * rr;
-        if (qb < R(0)) {
-            const R disc = qb * qb - qa * qc;
-            if (disc >= R(0)) {
-                const R d = (qc < R(0)) ? R(0) : r_div(qc, -qb + r_sqrt(disc));
-                if (d < db) { db = d; hit = g.pore_id[c]; }
-            }
-        }
-    }
-    // event: the time horizon first, then the boundary (segment (x0, x1]), then relaxation
-    const R dmin = db < ds ? db : ds;
-    const R tmax = (R)T.t_max;
-    int ev;             // 0 relax, 1 boundary, 2 time horizon
-    R d;
-    if (T.transient && vm * (tmax - p.t) <= dmin) { ev = 2; d = vm * (tmax - p.t); }
-    else if (db <= ds) { ev = 1; d = db; }
-    else { ev = 0; d = ds; }
-    const R dt = (ev == 0) ? p.dtr : (ev == 1 ? r_div(d, vm) : tmax - p.t);
-    const R t_end = (ev == 2) ? tmax : p.t + dt;
     const R sg = (R)p.s;
-    if (TK == TALLY_TRANSIENT) {
-        tally_snap(T, tc, p.x, p.o, p.t, t_end, vm, sg);
-    } else {
-        if (TK == TALLY_STEADY_ONE) {
-            if (d > R(0)) add4(tc, T.det, (int64_t)p.m, sg, d, vm, p.o);
-        } else {
-            tally_grid(T, tc, p.x, p.o, d, p.m, sg, vm);
+    int hit, pore, ev, fa, fs;
+    R pcx, pcy, pr;                      // centre and radius of the pore hit
+    uint32_t fcode;
+    for (;;) {
+        if (p.k >= (uint32_t)H.max_events) {
+            ++cnt.c[9];
+            lg.put(EV_CAP, 0, p.m);
+            if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
+                adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+            if (AK == 2) pc.flush(adj.bins, p.s, H.score_axis, adj.bad);
+            return true;
         }
-        const int sa = T.score_axis;
-        const R os = sa == 0 ? p.o[0] : (sa == 1 ? p.o[1] : p.o[2]);
-        p.cT += (double)(sg * r_div(d, vm));
-        p.cq += (double)(sg * (d * os));
-    }
-    ++cnt.c[1];
+        const R ds = vm * p.dtr;
+        // nearest boundary along the ray: faces in id order, then pores; ties keep the lower id
+        R db = R(1) / R(0);
+        hit = 0;
+        pore = -1;
+        pcx = R(0);
+        pcy = R(0);
+        pr = R(1);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) p.x[a] = p.x[a] + d * p.o[a];
-    p.t = t_end;
-    if (ev == 1) {
-        const R r = p.dtr - dt;
-        p.dtr = r > R(0) ? r : R(0);
-    } else {
-        p.dtr = R(0);
-    }
-    p.k += 1;
-    if (ev == 2) {
-        ++cnt.c[7];
-        lg.put(EV_TIMEOUT, 0, p.m);
-        if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
-            adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
-        if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
-        return true;
-    }
-    const bool on_face = (ev == 1) && hit <= 6;
-    const int fa = on_face ? face_axis(hit - 1) : -1;
-    const int fs = on_face ? face_side(hit - 1) : 0;
-    bool escaped = false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const R L = Geo<R>::L(g, a);
-        if (a == fa) p.x[a] = fs ? L : R(0);     // exactly on the wall
-        if (!g.unb[a] && (p.x[a] < R(-1e-9) * L || p.x[a] > L + R(1e-9) * L)) escaped = true;
-    }
-    if (AK == 2) {   // the segment's end, for the pathwise state
-        const R dl = pc.dline + d;
-        pc.dline = R(0);
-        if (ev == 0) {
-            pc.end_flight(p.o, dl, vm * p.dtr0, T.bin_of[p.m]);
-        } else if (ev == 1 && hit <= 6 && g.face_type[hit - 1] == 3) {
-            pc.dline = dl;
-        } else if (ev == 1) {
-            R nh[3] = {R(0), R(0), R(0)};
-            if (hit <= 6) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) nh[a] = a == fa ? R(1) : R(0);
-            } else {
-                for (int c = 0; c < g.n_pores; ++c)
-                    if (g.pore_id[c] == hit) {
-                        const R rr = Geo<R>::r(g, c);
-                        nh[0] = r_div(p.x[0] - Geo<R>::cx(g, c), rr);
-                        nh[1] = r_div(p.x[1] - Geo<R>::cy(g, c), rr);
-                    }
+        for (int i = 0; i < 6; ++i) {
+            const int a = face_axis(i), side = face_side(i);
+            if (H.unb & (1u << a)) continue;
+            const R oa = p.o[a];
+            const bool toward = side ? (oa > R(0)) : (oa < R(0));
+            if (toward) {
+                const R d = side ? r_div(H.L[a] - p.x[a], oa) : r_div(R(0) - p.x[a], oa);
+                if (d < db) { db = d; hit = i + 1; }
             }
-            pc.hit(p.o, dl, nh);
         }
-    }
-    if (escaped) {
-        ++cnt.c[10];
-        lg.put(EV_ESCAPE, 0, p.m);
-        if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
-            adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
-        if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
-        return true;
+        for (int c = 0; c < H.n_pores; ++c) {
+            const auto P = Geo<R>::pore(g, c);
+            const R dx = p.x[0] - P.cx, dy = p.x[1] - P.cy;
+            const R qa = p.o[0] * p.o[0] + p.o[1] * p.o[1];
+            const R qb = dx * p.o[0] + dy * p.o[1];
+            const R rr = P.r;
+            const R qc = dx * dx + dy * dy - rr * rr;
+            if (qb < R(0)) {
+                const R disc = qb * qb - qa * qc;
+                if (disc >= R(0)) {
+                    const R d = (qc < R(0)) ? R(0) : r_div(qc, -qb + r_sqrt(disc));
+                    if (d < db) { db = d; hit = P.id; pore = c; pcx = P.cx; pcy = P.cy; pr = rr; }
+                }
+            }
+        }
+        // event: the time horizon first, then the boundary (segment (x0, x1]), then relaxation
+        const R dmin = db < ds ? db : ds;
+        const R tmax = H.t_max;
+        R d;
+        if (H.transient && vm * (tmax - p.t) <= dmin) { ev = 2; d = vm * (tmax - p.t); }
+        else if (db <= ds) { ev = 1; d = db; }
+        else { ev = 0; d = ds; }
+        const R dt = (ev == 0) ? p.dtr : (ev == 1 ? r_div(d, vm) : tmax - p.t);
+        const R t_end = (ev == 2) ? tmax : p.t + dt;
+        if (TK == TALLY_TRANSIENT) {
+            tally_snap(T, tc, p.x, p.o, p.t, t_end, vm, sg);
+        } else {
+            if (TK == TALLY_STEADY_ONE) {
+                if (d > R(0)) add4_c(tc, H.det_mask, H.det_ncomp, H.det_slot, (int64_t)p.m, sg, d, vm, p.o);
+            } else {
+                tally_grid(T, tc, p.x, p.o, d, p.m, sg, vm);
+            }
+            const int sa = H.score_axis;
+            const R os = sa == 0 ? p.o[0] : (sa == 1 ? p.o[1] : p.o[2]);
+            p.cT += (double)(sg * r_div(d, vm));
+            p.cq += (double)(sg * (d * os));
+        }
+        ++cnt.c[1];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p.x[a] = p.x[a] + d * p.o[a];
+        p.t = t_end;
+        if (ev == 1) {
+            const R r = p.dtr - dt;
+            p.dtr = r > R(0) ? r : R(0);
+        } else {
+            p.dtr = R(0);
+        }
+        p.k += 1;
+        if (ev == 2) {
+            ++cnt.c[7];
+            lg.put(EV_TIMEOUT, 0, p.m);
+            if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
+                adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+            if (AK == 2) pc.flush(adj.bins, p.s, H.score_axis, adj.bad);
+            return true;
+        }
+        const bool on_face = (ev == 1) && hit <= 6;
+        fa = on_face ? face_axis(hit - 1) : -1;
+        fs = on_face ? face_side(hit - 1) : 0;
+        bool escaped = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const R L = H.L[a];
+            if (a == fa) p.x[a] = fs ? L : R(0);     // exactly on the wall
+            if (!(H.unb & (1u << a)) && (p.x[a] < R(-1e-9) * L || p.x[a] > L + R(1e-9) * L)) escaped = true;
+        }
+        fcode = on_face ? (H.face >> (4 * (hit - 1))) & 15u : 0u;
+        const bool periodic = on_face && (fcode & 3u) == 3u;
+        if (AK == 2) {   // the segment's end, for the pathwise state
+            const R dl = pc.dline + d;
+            pc.dline = R(0);
+            if (ev == 0) {
+                pc.end_flight(p.o, dl, vm * p.dtr0, T.bin_of[p.m]);
+            } else if (periodic) {
+                pc.dline = dl;
+            } else if (ev == 1) {
+                R nh[3] = {R(0), R(0), R(0)};
+                if (hit <= 6) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) nh[a] = a == fa ? R(1) : R(0);
+                } else {
+                    nh[0] = r_div(p.x[0] - pcx, pr);
+                    nh[1] = r_div(p.x[1] - pcy, pr);
+                }
+                pc.hit(p.o, dl, nh);
+            }
+        }
+        if (escaped) {
+            ++cnt.c[10];
+            lg.put(EV_ESCAPE, 0, p.m);
+            if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
+                adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+            if (AK == 2) pc.flush(adj.bins, p.s, H.score_axis, adj.bad);
+            return true;
+        }
+        if (!periodic) break;
+        // linearised periodic condition: reinsert unchanged at the partner face
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (a == fa) p.x[a] = fs ? R(0) : H.L[a];
+        ++cnt.c[5];
+        lg.put(EV_PERIODIC, hit, p.m);
+        if (AK == 2 || !chain) return false;
     }
     // what the event needs
     bool relax = (ev == 0);
@@ -804,80 +891,79 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
         p.nrel += 1;
         ++cnt.c[2];
         if (AK == 3 && local_form<AK>(T, p.m, adj)) {
-            const int sa = T.score_axis;
+            const int sa = H.score_axis;
             const double os = (double)(sa == 0 ? p.o[0] : (sa == 1 ? p.o[1] : p.o[2]));
             atomicAdd(adj.bins + T.bin_of[p.m], (double)p.s * (T.v64[p.m] * (double)p.dtr0) * os);
             adj.add(T.bin_of[p.m], (double)p.dtr0 / T.tau64[p.m] - 1.0, adj.F_total - p.cq);
         } else if (AK == 1 || AK == 3) {
             adj.add(T.bin_of[p.m], (double)p.dtr0 / T.tau64[p.m] - 1.0, adj.F_total - p.F0);
         }
-        if (T.n_scat_max > 0 && p.nrel >= T.n_scat_max) {
+        if (H.n_scat_max > 0 && p.nrel >= H.n_scat_max) {
             ++cnt.c[8];
             lg.put(EV_NSCAT, 0, p.m);
-            if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
+            if (AK == 2) pc.flush(adj.bins, p.s, H.score_axis, adj.bad);
             return true;
         }
     }
-    int btype = 0;
-    R spec = R(0);
-    uint64_t sthr = 0;
-    int pore = -1;
+    uint32_t cls = SURF_DIFFUSE;
     if (ev == 1) {
+        int btype;
         if (hit <= 6) {
-            btype = g.face_type[hit - 1];
-            spec = (R)g.face_spec[hit - 1];
-            sthr = g.face_thr[hit - 1];
+            btype = (int)(fcode & 3u);
+            cls = fcode >> 2;
         } else {
-            for (int c = 0; c < g.n_pores; ++c)
-                if (g.pore_id[c] == hit) pore = c;
             btype = 2;
-            spec = (R)g.pore_spec[pore];
-            sthr = g.pore_thr[pore];
+            cls = (H.pcls >> (2 * pore)) & 3u;
         }
         if (btype == 1) {
             ++cnt.c[6];
             lg.put(EV_ABSORB, hit, p.m);
             if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
-            adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
-            if (AK == 2) pc.flush(adj.bins, p.s, T.score_axis, adj.bad);
+                adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+            if (AK == 2) pc.flush(adj.bins, p.s, H.score_axis, adj.bad);
             return true;
-        }
-        if (btype == 3) {   // linearised periodic condition: reinsert unchanged at the partner face
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                if (a == fa) p.x[a] = fs ? R(0) : Geo<R>::L(g, a);
-            ++cnt.c[5];
-            lg.put(EV_PERIODIC, hit, p.m);
-            return false;
         }
     }
     // FP32, film-like problem: a diffuse reflection off the film wall with a long free path left
     // is handed to the whole wave (coop_bounces), which runs the coming bounces 64 at a time
-    if (std::is_same<R, float>::value && ev == 1 && T.coop_axis >= 0 && fa == T.coop_axis && !lg.row &&
-        vm * p.dtr > (R)T.coop_min_path) {
+    if (std::is_same<R, float>::value && ev == 1 && H.coop_axis >= 0 && fa == H.coop_axis && !lg.row &&
+        vm * p.dtr > H.coop_min) {
         if (AK == 2) pc.plane(fa, false);    // the chain starts with a diffuse reflection
         coop = true;
         return false;
     }
     const bool adia = (ev == 1);
-    const bool partial = adia && spec > R(0) && spec < R(1);
+    const bool partial = adia && cls == SURF_PARTIAL;
     const bool need_b0 = relax || partial;
-    const bool need_rec = need_b0 || (adia && !(spec > R(0)));
+    const bool need_rec = need_b0 || (adia && cls == SURF_DIFFUSE);
     if (need_rec) p.j += 1;
     const uint32_t blk = 2u * (2u + p.j);
     W4 w0 = {0u, 0u, 0u, 0u};
     if (need_b0) w0 = st.block(blk);
-    const bool specular = adia && (spec >= R(1) || (partial && key64(w0.x, w0.y) < sthr));
+    bool specular = adia && cls == SURF_SPECULAR;
+    if (partial) specular = key64(w0.x, w0.y) < (pore >= 0 ? g.pore_thr[pore] : g.face_thr[hit - 1]);
     const bool diffuse = adia && !specular;
     if (relax || diffuse) {
         const W4 w1 = st.block(blk + 1u);
         const R u1 = unif<R>(w1.x, w1.y), u2 = unif<R>(w1.z, w1.w);
+        // the new direction's polar cosine mu and sine about its axis: isotropic for a relaxation
+        // (axis e_z, mu = 1 - 2 u1), cosine-weighted about the inward normal for a diffuse wall
+        // (mu = sqrt(u1)); one azimuth 2 pi u2 serves both (dir_iso and dir_cos, shared by the
+        // lanes of a wave that do different ones)
+        const R mu_i = R(1) - R(2) * u1;
+        const R s2 = (R(1) - mu_i) * (R(1) + mu_i);
+        const R mu = relax ? mu_i : r_sqrt(u1);
+        const R sth = r_sqrt(relax ? (s2 > R(0) ? s2 : R(0)) : R(1) - u1);
+        R sn, cs;
+        r_sincos_2pi(u2, &sn, &cs);
         if (relax) {
             // three-phonon relaxation: frequency from the post-scattering distribution
             // (weights C/tau), isotropic direction, new free flight, sign kept
-            p.m = tb.guide ? cdf_pick_guided(tb.thr_rel, tb.guide, T.M, T.last_rel, key64(w0.x, w0.y))
-                           : cdf_pick(tb.thr_rel, T.M, T.last_rel, key64(w0.x, w0.y));
-            dir_iso(u1, u2, p.o);
+            p.m = tb.guide ? cdf_pick_guided(tb.thr_rel, tb.guide, H.M, H.last_rel, key64(w0.x, w0.y))
+                           : cdf_pick(tb.thr_rel, H.M, H.last_rel, key64(w0.x, w0.y));
+            p.o[0] = sth * cs;
+            p.o[1] = sth * sn;
+            p.o[2] = mu;
             p.dtr = -tb.tau[p.m] * r_log(R(1) - unif<R>(w0.z, w0.w));
             lg.put(EV_RELAX, 0, p.m);
             if (AK != 0) {
@@ -889,17 +975,16 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
         } else {
             R n[3];
             if (pore >= 0) {
-                const R rr = Geo<R>::r(g, pore);
-                n[0] = r_div(p.x[0] - Geo<R>::cx(g, pore), rr);
-                n[1] = r_div(p.x[1] - Geo<R>::cy(g, pore), rr);
+                n[0] = r_div(p.x[0] - pcx, pr);
+                n[1] = r_div(p.x[1] - pcy, pr);
                 n[2] = R(0);
             } else {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) n[a] = (a == fa) ? (fs ? R(-1) : R(1)) : R(0);
             }
-            dir_cos(u1, u2, n, p.o);
+            dir_about(mu, sth * cs, sth * sn, n, p.o);
             if (AK == 2) {
-                if (pore >= 0) pc.cyl_diffuse(p.o, n, Geo<R>::r(g, pore));
+                if (pore >= 0) pc.cyl_diffuse(p.o, n, pr);
                 else pc.plane(fa, false);
             }
             ++cnt.c[4];
@@ -907,9 +992,9 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Tabs<R>& tb, const
         }
     } else if (specular) {
         if (pore >= 0) {   // k' = k - 2 (k.n) n
-            const R rr = Geo<R>::r(g, pore);
-            const R n0 = r_div(p.x[0] - Geo<R>::cx(g, pore), rr);
-            const R n1 = r_div(p.x[1] - Geo<R>::cy(g, pore), rr);
+            const R rr = pr;
+            const R n0 = r_div(p.x[0] - pcx, rr);
+            const R n1 = r_div(p.x[1] - pcy, rr);
             if (AK == 2) {
                 const R nn[3] = {n0, n1, R(0)};
                 pc.cyl_specular(p.o, nn, rr);
@@ -1226,6 +1311,7 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const DevTab& T = tabs[0];
+    const Hot<R> H = load_hot<R>(T);
     constexpr bool WIDE = (FT & FT_WIDE) != 0;
     const Tabs<R> tb = WIDE ? Tabs<R>{T.thr_rel, Geo<R>::v(T), Geo<R>::tau(T), T.rel_guide} : stage_tables<R>(T, smem);
     double* s_tally = (double*)(smem + a.lds_tab_bytes);
@@ -1265,8 +1351,8 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
     bool exhausted = false;        // wave-uniform: the particle counter has run past n
     int since_refill = 0;
     for (;;) {
-        bool any_alive = __ballot(alive) != 0ull;
-        if (!exhausted && (!any_alive || since_refill >= a.refill)) {
+        unsigned long long live = __ballot(alive);
+        if (!exhausted && (live == 0ull || since_refill >= a.refill)) {
             since_refill = 0;
             const unsigned long long need = __ballot(!alive);
             if (need) {
@@ -1289,17 +1375,18 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
                         alive = true;
                     }
                 }
-                any_alive = __ballot(alive) != 0ull;
+                live = __ballot(alive);
             }
         }
-        if (!any_alive) {
+        if (live == 0ull) {
             if (exhausted) break;
             continue;
         }
         ++since_refill;
+        const bool lone = exhausted && (live & (live - 1ull)) == 0ull;   // one lane left in the wave
         bool coop = false;
         if (alive) {
-            if (flight<R, TK, AK, FT>(T, tb, tc, st, p, cnt, lg, coop, adj, pc)) {
+            if (flight<R, TK, AK, FT>(T, H, tb, tc, st, p, cnt, lg, coop, adj, pc, lone)) {
                 end_particle(p, T.transient, mom, lg);
                 if (!ADJ && a.particle_F) a.particle_F[my_pid - a.first_pid] = p.cq;
                 alive = false;
@@ -1374,6 +1461,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
         }
         if (inst < 0) break;
         const DevTab& T = tabs[inst];
+        const Hot<R> H = load_hot<R>(T);
         if (inst != cur) {
             tb = stage_tables<R>(T, smem);
             if (a.tally_lds) {
@@ -1403,8 +1491,8 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
         bool exhausted = false;
         int since_refill = 0;
         for (;;) {
-            bool any_alive = __ballot(alive) != 0ull;
-            if (!exhausted && (!any_alive || since_refill >= a.refill)) {
+            unsigned long long live = __ballot(alive);
+            if (!exhausted && (live == 0ull || since_refill >= a.refill)) {
                 since_refill = 0;
                 const unsigned long long need = __ballot(!alive);
                 if (need) {
@@ -1427,17 +1515,18 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
                             alive = true;
                         }
                     }
-                    any_alive = __ballot(alive) != 0ull;
+                    live = __ballot(alive);
                 }
             }
-            if (!any_alive) {
+            if (live == 0ull) {
                 if (exhausted) break;
                 continue;
             }
             ++since_refill;
+            const bool lone = exhausted && (live & (live - 1ull)) == 0ull;
             bool coop = false;
             if (alive) {
-                if (flight<R, TK, 0, 0>(T, tb, tc, st, p, cnt, lg, coop, adj, pc)) {
+                if (flight<R, TK, 0, 0>(T, H, tb, tc, st, p, cnt, lg, coop, adj, pc, lone)) {
                     end_particle(p, T.transient, mom, lg);
                     alive = false;
                 }
