@@ -226,7 +226,8 @@ class Tables:
         self.M, self.S, self.n_cells, self.n_cols, self.n_bins = list(ii)
 
     def __del__(self):
-        if getattr(self, "h", None):
+        # at interpreter shutdown the module's globals may already be gone
+        if getattr(self, "h", None) and callable(globals().get("lib")):
             lib().orc_free(self.h)
             self.h = None
 

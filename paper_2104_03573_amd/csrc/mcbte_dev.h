@@ -17,10 +17,11 @@ enum SourceKind : int32_t { SRC_WALL = 0, SRC_GRAD = 1, SRC_IC = 2 };
 enum TallyKind : int32_t { TALLY_STEADY_ONE = 0, TALLY_STEADY_GRID = 1, TALLY_TRANSIENT = 2 };
 
 // optional features of the trace kernels, compiled in only where used: particles loaded from a
-// state buffer written by k_emit, the per-particle event log, and (FP32 trace) wide workgroups
+// state buffer written by k_emit, the per-particle event log, (FP32 trace) wide workgroups
 // whose whole LDS holds an FP32 copy of a tally too large for the FP64 one, the mode tables
-// being read from global memory instead
-enum : int { FT_STATE = 1, FT_LOG = 2, FT_WIDE = 4 };
+// being read from global memory instead, and (FP64 film-like problems) the exact cooperative
+// bouncing, whose registers the other FP64 problems need not reserve
+enum : int { FT_STATE = 1, FT_LOG = 2, FT_WIDE = 4, FT_COOP = 8 };
 
 // Geometry in the form the flight loop reads it (uniform across a launch; scalar loads).
 struct DevPore32 { float cx, cy, r; int32_t id; };

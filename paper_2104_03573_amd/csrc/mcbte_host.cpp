@@ -643,6 +643,8 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
         const bool fits64 = t64 <= MCBTE_LDS_TALLY_BYTES && tab + t64 <= t->max_lds;
         if (!fits64 && t64 / 2 <= t->max_lds) ft = FT_WIDE;
     }
+    // FP64 film-like problems: the kernel with the exact cooperative bouncing
+    if (run->precision == 64 && t->host_view.coop_axis >= 0) ft |= FT_COOP;
     const int rc = plan_launch(&t, 1, run, 0, ft, lp);
     if (rc != MCBTE_OK) return rc;
     LaunchArgs a;
@@ -839,7 +841,8 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
     DeviceGuard g(t->device);
     if (!g.ok) return MCBTE_EHIP;
     const int mode = estimator == MCBTE_SENS_PATHWISE ? 3 : (estimator == MCBTE_SENS_LOCAL ? 4 : 2);
-    const int ft = 0;
+    // FP64 film-like problems replay with the exact cooperative bouncing, as they trace
+    const int ft = (run->precision == 64 && t->host_view.coop_axis >= 0) ? FT_COOP : 0;
     LaunchPlan lp;
     const int rc = plan_launch(&t, 1, run, mode, ft, lp);
     if (rc != MCBTE_OK) return rc;

@@ -559,6 +559,8 @@ struct Hot {
     uint32_t det_slot;   // 8 bits per tally component: compact slot
     int32_t det_mask, det_ncomp;
     int32_t n_pores, max_events, n_scat_max, M, last_rel, transient, score_axis, coop_axis;
+    R p0cx, p0cy, p0r;   // the first pore (most geometries have at most one)
+    int32_t p0id;
 };
 
 template <typename R>
@@ -587,6 +589,11 @@ __device__ __forceinline__ Hot<R> load_hot(const DevTab& T)
     h.transient = T.transient;
     h.score_axis = T.score_axis;
     h.coop_axis = T.coop_axis;
+    const auto P0 = Geo<R>::pore(g, 0);
+    h.p0cx = P0.cx;
+    h.p0cy = P0.cy;
+    h.p0r = P0.r;
+    h.p0id = P0.id;
     return h;
 }
 
@@ -753,8 +760,20 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     int hit, pore, ev, fa, fs;
     R pcx, pcy, pr;                      // centre and radius of the pore hit
     uint32_t fcode;
+    // a chain of segments (one mode, one direction) of the FP32 trajectories sums its steady
+    // tally terms here and adds them to the tally once, where it ends
+    constexpr bool ACC = TK == TALLY_STEADY_ONE && AK != 2 && std::is_same<R, float>::value;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    auto flush_acc = [&]() {
+        if (ACC && chain) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if ((H.det_mask >> q) & 1) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)p.m, q, acc[q]);
+        }
+    };
     for (;;) {
         if (p.k >= (uint32_t)H.max_events) {
+            flush_acc();
             ++cnt.c[9];
             lg.put(EV_CAP, 0, p.m);
             if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
@@ -782,17 +801,24 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             }
         }
         for (int c = 0; c < H.n_pores; ++c) {
-            const auto P = Geo<R>::pore(g, c);
-            const R dx = p.x[0] - P.cx, dy = p.x[1] - P.cy;
+            R cx = H.p0cx, cy = H.p0cy, rr = H.p0r;
+            int id = H.p0id;
+            if (c > 0) {
+                const auto P = Geo<R>::pore(g, c);
+                cx = P.cx;
+                cy = P.cy;
+                rr = P.r;
+                id = P.id;
+            }
+            const R dx = p.x[0] - cx, dy = p.x[1] - cy;
             const R qa = p.o[0] * p.o[0] + p.o[1] * p.o[1];
             const R qb = dx * p.o[0] + dy * p.o[1];
-            const R rr = P.r;
             const R qc = dx * dx + dy * dy - rr * rr;
             if (qb < R(0)) {
                 const R disc = qb * qb - qa * qc;
                 if (disc >= R(0)) {
                     const R d = (qc < R(0)) ? R(0) : r_div(qc, -qb + r_sqrt(disc));
-                    if (d < db) { db = d; hit = P.id; pore = c; pcx = P.cx; pcy = P.cy; pr = rr; }
+                    if (d < db) { db = d; hit = id; pore = c; pcx = cx; pcy = cy; pr = rr; }
                 }
             }
         }
@@ -809,7 +835,16 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             tally_snap(T, tc, p.x, p.o, p.t, t_end, vm, sg);
         } else {
             if (TK == TALLY_STEADY_ONE) {
-                if (d > R(0)) add4_c(tc, H.det_mask, H.det_ncomp, H.det_slot, (int64_t)p.m, sg, d, vm, p.o);
+                if (ACC && chain) {
+                    if (d > R(0)) {
+                        acc[0] += (double)(sg * r_div(d, vm));
+                        acc[1] += (double)(sg * (d * p.o[0]));
+                        acc[2] += (double)(sg * (d * p.o[1]));
+                        acc[3] += (double)(sg * (d * p.o[2]));
+                    }
+                } else if (d > R(0)) {
+                    add4_c(tc, H.det_mask, H.det_ncomp, H.det_slot, (int64_t)p.m, sg, d, vm, p.o);
+                }
             } else {
                 tally_grid(T, tc, p.x, p.o, d, p.m, sg, vm);
             }
@@ -830,6 +865,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         }
         p.k += 1;
         if (ev == 2) {
+            flush_acc();
             ++cnt.c[7];
             lg.put(EV_TIMEOUT, 0, p.m);
             if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
@@ -869,6 +905,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             }
         }
         if (escaped) {
+            flush_acc();
             ++cnt.c[10];
             lg.put(EV_ESCAPE, 0, p.m);
             if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
@@ -876,7 +913,10 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             if (AK == 2) pc.flush(adj.bins, p.s, H.score_axis, adj.bad);
             return true;
         }
-        if (!periodic) break;
+        if (!periodic) {
+            flush_acc();
+            break;
+        }
         // linearised periodic condition: reinsert unchanged at the partner face
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -924,9 +964,11 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             return true;
         }
     }
-    // FP32, film-like problem: a diffuse reflection off the film wall with a long free path left
-    // is handed to the whole wave (coop_bounces), which runs the coming bounces 64 at a time
-    if (std::is_same<R, float>::value && ev == 1 && H.coop_axis >= 0 && fa == H.coop_axis && !lg.row &&
+    // film-like problem: a diffuse reflection off the film wall with a long free path left is
+    // handed to the whole wave, which runs the coming bounces 64 at a time (coop_bounces for the
+    // FP32 trajectories, which it does not log; coop_exact for the FP64 ones)
+    constexpr bool COOP = std::is_same<R, float>::value || (FT & FT_COOP) != 0;
+    if (COOP && ev == 1 && H.coop_axis >= 0 && fa == H.coop_axis && (std::is_same<R, double>::value || !lg.row) &&
         vm * p.dtr > H.coop_min) {
         if (AK == 2) pc.plane(fa, false);    // the chain starts with a diffuse reflection
         coop = true;
@@ -1140,6 +1182,133 @@ __device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb,
         p.k += full;
         cnt.c[1] += full;              // completed segments
         cnt.c[4] += full + 1u;         // diffuse reflections
+    }
+}
+
+// value of v in lane k (k the same in every lane)
+__device__ __forceinline__ double lane_value(double v, int k)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+
+// Exact form of the cooperative bouncing for the FP64 trajectories.  A reflection's direction,
+// the chord to the opposite wall, its flight time and its flux terms depend only on the
+// reflection's own record and on the wall it starts from, so the lanes evaluate 64 consecutive
+// reflections at once, each with the sequential loop's own arithmetic (the chord is the division
+// the geometry step makes from the wall coordinate).  One pass of the whole wave then walks them
+// in order with the sequential arithmetic for everything that carries over from one segment to
+// the next (remaining flight time and the test against it, position, time, the particle's scores,
+// segment count, event log), so the particle leaves the chain in exactly the state the
+// one-segment-at-a-time loop reaches.  The tallies take each lane's terms (their summation order
+// is free, as it is for the atomics).
+__device__ __forceinline__ void coop_exact(const Hot<double>& H, const Tabs<double>& tb, const TallyCtx& tc,
+                                           Part<double>& p, const Stream& st_own, int leader, LaneCounts& cnt,
+                                           LogRow& lg)
+{
+    const int lane = threadIdx.x & 63;
+    const int aw = H.coop_axis;
+    const double L = aw == 0 ? H.L[0] : (aw == 1 ? H.L[1] : H.L[2]);
+    const int m = __shfl(p.m, leader, 64);
+    const double sg = (double)__shfl(p.s, leader, 64);
+    const Stream st{(uint32_t)__shfl((int)st_own.k0, leader, 64), (uint32_t)__shfl((int)st_own.k1, leader, 64),
+                    (uint32_t)__shfl((int)st_own.plo, leader, 64), (uint32_t)__shfl((int)st_own.phi, leader, 64),
+                    (uint32_t)__shfl((int)st_own.inst, leader, 64)};
+    double x[3] = {__shfl(p.x[0], leader, 64), __shfl(p.x[1], leader, 64), __shfl(p.x[2], leader, 64)};
+    const int side0 = (aw == 0 ? x[0] : (aw == 1 ? x[1] : x[2])) > 0.5 * L ? 1 : 0;
+    uint32_t j = (uint32_t)__shfl((int)p.j, leader, 64);
+    uint32_t pk = (uint32_t)__shfl((int)p.k, leader, 64);
+    double D = __shfl(p.dtr, leader, 64);
+    double t = __shfl(p.t, leader, 64);
+    double cT = __shfl(p.cT, leader, 64);
+    double cq = __shfl(p.cq, leader, 64);
+    const double vm = tb.v[m];
+    const int sa = H.score_axis;
+    int id0 = 0, id1 = 0;              // boundary ids of the faces at 0 and at L of the film axis
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        if (face_axis(i) == aw) {
+            if (face_side(i)) id1 = i + 1;
+            else id0 = i + 1;
+        }
+    double aT = 0.0, aQ0 = 0.0, aQ1 = 0.0, aQ2 = 0.0;
+    uint32_t full = 0;
+    uint32_t refl = 0;
+    int side = side0;                  // wall of the current chunk's first reflection
+    double o_end[3] = {0.0, 0.0, 0.0};
+    for (int chunk = 0; chunk < (1 << 24); ++chunk) {
+        const int sk = side ^ (lane & 1);
+        const W4 w1 = st.block(2u * (2u + j + 1u + (uint32_t)lane) + 1u);
+        const double u1 = unif<double>(w1.x, w1.y), u2 = unif<double>(w1.z, w1.w);
+        double n[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) n[a] = (a == aw) ? (sk ? -1.0 : 1.0) : 0.0;
+        double o[3];
+        dir_cos(u1, u2, n, o);
+        const double oa = aw == 0 ? o[0] : (aw == 1 ? o[1] : o[2]);
+        double d = 1.0 / 0.0;
+        if (sk ? oa < 0.0 : oa > 0.0) d = sk ? (0.0 - L) / oa : (L - 0.0) / oa;
+        const double dt = d / vm;
+        const double q0 = d * o[0], q1 = d * o[1], q2 = d * o[2];
+        const double qs = sa == 0 ? q0 : (sa == 1 ? q1 : q2);
+        int kstop = 64;
+        for (int k = 0; k < 64; ++k) {
+            ++refl;                                      // the reflection that drew lane k's record
+            if (lane == leader) lg.put(EV_DIFFUSE, (side ^ (k & 1)) ? id1 : id0, m);
+            if (pk >= (uint32_t)H.max_events) { kstop = k; break; }
+            const double dk = lane_value(d, k);
+            if (!(dk <= vm * D)) { kstop = k; break; }   // the free flight ends in this segment
+            const double dtk = lane_value(dt, k);
+            const double r = D - dtk;
+            D = r > 0.0 ? r : 0.0;
+            x[0] = x[0] + lane_value(q0, k);
+            x[1] = x[1] + lane_value(q1, k);
+            x[2] = x[2] + lane_value(q2, k);
+            t = t + dtk;
+            cT += sg * dtk;
+            cq += sg * lane_value(qs, k);
+            pk += 1;
+            full += 1;
+            if (lane == k) {
+                aT += sg * dt;
+                aQ0 += sg * q0;
+                aQ1 += sg * q1;
+                aQ2 += sg * q2;
+            }
+        }
+        if (kstop < 64) {
+            o_end[0] = __shfl(o[0], kstop, 64);
+            o_end[1] = __shfl(o[1], kstop, 64);
+            o_end[2] = __shfl(o[2], kstop, 64);
+            side ^= (kstop & 1);
+            j += (uint32_t)kstop + 1u;
+            break;
+        }
+        j += 64u;                                        // 64 reflections: back on the same wall
+    }
+    const double sT = wave_sum<double>(aT), s0 = wave_sum<double>(aQ0), s1 = wave_sum<double>(aQ1),
+                 s2 = wave_sum<double>(aQ2);
+    if (lane == leader) {
+        if (full > 0) {
+            if (H.det_mask & 1) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)m, 0, sT);
+            if (H.det_mask & 2) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)m, 1, s0);
+            if (H.det_mask & 4) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)m, 2, s1);
+            if (H.det_mask & 8) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)m, 3, s2);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            p.x[a] = (a == aw) ? (side ? L : 0.0) : x[a];
+            p.o[a] = o_end[a];
+        }
+        p.t = t;
+        p.dtr = D;
+        p.j = j;
+        p.k = pk;
+        p.cT = cT;
+        p.cq = cq;
+        cnt.c[1] += full;              // completed segments
+        cnt.c[4] += refl;              // diffuse reflections
     }
 }
 
@@ -1392,9 +1561,13 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
                 alive = false;
             }
         }
-        if (std::is_same<R, float>::value && TK == TALLY_STEADY_ONE) {
-            for (unsigned long long pend = __ballot(coop); pend; pend &= pend - 1ull)
-                coop_bounces<R>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
+        if constexpr (TK == TALLY_STEADY_ONE) {
+            for (unsigned long long pend = __ballot(coop); pend; pend &= pend - 1ull) {
+                if constexpr (std::is_same<R, float>::value)
+                    coop_bounces<R>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
+                else if constexpr ((FT & FT_COOP) != 0)
+                    coop_exact(H, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt, lg);
+            }
         }
     }
     if (ADJ) {
@@ -1531,9 +1704,11 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
                     alive = false;
                 }
             }
-            if (std::is_same<R, float>::value && TK == TALLY_STEADY_ONE) {
-                for (unsigned long long pend = __ballot(coop); pend; pend &= pend - 1ull)
-                    coop_bounces<R>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
+            if constexpr (TK == TALLY_STEADY_ONE) {
+                for (unsigned long long pend = __ballot(coop); pend; pend &= pend - 1ull) {
+                    if constexpr (std::is_same<R, float>::value)
+                        coop_bounces<R>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
+                }
             }
         }
         __syncthreads();
@@ -1582,6 +1757,15 @@ template <typename R, int TK>
 static const void* pick_kernel(int mode, int ft)
 {
     if (mode == 1) return (const void*)k_trace_batch<R, TK>;
+    if constexpr (std::is_same<R, double>::value && TK == TALLY_STEADY_ONE) {
+        if (ft & FT_COOP) {
+            if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, FT_COOP>;
+            if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, FT_COOP>;
+            if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, FT_COOP>;
+            if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG | FT_COOP>;
+            return (const void*)k_trace_solo<R, TK, 0, FT_COOP>;
+        }
+    }
     if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, 0>;
     if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, 0>;
     if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, 0>;

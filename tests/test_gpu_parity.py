@@ -260,6 +260,30 @@ def test_fp32_long_flights_in_pore_lattice_against_fp64_oracle(lam, spec):
     assert abs(got["kappa"] - ref["kappa"]) < 3.0 * ref["kappa_sigma"]
 
 
+def test_fp64_long_pore_lattice_walks_independent_of_launch_shape():
+    """Free paths of 20 um (40 cells) in the pore cell: the FP64 event sequences, counters and
+    particle scores do not depend on the launch shape, which decides when a lane is the last one
+    of its wave and follows its chains of periodic transfers within one call.  (Against the oracle
+    such walks agree only up to the tens of pore reflections after which the lattice's dispersion
+    of neighbouring rays has grown the last-place differences of the device and host sin, cos and
+    log into different events; the FP32 counts are compared with the oracle's statistically.)"""
+    M = _pkg()
+    w = W.with_(W.porous_cell(N=300, modes=W.gray_modes(6400.0, 20e-6 / 6400.0), n_scat_max=3),
+                **{"problem.format": 2})
+    n, stride = 300, 2048
+    runs = [M.run(w, precision=64, n_log=n, log_stride=stride, **shape)
+            for shape in ({}, {"block": 64, "refill": 1}, {"block": 256, "refill": 64, "grid": 2})]
+    base = runs[0]
+    assert int(base["log"][:, 0].max()) + 1 < stride
+    for r in runs[1:]:
+        assert np.array_equal(r["log"], base["log"])
+        assert np.array_equal(r["counts_raw"], base["counts_raw"])
+        scale = np.abs(base["raw"]).max()
+        assert np.abs(r["raw"] - base["raw"]).max() <= 1e-12 * scale
+    _say(f"[long walks] counts {base['counts']}")
+    assert base["counts"]["periodic"] > 20 * n
+
+
 def test_fp32_transient_wide_kernel_against_fp64_oracle():
     """The transient bump with its full snapshot detector (100 bins x 200 times, too large for a
     per-workgroup FP64 copy): the FP32 kernel sums it per workgroup in FP32 in LDS.  Each particle
