@@ -32,6 +32,8 @@ namespace mcbte {
 // boundary id - 1 -> (axis, side) in the paper's boundary-table order
 __device__ __forceinline__ constexpr int face_axis(int i) { return (i == 1 || i == 3) ? 0 : (i == 0 || i == 2) ? 1 : 2; }
 __device__ __forceinline__ constexpr int face_side(int i) { return (i == 1 || i == 2 || i == 5) ? 1 : 0; }
+// boundary id (index + 1) of the face of axis a on side s (1: at L, 0: at 0)
+__device__ __forceinline__ constexpr int face_id(int a, int s) { return a == 0 ? (s ? 2 : 4) : (a == 1 ? (s ? 3 : 1) : (s ? 6 : 5)); }
 
 __host__ __device__ __forceinline__ int64_t align16(int64_t x) { return (x + 15) & ~int64_t(15); }
 
@@ -789,16 +791,18 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         pcx = R(0);
         pcy = R(0);
         pr = R(1);
+        // (evaluated without branches: per axis the one face the ray moves toward, then the
+        // lexicographic minimum of (distance, id), which is the id-order scan's first minimum)
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            const int a = face_axis(i), side = face_side(i);
-            if (H.unb & (1u << a)) continue;
+        for (int a = 0; a < 3; ++a) {
             const R oa = p.o[a];
-            const bool toward = side ? (oa > R(0)) : (oa < R(0));
-            if (toward) {
-                const R d = side ? r_div(H.L[a] - p.x[a], oa) : r_div(R(0) - p.x[a], oa);
-                if (d < db) { db = d; hit = i + 1; }
-            }
+            const bool up = oa > R(0);
+            const bool valid = !(H.unb & (1u << a)) && (up || oa < R(0));
+            const R d = up ? r_div(H.L[a] - p.x[a], oa) : r_div(R(0) - p.x[a], oa);
+            const int id = face_id(a, up ? 1 : 0);
+            const bool better = valid && (d < db || (d == db && id < hit));
+            db = better ? d : db;
+            hit = better ? id : hit;
         }
         for (int c = 0; c < H.n_pores; ++c) {
             R cx = H.p0cx, cy = H.p0cy, rr = H.p0r;
@@ -814,13 +818,17 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             const R qa = p.o[0] * p.o[0] + p.o[1] * p.o[1];
             const R qb = dx * p.o[0] + dy * p.o[1];
             const R qc = dx * dx + dy * dy - rr * rr;
-            if (qb < R(0)) {
-                const R disc = qb * qb - qa * qc;
-                if (disc >= R(0)) {
-                    const R d = (qc < R(0)) ? R(0) : r_div(qc, -qb + r_sqrt(disc));
-                    if (d < db) { db = d; hit = id; pore = c; pcx = cx; pcy = cy; pr = rr; }
-                }
-            }
+            const R disc = qb * qb - qa * qc;
+            // the ray meets the circle while approaching its centre: qb < 0, disc >= 0
+            const bool meets = qb < R(0) && disc >= R(0);
+            const R d = (qc < R(0)) ? R(0) : r_div(qc, -qb + r_sqrt(disc >= R(0) ? disc : R(0)));
+            const bool better = meets && d < db;
+            db = better ? d : db;
+            hit = better ? id : hit;
+            pore = better ? c : pore;
+            pcx = better ? cx : pcx;
+            pcy = better ? cy : pcy;
+            pr = better ? rr : pr;
         }
         // event: the time horizon first, then the boundary (segment (x0, x1]), then relaxation
         const R dmin = db < ds ? db : ds;
