@@ -176,6 +176,7 @@ template <typename R> struct Part {
     double cT, cq;       // per-particle contributions (variance estimate); cq is the flux score F
     R dtr0;              // free-flight time drawn for the current flight (sensitivity replay)
     double F0;           // flux score at the start of the current flight (sensitivity replay)
+    int32_t tk;          // transient tallies: first measurement time not before t (-1: not yet known)
 };
 
 // cosine-weighted direction about the unit normal n (Eq. wall_dir), frame t1 = e_j x n / |.|
@@ -450,17 +451,24 @@ __device__ __forceinline__ void tally_grid(const DevTab& T, const TallyCtx& tc, 
 // transient snapshot estimator (Eq. sampling): every measurement time t_k in [t0, t1)
 template <typename R>
 __device__ __forceinline__ void tally_snap(const DevTab& T, const TallyCtx& tc, const R x0[3], const R o[3], R t0, R t1,
-                                           R vm, R sg)
+                                           R vm, R sg, int32_t& cursor)
 {
     const DevDet& D = T.det;
     const int nt = T.n_times;
-    int lo = 0, hi = nt;                       // first k with t_k >= t0
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (Geo<R>::tmeas(T, mid) < t0) lo = mid + 1;
-        else hi = mid;
+    // first k with t_k >= t0: found once per particle, then carried from segment to segment (a
+    // particle's time only grows, and each segment starts where the previous one ended)
+    int lo = cursor;
+    if (lo < 0) {
+        int hi = nt;
+        lo = 0;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (Geo<R>::tmeas(T, mid) < t0) lo = mid + 1;
+            else hi = mid;
+        }
     }
-    for (int k = lo; k < nt; ++k) {
+    int k = lo;
+    for (; k < nt; ++k) {
         const R tk = Geo<R>::tmeas(T, k);
         if (!(tk < t1)) break;
         const R dist = vm * (tk - t0);
@@ -487,6 +495,7 @@ __device__ __forceinline__ void tally_snap(const DevTab& T, const TallyCtx& tc, 
         if (mask & 4) tadd(tc, D, cc, 2, (double)(sg * (vm * o[1])));
         if (mask & 8) tadd(tc, D, cc, 3, (double)(sg * (vm * o[2])));
     }
+    cursor = k;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -797,10 +806,11 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         for (int a = 0; a < 3; ++a) {
             const R oa = p.o[a];
             const bool up = oa > R(0);
-            const bool valid = !(H.unb & (1u << a)) && (up || oa < R(0));
-            const R d = up ? r_div(H.L[a] - p.x[a], oa) : r_div(R(0) - p.x[a], oa);
+            // (bitwise rather than short-circuit logic: selects, no branches)
+            const bool valid = ((H.unb >> a) & 1u) == 0u && (up | (oa < R(0)));
+            const R d = r_div(up ? H.L[a] - p.x[a] : R(0) - p.x[a], oa);
             const int id = face_id(a, up ? 1 : 0);
-            const bool better = valid && (d < db || (d == db && id < hit));
+            const bool better = valid & ((d < db) | ((d == db) & (id < hit)));
             db = better ? d : db;
             hit = better ? id : hit;
         }
@@ -820,9 +830,9 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             const R qc = dx * dx + dy * dy - rr * rr;
             const R disc = qb * qb - qa * qc;
             // the ray meets the circle while approaching its centre: qb < 0, disc >= 0
-            const bool meets = qb < R(0) && disc >= R(0);
+            const bool meets = (qb < R(0)) & (disc >= R(0));
             const R d = (qc < R(0)) ? R(0) : r_div(qc, -qb + r_sqrt(disc >= R(0) ? disc : R(0)));
-            const bool better = meets && d < db;
+            const bool better = meets & (d < db);
             db = better ? d : db;
             hit = better ? id : hit;
             pore = better ? c : pore;
@@ -840,7 +850,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         const R dt = (ev == 0) ? p.dtr : (ev == 1 ? r_div(d, vm) : tmax - p.t);
         const R t_end = (ev == 2) ? tmax : p.t + dt;
         if (TK == TALLY_TRANSIENT) {
-            tally_snap(T, tc, p.x, p.o, p.t, t_end, vm, sg);
+            tally_snap(T, tc, p.x, p.o, p.t, t_end, vm, sg, p.tk);
         } else {
             if (TK == TALLY_STEADY_ONE) {
                 if (ACC && chain) {
@@ -1457,6 +1467,7 @@ __device__ __forceinline__ void start_particle(const DevTab& T, const LaunchArgs
     uint32_t rej = 0;
     if ((FT & FT_STATE) && a.state) StateView<R>((void*)a.state, a.capacity).load(pid - a.first_pid, p, rej);
     else emit_particle<R>(T, st, p, rej);
+    p.tk = -1;
     cnt.c[0] += 1;
     cnt.c[11] += rej;
     lg.row = nullptr;
@@ -1691,6 +1702,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
                                         (uint32_t)((uint64_t)pid >> 32), inst_id};
                             uint32_t rej = 0;
                             emit_particle<R>(T, st, p, rej);
+                            p.tk = -1;
                             cnt.c[0] += 1;
                             cnt.c[11] += rej;
                             alive = true;
