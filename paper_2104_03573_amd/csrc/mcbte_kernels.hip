@@ -115,6 +115,9 @@ template <> struct Geo<double> {
     static __device__ __forceinline__ double dw(const DevDet& d, int a) { return d.w[a]; }
     // cell index of a coordinate: floor((x - lo) / w), exactly as the method's detector binning
     static __device__ __forceinline__ double cellf(const DevDet& d, int a, double x) { return floor((x - d.lo[a]) / d.w[a]); }
+    // the same from values held in registers: cell_scale is the width
+    static __device__ __forceinline__ double cell_scale(const DevDet& d, int a) { return d.w[a]; }
+    static __device__ __forceinline__ double cellf_of(double x, double lo, double sc) { return floor((x - lo) / sc); }
     static __device__ __forceinline__ double tmeas(const DevTab& t, int k) { return t.t_meas64[k]; }
     static __device__ __forceinline__ const double* v(const DevTab& t) { return t.v64; }
     static __device__ __forceinline__ const double* tau(const DevTab& t) { return t.tau64; }
@@ -131,6 +134,9 @@ template <> struct Geo<float> {
     static __device__ __forceinline__ float dhi(const DevDet& d, int a) { return d.hi32[a]; }
     static __device__ __forceinline__ float dw(const DevDet& d, int a) { return (float)d.w[a]; }
     static __device__ __forceinline__ float cellf(const DevDet& d, int a, float x) { return floorf((x - d.lo32[a]) * d.inv_w32[a]); }
+    // the same from values held in registers: cell_scale is the inverse width
+    static __device__ __forceinline__ float cell_scale(const DevDet& d, int a) { return d.inv_w32[a]; }
+    static __device__ __forceinline__ float cellf_of(float x, float lo, float sc) { return floorf((x - lo) * sc); }
     static __device__ __forceinline__ float tmeas(const DevTab& t, int k) { return t.t_meas32[k]; }
     static __device__ __forceinline__ const float* v(const DevTab& t) { return t.v32; }
     static __device__ __forceinline__ const float* tau(const DevTab& t) { return t.tau32; }
@@ -362,11 +368,26 @@ __device__ __forceinline__ void tally_grid(const DevTab& T, const TallyCtx& tc, 
 {
     const DevDet& D = T.det;
     if (!(d > R(0))) return;
+    // the detector grid, read once per segment
+    int gn[3];
+    R glo[3], ghi[3], gw[3], gsc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        gn[a] = D.n[a];
+        glo[a] = Geo<R>::dlo(D, a);
+        ghi[a] = Geo<R>::dhi(D, a);
+        gw[a] = Geo<R>::dw(D, a);
+        gsc[a] = Geo<R>::cell_scale(D, a);
+    }
+    const int mask = D.mask, ncomp = D.ncomp, n_cols = D.n_cols;
+    uint32_t slots = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) slots |= ((uint32_t)D.slot[q] & 0xFFu) << (8 * q);
     R s_lo = R(0), s_hi = d;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (D.n[a] <= 0) continue;
-        const R lo = Geo<R>::dlo(D, a), hi = Geo<R>::dhi(D, a);
+        if (gn[a] <= 0) continue;
+        const R lo = glo[a], hi = ghi[a];
         if (o[a] == R(0)) {
             if (x0[a] < lo || x0[a] > hi) return;
         } else {
@@ -385,14 +406,13 @@ __device__ __forceinline__ void tally_grid(const DevTab& T, const TallyCtx& tc, 
     for (int a = 0; a < 3; ++a) {
         jn[a] = 0;
         sn[a] = INF;
-        const int n = D.n[a];
+        const int n = gn[a];
         if (n <= 1 || o[a] == R(0)) continue;
-        const R lo = Geo<R>::dlo(D, a), w = Geo<R>::dw(D, a);
+        const R lo = glo[a], w = gw[a];
         const int dir = o[a] > R(0) ? 1 : -1;
-        // guess from the entry point, then correct so that j is the first plane (in travel
-        // order) whose parameter exceeds s_lo
         // entry cell (clamped: a segment may start exactly on the outer faces of the grid), then
-        // the plane ahead of it
+        // the plane ahead of it, corrected so that j is the first plane (in travel order) whose
+        // parameter exceeds s_lo
         const R xs = x0[a] + o[a] * s_lo;
         int ic = (int)floor((double)((xs - lo) / w));
         ic = ic < 0 ? 0 : (ic > n - 1 ? n - 1 : ic);
@@ -421,17 +441,17 @@ __device__ __forceinline__ void tally_grid(const DevTab& T, const TallyCtx& tc, 
             int64_t cell = 0;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const int n = D.n[a] > 0 ? D.n[a] : 1;
+                const int n = gn[a] > 0 ? gn[a] : 1;
                 int64_t ci = 0;
-                if (D.n[a] > 0) {
+                if (gn[a] > 0) {
                     const R xa = x0[a] + o[a] * mid;
-                    const R f = Geo<R>::cellf(D, a, xa);
+                    const R f = Geo<R>::cellf_of(xa, glo[a], gsc[a]);
                     ci = (int64_t)f;
                     ci = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
                 }
                 cell = cell * n + ci;
             }
-            add4(tc, D, cell * D.n_cols + m, sg, l, vm, o);
+            add4_c(tc, mask, ncomp, slots, cell * n_cols + m, sg, l, vm, o);
         }
         if (!(s_n < s_hi)) break;
 #pragma unroll
@@ -440,15 +460,13 @@ __device__ __forceinline__ void tally_grid(const DevTab& T, const TallyCtx& tc, 
                 const int dir = o[a] > R(0) ? 1 : -1;
                 jn[a] += dir;
                 const int j = jn[a];
-                sn[a] = (j >= 1 && j <= D.n[a] - 1)
-                            ? r_div(Geo<R>::dlo(D, a) + (R)j * Geo<R>::dw(D, a) - x0[a], o[a]) : INF;
+                sn[a] = (j >= 1 && j <= gn[a] - 1) ? r_div(glo[a] + (R)j * gw[a] - x0[a], o[a]) : INF;
             }
         }
         s_cur = s_n;
     }
 }
 
-// transient snapshot estimator (Eq. sampling): every measurement time t_k in [t0, t1)
 template <typename R>
 __device__ __forceinline__ void tally_snap(const DevTab& T, const TallyCtx& tc, const R x0[3], const R o[3], R t0, R t1,
                                            R vm, R sg, int32_t& cursor)
