@@ -770,14 +770,137 @@ struct PathCtx {
     }
 };
 
+// The segments of a lane that is the last one live in its wave, up to its next event that is
+// neither a transfer through a periodic face nor a diffuse or specular reflection off the pore
+// (these leave the mode and the remaining flight as they were): the faces the ray moves toward
+// are fixed while the direction is, so the loop keeps only positions, times, the direction and
+// the particle's scores, and the steady tally terms (one mode throughout) are summed here and
+// added once.  Every quantity is computed as the one-segment step computes it, so the trajectory is the
+// same; the next event (found again by the caller) is left to that step.  Lanes that share a wave
+// take one segment per trace-loop pass instead, so that a long chain in one lane does not hold up
+// the others.  Returns true if the particle left the box on the way (the caller ends it).
+template <typename R>
+__device__ __forceinline__ bool lone_chain(const Hot<R>& H, const TallyCtx& tc, const Stream& st, Part<R>& p,
+                                           LaneCounts& cnt, R vm, R sg)
+{
+    if (H.n_pores > 1) return false;
+    const uint32_t pcls = H.pcls & 3u;       // the pore's reflection class
+    const bool pore_walk = H.n_pores == 1 && pcls != SURF_PARTIAL;
+    bool ok[3], up[3], per[3];
+    int fid[3];
+    R os, qa;
+    // the faces the ray moves toward, fixed while the direction is
+    auto aim = [&]() {
+        bool any = pore_walk;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const R oa = p.o[a];
+            up[a] = oa > R(0);
+            ok[a] = ((H.unb >> a) & 1u) == 0u && (up[a] | (oa < R(0)));
+            fid[a] = face_id(a, up[a] ? 1 : 0);
+            per[a] = ((H.face >> (4 * (fid[a] - 1))) & 3u) == 3u;
+            any = any | (ok[a] & per[a]);
+        }
+        const int sa = H.score_axis;
+        os = sa == 0 ? p.o[0] : (sa == 1 ? p.o[1] : p.o[2]);
+        qa = p.o[0] * p.o[0] + p.o[1] * p.o[1];
+        return any;
+    };
+    if (!aim()) return false;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    uint32_t n = 0;
+    bool escaped = false;
+    for (;;) {
+        if (p.k >= (uint32_t)H.max_events) break;
+        const R ds = vm * p.dtr;
+        R db = R(1) / R(0);
+        int hit = 0, ax = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const R d = r_div(up[a] ? H.L[a] - p.x[a] : R(0) - p.x[a], p.o[a]);
+            const bool better = ok[a] & ((d < db) | ((d == db) & (fid[a] < hit)));
+            db = better ? d : db;
+            hit = better ? fid[a] : hit;
+            ax = better ? a : ax;
+        }
+        bool at_pore = false;
+        if (H.n_pores == 1) {
+            const R dx = p.x[0] - H.p0cx, dy = p.x[1] - H.p0cy, rr = H.p0r;
+            const R qb = dx * p.o[0] + dy * p.o[1];
+            const R qc = dx * dx + dy * dy - rr * rr;
+            const R disc = qb * qb - qa * qc;
+            const R d = (qc < R(0)) ? R(0) : r_div(qc, -qb + r_sqrt(disc >= R(0) ? disc : R(0)));
+            at_pore = (qb < R(0)) & (disc >= R(0)) & (d < db);
+            db = at_pore ? d : db;
+        }
+        // a transfer through a periodic face, or a reflection off the pore (diffuse or specular),
+        // before the flight ends; anything else is left to the one-segment step
+        const bool go = (db <= ds) & (at_pore ? pore_walk : ((hit > 0) & (ax == 0 ? per[0] : (ax == 1 ? per[1] : per[2]))));
+        if (!go) break;
+        const R d = db;
+        const R dt = r_div(d, vm);
+        if (d > R(0)) {
+            acc[0] += (double)(sg * r_div(d, vm));
+            acc[1] += (double)(sg * (d * p.o[0]));
+            acc[2] += (double)(sg * (d * p.o[1]));
+            acc[3] += (double)(sg * (d * p.o[2]));
+        }
+        p.cT += (double)(sg * r_div(d, vm));
+        p.cq += (double)(sg * (d * os));
+        ++cnt.c[1];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p.x[a] = p.x[a] + d * p.o[a];
+        p.t = p.t + dt;
+        const R r = p.dtr - dt;
+        p.dtr = r > R(0) ? r : R(0);
+        p.k += 1;
+        ++n;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const R L = H.L[a];
+            if (!at_pore && a == ax) p.x[a] = up[a] ? L : R(0);    // exactly on the face
+            if (!((H.unb >> a) & 1u) && (p.x[a] < R(-1e-9) * L || p.x[a] > L + R(1e-9) * L)) escaped = true;
+        }
+        if (escaped) break;
+        if (!at_pore) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (a == ax) p.x[a] = up[a] ? R(0) : H.L[a];   // reinserted at the partner face
+            ++cnt.c[5];
+            continue;
+        }
+        // reflection off the pore, as the one-segment step makes it
+        const R n0 = r_div(p.x[0] - H.p0cx, H.p0r), n1 = r_div(p.x[1] - H.p0cy, H.p0r);
+        if (pcls == SURF_DIFFUSE) {
+            p.j += 1;
+            const W4 w1 = st.block(2u * (2u + p.j) + 1u);
+            const R u1 = unif<R>(w1.x, w1.y), u2 = unif<R>(w1.z, w1.w);
+            const R mu = r_sqrt(u1), sth = r_sqrt(R(1) - u1);
+            R sn, cs;
+            r_sincos_2pi(u2, &sn, &cs);
+            const R n[3] = {n0, n1, R(0)};
+            dir_about(mu, sth * cs, sth * sn, n, p.o);
+            ++cnt.c[4];
+        } else {
+            const R k2 = R(2) * (p.o[0] * n0 + p.o[1] * n1 + p.o[2] * R(0));
+            p.o[0] = p.o[0] - k2 * n0;
+            p.o[1] = p.o[1] - k2 * n1;
+            p.o[2] = p.o[2] - k2 * R(0);
+            ++cnt.c[3];
+        }
+        aim();
+    }
+    if (n > 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if ((H.det_mask >> q) & 1) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)p.m, q, acc[q]);
+    }
+    return escaped;
+}
+
 // Advance particle p by one segment; returns true when the particle has ended.  With `chain`
-// set (the lane is the last one of its wave still tracing), segments that end in a transfer
-// through a periodic face, which leaves mode, direction and remaining flight as they were, are
-// followed by the next one in the same call, up to an event of another kind: the lone lane then
-// skips the wave-level work of the trace loop between them.  Lanes that share a wave take one
-// segment per call, so that a long chain of transfers in one lane does not hold up the others
-// (as do all lanes of the pathwise replay, whose state leaves no registers for the chain).
-// AK: 0 trace, 1 likelihood-ratio replay, 2 pathwise replay, 3 local pathwise replay.
+// set (the lane is the last one of its wave still tracing), the transfers through periodic faces
+// ahead of it run first in lone_chain.  AK: 0 trace, 1 likelihood-ratio replay, 2 pathwise replay, 3 local pathwise replay.
 template <typename R, int TK, int AK, int FT>
 __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const Tabs<R>& tb, const TallyCtx& tc,
                                        const Stream& st, Part<R>& p, LaneCounts& cnt, LogRow& lg, bool& coop,
@@ -789,20 +912,16 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     int hit, pore, ev, fa, fs;
     R pcx, pcy, pr;                      // centre and radius of the pore hit
     uint32_t fcode;
-    // a chain of segments (one mode, one direction) of the FP32 trajectories sums its steady
-    // tally terms here and adds them to the tally once, where it ends
-    constexpr bool ACC = TK == TALLY_STEADY_ONE && AK != 2 && std::is_same<R, float>::value;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    auto flush_acc = [&]() {
-        if (ACC && chain) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if ((H.det_mask >> q) & 1) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)p.m, q, acc[q]);
+    if constexpr (TK == TALLY_STEADY_ONE && AK != 2 && (FT & FT_LOG) == 0) {
+        if (chain && lone_chain<R>(H, tc, st, p, cnt, vm, sg)) {   // left the box on the way
+            ++cnt.c[10];
+            if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
+                adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+            return true;
         }
-    };
+    }
     for (;;) {
         if (p.k >= (uint32_t)H.max_events) {
-            flush_acc();
             ++cnt.c[9];
             lg.put(EV_CAP, 0, p.m);
             if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
@@ -871,16 +990,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             tally_snap(T, tc, p.x, p.o, p.t, t_end, vm, sg, p.tk);
         } else {
             if (TK == TALLY_STEADY_ONE) {
-                if (ACC && chain) {
-                    if (d > R(0)) {
-                        acc[0] += (double)(sg * r_div(d, vm));
-                        acc[1] += (double)(sg * (d * p.o[0]));
-                        acc[2] += (double)(sg * (d * p.o[1]));
-                        acc[3] += (double)(sg * (d * p.o[2]));
-                    }
-                } else if (d > R(0)) {
-                    add4_c(tc, H.det_mask, H.det_ncomp, H.det_slot, (int64_t)p.m, sg, d, vm, p.o);
-                }
+                if (d > R(0)) add4_c(tc, H.det_mask, H.det_ncomp, H.det_slot, (int64_t)p.m, sg, d, vm, p.o);
             } else {
                 tally_grid(T, tc, p.x, p.o, d, p.m, sg, vm);
             }
@@ -901,7 +1011,6 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         }
         p.k += 1;
         if (ev == 2) {
-            flush_acc();
             ++cnt.c[7];
             lg.put(EV_TIMEOUT, 0, p.m);
             if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
@@ -941,7 +1050,6 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             }
         }
         if (escaped) {
-            flush_acc();
             ++cnt.c[10];
             lg.put(EV_ESCAPE, 0, p.m);
             if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
@@ -949,17 +1057,14 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             if (AK == 2) pc.flush(adj.bins, p.s, H.score_axis, adj.bad);
             return true;
         }
-        if (!periodic) {
-            flush_acc();
-            break;
-        }
+        if (!periodic) break;
         // linearised periodic condition: reinsert unchanged at the partner face
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             if (a == fa) p.x[a] = fs ? R(0) : H.L[a];
         ++cnt.c[5];
         lg.put(EV_PERIODIC, hit, p.m);
-        if (AK == 2 || !chain) return false;
+        return false;
     }
     // what the event needs
     bool relax = (ev == 0);
@@ -1734,10 +1839,11 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
                 continue;
             }
             ++since_refill;
-            const bool lone = exhausted && (live & (live - 1ull)) == 0ull;
             bool coop = false;
             if (alive) {
-                if (flight<R, TK, 0, 0>(T, H, tb, tc, st, p, cnt, lg, coop, adj, pc, lone)) {
+                // (no lone-lane chains here: their registers would cost the film sweeps, for which
+                // this kernel exists, an occupancy step)
+                if (flight<R, TK, 0, 0>(T, H, tb, tc, st, p, cnt, lg, coop, adj, pc, false)) {
                     end_particle(p, T.transient, mom, lg);
                     alive = false;
                 }
