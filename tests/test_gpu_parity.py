@@ -284,6 +284,27 @@ def test_fp64_long_pore_lattice_walks_independent_of_launch_shape():
     assert base["counts"]["periodic"] > 20 * n
 
 
+@pytest.mark.parametrize("spec", [0.0, 1.0, 0.5])
+@pytest.mark.parametrize("precision", [64, 32])
+def test_lone_lane_walk_matches_one_segment_steps(precision, spec):
+    """Free paths of 20 um in the pore cell, 300 particles (few per wave): the last live lane of
+    a wave runs its periodic transfers and diffuse or specular pore reflections in the lone-lane
+    loop (a partly specular pore stops it), the event-logging launch takes one segment per step.
+    Both give the same counters and the same particle scores; the tally sums agree to rounding."""
+    M = _pkg()
+    w = W.with_(W.porous_cell(N=300, modes=W.gray_modes(6400.0, 20e-6 / 6400.0), n_scat_max=3,
+                              specularity=spec), **{"problem.format": 2})
+    plain = M.run(w, precision=precision)
+    other = M.run(w, precision=precision, block=64, refill=1)
+    logged = M.run(w, precision=precision, n_log=300, log_stride=16)
+    for r in (other, logged):
+        assert np.array_equal(r["counts_raw"], plain["counts_raw"])
+        scale = np.abs(plain["raw"]).max()
+        assert np.abs(r["raw"] - plain["raw"]).max() <= 1e-12 * scale
+        assert np.allclose(r["moments"], plain["moments"], rtol=1e-12, atol=1e-12 * np.abs(plain["moments"]).max())
+    assert plain["counts"]["periodic"] > 20 * 300
+
+
 def test_fp32_transient_wide_kernel_against_fp64_oracle():
     """The transient bump with its full snapshot detector (100 bins x 200 times, too large for a
     per-workgroup FP64 copy): the FP32 kernel sums it per workgroup in FP32 in LDS.  Each particle
