@@ -130,6 +130,7 @@ struct LaunchArgs {
     int64_t n_chunks;
     int32_t tally_lds;           // tallies privatised in LDS
     int32_t lds_tab_bytes;       // offset of the tally region in dynamic LDS
+    int32_t lds_tmeas;           // offset of the staged measurement times in dynamic LDS (0: not staged)
     // sensitivity replay
     double* particle_F;          // per-particle flux score (written by the trace, read by the replay)
     double* adj;                 // n_bins sums, the relaxation-draw sum B, then a work counter

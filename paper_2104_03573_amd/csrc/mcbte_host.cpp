@@ -575,6 +575,7 @@ struct LaunchPlan {
     int block, grid, refill;
     int tally_lds;
     int64_t lds_tab;
+    int64_t lds_tmeas;           // offset of the staged measurement times (0: none)
     size_t lds;
 };
 
@@ -606,6 +607,16 @@ int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run,
     } else {
         lp.tally_lds = (lds_tally <= MCBTE_LDS_TALLY_BYTES && lds_tab + lds_tally <= t0->max_lds) ? 1 : 0;
         lp.lds = (size_t)(lds_tab + (lp.tally_lds ? lds_tally : 0));
+    }
+    // a solo transient trace also stages its measurement times after the tally where they fit
+    lp.lds_tmeas = 0;
+    if (mode == 0 && n_inst == 1 && t0->host_view.tally_kind == TALLY_TRANSIENT) {
+        const int64_t off = ((int64_t)lp.lds + 15) & ~int64_t(15);
+        const int64_t end = off + (int64_t)t0->host_view.n_times * rb;
+        if (off > 0 && end <= t0->max_lds) {
+            lp.lds_tmeas = off;
+            lp.lds = (size_t)end;
+        }
     }
     const int max_block = (ft & FT_WIDE) ? 1024 : 256;
     lp.block = run->block > 0 ? run->block : max_block;
@@ -664,6 +675,7 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     a.n_log = run->event_log ? run->n_log : 0;
     a.tally_lds = lp.tally_lds;
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
+    a.lds_tmeas = (int32_t)lp.lds_tmeas;
     a.particle_F = run->particle_F;
     const hipError_t e = launch_trace(a, 0, run->precision, t->host_view.tally_kind, ft, lp.block, lp.grid, lp.lds,
                                       (hipStream_t)stream);

@@ -119,6 +119,7 @@ template <> struct Geo<double> {
     static __device__ __forceinline__ double cell_scale(const DevDet& d, int a) { return d.w[a]; }
     static __device__ __forceinline__ double cellf_of(double x, double lo, double sc) { return floor((x - lo) / sc); }
     static __device__ __forceinline__ double tmeas(const DevTab& t, int k) { return t.t_meas64[k]; }
+    static __device__ __forceinline__ const double* tmeas_ptr(const DevTab& t) { return t.t_meas64; }
     static __device__ __forceinline__ const double* v(const DevTab& t) { return t.v64; }
     static __device__ __forceinline__ const double* tau(const DevTab& t) { return t.tau64; }
     static __device__ __forceinline__ const DevPore64& pore(const DevGeom& g, int i) { return g.pore64[i]; }
@@ -138,6 +139,7 @@ template <> struct Geo<float> {
     static __device__ __forceinline__ float cell_scale(const DevDet& d, int a) { return d.inv_w32[a]; }
     static __device__ __forceinline__ float cellf_of(float x, float lo, float sc) { return floorf((x - lo) * sc); }
     static __device__ __forceinline__ float tmeas(const DevTab& t, int k) { return t.t_meas32[k]; }
+    static __device__ __forceinline__ const float* tmeas_ptr(const DevTab& t) { return t.t_meas32; }
     static __device__ __forceinline__ const float* v(const DevTab& t) { return t.v32; }
     static __device__ __forceinline__ const float* tau(const DevTab& t) { return t.tau32; }
     static __device__ __forceinline__ const DevPore32& pore(const DevGeom& g, int i) { return g.pore32[i]; }
@@ -468,50 +470,64 @@ __device__ __forceinline__ void tally_grid(const DevTab& T, const TallyCtx& tc, 
 }
 
 template <typename R>
-__device__ __forceinline__ void tally_snap(const DevTab& T, const TallyCtx& tc, const R x0[3], const R o[3], R t0, R t1,
-                                           R vm, R sg, int32_t& cursor)
+__device__ __forceinline__ void tally_snap(const DevTab& T, const TallyCtx& tc, const R* tmeas, const R x0[3],
+                                           const R o[3], R t0, R t1, R vm, R sg, int32_t& cursor)
 {
     const DevDet& D = T.det;
     const int nt = T.n_times;
     // first k with t_k >= t0: found once per particle, then carried from segment to segment (a
     // particle's time only grows, and each segment starts where the previous one ended)
-    int lo = cursor;
-    if (lo < 0) {
+    int k = cursor;
+    if (k < 0) {
         int hi = nt;
-        lo = 0;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (Geo<R>::tmeas(T, mid) < t0) lo = mid + 1;
+        k = 0;
+        while (k < hi) {
+            const int mid = (k + hi) >> 1;
+            if (tmeas[mid] < t0) k = mid + 1;
             else hi = mid;
         }
     }
-    int k = lo;
-    for (; k < nt; ++k) {
-        const R tk = Geo<R>::tmeas(T, k);
-        if (!(tk < t1)) break;
-        const R dist = vm * (tk - t0);
-        int64_t cell = 0;
-        bool inside = true;
+    if (k < nt && tmeas[k] < t1) {
+        // the detector grid, read once for the segment's snapshots
+        int gn[3];
+        R glo[3], ghi[3], gsc[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const int n = D.n[a] > 0 ? D.n[a] : 1;
-            int64_t ci = 0;
-            if (D.n[a] > 0) {
-                const R xa = x0[a] + o[a] * dist;
-                if (xa < Geo<R>::dlo(D, a) || xa > Geo<R>::dhi(D, a)) inside = false;
-                const R f = Geo<R>::cellf(D, a, xa);
-                ci = (int64_t)f;
-                ci = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
-            }
-            cell = cell * n + ci;
+            gn[a] = D.n[a];
+            glo[a] = Geo<R>::dlo(D, a);
+            ghi[a] = Geo<R>::dhi(D, a);
+            gsc[a] = Geo<R>::cell_scale(D, a);
         }
-        if (!inside) continue;
-        const int64_t cc = cell * D.n_cols + k;
-        const int mask = D.mask;
-        if (mask & 1) tadd(tc, D, cc, 0, (double)sg);
-        if (mask & 2) tadd(tc, D, cc, 1, (double)(sg * (vm * o[0])));
-        if (mask & 4) tadd(tc, D, cc, 2, (double)(sg * (vm * o[1])));
-        if (mask & 8) tadd(tc, D, cc, 3, (double)(sg * (vm * o[2])));
+        const int mask = D.mask, ncomp = D.ncomp, n_cols = D.n_cols;
+        uint32_t slots = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) slots |= ((uint32_t)D.slot[q] & 0xFFu) << (8 * q);
+        for (; k < nt; ++k) {
+            const R tk = tmeas[k];
+            if (!(tk < t1)) break;
+            const R dist = vm * (tk - t0);
+            int64_t cell = 0;
+            bool inside = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int n = gn[a] > 0 ? gn[a] : 1;
+                int64_t ci = 0;
+                if (gn[a] > 0) {
+                    const R xa = x0[a] + o[a] * dist;
+                    if (xa < glo[a] || xa > ghi[a]) inside = false;
+                    const R f = Geo<R>::cellf_of(xa, glo[a], gsc[a]);
+                    ci = (int64_t)f;
+                    ci = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
+                }
+                cell = cell * n + ci;
+            }
+            if (!inside) continue;
+            const int64_t cc = cell * n_cols + k;
+            if (mask & 1) tadd_c(tc, ncomp, slots, cc, 0, (double)sg);
+            if (mask & 2) tadd_c(tc, ncomp, slots, cc, 1, (double)(sg * (vm * o[0])));
+            if (mask & 4) tadd_c(tc, ncomp, slots, cc, 2, (double)(sg * (vm * o[1])));
+            if (mask & 8) tadd_c(tc, ncomp, slots, cc, 3, (double)(sg * (vm * o[2])));
+        }
     }
     cursor = k;
 }
@@ -573,6 +589,7 @@ struct Tabs {
     const R* v;                // LDS
     const R* tau;              // LDS
     const uint32_t* guide;     // LDS: bounds of the relaxation draw, or NULL (search the whole table)
+    const R* tmeas;            // measurement times (transient tallies): LDS where staged, else the table block
 };
 
 // The launch-uniform values the flight loop reads, loaded once before it so that they stay in
@@ -987,7 +1004,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         const R dt = (ev == 0) ? p.dtr : (ev == 1 ? r_div(d, vm) : tmax - p.t);
         const R t_end = (ev == 2) ? tmax : p.t + dt;
         if (TK == TALLY_TRANSIENT) {
-            tally_snap(T, tc, p.x, p.o, p.t, t_end, vm, sg, p.tk);
+            tally_snap(T, tc, tb.tmeas, p.x, p.o, p.t, t_end, vm, sg, p.tk);
         } else {
             if (TK == TALLY_STEADY_ONE) {
                 if (d > R(0)) add4_c(tc, H.det_mask, H.det_ncomp, H.det_slot, (int64_t)p.m, sg, d, vm, p.o);
@@ -1529,7 +1546,7 @@ __device__ __forceinline__ Tabs<R> stage_tables(const DevTab& T, unsigned char* 
     }
     if (T.rel_guide)
         for (int i = threadIdx.x; i < 256; i += blockDim.x) s_guide[i] = T.rel_guide[i];
-    return Tabs<R>{s_thr, s_v, s_tau, T.rel_guide ? s_guide : nullptr};
+    return Tabs<R>{s_thr, s_v, s_tau, T.rel_guide ? s_guide : nullptr, Geo<R>::tmeas_ptr(T)};
 }
 
 __device__ __forceinline__ int64_t lds_tally_size(const DevTab& T) { return T.det.n_cells * T.det.n_cols * T.det.ncomp; }
@@ -1624,7 +1641,13 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
     const DevTab& T = tabs[0];
     const Hot<R> H = load_hot<R>(T);
     constexpr bool WIDE = (FT & FT_WIDE) != 0;
-    const Tabs<R> tb = WIDE ? Tabs<R>{T.thr_rel, Geo<R>::v(T), Geo<R>::tau(T), T.rel_guide} : stage_tables<R>(T, smem);
+    Tabs<R> tb = WIDE ? Tabs<R>{T.thr_rel, Geo<R>::v(T), Geo<R>::tau(T), T.rel_guide, Geo<R>::tmeas_ptr(T)}
+                      : stage_tables<R>(T, smem);
+    if (TK == TALLY_TRANSIENT && a.lds_tmeas > 0) {     // the measurement times, where the LDS has room
+        R* s_tm = (R*)(smem + a.lds_tmeas);
+        for (int i = threadIdx.x; i < T.n_times; i += blockDim.x) s_tm[i] = tb.tmeas[i];
+        tb.tmeas = s_tm;
+    }
     double* s_tally = (double*)(smem + a.lds_tab_bytes);
     float* s_tally32 = (float*)smem;
     constexpr bool ADJ = AK != 0;
