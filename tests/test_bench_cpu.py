@@ -1,0 +1,42 @@
+"""The benchmark's host-side contract (no GPU): the one-GPU guard and the algorithmic work model
+behind its roofline figure."""
+import math
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_algorithmic_work_model_counts_each_event_once():
+    import bench
+    O = bench.OPS
+    info = {"n_modes": 1400, "n_sources": 3}
+    geom = {"unbounded": (True, True, False), "cylinders": []}
+    counts = {"particles": 10, "flights": 100, "relaxations": 60, "nscat_end": 10, "diffuse": 30,
+              "rejections": 2}
+    got = bench.algorithmic_lane_ops(counts, info, geom, ncomp=2, transient=False)
+    steps_m, steps_s = math.ceil(math.log2(1401)), math.ceil(math.log2(4))
+    emit = 10 * (4 * O["philox_block"] + (steps_s + steps_m) * O["search_step"] + O["cos_dir"]
+                 + O["free_flight"] + O["emit_misc"])
+    flights = 100 * (O["flight_base"] + 1 * O["face_axis"] + 2 * O["tally_comp"])
+    relax = 50 * (2 * O["philox_block"] + steps_m * O["search_step"] + O["iso_dir"] + O["free_flight"])
+    diffuse = 30 * (O["philox_block"] + O["cos_dir"])
+    assert got == emit + flights + relax + diffuse + 2 * 2 * O["philox_block"]
+    # a pore adds its ray test to every flight
+    geom2 = {"unbounded": (False, False, False), "cylinders": [(0, 0, 1, 7, 2, 0.0)]}
+    got2 = bench.algorithmic_lane_ops(counts, info, geom2, ncomp=2, transient=False)
+    assert got2 - got == 100 * (2 * O["face_axis"] + O["pore"])
+
+
+def test_traffic_figure_is_withheld_for_an_unprofiled_kernel():
+    import bench
+    assert bench.profiled_traffic("no_such_kernel_profile") is None
