@@ -413,6 +413,16 @@ def other_forms(args, M, torch) -> dict:
         w, wname = workload(name, 1.0)
         print(f"[bench] form {key}: {wname}", file=sys.stderr, flush=True)
         forms[key] = _brief(measure(args, w, M, torch, prec, steps, 1, 1, 1_000_000, 1), wname, prec)
+    # the main line's launches each end with a tail (the last particles of every wave, one
+    # flight after another) of about half a launch; a job of many batches overlaps one batch's
+    # tail with the next batch on a second stream (throughput by wall clock, no roofline figure)
+    w, wname = workload("film", 1.0)
+    print(f"[bench] form film_fp32_two_streams: {wname}", file=sys.stderr, flush=True)
+    mf = measure(args, w, M, torch, 32, 20, 3, 2, 1_000_000, 1)
+    forms["film_fp32_two_streams"] = {
+        "workload": wname, "precision": 32, "streams": 2, "steps": 20, "flights_per_s": mf["flights_per_s"],
+        "ms_per_step": mf["ms_per_step"], "launch": mf["launch"], "kappa_eff": mf.get("kappa_eff"),
+        "kappa_sigma": mf.get("kappa_sigma")}
     # the pore cell's step ends with the few particles of the longest mean free paths walking
     # through the lattice one segment at a time; a job of several batches overlaps one batch's
     # tail with the next batch on a second stream (throughput by wall clock; the per-launch
