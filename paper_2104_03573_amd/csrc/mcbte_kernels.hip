@@ -113,12 +113,10 @@ template <> struct Geo<double> {
     static __device__ __forceinline__ double dlo(const DevDet& d, int a) { return d.lo[a]; }
     static __device__ __forceinline__ double dhi(const DevDet& d, int a) { return d.hi[a]; }
     static __device__ __forceinline__ double dw(const DevDet& d, int a) { return d.w[a]; }
-    // cell index of a coordinate: floor((x - lo) / w), exactly as the method's detector binning
-    static __device__ __forceinline__ double cellf(const DevDet& d, int a, double x) { return floor((x - d.lo[a]) / d.w[a]); }
-    // the same from values held in registers: cell_scale is the width
+    // cell index of a coordinate, floor((x - lo) / w) exactly as the method's detector binning,
+    // from values held in registers: cell_scale is the width
     static __device__ __forceinline__ double cell_scale(const DevDet& d, int a) { return d.w[a]; }
     static __device__ __forceinline__ double cellf_of(double x, double lo, double sc) { return floor((x - lo) / sc); }
-    static __device__ __forceinline__ double tmeas(const DevTab& t, int k) { return t.t_meas64[k]; }
     static __device__ __forceinline__ const double* tmeas_ptr(const DevTab& t) { return t.t_meas64; }
     static __device__ __forceinline__ const double* v(const DevTab& t) { return t.v64; }
     static __device__ __forceinline__ const double* tau(const DevTab& t) { return t.tau64; }
@@ -134,11 +132,10 @@ template <> struct Geo<float> {
     static __device__ __forceinline__ float dlo(const DevDet& d, int a) { return d.lo32[a]; }
     static __device__ __forceinline__ float dhi(const DevDet& d, int a) { return d.hi32[a]; }
     static __device__ __forceinline__ float dw(const DevDet& d, int a) { return (float)d.w[a]; }
-    static __device__ __forceinline__ float cellf(const DevDet& d, int a, float x) { return floorf((x - d.lo32[a]) * d.inv_w32[a]); }
-    // the same from values held in registers: cell_scale is the inverse width
+    // cell index of a coordinate, floor((x - lo) / w), from values held in registers: cell_scale is
+    // the inverse width
     static __device__ __forceinline__ float cell_scale(const DevDet& d, int a) { return d.inv_w32[a]; }
     static __device__ __forceinline__ float cellf_of(float x, float lo, float sc) { return floorf((x - lo) * sc); }
-    static __device__ __forceinline__ float tmeas(const DevTab& t, int k) { return t.t_meas32[k]; }
     static __device__ __forceinline__ const float* tmeas_ptr(const DevTab& t) { return t.t_meas32; }
     static __device__ __forceinline__ const float* v(const DevTab& t) { return t.v32; }
     static __device__ __forceinline__ const float* tau(const DevTab& t) { return t.tau32; }
@@ -330,16 +327,6 @@ __device__ __forceinline__ void tadd(const TallyCtx& tc, const DevDet& D, int64_
     if (tc.lds32) atomicAdd(tc.lds32 + cc * D.ncomp + D.slot[q], (float)val);
     else if (tc.lds) atomicAdd(tc.lds + cc * D.ncomp + D.slot[q], val);
     else if (tc.glob) atomicAdd(tc.glob + cc * 4 + q, val);
-}
-
-template <typename R>
-__device__ __forceinline__ void add4(const TallyCtx& tc, const DevDet& D, int64_t cc, R sg, R l, R vm, const R o[3])
-{
-    const int mask = D.mask;
-    if (mask & 1) tadd(tc, D, cc, 0, (double)(sg * r_div(l, vm)));
-    if (mask & 2) tadd(tc, D, cc, 1, (double)(sg * (l * o[0])));
-    if (mask & 4) tadd(tc, D, cc, 2, (double)(sg * (l * o[1])));
-    if (mask & 8) tadd(tc, D, cc, 3, (double)(sg * (l * o[2])));
 }
 
 __device__ __forceinline__ void tadd_c(const TallyCtx& tc, int ncomp, uint32_t slots, int64_t cc, int q, double val)
