@@ -182,6 +182,10 @@ template <typename R> struct Part {
     R dtr0;              // free-flight time drawn for the current flight (sensitivity replay)
     double F0;           // flux score at the start of the current flight (sensitivity replay)
     int32_t tk;          // transient tallies: first measurement time not before t (-1: not yet known)
+    // transient tallies: the last segment's snapshots, scored by the whole wave after the step
+    // (start, direction, start time and speed of the segment; first measurement index and count)
+    R sx[3], so[3], st0, svm;
+    int32_t sk0, sn;
 };
 
 // cosine-weighted direction about the unit normal n (Eq. wall_dir), frame t1 = e_j x n / |.|
@@ -456,43 +460,98 @@ __device__ __forceinline__ void tally_grid(const DevTab& T, const TallyCtx& tc, 
     }
 }
 
+// Transient snapshot estimator (Eq. sampling): a particle alive at measurement time t_k scores
+// s (and s v Omega) into the detector cell holding x(t_k).  A segment [t0, t1) holds the times
+// t_k with t0 <= t_k < t1; the step only records them (snap_pend) and the whole wave then scores
+// the records of all its lanes together (snap_wave), 64 snapshots per pass however they are
+// spread over the lanes (a per-lane loop ran at 9 % lane efficiency: few lanes have many).
 template <typename R>
-__device__ __forceinline__ void tally_snap(const DevTab& T, const TallyCtx& tc, const R* tmeas, const R x0[3],
-                                           const R o[3], R t0, R t1, R vm, R sg, int32_t& cursor)
+__device__ __forceinline__ void snap_pend(const R* tmeas, int nt, Part<R>& p, R t1, R vm)
 {
-    const DevDet& D = T.det;
-    const int nt = T.n_times;
     // first k with t_k >= t0: found once per particle, then carried from segment to segment (a
     // particle's time only grows, and each segment starts where the previous one ended)
-    int k = cursor;
-    if (k < 0) {
+    int k0 = p.tk;
+    if (k0 < 0) {
         int hi = nt;
-        k = 0;
-        while (k < hi) {
-            const int mid = (k + hi) >> 1;
-            if (tmeas[mid] < t0) k = mid + 1;
+        k0 = 0;
+        while (k0 < hi) {
+            const int mid = (k0 + hi) >> 1;
+            if (tmeas[mid] < p.t) k0 = mid + 1;
             else hi = mid;
         }
     }
-    if (k < nt && tmeas[k] < t1) {
-        // the detector grid, read once for the segment's snapshots
-        int gn[3];
-        R glo[3], ghi[3], gsc[3];
+    int k1 = k0;                     // first k >= k0 with t_k >= t1
+    if (k1 < nt && tmeas[k1] < t1) {
+        int hi = nt;
+        ++k1;
+        while (k1 < hi) {
+            const int mid = (k1 + hi) >> 1;
+            if (tmeas[mid] < t1) k1 = mid + 1;
+            else hi = mid;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        p.sx[a] = p.x[a];
+        p.so[a] = p.o[a];
+    }
+    p.st0 = p.t;
+    p.svm = vm;
+    p.sk0 = k0;
+    p.sn = k1 - k0;
+    p.tk = k1;
+}
+
+template <typename R>
+__device__ __forceinline__ R lane_r(R v, int src) { return __shfl(v, src, 64); }
+
+template <typename R>
+__device__ __forceinline__ void snap_wave(const DevTab& T, const TallyCtx& tc, const R* tmeas, Part<R>& p)
+{
+    if (__ballot(p.sn > 0) == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    int S = p.sn;                    // inclusive prefix sum of the lanes' snapshot counts
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(S, off, 64);
+        if (lane >= off) S += t;
+    }
+    const int total = __shfl(S, 63, 64);
+    const DevDet& D = T.det;
+    int gn[3];
+    R glo[3], ghi[3], gsc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        gn[a] = D.n[a];
+        glo[a] = Geo<R>::dlo(D, a);
+        ghi[a] = Geo<R>::dhi(D, a);
+        gsc[a] = Geo<R>::cell_scale(D, a);
+    }
+    const int mask = D.mask, ncomp = D.ncomp, n_cols = D.n_cols;
+    uint32_t slots = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) slots |= ((uint32_t)D.slot[q] & 0xFFu) << (8 * q);
+    for (int base = 0; base < total; base += 64) {
+        const int g = base + lane;
+        int own = 0;                 // the lane whose records hold snapshot g: count of S_i <= g
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+            const int c = own + step - 1;
+            if (__shfl(S, c < 63 ? c : 63, 64) <= g) own += step;
+        }
+        own = own < 63 ? own : 63;
+        const int first = __shfl(S, own, 64) - __shfl(p.sn, own, 64);
+        const int k = __shfl(p.sk0, own, 64) + (g - first);
+        R x0[3], o[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            gn[a] = D.n[a];
-            glo[a] = Geo<R>::dlo(D, a);
-            ghi[a] = Geo<R>::dhi(D, a);
-            gsc[a] = Geo<R>::cell_scale(D, a);
+            x0[a] = lane_r<R>(p.sx[a], own);
+            o[a] = lane_r<R>(p.so[a], own);
         }
-        const int mask = D.mask, ncomp = D.ncomp, n_cols = D.n_cols;
-        uint32_t slots = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) slots |= ((uint32_t)D.slot[q] & 0xFFu) << (8 * q);
-        for (; k < nt; ++k) {
-            const R tk = tmeas[k];
-            if (!(tk < t1)) break;
-            const R dist = vm * (tk - t0);
+        const R t0 = lane_r<R>(p.st0, own), vm = lane_r<R>(p.svm, own);
+        const R sg = (R)__shfl(p.s, own, 64);
+        if (g < total) {
+            const R dist = vm * (tmeas[k] - t0);
             int64_t cell = 0;
             bool inside = true;
 #pragma unroll
@@ -508,15 +567,16 @@ __device__ __forceinline__ void tally_snap(const DevTab& T, const TallyCtx& tc, 
                 }
                 cell = cell * n + ci;
             }
-            if (!inside) continue;
-            const int64_t cc = cell * n_cols + k;
-            if (mask & 1) tadd_c(tc, ncomp, slots, cc, 0, (double)sg);
-            if (mask & 2) tadd_c(tc, ncomp, slots, cc, 1, (double)(sg * (vm * o[0])));
-            if (mask & 4) tadd_c(tc, ncomp, slots, cc, 2, (double)(sg * (vm * o[1])));
-            if (mask & 8) tadd_c(tc, ncomp, slots, cc, 3, (double)(sg * (vm * o[2])));
+            if (inside) {
+                const int64_t cc = cell * n_cols + k;
+                if (mask & 1) tadd_c(tc, ncomp, slots, cc, 0, (double)sg);
+                if (mask & 2) tadd_c(tc, ncomp, slots, cc, 1, (double)(sg * (vm * o[0])));
+                if (mask & 4) tadd_c(tc, ncomp, slots, cc, 2, (double)(sg * (vm * o[1])));
+                if (mask & 8) tadd_c(tc, ncomp, slots, cc, 3, (double)(sg * (vm * o[2])));
+            }
         }
     }
-    cursor = k;
+    p.sn = 0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -991,7 +1051,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         const R dt = (ev == 0) ? p.dtr : (ev == 1 ? r_div(d, vm) : tmax - p.t);
         const R t_end = (ev == 2) ? tmax : p.t + dt;
         if (TK == TALLY_TRANSIENT) {
-            tally_snap(T, tc, tb.tmeas, p.x, p.o, p.t, t_end, vm, sg, p.tk);
+            snap_pend<R>(tb.tmeas, T.n_times, p, t_end, vm);
         } else {
             if (TK == TALLY_STEADY_ONE) {
                 if (d > R(0)) add4_c(tc, H.det_mask, H.det_ncomp, H.det_slot, (int64_t)p.m, sg, d, vm, p.o);
@@ -1595,6 +1655,7 @@ __device__ __forceinline__ void start_particle(const DevTab& T, const LaunchArgs
     if ((FT & FT_STATE) && a.state) StateView<R>((void*)a.state, a.capacity).load(pid - a.first_pid, p, rej);
     else emit_particle<R>(T, st, p, rej);
     p.tk = -1;
+    p.sn = 0;
     cnt.c[0] += 1;
     cnt.c[11] += rej;
     lg.row = nullptr;
@@ -1658,6 +1719,8 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
     const unsigned long long n = (unsigned long long)a.n;
 
     Part<R> p;
+    p.sn = 0;                          // no pending snapshots (lanes that never hold a particle too)
+    p.tk = -1;
     Stream st{0u, 0u, 0u, 0u, 0u};
     LaneCounts cnt;
 #pragma unroll
@@ -1721,6 +1784,7 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
                     coop_exact(H, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt, lg);
             }
         }
+        if constexpr (TK == TALLY_TRANSIENT) snap_wave<R>(T, tc, tb.tmeas, p);
     }
     if (ADJ) {
         const double d = wave_sum<double>(adj.dense);
@@ -1807,6 +1871,8 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
         const TallyCtx tc{a.tally_lds ? s_tally : nullptr, (double*)(a.tallies[inst] + MCBTE_TALLY_HEADER_BYTES),
                           nullptr};
         Part<R> p;
+        p.sn = 0;
+        p.tk = -1;
         Stream st{0u, 0u, 0u, 0u, 0u};
         LogRow lg{nullptr, 0, 2};
         AdjCtx adj{nullptr, 0.0, 0.0, 0u, 0.0};
@@ -1836,6 +1902,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
                             uint32_t rej = 0;
                             emit_particle<R>(T, st, p, rej);
                             p.tk = -1;
+                            p.sn = 0;
                             cnt.c[0] += 1;
                             cnt.c[11] += rej;
                             alive = true;
@@ -1864,6 +1931,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
                         coop_bounces<R>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
                 }
             }
+            if constexpr (TK == TALLY_TRANSIENT) snap_wave<R>(T, tc, tb.tmeas, p);
         }
         __syncthreads();
     }
