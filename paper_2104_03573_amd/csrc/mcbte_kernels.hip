@@ -182,8 +182,9 @@ template <typename R> struct Part {
     R dtr0;              // free-flight time drawn for the current flight (sensitivity replay)
     double F0;           // flux score at the start of the current flight (sensitivity replay)
     int32_t tk;          // transient tallies: first measurement time not before t (-1: not yet known)
-    // transient tallies: the last segment's snapshots, scored by the whole wave after the step
-    // (start, direction, start time and speed of the segment; first measurement index and count)
+    // the last segment's scores left to the whole wave after the step: transient snapshots (start,
+    // direction, start time, speed; first measurement index, count) or, in a sparse wave, the
+    // detector-grid pieces (start, direction, length, speed; mode, pending flag)
     R sx[3], so[3], st0, svm;
     int32_t sk0, sn;
 };
@@ -654,6 +655,7 @@ struct Hot {
     int32_t n_pores, max_events, n_scat_max, M, last_rel, transient, score_axis, coop_axis;
     R p0cx, p0cy, p0r;   // the first pore (most geometries have at most one)
     int32_t p0id;
+    int32_t grid_axis;   // the one detector axis with more than one cell, if only one has (else -1)
 };
 
 template <typename R>
@@ -687,6 +689,11 @@ __device__ __forceinline__ Hot<R> load_hot(const DevTab& T)
     h.p0cy = P0.cy;
     h.p0r = P0.r;
     h.p0id = P0.id;
+    int na = 0, ax = -1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (T.det.n[a] > 1) { ++na; ax = a; }
+    h.grid_axis = na == 1 ? ax : -1;
     return h;
 }
 
@@ -834,6 +841,145 @@ struct PathCtx {
     }
 };
 
+// Detector-grid scores of the pending segments of a sparse wave, for grids with one axis of more
+// than one cell: the pieces of a segment lie between consecutive planes of that axis, each piece's
+// bounds are the plane parameters tally_grid computes one after another, so the wave evaluates 64
+// pieces per pass whichever lanes they belong to (a lone lane's flight across a 50-cell slab is
+// one pass instead of 50 steps).  Same pieces, lengths, cells and values as tally_grid.
+template <typename R>
+__device__ __forceinline__ void grid_wave(const DevTab& T, const Hot<R>& H, const TallyCtx& tc, Part<R>& p)
+{
+    if (__ballot(p.sn > 0) == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    const DevDet& D = T.det;
+    int gn[3];
+    R glo[3], ghi[3], gw[3], gsc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        gn[a] = D.n[a];
+        glo[a] = Geo<R>::dlo(D, a);
+        ghi[a] = Geo<R>::dhi(D, a);
+        gw[a] = Geo<R>::dw(D, a);
+        gsc[a] = Geo<R>::cell_scale(D, a);
+    }
+    const int mask = D.mask, ncomp = D.ncomp, n_cols = D.n_cols;
+    uint32_t slots = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) slots |= ((uint32_t)D.slot[q] & 0xFFu) << (8 * q);
+    const int A = H.grid_axis;
+    const int nA = A == 0 ? gn[0] : (A == 1 ? gn[1] : gn[2]);
+    const R loA = A == 0 ? glo[0] : (A == 1 ? glo[1] : glo[2]);
+    const R wA = A == 0 ? gw[0] : (A == 1 ? gw[1] : gw[2]);
+    // this lane's segment: the part inside the grid [s_lo, s_hi], its first plane j0 and the
+    // number of planes P it crosses (pieces: P + 1)
+    R s_lo = R(0), s_hi = R(0);
+    int j0 = 0, c = 0;
+    if (p.sn > 0) {
+        const R d = p.st0;
+        bool in = d > R(0);
+        s_hi = d;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (gn[a] <= 0) continue;
+            if (p.so[a] == R(0)) {
+                if (p.sx[a] < glo[a] || p.sx[a] > ghi[a]) in = false;
+            } else {
+                R s1 = r_div(glo[a] - p.sx[a], p.so[a]);
+                R s2 = r_div(ghi[a] - p.sx[a], p.so[a]);
+                if (s1 > s2) { const R tt = s1; s1 = s2; s2 = tt; }
+                if (s1 > s_lo) s_lo = s1;
+                if (s2 < s_hi) s_hi = s2;
+            }
+        }
+        if (in && s_hi > s_lo) {
+            const R xA = A == 0 ? p.sx[0] : (A == 1 ? p.sx[1] : p.sx[2]);
+            const R oA = A == 0 ? p.so[0] : (A == 1 ? p.so[1] : p.so[2]);
+            int P = 0;
+            if (oA != R(0)) {
+                const int dir = oA > R(0) ? 1 : -1;
+                const R xs = xA + oA * s_lo;
+                int ic = (int)floor((double)((xs - loA) / wA));
+                ic = ic < 0 ? 0 : (ic > nA - 1 ? nA - 1 : ic);
+                int j = ic + (dir > 0 ? 1 : 0);
+                for (int it = 0; it < 4; ++it) {
+                    const int jb = j - dir;
+                    if (jb >= 1 && jb <= nA - 1 && r_div(loA + (R)jb * wA - xA, oA) > s_lo) j = jb;
+                    else break;
+                }
+                for (int it = 0; it < 4; ++it) {
+                    if (j >= 1 && j <= nA - 1 && !(r_div(loA + (R)j * wA - xA, oA) > s_lo)) j += dir;
+                    else break;
+                }
+                j0 = j;
+                const int Rn = (j >= 1 && j <= nA - 1) ? (dir > 0 ? nA - j : j) : 0;
+                int lo = 0, hi = Rn;     // first plane of the run not before s_hi
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (r_div(loA + (R)(j0 + mid * dir) * wA - xA, oA) < s_hi) lo = mid + 1;
+                    else hi = mid;
+                }
+                P = lo;
+            }
+            c = P + 1;
+        }
+    }
+    int S = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(S, off, 64);
+        if (lane >= off) S += t;
+    }
+    const int total = __shfl(S, 63, 64);
+    for (int base = 0; base < total; base += 64) {
+        const int g = base + lane;
+        int own = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+            const int cc = own + step - 1;
+            if (__shfl(S, cc < 63 ? cc : 63, 64) <= g) own += step;
+        }
+        own = own < 63 ? own : 63;
+        const int cnt_own = __shfl(c, own, 64);
+        const int q = g - (__shfl(S, own, 64) - cnt_own);       // piece index within the segment
+        R x0[3], o[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            x0[a] = lane_r<R>(p.sx[a], own);
+            o[a] = lane_r<R>(p.so[a], own);
+        }
+        const R lo_s = lane_r<R>(s_lo, own), hi_s = lane_r<R>(s_hi, own), vm = lane_r<R>(p.svm, own);
+        const int jj = __shfl(j0, own, 64), m = __shfl(p.sk0, own, 64);
+        const R sg = (R)__shfl(p.s, own, 64);
+        if (g < total) {
+            const R xA = A == 0 ? x0[0] : (A == 1 ? x0[1] : x0[2]);
+            const R oA = A == 0 ? o[0] : (A == 1 ? o[1] : o[2]);
+            const int dir = oA > R(0) ? 1 : -1;
+            const int P = cnt_own - 1;
+            const R s_a = q == 0 ? lo_s : r_div(loA + (R)(jj + (q - 1) * dir) * wA - xA, oA);
+            const R s_b = q == P ? hi_s : r_div(loA + (R)(jj + q * dir) * wA - xA, oA);
+            const R l = s_b - s_a;
+            if (l > R(0)) {
+                const R mid = R(0.5) * (s_a + s_b);
+                int64_t cell = 0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int n = gn[a] > 0 ? gn[a] : 1;
+                    int64_t ci = 0;
+                    if (gn[a] > 0) {
+                        const R xa = x0[a] + o[a] * mid;
+                        const R f = Geo<R>::cellf_of(xa, glo[a], gsc[a]);
+                        ci = (int64_t)f;
+                        ci = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
+                    }
+                    cell = cell * n + ci;
+                }
+                add4_c(tc, mask, ncomp, slots, cell * n_cols + m, sg, l, vm, o);
+            }
+        }
+    }
+    p.sn = 0;
+}
+
 // The segments of a lane that is the last one live in its wave, up to its next event that is
 // neither a transfer through a periodic face nor a diffuse or specular reflection off the pore
 // (these leave the mode and the remaining flight as they were): the faces the ray moves toward
@@ -968,7 +1114,7 @@ __device__ __forceinline__ bool lone_chain(const Hot<R>& H, const TallyCtx& tc, 
 template <typename R, int TK, int AK, int FT>
 __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const Tabs<R>& tb, const TallyCtx& tc,
                                        const Stream& st, Part<R>& p, LaneCounts& cnt, LogRow& lg, bool& coop,
-                                       AdjCtx& adj, PathCtx<R>& pc, bool chain)
+                                       AdjCtx& adj, PathCtx<R>& pc, bool chain, bool spread = false)
 {
     const DevGeom& g = T.g;
     const R vm = tb.v[p.m];
@@ -1056,7 +1202,19 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             if (TK == TALLY_STEADY_ONE) {
                 if (d > R(0)) add4_c(tc, H.det_mask, H.det_ncomp, H.det_slot, (int64_t)p.m, sg, d, vm, p.o);
             } else {
-                tally_grid(T, tc, p.x, p.o, d, p.m, sg, vm);
+                if (spread && H.grid_axis >= 0) {   // the wave scores the pieces after the step
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        p.sx[a] = p.x[a];
+                        p.so[a] = p.o[a];
+                    }
+                    p.st0 = d;
+                    p.svm = vm;
+                    p.sk0 = p.m;
+                    p.sn = 1;
+                } else {
+                    tally_grid(T, tc, p.x, p.o, d, p.m, sg, vm);
+                }
             }
             const int sa = H.score_axis;
             const R os = sa == 0 ? p.o[0] : (sa == 1 ? p.o[1] : p.o[2]);
@@ -1768,9 +1926,11 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
         }
         ++since_refill;
         const bool lone = exhausted && (live & (live - 1ull)) == 0ull;   // one lane left in the wave
+        // detector-grid pieces of a sparse wave are scored by the whole wave after the step
+        const bool spread = TK == TALLY_STEADY_GRID && !ADJ && __popcll(live) <= 16;
         bool coop = false;
         if (alive) {
-            if (flight<R, TK, AK, FT>(T, H, tb, tc, st, p, cnt, lg, coop, adj, pc, lone)) {
+            if (flight<R, TK, AK, FT>(T, H, tb, tc, st, p, cnt, lg, coop, adj, pc, lone, spread)) {
                 end_particle(p, T.transient, mom, lg);
                 if (!ADJ && a.particle_F) a.particle_F[my_pid - a.first_pid] = p.cq;
                 alive = false;
@@ -1785,6 +1945,7 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
             }
         }
         if constexpr (TK == TALLY_TRANSIENT) snap_wave<R>(T, tc, tb.tmeas, p);
+        if constexpr (TK == TALLY_STEADY_GRID && !ADJ) grid_wave<R>(T, H, tc, p);
     }
     if (ADJ) {
         const double d = wave_sum<double>(adj.dense);
