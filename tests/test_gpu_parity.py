@@ -172,6 +172,21 @@ def test_fp64_launch_shape_invariance():
         assert np.abs(r["raw"] - base["raw"]).max() <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("precision", [64, 32])
+def test_grid_pieces_scored_by_the_wave_match_per_lane_scoring(precision):
+    """Gray slab with 50 detector cells: in sparse waves the whole wave scores the pending
+    segments' grid pieces, in dense waves each lane walks its own; launch shapes that mix the two
+    differently give the same counters and the same sums up to summation order."""
+    M = _pkg()
+    w = W.gray_slab(N=4000)
+    base = M.run(w, precision=precision)
+    for block, refill, grid in ((64, 1, 1), (64, 4, 0), (256, 64, 2)):
+        r = M.run(w, precision=precision, block=block, refill=refill, grid=grid)
+        assert np.array_equal(r["counts_raw"], base["counts_raw"]), (block, refill, grid)
+        scale = np.abs(base["raw"]).max()
+        assert np.abs(r["raw"] - base["raw"]).max() <= 1e-12 * scale, (block, refill, grid)
+
+
 def test_emit_then_trace_equals_fused():
     M = _pkg()
     for w, prec in ((W.film(N=5000), 64), (W.transient_bump(N=300), 64), (W.film(N=5000), 32)):
