@@ -320,6 +320,28 @@ def test_lone_lane_walk_matches_one_segment_steps(precision, spec):
     assert plain["counts"]["periodic"] > 20 * 300
 
 
+@pytest.mark.parametrize("cap", [1, 7, 20])
+def test_event_cap_fp64_bit_exact_and_in_the_lone_lane_walk(cap):
+    """The per-particle segment cap ends a walk where the oracle ends it: FP64 event sequences and
+    counters bit-exact (pore cell with long free paths, film), and the lone-lane walk, which
+    checks the cap before every segment, gives the one-segment step's counters."""
+    M = _pkg()
+    long_pores = W.with_(W.porous_cell(N=300, modes=W.gray_modes(6400.0, 20e-6 / 6400.0), n_scat_max=3),
+                         **{"problem.format": 2, "problem.max_events": cap})
+    film = W.with_(W.film(N=500), **{"problem.max_events": cap})
+    for w in (long_pores, film):
+        n = w["problem"]["N"]
+        got = M.run(w, precision=64, n_log=n, log_stride=64)
+        ref = oracle.trace(w, n_log=n, log_stride=64, threads=THREADS)
+        assert _first_log_mismatch(got["log"], ref["log"]) is None
+        assert np.array_equal(got["counts_raw"], ref["counts"])
+        assert got["counts"]["cap_end"] > 0
+        assert got["counts"]["flights"] <= cap * n
+    plain = M.run(long_pores, precision=64)
+    logged = M.run(long_pores, precision=64, n_log=300, log_stride=16)
+    assert np.array_equal(plain["counts_raw"], logged["counts_raw"])
+
+
 def test_fp32_transient_wide_kernel_against_fp64_oracle():
     """The transient bump with its full snapshot detector (100 bins x 200 times, too large for a
     per-workgroup FP64 copy): the FP32 kernel sums it per workgroup in FP32 in LDS.  Each particle

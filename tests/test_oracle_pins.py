@@ -268,3 +268,28 @@ def test_next_boundary_matches_ray_march():
     # a corner: equal distances to two faces resolve to the lower id
     d, hit = tb.next_boundary(np.array([Wd - 1e-8, 1e-8, 3e-7]), np.array([1.0, -1.0, 0.0]) / math.sqrt(2))
     assert hit == 1
+
+
+@pytest.mark.parametrize("cap", [1, 5])
+def test_segment_cap_ends_each_walk_after_cap_segments(cap):
+    """The per-particle segment cap: no particle takes more than `cap` segments; a particle that
+    has not ended otherwise by then ends there (counted as a cap end), and the event log records
+    exactly `cap` segment-ending events before the cap event for those particles."""
+    w = W.with_(W.porous_cell(N=400, modes=W.gray_modes(6400.0, 5e-6 / 6400.0), n_scat_max=3),
+                **{"problem.format": 2, "problem.max_events": cap})
+    r = oracle.trace(w, n_log=400, log_stride=32, threads=4)
+    c = dict(zip(oracle.COUNT_NAMES, (int(x) for x in r["counts"])))
+    assert c["flights"] <= cap * c["particles"]
+    ended = c["nscat_end"] + c["cap_end"] + c["absorbed"] + c["escaped"] + c["timeouts"]
+    assert ended == c["particles"]
+    assert c["cap_end"] > 0
+    cap_code = next(k for k, v in oracle.EV_NAMES.items() if v == "cap_end")
+    n_cap = 0
+    for row in r["log"]:
+        n = int(row[0])
+        kinds = [int(e) >> 28 for e in row[1:1 + n]]
+        if kinds and kinds[-1] == cap_code:
+            # the emission, one event closing each of the `cap` segments, then the cap
+            assert len(kinds) == cap + 2
+            n_cap += 1
+    assert n_cap == c["cap_end"]
