@@ -31,8 +31,8 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 # Algorithmic VALU work of the method's steps, in full-rate lane-operation equivalents
 # (quarter-rate instructions -- 32x32->64 integer products, reciprocal, square root, log,
-# sin/cos -- count 4).  Derived from the operations the method prescribes, not from the
-# compiled code; the derivation is in the design notes.
+# sin/cos -- count 4).  Derived from the operations the method prescribes (each entry below
+# names them), not from the compiled code.
 OPS = {
     "philox_block": 100,      # 10 rounds x (2 products x 4 + 2 three-way XORs)
     "flight_base": 34,        # choice of event, position/time update, one track-length score, particle scores

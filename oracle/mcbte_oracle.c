@@ -6,8 +6,7 @@
  * method states.  Build with -O2 -ffp-contract=off (no fused multiply-adds, no
  * fast-math) so that every arithmetic step rounds exactly as written.
  *
- * Conventions fixed where the paper is silent (each is listed with its reason
- * in the design notes of the repository):
+ * Conventions fixed where the paper is silent:
  *   - random numbers: Philox4x32-10, key = seed, counter = (block, pid, instance);
  *     a "record" is two consecutive blocks (eight 32-bit words W0..W7);
  *   - discrete draws invert cumulative distributions held as 64-bit integer

@@ -1,18 +1,23 @@
 // HIP kernels (gfx950) of the deviational phonon Monte Carlo tracer.
 //
 // One engine, templated on the trajectory precision R (double: FP64 form, bit-for-bit the
-// event sequence of the method's steps as spelled out in the design notes; float: FP32 form,
-// tables built and tallies summed in FP64), drives three kernels:
+// event sequence of the method's steps; float: FP32 form, tables built and tallies summed in
+// FP64), drives three kernels:
 //   k_emit        one lane per particle, writes the emitted state (section 3.2)
 //   k_trace_solo  persistent lanes; a lane whose particle ended is refilled every `refill`
 //                 flights from a global counter (wave ballot + prefix popcount, one atomic per
 //                 wave); relaxation table, velocities and relaxation times staged in LDS;
-//                 tallies privatised in LDS when they fit, then flushed with FP64 atomics
+//                 tallies privatised in LDS when they fit, then flushed with FP64 atomics.
+//                 Where one lane's work would keep a wave waiting, the wave shares it: film
+//                 bouncing 64 reflections at a time (coop_bounces, coop_exact), transient
+//                 snapshots and sparse waves' detector-grid pieces 64 per pass (snap_wave,
+//                 grid_wave); a wave's last lane walks periodic transfers and pore reflections
+//                 in a lean loop (lone_chain)
 //   k_trace_batch the same lanes over many problem instances: workgroups pull (instance,
 //                 particle-chunk) items from a queue, re-stage the tables when the instance
 //                 changes and flush that instance's tallies before moving on.
 // Nothing here is a dense contraction: the path is bound by plain vector ALU work (Philox,
-// transcendentals, divisions) and LDS traffic, not by MFMA or HBM.
+// transcendentals, divisions), its latency and LDS traffic, not by MFMA or HBM.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -1109,8 +1114,10 @@ __device__ __forceinline__ bool lone_chain(const Hot<R>& H, const TallyCtx& tc, 
 }
 
 // Advance particle p by one segment; returns true when the particle has ended.  With `chain`
-// set (the lane is the last one of its wave still tracing), the transfers through periodic faces
-// ahead of it run first in lone_chain.  AK: 0 trace, 1 likelihood-ratio replay, 2 pathwise replay, 3 local pathwise replay.
+// set (the lane is the last one of its wave still tracing), the periodic transfers and pore
+// reflections ahead of it run first in lone_chain; with `spread` set (a sparse wave), a
+// detector-grid segment is left to grid_wave.
+// AK: 0 trace, 1 likelihood-ratio replay, 2 pathwise replay, 3 local pathwise replay.
 template <typename R, int TK, int AK, int FT>
 __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const Tabs<R>& tb, const TallyCtx& tc,
                                        const Stream& st, Part<R>& p, LaneCounts& cnt, LogRow& lg, bool& coop,
