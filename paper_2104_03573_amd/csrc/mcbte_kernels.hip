@@ -1567,12 +1567,13 @@ __device__ __forceinline__ double lane_value(double v, int k)
 // the chord to the opposite wall, its flight time and its flux terms depend only on the
 // reflection's own record and on the wall it starts from, so the lanes evaluate 64 consecutive
 // reflections at once, each with the sequential loop's own arithmetic (the chord is the division
-// the geometry step makes from the wall coordinate).  One pass of the whole wave then walks them
-// in order with the sequential arithmetic for everything that carries over from one segment to
-// the next (remaining flight time and the test against it, position, time, the particle's scores,
-// segment count, event log), so the particle leaves the chain in exactly the state the
-// one-segment-at-a-time loop reaches.  The tallies take each lane's terms (their summation order
-// is free, as it is for the atomics).
+// the geometry step makes from the wall coordinate).  The whole wave then walks them in order
+// with the sequential arithmetic for everything that carries over from one segment to the next:
+// first the remaining flight time and the test against it, which alone decide where the walk
+// stops, then (a loop with no exit) position, time and the particle's scores over the segments
+// completed before that, then segment count and event log; the particle leaves the chain in
+// exactly the state the one-segment-at-a-time loop reaches.  The tallies take each lane's terms
+// (their summation order is free, as it is for the atomics).
 __device__ __forceinline__ void coop_exact(const Hot<double>& H, const Tabs<double>& tb, const TallyCtx& tc,
                                            Part<double>& p, const Stream& st_own, int leader, LaneCounts& cnt,
                                            LogRow& lg)
@@ -1585,8 +1586,12 @@ __device__ __forceinline__ void coop_exact(const Hot<double>& H, const Tabs<doub
     const Stream st{(uint32_t)__shfl((int)st_own.k0, leader, 64), (uint32_t)__shfl((int)st_own.k1, leader, 64),
                     (uint32_t)__shfl((int)st_own.plo, leader, 64), (uint32_t)__shfl((int)st_own.phi, leader, 64),
                     (uint32_t)__shfl((int)st_own.inst, leader, 64)};
-    double x[3] = {__shfl(p.x[0], leader, 64), __shfl(p.x[1], leader, 64), __shfl(p.x[2], leader, 64)};
-    const int side0 = (aw == 0 ? x[0] : (aw == 1 ? x[1] : x[2])) > 0.5 * L ? 1 : 0;
+    const double x0 = __shfl(p.x[0], leader, 64), x1 = __shfl(p.x[1], leader, 64), x2 = __shfl(p.x[2], leader, 64);
+    const int side0 = (aw == 0 ? x0 : (aw == 1 ? x1 : x2)) > 0.5 * L ? 1 : 0;
+    // the in-plane axes b0 < b1 and the particle's coordinates along them (the coordinate along
+    // the film axis is the wall's at every reflection)
+    const int b0 = aw == 0 ? 1 : 0;
+    double y0 = aw == 0 ? x1 : x0, y1 = aw == 2 ? x1 : x2;
     uint32_t j = (uint32_t)__shfl((int)p.j, leader, 64);
     uint32_t pk = (uint32_t)__shfl((int)p.k, leader, 64);
     double D = __shfl(p.dtr, leader, 64);
@@ -1622,31 +1627,56 @@ __device__ __forceinline__ void coop_exact(const Hot<double>& H, const Tabs<doub
         const double dt = d / vm;
         const double q0 = d * o[0], q1 = d * o[1], q2 = d * o[2];
         const double qs = sa == 0 ? q0 : (sa == 1 ? q1 : q2);
+        const double r0 = aw == 0 ? q1 : q0, r1 = aw == 2 ? q1 : q2;   // in-plane displacements
+        // the segment in which the free flight ends (or the event cap stops the walk): the
+        // remaining-time recursion alone, in order, decides it
         int kstop = 64;
+        double Dk = D;
         for (int k = 0; k < 64; ++k) {
-            ++refl;                                      // the reflection that drew lane k's record
-            if (lane == leader) lg.put(EV_DIFFUSE, (side ^ (k & 1)) ? id1 : id0, m);
-            if (pk >= (uint32_t)H.max_events) { kstop = k; break; }
-            const double dk = lane_value(d, k);
-            if (!(dk <= vm * D)) { kstop = k; break; }   // the free flight ends in this segment
-            const double dtk = lane_value(dt, k);
-            const double r = D - dtk;
-            D = r > 0.0 ? r : 0.0;
-            x[0] = x[0] + lane_value(q0, k);
-            x[1] = x[1] + lane_value(q1, k);
-            x[2] = x[2] + lane_value(q2, k);
-            t = t + dtk;
-            cT += sg * dtk;
-            cq += sg * lane_value(qs, k);
-            pk += 1;
-            full += 1;
-            if (lane == k) {
-                aT += sg * dt;
-                aQ0 += sg * q0;
-                aQ1 += sg * q1;
-                aQ2 += sg * q2;
+            if (pk + (uint32_t)k >= (uint32_t)H.max_events || !(lane_value(d, k) <= vm * Dk)) {
+                kstop = k;
+                break;
+            }
+            const double r = Dk - lane_value(dt, k);
+            Dk = r > 0.0 ? r : 0.0;
+        }
+        // the segments completed before it, in order: nothing in them ends the walk (every lane
+        // holds the same kstop)
+        kstop = __builtin_amdgcn_readfirstlane(kstop);
+        if (sa != aw) {                  // the scored flux is one of the in-plane displacements
+            const bool s0 = sa == b0;
+            for (int k = 0; k < kstop; ++k) {
+                const double dtk = lane_value(dt, k), e0 = lane_value(r0, k), e1 = lane_value(r1, k);
+                y0 = y0 + e0;
+                y1 = y1 + e1;
+                t = t + dtk;
+                cT += sg * dtk;
+                cq += sg * (s0 ? e0 : e1);
+            }
+        } else {
+            for (int k = 0; k < kstop; ++k) {
+                const double dtk = lane_value(dt, k);
+                y0 = y0 + lane_value(r0, k);
+                y1 = y1 + lane_value(r1, k);
+                t = t + dtk;
+                cT += sg * dtk;
+                cq += sg * lane_value(qs, k);
             }
         }
+        D = Dk;
+        pk += (uint32_t)kstop;
+        full += (uint32_t)kstop;
+        if (lane < kstop) {              // each lane's own segment, if completed
+            aT += sg * dt;
+            aQ0 += sg * q0;
+            aQ1 += sg * q1;
+            aQ2 += sg * q2;
+        }
+        // every reflection up to the one that stopped the walk drew its record
+        const int drawn = kstop < 64 ? kstop + 1 : 64;
+        refl += (uint32_t)drawn;
+        if (lane == leader && lg.row)
+            for (int k = 0; k < drawn; ++k) lg.put(EV_DIFFUSE, (side ^ (k & 1)) ? id1 : id0, m);
         if (kstop < 64) {
             o_end[0] = __shfl(o[0], kstop, 64);
             o_end[1] = __shfl(o[1], kstop, 64);
@@ -1668,7 +1698,7 @@ __device__ __forceinline__ void coop_exact(const Hot<double>& H, const Tabs<doub
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            p.x[a] = (a == aw) ? (side ? L : 0.0) : x[a];
+            p.x[a] = (a == aw) ? (side ? L : 0.0) : (a == b0 ? y0 : y1);
             p.o[a] = o_end[a];
         }
         p.t = t;
