@@ -29,7 +29,7 @@ _lib = None
 
 N_COUNTS = 16
 COUNT_NAMES = ["particles", "flights", "relaxations", "specular", "diffuse", "periodic", "absorbed",
-               "timeouts", "nscat_end", "cap_end", "escaped", "rejections"]
+               "timeouts", "nscat_end", "cap_end", "escaped", "rejections", "two_phonon"]
 EV_NAMES = {0: "emit+", 1: "relax", 2: "specular", 3: "diffuse", 4: "periodic", 5: "absorb",
             6: "timeout", 7: "nscat_end", 8: "cap_end", 9: "emit-", 10: "escape"}
 
@@ -107,6 +107,8 @@ def lib():
         L.orc_tally_segment.argtypes = [p, p, p, C.c_double, C.c_int32, C.c_double, p]
         L.orc_emit_state.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, p, p]
         L.orc_emit_state.restype = C.c_int
+        L.orc_emit_clocks.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, p, p]
+        L.orc_emit_clocks.restype = C.c_int
         L.orc_adjoint.argtypes = [p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, C.c_int32, C.c_double, p, p, p, p, p]
         L.orc_adjoint.restype = C.c_int
         L.orc_next_boundary.argtypes = [p, p, p, p]
@@ -265,6 +267,15 @@ class Tables:
         if lib().orc_emit_state(self.h, sd, instance, pid, _ptr(d8), _ptr(i4)) != 0:
             raise ValueError("emission failed")
         return d8, i4
+
+    def emit_clocks(self, pid: int, seed: int | None = None, instance: int = 0):
+        """Two-clock tables: (lead of the later clock, 1 if the two-phonon clock fires first)."""
+        lead = np.zeros(1)
+        nx2 = np.zeros(1, dtype=np.int32)
+        sd = int(self.w["seed"]) if seed is None else int(seed)
+        if lib().orc_emit_clocks(self.h, sd, instance, pid, _ptr(lead), _ptr(nx2)) != 0:
+            raise ValueError("emission failed")
+        return float(lead[0]), int(nx2[0])
 
     def next_boundary(self, x, o) -> tuple[float, int]:
         x = np.ascontiguousarray(x, dtype=np.float64)

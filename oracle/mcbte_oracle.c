@@ -39,6 +39,8 @@ static const int FACE_SIDE[6] = {0, 1, 1, 0, 0, 1};
 struct orc_tables {
     int32_t M;
     double *C, *v, *tau;
+    double* tau2;        /* two-phonon (impurity) relaxation time of each row; 0: no such process */
+    int32_t two;         /* some row has a two-phonon clock */
     double C_tot, Wv, kappa_bulk;
     uint64_t *thr_ic, *thr_wall, *thr_rel;
     int64_t last_ic, last_wall, last_rel;
@@ -199,7 +201,7 @@ static double extent(const orc_geom* g, int a) { return g->unbounded[a] ? 1.0 : 
 void orc_free(orc_tables* t)
 {
     if (!t) return;
-    free(t->C); free(t->v); free(t->tau);
+    free(t->C); free(t->v); free(t->tau); free(t->tau2);
     free(t->thr_ic); free(t->thr_wall); free(t->thr_rel);
     free(t->src_kind); free(t->src_ref); free(t->src_sign); free(t->src_E); free(t->thr_src);
     free(t->t_meas); free(t->ic_edges); free(t->ic_dT);
@@ -258,19 +260,23 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
     t->C = (double*)malloc(sizeof(double) * M);
     t->v = (double*)malloc(sizeof(double) * M);
     t->tau = (double*)malloc(sizeof(double) * M);
+    t->tau2 = (double*)malloc(sizeof(double) * M);
     t->thr_ic = (uint64_t*)malloc(sizeof(uint64_t) * M);
     t->thr_wall = (uint64_t*)malloc(sizeof(uint64_t) * M);
     t->thr_rel = (uint64_t*)malloc(sizeof(uint64_t) * M);
     double* w = (double*)malloc(sizeof(double) * M);
-    if (!t->C || !t->v || !t->tau || !t->thr_ic || !t->thr_wall || !t->thr_rel || !w) {
+    if (!t->C || !t->v || !t->tau || !t->tau2 || !t->thr_ic || !t->thr_wall || !t->thr_rel || !w) {
         free(w); orc_free(t); return E_NOMEM;
     }
     /* per-mode heat capacity: given (second format) or DOS * delta-omega * de/dT (first format) */
     for (int m = 0; m < M; ++m) {
         const orc_mode* r = &modes[m];
         if (!(r->v > 0.0) || !(r->tau > 0.0)) { free(w); orc_free(t); return E_INVAL; }
+        if (!(r->tau_imp >= 0.0) || !isfinite(r->tau_imp)) { free(w); orc_free(t); return E_INVAL; }
         t->v[m] = r->v;
         t->tau[m] = r->tau;
+        t->tau2[m] = r->tau_imp;
+        if (r->tau_imp > 0.0) t->two = 1;
         if (pr->format == 1) {
             if (r->dos < 0.0 || r->domega < 0.0 || !(r->omega > 0.0)) { free(w); orc_free(t); return E_INVAL; }
             t->C[m] = (r->dos * r->domega) * orc_dedT(r->omega, pr->T_lin);
@@ -283,7 +289,9 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
     for (int m = 0; m < M; ++m) {
         t->C_tot += t->C[m];
         t->Wv += t->C[m] * t->v[m];
-        t->kappa_bulk += ((t->C[m] * t->v[m]) * t->v[m]) * t->tau[m];
+        /* both processes relax the odd part of the deviation: their rates add */
+        const double tau_eff = t->tau2[m] > 0.0 ? 1.0 / (1.0 / t->tau[m] + 1.0 / t->tau2[m]) : t->tau[m];
+        t->kappa_bulk += ((t->C[m] * t->v[m]) * t->v[m]) * tau_eff;
     }
     t->kappa_bulk = t->kappa_bulk / 3.0;
     if (!(t->C_tot > 0.0)) { free(w); orc_free(t); return E_TABLE; }
@@ -568,12 +576,40 @@ static void tally_transient(const orc_tables* t, const double x0[3], const doubl
 
 typedef struct {
     double x[3], o[3];
-    double t, dtr;       /* time, remaining free-flight time */
+    double t, dtr;       /* time, time left until the next scattering event */
+    double lead;         /* two clocks: how much later the other clock fires (+inf: never) */
+    int32_t nx2;         /* two clocks: the next scattering is the two-phonon one */
     double cT, cq;       /* per-particle contributions for the variance estimate */
     int32_t m, s, nrel;
     uint32_t k;          /* segments so far (bounded by max_events) */
     uint32_t j;          /* events so far that drew random numbers; the j-th one draws record 2 + j */
 } prt;
+
+/* Section 3.3 draws two times to scattering, one per process, from Eq. time_to_scat; both run
+   down together with the particle's time, so what is kept is the earlier one (dtr) and the
+   other's lead over it.  A tie goes to the three-phonon clock. */
+static void set_clocks(prt* p, double t2, double t3)
+{
+    if (t2 < t3) {
+        p->dtr = t2;
+        p->lead = t3 - t2;
+        p->nx2 = 1;
+    } else {
+        p->dtr = t3;
+        p->lead = t2 - t3;
+        p->nx2 = 0;
+    }
+}
+
+/* the two-phonon clock of row m drawn at the j-th drawing event (j = 0: emission): words W0W1
+   of record 0x60000000 + j; +inf for a row without the process */
+static double draw_t2(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t pid, uint32_t j, int32_t m)
+{
+    if (!(t->tau2[m] > 0.0)) return INFINITY;
+    uint32_t Q[8];
+    orc_record(seed, inst, pid, 0x60000000u + j, Q);
+    return -t->tau2[m] * log(1.0 - unif(Q, 0));
+}
 
 static int emit(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t pid, prt* p, uint64_t* counts,
                 int64_t* src_out)
@@ -633,6 +669,7 @@ static int emit(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t pid, 
     }
     p->t = (t->pr.transient && kind != S_IC) ? unif(R2, 2) * t->pr.t_max : 0.0;
     p->dtr = -t->tau[p->m] * log(1.0 - unif(R0, 2));
+    if (t->two) set_clocks(p, draw_t2(t, seed, inst, pid, 0u, p->m), p->dtr);
     *src_out = src;
     return 0;
 }
@@ -686,6 +723,17 @@ int orc_emit_state(const orc_tables* t, uint64_t seed, uint32_t instance, int64_
     d8[3] = p.o[0]; d8[4] = p.o[1]; d8[5] = p.o[2];
     d8[6] = p.t; d8[7] = p.dtr;
     i4[0] = p.m; i4[1] = p.s; i4[2] = (int32_t)src; i4[3] = (int32_t)counts[ORC_C_REJECT];
+    return E_OK;
+}
+
+int orc_emit_clocks(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t pid, double* lead, int32_t* nx2)
+{
+    prt p;
+    int64_t src = 0;
+    uint64_t counts[ORC_N_COUNTS] = {0};
+    if (emit(t, seed, instance, pid, &p, counts, &src) != 0) return E_INVAL;
+    *lead = p.lead;
+    *nx2 = p.nx2;
     return E_OK;
 }
 
@@ -989,6 +1037,19 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
             CENSORED();
             break;
         }
+        if (ev == EV_RELAX && p.nx2) {
+            /* two-phonon (impurity) scattering (section 3.5.1): the same phonon takes a new
+               isotropic direction and a new two-phonon clock; the three-phonon clock keeps
+               running (case ii of section 3.3) */
+            uint32_t R[8];
+            p.j += 1;
+            orc_record(seed, inst, pid, 2u + p.j, R);
+            orc_dir_iso(unif(R, 4), unif(R, 6), p.o);
+            set_clocks(&p, draw_t2(t, seed, inst, pid, p.j, p.m), p.lead);
+            counts[ORC_C_TWO] += 1;
+            LOG(ORC_EV_TWO, 0, p.m);
+            continue;
+        }
         if (ev == EV_RELAX) {
             /* three-phonon relaxation (section 3.5.2): new frequency from the post-scattering
                distribution, isotropic direction, sign kept; termination after N_scat^max */
@@ -1010,6 +1071,7 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
             p.m = (int32_t)orc_cdf_pick(t->thr_rel, t->M, t->last_rel, key64(R, 0));
             orc_dir_iso(unif(R, 4), unif(R, 6), p.o);
             p.dtr = -t->tau[p.m] * log(1.0 - unif(R, 2));
+            if (t->two) set_clocks(&p, draw_t2(t, seed, inst, pid, p.j, p.m), p.dtr);   /* both resampled */
             LOG(ORC_EV_RELAX, 0, p.m);
             adj_push(al, t->bin[p.m], -1.0, p.cq, 1);                        /* the draw of the new row */
             tan_birth(al, t->bin[p.m], t->v[p.m] * p.dtr);
@@ -1119,6 +1181,7 @@ int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t f
                 int64_t* n_bad)
 {
     if (!t || n < 0 || first_pid < 0 || t->pr.transient || kind < 0 || kind > 2) return E_INVAL;
+    if (t->two) return E_INVAL;     /* the estimators differentiate the one-clock flight law */
     int cap = 2;
     for (int a = 0; a < 3; ++a) cap += t->det.n[a];
     double* pts = (double*)malloc(sizeof(double) * cap);

@@ -49,13 +49,14 @@ typedef struct orc_tables orc_tables;
 /* counters (indices into the uint64 counts array) */
 enum {
     ORC_C_PARTICLES = 0, ORC_C_FLIGHTS, ORC_C_RELAX, ORC_C_SPECULAR, ORC_C_DIFFUSE, ORC_C_PERIODIC,
-    ORC_C_ABSORBED, ORC_C_TIMEOUT, ORC_C_NSCAT_END, ORC_C_CAP_END, ORC_C_ESCAPED, ORC_C_REJECT
+    ORC_C_ABSORBED, ORC_C_TIMEOUT, ORC_C_NSCAT_END, ORC_C_CAP_END, ORC_C_ESCAPED, ORC_C_REJECT,
+    ORC_C_TWO
 };
 /* event-log entry types */
 enum {
     ORC_EV_EMIT_POS = 0, ORC_EV_RELAX = 1, ORC_EV_SPECULAR = 2, ORC_EV_DIFFUSE = 3,
     ORC_EV_PERIODIC = 4, ORC_EV_ABSORB = 5, ORC_EV_TIMEOUT = 6, ORC_EV_NSCAT_END = 7,
-    ORC_EV_CAP_END = 8, ORC_EV_EMIT_NEG = 9, ORC_EV_ESCAPE = 10
+    ORC_EV_CAP_END = 8, ORC_EV_EMIT_NEG = 9, ORC_EV_ESCAPE = 10, ORC_EV_TWO = 11
 };
 
 int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det* det,
@@ -93,6 +94,9 @@ void orc_dir_cos(double u1, double u2, const double n[3], double out[3]);
 double orc_dedT(double omega, double T);
 /* emitted state of one particle: d8 = x, y, z, ox, oy, oz, t, dt_rem; i4 = mode, sign, source, rejections */
 int orc_emit_state(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t pid, double* d8, int32_t* i4);
+/* its two clocks (tables with a two-phonon process): lead of the later one, and 1 if the next
+   scattering is the two-phonon one */
+int orc_emit_clocks(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t pid, double* lead, int32_t* nx2);
 /* nearest boundary along a ray: distance and boundary id (0: none) */
 double orc_next_boundary(const orc_tables* t, const double x[3], const double o[3], int32_t* hit);
 /* tally one straight steady segment into raw (testing the detector clipping) */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libmcbte.so")
 OK, EINVAL, ENOMEM, EHIP, ENODEV, ETABLE, EGEOM, ESIZE, ERANGE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 N_COUNTS = 16
 COUNT_NAMES = ["particles", "flights", "relaxations", "specular", "diffuse", "periodic", "absorbed",
-               "timeouts", "nscat_end", "cap_end", "escaped", "rejections"]
+               "timeouts", "nscat_end", "cap_end", "escaped", "rejections", "two_phonon"]
 MAX_PORES = 8
 TALLY_HEADER_BYTES = 256
 

@@ -446,3 +446,103 @@ def test_local_pathwise_at_absorbing_walls_against_crn_finite_difference():
         se = math.sqrt(v.var(ddof=1) / nb + fd.var(ddof=1) / nb)
         assert abs(v.mean() - fd.mean()) < 3.0 * se, (e, v.mean(), fd.mean(), se)
         assert se < 0.1 * abs(fd.mean())
+
+
+# --------------------------------------------------------------------------------------------
+# Separate two-phonon and three-phonon clocks (section 3.3): each process draws its own time to
+# scattering from Eq. time_to_scat, the earlier one fires; a two-phonon event redraws only the
+# direction (section 3.5.1), a three-phonon event redraws the phonon and both clocks.
+# --------------------------------------------------------------------------------------------
+
+def test_two_clock_gray_slab_matches_integral_equation_at_the_combined_free_path():
+    """Gray medium: both events send the phonon off isotropically, so the race of two
+    exponential clocks (rates 1/tau3 + 1/tau2) is one process with tau_eff = 1 / (1/tau3 +
+    1/tau2); the slab must reproduce the E1 integral equation at Kn = v tau_eff / L = 1 and
+    the share of two-phonon events must be tau3 / (tau2 + tau3)."""
+    L, v, N = 100e-9, 6400.0, 100000
+    tau_eff = L / v
+    tau3, tau2 = 1.5 * tau_eff, 3.0 * tau_eff          # 1/1.5 + 1/3 = 1
+    w = W.gray_slab(N=N, Lambda=L)
+    w["modes"] = W.gray_modes(v, tau3, tau_imp=tau2)
+    t, phi, Psi = cf.gray_slab_integral_equation(1.0, 2000)
+    _, _, Psi2 = cf.gray_slab_integral_equation(1.0, 1000)
+    disc = abs(Psi - Psi2)
+    r = oracle.run(w, threads=THREADS)
+    q_ref = Psi * 1e6 * v * 2.0 / 4.0
+    assert abs(r["q_score"] - q_ref) < 3.0 * r["q_score_sigma"] + disc * q_ref
+    n2, n3 = r["counts"]["two_phonon"], r["counts"]["relaxations"]
+    p = tau3 / (tau2 + tau3)
+    n = n2 + n3
+    assert n > 10000
+    assert abs(n2 / n - p) < 4.0 * math.sqrt(p * (1 - p) / n), (n2, n3)
+    nb = w["detectors"]["n"][2]
+    ref = (2.0 * phi - 1.0).reshape(nb, -1).mean(1)
+    batches = oracle.run_batches(w, NB, n=N, threads=THREADS)
+    assert_bins_agree([b["T"][:, 0] for b in batches], ref, sys_err=1e-4)
+
+
+def test_two_clock_race_and_scattering_cap_counts_three_phonon_events_only():
+    """Gray bulk, N_scat^max = 1: a walk ends at its first three-phonon event, and the two-phonon
+    events before it are geometric with mean tau3 / tau2 (rate ratio); kappa = C v^2 tau_eff / 3."""
+    v, N = 6400.0, 200000
+    tau3, tau2 = 60e-12, 20e-12
+    w = W.bulk_gradient(N=N, n_scat_max=1, modes=W.gray_modes(v, tau3, tau_imp=tau2))
+    w["problem"]["format"] = 2                      # the gray row gives C directly
+    r = oracle.run(w, threads=THREADS)
+    c = r["counts"]
+    assert c["relaxations"] == N and c["nscat_end"] == N
+    mean2 = c["two_phonon"] / N
+    ratio = tau3 / tau2
+    p = ratio / (1.0 + ratio)
+    sd = math.sqrt(p / (1.0 - p) ** 2 / N)          # geometric count on {0, 1, ...}
+    assert abs(mean2 - ratio) < 4.0 * sd, (mean2, ratio, sd)
+    tau_eff = 1.0 / (1.0 / tau3 + 1.0 / tau2)
+    k_ref = 1e6 * v ** 2 * tau_eff / 3.0
+    assert abs(r["kappa"] - k_ref) < 3.0 * r["kappa_sigma"], (r["kappa"], r["kappa_sigma"], k_ref)
+
+
+def test_two_clock_dispersive_bulk_equals_the_summed_rate_kappa():
+    """Silicon-like rows with the A omega^4 term on its own (two-phonon) clock: in bulk both
+    processes relax the part of the deviation that carries heat, so kappa is
+    (1/3) sum_m C_m v_m^2 / (1/tau3 + 1/tau2) -- the same number as the single clock with the
+    rates summed."""
+    w = W.bulk_gradient(N=300000, n_scat_max=1, modes=W.silicon_like_modes(300.0, impurity_clock=True))
+    r = oracle.run(w, threads=THREADS)
+    C = r["tables"].get("C")
+    m = w["modes"]
+    k_ref = float(np.sum(C * m["v"] ** 2 / (1.0 / m["tau"] + 1.0 / m["tau_imp"])) / 3.0)
+    single = W.silicon_like_modes(300.0)
+    k_single = float(np.sum(C * single["v"] ** 2 * single["tau"]) / 3.0)
+    assert k_ref == pytest.approx(k_single, rel=1e-12)
+    assert abs(r["kappa"] - k_ref) < 3.0 * r["kappa_sigma"], (r["kappa"], r["kappa_sigma"], k_ref)
+    assert r["counts"]["two_phonon"] > 0
+
+
+def test_two_clock_film_matches_fuchs_sondheimer_at_the_combined_free_path():
+    """Diffuse film with the impurity term on the two-phonon clock: the deviation that carries
+    the in-plane flux is odd in Omega_y, so the direction-only redraw removes it like a
+    relaxation and kappa = sum_m kappa_m S(d / (v_m tau_eff,m))."""
+    d = 100e-9
+    w = W.film(N=150000, d=d, modes=W.silicon_like_modes(300.0, impurity_clock=True))
+    r = oracle.run(w, threads=THREADS)
+    C = r["tables"].get("C")
+    m = w["modes"]
+    tau_eff = 1.0 / (1.0 / m["tau"] + 1.0 / m["tau_imp"])
+    lam = m["v"] * tau_eff
+    k_fs = sum(C[i] * m["v"][i] ** 2 * tau_eff[i] / 3.0 * cf.fs_suppression(d / lam[i]) for i in range(len(m)))
+    assert abs(r["kappa"] - k_fs) < 3.0 * r["kappa_sigma"], (r["kappa"], r["kappa_sigma"], k_fs)
+    assert r["counts"]["two_phonon"] > 0
+
+
+def test_two_phonon_draws_use_their_own_records():
+    """A two-phonon clock that never fires (tau2 = 1e300 s) still draws its times, from records of
+    its own: every count, tally and logged event equals the single-clock run's."""
+    w1 = W.film(N=3000, modes=W.silicon_like_modes(300.0))
+    w2 = W.film(N=3000, modes=W.silicon_like_modes(300.0))
+    w2["modes"]["tau_imp"] = 1e300
+    o1, o2 = oracle.Tables(w1), oracle.Tables(w2)
+    sd = int(w1["seed"])
+    raw1, c1, m1, log1 = o1.trace_range(sd, 0, 0, 3000, n_log=3000, log_stride=64)
+    raw2, c2, m2, log2 = o2.trace_range(sd, 0, 0, 3000, n_log=3000, log_stride=64)
+    assert np.array_equal(c1, c2) and c2[12] == 0
+    assert np.array_equal(raw1, raw2) and np.array_equal(m1, m2) and np.array_equal(log1, log2)

@@ -49,7 +49,7 @@ TAU_B = 1.7e-19      # s / K   (Umklapp-like   B omega^2 T exp(-C/T))
 TAU_C = 137.0        # K
 
 
-def silicon_like_modes(T: float, n_bins: int = 1000) -> np.ndarray:
+def silicon_like_modes(T: float, n_bins: int = 1000, impurity_clock: bool = False) -> np.ndarray:
     """Material rows of the synthetic silicon-like crystal at temperature T.
 
     Rows are in the paper's first material-data format (omega, DOS, V_g,
@@ -60,6 +60,9 @@ def silicon_like_modes(T: float, n_bins: int = 1000) -> np.ndarray:
     g k^2 / (2 pi^2 V_g) per unit volume and unit angular frequency; the
     relaxation time is 1 / (A omega^4 + B omega^2 T exp(-C/T)).  Heat
     capacities are *not* computed here (the method derives them from the DOS).
+
+    impurity_clock: the impurity-like A omega^4 term becomes the separate two-phonon process
+    (tau_imp = 1 / (A omega^4)) and tau keeps the Umklapp-like term alone (three-phonon).
     """
     k_max = 2.0 * math.pi / A_SI
     a_eff = math.pi / k_max
@@ -73,14 +76,19 @@ def silicon_like_modes(T: float, n_bins: int = 1000) -> np.ndarray:
             k = (2.0 / a_eff) * math.asin(w / wmax)
             v = 0.5 * a_eff * math.sqrt(wmax * wmax - w * w)
             dos = g * k * k / (2.0 * math.pi ** 2 * v)
-            tau = 1.0 / (TAU_A * w ** 4 + TAU_B * w * w * T * math.exp(-TAU_C / T))
-            rows.append((w, dos, v, dw, tau, 0.0, 0.0, i, branch + 1))
+            r_imp = TAU_A * w ** 4
+            r_3ph = TAU_B * w * w * T * math.exp(-TAU_C / T)
+            if impurity_clock:
+                rows.append((w, dos, v, dw, 1.0 / r_3ph, 0.0, 1.0 / r_imp, i, branch + 1))
+            else:
+                rows.append((w, dos, v, dw, 1.0 / (r_imp + r_3ph), 0.0, 0.0, i, branch + 1))
     return np.array(rows, dtype=MODE_DTYPE)
 
 
-def gray_modes(v: float, tau: float, C: float = 1.0e6) -> np.ndarray:
-    """One gray mode in the paper's second material-data format (omega, V_g, tau, C)."""
-    return np.array([(1.0e13, 0.0, v, 0.0, tau, C, 0.0, 0, 1)], dtype=MODE_DTYPE)
+def gray_modes(v: float, tau: float, C: float = 1.0e6, tau_imp: float = 0.0) -> np.ndarray:
+    """One gray mode in the paper's second material-data format (omega, V_g, tau, C); tau_imp > 0
+    adds the separate two-phonon clock."""
+    return np.array([(1.0e13, 0.0, v, 0.0, tau, C, tau_imp, 0, 1)], dtype=MODE_DTYPE)
 
 
 def _geometry(L, unbounded=(False, False, False), faces=None, cylinders=(), gradT=(0.0, 0.0, 0.0),
