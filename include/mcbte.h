@@ -67,14 +67,23 @@ extern "C" {
 enum {
     MCBTE_CNT_PARTICLES = 0, MCBTE_CNT_FLIGHTS = 1, MCBTE_CNT_RELAXATIONS = 2, MCBTE_CNT_SPECULAR = 3,
     MCBTE_CNT_DIFFUSE = 4, MCBTE_CNT_PERIODIC = 5, MCBTE_CNT_ABSORBED = 6, MCBTE_CNT_TIMEOUT = 7,
-    MCBTE_CNT_NSCAT_END = 8, MCBTE_CNT_CAP_END = 9, MCBTE_CNT_ESCAPED = 10, MCBTE_CNT_REJECTIONS = 11
+    MCBTE_CNT_NSCAT_END = 8, MCBTE_CNT_CAP_END = 9, MCBTE_CNT_ESCAPED = 10, MCBTE_CNT_REJECTIONS = 11,
+    MCBTE_CNT_TWO_PHONON = 12
 };
 
 /* One material row (section 4.1).  First format: omega, dos (s rad^-1 m^-3), v, domega, tau;
    the heat capacity is then dos * domega * de/dT(omega, T_lin) (Eq. BE_derivative with the
    half argument, x = hbar omega / k_B T: k_B (x/2)^2 / sinh^2(x/2)).  Second format: omega, v,
-   tau and C (J m^-3 K^-1) given directly; dos / domega ignored.  tau_imp is reserved for the
-   separate two-phonon clock and must be 0.  bin: frequency-bin index (for per-bin outputs). */
+   tau and C (J m^-3 K^-1) given directly; dos / domega ignored.  tau is the three-phonon
+   relaxation time.  tau_imp > 0 (finite) gives the row the separate two-phonon (impurity)
+   process of section 3.3 with its own clock: both times to scattering are drawn from Eq.
+   time_to_scat, the earlier one fires (a tie goes to the three-phonon one); a two-phonon event
+   keeps the phonon and draws a new isotropic direction and a new two-phonon time (section
+   3.5.1) while the three-phonon clock runs on; a three-phonon event redraws the phonon and both
+   times; N_scat^max counts three-phonon events only.  The two-phonon time drawn at the j-th
+   random-number-drawing event (j = 0 at emission) uses words W0W1 of record 0x60000000 + j.
+   tau_imp = 0: no two-phonon process (Matthiessen's rule, if wanted, is then folded into tau).
+   bin: frequency-bin index (for per-bin outputs). */
 typedef struct {
     double omega, dos, v, domega, tau, C, tau_imp;
     int32_t bin, branch;
@@ -213,7 +222,9 @@ int mcbte_table_export(const mcbte_tables* tables, int32_t which, void* host_out
 
 /* Bytes of the particle-state buffer for `capacity` particles at `precision` (32 or 64); < 0 on
    a bad argument.  Layout (structure of arrays, each array 256-byte aligned): x, y, z, ox, oy, oz,
-   t, dt_rem (real), then mode, sign, n_rel, segments, draws (int32 / uint32). */
+   t, dt_rem (real; dt_rem is the time left until the next scattering), then mode, sign, n_rel,
+   segments, draws, source, rejections (int32 / uint32), then lead (real: with two clocks, how
+   much later the other clock fires, sign bit set when the next one is the two-phonon clock). */
 int64_t mcbte_state_bytes(int32_t precision, int64_t capacity);
 
 /* Emit particles first_pid .. first_pid + n - 1 (section 3.2: source chosen by deviational
@@ -239,7 +250,7 @@ int mcbte_emit(const mcbte_tables* tables, const mcbte_run* run, int64_t first_p
    Event log rows (if run->event_log): word 0 = number of entries, then entries
    (type << 28) | (min(boundary id or source index, 255) << 20) | mode, types 0 emit (sign +),
    9 emit (sign -), 1 relaxation (new mode), 2 specular, 3 diffuse, 4 periodic, 5 absorbed,
-   6 time horizon, 7 N_scat^max reached, 8 segment cap, 10 escaped. */
+   6 time horizon, 7 N_scat^max reached, 8 segment cap, 10 escaped, 11 two-phonon scattering. */
 int mcbte_trace(const mcbte_tables* tables, const mcbte_run* run, int64_t first_pid, int64_t n,
                 const void* state, void* tally, void* stream);
 
@@ -310,7 +321,8 @@ int mcbte_autotune(const mcbte_tables* const* tables, int32_t n_inst, const int6
    the caller; successive calls with one estimator accumulate): adj[0, n_bins) the per-bin sums,
    adj[n_bins] the relaxation-draw sum B, adj[n_bins + 1] the count of terms left out as not
    finite, adj[n_bins + 2] library scratch.  Async on `stream`.  Errors: MCBTE_EINVAL (transient run, event log set, unknown
-   estimator, n_scat_max outside the pathwise range), MCBTE_ENODEV, MCBTE_EHIP. */
+   estimator, n_scat_max outside the pathwise range, tables with a two-phonon clock), MCBTE_ENODEV,
+   MCBTE_EHIP. */
 int mcbte_adjoint(const mcbte_tables* tables, const mcbte_run* run, int32_t estimator, double lambda_split,
                   int64_t first_pid, int64_t n, const double* particle_F, double* adj, void* stream);
 

@@ -21,7 +21,7 @@ enum TallyKind : int32_t { TALLY_STEADY_ONE = 0, TALLY_STEADY_GRID = 1, TALLY_TR
 // whose whole LDS holds an FP32 copy of a tally too large for the FP64 one, the mode tables
 // being read from global memory instead, and (FP64 film-like problems) the exact cooperative
 // bouncing, whose registers the other FP64 problems need not reserve
-enum : int { FT_STATE = 1, FT_LOG = 2, FT_WIDE = 4, FT_COOP = 8 };
+enum : int { FT_STATE = 1, FT_LOG = 2, FT_WIDE = 4, FT_COOP = 8, FT_ONE = 16 };   // FT_ONE: no two-phonon clock in any table
 
 // Geometry in the form the flight loop reads it (uniform across a launch; scalar loads).
 struct DevPore32 { float cx, cy, r; int32_t id; };
@@ -99,8 +99,10 @@ struct DevTab {
     const float* t_meas32;
     const int32_t* bin_of;       // frequency bin of each mode (sensitivity parameters)
     const uint32_t* rel_guide;   // 256 packed search bounds of the relaxation draw, or NULL
+    const double* tau2_64;       // two-phonon relaxation time of each row (0: no such process)
+    const float* tau2_32;
     int32_t n_bins;
-    int32_t pad2;
+    int32_t two;                 // some row has a two-phonon clock
     DevGeom g;
     DevDet det;
 };

@@ -96,7 +96,8 @@ struct mcbte_tables {
     mcbte_geometry geom{};
     mcbte_detectors det{};
     // host tables
-    std::vector<double> C, v, tau, src_E, ic_edges, ic_dT, t_meas;
+    std::vector<double> C, v, tau, tau2, src_E, ic_edges, ic_dT, t_meas;   // tau2: two-phonon clock (0: none)
+    bool two = false;      // some row has a two-phonon clock
     std::vector<uint64_t> thr_ic, thr_wall, thr_rel, thr_src;
     std::vector<int32_t> src_kind, src_ref, src_sign, bin_of;
     std::vector<double> P_bin;   // relaxation probability mass per frequency bin
@@ -211,11 +212,15 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     t->C.resize(M);
     t->v.resize(M);
     t->tau.resize(M);
+    t->tau2.resize(M);
     for (int m = 0; m < M; ++m) {
         const mcbte_mode& r = modes[m];
-        if (!(r.v > 0.0) || !(r.tau > 0.0) || r.tau_imp != 0.0) { delete t; return MCBTE_EINVAL; }
+        if (!(r.v > 0.0) || !(r.tau > 0.0)) { delete t; return MCBTE_EINVAL; }
+        if (!(r.tau_imp >= 0.0) || !std::isfinite(r.tau_imp)) { delete t; return MCBTE_EINVAL; }
         t->v[m] = r.v;
         t->tau[m] = r.tau;
+        t->tau2[m] = r.tau_imp;
+        if (r.tau_imp > 0.0) t->two = true;
         if (pr.format == 1) {
             if (!(r.dos >= 0.0) || !(r.domega >= 0.0) || !(r.omega > 0.0)) { delete t; return MCBTE_EINVAL; }
             t->C[m] = (r.dos * r.domega) * bose_einstein_dedT(r.omega, pr.T_lin);
@@ -228,7 +233,9 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     for (int m = 0; m < M; ++m) {
         C_tot += t->C[m];
         Wv += t->C[m] * t->v[m];
-        kb += ((t->C[m] * t->v[m]) * t->v[m]) * t->tau[m];
+        // with a two-phonon clock both processes relax the heat-carrying part: the rates add
+        const double tau_eff = t->tau2[m] > 0.0 ? 1.0 / (1.0 / t->tau[m] + 1.0 / t->tau2[m]) : t->tau[m];
+        kb += ((t->C[m] * t->v[m]) * t->v[m]) * tau_eff;
     }
     if (!(C_tot > 0.0)) { delete t; return MCBTE_ETABLE; }
     std::vector<double> w(M);
@@ -365,6 +372,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     }
     h.max_events = pr.max_events;
     h.n_bins = n_bins;
+    h.two = t->two ? 1 : 0;
     h.t_max = pr.transient ? pr.t_max : 0.0;
     h.last_ic = last_ic;
     h.last_wall = last_wall;
@@ -441,8 +449,12 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         // one allocation, 256-byte aligned pieces
         std::vector<std::pair<const void*, size_t>> parts;
         auto add = [&](const void* src, size_t bytes) { parts.emplace_back(src, bytes); };
-        std::vector<float> v32(M), tau32(M), tm32(t->t_meas.size());
-        for (int m = 0; m < M; ++m) { v32[m] = (float)t->v[m]; tau32[m] = (float)t->tau[m]; }
+        std::vector<float> v32(M), tau32(M), tau2_32(M), tm32(t->t_meas.size());
+        for (int m = 0; m < M; ++m) {
+            v32[m] = (float)t->v[m];
+            tau32[m] = (float)t->tau[m];
+            tau2_32[m] = (float)t->tau2[m];
+        }
         for (size_t k = 0; k < t->t_meas.size(); ++k) tm32[k] = (float)t->t_meas[k];
         add(nullptr, sizeof(DevTab));
         add(t->v.data(), 8 * (size_t)M);
@@ -476,6 +488,8 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
             }
         }
         add(guide.data(), 4 * 256);
+        add(t->tau2.data(), 8 * (size_t)M);
+        add(tau2_32.data(), 4 * (size_t)M);
         size_t total = 0;
         std::vector<size_t> off;
         for (auto& p : parts) {
@@ -505,6 +519,8 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         h.t_meas32 = (const float*)dptr(14);
         h.bin_of = (const int32_t*)dptr(15);
         h.rel_guide = M <= 65535 ? (const uint32_t*)dptr(16) : nullptr;
+        h.tau2_64 = (const double*)dptr(17);
+        h.tau2_32 = (const float*)dptr(18);
         parts[0].first = &h;
         for (size_t i = 0; i < parts.size(); ++i) {
             if (parts[i].second == 0) continue;
@@ -553,7 +569,7 @@ int64_t mcbte_state_bytes(int32_t precision, int64_t cap)
     const int64_t rb = precision / 8;
     const int64_t fb = (cap * rb + 255) & ~int64_t(255);
     const int64_t ib = (cap * 4 + 255) & ~int64_t(255);
-    return 8 * fb + 7 * ib;
+    return 9 * fb + 7 * ib;
 }
 
 int mcbte_emit(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, int64_t n, void* state,
@@ -709,7 +725,11 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     if (!g.ok) return MCBTE_EHIP;
     LaunchPlan lp;
     if (run->particle_F) return MCBTE_EINVAL;
-    int rc = plan_launch(ts, n_inst, run, 1, 0, lp);
+    // the batched kernel without the two-clock code unless some instance needs it
+    int ft = FT_ONE;
+    for (int i = 0; i < n_inst; ++i)
+        if (ts[i]->two) ft = 0;
+    int rc = plan_launch(ts, n_inst, run, 1, ft, lp);
     if (rc != MCBTE_OK) return rc;
     // chunking: items of chunk_size particles, instance-major
     const int64_t chunk = 8192;
@@ -755,7 +775,7 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     a.n_chunks = cstart[n_inst];
     a.tally_lds = lp.tally_lds;
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
-    const hipError_t e = launch_trace(a, 1, run->precision, t0->host_view.tally_kind, 0, lp.block, lp.grid, lp.lds, s);
+    const hipError_t e = launch_trace(a, 1, run->precision, t0->host_view.tally_kind, ft, lp.block, lp.grid, lp.lds, s);
     return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
 }
 
@@ -844,6 +864,7 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
     if (run->event_log) return MCBTE_EINVAL;
     if (estimator != MCBTE_SENS_SCORE && estimator != MCBTE_SENS_PATHWISE && estimator != MCBTE_SENS_LOCAL)
         return MCBTE_EINVAL;
+    if (t->two) return MCBTE_EINVAL;       // the estimators differentiate the one-clock flight law
     if (t->device < 0 || !t->d_tab) return MCBTE_ENODEV;
     if (t->prob.transient) return MCBTE_EINVAL;
     if (estimator == MCBTE_SENS_PATHWISE &&

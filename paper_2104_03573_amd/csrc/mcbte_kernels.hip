@@ -125,6 +125,7 @@ template <> struct Geo<double> {
     static __device__ __forceinline__ const double* tmeas_ptr(const DevTab& t) { return t.t_meas64; }
     static __device__ __forceinline__ const double* v(const DevTab& t) { return t.v64; }
     static __device__ __forceinline__ const double* tau(const DevTab& t) { return t.tau64; }
+    static __device__ __forceinline__ const double* tau2(const DevTab& t) { return t.tau2_64; }
     static __device__ __forceinline__ const DevPore64& pore(const DevGeom& g, int i) { return g.pore64[i]; }
     static constexpr int prec = 1;
 };
@@ -144,6 +145,7 @@ template <> struct Geo<float> {
     static __device__ __forceinline__ const float* tmeas_ptr(const DevTab& t) { return t.t_meas32; }
     static __device__ __forceinline__ const float* v(const DevTab& t) { return t.v32; }
     static __device__ __forceinline__ const float* tau(const DevTab& t) { return t.tau32; }
+    static __device__ __forceinline__ const float* tau2(const DevTab& t) { return t.tau2_32; }
     static __device__ __forceinline__ const DevPore32& pore(const DevGeom& g, int i) { return g.pore32[i]; }
     static constexpr int prec = 0;
 };
@@ -179,8 +181,10 @@ __device__ __forceinline__ int cdf_pick_guided(const uint64_t* thr, const uint32
 
 template <typename R> struct Part {
     R x[3], o[3];
-    R t, dtr;            // time, remaining free-flight time
-    int32_t m, s, nrel;  // mode row, sign, relaxations so far
+    R t, dtr;            // time, time left until the next scattering event
+    R lead;              // two clocks: how much later the other one fires (+inf: never); the sign
+                         // bit set means the next scattering is the two-phonon one
+    int32_t m, s, nrel;  // mode row, sign, three-phonon relaxations so far
     uint32_t k, j;       // segments so far, random-number-drawing events so far
     int32_t src;         // source element (event log only)
     double cT, cq;       // per-particle contributions (variance estimate); cq is the flux score F
@@ -238,6 +242,40 @@ __device__ __forceinline__ void dir_iso(R u1, R u2, R o[3])
     o[0] = st * cs;
     o[1] = st * sn;
     o[2] = mu;
+}
+
+// ------------------------------------------------------------------------------------------
+// the two clocks of section 3.3: a two-phonon and a three-phonon time to scattering, each from
+// Eq. time_to_scat, running down together with the particle's time; the earlier one is kept in
+// dtr and the other's lead over it in lead (sign bit set: the two-phonon clock is the earlier);
+// a tie goes to the three-phonon clock.  An event that redraws the two-phonon time leaves the
+// three-phonon time in dtr and lead = NaN; the draw is made at the start of the next step
+// (resolve_clocks), where few other values are live.
+// ------------------------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ void set_clocks(Part<R>& p, R t2, R t3)
+{
+    const bool two_first = t2 < t3;
+    p.dtr = two_first ? t2 : t3;
+    p.lead = two_first ? -(t3 - t2) : t2 - t3;
+}
+
+// the two-phonon time of row m drawn at the j-th drawing event (j = 0: emission), from words
+// W0W1 of record 0x60000000 + j; +inf for a row without the process
+template <typename R>
+__device__ __forceinline__ R draw_t2(const DevTab& T, const Stream& st, uint32_t j, int m)
+{
+    const R tau2 = Geo<R>::tau2(T)[m];
+    if (!(tau2 > R(0))) return R(1) / R(0);
+    const W4 q = st.block(2u * (0x60000000u + j));
+    return -tau2 * r_log(R(1) - unif<R>(q.x, q.y));
+}
+
+template <typename R>
+__device__ __forceinline__ void resolve_clocks(const DevTab& T, const Stream& st, Part<R>& p)
+{
+    if (isnan(p.lead)) set_clocks(p, draw_t2<R>(T, st, p.j, p.m), p.dtr);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -318,6 +356,7 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
     p.t = (T.transient && kind != SRC_IC) ? unif<R>(r2a.z, r2a.w) * (R)T.t_max : R(0);
     const R tau = Geo<R>::tau(T)[p.m];
     p.dtr = -tau * r_log(R(1) - unif<R>(r0a.z, r0a.w));
+    p.lead = T.two ? R(NAN) : R(0);     // two clocks: the two-phonon time is still to be drawn
     p.dtr0 = p.dtr;
     p.F0 = 0.0;
 }
@@ -591,11 +630,12 @@ __device__ __forceinline__ void snap_wave(const DevTab& T, const TallyCtx& tc, c
 
 enum : uint32_t {
     EV_EMIT_POS = 0, EV_RELAX = 1, EV_SPECULAR = 2, EV_DIFFUSE = 3, EV_PERIODIC = 4, EV_ABSORB = 5,
-    EV_TIMEOUT = 6, EV_NSCAT = 7, EV_CAP = 8, EV_EMIT_NEG = 9, EV_ESCAPE = 10
+    EV_TIMEOUT = 6, EV_NSCAT = 7, EV_CAP = 8, EV_EMIT_NEG = 9, EV_ESCAPE = 10, EV_TWO = 11
 };
 
 struct LaneCounts {
-    uint32_t c[12];
+    static constexpr int N = 13;   // the counters up to the two-phonon events (MCBTE_CNT_*)
+    uint32_t c[N];
 };
 
 struct LogRow {
@@ -1129,6 +1169,8 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     int hit, pore, ev, fa, fs;
     R pcx, pcy, pr;                      // centre and radius of the pore hit
     uint32_t fcode;
+    constexpr bool TWO = (FT & FT_ONE) == 0;     // the two-clock code is compiled in
+    if (TWO && T.two) resolve_clocks<R>(T, st, p);
     if constexpr (TK == TALLY_STEADY_ONE && AK != 2 && (FT & FT_LOG) == 0) {
         if (chain && lone_chain<R>(H, tc, st, p, cnt, vm, sg)) {   // left the box on the way
             ++cnt.c[10];
@@ -1295,8 +1337,14 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         lg.put(EV_PERIODIC, hit, p.m);
         return false;
     }
-    // what the event needs
+    // what the event needs: the free flight's end is a two-phonon scattering when that clock
+    // is the earlier one, else a three-phonon relaxation
+    bool two_ev = false;
     bool relax = (ev == 0);
+    if (TWO && relax && T.two && signbit(p.lead)) {
+        relax = false;
+        two_ev = true;
+    }
     if (relax) {
         p.nrel += 1;
         ++cnt.c[2];
@@ -1347,7 +1395,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     const bool adia = (ev == 1);
     const bool partial = adia && cls == SURF_PARTIAL;
     const bool need_b0 = relax || partial;
-    const bool need_rec = need_b0 || (adia && cls == SURF_DIFFUSE);
+    const bool need_rec = need_b0 || two_ev || (adia && cls == SURF_DIFFUSE);
     if (need_rec) p.j += 1;
     const uint32_t blk = 2u * (2u + p.j);
     W4 w0 = {0u, 0u, 0u, 0u};
@@ -1355,7 +1403,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     bool specular = adia && cls == SURF_SPECULAR;
     if (partial) specular = key64(w0.x, w0.y) < (pore >= 0 ? g.pore_thr[pore] : g.face_thr[hit - 1]);
     const bool diffuse = adia && !specular;
-    if (relax || diffuse) {
+    if (relax || diffuse || two_ev) {
         const W4 w1 = st.block(blk + 1u);
         const R u1 = unif<R>(w1.x, w1.y), u2 = unif<R>(w1.z, w1.w);
         // the new direction's polar cosine mu and sine about its axis: isotropic for a relaxation
@@ -1364,8 +1412,9 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         // lanes of a wave that do different ones)
         const R mu_i = R(1) - R(2) * u1;
         const R s2 = (R(1) - mu_i) * (R(1) + mu_i);
-        const R mu = relax ? mu_i : r_sqrt(u1);
-        const R sth = r_sqrt(relax ? (s2 > R(0) ? s2 : R(0)) : R(1) - u1);
+        const bool iso = relax || two_ev;
+        const R mu = iso ? mu_i : r_sqrt(u1);
+        const R sth = r_sqrt(iso ? (s2 > R(0) ? s2 : R(0)) : R(1) - u1);
         R sn, cs;
         r_sincos_2pi(u2, &sn, &cs);
         if (relax) {
@@ -1377,6 +1426,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             p.o[1] = sth * sn;
             p.o[2] = mu;
             p.dtr = -tb.tau[p.m] * r_log(R(1) - unif<R>(w0.z, w0.w));
+            if (TWO && T.two) p.lead = R(NAN);   // both clocks redrawn: the two-phonon one next step
             lg.put(EV_RELAX, 0, p.m);
             if (AK != 0) {
                 adj.add(T.bin_of[p.m], -1.0, adj.F_total - p.cq);
@@ -1384,6 +1434,16 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             }
             p.dtr0 = p.dtr;
             p.F0 = p.cq;
+        } else if (two_ev) {
+            // two-phonon scattering (section 3.5.1): the same phonon, a new isotropic direction and
+            // a new two-phonon clock; the three-phonon clock runs on (its lead is what is left)
+            p.o[0] = sth * cs;
+            p.o[1] = sth * sn;
+            p.o[2] = mu;
+            p.dtr = -p.lead;
+            p.lead = R(NAN);
+            ++cnt.c[12];
+            lg.put(EV_TWO, 0, p.m);
         } else {
             R n[3];
             if (pore >= 0) {
@@ -1718,7 +1778,7 @@ __device__ __forceinline__ void coop_exact(const Hot<double>& H, const Tabs<doub
 
 template <typename R>
 struct StateView {
-    R* f[8];          // x, y, z, ox, oy, oz, t, dtr
+    R* f[9];          // x, y, z, ox, oy, oz, t, dtr, then (after the integers) lead
     int32_t* i[7];    // m, s, nrel, k, j, src, rejections
     __device__ __host__ StateView(void* base, int64_t cap)
     {
@@ -1727,12 +1787,13 @@ struct StateView {
         const int64_t ib = (cap * 4 + 255) & ~int64_t(255);
         for (int q = 0; q < 8; ++q) f[q] = (R*)(b + q * fb);
         for (int q = 0; q < 7; ++q) i[q] = (int32_t*)(b + 8 * fb + q * ib);
+        f[8] = (R*)(b + 8 * fb + 7 * ib);
     }
     __device__ void store(int64_t s, const Part<R>& p, uint32_t rej) const
     {
         f[0][s] = p.x[0]; f[1][s] = p.x[1]; f[2][s] = p.x[2];
         f[3][s] = p.o[0]; f[4][s] = p.o[1]; f[5][s] = p.o[2];
-        f[6][s] = p.t; f[7][s] = p.dtr;
+        f[6][s] = p.t; f[7][s] = p.dtr; f[8][s] = p.lead;
         i[0][s] = p.m; i[1][s] = p.s; i[2][s] = p.nrel; i[3][s] = (int32_t)p.k; i[4][s] = (int32_t)p.j;
         i[5][s] = p.src; i[6][s] = (int32_t)rej;
     }
@@ -1740,7 +1801,7 @@ struct StateView {
     {
         p.x[0] = f[0][s]; p.x[1] = f[1][s]; p.x[2] = f[2][s];
         p.o[0] = f[3][s]; p.o[1] = f[4][s]; p.o[2] = f[5][s];
-        p.t = f[6][s]; p.dtr = f[7][s];
+        p.t = f[6][s]; p.dtr = f[7][s]; p.lead = f[8][s];
         p.m = i[0][s]; p.s = i[1][s]; p.nrel = i[2][s]; p.k = (uint32_t)i[3][s]; p.j = (uint32_t)i[4][s];
         p.src = i[5][s];
         rej = (uint32_t)i[6][s];
@@ -1763,6 +1824,7 @@ __global__ void __launch_bounds__(256) k_emit(const DevTab* __restrict__ tabs, u
     Part<R> p;
     uint32_t rej = 0;
     emit_particle<R>(T, st, p, rej);
+    if (T.two) resolve_clocks<R>(T, st, p);
     StateView<R>(state, cap).store(i, p, rej);
 }
 
@@ -1829,7 +1891,7 @@ __device__ __forceinline__ void flush_lane_stats(unsigned char* tally, const Lan
     double* moments = (double*)(tally + 128);
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int q = 0; q < 12; ++q) {
+    for (int q = 0; q < LaneCounts::N; ++q) {
         const uint32_t s = wave_sum<uint32_t>(cnt.c[q]);
         if (lane == 0 && s) atomicAdd(counts + q, (unsigned long long)s);
     }
@@ -1919,7 +1981,7 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
     Stream st{0u, 0u, 0u, 0u, 0u};
     LaneCounts cnt;
 #pragma unroll
-    for (int q = 0; q < 12; ++q) cnt.c[q] = 0;
+    for (int q = 0; q < LaneCounts::N; ++q) cnt.c[q] = 0;
     double mom[4] = {0.0, 0.0, 0.0, 0.0};
     LogRow lg{nullptr, 0, a.log_stride};
     AdjCtx adj{s_tally, 0.0, 0.0, 0u, a.lambda_split};
@@ -2007,7 +2069,7 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
 // Batched form: the work items are (instance, chunk of chunk_size particles), numbered
 // instance-major; a workgroup takes one item at a time, its lanes refill from the item's
 // particle range through an LDS counter, and the workgroup moves on once every lane is idle.
-template <typename R, int TK>
+template <typename R, int TK, int FT>
 __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ tabs, LaunchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -2056,7 +2118,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
                 for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s_tally[i] = 0.0;
             }
 #pragma unroll
-            for (int q = 0; q < 12; ++q) cnt.c[q] = 0;
+            for (int q = 0; q < LaneCounts::N; ++q) cnt.c[q] = 0;
             mom[0] = mom[1] = mom[2] = mom[3] = 0.0;
             cur = inst;
             __syncthreads();
@@ -2118,7 +2180,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
             if (alive) {
                 // (no lone-lane chains here: their registers would cost the film sweeps, for which
                 // this kernel exists, an occupancy step)
-                if (flight<R, TK, 0, 0>(T, H, tb, tc, st, p, cnt, lg, coop, adj, pc, false)) {
+                if (flight<R, TK, 0, FT>(T, H, tb, tc, st, p, cnt, lg, coop, adj, pc, false)) {
                     end_particle(p, T.transient, mom, lg);
                     alive = false;
                 }
@@ -2176,7 +2238,8 @@ static void ensure_lds_limit(const void* fn, size_t lds)
 template <typename R, int TK>
 static const void* pick_kernel(int mode, int ft)
 {
-    if (mode == 1) return (const void*)k_trace_batch<R, TK>;
+    if (mode == 1)
+        return (ft & FT_ONE) ? (const void*)k_trace_batch<R, TK, FT_ONE> : (const void*)k_trace_batch<R, TK, 0>;
     if constexpr (std::is_same<R, double>::value && TK == TALLY_STEADY_ONE) {
         if (ft & FT_COOP) {
             if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, FT_COOP>;

@@ -106,8 +106,8 @@ def test_device_calls_reject_host_only_tables():
 
 
 def test_sizes_and_messages():
-    assert M.state_bytes(32, 1000) == 8 * 4096 + 7 * 4096
-    assert M.state_bytes(64, 1) == 15 * 256
+    assert M.state_bytes(32, 1000) == 9 * 4096 + 7 * 4096
+    assert M.state_bytes(64, 1) == 16 * 256
     with pytest.raises(M.MCBTEError):
         M.state_bytes(16, 10)
     assert M.batch_queue_bytes(64) > 64 * 8 * 3
@@ -116,3 +116,24 @@ def test_sizes_and_messages():
     tb = M.Tables(W.gray_slab(N=10), device=-1)
     out = np.zeros(1)
     assert M.lib().mcbte_table_export(tb.h, 3, out.ctypes.data_as(C.c_void_p), 0) == M.mcbte.ESIZE
+
+
+def test_two_phonon_clock_inputs():
+    """tau_imp: >= 0 and finite (0: no two-phonon process); the bulk kappa the tables report uses
+    the summed rates, as the oracle's does; the sensitivity estimators refuse two-clock tables."""
+    w = W.bulk_gradient(N=10, modes=W.silicon_like_modes(300.0, impurity_clock=True))
+    for bad_val in (-1e-12, float("inf"), float("nan")):
+        bad = W.with_(w)
+        bad["modes"]["tau_imp"][3] = bad_val
+        assert _status(bad) == M.mcbte.EINVAL
+        with pytest.raises(ValueError):
+            oracle.Tables(bad)
+    t = M.Tables(w, device=-1)
+    o = oracle.Tables(w)
+    assert t.info["kappa_bulk"] == pytest.approx(o.kappa_bulk, rel=1e-13)
+    one = M.Tables(W.bulk_gradient(N=10, modes=W.silicon_like_modes(300.0)), device=-1)
+    assert t.info["kappa_bulk"] == pytest.approx(one.info["kappa_bulk"], rel=1e-12)
+    run = M.make_run(1, 32)
+    dummy = C.c_void_p(1)
+    assert M.lib().mcbte_adjoint(t.h, C.byref(run), M.mcbte.SENS_SCORE, 0.0, 0, 10, dummy, dummy, None) \
+        == M.mcbte.EINVAL

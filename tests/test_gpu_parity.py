@@ -41,6 +41,14 @@ FP64_CASES = {
     "grid3d": lambda: W.with_(W.gray_slab(N=1500), **{"detectors.lo": (0.0, 0.0, 0.0),
                                                       "detectors.hi": (3e-8, 2e-8, 1e-7),
                                                       "detectors.n": (3, 2, 5)}),
+    # separate two-phonon and three-phonon clocks
+    "film_two_clocks": lambda: W.film(N=3000, modes=W.silicon_like_modes(300.0, impurity_clock=True)),
+    "gray_slab_two_clocks": lambda: W.with_(W.gray_slab(N=2000),
+                                            modes=W.gray_modes(6400.0, 3e-11, tau_imp=1.5e-11)),
+    "bulk_two_clocks": lambda: W.bulk_gradient(N=2000, n_scat_max=3,
+                                               modes=W.silicon_like_modes(300.0, impurity_clock=True)),
+    "transient_two_clocks": lambda: W.transient_bump(N=300, modes=W.silicon_like_modes(300.0, impurity_clock=True)),
+    "porous_two_clocks": lambda: W.porous_cell(N=1000, modes=W.silicon_like_modes(300.0, impurity_clock=True)),
 }
 
 

@@ -1,0 +1,140 @@
+"""Separate two-phonon and three-phonon clocks (section 3.3) on the HIP path, through the C ABI.
+
+The FP64 event sequences of two-clock workloads are compared bit-exactly with the oracle in
+test_gpu_parity.py (FP64_CASES); this file covers the emitted clocks, the state-buffer path,
+the batched kernel, launch shapes that route walks through the lone-lane and wave-cooperative
+paths, and the FP32 form against the FP64 oracle.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _pkg():
+    import paper_2104_03573_amd as M
+    return M
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _two_film(N, **kw):
+    return W.film(N=N, modes=W.silicon_like_modes(300.0, impurity_clock=True), **kw)
+
+
+def _lead(buf, precision, cap):
+    """The clocks' lead array of a state buffer (after the real and integer arrays)."""
+    b = buf.cpu().numpy()
+    rb = precision // 8
+    fb = (cap * rb + 255) // 256 * 256
+    ib = (cap * 4 + 255) // 256 * 256
+    off = 8 * fb + 7 * ib
+    return np.frombuffer(b[off:off + cap * rb].tobytes(), dtype=np.float64 if precision == 64 else np.float32)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_emitted_clocks_match_oracle(precision):
+    """Which clock fires first agrees exactly; the lead agrees to the rounding of two logarithms
+    (FP64) or of the FP32 form."""
+    import torch
+    M = _pkg()
+    w = _two_film(2000)
+    n = 2000
+    t = M.Tables(w)
+    o = oracle.Tables(w)
+    buf = torch.zeros(M.state_bytes(precision, n), dtype=torch.uint8, device="cuda")
+    M.emit(t, M.make_run(int(w["seed"]), precision), 0, n, buf, n)
+    torch.cuda.synchronize()
+    lead = _lead(buf, precision, n).astype(np.float64)
+    ref = np.array([o.emit_clocks(k) for k in range(n)])
+    first = np.array([o.emit_state(k)[0][7] for k in range(n)])     # the earlier clock
+    nx2 = np.signbit(lead).astype(int)
+    assert np.array_equal(nx2, ref[:, 1].astype(int))
+    assert 0 < nx2.sum() < n
+    assert np.all(np.isfinite(ref[:, 0])) and np.all(np.isfinite(lead))
+    # the lead is a difference of the two times: its error is bounded by theirs, i.e. by the
+    # later time's rounding (FP64: device and host logarithms within 2 ulp each)
+    later = first + ref[:, 0]
+    err = np.abs(np.abs(lead) - ref[:, 0])
+    if precision == 64:
+        assert np.all(err <= 4 * np.spacing(later)), (err / later).max()
+    else:
+        # FP32 form: single-precision logarithm, whose relative error grows for arguments
+        # near 1 (short times), as for the free flights of the emission test
+        rel = err / later
+        assert np.median(rel) < 2e-6 and rel.max() < 1e-2, (np.median(rel), rel.max())
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_emit_then_trace_equals_fused(precision):
+    M = _pkg()
+    w = _two_film(4000)
+    fused = M.run(w, precision=precision, n_log=300, log_stride=64)
+    staged = M.run(w, precision=precision, n_log=300, log_stride=64, emit_first=True)
+    assert np.array_equal(fused["counts_raw"], staged["counts_raw"])
+    assert fused["counts"]["two_phonon"] > 0
+    assert np.array_equal(fused["log"], staged["log"])
+    scale = np.abs(fused["raw"]).max()
+    assert np.abs(fused["raw"] - staged["raw"]).max() <= 1e-12 * scale
+
+
+def test_batched_launch_with_two_clock_instances_equals_solo_runs():
+    """The batched kernel with the two-clock code (some instance has a two-phonon process) next
+    to a single-clock instance."""
+    import torch
+    M = _pkg()
+    ws = [_two_film(6000, d=2e-8), W.film(N=3000, d=1e-7, T=100.0), _two_film(9000, d=5e-7, T=400.0)]
+    for i, w in enumerate(ws):
+        w["instance"] = 3 + i
+    for prec in (64, 32):
+        tabs = [M.Tables(w) for w in ws]
+        tallies = [t.new_tally() for t in tabs]
+        queue = torch.zeros(M.batch_queue_bytes(len(ws)), dtype=torch.uint8, device="cuda")
+        run = M.make_run(int(ws[0]["seed"]), prec)
+        M.trace_batch(tabs, [w["problem"]["N"] for w in ws], [w["instance"] for w in ws], tallies, run, queue)
+        for w, t, tl in zip(ws, tabs, tallies):
+            b = M.tally(t, tl)
+            s = M.run(w, precision=prec, tables=t)
+            assert np.array_equal(b["counts_raw"], s["counts_raw"]), (prec, b["counts"], s["counts"])
+            assert np.abs(t.raw(tl) - s["raw"]).max() <= 1e-12 * np.abs(s["raw"]).max()
+
+
+@pytest.mark.parametrize("name", ["film", "porous"])
+def test_launch_shapes_route_two_clock_walks_through_every_path(name):
+    """One-wave grids leave lanes walking alone (lone-lane walk) and the film's long flights go
+    to the wave-cooperative bouncing; every shape gives the same FP64 counters and sums."""
+    M = _pkg()
+    w = _two_film(6000, d=40e-9) if name == "film" else \
+        W.porous_cell(N=1500, modes=W.silicon_like_modes(300.0, impurity_clock=True))
+    base = M.run(w, precision=64)
+    assert base["counts"]["two_phonon"] > 0
+    for block, refill, grid in ((64, 1, 1), (64, 8, 3), (256, 32, 0)):
+        r = M.run(w, precision=64, block=block, refill=refill, grid=grid)
+        assert np.array_equal(r["counts_raw"], base["counts_raw"]), (block, refill, grid)
+        assert np.abs(r["raw"] - base["raw"]).max() <= 1e-12 * np.abs(base["raw"]).max()
+
+
+def test_fp32_two_clock_film_against_fp64_oracle():
+    """FP32 trajectories with both clocks against the FP64 oracle on the same particles: kappa
+    and the flux within 2e-4 relative, event counts within 1e-3."""
+    M = _pkg()
+    w = _two_film(100000)
+    got = M.run(w, precision=32)
+    ref = oracle.run(w, threads=THREADS)
+    rel_k = abs(got["kappa"] - ref["kappa"]) / abs(ref["kappa"])
+    c, rc = got["counts"], ref["counts"]
+    _say(f"[fp32 two clocks] kappa {got['kappa']:.6g} vs {ref['kappa']:.6g} (rel {rel_k:.2e}); "
+         f"two-phonon {c['two_phonon']} vs {rc['two_phonon']}, relaxations {c['relaxations']} vs {rc['relaxations']}")
+    assert c["particles"] == rc["particles"]
+    assert rel_k < 2e-4
+    for k in ("flights", "two_phonon", "relaxations", "diffuse"):
+        assert abs(c[k] - rc[k]) <= 1e-3 * rc[k], k
