@@ -672,6 +672,7 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     }
     // FP64 film-like problems: the kernel with the exact cooperative bouncing
     if (run->precision == 64 && t->host_view.coop_axis >= 0) ft |= FT_COOP;
+    if (!t->two) ft |= FT_ONE;      // the kernel without the two-clock code
     const int rc = plan_launch(&t, 1, run, 0, ft, lp);
     if (rc != MCBTE_OK) return rc;
     LaunchArgs a;
@@ -875,7 +876,7 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
     if (!g.ok) return MCBTE_EHIP;
     const int mode = estimator == MCBTE_SENS_PATHWISE ? 3 : (estimator == MCBTE_SENS_LOCAL ? 4 : 2);
     // FP64 film-like problems replay with the exact cooperative bouncing, as they trace
-    const int ft = (run->precision == 64 && t->host_view.coop_axis >= 0) ? FT_COOP : 0;
+    const int ft = ((run->precision == 64 && t->host_view.coop_axis >= 0) ? FT_COOP : 0) | FT_ONE;
     LaunchPlan lp;
     const int rc = plan_launch(&t, 1, run, mode, ft, lp);
     if (rc != MCBTE_OK) return rc;

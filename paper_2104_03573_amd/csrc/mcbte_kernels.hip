@@ -2234,29 +2234,36 @@ static void ensure_lds_limit(const void* fn, size_t lds)
 
 // the kernel of a launch: mode 0 trace, 1 batched trace, 2 likelihood-ratio replay, 3 pathwise
 // replay, 4 local pathwise replay; ft the optional features (FT_STATE | FT_LOG: a state buffer and/or an event log;
-// FT_WIDE: FP32 trace with the tally in LDS in FP32)
+// FT_WIDE: FP32 trace with the tally in LDS in FP32; FT_ONE: no table has a two-phonon clock, the
+// kernels without that code).  The replays refuse two-clock tables and are built without it.
+template <typename R, int TK, int ONE>
+static const void* pick_solo(int mode, int ft)
+{
+    if constexpr (std::is_same<R, double>::value && TK == TALLY_STEADY_ONE) {
+        if (ft & FT_COOP) {
+            if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, FT_COOP | FT_ONE>;
+            if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, FT_COOP | FT_ONE>;
+            if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, FT_COOP | FT_ONE>;
+            if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG | FT_COOP | ONE>;
+            return (const void*)k_trace_solo<R, TK, 0, FT_COOP | ONE>;
+        }
+    }
+    if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, FT_ONE>;
+    if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, FT_ONE>;
+    if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, FT_ONE>;
+    if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG | ONE>;
+    if constexpr (std::is_same<R, float>::value) {
+        if (ft & FT_WIDE) return (const void*)k_trace_solo<R, TK, 0, FT_WIDE | ONE>;
+    }
+    return (const void*)k_trace_solo<R, TK, 0, ONE>;
+}
+
 template <typename R, int TK>
 static const void* pick_kernel(int mode, int ft)
 {
     if (mode == 1)
         return (ft & FT_ONE) ? (const void*)k_trace_batch<R, TK, FT_ONE> : (const void*)k_trace_batch<R, TK, 0>;
-    if constexpr (std::is_same<R, double>::value && TK == TALLY_STEADY_ONE) {
-        if (ft & FT_COOP) {
-            if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, FT_COOP>;
-            if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, FT_COOP>;
-            if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, FT_COOP>;
-            if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG | FT_COOP>;
-            return (const void*)k_trace_solo<R, TK, 0, FT_COOP>;
-        }
-    }
-    if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, 0>;
-    if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, 0>;
-    if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, 0>;
-    if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG>;
-    if constexpr (std::is_same<R, float>::value) {
-        if (ft & FT_WIDE) return (const void*)k_trace_solo<R, TK, 0, FT_WIDE>;
-    }
-    return (const void*)k_trace_solo<R, TK, 0, 0>;
+    return (ft & FT_ONE) ? pick_solo<R, TK, FT_ONE>(mode, ft) : pick_solo<R, TK, 0>(mode, ft);
 }
 
 static const void* kernel_for(int mode, int precision, int tally_kind, int ft)

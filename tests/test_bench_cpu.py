@@ -40,3 +40,16 @@ def test_algorithmic_work_model_counts_each_event_once():
 def test_traffic_figure_is_withheld_for_an_unprofiled_kernel():
     import bench
     assert bench.profiled_traffic("no_such_kernel_profile") is None
+
+
+def test_work_model_adds_the_two_phonon_clock_draws():
+    import bench
+    O = bench.OPS
+    info = {"n_modes": 1400, "n_sources": 3}
+    geom = {"unbounded": (True, True, False), "cylinders": []}
+    counts = {"particles": 10, "flights": 100, "relaxations": 60, "nscat_end": 10, "diffuse": 30,
+              "rejections": 0, "two_phonon": 7}
+    one = bench.algorithmic_lane_ops(counts, info, geom, ncomp=2, transient=False)
+    two = bench.algorithmic_lane_ops(counts, info, geom, ncomp=2, transient=False, two_clocks=True)
+    clock = O["philox_block"] + O["free_flight"]
+    assert two - one == 7 * (O["philox_block"] + O["iso_dir"] + clock) + (10 + 50) * clock
