@@ -46,7 +46,7 @@ class Face(C.Structure):
 
 class Cyl(C.Structure):
     _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("r", C.c_double), ("id", C.c_int32),
-                ("type", C.c_int32), ("spec", C.c_double)]
+                ("type", C.c_int32), ("spec", C.c_double), ("spec_wc", C.c_double)]
 
 
 class Geom(C.Structure):
@@ -195,8 +195,9 @@ class Tables:
             G.face[fid - 1].type = int(ty)
             G.face[fid - 1].data[0], G.face[fid - 1].data[1], G.face[fid - 1].data[2] = d0, d1, d2
         G.n_cyl = len(g["cylinders"])
-        for i, (cx, cy, r, cid, ty, spec) in enumerate(g["cylinders"]):
-            G.cyl[i] = Cyl(cx, cy, r, int(cid), int(ty), spec)
+        for i, c in enumerate(g["cylinders"]):
+            cx, cy, r, cid, ty, spec = c[:6]
+            G.cyl[i] = Cyl(cx, cy, r, int(cid), int(ty), spec, float(c[6]) if len(c) > 6 else 0.0)
         G.volume = g["volume"]
         self._geom = G
         d = w["detectors"]

@@ -39,6 +39,7 @@ static const int FACE_SIDE[6] = {0, 1, 1, 0, 0, 1};
 struct orc_tables {
     int32_t M;
     double *C, *v, *tau;
+    double* omega;       /* angular frequency of each row (frequency-dependent specularity) */
     double* tau2;        /* two-phonon (impurity) relaxation time of each row; 0: no such process */
     int32_t two;         /* some row has a two-phonon clock */
     double C_tot, Wv, kappa_bulk;
@@ -201,7 +202,7 @@ static double extent(const orc_geom* g, int a) { return g->unbounded[a] ? 1.0 : 
 void orc_free(orc_tables* t)
 {
     if (!t) return;
-    free(t->C); free(t->v); free(t->tau); free(t->tau2);
+    free(t->C); free(t->v); free(t->tau); free(t->tau2); free(t->omega);
     free(t->thr_ic); free(t->thr_wall); free(t->thr_rel);
     free(t->src_kind); free(t->src_ref); free(t->src_sign); free(t->src_E); free(t->thr_src);
     free(t->t_meas); free(t->ic_edges); free(t->ic_dT);
@@ -221,6 +222,8 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
         if (g->unbounded[a]) continue;
         int ty = g->face[id - 1].type;
         if (ty < B_ISO || ty > B_PERI) return E_GEOM;
+        if (ty == B_ADIA && (!(g->face[id - 1].data[1] >= 0.0) || !isfinite(g->face[id - 1].data[1])))
+            return E_GEOM;   /* the specular cutoff frequency */
     }
     for (int a = 0; a < 3; ++a) {          /* periodic faces come in pairs on one axis */
         if (g->unbounded[a]) continue;
@@ -234,6 +237,7 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
         const orc_cyl* y = &g->cyl[c];
         if (g->unbounded[0] || g->unbounded[1] || !(y->r > 0.0)) return E_GEOM;
         if (y->type != B_ADIA) return E_GEOM;
+        if (!(y->spec_wc >= 0.0) || !isfinite(y->spec_wc)) return E_GEOM;
         if (y->cx - y->r < 0.0 || y->cx + y->r > g->L[0] || y->cy - y->r < 0.0 || y->cy + y->r > g->L[1])
             return E_GEOM;
         if (y->id < 7 || (c > 0 && y->id <= g->cyl[c - 1].id)) return E_GEOM;
@@ -261,11 +265,12 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
     t->v = (double*)malloc(sizeof(double) * M);
     t->tau = (double*)malloc(sizeof(double) * M);
     t->tau2 = (double*)malloc(sizeof(double) * M);
+    t->omega = (double*)malloc(sizeof(double) * M);
     t->thr_ic = (uint64_t*)malloc(sizeof(uint64_t) * M);
     t->thr_wall = (uint64_t*)malloc(sizeof(uint64_t) * M);
     t->thr_rel = (uint64_t*)malloc(sizeof(uint64_t) * M);
     double* w = (double*)malloc(sizeof(double) * M);
-    if (!t->C || !t->v || !t->tau || !t->tau2 || !t->thr_ic || !t->thr_wall || !t->thr_rel || !w) {
+    if (!t->C || !t->v || !t->tau || !t->tau2 || !t->omega || !t->thr_ic || !t->thr_wall || !t->thr_rel || !w) {
         free(w); orc_free(t); return E_NOMEM;
     }
     /* per-mode heat capacity: given (second format) or DOS * delta-omega * de/dT (first format) */
@@ -276,6 +281,7 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
         t->v[m] = r->v;
         t->tau[m] = r->tau;
         t->tau2[m] = r->tau_imp;
+        t->omega[m] = r->omega;
         if (r->tau_imp > 0.0) t->two = 1;
         if (pr->format == 1) {
             if (r->dos < 0.0 || r->domega < 0.0 || !(r->omega > 0.0)) { free(w); orc_free(t); return E_INVAL; }
@@ -1081,17 +1087,22 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
         }
         /* boundary interaction (sections 3.5.3-3.5.5) */
         int type;
-        double spec = 0.0;
+        double spec = 0.0, spec_wc = 0.0;
         const orc_cyl* cy = NULL;
         if (hit <= 6) {
             type = g->face[hit - 1].type;
             spec = g->face[hit - 1].data[0];
+            spec_wc = g->face[hit - 1].data[1];
         } else {
             for (int c = 0; c < g->n_cyl; ++c)
                 if (g->cyl[c].id == hit) cy = &g->cyl[c];
             type = cy->type;
             spec = cy->spec;
+            spec_wc = cy->spec_wc;
         }
+        /* section 3.5.3: the specularity may depend on the phonon; below the boundary's cutoff
+           frequency the reflection is specular */
+        if (type == B_ADIA && spec_wc > 0.0 && t->omega[p.m] < spec_wc) spec = 1.0;
         if (type == B_ISO) {
             counts[ORC_C_ABSORBED] += 1;
             LOG(ORC_EV_ABSORB, hit, p.m);

@@ -23,7 +23,10 @@
 /* one material row: first format uses dos/domega, second format gives C */
 typedef struct { double omega, dos, v, domega, tau, C, tau_imp; int32_t bin, branch; } orc_mode;
 typedef struct { int32_t type, pad; double data[3]; } orc_face;
-typedef struct { double cx, cy, r; int32_t id, type; double spec; } orc_cyl;
+/* pore: spec is the degree of specularity d; spec_wc > 0 makes phonons with omega < spec_wc reflect
+   specularly whatever d is (frequency-dependent specularity, as in the paper's nanomesh with the
+   phonons below 2 THz specular).  Adiabatic faces carry the same cutoff in data[1]. */
+typedef struct { double cx, cy, r; int32_t id, type; double spec, spec_wc; } orc_cyl;
 typedef struct {
     double L[3];
     int32_t unbounded[3];

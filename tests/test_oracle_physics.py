@@ -546,3 +546,52 @@ def test_two_phonon_draws_use_their_own_records():
     raw2, c2, m2, log2 = o2.trace_range(sd, 0, 0, 3000, n_log=3000, log_stride=64)
     assert np.array_equal(c1, c2) and c2[12] == 0
     assert np.array_equal(raw1, raw2) and np.array_equal(m1, m2) and np.array_equal(log1, log2)
+
+
+# --------------------------------------------------------------------------------------------
+# Frequency-dependent specularity (section 3.5.3: the specularity depends on the phonon; the
+# paper's nanomesh reflects the phonons below 2 THz specularly): a boundary's cutoff frequency
+# makes every phonon below it reflect specularly, the others with the boundary's d.
+# --------------------------------------------------------------------------------------------
+
+def test_film_with_a_specular_cutoff_matches_fuchs_sondheimer_per_mode():
+    """Diffuse walls above the cutoff, specular below: kappa = sum_m kappa_m S(d / Lambda_m, p_m)
+    with p_m = 1 below the cutoff and 0 above."""
+    d = 100e-9
+    wc = W.OMEGA_2THZ * 2.5                         # 5 THz: a sizeable share of the flux is specular
+    w = W.film(N=150000, d=d, spec_omega=wc)
+    r = oracle.run(w, threads=THREADS)
+    C = r["tables"].get("C")
+    m = w["modes"]
+    lam = m["v"] * m["tau"]
+    p = (m["omega"] < wc).astype(float)
+    k_ref = sum(C[i] * m["v"][i] ** 2 * m["tau"][i] / 3.0 * cf.fs_suppression(d / lam[i], p[i])
+                for i in range(len(m)))
+    k_diffuse = sum(C[i] * m["v"][i] ** 2 * m["tau"][i] / 3.0 * cf.fs_suppression(d / lam[i])
+                    for i in range(len(m)))
+    assert k_ref > k_diffuse + 6.0 * r["kappa_sigma"]     # the pin separates the two readings
+    assert abs(r["kappa"] - k_ref) < 3.0 * r["kappa_sigma"], (r["kappa"], r["kappa_sigma"], k_ref)
+    assert r["counts"]["specular"] > 0 and r["counts"]["diffuse"] > 0
+
+
+def test_specular_cutoff_extremes_reduce_to_constant_specularity():
+    """A cutoff above every phonon is a specular wall, one below every phonon leaves d in force:
+    counts, tallies and event logs bit-identical to those runs (no draw is added or moved)."""
+    def trace(w):
+        o = oracle.Tables(w)
+        return o.trace_range(int(w["seed"]), 0, 0, 2000, n_log=2000, log_stride=64)
+    for d_wall in (0.0, 0.4):
+        base = W.film(N=2000, d=30e-9, specularity=d_wall)
+        low = W.film(N=2000, d=30e-9, specularity=d_wall, spec_omega=1.0)       # below every row
+        for a, b in zip(trace(base), trace(low)):
+            assert np.array_equal(a, b)
+    spec = W.film(N=2000, d=30e-9, specularity=1.0)
+    high = W.film(N=2000, d=30e-9, specularity=0.4, spec_omega=1e15)             # above every row
+    for a, b in zip(trace(spec), trace(high)):
+        assert np.array_equal(a, b)
+    pore = W.porous_cell(N=500, specularity=0.0)
+    pore_hi = W.porous_cell(N=500, specularity=0.0, spec_omega=1e15)
+    pore_sp = W.porous_cell(N=500, specularity=1.0)
+    for a, b in zip(trace(pore_sp), trace(pore_hi)):
+        assert np.array_equal(a, b)
+    assert not np.array_equal(trace(pore)[1], trace(pore_hi)[1])

@@ -230,7 +230,7 @@ def _march(w, x, o, step):
             idx = np.flatnonzero(bad)
             if idx.size and ks[idx[0]] * step < first:
                 first, who = ks[idx[0]] * step, face_of[(a, side)]
-    for (cx, cy, r, cid, _, _) in g["cylinders"]:
+    for (cx, cy, r, cid) in (c[:4] for c in g["cylinders"]):
         idx = np.flatnonzero((P[:, 0] - cx) ** 2 + (P[:, 1] - cy) ** 2 < r * r)
         if idx.size and ks[idx[0]] * step < first:
             first, who = ks[idx[0]] * step, cid

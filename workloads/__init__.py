@@ -47,6 +47,7 @@ OMEGA_MAX_TA = 3.0e13
 TAU_A = 1.3e-45      # s^3     (impurity-like  A omega^4)
 TAU_B = 1.7e-19      # s / K   (Umklapp-like   B omega^2 T exp(-C/T))
 TAU_C = 137.0        # K
+OMEGA_2THZ = 2.0 * math.pi * 2.0e12   # rad/s: the cutoff below which the paper's nanomesh reflects specularly
 
 
 def silicon_like_modes(T: float, n_bins: int = 1000, impurity_clock: bool = False) -> np.ndarray:
@@ -152,15 +153,17 @@ def gray_slab(N=100_000, Lambda=100e-9, L=100e-9, v=6400.0, T_hot=301.0, T_cold=
 
 
 def film(N=1_000_000, d=100e-9, T=300.0, gradT=-1.0e7, specularity=0.0, n_scat_max=10,
-         z_bins=0, seed=SEED_BASE + 2, modes=None):
+         z_bins=0, seed=SEED_BASE + 2, modes=None, spec_omega=0.0):
     """Steady in-plane thin film: diffuse (or partially specular) walls at z = 0, d; in-plane
-    axes unbounded; uniform gradient along y driving the spatially varying control."""
+    axes unbounded; uniform gradient along y driving the spatially varying control.
+    spec_omega > 0: phonons with omega below it reflect specularly off the walls (boundary data
+    word 2 of an adiabatic wall)."""
     det = _detectors((0, 0, 0), (0, 0, d), (0, 0, z_bins), MASK_T | MASK_QY)
     return {
         "name": "film",
         "modes": silicon_like_modes(T) if modes is None else modes,
         "geometry": _geometry((1.0, 1.0, d), (True, True, False),
-                              {5: (ADIABATIC, specularity, 0, 0), 6: (ADIABATIC, specularity, 0, 0)},
+                              {5: (ADIABATIC, specularity, spec_omega, 0), 6: (ADIABATIC, specularity, spec_omega, 0)},
                               gradT=(0.0, gradT, 0.0)),
         "detectors": det,
         "problem": _problem(N, T, n_scat_max, score_axis=1, fmt=1),
@@ -206,8 +209,9 @@ def film_sweep(scale=1.0, seed=SEED_BASE + 4):
 
 
 def porous_cell(N=100_000_000, W=500e-9, porosity=0.25, T=300.0, gradT=-2.0e6, n_scat_max=10,
-                specularity=0.0, seed=SEED_BASE + 5, modes=None):
-    """3-D periodic cubic cell with a centred z-axis cylindrical pore (diffuse pore wall)."""
+                specularity=0.0, seed=SEED_BASE + 5, modes=None, spec_omega=0.0):
+    """3-D periodic cubic cell with a centred z-axis cylindrical pore (diffuse pore wall);
+    spec_omega > 0: phonons with omega below it reflect specularly off the pore."""
     r = W * math.sqrt(porosity / math.pi)
     faces = {1: (PERIODIC, 0, W, 0), 3: (PERIODIC, 0, -W, 0), 2: (PERIODIC, -W, 0, 0),
              4: (PERIODIC, W, 0, 0), 5: (PERIODIC, 0, 0, W), 6: (PERIODIC, 0, 0, -W)}
@@ -215,7 +219,7 @@ def porous_cell(N=100_000_000, W=500e-9, porosity=0.25, T=300.0, gradT=-2.0e6, n
         "name": "porous_cell",
         "modes": silicon_like_modes(T) if modes is None else modes,
         "geometry": _geometry((W, W, W), (False, False, False), faces,
-                              cylinders=[(0.5 * W, 0.5 * W, r, 7, ADIABATIC, specularity)],
+                              cylinders=[(0.5 * W, 0.5 * W, r, 7, ADIABATIC, specularity, spec_omega)],
                               gradT=(0.0, gradT, 0.0)),
         "detectors": _detectors(mask=MASK_T | MASK_QY),
         "problem": _problem(N, T, n_scat_max, score_axis=1, fmt=1),
