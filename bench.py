@@ -99,6 +99,10 @@ def workload(name: str, scale: float = 1.0):
         # the impurity-like A omega^4 term on its own (two-phonon) clock, section 3.3
         return (W.film(N=int(1_000_000 * scale), modes=W.silicon_like_modes(300.0, impurity_clock=True)),
                 "film_d100nm_T300K_1400modes_N1e6_nscat10_two_clocks")
+    if name == "porous_cell_spec2thz":
+        # the pore reflects the phonons below 2 THz specularly (the paper's nanomesh variant)
+        return (W.porous_cell(N=int(100_000_000 * scale), spec_omega=W.OMEGA_2THZ),
+                "porous_cell_500nm_phi0.25_N1e8_specular_below_2THz")
     if name == "gray_slab":
         return W.gray_slab(N=int(100_000 * scale)), "gray_slab_L100nm_Kn1_N1e5_50bins"
     if name == "porous_cell":
@@ -418,7 +422,8 @@ def other_forms(args, M, torch) -> dict:
     forms = {}
     plan = [("gray_slab_fp64", "gray_slab", 64, 10), ("film_fp64", "film", 64, 5),
             ("transient_fp32", "transient", 32, 3), ("porous_cell_fp32", "porous_cell", 32, 3),
-            ("film_two_clocks_fp32", "film_two_clocks", 32, 10)]
+            ("film_two_clocks_fp32", "film_two_clocks", 32, 10),
+            ("porous_cell_specular_below_2THz_fp32", "porous_cell_spec2thz", 32, 3)]
     # each configuration is tuned on at most 1e6 particles with one timed launch per candidate
     # (the calibration stays outside the timed steps but inside the run's few minutes)
     for key, name, prec, steps in plan:

@@ -89,6 +89,11 @@ typedef struct {
     int32_t bin, branch;
 } mcbte_mode;
 
+/* boundary-table row (section 4.2): isothermal data[0] = T_b; periodic data = the translation
+   vector; adiabatic data[0] = d (degree of specularity, section 3.5.3) and data[1] = a cutoff
+   angular frequency (rad/s, >= 0): a phonon with omega below it reflects specularly whatever d
+   is (the frequency-dependent specularity of the paper's nanomesh, phonons below 2 THz
+   specular); 0 = none. */
 typedef struct {
     int32_t type;               /* MCBTE_ISOTHERMAL / _ADIABATIC / _PERIODIC */
     int32_t reserved;
@@ -101,6 +106,7 @@ typedef struct {
     int32_t id;                 /* boundary id, >= 7, strictly increasing over the array */
     int32_t type;               /* MCBTE_ADIABATIC */
     double specularity;
+    double spec_omega;          /* cutoff angular frequency below which reflection is specular (0: none) */
 } mcbte_pore;
 
 /* Box [0, L0] x [0, L1] x [0, L2] (one corner at the origin, section 4.2).  face[id - 1] holds
@@ -321,8 +327,8 @@ int mcbte_autotune(const mcbte_tables* const* tables, int32_t n_inst, const int6
    the caller; successive calls with one estimator accumulate): adj[0, n_bins) the per-bin sums,
    adj[n_bins] the relaxation-draw sum B, adj[n_bins + 1] the count of terms left out as not
    finite, adj[n_bins + 2] library scratch.  Async on `stream`.  Errors: MCBTE_EINVAL (transient run, event log set, unknown
-   estimator, n_scat_max outside the pathwise range, tables with a two-phonon clock), MCBTE_ENODEV,
-   MCBTE_EHIP. */
+   estimator, n_scat_max outside the pathwise range, tables with a two-phonon clock or a specular
+   cutoff frequency), MCBTE_ENODEV, MCBTE_EHIP. */
 int mcbte_adjoint(const mcbte_tables* tables, const mcbte_run* run, int32_t estimator, double lambda_split,
                   int64_t first_pid, int64_t n, const double* particle_F, double* adj, void* stream);
 

@@ -21,7 +21,8 @@ enum TallyKind : int32_t { TALLY_STEADY_ONE = 0, TALLY_STEADY_GRID = 1, TALLY_TR
 // whose whole LDS holds an FP32 copy of a tally too large for the FP64 one, the mode tables
 // being read from global memory instead, and (FP64 film-like problems) the exact cooperative
 // bouncing, whose registers the other FP64 problems need not reserve
-enum : int { FT_STATE = 1, FT_LOG = 2, FT_WIDE = 4, FT_COOP = 8, FT_ONE = 16 };   // FT_ONE: no two-phonon clock in any table
+// FT_PLAIN: no table uses the two-phonon clock or a specular cutoff frequency (kernels without that code)
+enum : int { FT_STATE = 1, FT_LOG = 2, FT_WIDE = 4, FT_COOP = 8, FT_PLAIN = 16 };
 
 // Geometry in the form the flight loop reads it (uniform across a launch; scalar loads).
 struct DevPore32 { float cx, cy, r; int32_t id; };
@@ -57,6 +58,9 @@ struct DevGeom {
     uint32_t pore_cls[2];
     DevPore32 pore32[MCBTE_DEV_MAX_PORES];
     DevPore64 pore64[MCBTE_DEV_MAX_PORES];
+    // frequency-dependent specularity: below these angular frequencies reflection is specular (0: none)
+    double face_wc[6];
+    double pore_wc[MCBTE_DEV_MAX_PORES];
 };
 
 struct DevDet {
@@ -101,8 +105,11 @@ struct DevTab {
     const uint32_t* rel_guide;   // 256 packed search bounds of the relaxation draw, or NULL
     const double* tau2_64;       // two-phonon relaxation time of each row (0: no such process)
     const float* tau2_32;
+    const double* omega64;       // angular frequency of each row
     int32_t n_bins;
     int32_t two;                 // some row has a two-phonon clock
+    int32_t spec_w;              // some boundary has a specular cutoff frequency
+    int32_t pad3;
     DevGeom g;
     DevDet det;
 };

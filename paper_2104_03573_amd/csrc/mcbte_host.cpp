@@ -98,6 +98,8 @@ struct mcbte_tables {
     // host tables
     std::vector<double> C, v, tau, tau2, src_E, ic_edges, ic_dT, t_meas;   // tau2: two-phonon clock (0: none)
     bool two = false;      // some row has a two-phonon clock
+    bool spec_w = false;   // some boundary has a specular cutoff frequency
+    std::vector<double> omega;
     std::vector<uint64_t> thr_ic, thr_wall, thr_rel, thr_src;
     std::vector<int32_t> src_kind, src_ref, src_sign, bin_of;
     std::vector<double> P_bin;   // relaxation probability mass per frequency bin
@@ -158,6 +160,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         const int ty = g.face[i].type;
         if (ty != MCBTE_ISOTHERMAL && ty != MCBTE_ADIABATIC && ty != MCBTE_PERIODIC) return MCBTE_EGEOM;
         if (ty == MCBTE_ADIABATIC && !(g.face[i].data[0] >= 0.0 && g.face[i].data[0] <= 1.0)) return MCBTE_EGEOM;
+        if (ty == MCBTE_ADIABATIC && !(g.face[i].data[1] >= 0.0 && std::isfinite(g.face[i].data[1]))) return MCBTE_EGEOM;
     }
     for (int a = 0; a < 3; ++a) {
         if (g.unbounded[a]) continue;
@@ -180,6 +183,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         const mcbte_pore& p = g.pore[c];
         if (g.unbounded[0] || g.unbounded[1] || !(p.r > 0.0) || p.type != MCBTE_ADIABATIC) return MCBTE_EGEOM;
         if (!(p.specularity >= 0.0 && p.specularity <= 1.0)) return MCBTE_EGEOM;
+        if (!(p.spec_omega >= 0.0 && std::isfinite(p.spec_omega))) return MCBTE_EGEOM;
         if (p.cx - p.r < 0.0 || p.cx + p.r > g.L[0] || p.cy - p.r < 0.0 || p.cy + p.r > g.L[1]) return MCBTE_EGEOM;
         if (p.id < 7 || p.id > 255 || (c > 0 && p.id <= g.pore[c - 1].id)) return MCBTE_EGEOM;
     }
@@ -213,6 +217,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     t->v.resize(M);
     t->tau.resize(M);
     t->tau2.resize(M);
+    t->omega.resize(M);
     for (int m = 0; m < M; ++m) {
         const mcbte_mode& r = modes[m];
         if (!(r.v > 0.0) || !(r.tau > 0.0)) { delete t; return MCBTE_EINVAL; }
@@ -221,6 +226,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         t->tau[m] = r.tau;
         t->tau2[m] = r.tau_imp;
         if (r.tau_imp > 0.0) t->two = true;
+        t->omega[m] = r.omega;
         if (pr.format == 1) {
             if (!(r.dos >= 0.0) || !(r.domega >= 0.0) || !(r.omega > 0.0)) { delete t; return MCBTE_EINVAL; }
             t->C[m] = (r.dos * r.domega) * bose_einstein_dedT(r.omega, pr.T_lin);
@@ -360,10 +366,16 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         for (int a = 0; a < 3; ++a)
             if (!g.unbounded[a]) { ++nb; axis = a; }
         if (nb == 1 && g.n_pores == 0 && !pr.transient && h.tally_kind == TALLY_STEADY_ONE) {
+            // (with a specular cutoff, the same one on both walls: a phonon's class is then the
+            // same at every bounce of a chain, and the kernel only starts chains of diffuse ones)
             bool diffuse = true;
-            for (int i = 0; i < 6; ++i)
-                if (kFaceAxis[i] == axis && !(g.face[i].type == MCBTE_ADIABATIC && g.face[i].data[0] == 0.0))
-                    diffuse = false;
+            double wc = -1.0;
+            for (int i = 0; i < 6; ++i) {
+                if (kFaceAxis[i] != axis) continue;
+                if (!(g.face[i].type == MCBTE_ADIABATIC && g.face[i].data[0] == 0.0)) diffuse = false;
+                if (wc >= 0.0 && g.face[i].data[1] != wc) diffuse = false;
+                wc = g.face[i].data[1];
+            }
             if (diffuse) {
                 h.coop_axis = axis;
                 h.coop_min_path = 16.0 * g.L[axis];
@@ -393,6 +405,8 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         dg.face_thr[i] = (d > 0.0 && d < 1.0) ? (uint64_t)(d * kTwo64) : 0;
         dg.face_code[0] |= ((uint32_t)dg.face_type[i] | surf_class<float>(d) << 2) << (4 * i);
         dg.face_code[1] |= ((uint32_t)dg.face_type[i] | surf_class<double>(d) << 2) << (4 * i);
+        dg.face_wc[i] = dg.face_type[i] == MCBTE_ADIABATIC ? g.face[i].data[1] : 0.0;
+        if (dg.face_wc[i] > 0.0) t->spec_w = true;
     }
     for (int a = 0; a < 3; ++a) dg.unb_mask |= (uint32_t)dg.unb[a] << a;
     dg.n_pores = g.n_pores;
@@ -411,7 +425,10 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         dg.pore64[c] = DevPore64{p.cx, p.cy, p.r, p.id, 0};
         dg.pore_cls[0] |= surf_class<float>(p.specularity) << (2 * c);
         dg.pore_cls[1] |= surf_class<double>(p.specularity) << (2 * c);
+        dg.pore_wc[c] = p.spec_omega;
+        if (p.spec_omega > 0.0) t->spec_w = true;
     }
+    h.spec_w = t->spec_w ? 1 : 0;
     DevDet& dd = h.det;
     int nc = 0;
     for (int q = 0; q < 4; ++q) {
@@ -490,6 +507,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         add(guide.data(), 4 * 256);
         add(t->tau2.data(), 8 * (size_t)M);
         add(tau2_32.data(), 4 * (size_t)M);
+        add(t->omega.data(), 8 * (size_t)M);
         size_t total = 0;
         std::vector<size_t> off;
         for (auto& p : parts) {
@@ -521,6 +539,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         h.rel_guide = M <= 65535 ? (const uint32_t*)dptr(16) : nullptr;
         h.tau2_64 = (const double*)dptr(17);
         h.tau2_32 = (const float*)dptr(18);
+        h.omega64 = (const double*)dptr(19);
         parts[0].first = &h;
         for (size_t i = 0; i < parts.size(); ++i) {
             if (parts[i].second == 0) continue;
@@ -672,7 +691,7 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     }
     // FP64 film-like problems: the kernel with the exact cooperative bouncing
     if (run->precision == 64 && t->host_view.coop_axis >= 0) ft |= FT_COOP;
-    if (!t->two) ft |= FT_ONE;      // the kernel without the two-clock code
+    if (!t->two && !t->spec_w) ft |= FT_PLAIN;   // the kernel without the extended physics
     const int rc = plan_launch(&t, 1, run, 0, ft, lp);
     if (rc != MCBTE_OK) return rc;
     LaunchArgs a;
@@ -726,10 +745,10 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     if (!g.ok) return MCBTE_EHIP;
     LaunchPlan lp;
     if (run->particle_F) return MCBTE_EINVAL;
-    // the batched kernel without the two-clock code unless some instance needs it
-    int ft = FT_ONE;
+    // the batched kernel without the extended physics unless some instance needs it
+    int ft = FT_PLAIN;
     for (int i = 0; i < n_inst; ++i)
-        if (ts[i]->two) ft = 0;
+        if (ts[i]->two || ts[i]->spec_w) ft = 0;
     int rc = plan_launch(ts, n_inst, run, 1, ft, lp);
     if (rc != MCBTE_OK) return rc;
     // chunking: items of chunk_size particles, instance-major
@@ -866,6 +885,7 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
     if (estimator != MCBTE_SENS_SCORE && estimator != MCBTE_SENS_PATHWISE && estimator != MCBTE_SENS_LOCAL)
         return MCBTE_EINVAL;
     if (t->two) return MCBTE_EINVAL;       // the estimators differentiate the one-clock flight law
+    if (t->spec_w) return MCBTE_EINVAL;    // the replays are built for constant specularities
     if (t->device < 0 || !t->d_tab) return MCBTE_ENODEV;
     if (t->prob.transient) return MCBTE_EINVAL;
     if (estimator == MCBTE_SENS_PATHWISE &&
@@ -876,7 +896,7 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
     if (!g.ok) return MCBTE_EHIP;
     const int mode = estimator == MCBTE_SENS_PATHWISE ? 3 : (estimator == MCBTE_SENS_LOCAL ? 4 : 2);
     // FP64 film-like problems replay with the exact cooperative bouncing, as they trace
-    const int ft = ((run->precision == 64 && t->host_view.coop_axis >= 0) ? FT_COOP : 0) | FT_ONE;
+    const int ft = ((run->precision == 64 && t->host_view.coop_axis >= 0) ? FT_COOP : 0) | FT_PLAIN;
     LaunchPlan lp;
     const int rc = plan_launch(&t, 1, run, mode, ft, lp);
     if (rc != MCBTE_OK) return rc;

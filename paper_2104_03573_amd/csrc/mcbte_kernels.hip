@@ -1036,10 +1036,10 @@ __device__ __forceinline__ void grid_wave(const DevTab& T, const Hot<R>& H, cons
 // the others.  Returns true if the particle left the box on the way (the caller ends it).
 template <typename R>
 __device__ __forceinline__ bool lone_chain(const Hot<R>& H, const TallyCtx& tc, const Stream& st, Part<R>& p,
-                                           LaneCounts& cnt, R vm, R sg)
+                                           LaneCounts& cnt, R vm, R sg, uint32_t pcls)
 {
     if (H.n_pores > 1) return false;
-    const uint32_t pcls = H.pcls & 3u;       // the pore's reflection class
+    // pcls: the pore's reflection class for this phonon
     const bool pore_walk = H.n_pores == 1 && pcls != SURF_PARTIAL;
     bool ok[3], up[3], per[3];
     int fid[3];
@@ -1169,14 +1169,20 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     int hit, pore, ev, fa, fs;
     R pcx, pcy, pr;                      // centre and radius of the pore hit
     uint32_t fcode;
-    constexpr bool TWO = (FT & FT_ONE) == 0;     // the two-clock code is compiled in
-    if (TWO && T.two) resolve_clocks<R>(T, st, p);
+    // the extended physics (two-phonon clock, specular cutoff frequencies) is compiled in
+    constexpr bool EXT = (FT & FT_PLAIN) == 0;
+    if (EXT && T.two) resolve_clocks<R>(T, st, p);
     if constexpr (TK == TALLY_STEADY_ONE && AK != 2 && (FT & FT_LOG) == 0) {
-        if (chain && lone_chain<R>(H, tc, st, p, cnt, vm, sg)) {   // left the box on the way
-            ++cnt.c[10];
-            if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
-                adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
-            return true;
+        if (chain) {
+            uint32_t pc0 = H.pcls & 3u;      // the first pore's reflection class for this phonon
+            if (EXT && T.spec_w && H.n_pores == 1 && g.pore_wc[0] > 0.0 && T.omega64[p.m] < g.pore_wc[0])
+                pc0 = SURF_SPECULAR;
+            if (lone_chain<R>(H, tc, st, p, cnt, vm, sg, pc0)) {   // left the box on the way
+                ++cnt.c[10];
+                if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
+                    adj.add(T.bin_of[p.m], (double)(p.dtr0 - p.dtr) / T.tau64[p.m], adj.F_total - p.F0);
+                return true;
+            }
         }
     }
     for (;;) {
@@ -1341,7 +1347,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     // is the earlier one, else a three-phonon relaxation
     bool two_ev = false;
     bool relax = (ev == 0);
-    if (TWO && relax && T.two && signbit(p.lead)) {
+    if (EXT && relax && T.two && signbit(p.lead)) {
         relax = false;
         two_ev = true;
     }
@@ -1373,6 +1379,11 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             btype = 2;
             cls = (H.pcls >> (2 * pore)) & 3u;
         }
+        // frequency-dependent specularity: below the boundary's cutoff the reflection is specular
+        if (EXT && T.spec_w && btype == 2) {
+            const double wc = hit <= 6 ? g.face_wc[hit - 1] : g.pore_wc[pore];
+            if (wc > 0.0 && T.omega64[p.m] < wc) cls = SURF_SPECULAR;
+        }
         if (btype == 1) {
             ++cnt.c[6];
             lg.put(EV_ABSORB, hit, p.m);
@@ -1387,7 +1398,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     // FP32 trajectories, which it does not log; coop_exact for the FP64 ones)
     constexpr bool COOP = std::is_same<R, float>::value || (FT & FT_COOP) != 0;
     if (COOP && ev == 1 && H.coop_axis >= 0 && fa == H.coop_axis && (std::is_same<R, double>::value || !lg.row) &&
-        vm * p.dtr > H.coop_min) {
+        vm * p.dtr > H.coop_min && (!EXT || cls == SURF_DIFFUSE)) {
         if (AK == 2) pc.plane(fa, false);    // the chain starts with a diffuse reflection
         coop = true;
         return false;
@@ -1426,7 +1437,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             p.o[1] = sth * sn;
             p.o[2] = mu;
             p.dtr = -tb.tau[p.m] * r_log(R(1) - unif<R>(w0.z, w0.w));
-            if (TWO && T.two) p.lead = R(NAN);   // both clocks redrawn: the two-phonon one next step
+            if (EXT && T.two) p.lead = R(NAN);   // both clocks redrawn: the two-phonon one next step
             lg.put(EV_RELAX, 0, p.m);
             if (AK != 0) {
                 adj.add(T.bin_of[p.m], -1.0, adj.F_total - p.cq);
@@ -2234,36 +2245,36 @@ static void ensure_lds_limit(const void* fn, size_t lds)
 
 // the kernel of a launch: mode 0 trace, 1 batched trace, 2 likelihood-ratio replay, 3 pathwise
 // replay, 4 local pathwise replay; ft the optional features (FT_STATE | FT_LOG: a state buffer and/or an event log;
-// FT_WIDE: FP32 trace with the tally in LDS in FP32; FT_ONE: no table has a two-phonon clock, the
-// kernels without that code).  The replays refuse two-clock tables and are built without it.
-template <typename R, int TK, int ONE>
+// FT_WIDE: FP32 trace with the tally in LDS in FP32; FT_PLAIN: no table has a two-phonon clock or a
+// specular cutoff, the kernels without that code).  The replays refuse such tables and are built without it.
+template <typename R, int TK, int PLAIN>
 static const void* pick_solo(int mode, int ft)
 {
     if constexpr (std::is_same<R, double>::value && TK == TALLY_STEADY_ONE) {
         if (ft & FT_COOP) {
-            if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, FT_COOP | FT_ONE>;
-            if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, FT_COOP | FT_ONE>;
-            if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, FT_COOP | FT_ONE>;
-            if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG | FT_COOP | ONE>;
-            return (const void*)k_trace_solo<R, TK, 0, FT_COOP | ONE>;
+            if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, FT_COOP | FT_PLAIN>;
+            if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, FT_COOP | FT_PLAIN>;
+            if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, FT_COOP | FT_PLAIN>;
+            if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG | FT_COOP | PLAIN>;
+            return (const void*)k_trace_solo<R, TK, 0, FT_COOP | PLAIN>;
         }
     }
-    if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, FT_ONE>;
-    if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, FT_ONE>;
-    if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, FT_ONE>;
-    if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG | ONE>;
+    if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, FT_PLAIN>;
+    if (mode == 3) return (const void*)k_trace_solo<R, TK, 2, FT_PLAIN>;
+    if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, FT_PLAIN>;
+    if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG | PLAIN>;
     if constexpr (std::is_same<R, float>::value) {
-        if (ft & FT_WIDE) return (const void*)k_trace_solo<R, TK, 0, FT_WIDE | ONE>;
+        if (ft & FT_WIDE) return (const void*)k_trace_solo<R, TK, 0, FT_WIDE | PLAIN>;
     }
-    return (const void*)k_trace_solo<R, TK, 0, ONE>;
+    return (const void*)k_trace_solo<R, TK, 0, PLAIN>;
 }
 
 template <typename R, int TK>
 static const void* pick_kernel(int mode, int ft)
 {
     if (mode == 1)
-        return (ft & FT_ONE) ? (const void*)k_trace_batch<R, TK, FT_ONE> : (const void*)k_trace_batch<R, TK, 0>;
-    return (ft & FT_ONE) ? pick_solo<R, TK, FT_ONE>(mode, ft) : pick_solo<R, TK, 0>(mode, ft);
+        return (ft & FT_PLAIN) ? (const void*)k_trace_batch<R, TK, FT_PLAIN> : (const void*)k_trace_batch<R, TK, 0>;
+    return (ft & FT_PLAIN) ? pick_solo<R, TK, FT_PLAIN>(mode, ft) : pick_solo<R, TK, 0>(mode, ft);
 }
 
 static const void* kernel_for(int mode, int precision, int tally_kind, int ft)

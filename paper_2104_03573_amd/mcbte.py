@@ -35,7 +35,7 @@ class Face(C.Structure):
 
 class Pore(C.Structure):
     _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("r", C.c_double), ("id", C.c_int32),
-                ("type", C.c_int32), ("specularity", C.c_double)]
+                ("type", C.c_int32), ("specularity", C.c_double), ("spec_omega", C.c_double)]
 
 
 class Geometry(C.Structure):
@@ -168,16 +168,12 @@ def structs_from_workload(w: dict):
         G.unbounded[a] = int(bool(g["unbounded"][a]))
         G.gradT[a] = g["gradT"][a]
     for fid, (ty, d0, d1, d2) in g["faces"].items():
-        if int(ty) == 2 and d1 != 0:
-            raise ValueError("frequency-dependent specularity is not supported by this library build")
         G.face[fid - 1].type = int(ty)
         G.face[fid - 1].data[0], G.face[fid - 1].data[1], G.face[fid - 1].data[2] = d0, d1, d2
     G.n_pores = len(g["cylinders"])
     for i, c in enumerate(g["cylinders"]):
-        if len(c) > 6 and c[6] != 0:
-            raise ValueError("frequency-dependent specularity is not supported by this library build")
         cx, cy, r, cid, ty, spec = c[:6]
-        G.pore[i] = Pore(cx, cy, r, int(cid), int(ty), spec)
+        G.pore[i] = Pore(cx, cy, r, int(cid), int(ty), spec, float(c[6]) if len(c) > 6 else 0.0)
     G.volume = g["volume"]
     d = w["detectors"]
     D = Detectors()

@@ -137,3 +137,19 @@ def test_two_phonon_clock_inputs():
     dummy = C.c_void_p(1)
     assert M.lib().mcbte_adjoint(t.h, C.byref(run), M.mcbte.SENS_SCORE, 0.0, 0, 10, dummy, dummy, None) \
         == M.mcbte.EINVAL
+
+
+def test_specular_cutoff_inputs():
+    """A boundary's cutoff frequency must be >= 0 and finite; the replays refuse such tables."""
+    for bad_val in (-1.0, float("inf"), float("nan")):
+        f = W.film(N=10, spec_omega=bad_val)
+        assert _status(f) == M.mcbte.EGEOM
+        with pytest.raises(ValueError):
+            oracle.Tables(f)
+        p = W.porous_cell(N=10, spec_omega=bad_val)
+        assert _status(p) == M.mcbte.EGEOM
+    t = M.Tables(W.film(N=10, spec_omega=W.OMEGA_2THZ), device=-1)
+    run = M.make_run(1, 32)
+    dummy = C.c_void_p(1)
+    assert M.lib().mcbte_adjoint(t.h, C.byref(run), M.mcbte.SENS_SCORE, 0.0, 0, 10, dummy, dummy, None) \
+        == M.mcbte.EINVAL

@@ -1,6 +1,7 @@
-"""Separate two-phonon and three-phonon clocks (section 3.3) on the HIP path, through the C ABI.
+"""The extended physics on the HIP path, through the C ABI: separate two-phonon and
+three-phonon clocks (section 3.3) and frequency-dependent specularity (section 3.5.3).
 
-The FP64 event sequences of two-clock workloads are compared bit-exactly with the oracle in
+The FP64 event sequences of such workloads are compared bit-exactly with the oracle in
 test_gpu_parity.py (FP64_CASES); this file covers the emitted clocks, the state-buffer path,
 the batched kernel, launch shapes that route walks through the lone-lane and wave-cooperative
 paths, and the FP32 form against the FP64 oracle.
@@ -138,3 +139,39 @@ def test_fp32_two_clock_film_against_fp64_oracle():
     assert rel_k < 2e-4
     for k in ("flights", "two_phonon", "relaxations", "diffuse"):
         assert abs(c[k] - rc[k]) <= 1e-3 * rc[k], k
+
+
+def test_specular_cutoff_launch_shapes_batched_kernel_and_fp32():
+    """Pore cell with the phonons below 2 THz specular: launch shapes that leave lanes walking
+    alone (whose pore reflections then take each phonon's own class) give the same FP64 counters
+    and sums; the batched kernel with the extended code equals solo runs; the FP32 film with a
+    cutoff agrees with the FP64 oracle."""
+    import torch
+    M = _pkg()
+    w = W.porous_cell(N=1500, spec_omega=W.OMEGA_2THZ)
+    base = M.run(w, precision=64)
+    assert base["counts"]["specular"] > 0 and base["counts"]["diffuse"] > 0
+    for block, refill, grid in ((64, 1, 1), (64, 8, 3)):
+        r = M.run(w, precision=64, block=block, refill=refill, grid=grid)
+        assert np.array_equal(r["counts_raw"], base["counts_raw"]), (block, refill, grid)
+        assert np.abs(r["raw"] - base["raw"]).max() <= 1e-12 * np.abs(base["raw"]).max()
+    ws = [W.film(N=5000, d=3e-8, spec_omega=2.5 * W.OMEGA_2THZ), W.film(N=4000, d=1e-7)]
+    for i, wi in enumerate(ws):
+        wi["instance"] = 11 + i
+    tabs = [M.Tables(wi) for wi in ws]
+    tallies = [t.new_tally() for t in tabs]
+    queue = torch.zeros(M.batch_queue_bytes(len(ws)), dtype=torch.uint8, device="cuda")
+    run = M.make_run(int(ws[0]["seed"]), 64)
+    M.trace_batch(tabs, [wi["problem"]["N"] for wi in ws], [wi["instance"] for wi in ws], tallies, run, queue)
+    for wi, t, tl in zip(ws, tabs, tallies):
+        b = M.tally(t, tl)
+        s = M.run(wi, precision=64, tables=t)
+        assert np.array_equal(b["counts_raw"], s["counts_raw"])
+    wf = W.film(N=100000, spec_omega=2.5 * W.OMEGA_2THZ)
+    got = M.run(wf, precision=32)
+    ref = oracle.run(wf, threads=THREADS)
+    rel_k = abs(got["kappa"] - ref["kappa"]) / abs(ref["kappa"])
+    _say(f"[fp32 cutoff film] kappa {got['kappa']:.6g} vs {ref['kappa']:.6g} (rel {rel_k:.2e})")
+    assert rel_k < 2e-4
+    for k in ("flights", "specular", "diffuse"):
+        assert abs(got["counts"][k] - ref["counts"][k]) <= 1e-3 * ref["counts"][k], k

@@ -49,6 +49,10 @@ FP64_CASES = {
                                                modes=W.silicon_like_modes(300.0, impurity_clock=True)),
     "transient_two_clocks": lambda: W.transient_bump(N=300, modes=W.silicon_like_modes(300.0, impurity_clock=True)),
     "porous_two_clocks": lambda: W.porous_cell(N=1000, modes=W.silicon_like_modes(300.0, impurity_clock=True)),
+    # frequency-dependent specularity: phonons below the cutoff reflect specularly
+    "film_spec_cutoff": lambda: W.film(N=3000, spec_omega=2.5 * W.OMEGA_2THZ),
+    "film_partial_spec_cutoff": lambda: W.film(N=2000, d=30e-9, specularity=0.4, spec_omega=2.5 * W.OMEGA_2THZ),
+    "porous_spec_cutoff": lambda: W.porous_cell(N=1000, spec_omega=W.OMEGA_2THZ),
 }
 
 
