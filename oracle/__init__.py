@@ -49,9 +49,16 @@ class Cyl(C.Structure):
                 ("type", C.c_int32), ("spec", C.c_double), ("spec_wc", C.c_double)]
 
 
+class Wall(C.Structure):
+    _fields_ = [("x1", C.c_double), ("y1", C.c_double), ("x2", C.c_double), ("y2", C.c_double),
+                ("nx", C.c_double), ("ny", C.c_double), ("id", C.c_int32), ("type", C.c_int32),
+                ("spec", C.c_double), ("spec_wc", C.c_double)]
+
+
 class Geom(C.Structure):
     _fields_ = [("L", C.c_double * 3), ("unbounded", C.c_int32 * 3), ("n_cyl", C.c_int32),
-                ("face", Face * 6), ("cyl", Cyl * 8), ("gradT", C.c_double * 3), ("volume", C.c_double)]
+                ("face", Face * 6), ("cyl", Cyl * 8), ("gradT", C.c_double * 3), ("volume", C.c_double),
+                ("n_wall", C.c_int32), ("pad_w", C.c_int32), ("wall", Wall * 16)]
 
 
 class Det(C.Structure):
@@ -198,6 +205,13 @@ class Tables:
         for i, c in enumerate(g["cylinders"]):
             cx, cy, r, cid, ty, spec = c[:6]
             G.cyl[i] = Cyl(cx, cy, r, int(cid), int(ty), spec, float(c[6]) if len(c) > 6 else 0.0)
+        walls = g.get("walls", [])
+        if len(walls) > 16:
+            raise ValueError("at most 16 internal line walls")
+        G.n_wall = len(walls)
+        for i, c in enumerate(walls):
+            x1, y1, x2, y2, nx, ny, wid, ty, spec = c[:9]
+            G.wall[i] = Wall(x1, y1, x2, y2, nx, ny, int(wid), int(ty), spec, float(c[9]) if len(c) > 9 else 0.0)
         G.volume = g["volume"]
         self._geom = G
         d = w["detectors"]

@@ -242,6 +242,20 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
             return E_GEOM;
         if (y->id < 7 || (c > 0 && y->id <= g->cyl[c - 1].id)) return E_GEOM;
     }
+    if (g->n_wall < 0 || g->n_wall > ORC_MAX_WALL) return E_GEOM;
+    for (int k = 0; k < g->n_wall; ++k) {
+        const orc_wall* wl = &g->wall[k];
+        const int prev = k > 0 ? g->wall[k - 1].id : (g->n_cyl > 0 ? g->cyl[g->n_cyl - 1].id : 6);
+        if (g->unbounded[0] || g->unbounded[1] || wl->type != B_ADIA || wl->id <= prev) return E_GEOM;
+        if (!(wl->spec >= 0.0 && wl->spec <= 1.0) || !(wl->spec_wc >= 0.0) || !isfinite(wl->spec_wc)) return E_GEOM;
+        const double pts[4] = {wl->x1, wl->y1, wl->x2, wl->y2};
+        for (int q = 0; q < 4; ++q)
+            if (!(pts[q] >= 0.0 && pts[q] <= g->L[q & 1])) return E_GEOM;
+        if (wl->x1 == wl->x2 && wl->y1 == wl->y2) return E_GEOM;
+        const double nn = sqrt(wl->nx * wl->nx + wl->ny * wl->ny);
+        if (!(fabs(nn - 1.0) <= 1e-9)) return E_GEOM;
+    }
+    if (g->n_wall > 0 && !(g->volume > 0.0)) return E_INVAL;   /* the solid volume must be given */
     for (int a = 0; a < 3; ++a)
         if (det->n[a] < 0 || (det->n[a] > 0 && !(det->hi[a] > det->lo[a]))) return E_INVAL;
     if (pr->transient) {
@@ -251,7 +265,7 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
     } else if (pr->n_ic > 0) {
         return E_INVAL;
     }
-    if (pr->n_ic > 0 && (pr->ic_axis < 0 || pr->ic_axis > 2 || g->n_cyl > 0)) return E_INVAL;
+    if (pr->n_ic > 0 && (pr->ic_axis < 0 || pr->ic_axis > 2 || g->n_cyl > 0 || g->n_wall > 0)) return E_INVAL;
     if (pr->score_axis < 0 || pr->score_axis > 2 || pr->max_events < 1 || pr->max_events > 0x3FFFFFF0LL)
         return E_INVAL;
 
@@ -259,6 +273,12 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
     if (!t) return E_NOMEM;
     t->M = M;
     t->g = *g;
+    for (int k = 0; k < t->g.n_wall; ++k) {         /* unit normals */
+        orc_wall* wl = &t->g.wall[k];
+        const double nn = sqrt(wl->nx * wl->nx + wl->ny * wl->ny);
+        wl->nx = wl->nx / nn;
+        wl->ny = wl->ny / nn;
+    }
     t->det = *det;
     t->pr = *pr;
     t->C = (double*)malloc(sizeof(double) * M);
@@ -617,6 +637,8 @@ static double draw_t2(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
     return -t->tau2[m] * log(1.0 - unif(Q, 0));
 }
 
+static int outside_solid(const orc_geom* g, const double x[3]);
+
 static int emit(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t pid, prt* p, uint64_t* counts,
                 int64_t* src_out)
 {
@@ -644,13 +666,8 @@ static int emit(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t pid, 
         p->m = (int32_t)orc_cdf_pick(t->thr_wall, t->M, t->last_wall, key64(R1, 0));
     } else if (kind == S_GRAD) {
         for (int a = 0; a < 3; ++a) p->x[a] = g->unbounded[a] ? 0.0 : up[a] * g->L[a];
-        for (uint32_t attempt = 1;; ++attempt) {      /* positions inside pores are redrawn */
-            int inside = 0;
-            for (int c = 0; c < g->n_cyl; ++c) {
-                double dx = p->x[0] - g->cyl[c].cx, dy = p->x[1] - g->cyl[c].cy;
-                if (dx * dx + dy * dy < g->cyl[c].r * g->cyl[c].r) inside = 1;
-            }
-            if (!inside) break;
+        for (uint32_t attempt = 1;; ++attempt) {      /* positions outside the solid are redrawn */
+            if (!outside_solid(g, p->x)) break;
             if (attempt > 4096) return -1;
             counts[ORC_C_REJECT] += 1;
             uint32_t RA[8];
@@ -707,8 +724,49 @@ static double next_boundary(const orc_geom* g, const double x[3], const double o
         double d = (qc < 0.0) ? 0.0 : qc / (-qb + sqrt(disc));
         if (d < db) { db = d; hit = y->id; }
     }
+    /* internal line walls (ids after the pores'), met from the side their normal points to:
+       x + d o = P1 + s (P2 - P1) in the x-y plane, d >= 0, 0 <= s <= 1 */
+    for (int k = 0; k < g->n_wall; ++k) {
+        const orc_wall* wl = &g->wall[k];
+        if (!(o[0] * wl->nx + o[1] * wl->ny < 0.0)) continue;
+        const double ex = wl->x2 - wl->x1, ey = wl->y2 - wl->y1;
+        const double den = o[0] * ey - o[1] * ex;
+        if (den == 0.0) continue;
+        const double wx = wl->x1 - x[0], wy = wl->y1 - x[1];
+        const double d = (wx * ey - wy * ex) / den;
+        const double sp = (wx * o[1] - wy * o[0]) / den;
+        if (d >= 0.0 && sp >= 0.0 && sp <= 1.0 && d < db) { db = d; hit = wl->id; }
+    }
     *hit_out = hit;
     return db;
+}
+
+/* a point of the box outside the solid: inside a pore, or inside a closed loop of line walls
+   (consecutive walls each starting where the previous one ends, the last ending where the first
+   starts; crossing-number test with half-open edges).  Walls outside such loops exclude nothing. */
+static int outside_solid(const orc_geom* g, const double x[3])
+{
+    for (int c = 0; c < g->n_cyl; ++c) {
+        double dx = x[0] - g->cyl[c].cx, dy = x[1] - g->cyl[c].cy;
+        if (dx * dx + dy * dy < g->cyl[c].r * g->cyl[c].r) return 1;
+    }
+    int k = 0;
+    while (k < g->n_wall) {
+        int j = k;
+        while (j + 1 < g->n_wall && g->wall[j + 1].x1 == g->wall[j].x2 && g->wall[j + 1].y1 == g->wall[j].y2) ++j;
+        if (g->wall[j].x2 == g->wall[k].x1 && g->wall[j].y2 == g->wall[k].y1) {
+            int in = 0;
+            for (int e = k; e <= j; ++e) {
+                const orc_wall* wl = &g->wall[e];
+                if ((wl->y1 > x[1]) != (wl->y2 > x[1]) &&
+                    x[0] < wl->x1 + (x[1] - wl->y1) * (wl->x2 - wl->x1) / (wl->y2 - wl->y1))
+                    in = !in;
+            }
+            if (in) return 1;
+        }
+        k = j + 1;
+    }
+    return 0;
 }
 
 double orc_next_boundary(const orc_tables* t, const double x[3], const double o[3], int32_t* hit)
@@ -1089,6 +1147,7 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
         int type;
         double spec = 0.0, spec_wc = 0.0;
         const orc_cyl* cy = NULL;
+        const orc_wall* wl = NULL;
         if (hit <= 6) {
             type = g->face[hit - 1].type;
             spec = g->face[hit - 1].data[0];
@@ -1096,9 +1155,11 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
         } else {
             for (int c = 0; c < g->n_cyl; ++c)
                 if (g->cyl[c].id == hit) cy = &g->cyl[c];
-            type = cy->type;
-            spec = cy->spec;
-            spec_wc = cy->spec_wc;
+            for (int k = 0; k < g->n_wall; ++k)
+                if (g->wall[k].id == hit) wl = &g->wall[k];
+            type = cy ? cy->type : wl->type;
+            spec = cy ? cy->spec : wl->spec;
+            spec_wc = cy ? cy->spec_wc : wl->spec_wc;
         }
         /* section 3.5.3: the specularity may depend on the phonon; below the boundary's cutoff
            frequency the reflection is specular */
@@ -1133,13 +1194,16 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
         if (cy) {
             n[0] = (p.x[0] - cy->cx) / cy->r;
             n[1] = (p.x[1] - cy->cy) / cy->r;
+        } else if (wl) {
+            n[0] = wl->nx;
+            n[1] = wl->ny;
         } else {
             n[face_axis] = face_side ? -1.0 : 1.0;
         }
         if (specular) {
             if (cy) tan_cyl(al, p.o, n, cy->r, 1);
-            else tan_plane(al, face_axis, 1);
-            if (cy) {                                 /* Eq. specular: k' = k - 2 (k.n) n */
+            else if (!wl) tan_plane(al, face_axis, 1);
+            if (cy || wl) {                           /* Eq. specular: k' = k - 2 (k.n) n */
                 double k2 = 2.0 * (p.o[0] * n[0] + p.o[1] * n[1] + p.o[2] * n[2]);
                 for (int a = 0; a < 3; ++a) p.o[a] = p.o[a] - k2 * n[a];
             } else {
@@ -1154,7 +1218,7 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
             }
             orc_dir_cos(unif(R, 4), unif(R, 6), n, p.o);
             if (cy) tan_cyl(al, p.o, n, cy->r, 0);
-            else tan_plane(al, face_axis, 0);
+            else if (!wl) tan_plane(al, face_axis, 0);
             counts[ORC_C_DIFFUSE] += 1;
             LOG(ORC_EV_DIFFUSE, hit, p.m);
         }
@@ -1193,6 +1257,7 @@ int orc_adjoint(const orc_tables* t, uint64_t seed, uint32_t instance, int64_t f
 {
     if (!t || n < 0 || first_pid < 0 || t->pr.transient || kind < 0 || kind > 2) return E_INVAL;
     if (t->two) return E_INVAL;     /* the estimators differentiate the one-clock flight law */
+    if (t->g.n_wall > 0) return E_INVAL;   /* their tangents know planes of the box and cylinders */
     int cap = 2;
     for (int a = 0; a < 3; ++a) cap += t->det.n[a];
     double* pts = (double*)malloc(sizeof(double) * cap);

@@ -17,6 +17,7 @@
 #include <stdint.h>
 
 #define ORC_MAX_CYL 8
+#define ORC_MAX_WALL 16
 #define ORC_N_COUNTS 16
 #define ORC_N_MOMENTS 4
 
@@ -27,6 +28,10 @@ typedef struct { int32_t type, pad; double data[3]; } orc_face;
    specularly whatever d is (frequency-dependent specularity, as in the paper's nanomesh with the
    phonons below 2 THz specular).  Adiabatic faces carry the same cutoff in data[1]. */
 typedef struct { double cx, cy, r; int32_t id, type; double spec, spec_wc; } orc_cyl;
+/* internal line wall (the paper's In_bnd rows): the segment (x1, y1)-(x2, y2) in the x-y plane,
+   extended through the thickness, normal (nx, ny) pointing into the domain; adiabatic with
+   specularity spec and cutoff spec_wc as for pores; ids above the pores' */
+typedef struct { double x1, y1, x2, y2, nx, ny; int32_t id, type; double spec, spec_wc; } orc_wall;
 typedef struct {
     double L[3];
     int32_t unbounded[3];
@@ -35,6 +40,8 @@ typedef struct {
     orc_cyl cyl[ORC_MAX_CYL];
     double gradT[3];
     double volume;             /* solid volume; <= 0 means: computed from the geometry */
+    int32_t n_wall, pad_w;
+    orc_wall wall[ORC_MAX_WALL];
 } orc_geom;
 typedef struct { double lo[3], hi[3]; int32_t n[3]; int32_t mask; } orc_det;
 typedef struct {

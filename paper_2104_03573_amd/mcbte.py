@@ -170,6 +170,8 @@ def structs_from_workload(w: dict):
     for fid, (ty, d0, d1, d2) in g["faces"].items():
         G.face[fid - 1].type = int(ty)
         G.face[fid - 1].data[0], G.face[fid - 1].data[1], G.face[fid - 1].data[2] = d0, d1, d2
+    if g.get("walls"):
+        raise ValueError("internal line walls are not supported by this library build")
     G.n_pores = len(g["cylinders"])
     for i, c in enumerate(g["cylinders"]):
         cx, cy, r, cid, ty, spec = c[:6]

@@ -595,3 +595,41 @@ def test_specular_cutoff_extremes_reduce_to_constant_specularity():
     for a, b in zip(trace(pore_sp), trace(pore_hi)):
         assert np.array_equal(a, b)
     assert not np.array_equal(trace(pore)[1], trace(pore_hi)[1])
+
+
+# --------------------------------------------------------------------------------------------
+# Internal line walls (the paper's In_bnd rows: segments in the x-y plane through the thickness,
+# normal into the domain)
+# --------------------------------------------------------------------------------------------
+
+def test_walled_film_matches_fuchs_sondheimer():
+    """A channel between two diffuse line walls, periodic along the gradient: the thin film of
+    thickness d, so kappa = sum_m kappa_m S(d / Lambda_m); the positions behind the walls are
+    redrawn (emission with rejection), so about (H - d)/H of the first draws are rejected."""
+    d = 100e-9
+    w = W.walled_film(N=150000, d=d)
+    r = oracle.run(w, threads=THREADS)
+    C = r["tables"].get("C")
+    m = w["modes"]
+    lam = m["v"] * m["tau"]
+    k_fs = sum(C[i] * m["v"][i] ** 2 * m["tau"][i] / 3.0 * cf.fs_suppression(d / lam[i]) for i in range(len(m)))
+    assert abs(r["kappa"] - k_fs) < 3.0 * r["kappa_sigma"], (r["kappa"], r["kappa_sigma"], k_fs)
+    H = w["geometry"]["L"][1]
+    c = r["counts"]
+    p_rej = (H - d) / H                   # rejections per emitted particle: geometric, mean p/(1-p)
+    mean = c["rejections"] / c["particles"]
+    sd = math.sqrt(p_rej / (1 - p_rej) ** 2 / c["particles"])
+    assert abs(mean - p_rej / (1 - p_rej)) < 4 * sd, (mean, p_rej / (1 - p_rej))
+
+
+def test_square_pore_of_line_walls_rejects_its_area_and_conserves_the_flux_sign():
+    """The square pore of four walls: emission rejects positions inside it at the pore's area
+    fraction; the pore lowers kappa below the bulk value but keeps it positive."""
+    w = W.square_pore_cell(N=40000)
+    r = oracle.run(w, threads=THREADS)
+    c = r["counts"]
+    p_rej = (250e-9 / 500e-9) ** 2
+    mean = c["rejections"] / c["particles"]
+    sd = math.sqrt(p_rej / (1 - p_rej) ** 2 / c["particles"])
+    assert abs(mean - p_rej / (1 - p_rej)) < 4 * sd, (mean, p_rej / (1 - p_rej))
+    assert c["diffuse"] > 0 and 0 < r["kappa"] < r["tables"].kappa_bulk

@@ -293,3 +293,52 @@ def test_segment_cap_ends_each_walk_after_cap_segments(cap):
             assert len(kinds) == cap + 2
             n_cap += 1
     assert n_cap == c["cap_end"]
+
+
+def _march_walls(w, x, o, step):
+    """First boundary met by marching: box faces as in _march, line walls by a sign change of the
+    signed distance to the wall's line while the projection falls on the segment."""
+    first, who = _march(w, x, o, step)
+    ks = np.arange(1, 500000, dtype=np.float64)
+    P = x[None, :] + o[None, :] * (ks * step)[:, None]
+    for (x1, y1, x2, y2, nx, ny, wid) in (c[:7] for c in w["geometry"]["walls"]):
+        if o[0] * nx + o[1] * ny >= 0.0:
+            continue                       # met only from the side the normal points to
+        s0 = (x[0] - x1) * nx + (x[1] - y1) * ny
+        sd = (P[:, 0] - x1) * nx + (P[:, 1] - y1) * ny
+        e = np.array([x2 - x1, y2 - y1])
+        t = ((P[:, 0] - x1) * e[0] + (P[:, 1] - y1) * e[1]) / (e @ e)
+        idx = np.flatnonzero((np.sign(sd) != np.sign(s0)) & (t >= 0) & (t <= 1))
+        if idx.size and ks[idx[0]] * step < first:
+            first, who = ks[idx[0]] * step, wid
+    return first, who
+
+
+def test_next_boundary_with_line_walls_matches_ray_march():
+    """The square pore of four internal line walls (the paper's nanomesh layout): distance and id
+    of the first boundary; walls are met only from the solid side."""
+    w = W.square_pore_cell(N=10)
+    tb = oracle.Tables(w)
+    Wd = w["geometry"]["L"][0]
+    a, b = 0.5 * (Wd - 250e-9), 0.5 * (Wd + 250e-9)
+    rng = np.random.default_rng(7)
+    n_wall = 0
+    step = 2e-12
+    for _ in range(120):
+        while True:
+            x = rng.random(3) * Wd
+            if not (a < x[0] < b and a < x[1] < b):
+                break
+        o = rng.normal(size=3)
+        o /= np.linalg.norm(o)
+        d, hit = tb.next_boundary(x, o)
+        dm, hm = _march_walls(w, x, o, step)
+        assert hit == hm and abs(d - dm) <= step, (x, o, d, hit, dm, hm)
+        n_wall += hit >= 7
+    assert n_wall > 20
+    # leaving a wall toward the solid: the wall is not met again
+    d, hit = tb.next_boundary(np.array([0.5 * Wd, a, 1e-7]), np.array([0.0, -1.0, 0.0]))
+    assert hit == 1 and d == pytest.approx(a)
+    # from inside the pore (behind the walls) nothing but the box is met
+    d, hit = tb.next_boundary(np.array([0.5 * Wd, 0.5 * Wd, 1e-7]), np.array([0.0, -1.0, 0.0]))
+    assert hit == 1 and d == pytest.approx(0.5 * Wd)

@@ -93,12 +93,14 @@ def gray_modes(v: float, tau: float, C: float = 1.0e6, tau_imp: float = 0.0) -> 
 
 
 def _geometry(L, unbounded=(False, False, False), faces=None, cylinders=(), gradT=(0.0, 0.0, 0.0),
-              volume=0.0):
+              volume=0.0, walls=()):
     return {
         "L": tuple(float(x) for x in L),
         "unbounded": tuple(bool(u) for u in unbounded),
         "faces": {int(k): tuple(float(x) for x in v) for k, v in (faces or {}).items()},
         "cylinders": [tuple(c) for c in cylinders],
+        # internal line walls (x1, y1, x2, y2, nx, ny, id, type, specularity[, cutoff omega])
+        "walls": [tuple(c) for c in walls],
         "gradT": tuple(float(x) for x in gradT),
         "volume": float(volume),
     }
@@ -223,6 +225,55 @@ def porous_cell(N=100_000_000, W=500e-9, porosity=0.25, T=300.0, gradT=-2.0e6, n
                               gradT=(0.0, gradT, 0.0)),
         "detectors": _detectors(mask=MASK_T | MASK_QY),
         "problem": _problem(N, T, n_scat_max, score_axis=1, fmt=1),
+        "seed": seed,
+    }
+
+
+def square_pore_cell(N=1_000_000, W=500e-9, side=250e-9, T=300.0, gradT=-2.0e6, n_scat_max=10,
+                     specularity=0.0, seed=SEED_BASE + 9, modes=None):
+    """3-D periodic cubic cell with a centred square pore bounded by four internal line walls
+    (the paper's nanomesh layout: walls in the x-y plane through the thickness, normals pointing
+    into the solid; ids 7..10)."""
+    a, b = 0.5 * (W - side), 0.5 * (W + side)
+    walls = [(a, a, b, a, 0.0, -1.0, 7, ADIABATIC, specularity),
+             (b, a, b, b, 1.0, 0.0, 8, ADIABATIC, specularity),
+             (b, b, a, b, 0.0, 1.0, 9, ADIABATIC, specularity),
+             (a, b, a, a, -1.0, 0.0, 10, ADIABATIC, specularity)]
+    faces = {1: (PERIODIC, 0, W, 0), 3: (PERIODIC, 0, -W, 0), 2: (PERIODIC, -W, 0, 0),
+             4: (PERIODIC, W, 0, 0), 5: (PERIODIC, 0, 0, W), 6: (PERIODIC, 0, 0, -W)}
+    return {
+        "name": "square_pore_cell",
+        "modes": silicon_like_modes(T) if modes is None else modes,
+        "geometry": _geometry((W, W, W), (False, False, False), faces, gradT=(0.0, gradT, 0.0),
+                              volume=(W * W - side * side) * W, walls=walls),
+        "detectors": _detectors(mask=MASK_T | MASK_QY),
+        "problem": _problem(N, T, n_scat_max, score_axis=1, fmt=1),
+        "seed": seed,
+    }
+
+
+def walled_film(N=1_000_000, d=100e-9, H=300e-9, Lx=200e-9, T=300.0, gradT=-1.0e7, n_scat_max=10,
+                specularity=0.0, seed=SEED_BASE + 10, modes=None):
+    """The thin film of `film` made of internal line walls: a channel of thickness d between
+    walls at y = (H - d)/2 and (H + d)/2 spanning a box periodic in x, unbounded in z, with the
+    gradient along x.  The regions below and above the channel are closed loops of walls (the
+    channel walls plus walls along the box edges, which no particle reaches), so emission leaves
+    them out."""
+    y0, y1 = 0.5 * (H - d), 0.5 * (H + d)
+    A, S = ADIABATIC, specularity
+    walls = [(0.0, y0, Lx, y0, 0.0, 1.0, 7, A, S), (Lx, y0, Lx, 0.0, 1.0, 0.0, 8, A, S),
+             (Lx, 0.0, 0.0, 0.0, 0.0, -1.0, 9, A, S), (0.0, 0.0, 0.0, y0, -1.0, 0.0, 10, A, S),
+             (Lx, y1, 0.0, y1, 0.0, -1.0, 11, A, S), (0.0, y1, 0.0, H, -1.0, 0.0, 12, A, S),
+             (0.0, H, Lx, H, 0.0, 1.0, 13, A, S), (Lx, H, Lx, y1, 1.0, 0.0, 14, A, S)]
+    faces = {2: (PERIODIC, -Lx, 0, 0), 4: (PERIODIC, Lx, 0, 0),
+             1: (ADIABATIC, 0.0, 0, 0), 3: (ADIABATIC, 0.0, 0, 0)}
+    return {
+        "name": "walled_film",
+        "modes": silicon_like_modes(T) if modes is None else modes,
+        "geometry": _geometry((Lx, H, 1.0), (False, False, True), faces, gradT=(gradT, 0.0, 0.0),
+                              volume=Lx * d * 1.0, walls=walls),
+        "detectors": _detectors(mask=MASK_T | MASK_QX),
+        "problem": _problem(N, T, n_scat_max, score_axis=0, fmt=1),
         "seed": seed,
     }
 
