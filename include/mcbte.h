@@ -55,6 +55,7 @@ extern "C" {
 #define MCBTE_TALLY_QZ 8
 
 #define MCBTE_MAX_PORES 8
+#define MCBTE_MAX_WALLS 16
 
 /* Sensitivity estimators (mcbte_adjoint). */
 #define MCBTE_SENS_SCORE 0          /* likelihood ratio: any steady problem                     */
@@ -109,12 +110,27 @@ typedef struct {
     double spec_omega;          /* cutoff angular frequency below which reflection is specular (0: none) */
 } mcbte_pore;
 
+/* internal line wall (the paper's In_bnd rows, section 4.2): the segment (x1, y1)-(x2, y2) in the
+   x-y plane extended through the thickness, (nx, ny) its normal pointing into the domain (unit
+   length within 1e-9; normalized by the library).  A wall is met only from the side its normal
+   points to; it reflects like a pore (specularity d, optional cutoff angular frequency).  Ids
+   continue after the pores' (> every pore id, strictly increasing).  Emission leaves out the
+   inside of every closed loop of walls (consecutive walls each starting where the previous one
+   ends, the last ending where the first starts); walls in no loop exclude nothing. */
+typedef struct {
+    double x1, y1, x2, y2, nx, ny;
+    int32_t id;
+    int32_t type;               /* MCBTE_ADIABATIC */
+    double specularity;
+    double spec_omega;
+} mcbte_wall;
+
 /* Box [0, L0] x [0, L1] x [0, L2] (one corner at the origin, section 4.2).  face[id - 1] holds
    boundary id 1..6 in the paper's order: 1 y=0, 2 x=L0, 3 y=L1, 4 x=0, 5 z=0, 6 z=L2.  An axis
    with unbounded[a] != 0 has no faces (translation-invariant direction, lengths taken as 1 m
    for areas and volumes; positions along it start at 0).  gradT is the uniform temperature
    gradient of the spatially varying control (section 2.6); volume is the solid volume
-   (section 4.4; <= 0: box volume minus the pores). */
+   (section 4.4; <= 0: box volume minus the pores; must be given when there are line walls). */
 typedef struct {
     double L[3];
     int32_t unbounded[3];
@@ -123,6 +139,9 @@ typedef struct {
     mcbte_pore pore[MCBTE_MAX_PORES];
     double gradT[3];
     double volume;
+    int32_t n_walls;
+    int32_t reserved_w;
+    mcbte_wall wall[MCBTE_MAX_WALLS];
 } mcbte_geometry;
 
 /* Detector grid (section 4.5): the cuboid [lo, hi] split into n[a] equal cells along each axis
@@ -327,8 +346,8 @@ int mcbte_autotune(const mcbte_tables* const* tables, int32_t n_inst, const int6
    the caller; successive calls with one estimator accumulate): adj[0, n_bins) the per-bin sums,
    adj[n_bins] the relaxation-draw sum B, adj[n_bins + 1] the count of terms left out as not
    finite, adj[n_bins + 2] library scratch.  Async on `stream`.  Errors: MCBTE_EINVAL (transient run, event log set, unknown
-   estimator, n_scat_max outside the pathwise range, tables with a two-phonon clock or a specular
-   cutoff frequency), MCBTE_ENODEV, MCBTE_EHIP. */
+   estimator, n_scat_max outside the pathwise range, tables with a two-phonon clock, a specular
+   cutoff frequency or internal line walls), MCBTE_ENODEV, MCBTE_EHIP. */
 int mcbte_adjoint(const mcbte_tables* tables, const mcbte_run* run, int32_t estimator, double lambda_split,
                   int64_t first_pid, int64_t n, const double* particle_F, double* adj, void* stream);
 

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #define MCBTE_DEV_MAX_PORES 8
+#define MCBTE_DEV_MAX_WALLS 16
 #define MCBTE_LDS_TABLE_BYTES (48 * 1024)   // mode tables staged in LDS (thresholds + v + tau)
 #define MCBTE_LDS_TALLY_BYTES (40 * 1024)   // per-workgroup tally privatisation budget
 #define MCBTE_LDS_GUIDE_BYTES 1024           // guide of the relaxation draw (256 packed bounds)
@@ -61,6 +62,20 @@ struct DevGeom {
     // frequency-dependent specularity: below these angular frequencies reflection is specular (0: none)
     double face_wc[6];
     double pore_wc[MCBTE_DEV_MAX_PORES];
+    // internal line walls: segment, unit normal (FP64 and FP32), id, 2 bits of class per wall and
+    // precision, partial-specularity threshold, cutoff, and the closed loops (loop_end[k] = last
+    // wall of the loop that wall k starts, -1 otherwise)
+    int32_t n_walls;
+    int32_t pad_w;
+    double wall_x1[MCBTE_DEV_MAX_WALLS], wall_y1[MCBTE_DEV_MAX_WALLS];
+    double wall_x2[MCBTE_DEV_MAX_WALLS], wall_y2[MCBTE_DEV_MAX_WALLS];
+    double wall_nx[MCBTE_DEV_MAX_WALLS], wall_ny[MCBTE_DEV_MAX_WALLS];
+    float wall32[MCBTE_DEV_MAX_WALLS][6];
+    int32_t wall_id[MCBTE_DEV_MAX_WALLS];
+    int32_t wall_loop_end[MCBTE_DEV_MAX_WALLS];
+    uint32_t wall_cls[2];
+    uint64_t wall_thr[MCBTE_DEV_MAX_WALLS];
+    double wall_wc[MCBTE_DEV_MAX_WALLS];
 };
 
 struct DevDet {

@@ -99,6 +99,7 @@ struct mcbte_tables {
     std::vector<double> C, v, tau, tau2, src_E, ic_edges, ic_dT, t_meas;   // tau2: two-phonon clock (0: none)
     bool two = false;      // some row has a two-phonon clock
     bool spec_w = false;   // some boundary has a specular cutoff frequency
+    bool walls = false;    // internal line walls
     std::vector<double> omega;
     std::vector<uint64_t> thr_ic, thr_wall, thr_rel, thr_src;
     std::vector<int32_t> src_kind, src_ref, src_sign, bin_of;
@@ -187,6 +188,22 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         if (p.cx - p.r < 0.0 || p.cx + p.r > g.L[0] || p.cy - p.r < 0.0 || p.cy + p.r > g.L[1]) return MCBTE_EGEOM;
         if (p.id < 7 || p.id > 255 || (c > 0 && p.id <= g.pore[c - 1].id)) return MCBTE_EGEOM;
     }
+    if (g.n_walls < 0 || g.n_walls > MCBTE_MAX_WALLS) return MCBTE_EGEOM;
+    for (int k = 0; k < g.n_walls; ++k) {
+        const mcbte_wall& w = g.wall[k];
+        const int prev = k > 0 ? g.wall[k - 1].id : (g.n_pores > 0 ? g.pore[g.n_pores - 1].id : 6);
+        if (g.unbounded[0] || g.unbounded[1] || w.type != MCBTE_ADIABATIC || w.id <= prev || w.id > 255)
+            return MCBTE_EGEOM;
+        if (!(w.specularity >= 0.0 && w.specularity <= 1.0)) return MCBTE_EGEOM;
+        if (!(w.spec_omega >= 0.0 && std::isfinite(w.spec_omega))) return MCBTE_EGEOM;
+        const double pts[4] = {w.x1, w.y1, w.x2, w.y2};
+        for (int q = 0; q < 4; ++q)
+            if (!(pts[q] >= 0.0 && pts[q] <= g.L[q & 1])) return MCBTE_EGEOM;
+        if (w.x1 == w.x2 && w.y1 == w.y2) return MCBTE_EGEOM;
+        const double nn = std::sqrt(w.nx * w.nx + w.ny * w.ny);
+        if (!(std::fabs(nn - 1.0) <= 1e-9)) return MCBTE_EGEOM;
+    }
+    if (g.n_walls > 0 && !(g.volume > 0.0)) return MCBTE_EINVAL;   // the solid volume must be given
     // detectors
     for (int a = 0; a < 3; ++a)
         if (dt.n[a] < 0 || (dt.n[a] > 0 && !(dt.hi[a] > dt.lo[a]))) return MCBTE_EINVAL;
@@ -199,7 +216,8 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     } else if (pr.n_ic > 0) {
         return MCBTE_EINVAL;
     }
-    if (pr.n_ic < 0 || (pr.n_ic > 0 && (!pr.ic_edges || !pr.ic_dT || pr.ic_axis < 0 || pr.ic_axis > 2 || g.n_pores > 0)))
+    if (pr.n_ic < 0 || (pr.n_ic > 0 && (!pr.ic_edges || !pr.ic_dT || pr.ic_axis < 0 || pr.ic_axis > 2 || g.n_pores > 0 ||
+                                        g.n_walls > 0)))
         return MCBTE_EINVAL;
 
     mcbte_tables* t = new (std::nothrow) mcbte_tables();
@@ -365,7 +383,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         int nb = 0, axis = -1;
         for (int a = 0; a < 3; ++a)
             if (!g.unbounded[a]) { ++nb; axis = a; }
-        if (nb == 1 && g.n_pores == 0 && !pr.transient && h.tally_kind == TALLY_STEADY_ONE) {
+        if (nb == 1 && g.n_pores == 0 && g.n_walls == 0 && !pr.transient && h.tally_kind == TALLY_STEADY_ONE) {
             // (with a specular cutoff, the same one on both walls: a phonon's class is then the
             // same at every bounce of a chain, and the kernel only starts chains of diffuse ones)
             bool diffuse = true;
@@ -428,6 +446,35 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         dg.pore_wc[c] = p.spec_omega;
         if (p.spec_omega > 0.0) t->spec_w = true;
     }
+    dg.n_walls = g.n_walls;
+    for (int k = 0; k < g.n_walls; ++k) {
+        const mcbte_wall& w = g.wall[k];
+        const double nn = std::sqrt(w.nx * w.nx + w.ny * w.ny);
+        dg.wall_x1[k] = w.x1;
+        dg.wall_y1[k] = w.y1;
+        dg.wall_x2[k] = w.x2;
+        dg.wall_y2[k] = w.y2;
+        dg.wall_nx[k] = w.nx / nn;
+        dg.wall_ny[k] = w.ny / nn;
+        const double v6[6] = {w.x1, w.y1, w.x2, w.y2, dg.wall_nx[k], dg.wall_ny[k]};
+        for (int q = 0; q < 6; ++q) dg.wall32[k][q] = (float)v6[q];
+        dg.wall_id[k] = w.id;
+        dg.wall_cls[0] |= surf_class<float>(w.specularity) << (2 * k);
+        dg.wall_cls[1] |= surf_class<double>(w.specularity) << (2 * k);
+        dg.wall_thr[k] = (w.specularity > 0.0 && w.specularity < 1.0) ? (uint64_t)(w.specularity * kTwo64) : 0;
+        dg.wall_wc[k] = w.spec_omega;
+        if (w.spec_omega > 0.0) t->spec_w = true;
+        dg.wall_loop_end[k] = -1;
+    }
+    // closed loops of walls: runs of walls each starting where the previous one ends, the last
+    // ending where the first starts
+    for (int k = 0; k < g.n_walls;) {
+        int j = k;
+        while (j + 1 < g.n_walls && g.wall[j + 1].x1 == g.wall[j].x2 && g.wall[j + 1].y1 == g.wall[j].y2) ++j;
+        if (g.wall[j].x2 == g.wall[k].x1 && g.wall[j].y2 == g.wall[k].y1) dg.wall_loop_end[k] = j;
+        k = j + 1;
+    }
+    if (g.n_walls > 0) t->walls = true;
     h.spec_w = t->spec_w ? 1 : 0;
     DevDet& dd = h.det;
     int nc = 0;
@@ -691,7 +738,7 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     }
     // FP64 film-like problems: the kernel with the exact cooperative bouncing
     if (run->precision == 64 && t->host_view.coop_axis >= 0) ft |= FT_COOP;
-    if (!t->two && !t->spec_w) ft |= FT_PLAIN;   // the kernel without the extended physics
+    if (!t->two && !t->spec_w && !t->walls) ft |= FT_PLAIN;   // the kernel without the extended physics
     const int rc = plan_launch(&t, 1, run, 0, ft, lp);
     if (rc != MCBTE_OK) return rc;
     LaunchArgs a;
@@ -748,7 +795,7 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     // the batched kernel without the extended physics unless some instance needs it
     int ft = FT_PLAIN;
     for (int i = 0; i < n_inst; ++i)
-        if (ts[i]->two || ts[i]->spec_w) ft = 0;
+        if (ts[i]->two || ts[i]->spec_w || ts[i]->walls) ft = 0;
     int rc = plan_launch(ts, n_inst, run, 1, ft, lp);
     if (rc != MCBTE_OK) return rc;
     // chunking: items of chunk_size particles, instance-major
@@ -885,7 +932,7 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
     if (estimator != MCBTE_SENS_SCORE && estimator != MCBTE_SENS_PATHWISE && estimator != MCBTE_SENS_LOCAL)
         return MCBTE_EINVAL;
     if (t->two) return MCBTE_EINVAL;       // the estimators differentiate the one-clock flight law
-    if (t->spec_w) return MCBTE_EINVAL;    // the replays are built for constant specularities
+    if (t->spec_w || t->walls) return MCBTE_EINVAL;   // the replays know constant specularities, faces and pores
     if (t->device < 0 || !t->d_tab) return MCBTE_ENODEV;
     if (t->prob.transient) return MCBTE_EINVAL;
     if (estimator == MCBTE_SENS_PATHWISE &&

@@ -272,6 +272,35 @@ __device__ __forceinline__ R draw_t2(const DevTab& T, const Stream& st, uint32_t
     return -tau2 * r_log(R(1) - unif<R>(q.x, q.y));
 }
 
+// internal line wall k in the trajectories' precision: segment ends and unit normal
+template <typename R> struct WallR { R x1, y1, x2, y2, nx, ny; };
+template <typename R>
+__device__ __forceinline__ WallR<R> wall_of(const DevGeom& g, int k)
+{
+    if constexpr (std::is_same<R, double>::value)
+        return WallR<R>{g.wall_x1[k], g.wall_y1[k], g.wall_x2[k], g.wall_y2[k], g.wall_nx[k], g.wall_ny[k]};
+    else
+        return WallR<R>{g.wall32[k][0], g.wall32[k][1], g.wall32[k][2], g.wall32[k][3], g.wall32[k][4], g.wall32[k][5]};
+}
+
+// inside a closed loop of walls (crossing number, half-open edges): outside the solid
+template <typename R>
+__device__ __forceinline__ bool inside_wall_loops(const DevGeom& g, R px, R py)
+{
+    bool inside = false;
+    for (int k = 0; k < g.n_walls; ++k) {
+        const int j = g.wall_loop_end[k];
+        if (j < 0) continue;
+        bool in = false;
+        for (int e = k; e <= j; ++e) {
+            const WallR<R> w = wall_of<R>(g, e);
+            if ((w.y1 > py) != (w.y2 > py) && px < w.x1 + (py - w.y1) * (w.x2 - w.x1) / (w.y2 - w.y1)) in = !in;
+        }
+        inside = inside || in;
+    }
+    return inside;
+}
+
 template <typename R>
 __device__ __forceinline__ void resolve_clocks(const DevTab& T, const Stream& st, Part<R>& p)
 {
@@ -317,13 +346,15 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
     } else if (kind == SRC_GRAD) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) p.x[ax] = g.unb[ax] ? R(0) : up[ax] * Geo<R>::L(g, ax);
-        for (uint32_t attempt = 1; g.n_pores > 0; ++attempt) {   // positions inside pores are redrawn
+        // positions outside the solid (inside pores or closed loops of walls) are redrawn
+        for (uint32_t attempt = 1; g.n_pores > 0 || g.n_walls > 0; ++attempt) {
             bool inside = false;
             for (int c = 0; c < g.n_pores; ++c) {
                 const R dx = p.x[0] - Geo<R>::cx(g, c), dy = p.x[1] - Geo<R>::cy(g, c);
                 const R r = Geo<R>::r(g, c);
                 if (dx * dx + dy * dy < r * r) inside = true;
             }
+            if (g.n_walls > 0 && inside_wall_loops<R>(g, p.x[0], p.x[1])) inside = true;
             if (!inside || attempt > 4096) break;
             ++rejections;
             const uint32_t blk = 2u * (0x40000000u + attempt);
@@ -1167,13 +1198,14 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     const R vm = tb.v[p.m];
     const R sg = (R)p.s;
     int hit, pore, ev, fa, fs;
+    int wall = -1;                       // the line wall hit (-1: none)
     R pcx, pcy, pr;                      // centre and radius of the pore hit
     uint32_t fcode;
     // the extended physics (two-phonon clock, specular cutoff frequencies) is compiled in
     constexpr bool EXT = (FT & FT_PLAIN) == 0;
     if (EXT && T.two) resolve_clocks<R>(T, st, p);
     if constexpr (TK == TALLY_STEADY_ONE && AK != 2 && (FT & FT_LOG) == 0) {
-        if (chain) {
+        if (chain && !(EXT && g.n_walls > 0)) {   // (the lone-lane walk knows faces and pores)
             uint32_t pc0 = H.pcls & 3u;      // the first pore's reflection class for this phonon
             if (EXT && T.spec_w && H.n_pores == 1 && g.pore_wc[0] > 0.0 && T.omega64[p.m] < g.pore_wc[0])
                 pc0 = SURF_SPECULAR;
@@ -1199,6 +1231,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         R db = R(1) / R(0);
         hit = 0;
         pore = -1;
+        wall = -1;
         pcx = R(0);
         pcy = R(0);
         pr = R(1);
@@ -1241,6 +1274,24 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             pcx = better ? cx : pcx;
             pcy = better ? cy : pcy;
             pr = better ? rr : pr;
+        }
+        if constexpr (EXT) {
+            // internal line walls (ids after the pores'), met from the side their normal points
+            // to: x + d o = P1 + s (P2 - P1) in the x-y plane, d >= 0, 0 <= s <= 1
+            for (int k = 0; k < g.n_walls; ++k) {
+                const WallR<R> w = wall_of<R>(g, k);
+                const R on = p.o[0] * w.nx + p.o[1] * w.ny;
+                const R ex = w.x2 - w.x1, ey = w.y2 - w.y1;
+                const R den = p.o[0] * ey - p.o[1] * ex;
+                const R wx = w.x1 - p.x[0], wy = w.y1 - p.x[1];
+                const R d = r_div(wx * ey - wy * ex, den);
+                const R sp = r_div(wx * p.o[1] - wy * p.o[0], den);
+                const bool better = (on < R(0)) & (den != R(0)) & (d >= R(0)) & (sp >= R(0)) & (sp <= R(1)) & (d < db);
+                db = better ? d : db;
+                hit = better ? g.wall_id[k] : hit;
+                wall = better ? k : wall;
+                pore = better ? -1 : pore;
+            }
         }
         // event: the time horizon first, then the boundary (segment (x0, x1]), then relaxation
         const R dmin = db < ds ? db : ds;
@@ -1375,13 +1426,16 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         if (hit <= 6) {
             btype = (int)(fcode & 3u);
             cls = fcode >> 2;
+        } else if (EXT && wall >= 0) {
+            btype = 2;
+            cls = (g.wall_cls[Geo<R>::prec] >> (2 * wall)) & 3u;
         } else {
             btype = 2;
             cls = (H.pcls >> (2 * pore)) & 3u;
         }
         // frequency-dependent specularity: below the boundary's cutoff the reflection is specular
         if (EXT && T.spec_w && btype == 2) {
-            const double wc = hit <= 6 ? g.face_wc[hit - 1] : g.pore_wc[pore];
+            const double wc = hit <= 6 ? g.face_wc[hit - 1] : (wall >= 0 ? g.wall_wc[wall] : g.pore_wc[pore]);
             if (wc > 0.0 && T.omega64[p.m] < wc) cls = SURF_SPECULAR;
         }
         if (btype == 1) {
@@ -1412,7 +1466,9 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     W4 w0 = {0u, 0u, 0u, 0u};
     if (need_b0) w0 = st.block(blk);
     bool specular = adia && cls == SURF_SPECULAR;
-    if (partial) specular = key64(w0.x, w0.y) < (pore >= 0 ? g.pore_thr[pore] : g.face_thr[hit - 1]);
+    if (partial)
+        specular = key64(w0.x, w0.y) <
+                   (pore >= 0 ? g.pore_thr[pore] : ((EXT && wall >= 0) ? g.wall_thr[wall] : g.face_thr[hit - 1]));
     const bool diffuse = adia && !specular;
     if (relax || diffuse || two_ev) {
         const W4 w1 = st.block(blk + 1u);
@@ -1461,6 +1517,11 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
                 n[0] = r_div(p.x[0] - pcx, pr);
                 n[1] = r_div(p.x[1] - pcy, pr);
                 n[2] = R(0);
+            } else if (EXT && wall >= 0) {
+                const WallR<R> w = wall_of<R>(g, wall);
+                n[0] = w.nx;
+                n[1] = w.ny;
+                n[2] = R(0);
             } else {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) n[a] = (a == fa) ? (fs ? R(-1) : R(1)) : R(0);
@@ -1485,6 +1546,12 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             const R k2 = R(2) * (p.o[0] * n0 + p.o[1] * n1 + p.o[2] * R(0));
             p.o[0] = p.o[0] - k2 * n0;
             p.o[1] = p.o[1] - k2 * n1;
+            p.o[2] = p.o[2] - k2 * R(0);
+        } else if (EXT && wall >= 0) {
+            const WallR<R> w = wall_of<R>(g, wall);
+            const R k2 = R(2) * (p.o[0] * w.nx + p.o[1] * w.ny + p.o[2] * R(0));
+            p.o[0] = p.o[0] - k2 * w.nx;
+            p.o[1] = p.o[1] - k2 * w.ny;
             p.o[2] = p.o[2] - k2 * R(0);
         } else {
             if (AK == 2) pc.plane(fa, true);

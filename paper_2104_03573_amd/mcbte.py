@@ -38,9 +38,19 @@ class Pore(C.Structure):
                 ("type", C.c_int32), ("specularity", C.c_double), ("spec_omega", C.c_double)]
 
 
+class Wall(C.Structure):
+    _fields_ = [("x1", C.c_double), ("y1", C.c_double), ("x2", C.c_double), ("y2", C.c_double),
+                ("nx", C.c_double), ("ny", C.c_double), ("id", C.c_int32), ("type", C.c_int32),
+                ("specularity", C.c_double), ("spec_omega", C.c_double)]
+
+
+MAX_WALLS = 16
+
+
 class Geometry(C.Structure):
     _fields_ = [("L", C.c_double * 3), ("unbounded", C.c_int32 * 3), ("n_pores", C.c_int32),
-                ("face", Face * 6), ("pore", Pore * MAX_PORES), ("gradT", C.c_double * 3), ("volume", C.c_double)]
+                ("face", Face * 6), ("pore", Pore * MAX_PORES), ("gradT", C.c_double * 3), ("volume", C.c_double),
+                ("n_walls", C.c_int32), ("reserved_w", C.c_int32), ("wall", Wall * MAX_WALLS)]
 
 
 class Detectors(C.Structure):
@@ -170,8 +180,13 @@ def structs_from_workload(w: dict):
     for fid, (ty, d0, d1, d2) in g["faces"].items():
         G.face[fid - 1].type = int(ty)
         G.face[fid - 1].data[0], G.face[fid - 1].data[1], G.face[fid - 1].data[2] = d0, d1, d2
-    if g.get("walls"):
-        raise ValueError("internal line walls are not supported by this library build")
+    walls = g.get("walls", [])
+    if len(walls) > MAX_WALLS:
+        raise ValueError(f"at most {MAX_WALLS} internal line walls")
+    G.n_walls = len(walls)
+    for i, c in enumerate(walls):
+        x1, y1, x2, y2, nx, ny, wid, ty, spec = c[:9]
+        G.wall[i] = Wall(x1, y1, x2, y2, nx, ny, int(wid), int(ty), spec, float(c[9]) if len(c) > 9 else 0.0)
     G.n_pores = len(g["cylinders"])
     for i, c in enumerate(g["cylinders"]):
         cx, cy, r, cid, ty, spec = c[:6]

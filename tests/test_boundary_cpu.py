@@ -153,3 +153,32 @@ def test_specular_cutoff_inputs():
     dummy = C.c_void_p(1)
     assert M.lib().mcbte_adjoint(t.h, C.byref(run), M.mcbte.SENS_SCORE, 0.0, 0, 10, dummy, dummy, None) \
         == M.mcbte.EINVAL
+
+
+def test_line_wall_inputs():
+    """Walls: adiabatic, inside the box, a unit normal, ids after the pores', a given volume; the
+    host and the oracle refuse the same inputs; the replays refuse walled tables."""
+    base = W.square_pore_cell(N=10)
+    assert _status(base) == 0
+    def bad(mutate):
+        w = W.with_(base)
+        mutate(w)
+        return w
+    cases = [
+        lambda w: w["geometry"]["walls"].__setitem__(0, (0.0, 0.0, 6e-7, 0.0, 0.0, 1.0, 7, W.ADIABATIC, 0.0)),  # outside
+        lambda w: w["geometry"]["walls"].__setitem__(0, w["geometry"]["walls"][0][:4] + (0.0, 0.5, 7, W.ADIABATIC, 0.0)),
+        lambda w: w["geometry"]["walls"].__setitem__(1, w["geometry"]["walls"][1][:6] + (7, W.ADIABATIC, 0.0)),
+        lambda w: w["geometry"]["walls"].__setitem__(0, w["geometry"]["walls"][0][:7] + (W.ISOTHERMAL, 0.0)),
+    ]
+    for mutate in cases:
+        w = bad(mutate)
+        assert _status(w) == M.mcbte.EGEOM
+        with pytest.raises(ValueError):
+            oracle.Tables(w)
+    novol = W.with_(base, **{"geometry.volume": 0.0})
+    assert _status(novol) == M.mcbte.EINVAL
+    t = M.Tables(base, device=-1)
+    run = M.make_run(1, 32)
+    dummy = C.c_void_p(1)
+    assert M.lib().mcbte_adjoint(t.h, C.byref(run), M.mcbte.SENS_SCORE, 0.0, 0, 10, dummy, dummy, None) \
+        == M.mcbte.EINVAL

@@ -1,5 +1,6 @@
 """The extended physics on the HIP path, through the C ABI: separate two-phonon and
-three-phonon clocks (section 3.3) and frequency-dependent specularity (section 3.5.3).
+three-phonon clocks (section 3.3), frequency-dependent specularity (section 3.5.3) and internal
+line walls (section 4.2).
 
 The FP64 event sequences of such workloads are compared bit-exactly with the oracle in
 test_gpu_parity.py (FP64_CASES); this file covers the emitted clocks, the state-buffer path,
@@ -174,4 +175,40 @@ def test_specular_cutoff_launch_shapes_batched_kernel_and_fp32():
     _say(f"[fp32 cutoff film] kappa {got['kappa']:.6g} vs {ref['kappa']:.6g} (rel {rel_k:.2e})")
     assert rel_k < 2e-4
     for k in ("flights", "specular", "diffuse"):
+        assert abs(got["counts"][k] - ref["counts"][k]) <= 1e-3 * ref["counts"][k], k
+
+
+def test_line_walls_launch_shapes_batched_kernel_and_fp32():
+    """Square pore of four walls: launch shapes (one-wave grids included) give the same FP64
+    counters and sums; a batch mixing a walled and a plain instance equals solo runs; the FP32
+    channel between two walls agrees with the FP64 oracle."""
+    import torch
+    M = _pkg()
+    w = W.square_pore_cell(N=1500)
+    base = M.run(w, precision=64)
+    assert base["counts"]["diffuse"] > 0 and base["counts"]["rejections"] > 0
+    for block, refill, grid in ((64, 1, 1), (64, 8, 3), (256, 32, 0)):
+        r = M.run(w, precision=64, block=block, refill=refill, grid=grid)
+        assert np.array_equal(r["counts_raw"], base["counts_raw"]), (block, refill, grid)
+        assert np.abs(r["raw"] - base["raw"]).max() <= 1e-12 * np.abs(base["raw"]).max()
+    ws = [W.square_pore_cell(N=3000), W.porous_cell(N=3000)]
+    for i, wi in enumerate(ws):
+        wi["instance"] = 21 + i
+        wi["seed"] = ws[0]["seed"]          # one launch, one key
+    tabs = [M.Tables(wi) for wi in ws]
+    tallies = [t.new_tally() for t in tabs]
+    queue = torch.zeros(M.batch_queue_bytes(len(ws)), dtype=torch.uint8, device="cuda")
+    run = M.make_run(int(ws[0]["seed"]), 64)
+    M.trace_batch(tabs, [wi["problem"]["N"] for wi in ws], [wi["instance"] for wi in ws], tallies, run, queue)
+    for wi, t, tl in zip(ws, tabs, tallies):
+        b = M.tally(t, tl)
+        s = M.run(wi, precision=64, tables=t)
+        assert np.array_equal(b["counts_raw"], s["counts_raw"])
+    wf = W.walled_film(N=100000)
+    got = M.run(wf, precision=32)
+    ref = oracle.run(wf, threads=THREADS)
+    rel_k = abs(got["kappa"] - ref["kappa"]) / abs(ref["kappa"])
+    _say(f"[fp32 walled film] kappa {got['kappa']:.6g} vs {ref['kappa']:.6g} (rel {rel_k:.2e})")
+    assert rel_k < 2e-4
+    for k in ("flights", "diffuse", "periodic"):
         assert abs(got["counts"][k] - ref["counts"][k]) <= 1e-3 * ref["counts"][k], k

@@ -53,6 +53,10 @@ FP64_CASES = {
     "film_spec_cutoff": lambda: W.film(N=3000, spec_omega=2.5 * W.OMEGA_2THZ),
     "film_partial_spec_cutoff": lambda: W.film(N=2000, d=30e-9, specularity=0.4, spec_omega=2.5 * W.OMEGA_2THZ),
     "porous_spec_cutoff": lambda: W.porous_cell(N=1000, spec_omega=W.OMEGA_2THZ),
+    # internal line walls: the paper's square pore of four walls, a channel between two walls
+    "square_pore_walls": lambda: W.square_pore_cell(N=1000),
+    "square_pore_walls_partial": lambda: W.square_pore_cell(N=800, specularity=0.5),
+    "walled_film": lambda: W.walled_film(N=2000),
 }
 
 
