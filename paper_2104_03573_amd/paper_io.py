@@ -9,8 +9,8 @@ inputs
                         (the optional last column is the impurity relaxation time; rows of equal
                         omega share one frequency bin)
   Out_bnd.txt           x_length y_length z_length (one corner at the origin)
-  In_bnd.txt            internal walls x1 y1 x2 y2 nx ny nz (read; polygonal walls are not traced
-                        by this library, so a case that lists any is refused)
+  In_bnd.txt            internal line walls x1 y1 x2 y2 nx ny nz (through the thickness; their
+                        Boundary_prop rows are ids 7, 8, ... in the same order)
   Boundary_prop.txt     bnd_ID bnd_type bnd_data1 bnd_data2 bnd_data3 (types 1 isothermal, 2
                         adiabatic, 3 periodic; ids 1..6: y=0, x=L, y=L, x=0, z=0, z=L)
   Thermal_gradient.txt  bnd_ID1 bnd_ID2 grad_x grad_y grad_z
@@ -77,21 +77,29 @@ def read_case(directory: str, fmt: int, seed: int = 1, transient: bool | None = 
     (L,) = _rows(p("Out_bnd.txt"))
     if len(L) != 3 or min(L) <= 0:
         raise ValueError("Out_bnd.txt: three positive lengths expected")
-    walls = _rows(p("In_bnd.txt")) if os.path.exists(p("In_bnd.txt")) else []
-    if walls:
-        raise NotImplementedError("In_bnd.txt lists internal line walls; this library traces cylindrical "
-                                  "pores only (workloads' 'cylinders')")
-    faces = {}
+    in_bnd = _rows(p("In_bnd.txt")) if os.path.exists(p("In_bnd.txt")) else []
+    if any(len(r) != 7 for r in in_bnd):
+        raise ValueError("In_bnd.txt: x1 y1 x2 y2 nx ny nz per wall")
+    faces, inner = {}, {}
     for r in _rows(p("Boundary_prop.txt")):
         bid, ty = int(r[0]), int(r[1])
         data = list(r[2:5]) + [0.0] * (3 - len(r[2:5]))
-        if not 1 <= bid <= 6:
-            raise NotImplementedError(f"Boundary_prop.txt: id {bid} refers to an internal line wall")
         if ty not in (1, 2, 3):
             raise ValueError(f"Boundary_prop.txt: unknown type {ty} for id {bid}")
-        faces[bid] = (ty, *data)
+        if 1 <= bid <= 6:
+            faces[bid] = (ty, *data)
+        else:
+            inner[bid] = (ty, *data)
     if sorted(faces) != [1, 2, 3, 4, 5, 6]:
         raise ValueError("Boundary_prop.txt: ids 1..6 must each appear once")
+    if sorted(inner) != list(range(7, 7 + len(in_bnd))):
+        raise ValueError("Boundary_prop.txt: one row per In_bnd wall, ids 7, 8, ... in order")
+    walls = []
+    for k, (x1, y1, x2, y2, nx, ny, nz) in enumerate(in_bnd):
+        ty, d0, d1, _ = inner[7 + k]
+        if ty != 2 or nz != 0.0:
+            raise NotImplementedError("internal walls: adiabatic, perpendicular to the x-y plane")
+        walls.append((x1, y1, x2, y2, nx, ny, 7 + k, 2, d0, d1))
     gradT = (0.0, 0.0, 0.0)
     if os.path.exists(p("Thermal_gradient.txt")):
         g = _rows(p("Thermal_gradient.txt"))
@@ -123,7 +131,7 @@ def read_case(directory: str, fmt: int, seed: int = 1, transient: bool | None = 
         "modes": modes,
         "geometry": {"L": tuple(L), "unbounded": (False, False, False),
                      "faces": {int(k): tuple(float(x) for x in v) for k, v in faces.items()},
-                     "cylinders": [], "gradT": gradT, "volume": V},
+                     "cylinders": [], "walls": walls, "gradT": gradT, "volume": V},
         "detectors": det,
         "problem": {"N": N, "T_lin": T_lin, "n_scat_max": nscat, "transient": bool(transient),
                     "t_max": t_max, "t_meas": t_meas, "ic_axis": 2, "ic_edges": np.zeros(0),
@@ -139,6 +147,9 @@ def write_case(w: dict, directory: str) -> None:
     g, pr, d = w["geometry"], w["problem"], w["detectors"]
     if g["cylinders"] or any(g["unbounded"]):
         raise NotImplementedError("the paper's files describe bounded boxes with line walls only")
+    walls = g.get("walls", [])
+    if [c[6] for c in walls] != list(range(7, 7 + len(walls))):
+        raise NotImplementedError("the paper's files number the line walls 7, 8, ... in order")
     os.makedirs(directory, exist_ok=True)
     p = lambda name: os.path.join(directory, name)
     m = w["modes"]
@@ -154,11 +165,16 @@ def write_case(w: dict, directory: str) -> None:
             fh.write(" ".join(repr(float(c)) for c in cols) + "\n")
     with open(p("Out_bnd.txt"), "w") as fh:
         fh.write(" ".join(repr(float(x)) for x in g["L"]) + "\n")
-    open(p("In_bnd.txt"), "w").close()
+    with open(p("In_bnd.txt"), "w") as fh:
+        for c in walls:
+            fh.write(" ".join(repr(float(x)) for x in c[:6]) + " 0.0\n")
     with open(p("Boundary_prop.txt"), "w") as fh:
         for bid in range(1, 7):
             ty, *data = g["faces"][bid]
             fh.write(f"{bid} {int(ty)} " + " ".join(repr(float(x)) for x in data) + "\n")
+        for c in walls:
+            wc = float(c[9]) if len(c) > 9 else 0.0
+            fh.write(f"{int(c[6])} {int(c[7])} {float(c[8])!r} {wc!r} 0.0\n")
     with open(p("Thermal_gradient.txt"), "w") as fh:
         fh.write("1 3 " + " ".join(repr(float(x)) for x in g["gradT"]) + "\n")
     with open(p("Sim_param.txt"), "w") as fh:

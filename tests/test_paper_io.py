@@ -58,10 +58,10 @@ def test_mat_data_formats_and_the_impurity_column(tmp_path):
         P.read_mat_data(str(f2), 1)
 
 
-def test_the_papers_nanomesh_files_are_read_and_line_walls_refused(tmp_path):
+def test_the_papers_nanomesh_files(tmp_path):
     """The example the paper's I/O section describes: a 34 x 34 x 22 nm cell, periodic in x and y,
-    diffuse top and bottom, four internal line walls (a square pore), N = 1e6, N_scat^max = 10,
-    V = 2.28e-23 m^3, T_lin = 300 K; this library traces cylindrical pores, not line walls."""
+    diffuse top and bottom, four internal line walls (an 11-nm square pore), N = 1e6,
+    N_scat^max = 10, V = 2.28e-23 m^3, T_lin = 300 K."""
     (tmp_path / "Out_bnd.txt").write_text("34e-9 34e-9 22e-9\n")
     (tmp_path / "In_bnd.txt").write_text("11.5e-9 11.5e-9 22.5e-9 11.5e-9 0 -1 0\n"
                                          "22.5e-9 11.5e-9 22.5e-9 22.5e-9 1 0 0\n"
@@ -73,13 +73,19 @@ def test_the_papers_nanomesh_files_are_read_and_line_walls_refused(tmp_path):
     (tmp_path / "Thermal_gradient.txt").write_text("1 3 0 -2.94e6 0\n")
     (tmp_path / "Sim_param.txt").write_text("1000000 10 2.28e-23 300\n")
     (tmp_path / "mat_data.txt").write_text("1e13 6400 1.5625e-11 1e6\n")
-    with pytest.raises(NotImplementedError):
-        P.read_case(str(tmp_path), fmt=2)
-    # without the line walls the same files describe a periodic slab between diffuse plates
-    (tmp_path / "In_bnd.txt").write_text("")
-    (tmp_path / "Boundary_prop.txt").write_text(
-        "1 3 0 34e-9 0\n2 3 -34e-9 0 0\n3 3 0 -34e-9 0\n4 3 34e-9 0 0\n5 2 0 0 0\n6 2 0 0 0\n")
     w = P.read_case(str(tmp_path), fmt=2)
+    assert [c[6] for c in w["geometry"]["walls"]] == [7, 8, 9, 10]
+    assert w["geometry"]["walls"][1][:6] == (22.5e-9, 11.5e-9, 22.5e-9, 22.5e-9, 1.0, 0.0)
+    r = oracle.trace(W.with_(w, **{"problem.N": 2000}), threads=4)
+    c = dict(zip(oracle.COUNT_NAMES, r["counts"]))
+    p_rej = (11e-9 / 34e-9) ** 2                 # the square pore's share of the cell
+    assert abs(c["rejections"] / 2000 - p_rej / (1 - p_rej)) < 4 * (p_rej / (1 - p_rej) ** 2 / 2000) ** 0.5
+    assert c["diffuse"] > 0
+    # written back and read again: the same case
+    P.write_case(w, str(tmp_path / "again"))
+    w2 = P.read_case(str(tmp_path / "again"), fmt=2)
+    assert w2["geometry"]["walls"] == [tuple(float(x) for x in c[:6]) + (c[6], 2, float(c[8]), 0.0)
+                                       for c in w["geometry"]["walls"]]
     assert w["problem"]["N"] == 1000000 and w["problem"]["n_scat_max"] == 10
     assert w["geometry"]["volume"] == 2.28e-23 and w["problem"]["T_lin"] == 300.0
     assert w["geometry"]["gradT"] == (0.0, -2.94e6, 0.0) and w["problem"]["score_axis"] == 1
