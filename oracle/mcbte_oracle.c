@@ -29,7 +29,7 @@
 #define TWO64 18446744073709551616.0
 
 enum { B_ISO = 1, B_ADIA = 2, B_PERI = 3 };
-enum { S_WALL = 0, S_GRAD = 1, S_IC = 2 };
+enum { S_WALL = 0, S_GRAD = 1, S_IC = 2, S_IWALL = 3 };   /* S_IWALL: isothermal line wall */
 enum { E_OK = 0, E_INVAL = -1, E_NOMEM = -2, E_TABLE = -5, E_GEOM = -6 };
 
 /* boundary-table order: 1 y=0, 2 x=Lx, 3 y=Ly, 4 x=0, 5 z=0, 6 z=Lz */
@@ -246,8 +246,11 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
     for (int k = 0; k < g->n_wall; ++k) {
         const orc_wall* wl = &g->wall[k];
         const int prev = k > 0 ? g->wall[k - 1].id : (g->n_cyl > 0 ? g->cyl[g->n_cyl - 1].id : 6);
-        if (g->unbounded[0] || g->unbounded[1] || wl->type != B_ADIA || wl->id <= prev) return E_GEOM;
-        if (!(wl->spec >= 0.0 && wl->spec <= 1.0) || !(wl->spec_wc >= 0.0) || !isfinite(wl->spec_wc)) return E_GEOM;
+        if (g->unbounded[0] || g->unbounded[1] || (wl->type != B_ADIA && wl->type != B_ISO) || wl->id <= prev)
+            return E_GEOM;
+        if (!(wl->spec_wc >= 0.0) || !isfinite(wl->spec_wc)) return E_GEOM;
+        if (wl->type == B_ADIA && !(wl->spec >= 0.0 && wl->spec <= 1.0)) return E_GEOM;
+        if (wl->type == B_ISO && !(wl->spec > 0.0 && isfinite(wl->spec))) return E_GEOM;   /* T_b */
         const double pts[4] = {wl->x1, wl->y1, wl->x2, wl->y2};
         for (int q = 0; q < 4; ++q)
             if (!(pts[q] >= 0.0 && pts[q] <= g->L[q & 1])) return E_GEOM;
@@ -367,7 +370,7 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
 
     /* sources (section 3.1, Eqs. dev_tot and source_energy), in the order: isothermal faces by
        id, gradient source, initial-condition cells */
-    int Smax = 6 + 1 + (pr->n_ic > 0 ? pr->n_ic : 0);
+    int Smax = 6 + g->n_wall + 1 + (pr->n_ic > 0 ? pr->n_ic : 0);
     t->src_kind = (int32_t*)malloc(sizeof(int32_t) * Smax);
     t->src_ref = (int32_t*)malloc(sizeof(int32_t) * Smax);
     t->src_sign = (int32_t*)malloc(sizeof(int32_t) * Smax);
@@ -386,6 +389,18 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
         double E = ((area * fabs(dT)) * t->Wv) / 4.0;
         if (pr->transient) E = E * pr->t_max;
         t->src_kind[S] = S_WALL; t->src_ref[S] = id; t->src_sign[S] = dT > 0.0 ? 1 : -1; t->src_E[S] = E;
+        ++S;
+    }
+    for (int k = 0; k < g->n_wall; ++k) {        /* isothermal line walls, by id */
+        const orc_wall* wl = &g->wall[k];
+        if (wl->type != B_ISO) continue;
+        double dT = wl->spec - pr->T_lin;
+        if (dT == 0.0) continue;
+        const double ex = wl->x2 - wl->x1, ey = wl->y2 - wl->y1;
+        double area = sqrt(ex * ex + ey * ey) * extent(g, 2);
+        double E = ((area * fabs(dT)) * t->Wv) / 4.0;
+        if (pr->transient) E = E * pr->t_max;
+        t->src_kind[S] = S_IWALL; t->src_ref[S] = k; t->src_sign[S] = dT > 0.0 ? 1 : -1; t->src_E[S] = E;
         ++S;
     }
     if (t->gnorm > 0.0) {
@@ -661,6 +676,17 @@ static int emit(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t pid, 
         p->x[a] = side ? g->L[a] : 0.0;
         double n[3] = {0.0, 0.0, 0.0};
         n[a] = side ? -1.0 : 1.0;
+        orc_dir_cos(ud1, ud2, n, p->o);
+        p->s = t->src_sign[src];
+        p->m = (int32_t)orc_cdf_pick(t->thr_wall, t->M, t->last_wall, key64(R1, 0));
+    } else if (kind == S_IWALL) {
+        /* a point of the wall (along the segment, then through the thickness), directions
+           cosine-weighted about its normal (Eq. wall_dir) */
+        const orc_wall* wl = &g->wall[t->src_ref[src]];
+        p->x[0] = wl->x1 + up[0] * (wl->x2 - wl->x1);
+        p->x[1] = wl->y1 + up[0] * (wl->y2 - wl->y1);
+        p->x[2] = g->unbounded[2] ? 0.0 : up[1] * g->L[2];
+        double n[3] = {wl->nx, wl->ny, 0.0};
         orc_dir_cos(ud1, ud2, n, p->o);
         p->s = t->src_sign[src];
         p->m = (int32_t)orc_cdf_pick(t->thr_wall, t->M, t->last_wall, key64(R1, 0));

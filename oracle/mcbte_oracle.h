@@ -29,8 +29,9 @@ typedef struct { int32_t type, pad; double data[3]; } orc_face;
    phonons below 2 THz specular).  Adiabatic faces carry the same cutoff in data[1]. */
 typedef struct { double cx, cy, r; int32_t id, type; double spec, spec_wc; } orc_cyl;
 /* internal line wall (the paper's In_bnd rows): the segment (x1, y1)-(x2, y2) in the x-y plane,
-   extended through the thickness, normal (nx, ny) pointing into the domain; adiabatic with
-   specularity spec and cutoff spec_wc as for pores; ids above the pores' */
+   extended through the thickness, normal (nx, ny) pointing into the domain; adiabatic (spec = the
+   specularity, spec_wc the cutoff, as for pores) or isothermal (spec = T_b: it absorbs and
+   emits); ids above the pores' */
 typedef struct { double x1, y1, x2, y2, nx, ny; int32_t id, type; double spec, spec_wc; } orc_wall;
 typedef struct {
     double L[3];

@@ -633,3 +633,27 @@ def test_square_pore_of_line_walls_rejects_its_area_and_conserves_the_flux_sign(
     sd = math.sqrt(p_rej / (1 - p_rej) ** 2 / c["particles"])
     assert abs(mean - p_rej / (1 - p_rej)) < 4 * sd, (mean, p_rej / (1 - p_rej))
     assert c["diffuse"] > 0 and 0 < r["kappa"] < r["tables"].kappa_bulk
+
+
+def test_isothermal_line_walls_ballistic_flux_is_deterministic():
+    """tau -> infinity between two isothermal line walls: every particle goes from its wall to the
+    other one and contributes exactly the gap to sum s l_y, so q = (|dT_hot| + |dT_cold|) C v / 4
+    to rounding -- the walls' emission (area = segment length x thickness), direction about the
+    normal and absorption."""
+    w = W.walled_slab(N=20000)
+    w["modes"]["tau"][0] = 1.0
+    r = oracle.run(w, threads=THREADS)
+    C, v = 1e6, 6400.0
+    assert r["counts"]["relaxations"] == 0 and r["counts"]["absorbed"] == 20000
+    assert r["q_score"] == pytest.approx(2.0 * C * v / 4.0, rel=1e-12)
+    assert r["q_score_sigma"] < 1e-9 * r["q_score"]
+
+
+def test_isothermal_line_walls_gray_slab_matches_integral_equation():
+    """The gray slab at Kn = 1 between isothermal line walls: flux against the E1 integral equation."""
+    w = W.walled_slab(N=100000)
+    _, _, Psi = cf.gray_slab_integral_equation(1.0, 2000)
+    _, _, Psi2 = cf.gray_slab_integral_equation(1.0, 1000)
+    r = oracle.run(w, threads=THREADS)
+    q_ref = Psi * 1e6 * 6400.0 * 2.0 / 4.0
+    assert abs(r["q_score"] - q_ref) < 3.0 * r["q_score_sigma"] + abs(Psi - Psi2) * q_ref

@@ -278,6 +278,29 @@ def walled_film(N=1_000_000, d=100e-9, H=300e-9, Lx=200e-9, T=300.0, gradT=-1.0e
     }
 
 
+def walled_slab(N=100_000, Lambda=100e-9, L=100e-9, H=300e-9, Lx=200e-9, v=6400.0, T_hot=301.0,
+                T_cold=299.0, seed=SEED_BASE + 11):
+    """The gray slab of `gray_slab` between two isothermal internal line walls: hot at
+    y = (H - L)/2 (normal +y), cold at (H + L)/2 (normal -y), periodic in x, unbounded in z; the
+    regions beyond the walls are closed loops (adiabatic walls along the box edges close them)."""
+    y0, y1 = 0.5 * (H - L), 0.5 * (H + L)
+    A, I = ADIABATIC, ISOTHERMAL
+    walls = [(0.0, y0, Lx, y0, 0.0, 1.0, 7, I, T_hot), (Lx, y0, Lx, 0.0, 1.0, 0.0, 8, A, 0.0),
+             (Lx, 0.0, 0.0, 0.0, 0.0, -1.0, 9, A, 0.0), (0.0, 0.0, 0.0, y0, -1.0, 0.0, 10, A, 0.0),
+             (Lx, y1, 0.0, y1, 0.0, -1.0, 11, I, T_cold), (0.0, y1, 0.0, H, -1.0, 0.0, 12, A, 0.0),
+             (0.0, H, Lx, H, 0.0, 1.0, 13, A, 0.0), (Lx, H, Lx, y1, 1.0, 0.0, 14, A, 0.0)]
+    faces = {2: (PERIODIC, -Lx, 0, 0), 4: (PERIODIC, Lx, 0, 0),
+             1: (ADIABATIC, 0.0, 0, 0), 3: (ADIABATIC, 0.0, 0, 0)}
+    return {
+        "name": "walled_slab",
+        "modes": gray_modes(v, Lambda / v),
+        "geometry": _geometry((Lx, H, 1.0), (False, False, True), faces, volume=Lx * L * 1.0, walls=walls),
+        "detectors": _detectors(mask=MASK_ALL),
+        "problem": _problem(N, 300.0, 0, score_axis=1, fmt=2),
+        "seed": seed,
+    }
+
+
 def ballistic_transient(N=200_000, L=3000e-9, v=12360.0, tau=1.0, T_l=303.0, T_r=297.0,
                         t_max=1.0e-9, t_meas=(5e-12, 50e-12, 100e-12, 200e-12, 300e-12, 900e-12),
                         bins=60, seed=SEED_BASE + 6):
