@@ -113,15 +113,17 @@ typedef struct {
 /* internal line wall (the paper's In_bnd rows, section 4.2): the segment (x1, y1)-(x2, y2) in the
    x-y plane extended through the thickness, (nx, ny) its normal pointing into the domain (unit
    length within 1e-9; normalized by the library).  A wall is met only from the side its normal
-   points to; it reflects like a pore (specularity d, optional cutoff angular frequency).  Ids
+   points to.  Adiabatic (data = specularity d, optional cutoff angular frequency): it reflects like
+   a pore.  Isothermal (data = T_b): it absorbs, and emits like an isothermal face (energy
+   A |T_b - T_lin| sum C v / 4, A = length x thickness, directions about its normal).  Ids
    continue after the pores' (> every pore id, strictly increasing).  Emission leaves out the
    inside of every closed loop of walls (consecutive walls each starting where the previous one
    ends, the last ending where the first starts); walls in no loop exclude nothing. */
 typedef struct {
     double x1, y1, x2, y2, nx, ny;
     int32_t id;
-    int32_t type;               /* MCBTE_ADIABATIC */
-    double specularity;
+    int32_t type;               /* MCBTE_ADIABATIC or MCBTE_ISOTHERMAL */
+    double data;                /* adiabatic: specularity d; isothermal: T_b (K) */
     double spec_omega;
 } mcbte_wall;
 

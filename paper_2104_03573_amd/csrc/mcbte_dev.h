@@ -14,7 +14,7 @@
 
 namespace mcbte {
 
-enum SourceKind : int32_t { SRC_WALL = 0, SRC_GRAD = 1, SRC_IC = 2 };
+enum SourceKind : int32_t { SRC_WALL = 0, SRC_GRAD = 1, SRC_IC = 2, SRC_IWALL = 3 };   // SRC_IWALL: isothermal line wall
 enum TallyKind : int32_t { TALLY_STEADY_ONE = 0, TALLY_STEADY_GRID = 1, TALLY_TRANSIENT = 2 };
 
 // optional features of the trace kernels, compiled in only where used: particles loaded from a
@@ -72,6 +72,7 @@ struct DevGeom {
     double wall_nx[MCBTE_DEV_MAX_WALLS], wall_ny[MCBTE_DEV_MAX_WALLS];
     float wall32[MCBTE_DEV_MAX_WALLS][6];
     int32_t wall_id[MCBTE_DEV_MAX_WALLS];
+    int32_t wall_type[MCBTE_DEV_MAX_WALLS];
     int32_t wall_loop_end[MCBTE_DEV_MAX_WALLS];
     uint32_t wall_cls[2];
     uint64_t wall_thr[MCBTE_DEV_MAX_WALLS];

@@ -192,9 +192,11 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     for (int k = 0; k < g.n_walls; ++k) {
         const mcbte_wall& w = g.wall[k];
         const int prev = k > 0 ? g.wall[k - 1].id : (g.n_pores > 0 ? g.pore[g.n_pores - 1].id : 6);
-        if (g.unbounded[0] || g.unbounded[1] || w.type != MCBTE_ADIABATIC || w.id <= prev || w.id > 255)
+        if (g.unbounded[0] || g.unbounded[1] || (w.type != MCBTE_ADIABATIC && w.type != MCBTE_ISOTHERMAL) ||
+            w.id <= prev || w.id > 255)
             return MCBTE_EGEOM;
-        if (!(w.specularity >= 0.0 && w.specularity <= 1.0)) return MCBTE_EGEOM;
+        if (w.type == MCBTE_ADIABATIC && !(w.data >= 0.0 && w.data <= 1.0)) return MCBTE_EGEOM;
+        if (w.type == MCBTE_ISOTHERMAL && !(w.data > 0.0 && std::isfinite(w.data))) return MCBTE_EGEOM;
         if (!(w.spec_omega >= 0.0 && std::isfinite(w.spec_omega))) return MCBTE_EGEOM;
         const double pts[4] = {w.x1, w.y1, w.x2, w.y2};
         for (int q = 0; q < 4; ++q)
@@ -312,6 +314,21 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         if (pr.transient) E = E * pr.t_max;
         t->src_kind.push_back(SRC_WALL);
         t->src_ref.push_back(i + 1);
+        t->src_sign.push_back(dT > 0.0 ? 1 : -1);
+        t->src_E.push_back(E);
+    }
+    // isothermal line walls by id: area = segment length x thickness
+    for (int k = 0; k < g.n_walls; ++k) {
+        const mcbte_wall& w = g.wall[k];
+        if (w.type != MCBTE_ISOTHERMAL) continue;
+        const double dT = w.data - pr.T_lin;
+        if (dT == 0.0) continue;
+        const double ex = w.x2 - w.x1, ey = w.y2 - w.y1;
+        const double area = std::sqrt(ex * ex + ey * ey) * extent(2);
+        double E = ((area * std::fabs(dT)) * Wv) / 4.0;
+        if (pr.transient) E = E * pr.t_max;
+        t->src_kind.push_back(SRC_IWALL);
+        t->src_ref.push_back(k);
         t->src_sign.push_back(dT > 0.0 ? 1 : -1);
         t->src_E.push_back(E);
     }
@@ -459,9 +476,11 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         const double v6[6] = {w.x1, w.y1, w.x2, w.y2, dg.wall_nx[k], dg.wall_ny[k]};
         for (int q = 0; q < 6; ++q) dg.wall32[k][q] = (float)v6[q];
         dg.wall_id[k] = w.id;
-        dg.wall_cls[0] |= surf_class<float>(w.specularity) << (2 * k);
-        dg.wall_cls[1] |= surf_class<double>(w.specularity) << (2 * k);
-        dg.wall_thr[k] = (w.specularity > 0.0 && w.specularity < 1.0) ? (uint64_t)(w.specularity * kTwo64) : 0;
+        dg.wall_type[k] = w.type;
+        const double d = w.type == MCBTE_ADIABATIC ? w.data : 0.0;
+        dg.wall_cls[0] |= surf_class<float>(d) << (2 * k);
+        dg.wall_cls[1] |= surf_class<double>(d) << (2 * k);
+        dg.wall_thr[k] = (d > 0.0 && d < 1.0) ? (uint64_t)(d * kTwo64) : 0;
         dg.wall_wc[k] = w.spec_omega;
         if (w.spec_omega > 0.0) t->spec_w = true;
         dg.wall_loop_end[k] = -1;

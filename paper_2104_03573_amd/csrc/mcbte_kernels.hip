@@ -343,6 +343,17 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
         dir_cos(ud1, ud2, n, p.o);
         p.s = T.src_sign[src];
         p.m = cdf_pick(T.thr_wall, T.M, T.last_wall, key64(r1a.x, r1a.y));
+    } else if (kind == SRC_IWALL) {
+        // a point of the isothermal line wall (along the segment, through the thickness),
+        // directions cosine-weighted about its normal
+        const WallR<R> w = wall_of<R>(g, T.src_ref[src]);
+        p.x[0] = w.x1 + up[0] * (w.x2 - w.x1);
+        p.x[1] = w.y1 + up[0] * (w.y2 - w.y1);
+        p.x[2] = g.unb[2] ? R(0) : up[1] * Geo<R>::L(g, 2);
+        const R n[3] = {w.nx, w.ny, R(0)};
+        dir_cos(ud1, ud2, n, p.o);
+        p.s = T.src_sign[src];
+        p.m = cdf_pick(T.thr_wall, T.M, T.last_wall, key64(r1a.x, r1a.y));
     } else if (kind == SRC_GRAD) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) p.x[ax] = g.unb[ax] ? R(0) : up[ax] * Geo<R>::L(g, ax);
@@ -1427,7 +1438,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             btype = (int)(fcode & 3u);
             cls = fcode >> 2;
         } else if (EXT && wall >= 0) {
-            btype = 2;
+            btype = g.wall_type[wall];
             cls = (g.wall_cls[Geo<R>::prec] >> (2 * wall)) & 3u;
         } else {
             btype = 2;

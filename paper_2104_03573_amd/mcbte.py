@@ -41,7 +41,7 @@ class Pore(C.Structure):
 class Wall(C.Structure):
     _fields_ = [("x1", C.c_double), ("y1", C.c_double), ("x2", C.c_double), ("y2", C.c_double),
                 ("nx", C.c_double), ("ny", C.c_double), ("id", C.c_int32), ("type", C.c_int32),
-                ("specularity", C.c_double), ("spec_omega", C.c_double)]
+                ("data", C.c_double), ("spec_omega", C.c_double)]
 
 
 MAX_WALLS = 16

@@ -97,9 +97,9 @@ def read_case(directory: str, fmt: int, seed: int = 1, transient: bool | None = 
     walls = []
     for k, (x1, y1, x2, y2, nx, ny, nz) in enumerate(in_bnd):
         ty, d0, d1, _ = inner[7 + k]
-        if ty != 2 or nz != 0.0:
-            raise NotImplementedError("internal walls: adiabatic, perpendicular to the x-y plane")
-        walls.append((x1, y1, x2, y2, nx, ny, 7 + k, 2, d0, d1))
+        if ty not in (1, 2) or nz != 0.0:
+            raise NotImplementedError("internal walls: isothermal or adiabatic, perpendicular to the x-y plane")
+        walls.append((x1, y1, x2, y2, nx, ny, 7 + k, ty, d0, d1 if ty == 2 else 0.0))
     gradT = (0.0, 0.0, 0.0)
     if os.path.exists(p("Thermal_gradient.txt")):
         g = _rows(p("Thermal_gradient.txt"))

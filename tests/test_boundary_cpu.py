@@ -175,6 +175,14 @@ def test_line_wall_inputs():
         assert _status(w) == M.mcbte.EGEOM
         with pytest.raises(ValueError):
             oracle.Tables(w)
+    hot = W.walled_slab(N=10)
+    assert _status(hot) == 0
+    cold0 = W.with_(hot)
+    cold0["geometry"]["walls"][0] = cold0["geometry"]["walls"][0][:8] + (0.0,)       # T_b must be > 0
+    assert _status(cold0) == M.mcbte.EGEOM
+    with pytest.raises(ValueError):
+        oracle.Tables(cold0)
+    assert M.Tables(hot, device=-1).info["n_sources"] == oracle.Tables(hot).S == 2
     novol = W.with_(base, **{"geometry.volume": 0.0})
     assert _status(novol) == M.mcbte.EINVAL
     t = M.Tables(base, device=-1)

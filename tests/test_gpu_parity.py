@@ -57,6 +57,7 @@ FP64_CASES = {
     "square_pore_walls": lambda: W.square_pore_cell(N=1000),
     "square_pore_walls_partial": lambda: W.square_pore_cell(N=800, specularity=0.5),
     "walled_film": lambda: W.walled_film(N=2000),
+    "walled_slab": lambda: W.walled_slab(N=2000),     # isothermal line walls: emission and absorption
 }
 
 
