@@ -104,7 +104,8 @@ def _read_state(M, buf, precision, cap):
     return np.stack(f, 1), np.stack(i, 1)
 
 
-@pytest.mark.parametrize("name", ["gray_slab", "film", "transient_bump", "porous_cell", "ballistic_transient"])
+@pytest.mark.parametrize("name", ["gray_slab", "film", "transient_bump", "porous_cell", "ballistic_transient",
+                                  "square_pore_walls", "walled_slab", "film_two_clocks"])
 def test_emission_matches_oracle(name):
     import torch
     M = _pkg()
@@ -206,7 +207,9 @@ def test_grid_pieces_scored_by_the_wave_match_per_lane_scoring(precision):
 
 def test_emit_then_trace_equals_fused():
     M = _pkg()
-    for w, prec in ((W.film(N=5000), 64), (W.transient_bump(N=300), 64), (W.film(N=5000), 32)):
+    for w, prec in ((W.film(N=5000), 64), (W.transient_bump(N=300), 64), (W.film(N=5000), 32),
+                    (W.square_pore_cell(N=2000), 64), (W.walled_slab(N=3000), 64),
+                    (W.porous_cell(N=2000, spec_omega=W.OMEGA_2THZ), 32)):
         fused = M.run(w, precision=prec, n_log=200, log_stride=64)
         staged = M.run(w, precision=prec, n_log=200, log_stride=64, emit_first=True)
         assert np.array_equal(fused["counts_raw"], staged["counts_raw"])
