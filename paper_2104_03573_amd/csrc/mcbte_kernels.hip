@@ -1716,13 +1716,14 @@ __device__ __forceinline__ double lane_value(double v, int k)
 // the chord to the opposite wall, its flight time and its flux terms depend only on the
 // reflection's own record and on the wall it starts from, so the lanes evaluate 64 consecutive
 // reflections at once, each with the sequential loop's own arithmetic (the chord is the division
-// the geometry step makes from the wall coordinate).  The whole wave then walks them in order
-// with the sequential arithmetic for everything that carries over from one segment to the next:
-// first the remaining flight time and the test against it, which alone decide where the walk
-// stops, then (a loop with no exit) position, time and the particle's scores over the segments
-// completed before that, then segment count and event log; the particle leaves the chain in
-// exactly the state the one-segment-at-a-time loop reaches.  The tallies take each lane's terms
-// (their summation order is free, as it is for the atomics).
+// the geometry step makes from the wall coordinate).  Where the walk stops is decided by the
+// remaining flight time and the test against it alone: a wave prefix sum settles it whenever every
+// test clears its rounding bound, the in-order recursion otherwise.  Then, in a loop with no exit,
+// the sequential arithmetic for everything that carries over from one segment to the next
+// (remaining time, position, time, the particle's scores) runs over the completed segments in
+// order, then segment count and event log; the particle leaves the chain in exactly the state the
+// one-segment-at-a-time loop reaches.  The tallies take each lane's terms (their summation order
+// is free, as it is for the atomics).
 __device__ __forceinline__ void coop_exact(const Hot<double>& H, const Tabs<double>& tb, const TallyCtx& tc,
                                            Part<double>& p, const Stream& st_own, int leader, LaneCounts& cnt,
                                            LogRow& lg)
@@ -1777,25 +1778,46 @@ __device__ __forceinline__ void coop_exact(const Hot<double>& H, const Tabs<doub
         const double q0 = d * o[0], q1 = d * o[1], q2 = d * o[2];
         const double qs = sa == 0 ? q0 : (sa == 1 ? q1 : q2);
         const double r0 = aw == 0 ? q1 : q0, r1 = aw == 2 ? q1 : q2;   // in-plane displacements
-        // the segment in which the free flight ends (or the event cap stops the walk): the
-        // remaining-time recursion alone, in order, decides it
-        int kstop = 64;
-        double Dk = D;
-        for (int k = 0; k < 64; ++k) {
-            if (pk + (uint32_t)k >= (uint32_t)H.max_events || !(lane_value(d, k) <= vm * Dk)) {
-                kstop = k;
-                break;
+        // the segment in which the free flight ends (or the event cap stops the walk): decided by
+        // the remaining-time recursion D_k = D_(k-1) - dt_(k-1).  Each lane takes the prefix sum of
+        // the earlier chords' times (tree order), which differs from the recursion by at most a
+        // few hundred ulp of D + prefix; where every test up to the stop clears that by more, the
+        // decisions are the recursion's, else the recursion itself is run in order
+        const uint32_t cap_left = pk < (uint32_t)H.max_events ? (uint32_t)H.max_events - pk : 0u;
+        const bool capped = (uint32_t)lane >= cap_left;
+        double P = dt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double tt = __shfl_up(P, off, 64);
+            if (lane >= off) P += tt;
+        }
+        double Pex = __shfl_up(P, 1, 64);
+        if (lane == 0) Pex = 0.0;
+        const double rhs = vm * (D - Pex);
+        const unsigned long long stops = __ballot(capped || !(d <= rhs));
+        int kstop = stops ? __ffsll((long long)stops) - 1 : 64;
+        const double tol = 0x1p-45 * (vm * (D + Pex) + d);
+        if (__ballot(!capped && lane <= kstop && !(fabs(d - rhs) > tol))) {
+            kstop = 64;
+            double Dk = D;
+            for (int k = 0; k < 64; ++k) {
+                if (pk + (uint32_t)k >= (uint32_t)H.max_events || !(lane_value(d, k) <= vm * Dk)) {
+                    kstop = k;
+                    break;
+                }
+                const double r = Dk - lane_value(dt, k);
+                Dk = r > 0.0 ? r : 0.0;
             }
-            const double r = Dk - lane_value(dt, k);
-            Dk = r > 0.0 ? r : 0.0;
         }
         // the segments completed before it, in order: nothing in them ends the walk (every lane
-        // holds the same kstop)
+        // holds the same kstop); the remaining time as the recursion computes it
         kstop = __builtin_amdgcn_readfirstlane(kstop);
         if (sa != aw) {                  // the scored flux is one of the in-plane displacements
             const bool s0 = sa == b0;
             for (int k = 0; k < kstop; ++k) {
                 const double dtk = lane_value(dt, k), e0 = lane_value(r0, k), e1 = lane_value(r1, k);
+                const double r = D - dtk;
+                D = r > 0.0 ? r : 0.0;
                 y0 = y0 + e0;
                 y1 = y1 + e1;
                 t = t + dtk;
@@ -1805,6 +1827,8 @@ __device__ __forceinline__ void coop_exact(const Hot<double>& H, const Tabs<doub
         } else {
             for (int k = 0; k < kstop; ++k) {
                 const double dtk = lane_value(dt, k);
+                const double r = D - dtk;
+                D = r > 0.0 ? r : 0.0;
                 y0 = y0 + lane_value(r0, k);
                 y1 = y1 + lane_value(r1, k);
                 t = t + dtk;
@@ -1812,7 +1836,6 @@ __device__ __forceinline__ void coop_exact(const Hot<double>& H, const Tabs<doub
                 cq += sg * lane_value(qs, k);
             }
         }
-        D = Dk;
         pk += (uint32_t)kstop;
         full += (uint32_t)kstop;
         if (lane < kstop) {              // each lane's own segment, if completed
