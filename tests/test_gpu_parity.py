@@ -58,6 +58,16 @@ FP64_CASES = {
     "square_pore_walls_partial": lambda: W.square_pore_cell(N=800, specularity=0.5),
     "walled_film": lambda: W.walled_film(N=2000),
     "walled_slab": lambda: W.walled_slab(N=2000),     # isothermal line walls: emission and absorption
+    # the extended physics together: walls with a cutoff and partial specularity, two clocks
+    "square_pore_all": lambda: W.with_(W.square_pore_cell(N=800, modes=W.silicon_like_modes(300.0, impurity_clock=True)),
+                                       **{"geometry.walls": [c[:8] + (0.5, W.OMEGA_2THZ) for c in
+                                                             W.square_pore_cell(N=1)["geometry"]["walls"]]}),
+    # isothermal line walls switched on at t = 0, measured at a few times
+    "walled_slab_transient": lambda: W.with_(W.walled_slab(N=1500, Lambda=50e-9),
+                                             **{"problem.transient": True, "problem.t_max": 40e-12,
+                                                "problem.t_meas": np.array([5e-12, 10e-12, 20e-12, 39e-12]),
+                                                "detectors.lo": (0.0, 100e-9, 0.0), "detectors.hi": (200e-9, 200e-9, 0.0),
+                                                "detectors.n": (0, 5, 0)}),
 }
 
 
