@@ -212,3 +212,28 @@ def test_line_walls_launch_shapes_batched_kernel_and_fp32():
     assert rel_k < 2e-4
     for k in ("flights", "diffuse", "periodic"):
         assert abs(got["counts"][k] - ref["counts"][k]) <= 1e-3 * ref["counts"][k], k
+
+
+def test_paper_format_case_runs_through_the_library(tmp_path):
+    """The paper's nanomesh example files (a 34-nm cell, 22 nm thick, an 11-nm square pore of
+    four line walls) traced on the GPU through the file front end: the output files hold the
+    library's result for the case, and the FP64 counters equal the oracle's."""
+    from paper_2104_03573_amd import paper_io as P
+    (tmp_path / "Out_bnd.txt").write_text("34e-9 34e-9 22e-9\n")
+    (tmp_path / "In_bnd.txt").write_text("11.5e-9 11.5e-9 22.5e-9 11.5e-9 0 -1 0\n"
+                                         "22.5e-9 11.5e-9 22.5e-9 22.5e-9 1 0 0\n"
+                                         "22.5e-9 22.5e-9 11.5e-9 22.5e-9 0 1 0\n"
+                                         "11.5e-9 22.5e-9 11.5e-9 11.5e-9 -1 0 0\n")
+    (tmp_path / "Boundary_prop.txt").write_text(
+        "1 3 0 34e-9 0\n2 3 -34e-9 0 0\n3 3 0 -34e-9 0\n4 3 34e-9 0 0\n5 2 0 0 0\n6 2 0 0 0\n"
+        "7 2 0 0 0\n8 2 0 0 0\n9 2 0 0 0\n10 2 0 0 0\n")
+    (tmp_path / "Thermal_gradient.txt").write_text("1 3 0 -2.94e6 0\n")
+    (tmp_path / "Sim_param.txt").write_text("2000 10 2.28e-23 300\n")
+    (tmp_path / "mat_data.txt").write_text("1e13 6400 1.5625e-11 1e6\n")
+    (tmp_path / "Measure_region.txt").write_text("0 34e-9 0 34e-9 0 22e-9 1\n")
+    res = P.run_case(str(tmp_path), fmt=2, precision=64)
+    qy = np.loadtxt(tmp_path / "Qy300.txt")
+    assert qy.shape == (8,) and np.allclose(qy, res["q"][:, 0, 1])
+    w = P.read_case(str(tmp_path), fmt=2)
+    ref = oracle.trace(w, threads=THREADS)
+    assert np.array_equal(res["counts_raw"], ref["counts"])
