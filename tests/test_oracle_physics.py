@@ -657,3 +657,28 @@ def test_isothermal_line_walls_gray_slab_matches_integral_equation():
     r = oracle.run(w, threads=THREADS)
     q_ref = Psi * 1e6 * 6400.0 * 2.0 / 4.0
     assert abs(r["q_score"] - q_ref) < 3.0 * r["q_score_sigma"] + abs(Psi - Psi2) * q_ref
+
+
+def test_pore_lattice_kappa_is_isotropic_in_plane_and_translation_invariant():
+    """The cell with a z-axis pore tiles a square lattice of pores: its in-plane conductivity
+    tensor is isotropic (a 90-degree rotation maps the lattice onto itself), and moving the pore
+    inside the cell only moves the lattice's origin.  Gray phonons, Lambda = 100 nm against a
+    500 nm pitch and a 141 nm pore radius, so the pores cut kappa well below its bulk value."""
+    base = W.porous_cell(N=400000, modes=W.gray_modes(6400.0, 1.5625e-11), n_scat_max=10)
+    base["problem"]["format"] = 2
+    Wc = base["geometry"]["L"][0]
+    cyl = base["geometry"]["cylinders"][0]
+    g = base["geometry"]["gradT"][1]
+    runs = {
+        "y": base,
+        "x": W.with_(base, **{"geometry.gradT": (g, 0.0, 0.0), "problem.score_axis": 0}),
+        "moved": W.with_(base, **{"geometry.cylinders": [(0.3 * Wc, 0.7 * Wc) + tuple(cyl[2:])]}),
+    }
+    res = {k: oracle.run(w, threads=THREADS) for k, w in runs.items()}
+    k_bulk = res["y"]["tables"].kappa_bulk
+    for k, r in res.items():
+        assert r["kappa"] < 0.9 * k_bulk - 10.0 * r["kappa_sigma"], (k, r["kappa"], k_bulk)
+    for a, b in (("y", "x"), ("y", "moved"), ("x", "moved")):
+        ra, rb = res[a], res[b]
+        assert abs(ra["kappa"] - rb["kappa"]) < 3.5 * math.hypot(ra["kappa_sigma"], rb["kappa_sigma"]), \
+            (a, b, ra["kappa"], rb["kappa"], ra["kappa_sigma"], rb["kappa_sigma"])
