@@ -36,6 +36,11 @@ FP64_CASES = {
     "transient_bump": lambda: W.transient_bump(N=400),
     "porous_cell": lambda: W.porous_cell(N=2000),
     "porous_cell_specular": lambda: W.porous_cell(N=1000, specularity=0.5),
+    # the same lattice driven along x, and with the pore moved off the cell's centre
+    "porous_cell_x": lambda: W.with_(W.porous_cell(N=1500), **{"geometry.gradT": (-2.0e6, 0.0, 0.0),
+                                                              "problem.score_axis": 0}),
+    "porous_cell_moved": lambda: W.with_(W.porous_cell(N=1500), **{"geometry.cylinders": [
+        (150e-9, 350e-9) + tuple(W.porous_cell(N=1)["geometry"]["cylinders"][0][2:])]}),
     "ballistic_transient": lambda: W.ballistic_transient(N=3000),
     "bulk_dispersive": lambda: W.bulk_gradient(N=2000, n_scat_max=3, modes=W.silicon_like_modes(300.0)),
     "grid3d": lambda: W.with_(W.gray_slab(N=1500), **{"detectors.lo": (0.0, 0.0, 0.0),
