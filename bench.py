@@ -7,9 +7,12 @@ frequency, direction, sign, free flights, boundaries, relaxations, detector scor
 finalize the tallies on the host (kappa and its standard error).  The mode tables are built
 once before the timed region (inputs resident in HBM).  Each step uses its own seed.
 
-Default workload: the in-plane thin film (100 nm, diffuse walls, synthetic silicon-like
-dispersion of 1400 mode rows at 300 K, 1e6 particles, N_scat^max = 10), FP32 trajectories
-with FP64 tables and sums.  One JSON line on stdout.
+Default workload: the 3-D periodic nanostructure -- a 500 nm cubic cell with a centred
+cylindrical pore at 25 % porosity, diffuse pore wall, periodic faces, a temperature gradient
+along y, the synthetic silicon-like dispersion of 1400 mode rows at 300 K, 1e8 particles,
+N_scat^max = 10 -- FP32 trajectories with FP64 tables and sums.  The other configurations (the
+thin film, the gray slab, the transient bump, the batched sweep, the sensitivities) are
+reported under "forms".  One JSON line on stdout.
 """
 from __future__ import annotations
 
@@ -114,19 +117,51 @@ def workload(name: str, scale: float = 1.0):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(w: dict, seconds: float, threads: int) -> dict:
-    """The oracle as it stands, on the host cores: whole batches of the same workload (a new seed
-    per batch, like the GPU steps) until about `seconds` of CPU time have passed; a batch larger
-    than that is cut to a prefix of its particles."""
+def is_pore_lattice(w: dict) -> bool:
+    """A steady cell periodic in x and y (periodic or unbounded in z) with one pore inside it and no
+    line walls: the FP32 trace then walks long free paths from pore to pore with the whole wave."""
+    g, p = w["geometry"], w["problem"]
+    if p["transient"] or len(g["cylinders"]) != 1 or g.get("walls") or any(w["detectors"]["n"]):
+        return False
+    if g["unbounded"][0] or g["unbounded"][1]:
+        return False
+    axis = {1: 1, 2: 0, 3: 1, 4: 0, 5: 2, 6: 2}
+    if any(not g["unbounded"][axis[i]] and g["faces"][i][0] != 3 for i in range(1, 7)):
+        return False
+    cx, cy, r = g["cylinders"][0][:3]
+    return cx - r > 0 and cx + r < g["L"][0] and cy - r > 0 and cy + r < g["L"][1]
+
+
+def host_cores() -> int:
+    """Cores this process may run on (its CPU affinity), at most 16: the host share of one GPU on
+    the benchmark machines, whatever the machine's total is."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(w, tb, threads: int, seconds: float):
+    """flights/s of the oracle on whole batches of w (a new seed per batch), each batch a prefix of
+    the particles sized to take a fraction of `seconds`, until `seconds` have passed."""
     import oracle
-    tb = oracle.Tables(w)
     N = w["problem"]["N"]
     t0 = time.perf_counter()
     probe = oracle.trace(w, n=min(N, 2000), threads=threads, tables=tb)
     rate = probe["counts"][0] / max(time.perf_counter() - t0, 1e-6)
-    n = int(min(N, max(2000, rate * seconds)))
-    flights = 0
-    batches = 0
+    n = int(min(N, max(2000, rate * seconds / 4)))
+    flights, batches = 0, 0
     t0 = time.perf_counter()
     while True:
         wb = dict(w, seed=int(w["seed"]) + batches)
@@ -136,10 +171,25 @@ def cpu_baseline(w: dict, seconds: float, threads: int) -> dict:
         dt = time.perf_counter() - t0
         if dt >= seconds or batches >= 10000:
             break
+    return flights / dt, flights, dt, batches, n
+
+
+def cpu_baseline(w: dict, seconds: float, threads: int) -> dict:
+    """The oracle as it stands, on the host cores (threads over contiguous particle ranges): whole
+    batches of the same workload, a new seed per batch like the GPU steps, each batch a prefix of
+    the particles, until about `seconds` have passed; then the same on one core for a fifth of the
+    time (the single-core rate)."""
+    import oracle
+    tb = oracle.Tables(w)
+    N = w["problem"]["N"]
+    rate, flights, dt, batches, n = _oracle_rate(w, tb, threads, seconds)
+    rate1, flights1, dt1, _, n1 = _oracle_rate(w, tb, 1, max(2.0, seconds / 5))
     what = f"{batches} batches of particles 0..{n - 1}" if n < N else f"{batches} full batches of {N} particles"
-    return {"value": flights / dt, "unit": "flights/s", "cores": threads, "kind": "oracle",
-            "sample": f"{what} of the same workload, new seed per batch ({flights} flights in {dt:.1f} s, "
-                      f"{threads} threads over contiguous particle ranges)"}
+    return {"value": rate, "unit": "flights/s", "cores": threads, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(), "single_core_value": rate1,
+            "sample": f"{what} of the same workload, new seed per batch ({flights} flights in {dt:.1f} s on "
+                      f"{threads} threads over contiguous particle ranges; single core: particles 0..{n1 - 1}, "
+                      f"{flights1} flights in {dt1:.1f} s)"}
 
 
 def launch_config(args, tabs, w, M, precision, probe_cap: int = 4_000_000, reps: int = 3):
@@ -151,7 +201,8 @@ def launch_config(args, tabs, w, M, precision, probe_cap: int = 4_000_000, reps:
     t0 = time.perf_counter()
     # the calibration runs the whole batch up to probe_cap particles: a smaller probe shifts the
     # balance between the steady part and the tail of a launch, and with it the best shape
-    r = M.tune(w, precision=precision, n_probe=max(1, min(total, probe_cap)), reps=reps, tables=tabs)
+    r = M.tune(w, precision=precision, n_probe=max(1, min(total, probe_cap)), reps=reps, tables=tabs,
+               segments=getattr(args, "segments", False))
     return {"block": r["block"], "refill": r["refill"], "autotuned": True,
             "tune_s": round(time.perf_counter() - t0, 3),
             "tune_candidates": M.TUNE_CANDIDATES}
@@ -175,7 +226,8 @@ def measure(args, w, M, torch, precision: int, steps: int, warmup: int, streams:
     def launch(slot: int, seed: int, ev=None):
         tl = tallies[slot]
         tl.zero_()
-        run = M.make_run(seed, precision, block=lc["block"], refill=lc["refill"], grid=args.grid)
+        run = M.make_run(seed, precision, block=lc["block"], refill=lc["refill"], grid=args.grid,
+                         segments=args.segments)
         if ev is not None:
             ev[0].record()
         M.trace(tabs, run, 0, N, None, tl)
@@ -220,7 +272,8 @@ def measure(args, w, M, torch, precision: int, steps: int, warmup: int, streams:
            "frac": achieved / PEAK_LANE_OPS, "flights_per_step": flights / steps,
            "particles_per_s": N * steps / wall,
            "relaxations_per_s": sum(r["counts"]["relaxations"] for r in results) / wall,
-           "table_build_s": t_tables, "launch": lc, "tables": tabs, "last": results[-1], "N": N}
+           "table_build_s": t_tables, "launch": lc, "tables": tabs, "last": results[-1], "N": N,
+           "pore_walk": precision == 32 and not args.segments and is_pore_lattice(w)}
     last = results[-1]
     if not w["problem"]["transient"] and last.get("kappa"):
         sig = last["kappa_sigma"] / abs(last["kappa"])
@@ -280,14 +333,18 @@ def measure_batched(args, ws, M, torch, precision: int, steps: int, warmup: int,
 def measure_sensitivity(args, w, M, torch, estimators, steps: int):
     """Forward trace recording each particle's flux score, then the sensitivity replay of each
     estimator (1000 frequency bins), every launch timed with HIP events; the spread of the summed
-    sensitivity over the steps is reported per estimator."""
+    sensitivity over the steps is reported per estimator.  A replay re-traces the forward's
+    particles event for event, so its algorithmic work is taken as the forward's (the score terms
+    it adds are a few operations per relaxation and flight end) and its roofline fraction is that
+    work over the replay's time."""
     tabs = M.Tables(w, 0)
     lc = launch_config(args, tabs, w, M, 32, 1_000_000, 1)
     N = w["problem"]["N"]
+    ncomp = bin(w["detectors"]["mask"]).count("1")
     F = torch.zeros(N, dtype=torch.float64, device="cuda")
     tl = tabs.new_tally()
     adj = torch.zeros(tabs.info["adj_doubles"], dtype=torch.float64, device="cuda")
-    fwd, flights = [], 0
+    fwd, flights, ops = [], 0, []
     rep = {e: [] for e in estimators}
     total = {e: [] for e in estimators}
     for i in range(steps + 1):
@@ -301,6 +358,7 @@ def measure_sensitivity(args, w, M, torch, estimators, steps: int):
         if i > 0:
             fwd.append(e0.elapsed_time(e1))
             flights += res["counts"]["flights"]
+            ops.append(algorithmic_lane_ops(res["counts"], tabs.info, w["geometry"], ncomp, False))
         for est in estimators:
             adj.zero_()
             r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -312,10 +370,16 @@ def measure_sensitivity(args, w, M, torch, estimators, steps: int):
             if i > 0:                                     # the first step warms up
                 rep[est].append(r0.elapsed_time(r1))
                 total[est].append(float(d.sum()))
-    out = {"forward_ms": fwd, "flights_per_s_forward": flights / (sum(fwd) / 1e3),
-           "bins": int(tabs.info["n_bins"]), "launch": lc}
+    out = {"forward_ms": fwd, "forward_ms_spread": _spread(fwd), "flights_per_s_forward": flights / (sum(fwd) / 1e3),
+           "roofline_frac_forward": sum(ops) / (sum(fwd) / 1e3) / PEAK_LANE_OPS,
+           "bins": int(tabs.info["n_bins"]), "launch": lc, "steps": steps}
     for est in estimators:
-        out[est] = {"replay_ms": rep[est], "sum_dkappa_dlntau_per_step": total[est]}
+        tot = total[est]
+        mean = sum(tot) / len(tot)
+        sd = (sum((x - mean) ** 2 for x in tot) / max(1, len(tot) - 1)) ** 0.5
+        out[est] = {"replay_ms": rep[est], "replay_ms_spread": _spread(rep[est]),
+                    "roofline_frac_replay": sum(ops) / (sum(rep[est]) / 1e3) / PEAK_LANE_OPS,
+                    "sum_dkappa_dlntau_per_step": tot, "sum_dkappa_dlntau_mean": mean, "sum_dkappa_dlntau_sd": sd}
     return out
 
 
@@ -324,7 +388,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="film")
+    ap.add_argument("--workload", default="porous_cell")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
     ap.add_argument("--block", type=int, default=0)
@@ -332,9 +396,11 @@ def main():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--streams", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true", help="default launch shape (block 256, refill 4)")
+    ap.add_argument("--segments", action="store_true",
+                    help="trace pore lattices one segment at a time in FP32 too (no pore-to-pore wave walk)")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the other configurations (gray slab FP64, transient, batched sweep, porous cell "
-                         "with sensitivities) reported under 'forms'")
+                    help="skip the other configurations (thin film, gray slab FP64, transient, batched sweep, "
+                         "sensitivities) reported under 'forms'")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -378,37 +444,48 @@ def main():
                    kernel_ms_per_step=m["kernel_ms"], kappa_eff_per_instance=m["kappa_eff_per_instance"],
                    worst_kappa_sigma_rel=m["worst_kappa_sigma_rel"], table_build_s=m["table_build_s"])
         if not args.no_cpu_baseline:
-            out["cpu_baseline"] = cpu_baseline(w[-1], args.cpu_seconds, min(16, os.cpu_count() or 1))
+            out["cpu_baseline"] = cpu_baseline(w[-1], args.cpu_seconds, host_cores())
         print(json.dumps(out), flush=True)
         return
+    print(f"[bench] main line: {wname}, FP{args.precision}", file=sys.stderr, flush=True)
     m = measure(args, w, M, torch, args.precision, args.steps, args.warmup, args.streams)
     S = max(1, args.streams)
+    tag = f"k_trace_solo_{args.workload}_fp{args.precision}"
     out = dict(common, value=m["flights_per_s"], ms_per_step=m["ms_per_step"],
                config={"workload": wname, "particles_per_step": m["N"], "modes": int(m["tables"].info["n_modes"]),
                        "precision": args.precision, "tallies": "f64", "streams": S, "launch": m["launch"],
+                       "pore_walk": m["pore_walk"],
                        "parallelism": "single GPU" + (", batches overlapped on %d streams" % S if S > 1 else "")},
                roofline={"bound": "alu", "achieved": m["achieved"] / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                          "unit": "T lane-op/s", "frac": m["frac"],
-                         "traffic": (profiled_traffic("k_trace_solo_film_fp32")
-                                     if args.workload == "film" and args.precision == 32 and S == 1 else None),
-                         "kernel": "k_trace_solo", "kernel_ms": sum(m["kernel_ms"]) / len(m["kernel_ms"]),
+                         "traffic": profiled_traffic(tag) if S == 1 and not args.segments else None,
+                         "kernel": "k_trace_solo", "profile": f"profiles/{tag}.txt",
+                         "kernel_ms": sum(m["kernel_ms"]) / len(m["kernel_ms"]),
                          "lane_ops_per_launch": m["lane_ops_per_launch"]},
-               kernel_ms_per_step=m["kernel_ms"], flights_per_step=m["flights_per_step"],
+               kernel_ms_per_step=m["kernel_ms"], kernel_ms_spread=_spread(m["kernel_ms"]),
+               flights_per_step=m["flights_per_step"],
                particles_per_s=m["particles_per_s"], relaxations_per_s=m["relaxations_per_s"],
                table_build_s=m["table_build_s"])
     for k in ("kappa_eff", "kappa_sigma", "time_to_sigma_0p5pct_s"):
         if k in m:
             out[k] = m[k]
-    if not args.no_forms and args.workload == "film":
+    if not args.no_forms and args.workload == "porous_cell" and args.precision == 32 and S == 1:
         out["forms"] = other_forms(args, M, torch)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, min(16, os.cpu_count() or 1))
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, host_cores())
     print(json.dumps(out), flush=True)
+
+
+def _spread(xs) -> dict:
+    ys = sorted(xs)
+    return {"min": ys[0], "median": ys[len(ys) // 2], "max": ys[-1], "n": len(ys)}
 
 
 def _brief(m: dict, workload: str, precision: int) -> dict:
     r = {"workload": workload, "precision": precision, "flights_per_s": m["flights_per_s"],
          "ms_per_step": m["ms_per_step"], "kernel_ms": sum(m["kernel_ms"]) / len(m["kernel_ms"]),
+         "kernel_ms_spread": _spread(m["kernel_ms"]),
          "roofline_frac": m["frac"], "achieved_T_lane_ops": m["achieved"] / 1e12, "launch": m["launch"]}
     for k in ("kappa_eff", "kappa_sigma", "time_to_sigma_0p5pct_s", "kappa_eff_per_instance",
               "worst_kappa_sigma_rel", "particles_per_step"):
@@ -420,10 +497,9 @@ def _brief(m: dict, workload: str, precision: int) -> dict:
 def other_forms(args, M, torch) -> dict:
     """The remaining configurations, a few steps each, every one timed like the main line."""
     forms = {}
-    plan = [("gray_slab_fp64", "gray_slab", 64, 10), ("film_fp64", "film", 64, 5),
-            ("transient_fp32", "transient", 32, 3), ("porous_cell_fp32", "porous_cell", 32, 3),
-            ("film_two_clocks_fp32", "film_two_clocks", 32, 10),
-            ("porous_cell_specular_below_2THz_fp32", "porous_cell_spec2thz", 32, 3)]
+    plan = [("film_fp32", "film", 32, 20), ("gray_slab_fp64", "gray_slab", 64, 10), ("film_fp64", "film", 64, 5),
+            ("transient_fp32", "transient", 32, 3), ("film_two_clocks_fp32", "film_two_clocks", 32, 10),
+            ("porous_cell_specular_below_2THz_fp32", "porous_cell_spec2thz", 32, 5)]
     # each configuration is tuned on at most 1e6 particles with one timed launch per candidate
     # (the calibration stays outside the timed steps but inside the run's few minutes)
     for key, name, prec, steps in plan:
@@ -440,12 +516,16 @@ def other_forms(args, M, torch) -> dict:
         "workload": wname, "precision": 32, "streams": 2, "steps": 20, "flights_per_s": mf["flights_per_s"],
         "ms_per_step": mf["ms_per_step"], "launch": mf["launch"], "kappa_eff": mf.get("kappa_eff"),
         "kappa_sigma": mf.get("kappa_sigma")}
-    # the pore cell's step ends with the few particles of the longest mean free paths walking
-    # through the lattice, one lane each; a job of several batches overlaps those tails with the
-    # next batches on other streams (four here: 0.22 s per batch, against 0.38 s on two and
-    # 0.19 s on eight; throughput by wall clock, the per-launch event times then include the
-    # overlap, so no roofline figure is given for it)
+    # the same pore cell traced one segment at a time (no pore-to-pore walk by the wave): the
+    # step then waits for the few particles of the longest free paths, one lane each
     w, wname = workload("porous_cell", 1.0)
+    print(f"[bench] form porous_cell_fp32_segments: {wname}", file=sys.stderr, flush=True)
+    seg_args = argparse.Namespace(**dict(vars(args), segments=True))
+    forms["porous_cell_fp32_segments"] = _brief(measure(seg_args, w, M, torch, 32, 4, 1, 1, 1_000_000, 1),
+                                                wname, 32)
+    # a job of several batches overlaps each batch's tail (its last particles) with the next
+    # batches on other streams (throughput by wall clock; the per-launch event times then include
+    # the overlap, so no roofline figure is given for it)
     print(f"[bench] form porous_cell_fp32_four_streams: {wname}", file=sys.stderr, flush=True)
     m2 = measure(args, w, M, torch, 32, 8, 2, 4, 1_000_000, 1)
     forms["porous_cell_fp32_four_streams"] = {
@@ -457,7 +537,7 @@ def other_forms(args, M, torch) -> dict:
     forms["batched_sweep_fp32"] = _brief(measure_batched(args, ws, M, torch, 32, 3, 1, 8_000_000, 1), wname, 32)
     w, wname = workload("porous_cell", 1.0)
     print(f"[bench] form sensitivities: {wname}", file=sys.stderr, flush=True)
-    sens = measure_sensitivity(args, w, M, torch, ("score", "local"), 2)
+    sens = measure_sensitivity(args, w, M, torch, ("score", "local"), 5)
     sens["workload"] = wname
     forms["porous_cell_sensitivities_fp32"] = sens
     return forms

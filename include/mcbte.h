@@ -209,7 +209,19 @@ typedef struct {
     double* particle_F;   /* device pointer, n doubles, or NULL: mcbte_trace writes each particle's
                              flux score F (sum of s l Omega_score over its segments) at index
                              pid - first_pid, the input of mcbte_adjoint                     */
+    int32_t flags;        /* MCBTE_RUN_* bits (0: defaults)                                 */
+    int32_t reserved;     /* must be 0                                                      */
 } mcbte_run;
+
+/* mcbte_run.flags.  MCBTE_RUN_SEGMENTS: trace a periodic pore lattice one segment at a time in the
+   FP32 form too.  By default an FP32 steady trace of a cell that is periodic in x and y (periodic or
+   unbounded in z) with one pore and no line walls follows a particle with a long free path from pore
+   to pore with its whole wave, in the lattice's unfolded coordinates (a transfer through a periodic
+   face reinserts the particle unchanged at the partner face, Eq. periodic_lin_final, which is flying
+   on through the lattice): the same events and counts, the FP32 positions rounded differently.  The
+   FP64 form always steps one segment at a time (its event sequences are the oracle's).  A sensitivity
+   replay must use the flags of the forward trace that wrote particle_F. */
+#define MCBTE_RUN_SEGMENTS 1
 
 /* Finalized results (mcbte_tally). */
 typedef struct {
@@ -349,7 +361,9 @@ int mcbte_autotune(const mcbte_tables* const* tables, int32_t n_inst, const int6
    adj[n_bins] the relaxation-draw sum B, adj[n_bins + 1] the count of terms left out as not
    finite, adj[n_bins + 2] library scratch.  Async on `stream`.  Errors: MCBTE_EINVAL (transient run, event log set, unknown
    estimator, n_scat_max outside the pathwise range, tables with a two-phonon clock, a specular
-   cutoff frequency or internal line walls), MCBTE_ENODEV, MCBTE_EHIP. */
+   cutoff frequency or internal line walls, the pathwise estimator in the FP32 form on a pore lattice
+   without MCBTE_RUN_SEGMENTS: the replay follows the forward trace segment by segment and the
+   pathwise tangents are carried through every transfer), MCBTE_ENODEV, MCBTE_EHIP. */
 int mcbte_adjoint(const mcbte_tables* tables, const mcbte_run* run, int32_t estimator, double lambda_split,
                   int64_t first_pid, int64_t n, const double* particle_F, double* adj, void* stream);
 

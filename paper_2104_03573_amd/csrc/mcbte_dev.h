@@ -23,7 +23,9 @@ enum TallyKind : int32_t { TALLY_STEADY_ONE = 0, TALLY_STEADY_GRID = 1, TALLY_TR
 // being read from global memory instead, and (FP64 film-like problems) the exact cooperative
 // bouncing, whose registers the other FP64 problems need not reserve
 // FT_PLAIN: no table uses the two-phonon clock or a specular cutoff frequency (kernels without that code)
-enum : int { FT_STATE = 1, FT_LOG = 2, FT_WIDE = 4, FT_COOP = 8, FT_PLAIN = 16 };
+// FT_LATTICE: (FP32 steady trace of a cell periodic in x and y, one pore, no line walls) a particle
+// with a long free path is followed from pore to pore by its whole wave (lattice_walk)
+enum : int { FT_STATE = 1, FT_LOG = 2, FT_WIDE = 4, FT_COOP = 8, FT_PLAIN = 16, FT_LATTICE = 32 };
 
 // Geometry in the form the flight loop reads it (uniform across a launch; scalar loads).
 struct DevPore32 { float cx, cy, r; int32_t id; };
@@ -99,6 +101,8 @@ struct DevTab {
     int32_t tally_kind;          // TallyKind
     int32_t coop_axis;           // film axis for wave-cooperative diffuse bouncing (FP32), -1: off
     double coop_min_path;        // remaining free path (m) above which a wall bounce turns cooperative
+    double lat_min_path;         // pore lattice: remaining free path (m) above which the wave walks the
+                                 // particle from pore to pore (0: the geometry is not such a lattice)
     int64_t max_events;
     double t_max;
     int64_t last_ic, last_wall, last_rel, last_src;
@@ -125,7 +129,7 @@ struct DevTab {
     int32_t n_bins;
     int32_t two;                 // some row has a two-phonon clock
     int32_t spec_w;              // some boundary has a specular cutoff frequency
-    int32_t pad3;
+    int32_t lattice;             // the cell tiles a lattice of pores (lat_min_path > 0)
     DevGeom g;
     DevDet det;
 };

@@ -417,6 +417,26 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
             }
         }
     }
+    // a lattice of pores: x and y periodic, z periodic or unbounded, one pore lying inside the cell,
+    // no line walls, steady, one detector cell.  A free path of more than 64 cell widths ahead is
+    // walked from pore to pore by the wave in the FP32 form (long enough that the wave's work on one
+    // particle pays; the shorter ones leave the wave to its other lanes)
+    h.lattice = 0;
+    h.lat_min_path = 0.0;
+    {
+        bool per = g.n_pores == 1 && g.n_walls == 0 && !pr.transient && h.tally_kind == TALLY_STEADY_ONE &&
+                   !g.unbounded[0] && !g.unbounded[1];
+        for (int i = 0; i < 6 && per; ++i)
+            if (!g.unbounded[kFaceAxis[i]] && g.face[i].type != MCBTE_PERIODIC) per = false;
+        if (per) {
+            const mcbte_pore& q = g.pore[0];
+            per = q.cx - q.r > 0.0 && q.cx + q.r < g.L[0] && q.cy - q.r > 0.0 && q.cy + q.r < g.L[1];
+        }
+        if (per) {
+            h.lattice = 1;
+            h.lat_min_path = 64.0 * std::max(g.L[0], g.L[1]);
+        }
+    }
     h.max_events = pr.max_events;
     h.n_bins = n_bins;
     h.two = t->two ? 1 : 0;
@@ -739,6 +759,7 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
 {
     if (!t || !run || !tally || n < 0 || first_pid < 0) return MCBTE_EINVAL;
     if (run->precision != 32 && run->precision != 64) return MCBTE_EINVAL;
+    if ((run->flags & ~MCBTE_RUN_SEGMENTS) != 0 || run->reserved != 0) return MCBTE_EINVAL;
     if (run->event_log && (run->log_stride < 2 || run->n_log < 0)) return MCBTE_EINVAL;
     if (t->device < 0 || !t->d_tab) return MCBTE_ENODEV;
     if (n == 0) return MCBTE_OK;
@@ -758,6 +779,10 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     // FP64 film-like problems: the kernel with the exact cooperative bouncing
     if (run->precision == 64 && t->host_view.coop_axis >= 0) ft |= FT_COOP;
     if (!t->two && !t->spec_w && !t->walls) ft |= FT_PLAIN;   // the kernel without the extended physics
+    // FP32 pore lattices: long free paths walked from pore to pore by the wave
+    if (run->precision == 32 && t->host_view.lattice && !(ft & (FT_STATE | FT_LOG | FT_WIDE)) &&
+        !(run->flags & MCBTE_RUN_SEGMENTS))
+        ft |= FT_LATTICE;
     const int rc = plan_launch(&t, 1, run, 0, ft, lp);
     if (rc != MCBTE_OK) return rc;
     LaunchArgs a;
@@ -799,6 +824,7 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
 {
     if (!ts || n_inst < 1 || !n_particles || !instance_ids || !tallies || !run || !queue) return MCBTE_EINVAL;
     if (run->precision != 32 && run->precision != 64) return MCBTE_EINVAL;
+    if ((run->flags & ~MCBTE_RUN_SEGMENTS) != 0 || run->reserved != 0) return MCBTE_EINVAL;
     if (run->event_log) return MCBTE_EINVAL;
     const mcbte_tables* t0 = ts[0];
     if (!t0 || t0->device < 0) return MCBTE_ENODEV;
@@ -947,6 +973,7 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
 {
     if (!t || !run || !particle_F || !adj || n < 0 || first_pid < 0) return MCBTE_EINVAL;
     if (run->precision != 32 && run->precision != 64) return MCBTE_EINVAL;
+    if ((run->flags & ~MCBTE_RUN_SEGMENTS) != 0 || run->reserved != 0) return MCBTE_EINVAL;
     if (run->event_log) return MCBTE_EINVAL;
     if (estimator != MCBTE_SENS_SCORE && estimator != MCBTE_SENS_PATHWISE && estimator != MCBTE_SENS_LOCAL)
         return MCBTE_EINVAL;
@@ -961,8 +988,12 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
     DeviceGuard g(t->device);
     if (!g.ok) return MCBTE_EHIP;
     const int mode = estimator == MCBTE_SENS_PATHWISE ? 3 : (estimator == MCBTE_SENS_LOCAL ? 4 : 2);
-    // FP64 film-like problems replay with the exact cooperative bouncing, as they trace
-    const int ft = ((run->precision == 64 && t->host_view.coop_axis >= 0) ? FT_COOP : 0) | FT_PLAIN;
+    // FP64 film-like problems replay with the exact cooperative bouncing, as they trace; FP32 pore
+    // lattices with the pore-to-pore walk, as they trace (the pathwise tangents need every segment)
+    const bool lat = run->precision == 32 && t->host_view.lattice && !(run->flags & MCBTE_RUN_SEGMENTS);
+    if (lat && mode == 3) return MCBTE_EINVAL;
+    const int ft = ((run->precision == 64 && t->host_view.coop_axis >= 0) ? FT_COOP : 0) | FT_PLAIN |
+                   (lat ? FT_LATTICE : 0);
     LaunchPlan lp;
     const int rc = plan_launch(&t, 1, run, mode, ft, lp);
     if (rc != MCBTE_OK) return rc;

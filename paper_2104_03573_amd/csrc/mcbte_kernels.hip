@@ -186,6 +186,7 @@ template <typename R> struct Part {
                          // bit set means the next scattering is the two-phonon one
     int32_t m, s, nrel;  // mode row, sign, three-phonon relaxations so far
     uint32_t k, j;       // segments so far, random-number-drawing events so far
+    uint32_t kc;         // pore lattice: k after the last wave walk (no new walk before a segment)
     int32_t src;         // source element (event log only)
     double cT, cq;       // per-particle contributions (variance estimate); cq is the flux score F
     R dtr0;              // free-flight time drawn for the current flight (sensitivity replay)
@@ -734,6 +735,7 @@ struct Hot {
     R L[3];
     R t_max;
     R coop_min;          // remaining free path above which a film-wall bounce turns cooperative
+    R lat_min;           // pore lattice: remaining free path above which the wave walks the particle
     uint32_t unb;        // bit a: axis a has no faces
     uint32_t face;       // 4 bits per face id - 1: type | class << 2
     uint32_t pcls;       // 2 bits per pore: class
@@ -754,6 +756,7 @@ __device__ __forceinline__ Hot<R> load_hot(const DevTab& T)
     for (int a = 0; a < 3; ++a) h.L[a] = Geo<R>::L(g, a);
     h.t_max = (R)T.t_max;
     h.coop_min = (R)T.coop_min_path;
+    h.lat_min = (R)T.lat_min_path;
     h.unb = g.unb_mask;
     h.face = g.face_code[Geo<R>::prec];
     h.pcls = g.pore_cls[Geo<R>::prec];
@@ -1215,6 +1218,18 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     // the extended physics (two-phonon clock, specular cutoff frequencies) is compiled in
     constexpr bool EXT = (FT & FT_PLAIN) == 0;
     if (EXT && T.two) resolve_clocks<R>(T, st, p);
+    if constexpr ((FT & FT_LATTICE) != 0) {
+        // pore lattice: a long free path ahead is walked from pore to pore by the whole wave
+        // (lattice_walk), unless the last walk left the particle where it is
+        if (p.kc != p.k && vm * p.dtr > H.lat_min) {
+            uint32_t pc0 = H.pcls & 3u;
+            if (EXT && T.spec_w && g.pore_wc[0] > 0.0 && T.omega64[p.m] < g.pore_wc[0]) pc0 = SURF_SPECULAR;
+            if (pc0 != SURF_PARTIAL) {
+                coop = true;
+                return false;
+            }
+        }
+    }
     if constexpr (TK == TALLY_STEADY_ONE && AK != 2 && (FT & FT_LOG) == 0) {
         if (chain && !(EXT && g.n_walls > 0)) {   // (the lone-lane walk knows faces and pores)
             uint32_t pc0 = H.pcls & 3u;      // the first pore's reflection class for this phonon
@@ -1885,6 +1900,283 @@ __device__ __forceinline__ void coop_exact(const Hot<double>& H, const Tabs<doub
 }
 
 // ------------------------------------------------------------------------------------------
+// wave-cooperative walk through a periodic lattice of pores (FP32 form)
+// ------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ float lane_f(float v, int k)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+// A cell periodic in x and y (periodic or without faces in z) holding one z-axis pore tiles an
+// infinite square lattice of pores, and a transfer through a periodic face -- the particle
+// reinserted unchanged at the partner face (Eq. periodic_lin_final) -- is the same as flying on
+// through that lattice.  The particle of lane `leader`, with a free path of many cells ahead, is
+// followed by the whole wave from pore to pore in these unfolded coordinates:
+//   - the lanes test the pores of the next 32 lattice columns along the ray, two rows per column
+//     (along the axis the ray moves fastest on, one column spans at most two rows), and a ballot
+//     finds the first column with a pore met before the free path runs out; a pore lies inside
+//     its cell, so the order of the columns is the order along the ray;
+//   - a pore's discriminant is taken in Lagrange's form, qa r^2 - (dP x o)^2 (dP the pore's offset,
+//     o the direction, in the x-y plane), so that a pore 32 cells away is decided from the cross
+//     product's rounding rather than from a difference of squares of its distance;
+//   - the transfers on the way are the cell boundaries crossed, counted per axis;
+//   - the reflection uses the unit normal at the hit point (the hit point's offset from the axis,
+//     normalized) and, for a diffuse one, the record the one-segment step would draw; the
+//     records are drawn 64 at a time, one per lane (the polar and azimuthal cosines do not depend
+//     on the hit point), and turned into the direction in the cylinder's frame (n, e_z x n, e_z);
+//   - the walked segments' scores are the summed length and displacement (one mode, one sign);
+//   - once the free path ends before the next pore, the particle is placed at its last face
+//     crossing and the one-segment step makes the final segment.
+// The events and their counts are the one-segment stepping's; positions and directions differ by
+// rounding (a hit point is computed from its pore's centre instead of through the transfers before
+// it, and the frame about the normal is written out for the cylinder).
+template <int FT>
+__device__ void lattice_walk(const DevTab& T, const Hot<float>& H, const Tabs<float>& tb, const TallyCtx& tc,
+                             Part<float>& p, const Stream& st_own, int leader, LaneCounts& cnt)
+{
+    constexpr bool EXT = (FT & FT_PLAIN) == 0;
+    const int lane = threadIdx.x & 63;
+    leader = __builtin_amdgcn_readfirstlane(leader);
+    const int m = __builtin_amdgcn_readlane(p.m, leader);
+    const float sg = (float)__builtin_amdgcn_readlane(p.s, leader);
+    const Stream st{(uint32_t)__builtin_amdgcn_readlane((int)st_own.k0, leader),
+                    (uint32_t)__builtin_amdgcn_readlane((int)st_own.k1, leader),
+                    (uint32_t)__builtin_amdgcn_readlane((int)st_own.plo, leader),
+                    (uint32_t)__builtin_amdgcn_readlane((int)st_own.phi, leader),
+                    (uint32_t)__builtin_amdgcn_readlane((int)st_own.inst, leader)};
+    float x0 = lane_f(p.x[0], leader), x1 = lane_f(p.x[1], leader), x2 = lane_f(p.x[2], leader);
+    float o0 = lane_f(p.o[0], leader), o1 = lane_f(p.o[1], leader), o2 = lane_f(p.o[2], leader);
+    float dtr = lane_f(p.dtr, leader), t = lane_f(p.t, leader);
+    uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)p.k, leader);
+    uint32_t j = (uint32_t)__builtin_amdgcn_readlane((int)p.j, leader);
+    const float vm = tb.v[m];
+    // the phonon's reflection class at the pore (diffuse or specular; partly specular pores are not walked)
+    uint32_t cls = H.pcls & 3u;
+    if (EXT && T.spec_w && T.g.pore_wc[0] > 0.0 && T.omega64[m] < T.g.pore_wc[0]) cls = SURF_SPECULAR;
+    const float Wx = H.L[0], Wy = H.L[1], Wz = H.L[2];
+    const bool zper = ((H.unb >> 2) & 1u) == 0u;
+    const float cx = H.p0cx, cy = H.p0cy, rr = H.p0r;
+    const float iWx = r_div(1.0f, Wx), iWy = r_div(1.0f, Wy), iWz = r_div(1.0f, Wz);
+    const uint32_t kmax = (uint32_t)H.max_events;
+    const int sa = H.score_axis;
+    // scores of the walked segments (one mode, one sign): the summed length and the summed
+    // displacement, in FP64 (s l / v and s l Omega_a follow at the end)
+    double aL = 0.0, aQ0 = 0.0, aQ1 = 0.0, aQ2 = 0.0;
+    uint32_t nf = 0, np = 0, nd = 0, ns = 0;   // segments, periodic transfers, diffuse, specular
+    // a straight piece of length l along the current direction: clocks and scores
+    auto advance_time = [&](float l) {
+        const float dt = r_div(l, vm);
+        t = t + dt;
+        const float rem = dtr - dt;
+        dtr = rem > 0.0f ? rem : 0.0f;
+        aL += (double)l;
+        aQ0 += (double)(l * o0);
+        aQ1 += (double)(l * o1);
+        aQ2 += (double)(l * o2);
+    };
+    // this lane's pre-drawn diffuse reflection: (mu, sin theta cos phi, sin theta sin phi) of
+    // record 2 + jb + 1 + lane, jb the draws made before the batch
+    float dmu = 0.0f, dca = 0.0f, dcb = 0.0f;
+    uint32_t used = 64;
+    const int col = lane & 31;
+    const bool hi_row = lane >= 32;
+    const float cWx = (float)col * Wx, cWy = (float)col * Wy;   // this lane's column offset, per axis
+    const float r2 = rr * rr;
+    bool finish = true;          // false: stopped ahead of the segment cap (left to the one-segment step)
+    for (int guard = 0; guard < (1 << 24); ++guard) {
+        const float D = vm * dtr;
+        // the segment cap: one step below crosses at most 32 columns, 33 rows and the z cells
+        // within the free path; closer to the cap the one-segment step goes on (and ends it there)
+        const float zcap = zper ? fminf(D * fabsf(o2) * iWz, 1.0e9f) : 0.0f;
+        if (!__builtin_amdgcn_readfirstlane((int)((double)k + 67.0 + (double)zcap <= (double)kmax))) {
+            finish = false;
+            break;
+        }
+        const float ax = fabsf(o0), ay = fabsf(o1);
+        if (!__builtin_amdgcn_readfirstlane((int)(ax > 0.0f || ay > 0.0f))) break;   // along z: no pore ahead
+        const bool xm = __builtin_amdgcn_readfirstlane((int)(ax >= ay)) != 0;
+        const float oM = xm ? o0 : o1, om = xm ? o1 : o0;
+        const float pM = xm ? x0 : x1, pm = xm ? x1 : x0;
+        const float WM = xm ? Wx : Wy, Wm = xm ? Wy : Wx, iWm = xm ? iWy : iWx;
+        const float cM = xm ? cx : cy, cm = xm ? cy : cx;
+        const float aM = xm ? ax : ay;
+        const bool up = oM > 0.0f;
+        const float qa = oM * oM + om * om;
+        const float iqa = r_div(1.0f, qa), qar2 = qa * r2;
+        // distance along the column axis to the column boundary ahead, then column `col`'s range
+        const float e0 = up ? WM - pM : pM;
+        const float tmin = r_div(om, aM);            // minor displacement per unit of column-axis travel
+        const float cW = xm ? cWx : cWy;
+        const float ua = col == 0 ? 0.0f : e0 + (cW - WM);
+        const float ub = e0 + cW;
+        const float ya = pm + ua * tmin, yb = pm + ub * tmin;
+        const float rlo = floorf((ya < yb ? ya : yb) * iWm), rhi = floorf((ya < yb ? yb : ya) * iWm);
+        const float row = hi_row ? rhi : rlo;
+        // the pore of that column and row relative to the particle, and the ray's entry into it:
+        // the discriminant in Lagrange's form qa r^2 - (dP x o)^2, which keeps the precision of the
+        // cross product for a distant pore (no difference of squares of the distance)
+        const float dM = pM - ((up ? cW : -cW) + cM);
+        const float dm = pm - (row * Wm + cm);
+        const float qb = dM * oM + dm * om;
+        const float cr = dM * om - dm * oM;
+        const float disc = qar2 - cr * cr;
+        const float dd = (-qb - r_sqrt(disc > 0.0f ? disc : 0.0f)) * iqa;
+        const float d = dd > 0.0f ? dd : 0.0f;
+        const unsigned long long bal = __ballot((qb < 0.0f) & (disc >= 0.0f) & !(hi_row & (rhi == rlo)) & (d <= D));
+        const uint32_t cols = (uint32_t)bal | (uint32_t)(bal >> 32);
+        if (cols == 0u) {
+            // no pore met in the 32 columns: the free path ends in them, or the walk moves on to the
+            // entry of the next column (32 column boundaries crossed, the last on a face as after a
+            // transfer)
+            const float u = e0 + 31.0f * WM;
+            if (!__builtin_amdgcn_readfirstlane((int)(D * aM > u))) break;   // the free path ends first
+            const float s = r_div(u, aM);
+            const float ym = pm + u * tmin;
+            const float km = floorf(ym * iWm);
+            float z = x2 + s * o2, kz = 0.0f;
+            if (zper) kz = floorf(z * iWz);
+            const uint32_t nx = 32u + (uint32_t)fabsf(km) + (uint32_t)fabsf(kz);
+            advance_time(s);
+            const float pm2 = ym - km * Wm;
+            const float pM2 = up ? 0.0f : WM;
+            if (zper) z = z - kz * Wz;
+            x0 = xm ? pM2 : pm2;
+            x1 = xm ? pm2 : pM2;
+            x2 = zper ? (z < 0.0f ? 0.0f : (z > Wz ? Wz : z)) : z;
+            k += nx;
+            nf += nx;
+            np += nx;
+            continue;
+        }
+        // the first column with a pore met; of its two rows, the nearer
+        const int kc = __builtin_ctz(cols);
+        const bool v0 = ((bal >> kc) & 1ull) != 0ull, v1 = ((bal >> (kc + 32)) & 1ull) != 0ull;
+        const float d0 = lane_f(d, kc), d1 = lane_f(d, kc + 32);
+        const bool pick1 = v1 && (!v0 || d1 < d0);
+        const int wl = pick1 ? kc + 32 : kc;
+        const float dh = pick1 ? d1 : d0;
+        const float rowh = lane_f(row, wl);
+        // hit point relative to the pore's centre, and the cells crossed on the way
+        const float relM = lane_f(dM, wl) + dh * oM, relm = lane_f(dm, wl) + dh * om;
+        float z = x2 + dh * o2, kz = 0.0f;
+        if (zper) kz = floorf(z * iWz);
+        const uint32_t nx = (uint32_t)kc + (uint32_t)fabsf(rowh) + (uint32_t)fabsf(kz);
+        advance_time(dh);
+        if (zper) z = z - kz * Wz;
+        const float rx = xm ? relM : relm, ry = xm ? relm : relM;
+        x0 = cx + rx;
+        x1 = cy + ry;
+        x2 = zper ? (z < 0.0f ? 0.0f : (z > Wz ? Wz : z)) : z;
+        k += nx + 1u;
+        nf += nx + 1u;
+        np += nx;
+        // the reflection off the pore about the unit normal at the hit point
+        const float inv = __builtin_amdgcn_rsqf(rx * rx + ry * ry);
+        const float n0 = rx * inv, n1 = ry * inv;
+        if (cls == SURF_DIFFUSE) {
+            if (used == 64u) {
+                const W4 w1 = st.block(2u * (2u + j + 1u + (uint32_t)lane) + 1u);
+                const float u1 = unif<float>(w1.x, w1.y), u2 = unif<float>(w1.z, w1.w);
+                dmu = r_sqrt(u1);
+                const float sth = r_sqrt(1.0f - u1);
+                float sn, cs;
+                r_sincos_2pi(u2, &sn, &cs);
+                dca = sth * cs;
+                dcb = sth * sn;
+                used = 0u;
+            }
+            const float mu = lane_f(dmu, (int)used), ca = lane_f(dca, (int)used), cb = lane_f(dcb, (int)used);
+            ++used;
+            j += 1u;
+            // cosine-weighted about n (Eq. wall_dir) in the frame (n, e_z x n, e_z)
+            o0 = mu * n0 - ca * n1;
+            o1 = mu * n1 + ca * n0;
+            o2 = cb;
+            ++nd;
+        } else {                                     // Eq. specular: k' = k - 2 (k.n) n
+            const float k2 = 2.0f * (o0 * n0 + o1 * n1);
+            o0 = o0 - k2 * n0;
+            o1 = o1 - k2 * n1;
+            ++ns;
+        }
+    }
+    if (finish) {
+        // the free path ends before the next pore: the face crossings ahead within it, per axis
+        // (distance to the first face g, then one per cell width), and the particle placed at the
+        // last of them, on the partner face
+        const double D = (double)(vm * dtr);
+        const double xs[3] = {x0, x1, x2}, os[3] = {o0, o1, o2}, Ws[3] = {Wx, Wy, Wz};
+        double s_last = 0.0;
+        int a_last = -1;
+        uint32_t ncr[3] = {0u, 0u, 0u};
+        for (int a = 0; a < 3; ++a) {
+            if ((a == 2 && !zper) || os[a] == 0.0) continue;
+            const double ao = fabs(os[a]);
+            const double g = os[a] > 0.0 ? Ws[a] - xs[a] : xs[a];
+            const double La = D * ao;
+            if (!(La >= g)) continue;
+            const double n = floor((La - g) / Ws[a]) + 1.0;
+            ncr[a] = (uint32_t)n;
+            const double sa_ = (g + (n - 1.0) * Ws[a]) / ao;
+            if (sa_ > s_last || a_last < 0) {
+                s_last = sa_;
+                a_last = a;
+            }
+        }
+        const uint32_t nx = ncr[0] + ncr[1] + ncr[2];
+        if (nx > 0u && k + nx <= kmax) {
+            const float s = (float)s_last;
+            double xn[3];
+            for (int a = 0; a < 3; ++a) {
+                xn[a] = xs[a] + s_last * os[a];
+                if (a == 2 && !zper) continue;
+                xn[a] = xn[a] - (os[a] > 0.0 ? (double)ncr[a] : -(double)ncr[a]) * Ws[a];
+                if (a == a_last) xn[a] = os[a] > 0.0 ? 0.0 : Ws[a];     // reinserted at the partner face
+                xn[a] = xn[a] < 0.0 ? 0.0 : (xn[a] > Ws[a] ? Ws[a] : xn[a]);
+            }
+            advance_time(s);
+            x0 = (float)xn[0];
+            x1 = (float)xn[1];
+            x2 = (float)xn[2];
+            k += nx;
+            nf += nx;
+            np += nx;
+        }
+    }
+    const double aT = (double)sg * aL / (double)vm;
+    aQ0 *= (double)sg;
+    aQ1 *= (double)sg;
+    aQ2 *= (double)sg;
+    const double aF = sa == 0 ? aQ0 : (sa == 1 ? aQ1 : aQ2);
+    if (lane == leader) {
+        if (nf > 0u) {
+            if (H.det_mask & 1) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)m, 0, aT);
+            if (H.det_mask & 2) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)m, 1, aQ0);
+            if (H.det_mask & 4) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)m, 2, aQ1);
+            if (H.det_mask & 8) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)m, 3, aQ2);
+        }
+        p.cT += aT;
+        p.cq += aF;
+        p.x[0] = x0;
+        p.x[1] = x1;
+        p.x[2] = x2;
+        p.o[0] = o0;
+        p.o[1] = o1;
+        p.o[2] = o2;
+        p.t = t;
+        p.dtr = dtr;
+        p.k = k;
+        p.j = j;
+        p.kc = k;
+        cnt.c[1] += nf;
+        cnt.c[3] += ns;
+        cnt.c[4] += nd;
+        cnt.c[5] += np;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // particle state buffer (structure of arrays)
 // ------------------------------------------------------------------------------------------
 
@@ -2025,6 +2317,7 @@ __device__ __forceinline__ void start_particle(const DevTab& T, const LaunchArgs
     else emit_particle<R>(T, st, p, rej);
     p.tk = -1;
     p.sn = 0;
+    p.kc = 0xFFFFFFFFu;
     cnt.c[0] += 1;
     cnt.c[11] += rej;
     lg.row = nullptr;
@@ -2149,7 +2442,9 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
         }
         if constexpr (TK == TALLY_STEADY_ONE) {
             for (unsigned long long pend = __ballot(coop); pend; pend &= pend - 1ull) {
-                if constexpr (std::is_same<R, float>::value)
+                if constexpr ((FT & FT_LATTICE) != 0 && std::is_same<R, float>::value)
+                    lattice_walk<FT>(T, H, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
+                else if constexpr (std::is_same<R, float>::value)
                     coop_bounces<R>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
                 else if constexpr ((FT & FT_COOP) != 0)
                     coop_exact(H, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt, lg);
@@ -2347,7 +2642,9 @@ static void ensure_lds_limit(const void* fn, size_t lds)
 // the kernel of a launch: mode 0 trace, 1 batched trace, 2 likelihood-ratio replay, 3 pathwise
 // replay, 4 local pathwise replay; ft the optional features (FT_STATE | FT_LOG: a state buffer and/or an event log;
 // FT_WIDE: FP32 trace with the tally in LDS in FP32; FT_PLAIN: no table has a two-phonon clock or a
-// specular cutoff, the kernels without that code).  The replays refuse such tables and are built without it.
+// specular cutoff, the kernels without that code; FT_LATTICE: FP32 steady trace or likelihood-ratio /
+// local replay of a pore lattice, walked pore to pore by the wave).  The replays refuse tables with the
+// extended physics and are built without it.  NULL: no such kernel.
 template <typename R, int TK, int PLAIN>
 static const void* pick_solo(int mode, int ft)
 {
@@ -2358,6 +2655,14 @@ static const void* pick_solo(int mode, int ft)
             if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, FT_COOP | FT_PLAIN>;
             if (ft & (FT_STATE | FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | FT_LOG | FT_COOP | PLAIN>;
             return (const void*)k_trace_solo<R, TK, 0, FT_COOP | PLAIN>;
+        }
+    }
+    if constexpr (std::is_same<R, float>::value && TK == TALLY_STEADY_ONE) {
+        if (ft & FT_LATTICE) {   // (never with a state buffer or an event log)
+            if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, FT_LATTICE | FT_PLAIN>;
+            if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, FT_LATTICE | FT_PLAIN>;
+            if (mode == 0) return (const void*)k_trace_solo<R, TK, 0, FT_LATTICE | PLAIN>;
+            return nullptr;
         }
     }
     if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, FT_PLAIN>;
@@ -2398,6 +2703,7 @@ hipError_t launch_trace(const LaunchArgs& a, int mode, int precision, int tally_
                         size_t lds, hipStream_t s)
 {
     const void* fn = kernel_for(mode, precision, tally_kind, ft);
+    if (!fn) return hipErrorInvalidDeviceFunction;
     ensure_lds_limit(fn, lds);
     if (mode == 0) {   // the work counter of a solo trace lives in the tally header
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s,
@@ -2421,6 +2727,7 @@ hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s)
 int trace_occupancy(int mode, int precision, int tally_kind, int ft, int block, size_t lds)
 {
     const void* fn = kernel_for(mode, precision, tally_kind, ft);
+    if (!fn) return 1;
     static std::mutex mu;
     static std::map<std::tuple<const void*, int, size_t>, int> cache;
     const auto key = std::make_tuple(fn, block, lds);

@@ -76,7 +76,11 @@ class Info(C.Structure):
 class Run(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("instance", C.c_uint32), ("precision", C.c_int32), ("block", C.c_int32),
                 ("refill", C.c_int32), ("grid", C.c_int32), ("log_stride", C.c_int32), ("n_log", C.c_int64),
-                ("event_log", C.c_void_p), ("particle_F", C.c_void_p)]
+                ("event_log", C.c_void_p), ("particle_F", C.c_void_p), ("flags", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+RUN_SEGMENTS = 1
 
 
 class Result(C.Structure):
@@ -244,11 +248,13 @@ def state_bytes(precision: int, capacity: int) -> int:
 
 
 def make_run(seed: int, precision: int = 32, instance: int = 0, block: int = 0, refill: int = 0, grid: int = 0,
-             event_log=None, n_log: int = 0, log_stride: int = 64, particle_F=None) -> Run:
+             event_log=None, n_log: int = 0, log_stride: int = 64, particle_F=None, segments: bool = False) -> Run:
+    """segments=True sets MCBTE_RUN_SEGMENTS (FP32 pore lattices traced one segment at a time)."""
     return Run(seed & 0xFFFFFFFFFFFFFFFF, instance, precision, block, refill, grid, log_stride,
                n_log if event_log is not None else 0,
                C.c_void_p(event_log.data_ptr()) if event_log is not None else None,
-               C.c_void_p(particle_F.data_ptr()) if particle_F is not None else None)
+               C.c_void_p(particle_F.data_ptr()) if particle_F is not None else None,
+               RUN_SEGMENTS if segments else 0, 0)
 
 
 def emit(t: "Tables", run: Run, first_pid: int, n: int, state, capacity: int, stream=None):
@@ -304,7 +310,8 @@ def autotune(tables: list, n_particles, instance_ids, tallies: list, queue, base
     return out, np.array(tim[:])
 
 
-def tune(w, precision: int = 32, n_probe: int = 1 << 18, reps: int = 3, tables=None, device: int = 0) -> dict:
+def tune(w, precision: int = 32, n_probe: int = 1 << 18, reps: int = 3, tables=None, device: int = 0,
+         segments: bool = False) -> dict:
     """Autotune the launch shape for a workload (dict) or a sweep (list of dicts, batched form)."""
     import torch
     ws = w if isinstance(w, list) else [w]
@@ -313,7 +320,7 @@ def tune(w, precision: int = 32, n_probe: int = 1 << 18, reps: int = 3, tables=N
     tallies = [t.new_tally() for t in tabs]
     queue = (torch.zeros(batch_queue_bytes(len(ws)), dtype=torch.uint8, device=f"cuda:{device}")
              if len(ws) > 1 else None)
-    base = make_run(int(ws[0]["seed"]), precision)
+    base = make_run(int(ws[0]["seed"]), precision, segments=segments)
     run_, tim = autotune(tabs, [x["problem"]["N"] for x in ws], [int(x.get("instance", 0)) for x in ws], tallies,
                          queue, base, n_probe, reps)
     return {"block": run_.block, "refill": run_.refill, "timings_ms": tim, "tables": tabs}
@@ -430,6 +437,9 @@ def sensitivities(w: dict, n: int | None = None, first_pid: int = 0, precision: 
     dev = f"cuda:{device}"
     F = torch.zeros(n, dtype=torch.float64, device=dev)
     tl = t.new_tally()
+    if estimator == "pathwise":
+        # the pathwise replay carries its tangents through every transfer of the forward trace
+        launch.setdefault("segments", True)
     r = make_run(int(w["seed"]), precision, int(w.get("instance", 0)), particle_F=F, **launch)
     trace(t, r, first_pid, n, None, tl)
     adj = torch.zeros(t.info["adj_doubles"], dtype=torch.float64, device=dev)
