@@ -284,8 +284,11 @@ int mcbte_emit(const mcbte_tables* tables, const mcbte_run* run, int64_t first_p
    tallies: Eq. sampling (transient) or Eqs. temp_steady / flux_x_steady (steady).  Async on
    `stream`.  Errors: MCBTE_EINVAL, MCBTE_ENODEV, MCBTE_EHIP.
    Tally buffer layout (bytes): [0,128) counts uint64[16]; [128,160) moments double[4];
-   [192,200) library work counter; [256, ...) raw sums double[n_cells][n_cols][4] with
-   components (sum s l / v | sum s, sum s l Omega_x | sum s v Omega_x, ... y, ... z).
+   [192,256) library scratch (work counters); [256, ...) raw sums double[n_cells][n_cols][4] with
+   components (sum s l / v | sum s, sum s l Omega_x | sum s v Omega_x, ... y, ... z); for a pore
+   lattice (see MCBTE_RUN_SEGMENTS) the FP32 trace also keeps, after the raw sums, a list of the
+   particles whose first free flight exceeds 1000 cell widths, which it starts before the others
+   (an order that changes no result; more than 4096 of them and it takes every particle in order).
    Event log rows (if run->event_log): word 0 = number of entries, then entries
    (type << 28) | (min(boundary id or source index, 255) << 20) | mode, types 0 emit (sign +),
    9 emit (sign -), 1 relaxation (new mode), 2 specular, 3 diffuse, 4 periodic, 5 absorbed,

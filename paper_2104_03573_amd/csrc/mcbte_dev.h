@@ -10,6 +10,12 @@
 #define MCBTE_LDS_GUIDE_BYTES 1024           // guide of the relaxation draw (256 packed bounds)
 #define MCBTE_TALLY_HEADER_BYTES 256
 #define MCBTE_TALLY_COUNTER_OFFSET 192
+// pore lattices: particles whose first free path is long enough to be walked for a while are
+// listed before the trace and started first; the list's length and the next entry to take live in
+// the tally header, the list after the raw sums
+#define MCBTE_TALLY_PRIO_COUNT_OFFSET 200
+#define MCBTE_TALLY_PRIO_NEXT_OFFSET 208
+#define MCBTE_PRIO_CAP 4096
 #define MCBTE_PATH_MAX 16                    // flights per particle the pathwise replay holds
 
 namespace mcbte {
@@ -126,6 +132,9 @@ struct DevTab {
     const double* tau2_64;       // two-phonon relaxation time of each row (0: no such process)
     const float* tau2_32;
     const double* omega64;       // angular frequency of each row
+    const uint64_t* prio_thr;    // pore lattice: a particle is started first when the top 53 bits of its first
+                                 // free-flight key reach prio_thr[mode] (NULL: no such scheduling)
+    int64_t prio_list_off;       // byte offset of the list of those particles in the tally buffer
     int32_t n_bins;
     int32_t two;                 // some row has a two-phonon clock
     int32_t spec_w;              // some boundary has a specular cutoff frequency

@@ -104,6 +104,7 @@ struct mcbte_tables {
     std::vector<uint64_t> thr_ic, thr_wall, thr_rel, thr_src;
     std::vector<int32_t> src_kind, src_ref, src_sign, bin_of;
     std::vector<double> P_bin;   // relaxation probability mass per frequency bin
+    std::vector<uint64_t> prio_thr;   // pore lattice: first-flight keys started first (per mode)
     DevTab host_view{};   // device pointers once uploaded
     void* d_mem = nullptr;
     DevTab* d_tab = nullptr;
@@ -437,6 +438,22 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
             h.lat_min_path = 64.0 * std::max(g.L[0], g.L[1]);
         }
     }
+    // ... and there, particles whose first free path exceeds 1000 cell widths are started first (so
+    // that their walks run beside the rest instead of after it): a particle qualifies when the top
+    // 53 bits of its free-flight key (u = that x 2^-53, flight -lambda ln(1 - u)) reach
+    // floor(2^53 (1 - exp(-P / lambda_m))) + 1 for its mode, an integer test both the list and the
+    // trace make alike
+    if (h.lattice) {
+        const double P = 1000.0 * std::max(g.L[0], g.L[1]);
+        t->prio_thr.assign((size_t)M, (uint64_t)1 << 53);
+        for (int m = 0; m < M; ++m) {
+            const double lam = t->v[(size_t)m] * t->tau[(size_t)m];
+            if (!(lam > 0.0)) continue;
+            const double q = -std::expm1(-P / lam);          // probability mass below the cut
+            if (q < 1.0) t->prio_thr[(size_t)m] = (uint64_t)std::floor(q * 0x1p53) + 1;
+        }
+        t->info.tally_bytes = ((t->info.tally_bytes + 255) & ~int64_t(255)) + 8 * (int64_t)MCBTE_PRIO_CAP;
+    }
     h.max_events = pr.max_events;
     h.n_bins = n_bins;
     h.two = t->two ? 1 : 0;
@@ -594,6 +611,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         add(t->tau2.data(), 8 * (size_t)M);
         add(tau2_32.data(), 4 * (size_t)M);
         add(t->omega.data(), 8 * (size_t)M);
+        add(t->prio_thr.data(), 8 * t->prio_thr.size());
         size_t total = 0;
         std::vector<size_t> off;
         for (auto& p : parts) {
@@ -626,6 +644,8 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         h.tau2_64 = (const double*)dptr(17);
         h.tau2_32 = (const float*)dptr(18);
         h.omega64 = (const double*)dptr(19);
+        h.prio_thr = t->prio_thr.empty() ? nullptr : (const uint64_t*)dptr(20);
+        h.prio_list_off = t->prio_thr.empty() ? 0 : t->info.tally_bytes - 8 * (int64_t)MCBTE_PRIO_CAP;
         parts[0].first = &h;
         for (size_t i = 0; i < parts.size(); ++i) {
             if (parts[i].second == 0) continue;

@@ -312,8 +312,10 @@ __device__ __forceinline__ void resolve_clocks(const DevTab& T, const Stream& st
 // emission (section 3.2)
 // ------------------------------------------------------------------------------------------
 
+// kf (optional): the top 53 bits of the first free flight's key (the scheduling test of pore lattices)
 template <typename R>
-__device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st, Part<R>& p, uint32_t& rejections)
+__device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st, Part<R>& p, uint32_t& rejections,
+                                              uint64_t* kf = nullptr)
 {
     const DevGeom& g = T.g;
     const W4 r0a = st.block(0), r0b = st.block(1), r1a = st.block(2), r1b = st.block(3);
@@ -399,6 +401,7 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
     p.t = (T.transient && kind != SRC_IC) ? unif<R>(r2a.z, r2a.w) * (R)T.t_max : R(0);
     const R tau = Geo<R>::tau(T)[p.m];
     p.dtr = -tau * r_log(R(1) - unif<R>(r0a.z, r0a.w));
+    if (kf) *kf = key64(r0a.z, r0a.w) >> 11;
     p.lead = T.two ? R(NAN) : R(0);     // two clocks: the two-phonon time is still to be drawn
     p.dtr0 = p.dtr;
     p.F0 = 0.0;
@@ -2306,15 +2309,17 @@ __device__ __forceinline__ void flush_lane_stats(unsigned char* tally, const Lan
     }
 }
 
+// returns the emission's rejected position draws; kf as for emit_particle (emitted particles only)
 template <typename R, int TK, int FT>
-__device__ __forceinline__ void start_particle(const DevTab& T, const LaunchArgs& a, int64_t pid, uint32_t inst,
-                                               Part<R>& p, Stream& st, LaneCounts& cnt, LogRow& lg)
+__device__ __forceinline__ uint32_t start_particle(const DevTab& T, const LaunchArgs& a, int64_t pid, uint32_t inst,
+                                                   Part<R>& p, Stream& st, LaneCounts& cnt, LogRow& lg,
+                                                   uint64_t* kf = nullptr)
 {
     st = Stream{(uint32_t)a.seed, (uint32_t)(a.seed >> 32), (uint32_t)(uint64_t)pid, (uint32_t)((uint64_t)pid >> 32),
                 inst};
     uint32_t rej = 0;
     if ((FT & FT_STATE) && a.state) StateView<R>((void*)a.state, a.capacity).load(pid - a.first_pid, p, rej);
-    else emit_particle<R>(T, st, p, rej);
+    else emit_particle<R>(T, st, p, rej, kf);
     p.tk = -1;
     p.sn = 0;
     p.kc = 0xFFFFFFFFu;
@@ -2326,6 +2331,31 @@ __device__ __forceinline__ void start_particle(const DevTab& T, const LaunchArgs
     if ((FT & FT_LOG) && a.event_log && pid - a.first_pid < a.n_log) {
         lg.row = a.event_log + (pid - a.first_pid) * (int64_t)a.log_stride;
         lg.put(p.s > 0 ? EV_EMIT_POS : EV_EMIT_NEG, p.src, p.m);
+    }
+    return rej;
+}
+
+// Pore lattices: the particles whose first free flight passes the scheduling test (emission's
+// source, mode and flight keys, records 0 and 1, against the mode's threshold) are listed, so that
+// the trace starts them first.  Their number goes to the tally header; a list longer than the
+// room for it turns the scheduling off (the trace then takes every particle in order).
+__global__ void __launch_bounds__(256) k_prio_scan(const DevTab* __restrict__ tabs, uint64_t seed, uint32_t inst,
+                                                   int64_t first_pid, int64_t n, unsigned char* tally)
+{
+    const DevTab& T = tabs[0];
+    unsigned long long* count = (unsigned long long*)(tally + MCBTE_TALLY_PRIO_COUNT_OFFSET);
+    int64_t* list = (int64_t*)(tally + T.prio_list_off);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t pid = (uint64_t)(first_pid + i);
+        const Stream st{(uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)pid, (uint32_t)(pid >> 32), inst};
+        const W4 r0a = st.block(0), r1a = st.block(2);
+        const int src = T.S == 1 ? 0 : cdf_pick(T.thr_src, T.S, T.last_src, key64(r0a.x, r0a.y));
+        const int m = T.src_kind[src] == SRC_IC ? cdf_pick(T.thr_ic, T.M, T.last_ic, key64(r1a.x, r1a.y))
+                                                : cdf_pick(T.thr_wall, T.M, T.last_wall, key64(r1a.x, r1a.y));
+        if ((key64(r0a.z, r0a.w) >> 11) >= T.prio_thr[m]) {
+            const unsigned long long k = atomicAdd(count, 1ull);
+            if (k < MCBTE_PRIO_CAP) list[k] = (int64_t)pid;
+        }
     }
 }
 
@@ -2396,40 +2426,75 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
     bool alive = false;
     bool exhausted = false;        // wave-uniform: the particle counter has run past n
     int since_refill = 0;
+    // pore lattices: the listed particles (long first flights) are taken first, one per refill of a
+    // wave, and skipped when the counter reaches them; a list that overflowed is not used
+    constexpr bool PRIO = (FT & FT_LATTICE) != 0 && AK == 0;
+    unsigned long long* const pnext = (unsigned long long*)(a.tally + MCBTE_TALLY_PRIO_NEXT_OFFSET);
+    const int64_t* const plist = PRIO ? (const int64_t*)(a.tally + T.prio_list_off) : nullptr;
+    unsigned long long pcount = 0;
+    if constexpr (PRIO)
+        if (T.prio_thr) pcount = *(volatile const unsigned long long*)(a.tally + MCBTE_TALLY_PRIO_COUNT_OFFSET);
+    const bool prio_on = PRIO && T.prio_thr && pcount <= MCBTE_PRIO_CAP;
+    bool prio_left = prio_on && pcount > 0;   // wave-uniform
     for (;;) {
         unsigned long long live = __ballot(alive);
-        if (!exhausted && (live == 0ull || since_refill >= a.refill)) {
+        if ((!exhausted || prio_left) && (live == 0ull || since_refill >= a.refill)) {
             since_refill = 0;
-            const unsigned long long need = __ballot(!alive);
-            if (need) {
+            unsigned long long need = __ballot(!alive);
+            if constexpr (PRIO) {
+                if (need && prio_left) {
+                    const int ld = __ffsll((long long)need) - 1;
+                    unsigned long long pi = 0;
+                    if (lane == ld) pi = atomicAdd(pnext, 1ull);
+                    pi = __shfl(pi, ld, 64);
+                    if (pi < pcount) {
+                        if (lane == ld) {
+                            my_pid = plist[pi];
+                            start_particle<R, TK, FT>(T, a, my_pid, a.inst0, p, st, cnt, lg);
+                            alive = true;
+                        }
+                        need &= need - 1ull;
+                    } else {
+                        prio_left = false;
+                    }
+                }
+            }
+            if (need && !exhausted) {
                 const uint32_t cnt_need = (uint32_t)__popcll(need);
                 const int leader = __ffsll((long long)need) - 1;
                 unsigned long long base = 0;
                 if (lane == leader) base = atomicAdd(counter, (unsigned long long)cnt_need);
                 base = __shfl(base, leader, 64);
                 if (base + cnt_need >= n) exhausted = true;
-                if (!alive) {
+                if ((need >> lane) & 1ull) {
                     const unsigned long long idx = base + wave_rank(need);
                     if (idx < n) {
                         my_pid = a.first_pid + (int64_t)idx;
-                        start_particle<R, TK, FT>(T, a, my_pid, a.inst0, p, st, cnt, lg);
+                        uint64_t kf = 0;
+                        const uint32_t rej = start_particle<R, TK, FT>(T, a, my_pid, a.inst0, p, st, cnt, lg,
+                                                                       PRIO ? &kf : nullptr);
+                        alive = true;
+                        if (PRIO && prio_on && kf >= T.prio_thr[p.m]) {   // listed: traced from the list
+                            cnt.c[0] -= 1;
+                            cnt.c[11] -= rej;
+                            alive = false;
+                        }
                         if (ADJ) adj.F_total = a.particle_F[idx];
                         if (AK == 2) {
                             pc.nt = 0;
                             pc.begin_flight();
                         }
-                        alive = true;
                     }
                 }
-                live = __ballot(alive);
             }
+            live = __ballot(alive);
         }
         if (live == 0ull) {
-            if (exhausted) break;
+            if (exhausted && !prio_left) break;
             continue;
         }
         ++since_refill;
-        const bool lone = exhausted && (live & (live - 1ull)) == 0ull;   // one lane left in the wave
+        const bool lone = exhausted && !prio_left && (live & (live - 1ull)) == 0ull;   // one lane left in the wave
         // detector-grid pieces of a sparse wave are scored by the whole wave after the step
         const bool spread = TK == TALLY_STEADY_GRID && !ADJ && __popcll(live) <= 16;
         bool coop = false;
@@ -2609,6 +2674,10 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
 // ------------------------------------------------------------------------------------------
 
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+__global__ void k_zero_u64_n(unsigned long long* p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
 
 template <typename R>
 static hipError_t emit_t(const DevTab* d_tab, uint64_t seed, uint32_t inst, int64_t first_pid, int64_t n, void* state,
@@ -2705,7 +2774,16 @@ hipError_t launch_trace(const LaunchArgs& a, int mode, int precision, int tally_
     const void* fn = kernel_for(mode, precision, tally_kind, ft);
     if (!fn) return hipErrorInvalidDeviceFunction;
     ensure_lds_limit(fn, lds);
-    if (mode == 0) {   // the work counter of a solo trace lives in the tally header
+    if (mode == 0 && (ft & FT_LATTICE)) {
+        // the work counter, the scheduling list's length and its next entry (tally header), then
+        // the list of the particles to start first
+        hipLaunchKernelGGL(k_zero_u64_n, dim3(1), dim3(64), 0, s,
+                           (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET), 3);
+        const int64_t blocks = std::min<int64_t>(4096, (a.n + 255) / 256);
+        if (blocks > 0)
+            hipLaunchKernelGGL(k_prio_scan, dim3((unsigned)blocks), dim3(256), 0, s, a.tabs, a.seed, a.inst0,
+                               a.first_pid, a.n, a.tally);
+    } else if (mode == 0) {   // the work counter of a solo trace lives in the tally header
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s,
                            (unsigned long long*)(a.tally + MCBTE_TALLY_COUNTER_OFFSET));
     }

@@ -153,3 +153,36 @@ def test_segments_flag_and_the_pathwise_replay():
     bad.flags = 2
     with pytest.raises(M.MCBTEError):
         M.trace(t, bad, 0, 100, None, tl)
+
+
+def test_long_first_flights_started_first_change_no_count():
+    """Particles whose first free flight passes 1000 cell widths are listed before the trace and
+    started first (their walks then run beside the others).  Order changes no particle: gray
+    medium with a 100 um mean free path, where e^-5 of the first flights qualify.  One call over
+    1e6 particles (6700 listed: more than the list holds, so the scheduling is off) and two calls
+    over its halves (3400 listed each, scheduled) give the same counters; so do launch shapes; the
+    listed count is the qualifying share (binomial, 5 sigma)."""
+    import math
+    M = _pkg()
+    w = _gray_lattice(100e-6, 1_000_000, n_scat_max=2)
+    t = M.Tables(w)
+    whole = M.run(w, precision=32, tables=t)
+    tl = t.new_tally()
+    listed = []
+    for first in (0, 500_000):
+        M.trace(t, M.make_run(int(w["seed"]), 32), first, 500_000, None, tl)
+        listed.append(int(tl[200:208].view(__import__("torch").int64).item()))
+    halves = M.tally(t, tl)
+    p = math.exp(-5.0)
+    _say(f"[scheduling] listed {listed} of 500000 each (expected {500000 * p:.0f}); counts {whole['counts']}")
+    for k in listed:
+        assert abs(k - 500000 * p) < 5.0 * math.sqrt(500000 * p * (1 - p))
+        assert k <= 4096
+    assert np.array_equal(halves["counts_raw"], whole["counts_raw"])
+    assert abs(halves["kappa"] - whole["kappa"]) <= 1e-9 * abs(whole["kappa"])
+    small = W.with_(w, **{"problem.N": 300_000})
+    base = M.run(small, precision=32, tables=t)
+    for shape in ({"block": 64, "refill": 1}, {"block": 256, "refill": 32, "grid": 2}):
+        r = M.run(small, precision=32, tables=t, **shape)
+        assert np.array_equal(r["counts_raw"], base["counts_raw"]), shape
+    assert base["counts"]["particles"] == 300_000
