@@ -42,6 +42,7 @@ extern "C" {
 #define MCBTE_EGEOM (-6)    /* geometry not closed / periodic faces not paired / pore outside */
 #define MCBTE_ESIZE (-7)    /* a caller buffer is smaller than required               */
 #define MCBTE_ERANGE (-8)   /* a sensitivity term was not finite (mcbte_adjoint_finalize) */
+#define MCBTE_ELIMIT (-9)   /* more instances than mcbte_trace_batch_static's fixed scratch holds */
 
 /* boundary types (order of the paper's boundary table, section 4.3) */
 #define MCBTE_ISOTHERMAL 1  /* data[0] = wall temperature T_b                       */
@@ -307,6 +308,21 @@ int64_t mcbte_batch_queue_bytes(int32_t n_inst);
 int mcbte_trace_batch(const mcbte_tables* const* tables, int32_t n_inst, const int64_t* n_particles,
                       const uint32_t* instance_ids, void* const* tallies, const mcbte_run* run, void* queue,
                       void* stream);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+   that forbid hipMalloc): mcbte_trace_batch without the queue argument.  The work queue lives in a
+   file-scope static device array of the library (about 206 KB, enough for
+   MCBTE_STATIC_MAX_INSTANCES instances), which each device holds from its first use until the
+   process ends; the work table reaches it through a setup kernel's arguments on `stream`, so the
+   call allocates nothing, copies nothing from the host and does not synchronize (fully
+   asynchronous on `stream`).  Every call on a device shares that one array: calls that overlap on
+   one device (other streams, other threads) race and must be ordered by the caller; a call's
+   queue counter is cleared by its own setup kernel.  Same arguments and results as
+   mcbte_trace_batch (run->particle_F must be NULL as well).  Errors: as mcbte_trace_batch, and
+   MCBTE_ELIMIT when n_inst > MCBTE_STATIC_MAX_INSTANCES. */
+#define MCBTE_STATIC_MAX_INSTANCES 64
+int mcbte_trace_batch_static(const mcbte_tables* const* tables, int32_t n_inst, const int64_t* n_particles,
+                             const uint32_t* instance_ids, void* const* tallies, const mcbte_run* run, void* stream);
 
 /* Launch-shape autotuner.  The launch shape -- threads per workgroup and the refill period
    (flights between refills of finished lanes) -- changes no result (every integer count and

@@ -175,4 +175,36 @@ struct LaunchArgs {
     double lambda_split;         // local pathwise replay: modes with v tau <= this take that form
 };
 
+// Work-queue layout of the batched trace (in the caller's queue buffer, or in the library's static
+// scratch for the allocation-free entry point): counter page, per-instance tally pointers, particle
+// counts, chunk starts (n + 1), Philox instance ids, tables; every piece 256-byte aligned.
+struct QueueLayout {
+    int64_t o_tp, o_n, o_cs, o_id, o_tab, end;
+};
+__host__ __device__ inline int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+__host__ __device__ inline QueueLayout queue_layout(int64_t n_inst)
+{
+    QueueLayout q;
+    q.o_tp = 256;
+    q.o_n = q.o_tp + align256(8 * n_inst);
+    q.o_cs = q.o_n + align256(8 * n_inst);
+    q.o_id = q.o_cs + align256(8 * (n_inst + 1));
+    q.o_tab = q.o_id + align256(4 * n_inst);
+    q.end = q.o_tab + align256((int64_t)sizeof(DevTab) * n_inst);
+    return q;
+}
+
+// the allocation-free batched trace: at most this many instances (its per-instance data travel as
+// the setup kernel's arguments, and its work queue lives in a static device array of this size)
+#define MCBTE_STATIC_INSTANCES 64
+struct BatchSetupArgs {
+    int32_t n_inst;
+    int32_t pad;
+    const DevTab* tab[MCBTE_STATIC_INSTANCES];    // device copies of the instances' tables
+    unsigned char* tally[MCBTE_STATIC_INSTANCES];
+    int64_t n[MCBTE_STATIC_INSTANCES];
+    int64_t cstart[MCBTE_STATIC_INSTANCES + 1];
+    uint32_t id[MCBTE_STATIC_INSTANCES];
+};
+
 }  // namespace mcbte

@@ -18,6 +18,9 @@ hipError_t launch_emit(const DevTab* d_tab, int precision, uint64_t seed, uint32
 hipError_t launch_trace(const LaunchArgs& a, int mode, int precision, int tally_kind, int ft, int block, int grid, size_t lds,
                         hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);
+hipError_t static_queue(int dev, unsigned char** out);
+int64_t static_queue_bytes();
+hipError_t launch_batch_setup(const BatchSetupArgs& args, unsigned char* q, hipStream_t s);
 int trace_occupancy(int mode, int precision, int tally_kind, int ft, int block, size_t lds);
 }  // namespace mcbte
 
@@ -126,6 +129,7 @@ const char* mcbte_strerror(int status)
     case MCBTE_EGEOM: return "invalid geometry";
     case MCBTE_ESIZE: return "caller buffer too small";
     case MCBTE_ERANGE: return "a sensitivity term was not finite (pathwise tangents grew without bound)";
+    case MCBTE_ELIMIT: return "more instances than the allocation-free batched trace holds (MCBTE_STATIC_MAX_INSTANCES)";
     default: return "unknown status";
     }
 }
@@ -905,6 +909,70 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     a.chunk_size = chunk;
     a.queue = (unsigned long long*)qd;
     a.n_chunks = cstart[n_inst];
+    a.tally_lds = lp.tally_lds;
+    a.lds_tab_bytes = (int32_t)lp.lds_tab;
+    const hipError_t e = launch_trace(a, 1, run->precision, t0->host_view.tally_kind, ft, lp.block, lp.grid, lp.lds, s);
+    return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
+}
+
+static_assert(MCBTE_STATIC_MAX_INSTANCES == MCBTE_STATIC_INSTANCES, "static batch capacity");
+
+int mcbte_trace_batch_static(const mcbte_tables* const* ts, int32_t n_inst, const int64_t* n_particles,
+                             const uint32_t* instance_ids, void* const* tallies, const mcbte_run* run, void* stream)
+{
+    if (!ts || n_inst < 1 || !n_particles || !instance_ids || !tallies || !run) return MCBTE_EINVAL;
+    if (n_inst > MCBTE_STATIC_MAX_INSTANCES) return MCBTE_ELIMIT;
+    if (run->precision != 32 && run->precision != 64) return MCBTE_EINVAL;
+    if ((run->flags & ~MCBTE_RUN_SEGMENTS) != 0 || run->reserved != 0) return MCBTE_EINVAL;
+    if (run->event_log || run->particle_F) return MCBTE_EINVAL;
+    const mcbte_tables* t0 = ts[0];
+    if (!t0 || t0->device < 0) return MCBTE_ENODEV;
+    for (int i = 0; i < n_inst; ++i) {
+        if (!ts[i] || !tallies[i] || n_particles[i] < 0) return MCBTE_EINVAL;
+        if (ts[i]->device != t0->device || !ts[i]->d_tab) return MCBTE_ENODEV;
+        if (ts[i]->host_view.tally_kind != t0->host_view.tally_kind) return MCBTE_EINVAL;
+    }
+    DeviceGuard g(t0->device);
+    if (!g.ok) return MCBTE_EHIP;
+    unsigned char* q = nullptr;                  // this device's static work queue
+    if (static_queue(t0->device, &q) != hipSuccess) return MCBTE_EHIP;
+    if (queue_layout(n_inst).end > static_queue_bytes()) return MCBTE_ELIMIT;
+    int ft = FT_PLAIN;
+    for (int i = 0; i < n_inst; ++i)
+        if (ts[i]->two || ts[i]->spec_w || ts[i]->walls) ft = 0;
+    LaunchPlan lp;
+    int rc = plan_launch(ts, n_inst, run, 1, ft, lp);
+    if (rc != MCBTE_OK) return rc;
+    // the work table travels as the setup kernel's arguments (no host staging, no copy, no sync)
+    const int64_t chunk = 8192;
+    BatchSetupArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.n_inst = n_inst;
+    sa.cstart[0] = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        sa.tab[i] = ts[i]->d_tab;
+        sa.tally[i] = (unsigned char*)tallies[i];
+        sa.n[i] = n_particles[i];
+        sa.id[i] = instance_ids[i];
+        sa.cstart[i + 1] = sa.cstart[i] + (n_particles[i] + chunk - 1) / chunk;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (launch_batch_setup(sa, q, s) != hipSuccess) return MCBTE_EHIP;
+    const QueueLayout L = queue_layout(n_inst);
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.tabs = (const DevTab*)(q + L.o_tab);
+    a.n_inst = n_inst;
+    a.refill = lp.refill;
+    a.seed = run->seed;
+    a.inst_ids = (const uint32_t*)(q + L.o_id);
+    a.log_stride = 2;
+    a.tallies = (unsigned char* const*)(q + L.o_tp);
+    a.inst_n = (const int64_t*)(q + L.o_n);
+    a.chunk_start = (const int64_t*)(q + L.o_cs);
+    a.chunk_size = chunk;
+    a.queue = (unsigned long long*)q;
+    a.n_chunks = sa.cstart[n_inst];
     a.tally_lds = lp.tally_lds;
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
     const hipError_t e = launch_trace(a, 1, run->precision, t0->host_view.tally_kind, ft, lp.block, lp.grid, lp.lds, s);

@@ -2794,6 +2794,64 @@ hipError_t launch_trace(const LaunchArgs& a, int mode, int precision, int tally_
     return e != hipSuccess ? e : hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------
+// allocation-free batched trace: the work queue in a static device array
+// ------------------------------------------------------------------------------------------
+
+// The work queue of mcbte_trace_batch_static, for at most MCBTE_STATIC_INSTANCES instances; each
+// device holds its own copy until the process ends, and every call on a device shares it.
+static constexpr int64_t kStaticQueueBytes =
+    256 + 2 * ((8 * MCBTE_STATIC_INSTANCES + 255) / 256 * 256) + (8 * (MCBTE_STATIC_INSTANCES + 1) + 255) / 256 * 256 +
+    (4 * MCBTE_STATIC_INSTANCES + 255) / 256 * 256 + ((int64_t)sizeof(DevTab) * MCBTE_STATIC_INSTANCES + 255) / 256 * 256;
+static __device__ __align__(256) unsigned char scratch[kStaticQueueBytes];
+
+int64_t static_queue_bytes() { return kStaticQueueBytes; }
+
+// The device address of `scratch` on device `dev` (which must be current), looked up once per device
+// (in host code the array's name stands for no device address).
+hipError_t static_queue(int dev, unsigned char** out)
+{
+    static std::mutex mu;
+    static std::map<int, unsigned char*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+        it = addr.emplace(dev, (unsigned char*)ptr).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
+// Fill the work queue in q (the layout of queue_layout) from the setup arguments: the counter page
+// cleared, the per-instance arrays written, each instance's tables copied from its device copy.
+__global__ void __launch_bounds__(256) k_batch_setup(BatchSetupArgs args, unsigned char* q)
+{
+    const QueueLayout L = queue_layout(args.n_inst);
+    const int n = args.n_inst;
+    for (int i = threadIdx.x; i < 32; i += blockDim.x) ((unsigned long long*)q)[i] = 0ull;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        ((unsigned char**)(q + L.o_tp))[i] = args.tally[i];
+        ((int64_t*)(q + L.o_n))[i] = args.n[i];
+        ((uint32_t*)(q + L.o_id))[i] = args.id[i];
+    }
+    for (int i = threadIdx.x; i <= n; i += blockDim.x) ((int64_t*)(q + L.o_cs))[i] = args.cstart[i];
+    constexpr int W = (int)(sizeof(DevTab) / 8);
+    static_assert(sizeof(DevTab) % 8 == 0, "DevTab copied in 8-byte words");
+    for (int w = threadIdx.x; w < n * W; w += blockDim.x) {
+        const int inst = w / W, k = w - inst * W;
+        ((uint64_t*)(q + L.o_tab))[w] = ((const uint64_t*)args.tab[inst])[k];
+    }
+}
+
+hipError_t launch_batch_setup(const BatchSetupArgs& args, unsigned char* q, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_setup, dim3(1), dim3(256), 0, s, args, q);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p);

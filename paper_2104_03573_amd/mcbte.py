@@ -15,7 +15,8 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmcbte.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENODEV, ETABLE, EGEOM, ESIZE, ERANGE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+OK, EINVAL, ENOMEM, EHIP, ENODEV, ETABLE, EGEOM, ESIZE, ERANGE, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+STATIC_MAX_INSTANCES = 64
 N_COUNTS = 16
 COUNT_NAMES = ["particles", "flights", "relaxations", "specular", "diffuse", "periodic", "absorbed",
                "timeouts", "nscat_end", "cap_end", "escaped", "rejections", "two_phonon"]
@@ -92,7 +93,8 @@ class Result(C.Structure):
 
 EXPORTED = ["mcbte_build_tables", "mcbte_free_tables", "mcbte_table_info", "mcbte_table_export",
             "mcbte_state_bytes", "mcbte_emit", "mcbte_trace", "mcbte_batch_queue_bytes", "mcbte_trace_batch",
-            "mcbte_adjoint", "mcbte_adjoint_finalize", "mcbte_tally", "mcbte_strerror", "mcbte_autotune"]
+            "mcbte_adjoint", "mcbte_adjoint_finalize", "mcbte_tally", "mcbte_strerror", "mcbte_autotune",
+            "mcbte_trace_batch_static"]
 
 _lib = None
 
@@ -126,6 +128,9 @@ def lib():
         L.mcbte_trace_batch.argtypes = [C.POINTER(p), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
                                         C.POINTER(p), C.POINTER(Run), p, p]
         L.mcbte_trace_batch.restype = C.c_int
+        L.mcbte_trace_batch_static.argtypes = [C.POINTER(p), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
+                                               C.POINTER(p), C.POINTER(Run), p]
+        L.mcbte_trace_batch_static.restype = C.c_int
         L.mcbte_autotune.argtypes = [C.POINTER(p), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
                                      C.POINTER(p), p, C.POINTER(Run), C.c_int64, C.c_int32, C.POINTER(Run),
                                      C.POINTER(C.c_double), C.c_int32, p]
@@ -283,6 +288,17 @@ def trace_batch(tables: list, n_particles, instance_ids, tallies: list, run: Run
     tp = (C.c_void_p * k)(*[tl.data_ptr() for tl in tallies])
     _check("mcbte_trace_batch", lib().mcbte_trace_batch(th, k, npart, ids, tp, C.byref(run),
                                                         C.c_void_p(queue.data_ptr()), _stream(stream)))
+
+
+def trace_batch_static(tables: list, n_particles, instance_ids, tallies: list, run: Run, stream=None):
+    """The batched trace with the library's static work queue (no queue buffer; allocates nothing)."""
+    k = len(tables)
+    th = (C.c_void_p * k)(*[t.h for t in tables])
+    npart = (C.c_int64 * k)(*[int(x) for x in n_particles])
+    ids = (C.c_uint32 * k)(*[int(x) for x in instance_ids])
+    tp = (C.c_void_p * k)(*[tl.data_ptr() for tl in tallies])
+    _check("mcbte_trace_batch_static", lib().mcbte_trace_batch_static(th, k, npart, ids, tp, C.byref(run),
+                                                                      _stream(stream)))
 
 
 TUNE_CANDIDATES = 36
