@@ -402,6 +402,37 @@ int mcbte_adjoint_finalize(const mcbte_tables* tables, const double* adj, int64_
 int mcbte_tally(const mcbte_tables* tables, const void* tally, double* host_out, int64_t n_out,
                 mcbte_result* result, void* stream);
 
+/* Batch-mean statistics of tallies: the per-detector output of section 4.5 with its error bar.
+   Trajectories are independent (section 6), so separately traced particle groups are independent
+   samples of it.  tallies[b], b < n_tallies, are device tally
+   buffers of these tables, each filled by its own range of particles (each its own trace calls:
+   disjoint ranges of one seed, or other seeds).  Each is finalized as by mcbte_tally; host_mean
+   receives the particle-weighted mean over the batches (the finalized sum of all of them) and
+   host_sigma its batch-mean standard error sqrt(sum_b n_b (X_b - X)^2 / ((B - 1) N)) per element
+   (NaN when n_tallies == 1), both laid out [n_cells][n_cols][4] (n_out >= n_cells * n_cols * 4;
+   either may be NULL, not both).  Synchronizes `stream`.  Errors: MCBTE_EINVAL (a NULL buffer,
+   n_tallies < 1), MCBTE_ESIZE, MCBTE_ENODEV, MCBTE_EHIP. */
+int mcbte_tally_batches(const mcbte_tables* tables, const void* const* tallies, int32_t n_tallies, double* host_mean,
+                        double* host_sigma, int64_t n_out, void* stream);
+
+/* Cumulative thermal conductivity (the frequency-resolved flux output of section 4.5, accumulated as
+   in section 5.6).  Orders for mcbte_kappa_cumulative: */
+#define MCBTE_CUM_MFP 0    /* by table row, rows in ascending mean free path v tau, two clocks
+                              combined by Matthiessen's rule (ties by row)                         */
+#define MCBTE_CUM_OMEGA 1  /* by frequency bin, bins in ascending lowest angular frequency of their
+                              rows (ties by bin; a bin without rows last)                         */
+/* For a steady problem with one detector cell (no axis binned) whose mask holds the score axis'
+   flux: each row's (bin's) kappa_i = -q_score,i / gradT_score, summed in the order: kappa_cum[k] is
+   the sum over the first k + 1 rows (bins), so the last entry is kappa.  keys[k] (may be NULL)
+   receives the k-th row's mean free path (m) or bin's angular frequency (rad/s).  With several
+   tallies (as for mcbte_tally_batches), kappa_cum is the particle-weighted mean over them and
+   kappa_cum_sigma (may be NULL) its batch-mean standard error (NaN for one tally).  n_out >= n_modes
+   (MCBTE_CUM_MFP) or n_bins (MCBTE_CUM_OMEGA).  Synchronizes `stream`.  Errors: MCBTE_EINVAL
+   (transient or binned tallies, zero gradient along the score axis, flux not tallied, unknown
+   order, NULL buffers), MCBTE_ESIZE, MCBTE_ENODEV, MCBTE_EHIP. */
+int mcbte_kappa_cumulative(const mcbte_tables* tables, const void* const* tallies, int32_t n_tallies, int32_t order,
+                           double* keys, double* kappa_cum, double* kappa_cum_sigma, int64_t n_out, void* stream);
+
 /* Static text for a status code. */
 const char* mcbte_strerror(int status);
 

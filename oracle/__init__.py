@@ -401,6 +401,68 @@ def run_batches(w: dict, n_batches: int, n: int | None = None, threads: int = 8)
         return list(ex.map(one, range(n_batches)))
 
 
+def batch_statistics(batches: list[dict], key=None) -> dict:
+    """Particle-weighted mean over independently traced particle groups (each finalized on its
+    own) and the standard error of that mean from the spread of the group values (batch means;
+    trajectories are independent, section 6): mean = sum_b n_b X_b / N and
+    sigma^2 = sum_b n_b (X_b - mean)^2 / ((B - 1) N), NaN for one group.  key(batch) picks the
+    finalized array (default: T and q stacked as [..., 4])."""
+    pick = key or (lambda b: np.concatenate([b["T"][..., None], b["q"]], axis=-1))
+    X = np.stack([np.asarray(pick(b), dtype=np.float64) for b in batches])
+    nb = np.array([float(b["counts"]["particles"]) for b in batches])
+    N = nb.sum()
+    shape = (-1,) + (1,) * (X.ndim - 1)
+    mean = (nb.reshape(shape) * X).sum(axis=0) / N
+    if len(batches) < 2:
+        sigma = np.full(mean.shape, np.nan)
+    else:
+        sigma = np.sqrt((nb.reshape(shape) * (X - mean) ** 2).sum(axis=0) / ((len(batches) - 1) * N))
+    return {"mean": mean, "sigma": sigma}
+
+
+def kappa_cumulative(batches: list[dict], order: str = "mfp") -> dict:
+    """Cumulative thermal conductivity from the per-row steady flux columns (section 4.5's
+    frequency-resolved output, accumulated as in section 5.6).  Each row's kappa is
+    -q_score,row / gradT_score; order "mfp" sums rows in ascending mean free path v tau (two clocks
+    combined by Matthiessen's rule), order "omega" sums frequency bins in ascending order of their
+    lowest row frequency (a bin without rows last); ties keep index order.  Batch means over the
+    given groups as batch_statistics."""
+    w = batches[0]["tables"].w
+    modes = w["modes"]
+    sa = int(w["problem"]["score_axis"])
+    gs = float(w["geometry"]["gradT"][sa])
+    if w["problem"]["transient"] or any(int(x) > 0 for x in w["detectors"]["n"]) or gs == 0.0:
+        raise ValueError("cumulative kappa needs a steady problem, one detector cell and a gradient")
+    tau = np.asarray(modes["tau"], dtype=np.float64)
+    t2 = np.asarray(modes["tau_imp"], dtype=np.float64)
+    tau_eff = np.where(t2 > 0.0, 1.0 / (1.0 / tau + 1.0 / np.where(t2 > 0.0, t2, 1.0)), tau)
+    if order == "mfp":
+        keys_all = np.asarray(modes["v"], dtype=np.float64) * tau_eff
+    elif order == "omega":
+        bins = np.asarray(modes["bin"], dtype=np.int64)
+        keys_all = np.full(int(bins.max()) + 1, np.inf)
+        for r in range(len(modes)):
+            keys_all[bins[r]] = min(keys_all[bins[r]], float(modes["omega"][r]))
+    else:
+        raise ValueError(order)
+    idx = np.argsort(keys_all, kind="stable")
+
+    def cum(b):
+        q = np.asarray(b["q"], dtype=np.float64)
+        assert q.shape[0] == 1 and q.shape[1] == len(modes)
+        k_row = -q[0, :, sa] / gs
+        if order == "mfp":
+            part = k_row
+        else:
+            part = np.zeros(len(keys_all))
+            for r in range(len(modes)):
+                part[bins[r]] += k_row[r]
+        return np.cumsum(part[idx])
+
+    st = batch_statistics(batches, key=cum)
+    return {"keys": keys_all[idx], "kappa_cum": st["mean"], "kappa_cum_sigma": st["sigma"]}
+
+
 def default_lambda_split(w: dict) -> float:
     """The geometric length below which a mode's flights take the local pathwise form: the smallest
     bounded extent of the cell or pore diameter (infinite for the unbounded bulk)."""

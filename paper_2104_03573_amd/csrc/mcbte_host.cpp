@@ -115,6 +115,42 @@ struct mcbte_tables {
     int max_lds = 0;
 };
 
+namespace {
+
+// The deviational energy per particle's normalisation of raw sums (Eq. tally definitions):
+// T = e / (C_tot V_cell) * sum s*t, q = e / V_cell * sum s*dx, with e = E_tot / n and V_cell the
+// detector cell (the solid volume for an unbinned tally).  Writes n_cells * n_cols * 4 values
+// when out is given.
+void normalize_raw(const mcbte_tables* t, const double* raw, double n, double* out, double* e_out, double* Vc_out)
+{
+    const mcbte_info& inf = t->info;
+    const double e = inf.E_tot / n;
+    double Vc = 1.0;
+    bool binned = false;
+    for (int a = 0; a < 3; ++a) {
+        if (t->det.n[a] > 0) {
+            binned = true;
+            Vc *= (t->det.hi[a] - t->det.lo[a]) / (double)t->det.n[a];
+        } else if (!t->geom.unbounded[a]) {
+            Vc *= t->geom.L[a];
+        }
+    }
+    if (!binned) Vc = inf.V_solid;
+    if (e_out) *e_out = e;
+    if (Vc_out) *Vc_out = Vc;
+    if (!out) return;
+    const int64_t n_raw = inf.n_cells * inf.n_cols * 4;
+    const double sT = e / (inf.C_tot * Vc), sq = e / Vc;
+    for (int64_t i = 0; i < n_raw; i += 4) {
+        out[i] = sT * raw[i];
+        out[i + 1] = sq * raw[i + 1];
+        out[i + 2] = sq * raw[i + 2];
+        out[i + 3] = sq * raw[i + 3];
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* mcbte_strerror(int status)
@@ -1161,29 +1197,7 @@ int mcbte_tally(const mcbte_tables* t, const void* tally, double* host_out, int6
     const double n = (double)res->counts[MCBTE_CNT_PARTICLES];
     if (n <= 0.0) return MCBTE_OK;
     const mcbte_info& inf = t->info;
-    const double e = inf.E_tot / n;
-    double Vc = 1.0;
-    bool binned = false;
-    for (int a = 0; a < 3; ++a) {
-        if (t->det.n[a] > 0) {
-            binned = true;
-            Vc *= (t->det.hi[a] - t->det.lo[a]) / (double)t->det.n[a];
-        } else if (!t->geom.unbounded[a]) {
-            Vc *= t->geom.L[a];
-        }
-    }
-    if (!binned) Vc = inf.V_solid;
-    res->e_eff = e;
-    res->V_cell = Vc;
-    if (host_out) {
-        const double sT = e / (inf.C_tot * Vc), sq = e / Vc;
-        for (int64_t i = 0; i < n_raw; i += 4) {
-            host_out[i] = sT * raw[i];
-            host_out[i + 1] = sq * raw[i + 1];
-            host_out[i + 2] = sq * raw[i + 2];
-            host_out[i + 3] = sq * raw[i + 3];
-        }
-    }
+    normalize_raw(t, raw, n, host_out, &res->e_eff, &res->V_cell);
     if (!t->prob.transient && n > 1.0) {
         const double* m = res->moments;
         const double var_T = std::max(m[1] - m[0] * m[0] / n, 0.0) / (n - 1.0);
@@ -1201,6 +1215,143 @@ int mcbte_tally(const mcbte_tables* t, const void* tally, double* host_out, int6
             res->kappa_cell_avg = res->kappa * inf.V_solid / box;
         }
     }
+    return MCBTE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Copy a tally buffer to the host and normalise it: T and q per cell and column in
+// out[n_cells][n_cols][4]; returns the particles traced (0: none, out all zero).
+int64_t finalize_host(const mcbte_tables* t, const void* tally, std::vector<double>& out, hipStream_t s, int& rc)
+{
+    rc = MCBTE_OK;
+    std::vector<unsigned char> buf((size_t)t->info.tally_bytes);
+    if (hipMemcpyAsync(buf.data(), tally, buf.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        rc = MCBTE_EHIP;
+        return 0;
+    }
+    uint64_t counts[MCBTE_N_COUNTS];
+    std::memcpy(counts, buf.data(), sizeof(counts));
+    const int64_t n = (int64_t)counts[MCBTE_CNT_PARTICLES];
+    const int64_t n_raw = t->info.n_cells * t->info.n_cols * 4;
+    out.assign((size_t)n_raw, 0.0);
+    if (n <= 0) return 0;
+    normalize_raw(t, (const double*)(buf.data() + MCBTE_TALLY_HEADER_BYTES), (double)n, out.data(), nullptr,
+                  nullptr);
+    return n;
+}
+
+// particle-weighted mean of per-batch values x[b][k] (batch b traced n[b] particles) and its
+// batch-mean standard error sqrt(sum_b n_b (x_b - mean)^2 / ((B - 1) N)) (NaN for one batch)
+void batch_mean(const std::vector<std::vector<double>>& x, const std::vector<int64_t>& n, double* mean, double* sigma,
+                int64_t K)
+{
+    const size_t B = x.size();
+    double N = 0.0;
+    for (size_t b = 0; b < B; ++b) N += (double)n[b];
+    for (int64_t k = 0; k < K; ++k) {
+        double m = 0.0;
+        for (size_t b = 0; b < B; ++b) m += (double)n[b] * x[b][(size_t)k];
+        m = N > 0.0 ? m / N : 0.0;
+        if (mean) mean[k] = m;
+        if (sigma) {
+            if (B < 2) {
+                sigma[k] = NAN;
+            } else {
+                double v = 0.0;
+                for (size_t b = 0; b < B; ++b) v += (double)n[b] * (x[b][(size_t)k] - m) * (x[b][(size_t)k] - m);
+                sigma[k] = std::sqrt(v / ((double)(B - 1) * N));
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcbte_tally_batches(const mcbte_tables* t, const void* const* tallies, int32_t n_tallies, double* host_mean,
+                        double* host_sigma, int64_t n_out, void* stream)
+{
+    if (!t || !tallies || n_tallies < 1 || (!host_mean && !host_sigma)) return MCBTE_EINVAL;
+    for (int b = 0; b < n_tallies; ++b)
+        if (!tallies[b]) return MCBTE_EINVAL;
+    const int64_t n_raw = t->info.n_cells * t->info.n_cols * 4;
+    if (n_out < n_raw) return MCBTE_ESIZE;
+    if (t->device < 0) return MCBTE_ENODEV;
+    DeviceGuard g(t->device);
+    if (!g.ok) return MCBTE_EHIP;
+    std::vector<std::vector<double>> x((size_t)n_tallies);
+    std::vector<int64_t> n((size_t)n_tallies);
+    for (int b = 0; b < n_tallies; ++b) {
+        int rc = MCBTE_OK;
+        n[(size_t)b] = finalize_host(t, tallies[b], x[(size_t)b], (hipStream_t)stream, rc);
+        if (rc != MCBTE_OK) return rc;
+    }
+    batch_mean(x, n, host_mean, host_sigma, n_raw);
+    return MCBTE_OK;
+}
+
+int mcbte_kappa_cumulative(const mcbte_tables* t, const void* const* tallies, int32_t n_tallies, int32_t order,
+                           double* keys, double* kappa_cum, double* kappa_cum_sigma, int64_t n_out, void* stream)
+{
+    if (!t || !tallies || n_tallies < 1 || !kappa_cum) return MCBTE_EINVAL;
+    if (order != MCBTE_CUM_MFP && order != MCBTE_CUM_OMEGA) return MCBTE_EINVAL;
+    if (t->prob.transient || t->host_view.tally_kind != TALLY_STEADY_ONE) return MCBTE_EINVAL;
+    const int sa = t->prob.score_axis;
+    const double gs = t->geom.gradT[sa];
+    if (gs == 0.0 || !((t->det.mask >> (1 + sa)) & 1)) return MCBTE_EINVAL;
+    const int64_t M = t->info.n_modes, NB = t->info.n_bins;
+    const int64_t K = order == MCBTE_CUM_MFP ? M : NB;
+    if (n_out < K) return MCBTE_ESIZE;
+    for (int b = 0; b < n_tallies; ++b)
+        if (!tallies[b]) return MCBTE_EINVAL;
+    if (t->device < 0) return MCBTE_ENODEV;
+    // the order: rows by mean free path v tau, or frequency bins by the lowest angular frequency of
+    // their rows (a bin without rows last); ties by index
+    std::vector<int64_t> idx((size_t)K);
+    std::vector<double> key((size_t)K, INFINITY);
+    if (order == MCBTE_CUM_MFP) {
+        for (int64_t m = 0; m < M; ++m) {
+            // two clocks combine by Matthiessen's rule into the row's relaxation time
+            const double tm = t->tau[(size_t)m], t2 = t->tau2[(size_t)m];
+            key[(size_t)m] = t->v[(size_t)m] * (t2 > 0.0 ? 1.0 / (1.0 / tm + 1.0 / t2) : tm);
+        }
+    } else {
+        for (int64_t m = 0; m < M; ++m) {
+            const int64_t b = t->bin_of[(size_t)m];
+            key[(size_t)b] = std::min(key[(size_t)b], t->omega[(size_t)m]);
+        }
+    }
+    for (int64_t k = 0; k < K; ++k) idx[(size_t)k] = k;
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return key[(size_t)a] < key[(size_t)b]; });
+    DeviceGuard g(t->device);
+    if (!g.ok) return MCBTE_EHIP;
+    std::vector<std::vector<double>> cum((size_t)n_tallies, std::vector<double>((size_t)K, 0.0));
+    std::vector<int64_t> n((size_t)n_tallies);
+    std::vector<double> fin, part((size_t)K);
+    for (int b = 0; b < n_tallies; ++b) {
+        int rc = MCBTE_OK;
+        n[(size_t)b] = finalize_host(t, tallies[b], fin, (hipStream_t)stream, rc);
+        if (rc != MCBTE_OK) return rc;
+        // each mode's (bin's) kappa, -q_score / gradT_score, then the prefix sums in the order
+        std::fill(part.begin(), part.end(), 0.0);
+        for (int64_t m = 0; m < M; ++m) {
+            const double km = -fin[(size_t)(m * 4 + 1 + sa)] / gs;
+            part[(size_t)(order == MCBTE_CUM_MFP ? m : t->bin_of[(size_t)m])] += km;
+        }
+        double acc = 0.0;
+        for (int64_t k = 0; k < K; ++k) {
+            acc += part[(size_t)idx[(size_t)k]];
+            cum[(size_t)b][(size_t)k] = acc;
+        }
+    }
+    batch_mean(cum, n, kappa_cum, kappa_cum_sigma, K);
+    if (keys)
+        for (int64_t k = 0; k < K; ++k) keys[k] = key[(size_t)idx[(size_t)k]];
     return MCBTE_OK;
 }
 

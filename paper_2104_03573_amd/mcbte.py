@@ -94,7 +94,10 @@ class Result(C.Structure):
 EXPORTED = ["mcbte_build_tables", "mcbte_free_tables", "mcbte_table_info", "mcbte_table_export",
             "mcbte_state_bytes", "mcbte_emit", "mcbte_trace", "mcbte_batch_queue_bytes", "mcbte_trace_batch",
             "mcbte_adjoint", "mcbte_adjoint_finalize", "mcbte_tally", "mcbte_strerror", "mcbte_autotune",
-            "mcbte_trace_batch_static"]
+            "mcbte_trace_batch_static", "mcbte_tally_batches", "mcbte_kappa_cumulative"]
+
+CUM_MFP = 0
+CUM_OMEGA = 1
 
 _lib = None
 
@@ -141,6 +144,12 @@ def lib():
         L.mcbte_adjoint_finalize.restype = C.c_int
         L.mcbte_tally.argtypes = [p, p, C.POINTER(C.c_double), C.c_int64, C.POINTER(Result), p]
         L.mcbte_tally.restype = C.c_int
+        L.mcbte_tally_batches.argtypes = [p, C.POINTER(p), C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                          C.c_int64, p]
+        L.mcbte_tally_batches.restype = C.c_int
+        L.mcbte_kappa_cumulative.argtypes = [p, C.POINTER(p), C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                             C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int64, p]
+        L.mcbte_kappa_cumulative.restype = C.c_int
         L.mcbte_strerror.argtypes = [C.c_int]
         L.mcbte_strerror.restype = C.c_char_p
         _lib = L
@@ -379,6 +388,40 @@ def tally(t: "Tables", tally_buf, stream=None, with_arrays: bool = True) -> dict
         r["T"] = arr[..., 0]
         r["q"] = arr[..., 1:]
     return r
+
+
+def _ptr_array(bufs):
+    arr = (C.c_void_p * len(bufs))(*[b.data_ptr() for b in bufs])
+    return C.cast(arr, C.POINTER(C.c_void_p)), arr
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def tally_batches(t: "Tables", tallies, stream=None) -> dict:
+    """Finalized T and q, particle-weighted over the tally buffers `tallies` (each its own particle
+    group), with batch-mean standard errors (NaN for one buffer): arrays (n_cells, n_cols)."""
+    n = t.info["n_cells"] * t.info["n_cols"] * 4
+    mean, sig = np.zeros(n), np.zeros(n)
+    pa, keep = _ptr_array(tallies)
+    _check("mcbte_tally_batches", lib().mcbte_tally_batches(t.h, pa, len(tallies), _dptr(mean), _dptr(sig), n,
+                                                            _stream(stream)))
+    shape = (t.info["n_cells"], t.info["n_cols"], 4)
+    mean, sig = mean.reshape(shape), sig.reshape(shape)
+    return {"T": mean[..., 0], "q": mean[..., 1:], "T_sigma": sig[..., 0], "q_sigma": sig[..., 1:]}
+
+
+def kappa_cumulative(t: "Tables", tallies, order: str = "mfp", stream=None) -> dict:
+    """Cumulative kappa over table rows by ascending mean free path (order "mfp") or over frequency
+    bins by ascending angular frequency ("omega"): keys, kappa_cum and its batch-mean standard error."""
+    k = t.info["n_modes"] if order == "mfp" else t.info["n_bins"]
+    keys, cum, sig = np.zeros(k), np.zeros(k), np.zeros(k)
+    pa, keep = _ptr_array(tallies)
+    _check("mcbte_kappa_cumulative", lib().mcbte_kappa_cumulative(
+        t.h, pa, len(tallies), CUM_MFP if order == "mfp" else CUM_OMEGA, _dptr(keys), _dptr(cum), _dptr(sig), k,
+        _stream(stream)))
+    return {"keys": keys, "kappa_cum": cum, "kappa_cum_sigma": sig}
 
 
 class Tables:

@@ -108,6 +108,42 @@ def test_device_calls_reject_host_only_tables():
     assert L.mcbte_trace(None, C.byref(run), 0, 10, None, dummy, None) == M.mcbte.EINVAL
 
 
+def test_finalize_calls_check_their_arguments_before_the_device():
+    """mcbte_kappa_cumulative needs a steady, unbinned problem whose tally holds the flux along the
+    score axis, and a known order; both finalize calls check buffer lists and output sizes, then refuse tables
+    without a device."""
+    L = M.lib()
+    dummy = C.c_void_p(1)
+    one = (C.c_void_p * 1)(dummy)
+    two_null = (C.c_void_p * 2)(dummy, None)
+    out = np.zeros(4000)
+    d = out.ctypes.data_as(C.POINTER(C.c_double))
+    film = M.Tables(W.film(N=10), device=-1)
+    M_rows, nb = film.info["n_modes"], film.info["n_bins"]
+    assert L.mcbte_kappa_cumulative(film.h, one, 1, M.mcbte.CUM_MFP, d, d, d, M_rows, None) == M.mcbte.ENODEV
+    assert L.mcbte_kappa_cumulative(film.h, one, 1, M.mcbte.CUM_OMEGA, None, d, None, nb, None) == M.mcbte.ENODEV
+    assert L.mcbte_kappa_cumulative(film.h, one, 1, M.mcbte.CUM_MFP, d, d, d, M_rows - 1, None) == M.mcbte.ESIZE
+    assert L.mcbte_kappa_cumulative(film.h, one, 1, M.mcbte.CUM_OMEGA, d, d, d, nb - 1, None) == M.mcbte.ESIZE
+    assert L.mcbte_kappa_cumulative(film.h, one, 1, 2, d, d, d, M_rows, None) == M.mcbte.EINVAL
+    assert L.mcbte_kappa_cumulative(film.h, one, 0, 0, d, d, d, M_rows, None) == M.mcbte.EINVAL
+    assert L.mcbte_kappa_cumulative(film.h, C.cast(two_null, C.POINTER(C.c_void_p)), 2, 0, d, d, d, M_rows,
+                                    None) == M.mcbte.EINVAL
+    assert L.mcbte_kappa_cumulative(film.h, one, 1, 0, d, None, d, M_rows, None) == M.mcbte.EINVAL
+    for w in (W.gray_slab(N=10), W.film(N=10, z_bins=4), W.transient_bump(N=10),
+              W.with_(W.film(N=10), **{"detectors.mask": W.MASK_T | W.MASK_QX})):
+        t = M.Tables(w, device=-1)
+        assert L.mcbte_kappa_cumulative(t.h, one, 1, 0, d, d, d, 4000, None) == M.mcbte.EINVAL, w["name"]
+    slab = M.Tables(W.gray_slab(N=10), device=-1)
+    n = slab.info["n_cells"] * slab.info["n_cols"] * 4
+    assert L.mcbte_tally_batches(slab.h, one, 1, d, d, n, None) == M.mcbte.ENODEV
+    assert L.mcbte_tally_batches(slab.h, one, 1, None, d, n, None) == M.mcbte.ENODEV
+    assert L.mcbte_tally_batches(slab.h, one, 1, d, d, n - 1, None) == M.mcbte.ESIZE
+    assert L.mcbte_tally_batches(slab.h, one, 1, None, None, n, None) == M.mcbte.EINVAL
+    assert L.mcbte_tally_batches(slab.h, one, 0, d, d, n, None) == M.mcbte.EINVAL
+    assert L.mcbte_tally_batches(slab.h, C.cast(two_null, C.POINTER(C.c_void_p)), 2, d, d, n,
+                                 None) == M.mcbte.EINVAL
+
+
 def test_sizes_and_messages():
     assert M.state_bytes(32, 1000) == 9 * 4096 + 7 * 4096
     assert M.state_bytes(64, 1) == 16 * 256

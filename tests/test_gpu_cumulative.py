@@ -1,0 +1,142 @@
+"""Cumulative thermal conductivity and batch-mean errors through the C ABI (mcbte_kappa_cumulative,
+mcbte_tally_batches) against the oracle's own implementation of the same outputs.
+
+Particle groups are contiguous ranges of one seed, each traced into its own tally buffer by its own
+mcbte_trace call (the oracle's run_batches splits the same way), so the FP64 kernel, bit-exact in
+its events, gives the oracle's per-group sums to rounding and the finalized curves, keys and
+standard errors follow.  The FP32 nanomesh case (phonons below 2 THz reflected specularly, the
+frequency-resolved example of section 5.6) is compared statistically.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _pkg():
+    import paper_2104_03573_amd as M
+    return M
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _gpu_groups(M, t, w, n_groups, precision, n=None):
+    n = w["problem"]["N"] if n is None else n
+    bounds = [(n * i) // n_groups for i in range(n_groups + 1)]
+    tallies = []
+    for lo, hi in zip(bounds[:-1], bounds[1:]):
+        tl = t.new_tally()
+        M.trace(t, M.make_run(int(w["seed"]), precision, int(w.get("instance", 0))), lo, hi - lo, None, tl)
+        tallies.append(tl)
+    return tallies
+
+
+@pytest.mark.parametrize("order", ["mfp", "omega"])
+def test_fp64_film_cumulative_kappa_equals_the_oracle(order):
+    """Silicon-like 100 nm film, 2e5 particles in 4 groups, FP64: keys equal, the curve within 1e-10
+    of kappa, the batch errors within 1e-6 of themselves."""
+    M = _pkg()
+    w = W.film(N=200_000, n_scat_max=10)
+    t = M.Tables(w)
+    got = M.kappa_cumulative(t, _gpu_groups(M, t, w, 4, 64), order)
+    ref = oracle.kappa_cumulative(oracle.run_batches(w, 4, threads=THREADS), order)
+    k = ref["kappa_cum"][-1]
+    err = np.abs(got["kappa_cum"] - ref["kappa_cum"]).max() / abs(k)
+    serr = np.abs(got["kappa_cum_sigma"] - ref["kappa_cum_sigma"]).max() / ref["kappa_cum_sigma"].max()
+    _say(f"[cumulative {order}, FP64 film] kappa {k:.6g}, curve error {err:.2e} of kappa, sigma error {serr:.2e}")
+    assert np.array_equal(got["keys"], ref["keys"])
+    assert err <= 1e-10
+    assert serr <= 1e-6
+    assert np.all(np.isfinite(got["kappa_cum_sigma"]))
+
+
+def test_fp64_binned_batch_errors_equal_the_oracle():
+    """Gray slab with 50 temperature and flux bins, FP64, unequal groups of 2e4, 3e4 and 5e4
+    particles: the particle-weighted means and batch errors per bin equal the oracle's."""
+    M = _pkg()
+    w = W.gray_slab(N=100_000)
+    t = M.Tables(w)
+    bounds = [0, 20_000, 50_000, 100_000]
+    tallies = []
+    tb = oracle.Tables(w)
+    groups = []
+    for lo, hi in zip(bounds[:-1], bounds[1:]):
+        tl = t.new_tally()
+        M.trace(t, M.make_run(int(w["seed"]), 64), lo, hi - lo, None, tl)
+        tallies.append(tl)
+        raw, counts, mom, _ = tb.trace_range(int(w["seed"]), 0, lo, hi - lo)
+        g = {"raw": raw, "counts": counts, "moments": mom, "tables": tb}
+        g.update(oracle.finalize(g))
+        groups.append(g)
+    got = M.tally_batches(t, tallies)
+    ref = oracle.batch_statistics(groups)
+    scale_T = np.abs(ref["mean"][..., 0]).max()
+    scale_q = np.abs(ref["mean"][..., 1:]).max()
+    assert np.abs(got["T"] - ref["mean"][..., 0]).max() <= 1e-10 * scale_T
+    assert np.abs(got["q"] - ref["mean"][..., 1:]).max() <= 1e-10 * scale_q
+    assert np.abs(got["T_sigma"] - ref["sigma"][..., 0]).max() <= 1e-6 * ref["sigma"][..., 0].max()
+    assert np.abs(got["q_sigma"] - ref["sigma"][..., 1:]).max() <= 1e-6 * ref["sigma"][..., 1:].max()
+    one = M.tally_batches(t, tallies[:1])
+    assert np.isnan(one["T_sigma"]).all()
+    whole = M.tally(t, tallies[0])
+    assert np.allclose(one["T"], whole["T"], rtol=1e-14, atol=0.0)     # n x / n
+
+
+def test_batched_sweep_instances_give_their_own_cumulative_curves():
+    """Three film thicknesses traced in one batched launch (FP64, uneven counts): each instance's
+    tally gives its cumulative curve over mean free path, equal to the oracle's for that instance
+    (one group each: no standard error)."""
+    import torch
+    M = _pkg()
+    ws, ns = [], [30_000, 60_000, 20_000]
+    for i, d in enumerate((20e-9, 200e-9, 2e-6)):
+        ws.append(W.with_(W.film(N=ns[i], d=d, n_scat_max=10), instance=i + 1))
+    ts = [M.Tables(w) for w in ws]
+    tallies = [t.new_tally() for t in ts]
+    queue = torch.zeros(M.batch_queue_bytes(3), dtype=torch.uint8, device="cuda")
+    M.trace_batch(ts, ns, [1, 2, 3], tallies, M.make_run(int(ws[0]["seed"]), 64), queue)
+    for i, w in enumerate(ws):
+        got = M.kappa_cumulative(ts[i], [tallies[i]], "mfp")
+        res = oracle.trace(w, threads=THREADS, instance=i + 1)
+        res.update(oracle.finalize(res))
+        ref = oracle.kappa_cumulative([res], "mfp")
+        k = ref["kappa_cum"][-1]
+        assert np.array_equal(got["keys"], ref["keys"])
+        assert np.abs(got["kappa_cum"] - ref["kappa_cum"]).max() <= 1e-10 * abs(k)
+        assert np.isnan(got["kappa_cum_sigma"]).all()
+        _say(f"[cumulative, batched instance {i + 1}] d {w['geometry']['L'][2]:.0e}: kappa {k:.5g}")
+
+
+def test_fp32_nanomesh_frequency_resolved_cumulative_kappa_against_the_oracle():
+    """The 500 nm periodic cell with its 25 % cylindrical pore, phonons below 2 THz reflected
+    specularly: FP32, 1e6 particles in 8 groups, the cumulative curve over frequency.  FP32
+    trajectories part from the oracle's after long free flights, so the curves agree to a share of
+    the batch errors: at every decile within 1 % of kappa plus 2 oracle standard errors."""
+    M = _pkg()
+    w = W.porous_cell(N=1_000_000, spec_omega=W.OMEGA_2THZ)
+    t = M.Tables(w)
+    got = M.kappa_cumulative(t, _gpu_groups(M, t, w, 8, 32), "omega")
+    ref = oracle.kappa_cumulative(oracle.run_batches(w, 8, threads=THREADS), "omega")
+    k_arr = ref["kappa_cum"]
+    k = k_arr[-1]
+    worst = 0.0
+    for q in (0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0):
+        i = min(int(np.searchsorted(k_arr, q * k)), len(k_arr) - 1)
+        d = abs(got["kappa_cum"][i] - k_arr[i])
+        worst = max(worst, d / abs(k))
+        _say(f"[cumulative omega, FP32 nanomesh] decile {q:.1f} (omega {ref['keys'][i]:.3g}): "
+             f"{got['kappa_cum'][i]:.5g} vs {k_arr[i]:.5g} (sigma {ref['kappa_cum_sigma'][i]:.3g})")
+        assert d <= 0.01 * abs(k) + 2.0 * ref["kappa_cum_sigma"][i]
+    assert np.array_equal(got["keys"], ref["keys"])
+    ratio = got["kappa_cum_sigma"][-1] / ref["kappa_cum_sigma"][-1]
+    _say(f"[cumulative omega, FP32 nanomesh] worst decile {worst:.2e} of kappa; sigma ratio {ratio:.3f}")
+    assert 0.7 < ratio < 1.4
