@@ -104,12 +104,14 @@ def workload(name: str, scale: float = 1.0):
                 "film_d100nm_T300K_1400modes_N1e6_nscat10_two_clocks")
     if name == "porous_cell_spec2thz":
         # the pore reflects the phonons below 2 THz specularly (the paper's nanomesh variant)
-        return (W.porous_cell(N=int(100_000_000 * scale), spec_omega=W.OMEGA_2THZ),
-                "porous_cell_500nm_phi0.25_N1e8_specular_below_2THz")
+        return (W.porous_cell(N=int(100_000_000 * scale), spec_omega=W.OMEGA_2THZ, n_scat_max=W.C5_NSCAT),
+                f"porous_cell_500nm_phi0.25_N1e8_nscat{W.C5_NSCAT}_specular_below_2THz")
     if name == "gray_slab":
         return W.gray_slab(N=int(100_000 * scale)), "gray_slab_L100nm_Kn1_N1e5_50bins"
     if name == "porous_cell":
-        return W.porous_cell(N=int(100_000_000 * scale)), "porous_cell_500nm_phi0.25_N1e8"
+        # the relaxation cap at which the cell's kappa has converged (a smaller cap biases it)
+        return (W.porous_cell(N=int(100_000_000 * scale), n_scat_max=W.C5_NSCAT),
+                f"porous_cell_500nm_phi0.25_N1e8_nscat{W.C5_NSCAT}")
     if name == "transient":
         return W.transient_bump(N=int(10_000_000 * scale)), "transient_bump_1um_200times_100bins_N1e7"
     if name == "sweep":
@@ -322,10 +324,23 @@ def measure_batched(args, ws, M, torch, precision: int, steps: int, warmup: int,
               for rs in results for r, t, w in zip(rs, tabs, ws))
     achieved = ops / (sum(kernel_ms) / 1e3)
     last = results[-1]
+    # each instance's cumulative kappa over mean free path from the last step's tallies (a host-side
+    # finalize, outside the timed region): the free path below which half of kappa is carried and
+    # the share carried by free paths up to the film's thickness
+    cum = []
+    for t, tl, w in zip(tabs, tallies, ws):
+        c = M.kappa_cumulative(t, [tl], "mfp")
+        k = c["kappa_cum"][-1]
+        d = float(w["geometry"]["L"][2])
+        i50 = next(i for i, v in enumerate(c["kappa_cum"]) if v >= 0.5 * k or i == len(c["keys"]) - 1)
+        i_d = sum(1 for x in c["keys"] if x <= d) - 1
+        cum.append({"instance": int(w["instance"]), "d_m": d, "T_K": float(w["problem"]["T_lin"]),
+                    "kappa": float(k), "lambda_half_kappa_m": float(c["keys"][i50]),
+                    "kappa_share_lambda_le_d": float(c["kappa_cum"][i_d] / k) if i_d >= 0 else 0.0})
     return {"wall_s": wall, "flights_per_s": flights / wall, "ms_per_step": wall / steps * 1e3,
             "kernel_ms": kernel_ms, "achieved": achieved, "frac": achieved / PEAK_LANE_OPS,
             "lane_ops_per_launch": ops / steps, "flights_per_step": flights / steps, "particles_per_step": sum(ns),
-            "kappa_eff_per_instance": [r["kappa"] for r in last],
+            "kappa_eff_per_instance": [r["kappa"] for r in last], "cumulative_kappa_per_instance": cum,
             "worst_kappa_sigma_rel": max(r["kappa_sigma"] / abs(r["kappa"]) for r in last),
             "table_build_s": t_tables, "launch": lc}
 
@@ -442,6 +457,7 @@ def main():
                              "unit": "T lane-op/s", "frac": m["frac"], "traffic": None, "kernel": "k_trace_batch",
                              "kernel_ms": sum(m["kernel_ms"]) / len(m["kernel_ms"])},
                    kernel_ms_per_step=m["kernel_ms"], kappa_eff_per_instance=m["kappa_eff_per_instance"],
+                   cumulative_kappa_per_instance=m["cumulative_kappa_per_instance"],
                    worst_kappa_sigma_rel=m["worst_kappa_sigma_rel"], table_build_s=m["table_build_s"])
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(w[-1], args.cpu_seconds, host_cores())
@@ -488,7 +504,7 @@ def _brief(m: dict, workload: str, precision: int) -> dict:
          "kernel_ms_spread": _spread(m["kernel_ms"]),
          "roofline_frac": m["frac"], "achieved_T_lane_ops": m["achieved"] / 1e12, "launch": m["launch"]}
     for k in ("kappa_eff", "kappa_sigma", "time_to_sigma_0p5pct_s", "kappa_eff_per_instance",
-              "worst_kappa_sigma_rel", "particles_per_step"):
+              "cumulative_kappa_per_instance", "worst_kappa_sigma_rel", "particles_per_step"):
         if k in m:
             r[k] = m[k]
     return r
