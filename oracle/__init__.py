@@ -41,18 +41,19 @@ class Mode(C.Structure):
 
 
 class Face(C.Structure):
-    _fields_ = [("type", C.c_int32), ("pad", C.c_int32), ("data", C.c_double * 3)]
+    _fields_ = [("type", C.c_int32), ("spec_table", C.c_int32), ("data", C.c_double * 3)]
 
 
 class Cyl(C.Structure):
     _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("r", C.c_double), ("id", C.c_int32),
-                ("type", C.c_int32), ("spec", C.c_double), ("spec_wc", C.c_double)]
+                ("type", C.c_int32), ("spec", C.c_double), ("spec_wc", C.c_double), ("spec_table", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class Wall(C.Structure):
     _fields_ = [("x1", C.c_double), ("y1", C.c_double), ("x2", C.c_double), ("y2", C.c_double),
                 ("nx", C.c_double), ("ny", C.c_double), ("id", C.c_int32), ("type", C.c_int32),
-                ("spec", C.c_double), ("spec_wc", C.c_double)]
+                ("spec", C.c_double), ("spec_wc", C.c_double), ("spec_table", C.c_int32), ("pad", C.c_int32)]
 
 
 class Geom(C.Structure):
@@ -69,9 +70,9 @@ class Problem(C.Structure):
     _fields_ = [("N", C.c_int64), ("max_events", C.c_int64), ("T_lin", C.c_double), ("t_max", C.c_double),
                 ("n_scat_max", C.c_int32), ("format", C.c_int32), ("transient", C.c_int32),
                 ("score_axis", C.c_int32), ("n_times", C.c_int32), ("ic_axis", C.c_int32),
-                ("n_ic", C.c_int32), ("pad", C.c_int32),
+                ("n_ic", C.c_int32), ("n_spec_tables", C.c_int32),
                 ("t_meas", C.POINTER(C.c_double)), ("ic_edges", C.POINTER(C.c_double)),
-                ("ic_dT", C.POINTER(C.c_double))]
+                ("ic_dT", C.POINTER(C.c_double)), ("spec_table", C.POINTER(C.c_double))]
 
 
 def build(force: bool = False) -> str:
@@ -198,20 +199,23 @@ class Tables:
             G.L[a] = g["L"][a]
             G.unbounded[a] = int(g["unbounded"][a])
             G.gradT[a] = g["gradT"][a]
-        for fid, (ty, d0, d1, d2) in g["faces"].items():
-            G.face[fid - 1].type = int(ty)
-            G.face[fid - 1].data[0], G.face[fid - 1].data[1], G.face[fid - 1].data[2] = d0, d1, d2
+        for fid, f in g["faces"].items():
+            G.face[fid - 1].type = int(f[0])
+            G.face[fid - 1].data[0], G.face[fid - 1].data[1], G.face[fid - 1].data[2] = f[1], f[2], f[3]
+            G.face[fid - 1].spec_table = int(f[4]) if len(f) > 4 else 0
         G.n_cyl = len(g["cylinders"])
         for i, c in enumerate(g["cylinders"]):
             cx, cy, r, cid, ty, spec = c[:6]
-            G.cyl[i] = Cyl(cx, cy, r, int(cid), int(ty), spec, float(c[6]) if len(c) > 6 else 0.0)
+            G.cyl[i] = Cyl(cx, cy, r, int(cid), int(ty), spec, float(c[6]) if len(c) > 6 else 0.0,
+                           int(c[7]) if len(c) > 7 else 0, 0)
         walls = g.get("walls", [])
         if len(walls) > 16:
             raise ValueError("at most 16 internal line walls")
         G.n_wall = len(walls)
         for i, c in enumerate(walls):
             x1, y1, x2, y2, nx, ny, wid, ty, spec = c[:9]
-            G.wall[i] = Wall(x1, y1, x2, y2, nx, ny, int(wid), int(ty), spec, float(c[9]) if len(c) > 9 else 0.0)
+            G.wall[i] = Wall(x1, y1, x2, y2, nx, ny, int(wid), int(ty), spec, float(c[9]) if len(c) > 9 else 0.0,
+                             int(c[10]) if len(c) > 10 else 0, 0)
         G.volume = g["volume"]
         self._geom = G
         d = w["detectors"]
@@ -224,12 +228,13 @@ class Tables:
         self._t_meas = np.ascontiguousarray(p["t_meas"], dtype=np.float64)
         self._ic_edges = np.ascontiguousarray(p["ic_edges"], dtype=np.float64)
         self._ic_dT = np.ascontiguousarray(p["ic_dT"], dtype=np.float64)
+        self._spec = np.ascontiguousarray(p.get("spec_tables", np.zeros((0, len(modes)))), dtype=np.float64)
         dp = C.POINTER(C.c_double)
         P = Problem(p["N"], p["max_events"], p["T_lin"], p["t_max"], p["n_scat_max"], p["format"],
                     int(p["transient"]), p["score_axis"], len(self._t_meas) if p["transient"] else 0,
-                    p["ic_axis"], len(self._ic_dT), 0,
+                    p["ic_axis"], len(self._ic_dT), self._spec.shape[0],
                     self._t_meas.ctypes.data_as(dp), self._ic_edges.ctypes.data_as(dp),
-                    self._ic_dT.ctypes.data_as(dp))
+                    self._ic_dT.ctypes.data_as(dp), self._spec.ctypes.data_as(dp) if self._spec.shape[0] else None)
         self._prob = P
         h = C.c_void_p()
         rc = L.orc_build(self._modes, len(modes), C.byref(G), C.byref(D), C.byref(P), C.byref(h))

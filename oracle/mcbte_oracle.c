@@ -40,6 +40,7 @@ struct orc_tables {
     int32_t M;
     double *C, *v, *tau;
     double* omega;       /* angular frequency of each row (frequency-dependent specularity) */
+    double* spec_tab;    /* per-row specularity tables (n_spec x M), or NULL */
     double* tau2;        /* two-phonon (impurity) relaxation time of each row; 0: no such process */
     int32_t two;         /* some row has a two-phonon clock */
     double C_tot, Wv, kappa_bulk;
@@ -206,7 +207,7 @@ void orc_free(orc_tables* t)
     free(t->thr_ic); free(t->thr_wall); free(t->thr_rel);
     free(t->src_kind); free(t->src_ref); free(t->src_sign); free(t->src_E); free(t->thr_src);
     free(t->t_meas); free(t->ic_edges); free(t->ic_dT);
-    free(t->bin); free(t->P_bin);
+    free(t->bin); free(t->P_bin); free(t->spec_tab);
     free(t);
 }
 
@@ -215,6 +216,10 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
 {
     *out = NULL;
     if (M < 1 || pr->N < 1 || pr->T_lin <= 0.0 || (pr->format != 1 && pr->format != 2)) return E_INVAL;
+    const int32_t NT = pr->n_spec_tables;
+    if (NT < 0 || (NT > 0 && !pr->spec_table)) return E_INVAL;
+    for (int64_t i = 0; i < (int64_t)NT * M; ++i)
+        if (!(pr->spec_table[i] >= 0.0 && pr->spec_table[i] <= 1.0)) return E_INVAL;
     for (int a = 0; a < 3; ++a)
         if (!g->unbounded[a] && !(g->L[a] > 0.0)) return E_GEOM;
     for (int id = 1; id <= 6; ++id) {
@@ -224,6 +229,9 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
         if (ty < B_ISO || ty > B_PERI) return E_GEOM;
         if (ty == B_ADIA && (!(g->face[id - 1].data[1] >= 0.0) || !isfinite(g->face[id - 1].data[1])))
             return E_GEOM;   /* the specular cutoff frequency */
+        const int32_t k = g->face[id - 1].spec_table;
+        if (k < 0 || k > NT || (k > 0 && (ty != B_ADIA || g->face[id - 1].data[0] != 0.0 || g->face[id - 1].data[1] != 0.0)))
+            return E_GEOM;   /* a per-row table replaces the face's own specularity */
     }
     for (int a = 0; a < 3; ++a) {          /* periodic faces come in pairs on one axis */
         if (g->unbounded[a]) continue;
@@ -238,6 +246,8 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
         if (g->unbounded[0] || g->unbounded[1] || !(y->r > 0.0)) return E_GEOM;
         if (y->type != B_ADIA) return E_GEOM;
         if (!(y->spec_wc >= 0.0) || !isfinite(y->spec_wc)) return E_GEOM;
+        if (y->spec_table < 0 || y->spec_table > NT || (y->spec_table > 0 && (y->spec != 0.0 || y->spec_wc != 0.0)))
+            return E_GEOM;
         if (y->cx - y->r < 0.0 || y->cx + y->r > g->L[0] || y->cy - y->r < 0.0 || y->cy + y->r > g->L[1])
             return E_GEOM;
         if (y->id < 7 || (c > 0 && y->id <= g->cyl[c - 1].id)) return E_GEOM;
@@ -249,6 +259,9 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
         if (g->unbounded[0] || g->unbounded[1] || (wl->type != B_ADIA && wl->type != B_ISO) || wl->id <= prev)
             return E_GEOM;
         if (!(wl->spec_wc >= 0.0) || !isfinite(wl->spec_wc)) return E_GEOM;
+        if (wl->spec_table < 0 || wl->spec_table > NT ||
+            (wl->spec_table > 0 && (wl->type != B_ADIA || wl->spec != 0.0 || wl->spec_wc != 0.0)))
+            return E_GEOM;
         if (wl->type == B_ADIA && !(wl->spec >= 0.0 && wl->spec <= 1.0)) return E_GEOM;
         if (wl->type == B_ISO && !(wl->spec > 0.0 && isfinite(wl->spec))) return E_GEOM;   /* T_b */
         const double pts[4] = {wl->x1, wl->y1, wl->x2, wl->y2};
@@ -346,6 +359,13 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
     t->gnorm = sqrt((g->gradT[0] * g->gradT[0] + g->gradT[1] * g->gradT[1]) + g->gradT[2] * g->gradT[2]);
     for (int a = 0; a < 3; ++a) t->ngrad[a] = t->gnorm > 0.0 ? -g->gradT[a] / t->gnorm : 0.0;
 
+    /* per-row specularity tables */
+    t->pr.spec_table = NULL;
+    if (NT > 0) {
+        t->spec_tab = (double*)malloc(sizeof(double) * (size_t)NT * (size_t)M);
+        if (!t->spec_tab) { orc_free(t); return E_NOMEM; }
+        memcpy(t->spec_tab, pr->spec_table, sizeof(double) * (size_t)NT * (size_t)M);
+    }
     /* transient arrays */
     if (pr->transient) {
         t->t_meas = (double*)malloc(sizeof(double) * pr->n_times);
@@ -1172,12 +1192,14 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
         /* boundary interaction (sections 3.5.3-3.5.5) */
         int type;
         double spec = 0.0, spec_wc = 0.0;
+        int32_t spec_tab = 0;
         const orc_cyl* cy = NULL;
         const orc_wall* wl = NULL;
         if (hit <= 6) {
             type = g->face[hit - 1].type;
             spec = g->face[hit - 1].data[0];
             spec_wc = g->face[hit - 1].data[1];
+            spec_tab = g->face[hit - 1].spec_table;
         } else {
             for (int c = 0; c < g->n_cyl; ++c)
                 if (g->cyl[c].id == hit) cy = &g->cyl[c];
@@ -1186,9 +1208,12 @@ static void trace_one(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t
             type = cy ? cy->type : wl->type;
             spec = cy ? cy->spec : wl->spec;
             spec_wc = cy ? cy->spec_wc : wl->spec_wc;
+            spec_tab = cy ? cy->spec_table : wl->spec_table;
         }
-        /* section 3.5.3: the specularity may depend on the phonon; below the boundary's cutoff
-           frequency the reflection is specular */
+        /* section 3.5.3: the specularity may depend on the phonon: the boundary's per-row table
+           gives it for the phonon's row, or below the boundary's cutoff frequency the reflection
+           is specular */
+        if (type == B_ADIA && spec_tab > 0) spec = t->spec_tab[(int64_t)(spec_tab - 1) * t->M + p.m];
         if (type == B_ADIA && spec_wc > 0.0 && t->omega[p.m] < spec_wc) spec = 1.0;
         if (type == B_ISO) {
             counts[ORC_C_ABSORBED] += 1;

@@ -23,16 +23,18 @@
 
 /* one material row: first format uses dos/domega, second format gives C */
 typedef struct { double omega, dos, v, domega, tau, C, tau_imp; int32_t bin, branch; } orc_mode;
-typedef struct { int32_t type, pad; double data[3]; } orc_face;
+/* spec_table (faces, pores, adiabatic walls): k >= 1 reads the phonon's specularity from row m of
+   the problem's k-th per-row table (the boundary's own d and cutoff are then 0); 0 = none */
+typedef struct { int32_t type, spec_table; double data[3]; } orc_face;
 /* pore: spec is the degree of specularity d; spec_wc > 0 makes phonons with omega < spec_wc reflect
    specularly whatever d is (frequency-dependent specularity, as in the paper's nanomesh with the
    phonons below 2 THz specular).  Adiabatic faces carry the same cutoff in data[1]. */
-typedef struct { double cx, cy, r; int32_t id, type; double spec, spec_wc; } orc_cyl;
+typedef struct { double cx, cy, r; int32_t id, type; double spec, spec_wc; int32_t spec_table, pad; } orc_cyl;
 /* internal line wall (the paper's In_bnd rows): the segment (x1, y1)-(x2, y2) in the x-y plane,
    extended through the thickness, normal (nx, ny) pointing into the domain; adiabatic (spec = the
    specularity, spec_wc the cutoff, as for pores) or isothermal (spec = T_b: it absorbs and
    emits); ids above the pores' */
-typedef struct { double x1, y1, x2, y2, nx, ny; int32_t id, type; double spec, spec_wc; } orc_wall;
+typedef struct { double x1, y1, x2, y2, nx, ny; int32_t id, type; double spec, spec_wc; int32_t spec_table, pad; } orc_wall;
 typedef struct {
     double L[3];
     int32_t unbounded[3];
@@ -49,10 +51,11 @@ typedef struct {
     int64_t N, max_events;
     double T_lin, t_max;
     int32_t n_scat_max, format, transient, score_axis;
-    int32_t n_times, ic_axis, n_ic, pad;
+    int32_t n_times, ic_axis, n_ic, n_spec_tables;
     const double* t_meas;
     const double* ic_edges;
     const double* ic_dT;
+    const double* spec_table;  /* n_spec_tables x M degrees of specularity, table-major */
 } orc_problem;
 
 typedef struct orc_tables orc_tables;

@@ -354,6 +354,44 @@ def gray_diffusive_bump(N=100_000, L=1e-6, v=6400.0, Lambda=10e-9, sigma=50e-9, 
     return w
 
 
+def ziman_specularity(modes: np.ndarray, eta: float) -> np.ndarray:
+    """Per-row specularity of the silicon-like crystal's rows for a surface of rms roughness eta
+    (m), by Ziman's model exp(-16 pi^2 eta^2 / lambda^2) = exp(-4 eta^2 k^2): the wave vector of
+    each row from its branch's dispersion omega = omega_max sin(k a / 2) (branch 1 LA, 2 TA)."""
+    k_max = 2.0 * math.pi / A_SI
+    a_eff = math.pi / k_max
+    out = np.zeros(len(modes))
+    for i, r in enumerate(modes):
+        wmax = OMEGA_MAX_LA if int(r["branch"]) == 1 else OMEGA_MAX_TA
+        k = (2.0 / a_eff) * math.asin(min(1.0, float(r["omega"]) / wmax))
+        out[i] = math.exp(-4.0 * eta * eta * k * k)
+    return out
+
+
+def random_specularity(n_rows: int, seed: int, binary: bool = False) -> np.ndarray:
+    """A seeded per-row specularity table: uniform in [0, 1), or 0 / 1 with equal odds."""
+    rng = np.random.default_rng(seed)
+    return (rng.random(n_rows) < 0.5).astype(np.float64) if binary else rng.random(n_rows)
+
+
+def with_spec_table(w: dict, table) -> dict:
+    """Copy of w whose adiabatic boundaries (faces, pores, adiabatic line walls) read their
+    specularity per material row from `table` (section 3.5.3): the table becomes the problem's
+    per-row table 1 and every such boundary's own d and cutoff are set to 0."""
+    w = copy.deepcopy(w)
+    table = np.asarray(table, dtype=np.float64)
+    assert table.shape == (len(w["modes"]),)
+    w["problem"]["spec_tables"] = table[None, :]
+    g = w["geometry"]
+    for fid, f in list(g["faces"].items()):
+        if int(f[0]) == ADIABATIC:
+            g["faces"][fid] = (ADIABATIC, 0.0, 0.0, 0.0, 1)
+    g["cylinders"] = [tuple(c[:5]) + (0.0, 0.0, 1) for c in g["cylinders"]]
+    g["walls"] = [tuple(c[:8]) + ((0.0, 0.0, 1) if int(c[7]) == ADIABATIC else (c[8], 0.0, 0))
+                  for c in g.get("walls", [])]
+    return w
+
+
 def with_(w: dict, **changes) -> dict:
     """Deep copy of a workload with dotted-path overrides, e.g. with_(w, **{"problem.N": 10})."""
     w = copy.deepcopy(w)
