@@ -102,6 +102,11 @@ def workload(name: str, scale: float = 1.0):
         # the impurity-like A omega^4 term on its own (two-phonon) clock, section 3.3
         return (W.film(N=int(1_000_000 * scale), modes=W.silicon_like_modes(300.0, impurity_clock=True)),
                 "film_d100nm_T300K_1400modes_N1e6_nscat10_two_clocks")
+    if name == "film_ziman":
+        # walls whose specularity follows each row's wavelength (Ziman, roughness 0.2 nm), section 3.5.3
+        f = W.film(N=int(1_000_000 * scale))
+        return (W.with_spec_table(f, W.ziman_specularity(f["modes"], 0.2e-9)),
+                "film_d100nm_T300K_1400modes_N1e6_nscat10_ziman_eta0.2nm")
     if name == "porous_cell_spec2thz":
         # the pore reflects the phonons below 2 THz specularly (the paper's nanomesh variant)
         return (W.porous_cell(N=int(100_000_000 * scale), spec_omega=W.OMEGA_2THZ, n_scat_max=W.C5_NSCAT),
@@ -515,6 +520,7 @@ def other_forms(args, M, torch) -> dict:
     forms = {}
     plan = [("film_fp32", "film", 32, 20), ("gray_slab_fp64", "gray_slab", 64, 10), ("film_fp64", "film", 64, 5),
             ("transient_fp32", "transient", 32, 3), ("film_two_clocks_fp32", "film_two_clocks", 32, 10),
+            ("film_ziman_specularity_fp32", "film_ziman", 32, 10),
             ("porous_cell_specular_below_2THz_fp32", "porous_cell_spec2thz", 32, 5)]
     # each configuration is tuned on at most 1e6 particles with one timed launch per candidate
     # (the calibration stays outside the timed steps but inside the run's few minutes)

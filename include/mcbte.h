@@ -95,10 +95,15 @@ typedef struct {
    vector; adiabatic data[0] = d (degree of specularity, section 3.5.3) and data[1] = a cutoff
    angular frequency (rad/s, >= 0): a phonon with omega below it reflects specularly whatever d
    is (the frequency-dependent specularity of the paper's nanomesh, phonons below 2 THz
-   specular); 0 = none. */
+   specular); 0 = none.
+   Specularity per phonon (section 3.5.3: d depends on the wavelength): an adiabatic boundary
+   whose spec_table is k >= 1 reflects a phonon of table row m specularly with probability
+   problem->spec_table[(k - 1) * n_modes + m]; its own d and cutoff must then be 0.  The cutoff is
+   the special case of a table holding 1 below the cutoff and d above it.  spec_table = 0: none;
+   other boundary types must have 0. */
 typedef struct {
     int32_t type;               /* MCBTE_ISOTHERMAL / _ADIABATIC / _PERIODIC */
-    int32_t reserved;
+    int32_t spec_table;         /* adiabatic: 1-based specularity table of the problem, 0 = none */
     double data[3];
 } mcbte_face;
 
@@ -109,6 +114,8 @@ typedef struct {
     int32_t type;               /* MCBTE_ADIABATIC */
     double specularity;
     double spec_omega;          /* cutoff angular frequency below which reflection is specular (0: none) */
+    int32_t spec_table;         /* 1-based specularity table of the problem (0: none), as for faces */
+    int32_t reserved;           /* must be 0 */
 } mcbte_pore;
 
 /* internal line wall (the paper's In_bnd rows, section 4.2): the segment (x1, y1)-(x2, y2) in the
@@ -126,6 +133,8 @@ typedef struct {
     int32_t type;               /* MCBTE_ADIABATIC or MCBTE_ISOTHERMAL */
     double data;                /* adiabatic: specularity d; isothermal: T_b (K) */
     double spec_omega;
+    int32_t spec_table;         /* adiabatic: 1-based specularity table of the problem (0: none) */
+    int32_t reserved;           /* must be 0 */
 } mcbte_wall;
 
 /* Box [0, L0] x [0, L1] x [0, L2] (one corner at the origin, section 4.2).  face[id - 1] holds
@@ -164,15 +173,18 @@ typedef struct {
    and cell-averaged temperature deviations ic_dT[0..n_ic-1].  n_scat_max: relaxations after
    which a particle ends (0 = unlimited).  max_events: cap on segments per particle (counted in
    MCBTE_CNT_CAP_END).  score_axis: flux component used for kappa and its standard error.
-   All pointers are host pointers, read during mcbte_build_tables only. */
+   spec_table: n_spec_tables tables of n_modes degrees of specularity in [0, 1] each (row-major),
+   referenced by the boundaries' spec_table numbers (section 3.5.3); may be NULL when
+   n_spec_tables = 0.  All pointers are host pointers, read during mcbte_build_tables only. */
 typedef struct {
     int64_t N, max_events;
     double T_lin, t_max;
     int32_t n_scat_max, format, transient, score_axis;
-    int32_t n_times, ic_axis, n_ic, reserved;
+    int32_t n_times, ic_axis, n_ic, n_spec_tables;
     const double* t_meas;
     const double* ic_edges;
     const double* ic_dT;
+    const double* spec_table;
 } mcbte_problem;
 
 typedef struct mcbte_tables mcbte_tables;

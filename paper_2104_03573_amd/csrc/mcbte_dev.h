@@ -67,11 +67,12 @@ struct DevGeom {
     uint32_t pore_cls[2];
     DevPore32 pore32[MCBTE_DEV_MAX_PORES];
     DevPore64 pore64[MCBTE_DEV_MAX_PORES];
-    // frequency-dependent specularity: below these angular frequencies reflection is specular (0: none)
-    double face_wc[6];
-    double pore_wc[MCBTE_DEV_MAX_PORES];
+    // specularity per phonon: 1 + the per-row table a boundary reads its class and threshold from
+    // (0: the boundary's own constant d)
+    int32_t face_tab[6];
+    int32_t pore_tab[MCBTE_DEV_MAX_PORES];
     // internal line walls: segment, unit normal (FP64 and FP32), id, 2 bits of class per wall and
-    // precision, partial-specularity threshold, cutoff, and the closed loops (loop_end[k] = last
+    // precision, partial-specularity threshold, per-row table, and the closed loops (loop_end[k] = last
     // wall of the loop that wall k starts, -1 otherwise)
     int32_t n_walls;
     int32_t pad_w;
@@ -84,7 +85,7 @@ struct DevGeom {
     int32_t wall_loop_end[MCBTE_DEV_MAX_WALLS];
     uint32_t wall_cls[2];
     uint64_t wall_thr[MCBTE_DEV_MAX_WALLS];
-    double wall_wc[MCBTE_DEV_MAX_WALLS];
+    int32_t wall_tab[MCBTE_DEV_MAX_WALLS];
 };
 
 struct DevDet {
@@ -132,12 +133,16 @@ struct DevTab {
     const double* tau2_64;       // two-phonon relaxation time of each row (0: no such process)
     const float* tau2_32;
     const double* omega64;       // angular frequency of each row
+    // per-row specularity tables (table k, row m at k * M + m): threshold floor(d 2^64) for a partly
+    // specular row, class (bits 0-1 as FP32 trajectories see d, bits 2-3 as FP64 ones do)
+    const uint64_t* spec_thr;
+    const uint8_t* spec_cls;
     const uint64_t* prio_thr;    // pore lattice: a particle is started first when the top 53 bits of its first
                                  // free-flight key reach prio_thr[mode] (NULL: no such scheduling)
     int64_t prio_list_off;       // byte offset of the list of those particles in the tally buffer
     int32_t n_bins;
     int32_t two;                 // some row has a two-phonon clock
-    int32_t spec_w;              // some boundary has a specular cutoff frequency
+    int32_t spec_w;              // some boundary's specularity depends on the phonon (a per-row table)
     int32_t lattice;             // the cell tiles a lattice of pores (lat_min_path > 0)
     DevGeom g;
     DevDet det;

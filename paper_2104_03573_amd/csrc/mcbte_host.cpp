@@ -108,6 +108,9 @@ struct mcbte_tables {
     std::vector<int32_t> src_kind, src_ref, src_sign, bin_of;
     std::vector<double> P_bin;   // relaxation probability mass per frequency bin
     std::vector<uint64_t> prio_thr;   // pore lattice: first-flight keys started first (per mode)
+    std::vector<double> spec_d;       // per-row specularity tables the boundaries read (table-major)
+    std::vector<uint64_t> spec_thr;   // their thresholds and classes
+    std::vector<uint8_t> spec_cls;
     DevTab host_view{};   // device pointers once uploaded
     void* d_mem = nullptr;
     DevTab* d_tab = nullptr;
@@ -194,6 +197,14 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     if (pr.N < 1 || !(pr.T_lin > 0.0) || (pr.format != 1 && pr.format != 2)) return MCBTE_EINVAL;
     if (pr.score_axis < 0 || pr.score_axis > 2 || pr.max_events < 1 || pr.max_events > 0x3FFFFFF0LL) return MCBTE_EINVAL;
     if (pr.n_scat_max < 0) return MCBTE_EINVAL;
+    const int32_t NT = pr.n_spec_tables;
+    if (NT < 0 || (NT > 0 && !pr.spec_table)) return MCBTE_EINVAL;
+    for (int64_t i = 0; i < (int64_t)NT * M; ++i)
+        if (!(pr.spec_table[i] >= 0.0 && pr.spec_table[i] <= 1.0)) return MCBTE_EINVAL;
+    // a boundary's per-row specularity table: a known number, adiabatic, its own d and cutoff 0
+    auto bad_tab = [&](int32_t k, bool adiabatic, double d, double wc) {
+        return k < 0 || k > NT || (k > 0 && (!adiabatic || d != 0.0 || wc != 0.0));
+    };
     // geometry
     for (int a = 0; a < 3; ++a)
         if (!g.unbounded[a] && !(g.L[a] > 0.0)) return MCBTE_EGEOM;
@@ -203,6 +214,9 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         if (ty != MCBTE_ISOTHERMAL && ty != MCBTE_ADIABATIC && ty != MCBTE_PERIODIC) return MCBTE_EGEOM;
         if (ty == MCBTE_ADIABATIC && !(g.face[i].data[0] >= 0.0 && g.face[i].data[0] <= 1.0)) return MCBTE_EGEOM;
         if (ty == MCBTE_ADIABATIC && !(g.face[i].data[1] >= 0.0 && std::isfinite(g.face[i].data[1]))) return MCBTE_EGEOM;
+        if (bad_tab(g.face[i].spec_table, ty == MCBTE_ADIABATIC, ty == MCBTE_ADIABATIC ? g.face[i].data[0] : 0.0,
+                    ty == MCBTE_ADIABATIC ? g.face[i].data[1] : 0.0))
+            return MCBTE_EGEOM;
     }
     for (int a = 0; a < 3; ++a) {
         if (g.unbounded[a]) continue;
@@ -226,6 +240,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         if (g.unbounded[0] || g.unbounded[1] || !(p.r > 0.0) || p.type != MCBTE_ADIABATIC) return MCBTE_EGEOM;
         if (!(p.specularity >= 0.0 && p.specularity <= 1.0)) return MCBTE_EGEOM;
         if (!(p.spec_omega >= 0.0 && std::isfinite(p.spec_omega))) return MCBTE_EGEOM;
+        if (p.reserved != 0 || bad_tab(p.spec_table, true, p.specularity, p.spec_omega)) return MCBTE_EGEOM;
         if (p.cx - p.r < 0.0 || p.cx + p.r > g.L[0] || p.cy - p.r < 0.0 || p.cy + p.r > g.L[1]) return MCBTE_EGEOM;
         if (p.id < 7 || p.id > 255 || (c > 0 && p.id <= g.pore[c - 1].id)) return MCBTE_EGEOM;
     }
@@ -239,6 +254,9 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         if (w.type == MCBTE_ADIABATIC && !(w.data >= 0.0 && w.data <= 1.0)) return MCBTE_EGEOM;
         if (w.type == MCBTE_ISOTHERMAL && !(w.data > 0.0 && std::isfinite(w.data))) return MCBTE_EGEOM;
         if (!(w.spec_omega >= 0.0 && std::isfinite(w.spec_omega))) return MCBTE_EGEOM;
+        if (w.reserved != 0 || bad_tab(w.spec_table, w.type == MCBTE_ADIABATIC, w.type == MCBTE_ADIABATIC ? w.data : 0.0,
+                                       w.spec_omega))
+            return MCBTE_EGEOM;
         const double pts[4] = {w.x1, w.y1, w.x2, w.y2};
         for (int q = 0; q < 4; ++q)
             if (!(pts[q] >= 0.0 && pts[q] <= g.L[q & 1])) return MCBTE_EGEOM;
@@ -270,6 +288,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     t->prob.t_meas = nullptr;
     t->prob.ic_edges = nullptr;
     t->prob.ic_dT = nullptr;
+    t->prob.spec_table = nullptr;
     t->geom = g;
     t->det = dt;
 
@@ -442,15 +461,19 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         for (int a = 0; a < 3; ++a)
             if (!g.unbounded[a]) { ++nb; axis = a; }
         if (nb == 1 && g.n_pores == 0 && g.n_walls == 0 && !pr.transient && h.tally_kind == TALLY_STEADY_ONE) {
-            // (with a specular cutoff, the same one on both walls: a phonon's class is then the
-            // same at every bounce of a chain, and the kernel only starts chains of diffuse ones)
+            // (with a specular cutoff or a per-row table, the same one on both walls: a phonon's
+            // class is then the same at every bounce of a chain, and the kernel only starts chains
+            // of diffuse ones)
             bool diffuse = true;
             double wc = -1.0;
+            int32_t tab = -1;
             for (int i = 0; i < 6; ++i) {
                 if (kFaceAxis[i] != axis) continue;
                 if (!(g.face[i].type == MCBTE_ADIABATIC && g.face[i].data[0] == 0.0)) diffuse = false;
                 if (wc >= 0.0 && g.face[i].data[1] != wc) diffuse = false;
+                if (tab >= 0 && g.face[i].spec_table != tab) diffuse = false;
                 wc = g.face[i].data[1];
+                tab = g.face[i].spec_table;
             }
             if (diffuse) {
                 h.coop_axis = axis;
@@ -503,6 +526,21 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     h.last_rel = last_rel;
     h.last_src = last_src;
     DevGeom& dg = h.g;
+    // per-row specularity: a boundary with a table of the problem reads it; a boundary with a cutoff
+    // frequency reads the table of its special case (1 below the cutoff, d above it); equal tables
+    // are stored once.  Returns 1 + the stored table, 0 for a constant d.
+    auto spec_tab = [&](int32_t user, double d, double wc) -> int32_t {
+        if (user <= 0 && !(wc > 0.0)) return 0;
+        std::vector<double> row((size_t)M);
+        for (int m = 0; m < M; ++m)
+            row[(size_t)m] = user > 0 ? pr.spec_table[(int64_t)(user - 1) * M + m] : (t->omega[(size_t)m] < wc ? 1.0 : d);
+        const size_t n_tab = t->spec_d.size() / (size_t)M;
+        for (size_t k = 0; k < n_tab; ++k)
+            if (std::equal(row.begin(), row.end(), t->spec_d.begin() + (ptrdiff_t)(k * (size_t)M))) return (int32_t)k + 1;
+        t->spec_d.insert(t->spec_d.end(), row.begin(), row.end());
+        t->spec_w = true;
+        return (int32_t)n_tab + 1;
+    };
     for (int a = 0; a < 3; ++a) {
         dg.L[a] = g.unbounded[a] ? 1.0 : g.L[a];
         dg.L32[a] = (float)dg.L[a];
@@ -517,8 +555,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         dg.face_thr[i] = (d > 0.0 && d < 1.0) ? (uint64_t)(d * kTwo64) : 0;
         dg.face_code[0] |= ((uint32_t)dg.face_type[i] | surf_class<float>(d) << 2) << (4 * i);
         dg.face_code[1] |= ((uint32_t)dg.face_type[i] | surf_class<double>(d) << 2) << (4 * i);
-        dg.face_wc[i] = dg.face_type[i] == MCBTE_ADIABATIC ? g.face[i].data[1] : 0.0;
-        if (dg.face_wc[i] > 0.0) t->spec_w = true;
+        dg.face_tab[i] = dg.face_type[i] == MCBTE_ADIABATIC ? spec_tab(g.face[i].spec_table, d, g.face[i].data[1]) : 0;
     }
     for (int a = 0; a < 3; ++a) dg.unb_mask |= (uint32_t)dg.unb[a] << a;
     dg.n_pores = g.n_pores;
@@ -537,8 +574,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         dg.pore64[c] = DevPore64{p.cx, p.cy, p.r, p.id, 0};
         dg.pore_cls[0] |= surf_class<float>(p.specularity) << (2 * c);
         dg.pore_cls[1] |= surf_class<double>(p.specularity) << (2 * c);
-        dg.pore_wc[c] = p.spec_omega;
-        if (p.spec_omega > 0.0) t->spec_w = true;
+        dg.pore_tab[c] = spec_tab(p.spec_table, p.specularity, p.spec_omega);
     }
     dg.n_walls = g.n_walls;
     for (int k = 0; k < g.n_walls; ++k) {
@@ -558,8 +594,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         dg.wall_cls[0] |= surf_class<float>(d) << (2 * k);
         dg.wall_cls[1] |= surf_class<double>(d) << (2 * k);
         dg.wall_thr[k] = (d > 0.0 && d < 1.0) ? (uint64_t)(d * kTwo64) : 0;
-        dg.wall_wc[k] = w.spec_omega;
-        if (w.spec_omega > 0.0) t->spec_w = true;
+        dg.wall_tab[k] = w.type == MCBTE_ADIABATIC ? spec_tab(w.spec_table, d, w.spec_omega) : 0;
         dg.wall_loop_end[k] = -1;
     }
     // closed loops of walls: runs of walls each starting where the previous one ends, the last
@@ -572,6 +607,13 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     }
     if (g.n_walls > 0) t->walls = true;
     h.spec_w = t->spec_w ? 1 : 0;
+    t->spec_thr.assign(t->spec_d.size(), 0);
+    t->spec_cls.assign(t->spec_d.size(), 0);
+    for (size_t i = 0; i < t->spec_d.size(); ++i) {
+        const double d = t->spec_d[i];
+        t->spec_thr[i] = (d > 0.0 && d < 1.0) ? (uint64_t)(d * kTwo64) : 0;
+        t->spec_cls[i] = (uint8_t)(surf_class<float>(d) | surf_class<double>(d) << 2);
+    }
     DevDet& dd = h.det;
     int nc = 0;
     for (int q = 0; q < 4; ++q) {
@@ -652,6 +694,8 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         add(tau2_32.data(), 4 * (size_t)M);
         add(t->omega.data(), 8 * (size_t)M);
         add(t->prio_thr.data(), 8 * t->prio_thr.size());
+        add(t->spec_thr.data(), 8 * t->spec_thr.size());
+        add(t->spec_cls.data(), t->spec_cls.size());
         size_t total = 0;
         std::vector<size_t> off;
         for (auto& p : parts) {
@@ -686,6 +730,8 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         h.omega64 = (const double*)dptr(19);
         h.prio_thr = t->prio_thr.empty() ? nullptr : (const uint64_t*)dptr(20);
         h.prio_list_off = t->prio_thr.empty() ? 0 : t->info.tally_bytes - 8 * (int64_t)MCBTE_PRIO_CAP;
+        h.spec_thr = t->spec_thr.empty() ? nullptr : (const uint64_t*)dptr(21);
+        h.spec_cls = t->spec_cls.empty() ? nullptr : (const uint8_t*)dptr(22);
         parts[0].first = &h;
         for (size_t i = 0; i < parts.size(); ++i) {
             if (parts[i].second == 0) continue;

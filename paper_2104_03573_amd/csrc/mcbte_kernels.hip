@@ -733,6 +733,15 @@ struct Tabs {
 
 // The launch-uniform values the flight loop reads, loaded once before it so that they stay in
 // registers instead of being fetched from the table block at every segment.
+// the reflection class of a phonon of row m at a boundary that reads per-row table tab (1-based),
+// as the trajectories of precision R see its specularity
+template <typename R>
+__device__ __forceinline__ uint32_t tab_class(const DevTab& T, int tab, int m)
+{
+    const uint32_t c = T.spec_cls[(int64_t)(tab - 1) * T.M + m];
+    return std::is_same<R, float>::value ? (c & 3u) : ((c >> 2) & 3u);
+}
+
 template <typename R>
 struct Hot {
     R L[3];
@@ -1226,7 +1235,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         // (lattice_walk), unless the last walk left the particle where it is
         if (p.kc != p.k && vm * p.dtr > H.lat_min) {
             uint32_t pc0 = H.pcls & 3u;
-            if (EXT && T.spec_w && g.pore_wc[0] > 0.0 && T.omega64[p.m] < g.pore_wc[0]) pc0 = SURF_SPECULAR;
+            if (EXT && T.spec_w && g.pore_tab[0] > 0) pc0 = tab_class<R>(T, g.pore_tab[0], p.m);
             if (pc0 != SURF_PARTIAL) {
                 coop = true;
                 return false;
@@ -1236,8 +1245,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     if constexpr (TK == TALLY_STEADY_ONE && AK != 2 && (FT & FT_LOG) == 0) {
         if (chain && !(EXT && g.n_walls > 0)) {   // (the lone-lane walk knows faces and pores)
             uint32_t pc0 = H.pcls & 3u;      // the first pore's reflection class for this phonon
-            if (EXT && T.spec_w && H.n_pores == 1 && g.pore_wc[0] > 0.0 && T.omega64[p.m] < g.pore_wc[0])
-                pc0 = SURF_SPECULAR;
+            if (EXT && T.spec_w && H.n_pores == 1 && g.pore_tab[0] > 0) pc0 = tab_class<R>(T, g.pore_tab[0], p.m);
             if (lone_chain<R>(H, tc, st, p, cnt, vm, sg, pc0)) {   // left the box on the way
                 ++cnt.c[10];
                 if (AK == 1 || (AK == 3 && !local_form<AK>(T, p.m, adj)))
@@ -1450,6 +1458,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         }
     }
     uint32_t cls = SURF_DIFFUSE;
+    int64_t tab_i = -1;                  // the boundary's per-row table entry for this phonon (-1: none)
     if (ev == 1) {
         int btype;
         if (hit <= 6) {
@@ -1462,10 +1471,13 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
             btype = 2;
             cls = (H.pcls >> (2 * pore)) & 3u;
         }
-        // frequency-dependent specularity: below the boundary's cutoff the reflection is specular
+        // specularity per phonon (a cutoff frequency is a table too): the row's class and threshold
         if (EXT && T.spec_w && btype == 2) {
-            const double wc = hit <= 6 ? g.face_wc[hit - 1] : (wall >= 0 ? g.wall_wc[wall] : g.pore_wc[pore]);
-            if (wc > 0.0 && T.omega64[p.m] < wc) cls = SURF_SPECULAR;
+            const int tab = hit <= 6 ? g.face_tab[hit - 1] : (wall >= 0 ? g.wall_tab[wall] : g.pore_tab[pore]);
+            if (tab > 0) {
+                tab_i = (int64_t)(tab - 1) * H.M + p.m;
+                cls = tab_class<R>(T, tab, p.m);
+            }
         }
         if (btype == 1) {
             ++cnt.c[6];
@@ -1497,7 +1509,8 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     bool specular = adia && cls == SURF_SPECULAR;
     if (partial)
         specular = key64(w0.x, w0.y) <
-                   (pore >= 0 ? g.pore_thr[pore] : ((EXT && wall >= 0) ? g.wall_thr[wall] : g.face_thr[hit - 1]));
+                   ((EXT && tab_i >= 0) ? T.spec_thr[tab_i]
+                                        : (pore >= 0 ? g.pore_thr[pore] : ((EXT && wall >= 0) ? g.wall_thr[wall] : g.face_thr[hit - 1])));
     const bool diffuse = adia && !specular;
     if (relax || diffuse || two_ev) {
         const W4 w1 = st.block(blk + 1u);
@@ -1956,7 +1969,7 @@ __device__ void lattice_walk(const DevTab& T, const Hot<float>& H, const Tabs<fl
     const float vm = tb.v[m];
     // the phonon's reflection class at the pore (diffuse or specular; partly specular pores are not walked)
     uint32_t cls = H.pcls & 3u;
-    if (EXT && T.spec_w && T.g.pore_wc[0] > 0.0 && T.omega64[m] < T.g.pore_wc[0]) cls = SURF_SPECULAR;
+    if (EXT && T.spec_w && T.g.pore_tab[0] > 0) cls = tab_class<float>(T, T.g.pore_tab[0], m);
     const float Wx = H.L[0], Wy = H.L[1], Wz = H.L[2];
     const bool zper = ((H.unb >> 2) & 1u) == 0u;
     const float cx = H.p0cx, cy = H.p0cy, rr = H.p0r;

@@ -31,18 +31,20 @@ class Mode(C.Structure):
 
 
 class Face(C.Structure):
-    _fields_ = [("type", C.c_int32), ("reserved", C.c_int32), ("data", C.c_double * 3)]
+    _fields_ = [("type", C.c_int32), ("spec_table", C.c_int32), ("data", C.c_double * 3)]
 
 
 class Pore(C.Structure):
     _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("r", C.c_double), ("id", C.c_int32),
-                ("type", C.c_int32), ("specularity", C.c_double), ("spec_omega", C.c_double)]
+                ("type", C.c_int32), ("specularity", C.c_double), ("spec_omega", C.c_double),
+                ("spec_table", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Wall(C.Structure):
     _fields_ = [("x1", C.c_double), ("y1", C.c_double), ("x2", C.c_double), ("y2", C.c_double),
                 ("nx", C.c_double), ("ny", C.c_double), ("id", C.c_int32), ("type", C.c_int32),
-                ("data", C.c_double), ("spec_omega", C.c_double)]
+                ("data", C.c_double), ("spec_omega", C.c_double), ("spec_table", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 MAX_WALLS = 16
@@ -62,8 +64,9 @@ class ProblemC(C.Structure):
     _fields_ = [("N", C.c_int64), ("max_events", C.c_int64), ("T_lin", C.c_double), ("t_max", C.c_double),
                 ("n_scat_max", C.c_int32), ("format", C.c_int32), ("transient", C.c_int32),
                 ("score_axis", C.c_int32), ("n_times", C.c_int32), ("ic_axis", C.c_int32), ("n_ic", C.c_int32),
-                ("reserved", C.c_int32), ("t_meas", C.POINTER(C.c_double)), ("ic_edges", C.POINTER(C.c_double)),
-                ("ic_dT", C.POINTER(C.c_double))]
+                ("n_spec_tables", C.c_int32), ("t_meas", C.POINTER(C.c_double)),
+                ("ic_edges", C.POINTER(C.c_double)), ("ic_dT", C.POINTER(C.c_double)),
+                ("spec_table", C.POINTER(C.c_double))]
 
 
 class Info(C.Structure):
@@ -195,20 +198,23 @@ def structs_from_workload(w: dict):
         G.L[a] = g["L"][a]
         G.unbounded[a] = int(bool(g["unbounded"][a]))
         G.gradT[a] = g["gradT"][a]
-    for fid, (ty, d0, d1, d2) in g["faces"].items():
-        G.face[fid - 1].type = int(ty)
-        G.face[fid - 1].data[0], G.face[fid - 1].data[1], G.face[fid - 1].data[2] = d0, d1, d2
+    for fid, f in g["faces"].items():
+        G.face[fid - 1].type = int(f[0])
+        G.face[fid - 1].data[0], G.face[fid - 1].data[1], G.face[fid - 1].data[2] = f[1], f[2], f[3]
+        G.face[fid - 1].spec_table = int(f[4]) if len(f) > 4 else 0
     walls = g.get("walls", [])
     if len(walls) > MAX_WALLS:
         raise ValueError(f"at most {MAX_WALLS} internal line walls")
     G.n_walls = len(walls)
     for i, c in enumerate(walls):
         x1, y1, x2, y2, nx, ny, wid, ty, spec = c[:9]
-        G.wall[i] = Wall(x1, y1, x2, y2, nx, ny, int(wid), int(ty), spec, float(c[9]) if len(c) > 9 else 0.0)
+        G.wall[i] = Wall(x1, y1, x2, y2, nx, ny, int(wid), int(ty), spec, float(c[9]) if len(c) > 9 else 0.0,
+                         int(c[10]) if len(c) > 10 else 0, 0)
     G.n_pores = len(g["cylinders"])
     for i, c in enumerate(g["cylinders"]):
         cx, cy, r, cid, ty, spec = c[:6]
-        G.pore[i] = Pore(cx, cy, r, int(cid), int(ty), spec, float(c[6]) if len(c) > 6 else 0.0)
+        G.pore[i] = Pore(cx, cy, r, int(cid), int(ty), spec, float(c[6]) if len(c) > 6 else 0.0,
+                         int(c[7]) if len(c) > 7 else 0, 0)
     G.volume = g["volume"]
     d = w["detectors"]
     D = Detectors()
@@ -216,13 +222,15 @@ def structs_from_workload(w: dict):
         D.lo[a], D.hi[a], D.n[a] = d["lo"][a], d["hi"][a], d["n"][a]
     D.mask = d["mask"]
     p = w["problem"]
+    spec = np.ascontiguousarray(p.get("spec_tables", np.zeros((0, len(modes_np)))), dtype=np.float64)
     keep = [np.ascontiguousarray(p["t_meas"], dtype=np.float64),
             np.ascontiguousarray(p["ic_edges"], dtype=np.float64),
-            np.ascontiguousarray(p["ic_dT"], dtype=np.float64)]
+            np.ascontiguousarray(p["ic_dT"], dtype=np.float64), spec]
     dp = C.POINTER(C.c_double)
     P = ProblemC(p["N"], p["max_events"], p["T_lin"], p["t_max"], p["n_scat_max"], p["format"], int(p["transient"]),
-                 p["score_axis"], len(keep[0]) if p["transient"] else 0, p["ic_axis"], len(keep[2]), 0,
-                 keep[0].ctypes.data_as(dp), keep[1].ctypes.data_as(dp), keep[2].ctypes.data_as(dp))
+                 p["score_axis"], len(keep[0]) if p["transient"] else 0, p["ic_axis"], len(keep[2]), spec.shape[0],
+                 keep[0].ctypes.data_as(dp), keep[1].ctypes.data_as(dp), keep[2].ctypes.data_as(dp),
+                 spec.ctypes.data_as(dp) if spec.shape[0] else None)
     return modes, G, D, P, keep
 
 

@@ -144,6 +144,44 @@ def test_finalize_calls_check_their_arguments_before_the_device():
                                  None) == M.mcbte.EINVAL
 
 
+def test_specularity_table_inputs():
+    """A boundary's per-row table: a known number, on an adiabatic boundary whose own d and cutoff
+    are 0; table values in [0, 1]; reserved words 0.  Equal to the oracle's checks."""
+    base = W.film(N=10)
+    M_rows = len(base["modes"])
+    ok = W.with_spec_table(base, np.linspace(0.0, 1.0, M_rows))
+    assert _status(ok) == 0
+    assert M.Tables(ok, device=-1).info["n_modes"] == M_rows
+
+    def face5(w, f):
+        w = W.with_(w)
+        w["geometry"]["faces"][5] = f
+        return w
+
+    bad_geom = [face5(ok, (W.ADIABATIC, 0.0, 0.0, 0.0, 2)),          # no table 2
+                face5(ok, (W.ADIABATIC, 0.2, 0.0, 0.0, 1)),          # own d with a table
+                face5(ok, (W.ADIABATIC, 0.0, 1e13, 0.0, 1)),         # own cutoff with a table
+                face5(ok, (W.ISOTHERMAL, 300.0, 0.0, 0.0, 1)),       # not adiabatic
+                face5(ok, (W.ADIABATIC, 0.0, 0.0, 0.0, -1))]
+    cell = W.with_spec_table(W.porous_cell(N=10), np.full(M_rows, 0.5))
+    c = list(cell["geometry"]["cylinders"][0])
+    c[5] = 0.5
+    bad_geom.append(W.with_(cell, **{"geometry.cylinders": [tuple(c)]}))
+    slab = W.walled_slab(N=10)
+    walls = [tuple(x[:9]) + (0.0, 1) for x in slab["geometry"]["walls"]]
+    bad_geom.append(W.with_(slab, **{"geometry.walls": walls, "problem.spec_tables": np.zeros((1, 1))}))
+    for w in bad_geom:
+        assert _status(w) == M.mcbte.EGEOM, w["geometry"]["faces"].get(5)
+        with pytest.raises(ValueError):
+            oracle.Tables(w)
+    for vals in (np.full(M_rows, 1.5), np.full(M_rows, -0.1), np.full(M_rows, np.nan)):
+        w = W.with_spec_table(base, np.zeros(M_rows))
+        w["problem"]["spec_tables"] = vals[None, :]
+        assert _status(w) == M.mcbte.EINVAL
+        with pytest.raises(ValueError):
+            oracle.Tables(w)
+
+
 def test_sizes_and_messages():
     assert M.state_bytes(32, 1000) == 9 * 4096 + 7 * 4096
     assert M.state_bytes(64, 1) == 16 * 256

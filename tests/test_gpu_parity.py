@@ -58,6 +58,14 @@ FP64_CASES = {
     "film_spec_cutoff": lambda: W.film(N=3000, spec_omega=2.5 * W.OMEGA_2THZ),
     "film_partial_spec_cutoff": lambda: W.film(N=2000, d=30e-9, specularity=0.4, spec_omega=2.5 * W.OMEGA_2THZ),
     "porous_spec_cutoff": lambda: W.porous_cell(N=1000, spec_omega=W.OMEGA_2THZ),
+    # specularity per material row from a table (random in [0, 1), or 0 / 1 at random: the film's
+    # cooperative bouncing then runs the diffuse rows, the cell's lone-lane walk the others)
+    "film_spec_table": lambda: W.with_spec_table(W.film(N=2000, d=30e-9), W.random_specularity(1400, 3)),
+    "film_spec_table_binary": lambda: W.with_spec_table(W.film(N=3000), W.random_specularity(1400, 4, binary=True)),
+    "porous_spec_table": lambda: W.with_spec_table(W.porous_cell(N=1000), W.random_specularity(1400, 5)),
+    "porous_spec_table_binary": lambda: W.with_spec_table(W.porous_cell(N=1500),
+                                                          W.random_specularity(1400, 6, binary=True)),
+    "walled_spec_table": lambda: W.with_spec_table(W.walled_film(N=1500), W.random_specularity(1400, 7)),
     # internal line walls: the paper's square pore of four walls, a channel between two walls
     "square_pore_walls": lambda: W.square_pore_cell(N=1000),
     "square_pore_walls_partial": lambda: W.square_pore_cell(N=800, specularity=0.5),
