@@ -72,7 +72,9 @@ class Problem(C.Structure):
                 ("score_axis", C.c_int32), ("n_times", C.c_int32), ("ic_axis", C.c_int32),
                 ("n_ic", C.c_int32), ("n_spec_tables", C.c_int32),
                 ("t_meas", C.POINTER(C.c_double)), ("ic_edges", C.POINTER(C.c_double)),
-                ("ic_dT", C.POINTER(C.c_double)), ("spec_table", C.POINTER(C.c_double))]
+                ("ic_dT", C.POINTER(C.c_double)), ("spec_table", C.POINTER(C.c_double)),
+                ("n_heat", C.c_int32), ("pad_h", C.c_int32), ("heat_lo", C.c_double * 3),
+                ("heat_hi", C.c_double * 3), ("heat_t", C.POINTER(C.c_double)), ("heat_P", C.POINTER(C.c_double))]
 
 
 def build(force: bool = False) -> str:
@@ -235,6 +237,14 @@ class Tables:
                     p["ic_axis"], len(self._ic_dT), self._spec.shape[0],
                     self._t_meas.ctypes.data_as(dp), self._ic_edges.ctypes.data_as(dp),
                     self._ic_dT.ctypes.data_as(dp), self._spec.ctypes.data_as(dp) if self._spec.shape[0] else None)
+        heat = p.get("heat")
+        if heat is not None:
+            self._heat_t = np.ascontiguousarray(heat["t"], dtype=np.float64)
+            self._heat_P = np.ascontiguousarray(heat["P"], dtype=np.float64)
+            P.n_heat = len(self._heat_P)
+            for a in range(3):
+                P.heat_lo[a], P.heat_hi[a] = heat["lo"][a], heat["hi"][a]
+            P.heat_t, P.heat_P = self._heat_t.ctypes.data_as(dp), self._heat_P.ctypes.data_as(dp)
         self._prob = P
         h = C.c_void_p()
         rc = L.orc_build(self._modes, len(modes), C.byref(G), C.byref(D), C.byref(P), C.byref(h))

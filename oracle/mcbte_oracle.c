@@ -29,7 +29,8 @@
 #define TWO64 18446744073709551616.0
 
 enum { B_ISO = 1, B_ADIA = 2, B_PERI = 3 };
-enum { S_WALL = 0, S_GRAD = 1, S_IC = 2, S_IWALL = 3 };   /* S_IWALL: isothermal line wall */
+/* S_IWALL: isothermal line wall; S_HEAT: one time interval of the external heat source */
+enum { S_WALL = 0, S_GRAD = 1, S_IC = 2, S_IWALL = 3, S_HEAT = 4 };
 enum { E_OK = 0, E_INVAL = -1, E_NOMEM = -2, E_TABLE = -5, E_GEOM = -6 };
 
 /* boundary-table order: 1 y=0, 2 x=Lx, 3 y=Ly, 4 x=0, 5 z=0, 6 z=Lz */
@@ -56,6 +57,7 @@ struct orc_tables {
     orc_det det;
     orc_problem pr;
     double *t_meas, *ic_edges, *ic_dT;
+    double *heat_t, *heat_P;   /* external heat source: interval edges and power densities */
     int64_t n_cells;
     int32_t n_cols;
     int32_t n_bins;
@@ -207,7 +209,7 @@ void orc_free(orc_tables* t)
     free(t->thr_ic); free(t->thr_wall); free(t->thr_rel);
     free(t->src_kind); free(t->src_ref); free(t->src_sign); free(t->src_E); free(t->thr_src);
     free(t->t_meas); free(t->ic_edges); free(t->ic_dT);
-    free(t->bin); free(t->P_bin); free(t->spec_tab);
+    free(t->bin); free(t->P_bin); free(t->spec_tab); free(t->heat_t); free(t->heat_P);
     free(t);
 }
 
@@ -284,6 +286,25 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
     if (pr->n_ic > 0 && (pr->ic_axis < 0 || pr->ic_axis > 2 || g->n_cyl > 0 || g->n_wall > 0)) return E_INVAL;
     if (pr->score_axis < 0 || pr->score_axis > 2 || pr->max_events < 1 || pr->max_events > 0x3FFFFFF0LL)
         return E_INVAL;
+    /* the external heat source: transient, intervals ascending in [0, t_max], a cuboid inside the
+       box that no pore or line wall reaches into */
+    if (pr->n_heat < 0) return E_INVAL;
+    if (pr->n_heat > 0) {
+        if (!pr->transient || g->n_wall > 0 || !pr->heat_t || !pr->heat_P) return E_INVAL;
+        if (!(pr->heat_t[0] >= 0.0) || !(pr->heat_t[pr->n_heat] <= pr->t_max)) return E_INVAL;
+        for (int k = 0; k < pr->n_heat; ++k)
+            if (!(pr->heat_t[k + 1] > pr->heat_t[k]) || !isfinite(pr->heat_P[k])) return E_INVAL;
+        for (int a = 0; a < 3; ++a)
+            if (!g->unbounded[a] && !(pr->heat_lo[a] >= 0.0 && pr->heat_hi[a] > pr->heat_lo[a] &&
+                                      pr->heat_hi[a] <= g->L[a]))
+                return E_INVAL;
+        for (int c = 0; c < g->n_cyl; ++c) {     /* nearest point of the rectangle to the pore axis */
+            double nx = fmin(fmax(g->cyl[c].cx, pr->heat_lo[0]), pr->heat_hi[0]);
+            double ny = fmin(fmax(g->cyl[c].cy, pr->heat_lo[1]), pr->heat_hi[1]);
+            double dx = nx - g->cyl[c].cx, dy = ny - g->cyl[c].cy;
+            if (dx * dx + dy * dy < g->cyl[c].r * g->cyl[c].r) return E_INVAL;
+        }
+    }
 
     orc_tables* t = (orc_tables*)calloc(1, sizeof(orc_tables));
     if (!t) return E_NOMEM;
@@ -390,7 +411,7 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
 
     /* sources (section 3.1, Eqs. dev_tot and source_energy), in the order: isothermal faces by
        id, gradient source, initial-condition cells */
-    int Smax = 6 + g->n_wall + 1 + (pr->n_ic > 0 ? pr->n_ic : 0);
+    int Smax = 6 + g->n_wall + 1 + (pr->n_ic > 0 ? pr->n_ic : 0) + (pr->n_heat > 0 ? pr->n_heat : 0);
     t->src_kind = (int32_t*)malloc(sizeof(int32_t) * Smax);
     t->src_ref = (int32_t*)malloc(sizeof(int32_t) * Smax);
     t->src_sign = (int32_t*)malloc(sizeof(int32_t) * Smax);
@@ -438,6 +459,26 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
         double E = (t->C_tot * fabs(t->ic_dT[c])) * Vc;
         t->src_kind[S] = S_IC; t->src_ref[S] = c; t->src_sign[S] = t->ic_dT[c] > 0.0 ? 1 : -1; t->src_E[S] = E;
         ++S;
+    }
+    /* the external heat source: the energy of interval k is |P_k| times the cuboid's volume times
+       the interval's length */
+    t->pr.heat_t = NULL;
+    t->pr.heat_P = NULL;
+    if (pr->n_heat > 0) {
+        t->heat_t = (double*)malloc(sizeof(double) * (pr->n_heat + 1));
+        t->heat_P = (double*)malloc(sizeof(double) * pr->n_heat);
+        if (!t->heat_t || !t->heat_P) { orc_free(t); return E_NOMEM; }
+        memcpy(t->heat_t, pr->heat_t, sizeof(double) * (pr->n_heat + 1));
+        memcpy(t->heat_P, pr->heat_P, sizeof(double) * pr->n_heat);
+        double Vh = 1.0;
+        for (int a = 0; a < 3; ++a) Vh *= g->unbounded[a] ? 1.0 : pr->heat_hi[a] - pr->heat_lo[a];
+        for (int k = 0; k < pr->n_heat; ++k) {
+            if (t->heat_P[k] == 0.0) continue;
+            double E = (fabs(t->heat_P[k]) * Vh) * (t->heat_t[k + 1] - t->heat_t[k]);
+            t->src_kind[S] = S_HEAT; t->src_ref[S] = k; t->src_sign[S] = t->heat_P[k] > 0.0 ? 1 : -1;
+            t->src_E[S] = E;
+            ++S;
+        }
     }
     t->S = S;
     if (S == 0) { orc_free(t); return E_TABLE; }
@@ -726,6 +767,14 @@ static int emit(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t pid, 
         p->s = (R2[0] >> 31) ? -1 : 1;
         if (p->s < 0) { p->o[0] = -p->o[0]; p->o[1] = -p->o[1]; p->o[2] = -p->o[2]; }
         p->m = (int32_t)orc_cdf_pick(t->thr_wall, t->M, t->last_wall, key64(R1, 0));
+    } else if (kind == S_HEAT) {
+        /* the external heat source: a point of its cuboid, an isotropic direction and the row of a
+           local temperature rise (weights C, as for the initial condition) */
+        for (int a = 0; a < 3; ++a)
+            p->x[a] = g->unbounded[a] ? 0.0 : t->pr.heat_lo[a] + up[a] * (t->pr.heat_hi[a] - t->pr.heat_lo[a]);
+        orc_dir_iso(ud1, ud2, p->o);
+        p->s = t->src_sign[src];
+        p->m = (int32_t)orc_cdf_pick(t->thr_ic, t->M, t->last_ic, key64(R1, 0));
     } else {
         int c = t->src_ref[src];
         int ia = t->pr.ic_axis;
@@ -736,7 +785,12 @@ static int emit(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t pid, 
         p->s = t->src_sign[src];
         p->m = (int32_t)orc_cdf_pick(t->thr_ic, t->M, t->last_ic, key64(R1, 0));
     }
-    p->t = (t->pr.transient && kind != S_IC) ? unif(R2, 2) * t->pr.t_max : 0.0;
+    if (kind == S_HEAT) {              /* a time uniform in the source's interval */
+        const double t0 = t->heat_t[t->src_ref[src]], t1 = t->heat_t[t->src_ref[src] + 1];
+        p->t = t0 + unif(R2, 2) * (t1 - t0);
+    } else {
+        p->t = (t->pr.transient && kind != S_IC) ? unif(R2, 2) * t->pr.t_max : 0.0;
+    }
     p->dtr = -t->tau[p->m] * log(1.0 - unif(R0, 2));
     if (t->two) set_clocks(p, draw_t2(t, seed, inst, pid, 0u, p->m), p->dtr);
     *src_out = src;

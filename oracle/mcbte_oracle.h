@@ -56,6 +56,12 @@ typedef struct {
     const double* ic_edges;
     const double* ic_dT;
     const double* spec_table;  /* n_spec_tables x M degrees of specularity, table-major */
+    /* external heat source (transient): power density heat_P[k] (W/m^3, signed) over
+       [heat_t[k], heat_t[k+1]) in the cuboid [heat_lo, heat_hi] (bounded axes) */
+    int32_t n_heat, pad_h;
+    double heat_lo[3], heat_hi[3];
+    const double* heat_t;
+    const double* heat_P;
 } orc_problem;
 
 typedef struct orc_tables orc_tables;

@@ -327,6 +327,41 @@ def ballistic_transient(N=200_000, L=3000e-9, v=12360.0, tau=1.0, T_l=303.0, T_r
     }
 
 
+def gaussian_pulse_profile(t0: float, sigma: float, peak: float, n: int, span: float = 3.0):
+    """A Gaussian pulse peak exp(-(t - t0)^2 / (2 sigma^2)) as n equal piecewise-constant intervals
+    over t0 +- span sigma, each holding the pulse's exact mean over it: (edges, values)."""
+    edges = np.linspace(t0 - span * sigma, t0 + span * sigma, n + 1)
+    z = (edges - t0) / (math.sqrt(2.0) * sigma)
+    integral = np.array([0.5 * math.sqrt(2.0 * math.pi) * sigma * (math.erf(z[k + 1]) - math.erf(z[k]))
+                         for k in range(n)])
+    return edges, peak * integral / np.diff(edges)
+
+
+def heated_slab(N=10_000_000, L=1e-6, T=300.0, depth=20e-9, sigma=5e-12, peak=None, t_max=2e-9, n_times=200,
+                n_cells=100, n_profile=12, n_scat_max=0, modes=None, specularity=0.0, seed=SEED_BASE + 12):
+    """Time-domain heating of a free-standing slab (the thermoreflectance setting of the paper's
+    summary): a slab of thickness L along z (in-plane unbounded, adiabatic faces of specularity
+    `specularity`) heated in its top `depth` by a Gaussian pulse of width sigma centred at 3 sigma,
+    tabulated as n_profile intervals; T and q_z in n_cells bins at n_times equally spaced times
+    over (0, t_max).  peak (W/m^3) defaults to the power that deposits 1 K of heat capacity 1.66e6
+    J/(m^3 K) (silicon-like) across the heated layer."""
+    if peak is None:
+        peak = 1.66e6 / (math.sqrt(2.0 * math.pi) * sigma)
+    edges, vals = gaussian_pulse_profile(3.0 * sigma, sigma, peak, n_profile)
+    t_meas = (np.arange(n_times) + 0.5) * (t_max / n_times)
+    prob = _problem(N, T, n_scat_max, transient=True, t_max=t_max, t_meas=t_meas, score_axis=2)
+    prob["heat"] = {"lo": (0.0, 0.0, L - depth), "hi": (1.0, 1.0, L), "t": edges, "P": vals}
+    return {
+        "name": "heated_slab",
+        "modes": silicon_like_modes(T) if modes is None else modes,
+        "geometry": _geometry((1.0, 1.0, L), (True, True, False),
+                              {5: (ADIABATIC, specularity, 0, 0), 6: (ADIABATIC, specularity, 0, 0)}),
+        "detectors": _detectors((0, 0, 0), (0, 0, L), (0, 0, n_cells), MASK_T | MASK_QZ),
+        "problem": prob,
+        "seed": seed,
+    }
+
+
 def bulk_gradient(N=200_000, v=6400.0, Lambda=100e-9, gradT=-1.0e7, n_scat_max=1, modes=None,
                   seed=SEED_BASE + 7, T=300.0):
     """Unbounded bulk driven only by the gradient source (no boundaries at all)."""
