@@ -119,6 +119,10 @@ def workload(name: str, scale: float = 1.0):
                 f"porous_cell_500nm_phi0.25_N1e8_nscat{W.C5_NSCAT}")
     if name == "transient":
         return W.transient_bump(N=int(10_000_000 * scale)), "transient_bump_1um_200times_100bins_N1e7"
+    if name == "heated_slab":
+        # time-domain heating: a 5 ps Gaussian pulse into the top 20 nm of a 1 um slab
+        return (W.heated_slab(N=int(10_000_000 * scale)),
+                "heated_slab_1um_pulse5ps_depth20nm_200times_100bins_N1e7")
     if name == "sweep":
         return W.film_sweep(scale=scale), "film_sweep_16d_x_4T_64instances_N7.2e7"
     raise SystemExit(f"unknown workload {name}")
@@ -520,7 +524,7 @@ def other_forms(args, M, torch) -> dict:
     forms = {}
     plan = [("film_fp32", "film", 32, 20), ("gray_slab_fp64", "gray_slab", 64, 10), ("film_fp64", "film", 64, 5),
             ("transient_fp32", "transient", 32, 3), ("film_two_clocks_fp32", "film_two_clocks", 32, 10),
-            ("film_ziman_specularity_fp32", "film_ziman", 32, 10),
+            ("film_ziman_specularity_fp32", "film_ziman", 32, 10), ("heated_slab_fp32", "heated_slab", 32, 3),
             ("porous_cell_specular_below_2THz_fp32", "porous_cell_spec2thz", 32, 5)]
     # each configuration is tuned on at most 1e6 particles with one timed launch per candidate
     # (the calibration stays outside the timed steps but inside the run's few minutes)

@@ -175,7 +175,18 @@ typedef struct {
    MCBTE_CNT_CAP_END).  score_axis: flux component used for kappa and its standard error.
    spec_table: n_spec_tables tables of n_modes degrees of specularity in [0, 1] each (row-major),
    referenced by the boundaries' spec_table numbers (section 3.5.3); may be NULL when
-   n_spec_tables = 0.  All pointers are host pointers, read during mcbte_build_tables only. */
+   n_spec_tables = 0.
+   External heat source (transient only; the phonon generation by an external source that the
+   summary section names for time-domain thermoreflectance): deviational power density heat_P[k]
+   (W m^-3, either sign) over [heat_t[k], heat_t[k+1]), k < n_heat, in the cuboid
+   [heat_lo, heat_hi] (bounded axes; an unbounded axis takes its whole 1 m).  Interval k is a
+   source of energy |heat_P[k]| V_heat (heat_t[k+1] - heat_t[k]) and sign that of heat_P[k]; its
+   particles start at a time uniform in the interval, at a position uniform in the cuboid, with a
+   row drawn by heat capacity (the equilibrium distribution of a temperature rise, as for the
+   initial condition) and an isotropic direction (emission record 2, words W2W3, gives the time).
+   The cuboid lies inside the box and inside the solid (no pore or line wall reaches into it);
+   0 <= heat_t[0] < ... <= t_max.  n_heat = 0: none.
+   All pointers are host pointers, read during mcbte_build_tables only. */
 typedef struct {
     int64_t N, max_events;
     double T_lin, t_max;
@@ -185,6 +196,10 @@ typedef struct {
     const double* ic_edges;
     const double* ic_dT;
     const double* spec_table;
+    int32_t n_heat, reserved;
+    double heat_lo[3], heat_hi[3];
+    const double* heat_t;
+    const double* heat_P;
 } mcbte_problem;
 
 typedef struct mcbte_tables mcbte_tables;

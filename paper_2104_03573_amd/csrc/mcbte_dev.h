@@ -20,7 +20,8 @@
 
 namespace mcbte {
 
-enum SourceKind : int32_t { SRC_WALL = 0, SRC_GRAD = 1, SRC_IC = 2, SRC_IWALL = 3 };   // SRC_IWALL: isothermal line wall
+// SRC_IWALL: isothermal line wall; SRC_HEAT: one time interval of the external heat source
+enum SourceKind : int32_t { SRC_WALL = 0, SRC_GRAD = 1, SRC_IC = 2, SRC_IWALL = 3, SRC_HEAT = 4 };
 enum TallyKind : int32_t { TALLY_STEADY_ONE = 0, TALLY_STEADY_GRID = 1, TALLY_TRANSIENT = 2 };
 
 // optional features of the trace kernels, compiled in only where used: particles loaded from a
@@ -126,6 +127,7 @@ struct DevTab {
     const int32_t* src_ref;
     const int32_t* src_sign;
     const double* ic_edges;
+    const double* heat_t;        // external heat source: interval edges (n_heat + 1), or NULL
     const double* t_meas64;
     const float* t_meas32;
     const int32_t* bin_of;       // frequency bin of each mode (sensitivity parameters)
@@ -144,6 +146,9 @@ struct DevTab {
     int32_t two;                 // some row has a two-phonon clock
     int32_t spec_w;              // some boundary's specularity depends on the phonon (a per-row table)
     int32_t lattice;             // the cell tiles a lattice of pores (lat_min_path > 0)
+    // external heat source region: corner and widths per axis (0 and 1 m along an unbounded axis)
+    double heat_lo[3], heat_w[3];
+    float heat_lo32[3], heat_w32[3];
     DevGeom g;
     DevDet det;
 };

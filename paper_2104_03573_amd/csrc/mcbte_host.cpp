@@ -100,6 +100,7 @@ struct mcbte_tables {
     mcbte_detectors det{};
     // host tables
     std::vector<double> C, v, tau, tau2, src_E, ic_edges, ic_dT, t_meas;   // tau2: two-phonon clock (0: none)
+    std::vector<double> heat_t, heat_P;   // external heat source: interval edges and power densities
     bool two = false;      // some row has a two-phonon clock
     bool spec_w = false;   // some boundary has a specular cutoff frequency
     bool walls = false;    // internal line walls
@@ -277,6 +278,22 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     } else if (pr.n_ic > 0) {
         return MCBTE_EINVAL;
     }
+    // external heat source: transient, ascending edges in [0, t_max], a cuboid inside the box and the solid
+    if (pr.n_heat < 0 || pr.reserved != 0) return MCBTE_EINVAL;
+    if (pr.n_heat > 0) {
+        if (!pr.transient || !pr.heat_t || !pr.heat_P || g.n_walls > 0) return MCBTE_EINVAL;
+        if (!(pr.heat_t[0] >= 0.0) || !(pr.heat_t[pr.n_heat] <= pr.t_max)) return MCBTE_EINVAL;
+        for (int k = 0; k < pr.n_heat; ++k)
+            if (!(pr.heat_t[k + 1] > pr.heat_t[k]) || !std::isfinite(pr.heat_P[k])) return MCBTE_EINVAL;
+        for (int a = 0; a < 3; ++a)
+            if (!g.unbounded[a] && !(pr.heat_lo[a] >= 0.0 && pr.heat_hi[a] > pr.heat_lo[a] && pr.heat_hi[a] <= g.L[a]))
+                return MCBTE_EINVAL;
+        for (int c = 0; c < g.n_pores; ++c) {   // the pore's disc keeps off the region's rectangle
+            const double dx = std::max({pr.heat_lo[0] - g.pore[c].cx, 0.0, g.pore[c].cx - pr.heat_hi[0]});
+            const double dy = std::max({pr.heat_lo[1] - g.pore[c].cy, 0.0, g.pore[c].cy - pr.heat_hi[1]});
+            if (dx * dx + dy * dy < g.pore[c].r * g.pore[c].r) return MCBTE_EINVAL;
+        }
+    }
     if (pr.n_ic < 0 || (pr.n_ic > 0 && (!pr.ic_edges || !pr.ic_dT || pr.ic_axis < 0 || pr.ic_axis > 2 || g.n_pores > 0 ||
                                         g.n_walls > 0)))
         return MCBTE_EINVAL;
@@ -287,6 +304,8 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     t->prob = pr;
     t->prob.t_meas = nullptr;
     t->prob.ic_edges = nullptr;
+    t->prob.heat_t = nullptr;
+    t->prob.heat_P = nullptr;
     t->prob.ic_dT = nullptr;
     t->prob.spec_table = nullptr;
     t->geom = g;
@@ -410,6 +429,20 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         t->src_sign.push_back(t->ic_dT[c] > 0.0 ? 1 : -1);
         t->src_E.push_back(E);
     }
+    // the external heat source, one source per time interval: |P_k| V_heat (t_k+1 - t_k)
+    if (pr.n_heat > 0) {
+        t->heat_t.assign(pr.heat_t, pr.heat_t + pr.n_heat + 1);
+        t->heat_P.assign(pr.heat_P, pr.heat_P + pr.n_heat);
+        double Vh = 1.0;
+        for (int a = 0; a < 3; ++a) Vh *= g.unbounded[a] ? 1.0 : pr.heat_hi[a] - pr.heat_lo[a];
+        for (int k = 0; k < pr.n_heat; ++k) {
+            if (t->heat_P[k] == 0.0) continue;
+            t->src_kind.push_back(SRC_HEAT);
+            t->src_ref.push_back(k);
+            t->src_sign.push_back(t->heat_P[k] > 0.0 ? 1 : -1);
+            t->src_E.push_back((std::fabs(t->heat_P[k]) * Vh) * (t->heat_t[k + 1] - t->heat_t[k]));
+        }
+    }
     const int S = (int)t->src_E.size();
     if (S == 0) { delete t; return MCBTE_ETABLE; }
     double E_tot = 0.0;
@@ -525,6 +558,13 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     h.last_wall = last_wall;
     h.last_rel = last_rel;
     h.last_src = last_src;
+    for (int a = 0; a < 3; ++a) {
+        const bool on = pr.n_heat > 0 && !g.unbounded[a];
+        h.heat_lo[a] = on ? pr.heat_lo[a] : 0.0;
+        h.heat_w[a] = on ? pr.heat_hi[a] - pr.heat_lo[a] : 1.0;
+        h.heat_lo32[a] = (float)h.heat_lo[a];
+        h.heat_w32[a] = (float)h.heat_w[a];
+    }
     DevGeom& dg = h.g;
     // per-row specularity: a boundary with a table of the problem reads it; a boundary with a cutoff
     // frequency reads the table of its special case (1 below the cutoff, d above it); equal tables
@@ -696,6 +736,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         add(t->prio_thr.data(), 8 * t->prio_thr.size());
         add(t->spec_thr.data(), 8 * t->spec_thr.size());
         add(t->spec_cls.data(), t->spec_cls.size());
+        add(t->heat_t.data(), 8 * t->heat_t.size());
         size_t total = 0;
         std::vector<size_t> off;
         for (auto& p : parts) {
@@ -732,6 +773,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         h.prio_list_off = t->prio_thr.empty() ? 0 : t->info.tally_bytes - 8 * (int64_t)MCBTE_PRIO_CAP;
         h.spec_thr = t->spec_thr.empty() ? nullptr : (const uint64_t*)dptr(21);
         h.spec_cls = t->spec_cls.empty() ? nullptr : (const uint8_t*)dptr(22);
+        h.heat_t = t->heat_t.empty() ? nullptr : (const double*)dptr(23);
         parts[0].first = &h;
         for (size_t i = 0; i < parts.size(); ++i) {
             if (parts[i].second == 0) continue;

@@ -127,6 +127,8 @@ template <> struct Geo<double> {
     static __device__ __forceinline__ const double* tau(const DevTab& t) { return t.tau64; }
     static __device__ __forceinline__ const double* tau2(const DevTab& t) { return t.tau2_64; }
     static __device__ __forceinline__ const DevPore64& pore(const DevGeom& g, int i) { return g.pore64[i]; }
+    static __device__ __forceinline__ double heat_lo(const DevTab& t, int a) { return t.heat_lo[a]; }
+    static __device__ __forceinline__ double heat_w(const DevTab& t, int a) { return t.heat_w[a]; }
     static constexpr int prec = 1;
 };
 template <> struct Geo<float> {
@@ -147,6 +149,8 @@ template <> struct Geo<float> {
     static __device__ __forceinline__ const float* tau(const DevTab& t) { return t.tau32; }
     static __device__ __forceinline__ const float* tau2(const DevTab& t) { return t.tau2_32; }
     static __device__ __forceinline__ const DevPore32& pore(const DevGeom& g, int i) { return g.pore32[i]; }
+    static __device__ __forceinline__ float heat_lo(const DevTab& t, int a) { return t.heat_lo32[a]; }
+    static __device__ __forceinline__ float heat_w(const DevTab& t, int a) { return t.heat_w32[a]; }
     static constexpr int prec = 0;
 };
 
@@ -386,6 +390,15 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
             p.o[2] = -p.o[2];
         }
         p.m = cdf_pick(T.thr_wall, T.M, T.last_wall, key64(r1a.x, r1a.y));
+    } else if (kind == SRC_HEAT) {
+        // the external heat source: a point of its cuboid, an isotropic direction, the row drawn
+        // by heat capacity (as for the initial condition)
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+            p.x[ax] = g.unb[ax] ? R(0) : Geo<R>::heat_lo(T, ax) + up[ax] * Geo<R>::heat_w(T, ax);
+        dir_iso(ud1, ud2, p.o);
+        p.s = T.src_sign[src];
+        p.m = cdf_pick(T.thr_ic, T.M, T.last_ic, key64(r1a.x, r1a.y));
     } else {
         const int c = T.src_ref[src];
         const int ia = T.ic_axis;
@@ -398,7 +411,12 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
         p.s = T.src_sign[src];
         p.m = cdf_pick(T.thr_ic, T.M, T.last_ic, key64(r1a.x, r1a.y));
     }
-    p.t = (T.transient && kind != SRC_IC) ? unif<R>(r2a.z, r2a.w) * (R)T.t_max : R(0);
+    if (kind == SRC_HEAT) {   // a time uniform in the source's interval
+        const int k = T.src_ref[src];
+        p.t = (R)T.heat_t[k] + unif<R>(r2a.z, r2a.w) * (R)(T.heat_t[k + 1] - T.heat_t[k]);
+    } else {
+        p.t = (T.transient && kind != SRC_IC) ? unif<R>(r2a.z, r2a.w) * (R)T.t_max : R(0);
+    }
     const R tau = Geo<R>::tau(T)[p.m];
     p.dtr = -tau * r_log(R(1) - unif<R>(r0a.z, r0a.w));
     if (kf) *kf = key64(r0a.z, r0a.w) >> 11;

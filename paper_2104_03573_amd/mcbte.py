@@ -66,7 +66,9 @@ class ProblemC(C.Structure):
                 ("score_axis", C.c_int32), ("n_times", C.c_int32), ("ic_axis", C.c_int32), ("n_ic", C.c_int32),
                 ("n_spec_tables", C.c_int32), ("t_meas", C.POINTER(C.c_double)),
                 ("ic_edges", C.POINTER(C.c_double)), ("ic_dT", C.POINTER(C.c_double)),
-                ("spec_table", C.POINTER(C.c_double))]
+                ("spec_table", C.POINTER(C.c_double)), ("n_heat", C.c_int32), ("reserved", C.c_int32),
+                ("heat_lo", C.c_double * 3), ("heat_hi", C.c_double * 3), ("heat_t", C.POINTER(C.c_double)),
+                ("heat_P", C.POINTER(C.c_double))]
 
 
 class Info(C.Structure):
@@ -231,6 +233,15 @@ def structs_from_workload(w: dict):
                  p["score_axis"], len(keep[0]) if p["transient"] else 0, p["ic_axis"], len(keep[2]), spec.shape[0],
                  keep[0].ctypes.data_as(dp), keep[1].ctypes.data_as(dp), keep[2].ctypes.data_as(dp),
                  spec.ctypes.data_as(dp) if spec.shape[0] else None)
+    heat = p.get("heat")
+    if heat is not None:
+        ht = np.ascontiguousarray(heat["t"], dtype=np.float64)
+        hP = np.ascontiguousarray(heat["P"], dtype=np.float64)
+        keep += [ht, hP]
+        P.n_heat = len(hP)
+        for a in range(3):
+            P.heat_lo[a], P.heat_hi[a] = heat["lo"][a], heat["hi"][a]
+        P.heat_t, P.heat_P = ht.ctypes.data_as(dp), hP.ctypes.data_as(dp)
     return modes, G, D, P, keep
 
 

@@ -37,7 +37,8 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.parametrize("make", [lambda: W.gray_slab(N=1000), lambda: W.film(N=1000),
                                   lambda: W.transient_bump(N=1000), lambda: W.porous_cell(N=1000),
                                   lambda: W.ballistic_transient(N=100), lambda: W.bulk_gradient(N=10),
-                                  lambda: W.film(N=7, d=3e-8, T=100.0, specularity=0.3)])
+                                  lambda: W.film(N=7, d=3e-8, T=100.0, specularity=0.3),
+                                  lambda: W.heated_slab(N=100, t_max=100e-12, n_times=4, n_cells=4)])
 def test_host_tables_identical_to_oracle(make):
     w = make()
     t = M.Tables(w, device=-1)
@@ -180,6 +181,41 @@ def test_specularity_table_inputs():
         assert _status(w) == M.mcbte.EINVAL
         with pytest.raises(ValueError):
             oracle.Tables(w)
+
+
+def test_heat_source_inputs():
+    """The external heat source: transient only, ascending edges inside [0, t_max], finite power
+    densities, a cuboid inside the box that no pore reaches into, no line walls; the library and
+    the oracle refuse the same inputs."""
+    ok = W.heated_slab(N=10, t_max=100e-12, n_times=4, n_cells=4)
+    assert _status(ok) == 0
+    t = M.Tables(ok, device=-1)
+    heat = ok["problem"]["heat"]
+    assert t.info["n_sources"] == len(heat["P"]) == oracle.Tables(ok).S
+
+    def hv(**kw):
+        w = W.with_(ok)
+        w["problem"]["heat"] = dict(heat, **kw)
+        return w
+
+    cell = W.with_(W.porous_cell(N=10), **{"problem.transient": True, "problem.t_max": 1e-11,
+                                           "problem.t_meas": np.array([5e-12])})
+    bad = [W.with_(ok, **{"problem.transient": False, "problem.t_meas": np.zeros(0)}),
+           hv(t=heat["t"][::-1].copy()),                                   # not ascending
+           hv(t=heat["t"] + 1.0),                                          # past t_max
+           hv(P=np.full(len(heat["P"]), np.inf)),
+           hv(lo=(0.0, 0.0, 0.5e-6), hi=(1.0, 1.0, 2e-6)),                 # outside the box
+           hv(lo=(0.0, 0.0, 0.6e-6), hi=(1.0, 1.0, 0.5e-6)),               # empty
+           W.with_(cell, **{"problem.heat": {"lo": (100e-9, 0.0, 0.0), "hi": (200e-9, 500e-9, 500e-9),
+                                             "t": np.array([0.0, 1e-12]), "P": np.array([1e16])}})]   # the pore
+    for w in bad:
+        assert _status(w) == M.mcbte.EINVAL
+        with pytest.raises(ValueError):
+            oracle.Tables(w)
+    beside = W.with_(cell, **{"problem.heat": {"lo": (0.0, 0.0, 0.0), "hi": (100e-9, 500e-9, 500e-9),
+                                               "t": np.array([0.0, 1e-12]), "P": np.array([1e16])}})
+    assert _status(beside) == 0
+    oracle.Tables(beside)
 
 
 def test_sizes_and_messages():

@@ -66,6 +66,14 @@ FP64_CASES = {
     "porous_spec_table_binary": lambda: W.with_spec_table(W.porous_cell(N=1500),
                                                           W.random_specularity(1400, 6, binary=True)),
     "walled_spec_table": lambda: W.with_spec_table(W.walled_film(N=1500), W.random_specularity(1400, 7)),
+    # the external heat source: a Gaussian pulse in the top layer of a slab; heating then cooling
+    # in a strip of the porous cell beside its pore (with the gradient source of the cell)
+    "heated_slab": lambda: W.heated_slab(N=1500, t_max=100e-12, n_times=20, n_cells=20),
+    "porous_heat": lambda: W.with_(W.porous_cell(N=1200), **{
+        "problem.transient": True, "problem.t_max": 60e-12, "problem.t_meas": np.array([10e-12, 30e-12, 59e-12]),
+        "detectors.lo": (0.0, 0.0, 0.0), "detectors.hi": (500e-9, 0.0, 0.0), "detectors.n": (5, 0, 0),
+        "problem.heat": {"lo": (0.0, 0.0, 0.0), "hi": (80e-9, 500e-9, 500e-9), "t": np.array([0.0, 5e-12, 20e-12]),
+                         "P": np.array([2e17, -5e16])}}),
     # internal line walls: the paper's square pore of four walls, a channel between two walls
     "square_pore_walls": lambda: W.square_pore_cell(N=1000),
     "square_pore_walls_partial": lambda: W.square_pore_cell(N=800, specularity=0.5),
