@@ -425,6 +425,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other configurations (thin film, gray slab FP64, transient, batched sweep, "
                          "sensitivities) reported under 'forms'")
+    ap.add_argument("--only-form", default=None, metavar="KEY",
+                    help="run just one of the configurations reported under 'forms' and print it")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -451,6 +453,13 @@ def main():
 
     import paper_2104_03573_amd as M
 
+    if args.only_form:
+        torch.cuda.set_device(torch.device("cuda:0"))
+        forms = other_forms(args, M, torch, only=args.only_form)
+        if not forms:
+            raise SystemExit(f"unknown form {args.only_form}")
+        print(json.dumps({"form": args.only_form, **forms[args.only_form]}), flush=True)
+        return
     w, wname = workload(args.workload, args.scale)
     torch.cuda.set_device(torch.device("cuda:0"))
     dtype = "f32" if args.precision == 32 else "f64"
@@ -519,9 +528,15 @@ def _brief(m: dict, workload: str, precision: int) -> dict:
     return r
 
 
-def other_forms(args, M, torch) -> dict:
-    """The remaining configurations, a few steps each, every one timed like the main line."""
+def other_forms(args, M, torch, only: str | None = None) -> dict:
+    """The remaining configurations, a few steps each, every one timed like the main line (only:
+    just the form of that key).  A form's HBM traffic is the committed rocprofv3 figure of its
+    kernel and workload while the kernel source is unchanged since it was taken."""
     forms = {}
+
+    def want(key):
+        return only is None or only == key
+
     plan = [("film_fp32", "film", 32, 20), ("gray_slab_fp64", "gray_slab", 64, 10), ("film_fp64", "film", 64, 5),
             ("transient_fp32", "transient", 32, 3), ("film_two_clocks_fp32", "film_two_clocks", 32, 10),
             ("film_ziman_specularity_fp32", "film_ziman", 32, 10), ("heated_slab_fp32", "heated_slab", 32, 3),
@@ -529,43 +544,52 @@ def other_forms(args, M, torch) -> dict:
     # each configuration is tuned on at most 1e6 particles with one timed launch per candidate
     # (the calibration stays outside the timed steps but inside the run's few minutes)
     for key, name, prec, steps in plan:
+        if not want(key):
+            continue
         w, wname = workload(name, 1.0)
         print(f"[bench] form {key}: {wname}", file=sys.stderr, flush=True)
         forms[key] = _brief(measure(args, w, M, torch, prec, steps, 1, 1, 1_000_000, 1), wname, prec)
+        forms[key]["traffic"] = profiled_traffic(f"k_trace_solo_{name}_fp{prec}")
     # the main line's launches each end with a tail (the last particles of every wave, one
     # flight after another) of about half a launch; a job of many batches overlaps one batch's
     # tail with the next batch on a second stream (throughput by wall clock, no roofline figure)
     w, wname = workload("film", 1.0)
-    print(f"[bench] form film_fp32_two_streams: {wname}", file=sys.stderr, flush=True)
-    mf = measure(args, w, M, torch, 32, 20, 3, 2, 1_000_000, 1)
-    forms["film_fp32_two_streams"] = {
-        "workload": wname, "precision": 32, "streams": 2, "steps": 20, "flights_per_s": mf["flights_per_s"],
-        "ms_per_step": mf["ms_per_step"], "launch": mf["launch"], "kappa_eff": mf.get("kappa_eff"),
-        "kappa_sigma": mf.get("kappa_sigma")}
+    if want("film_fp32_two_streams"):
+        print(f"[bench] form film_fp32_two_streams: {wname}", file=sys.stderr, flush=True)
+        mf = measure(args, w, M, torch, 32, 20, 3, 2, 1_000_000, 1)
+        forms["film_fp32_two_streams"] = {
+            "workload": wname, "precision": 32, "streams": 2, "steps": 20, "flights_per_s": mf["flights_per_s"],
+            "ms_per_step": mf["ms_per_step"], "launch": mf["launch"], "kappa_eff": mf.get("kappa_eff"),
+            "kappa_sigma": mf.get("kappa_sigma")}
     # the same pore cell traced one segment at a time (no pore-to-pore walk by the wave): the
     # step then waits for the few particles of the longest free paths, one lane each
     w, wname = workload("porous_cell", 1.0)
-    print(f"[bench] form porous_cell_fp32_segments: {wname}", file=sys.stderr, flush=True)
-    seg_args = argparse.Namespace(**dict(vars(args), segments=True))
-    forms["porous_cell_fp32_segments"] = _brief(measure(seg_args, w, M, torch, 32, 4, 1, 1, 1_000_000, 1),
-                                                wname, 32)
+    if want("porous_cell_fp32_segments"):
+        print(f"[bench] form porous_cell_fp32_segments: {wname}", file=sys.stderr, flush=True)
+        seg_args = argparse.Namespace(**dict(vars(args), segments=True))
+        forms["porous_cell_fp32_segments"] = _brief(measure(seg_args, w, M, torch, 32, 4, 1, 1, 1_000_000, 1),
+                                                    wname, 32)
     # a job of several batches overlaps each batch's tail (its last particles) with the next
     # batches on other streams (throughput by wall clock; the per-launch event times then include
     # the overlap, so no roofline figure is given for it)
-    print(f"[bench] form porous_cell_fp32_four_streams: {wname}", file=sys.stderr, flush=True)
-    m2 = measure(args, w, M, torch, 32, 8, 2, 4, 1_000_000, 1)
-    forms["porous_cell_fp32_four_streams"] = {
-        "workload": wname, "precision": 32, "streams": 4, "steps": 8, "flights_per_s": m2["flights_per_s"],
-        "ms_per_step": m2["ms_per_step"], "launch": m2["launch"], "kappa_eff": m2.get("kappa_eff"),
-        "kappa_sigma": m2.get("kappa_sigma")}
-    ws, wname = workload("sweep", 1.0)
-    print(f"[bench] form batched_sweep_fp32: {wname}", file=sys.stderr, flush=True)
-    forms["batched_sweep_fp32"] = _brief(measure_batched(args, ws, M, torch, 32, 3, 1, 8_000_000, 1), wname, 32)
-    w, wname = workload("porous_cell", 1.0)
-    print(f"[bench] form sensitivities: {wname}", file=sys.stderr, flush=True)
-    sens = measure_sensitivity(args, w, M, torch, ("score", "local"), 5)
-    sens["workload"] = wname
-    forms["porous_cell_sensitivities_fp32"] = sens
+    if want("porous_cell_fp32_four_streams"):
+        print(f"[bench] form porous_cell_fp32_four_streams: {wname}", file=sys.stderr, flush=True)
+        m2 = measure(args, w, M, torch, 32, 8, 2, 4, 1_000_000, 1)
+        forms["porous_cell_fp32_four_streams"] = {
+            "workload": wname, "precision": 32, "streams": 4, "steps": 8, "flights_per_s": m2["flights_per_s"],
+            "ms_per_step": m2["ms_per_step"], "launch": m2["launch"], "kappa_eff": m2.get("kappa_eff"),
+            "kappa_sigma": m2.get("kappa_sigma")}
+    if want("batched_sweep_fp32"):
+        ws, wname = workload("sweep", 1.0)
+        print(f"[bench] form batched_sweep_fp32: {wname}", file=sys.stderr, flush=True)
+        forms["batched_sweep_fp32"] = _brief(measure_batched(args, ws, M, torch, 32, 3, 1, 8_000_000, 1), wname, 32)
+        forms["batched_sweep_fp32"]["traffic"] = profiled_traffic("k_trace_batch_sweep_fp32")
+    if want("porous_cell_sensitivities_fp32"):
+        w, wname = workload("porous_cell", 1.0)
+        print(f"[bench] form sensitivities: {wname}", file=sys.stderr, flush=True)
+        sens = measure_sensitivity(args, w, M, torch, ("score", "local"), 5)
+        sens["workload"] = wname
+        forms["porous_cell_sensitivities_fp32"] = sens
     return forms
 
 

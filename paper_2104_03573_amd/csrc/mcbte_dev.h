@@ -108,6 +108,9 @@ struct DevTab {
     int32_t ic_axis, n_ic;
     int32_t tally_kind;          // TallyKind
     int32_t coop_axis;           // film axis for wave-cooperative diffuse bouncing (FP32), -1: off
+    int32_t fold_axis;           // film axis whose two walls reflect every phonon alike, -1: off (the
+                                 // FP32 trace then runs a specular phonon's wall-to-wall crossings at once)
+    int32_t pad_f;
     double coop_min_path;        // remaining free path (m) above which a wall bounce turns cooperative
     double lat_min_path;         // pore lattice: remaining free path (m) above which the wave walks the
                                  // particle from pore to pore (0: the geometry is not such a lattice)

@@ -488,6 +488,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     // cell): a particle with a long free path bounces between the two walls many times in a row,
     // which the FP32 kernel evaluates 64 bounces at a time with the whole wave
     h.coop_axis = -1;
+    h.fold_axis = -1;
     h.coop_min_path = 0.0;
     {
         int nb = 0, axis = -1;
@@ -510,6 +511,23 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
             }
             if (diffuse) {
                 h.coop_axis = axis;
+                h.coop_min_path = 16.0 * g.L[axis];
+            }
+            // both walls adiabatic with the same specularity rule: a phonon the walls reflect
+            // specularly crosses the film wall to wall until its free path runs out
+            bool same = true;
+            const mcbte_face* first = nullptr;
+            for (int i = 0; i < 6; ++i) {
+                if (kFaceAxis[i] != axis) continue;
+                const mcbte_face& f = g.face[i];
+                if (f.type != MCBTE_ADIABATIC) same = false;
+                if (first && (f.data[0] != first->data[0] || f.data[1] != first->data[1] ||
+                              f.spec_table != first->spec_table))
+                    same = false;
+                first = &f;
+            }
+            if (same) {
+                h.fold_axis = axis;
                 h.coop_min_path = 16.0 * g.L[axis];
             }
         }

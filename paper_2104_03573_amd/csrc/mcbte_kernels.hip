@@ -772,13 +772,16 @@ struct Hot {
     uint32_t det_slot;   // 8 bits per tally component: compact slot
     int32_t det_mask, det_ncomp;
     int32_t n_pores, max_events, n_scat_max, M, last_rel, transient, score_axis, coop_axis;
+    int32_t fold_axis;   // film axis whose specular crossings run at once (FP32 trace), -1: off
     R p0cx, p0cy, p0r;   // the first pore (most geometries have at most one)
     int32_t p0id;
     int32_t grid_axis;   // the one detector axis with more than one cell, if only one has (else -1)
 };
 
+// fold: the launch may run a specular phonon's film crossings at once (not when it records each
+// particle's flux score for a replay, which steps them one at a time)
 template <typename R>
-__device__ __forceinline__ Hot<R> load_hot(const DevTab& T)
+__device__ __forceinline__ Hot<R> load_hot(const DevTab& T, bool fold = false)
 {
     const DevGeom& g = T.g;
     Hot<R> h;
@@ -804,6 +807,7 @@ __device__ __forceinline__ Hot<R> load_hot(const DevTab& T)
     h.transient = T.transient;
     h.score_axis = T.score_axis;
     h.coop_axis = T.coop_axis;
+    h.fold_axis = (fold && std::is_same<R, float>::value) ? T.fold_axis : -1;
     const auto P0 = Geo<R>::pore(g, 0);
     h.p0cx = P0.cx;
     h.p0cy = P0.cy;
@@ -1228,6 +1232,56 @@ __device__ __forceinline__ bool lone_chain(const Hot<R>& H, const TallyCtx& tc, 
     return escaped;
 }
 
+// A phonon on a film wall, just reflected specularly, whose walls reflect it specularly: until its
+// free path runs out it crosses the film wall to wall, each crossing a chord L / |Omega_a| long
+// with the film-axis direction flipped at every wall.  The n complete crossings are run at once:
+// the in-plane coordinates and scores advance by n chords along the unchanged in-plane direction,
+// the film-axis score by the net displacement between the walls (L for an odd n, else 0), n
+// specular reflections and n segments are counted, and the particle is left on the wall it reaches
+// with the last partial segment to the one-segment step.  The lengths are taken in FP64 (the
+// remaining path is a small difference of large numbers).  The segment cap stays with the step.
+template <typename R>
+__device__ __forceinline__ void fold_crossings(const Hot<R>& H, const TallyCtx& tc, Part<R>& p, LaneCounts& cnt,
+                                               R vm, R sg, int fa)
+{
+    const double L = (double)H.L[fa];
+    const double oa = (double)(fa == 0 ? p.o[0] : (fa == 1 ? p.o[1] : p.o[2]));
+    const double chord = L / fabs(oa);
+    const double lam = (double)vm * (double)p.dtr;
+    double nd = floor(lam / chord);
+    const double room = (double)H.max_events - (double)p.k - 1.0;
+    nd = nd < room ? nd : room;
+    if (!(nd >= 1.0)) return;
+    const uint32_t n = (uint32_t)nd;
+    const double len = nd * chord;
+    const bool odd = (n & 1u) != 0u;
+    double dq[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        dq[a] = a == fa ? (odd ? (oa > 0.0 ? L : -L) : 0.0) : len * (double)(a == 0 ? p.o[0] : (a == 1 ? p.o[1] : p.o[2]));
+    const double s = (double)sg;
+    const double tT = s * (len / (double)vm);
+    for (int q = 0; q < 4; ++q)
+        if ((H.det_mask >> q) & 1) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)p.m, q, q == 0 ? tT : s * dq[q - 1]);
+    p.cT += tT;
+    p.cq += s * dq[H.score_axis];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a == fa) {
+            const bool at_far = (p.x[a] > R(0.5) * H.L[a]) != odd;
+            p.x[a] = at_far ? H.L[a] : R(0);
+            if (odd) p.o[a] = -p.o[a];
+        } else {
+            p.x[a] = (R)((double)p.x[a] + dq[a]);
+        }
+    }
+    p.dtr = (R)((lam - len) / (double)vm);
+    p.t = (R)((double)p.t + len / (double)vm);
+    p.k += n;
+    cnt.c[1] += n;
+    cnt.c[3] += n;
+}
+
 // Advance particle p by one segment; returns true when the particle has ended.  With `chain`
 // set (the lane is the last one of its wave still tracing), the periodic transfers and pore
 // reflections ahead of it run first in lone_chain; with `spread` set (a sparse wave), a
@@ -1509,9 +1563,11 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     // film-like problem: a diffuse reflection off the film wall with a long free path left is
     // handed to the whole wave, which runs the coming bounces 64 at a time (coop_bounces for the
     // FP32 trajectories, which it does not log; coop_exact for the FP64 ones)
+    // (FP32 trace: also walls that reflect this phonon partly specularly, the same on both walls)
     constexpr bool COOP = std::is_same<R, float>::value || (FT & FT_COOP) != 0;
-    if (COOP && ev == 1 && H.coop_axis >= 0 && fa == H.coop_axis && (std::is_same<R, double>::value || !lg.row) &&
-        vm * p.dtr > H.coop_min && (!EXT || cls == SURF_DIFFUSE)) {
+    if (COOP && ev == 1 && fa >= 0 && (std::is_same<R, double>::value || !lg.row) && vm * p.dtr > H.coop_min &&
+        ((cls == SURF_DIFFUSE && fa == H.coop_axis) ||
+         (std::is_same<R, float>::value && cls == SURF_PARTIAL && fa == H.fold_axis))) {
         if (AK == 2) pc.plane(fa, false);    // the chain starts with a diffuse reflection
         coop = true;
         return false;
@@ -1621,6 +1677,12 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         }
         ++cnt.c[3];
         lg.put(EV_SPECULAR, hit, p.m);
+        // a film whose walls reflect this phonon specularly: its next wall-to-wall crossings until
+        // the free path runs out, at once (FP32 trace)
+        if constexpr (std::is_same<R, float>::value && AK == 0) {
+            if (fa >= 0 && fa == H.fold_axis && cls == SURF_SPECULAR && !lg.row && vm * p.dtr > H.coop_min)
+                fold_crossings(H, tc, p, cnt, vm, sg, fa);
+        }
     }
     return false;
 }
@@ -1642,20 +1704,23 @@ __device__ __forceinline__ T wave_sum(T v)
 // wave-cooperative bouncing in a film (FP32 form)
 // ------------------------------------------------------------------------------------------
 
-// The particle of lane `leader` sits on a wall of the film, about to be reflected diffusely, with
-// remaining free path lam = v dt_rem.  Its next reflections draw the records the sequential loop
-// would draw (record 2 + j + 1 + k for the k-th), and between two reflections it crosses the film
-// wall to wall (chord L / |Omega_axis|), so 64 lanes evaluate 64 consecutive bounces at once: each
-// lane draws its bounce's direction, a prefix sum of the chords finds the bounce during which the
-// free path runs out, and the completed segments are scored with one reduction.  The particle is
-// handed back at the start of its last (partial) segment; the sequential loop then ends that
-// segment with the relaxation.
+// The particle of lane `leader` sits on a wall of the film, about to be reflected diffusely or
+// partly specularly, with remaining free path lam = v dt_rem.  Its next reflections draw the records
+// the sequential loop would draw (record 2 + j + 1 + k for the k-th), and between two reflections
+// it crosses the film wall to wall (chord L / |Omega_axis|), so 64 lanes evaluate 64 consecutive
+// bounces at once: each lane decides its reflection (partly specular walls: the record's key
+// against the threshold both walls share) and draws its direction (a diffuse one) or takes the
+// in-plane direction and |Omega_axis| of the last diffuse reflection before it, pointed away from
+// its wall (a specular one, which only flips the film-axis component); a prefix sum of the chords
+// finds the bounce during which the free path runs out, and the completed segments are scored
+// with one reduction.  The particle is handed back at the start of its last (partial) segment; the
+// sequential loop then ends that segment with the relaxation.
 template <typename R>
 __device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb, const TallyCtx& tc, Part<R>& p,
                                              const Stream& st_own, int leader, LaneCounts& cnt)
 {
     const int lane = threadIdx.x & 63;
-    const int aw = T.coop_axis;
+    const int aw = T.fold_axis;
     const R L = Geo<R>::L(T.g, aw);
     const int m = __shfl(p.m, leader, 64);
     const R sg = (R)__shfl(p.s, leader, 64);
@@ -1666,6 +1731,19 @@ __device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb,
     const R xw = __shfl(aw == 0 ? p.x[0] : (aw == 1 ? p.x[1] : p.x[2]), leader, 64);
     const int side = xw > R(0.5) * L ? 1 : 0;
     const uint32_t j0 = (uint32_t)__shfl((int)p.j, leader, 64);
+    // the segment cap: the step caps the particle once its segment count reaches max_events, so at
+    // most kcap more crossings complete (each one ends at a wall with the next reflection drawn)
+    const uint32_t k0 = (uint32_t)__shfl((int)p.k, leader, 64);
+    const uint32_t kcap = k0 < (uint32_t)T.max_events ? (uint32_t)T.max_events - k0 : 0u;
+    // the walls' reflection class and partial threshold for this phonon (both walls read the same rule)
+    const int fid = face_id(aw, 0) - 1;
+    uint32_t cls = (T.g.face_code[Geo<R>::prec] >> (4 * fid + 2)) & 3u;
+    uint64_t thr = T.g.face_thr[fid];
+    if (T.spec_w && T.g.face_tab[fid] > 0) {
+        cls = tab_class<R>(T, T.g.face_tab[fid], m);
+        thr = T.spec_thr[(int64_t)(T.g.face_tab[fid] - 1) * T.M + m];
+    }
+    const bool partial = cls == SURF_PARTIAL;
     const R vm = tb.v[m];
     double lam = (double)vm * (double)__shfl(p.dtr, leader, 64);
     const int sa = T.score_axis;
@@ -1673,19 +1751,48 @@ __device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb,
     R disp0 = R(0), disp1 = R(0), disp2 = R(0);
     uint32_t j = j0;
     uint32_t n_full = 0;       // this lane's completed segments
+    uint32_t n_spec = 0, n_diff = 0;   // this lane's reflections
     int kstar = 64;
     R of0 = R(0), of1 = R(0), of2 = R(0);
     double lam_end = 0.0;
+    // the direction a specular reflection starts from when no diffuse one precedes it in its chunk
+    R c0 = __shfl(p.o[0], leader, 64), c1 = __shfl(p.o[1], leader, 64), c2 = __shfl(p.o[2], leader, 64);
     for (int chunk = 0; chunk < (1 << 24); ++chunk) {
-        const int sk = side ^ (lane & 1);            // wall this lane's segment starts from
+        const int sk = side ^ (lane & 1);            // wall this lane's reflection happens at
         const uint32_t rec = 2u + j + 1u + (uint32_t)lane;
-        const W4 w1 = st.block(2u * rec + 1u);
-        const R u1 = unif<R>(w1.x, w1.y), u2 = unif<R>(w1.z, w1.w);
-        R n[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) n[a] = (a == aw) ? (sk ? R(-1) : R(1)) : R(0);
+        bool spec = false;
+        if (partial) {
+            const W4 w0 = st.block(2u * rec);
+            spec = key64(w0.x, w0.y) < thr;
+        }
         R o[3];
-        dir_cos(u1, u2, n, o);
+        if (!spec) {
+            const W4 w1 = st.block(2u * rec + 1u);
+            const R u1 = unif<R>(w1.x, w1.y), u2 = unif<R>(w1.z, w1.w);
+            R n[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) n[a] = (a == aw) ? (sk ? R(-1) : R(1)) : R(0);
+            dir_cos(u1, u2, n, o);
+        }
+        if (partial) {
+            // a specular lane takes the direction of the last diffuse lane at or before it
+            const unsigned long long dm = __ballot(!spec);
+            const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+            const unsigned long long below = dm & upto;
+            const int src = below ? 63 - __clzll((long long)below) : 0;
+            const R t0 = __shfl(o[0], src, 64), t1 = __shfl(o[1], src, 64), t2 = __shfl(o[2], src, 64);
+            if (spec) {
+                o[0] = below ? t0 : c0;
+                o[1] = below ? t1 : c1;
+                o[2] = below ? t2 : c2;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    if (a == aw) o[a] = sk ? -fabs(o[a]) : fabs(o[a]);
+            }
+            c0 = __shfl(o[0], 63, 64);
+            c1 = __shfl(o[1], 63, 64);
+            c2 = __shfl(o[2], 63, 64);
+        }
         const R oz = aw == 0 ? o[0] : (aw == 1 ? o[1] : o[2]);
         const R len = oz != R(0) ? r_div(L, fabs(oz)) : R(1) / R(0);
         R P = len;                                   // inclusive prefix sum of the chords
@@ -1694,8 +1801,12 @@ __device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb,
             const R t = __shfl_up(P, off, 64);
             if (lane >= off) P += t;
         }
-        const unsigned long long over = __ballot((double)P > lam);
+        const unsigned long long over = __ballot((double)P > lam || (j - j0) + (uint32_t)lane >= kcap);
         kstar = over ? __ffsll((long long)over) - 1 : 64;
+        if (lane <= kstar) {                         // this lane's reflection happens
+            n_spec += spec ? 1u : 0u;
+            n_diff += spec ? 0u : 1u;
+        }
         if (lane < kstar) {
             const R os = sa == 0 ? o[0] : (sa == 1 ? o[1] : o[2]);
             aT += (double)(sg * r_div(len, vm));
@@ -1721,6 +1832,7 @@ __device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb,
         j += 64u;
     }
     const uint32_t full = wave_sum<uint32_t>(n_full);
+    const uint32_t nspec = wave_sum<uint32_t>(n_spec), ndiff = wave_sum<uint32_t>(n_diff);
     const double sT = wave_sum<double>(aT), s0 = wave_sum<double>(aQ0), s1 = wave_sum<double>(aQ1),
                  s2 = wave_sum<double>(aQ2), scq = wave_sum<double>(acq);
     const R d0 = wave_sum<R>(disp0), d1 = wave_sum<R>(disp1), d2 = wave_sum<R>(disp2);
@@ -1749,7 +1861,8 @@ __device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb,
         p.j = j;
         p.k += full;
         cnt.c[1] += full;              // completed segments
-        cnt.c[4] += full + 1u;         // diffuse reflections
+        cnt.c[3] += nspec;             // specular reflections
+        cnt.c[4] += ndiff;             // diffuse reflections
     }
 }
 
@@ -2410,7 +2523,7 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const DevTab& T = tabs[0];
-    const Hot<R> H = load_hot<R>(T);
+    const Hot<R> H = load_hot<R>(T, AK == 0 && a.particle_F == nullptr);
     constexpr bool WIDE = (FT & FT_WIDE) != 0;
     Tabs<R> tb = WIDE ? Tabs<R>{T.thr_rel, Geo<R>::v(T), Geo<R>::tau(T), T.rel_guide, Geo<R>::tmeas_ptr(T)}
                       : stage_tables<R>(T, smem);
@@ -2613,7 +2726,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
         }
         if (inst < 0) break;
         const DevTab& T = tabs[inst];
-        const Hot<R> H = load_hot<R>(T);
+        const Hot<R> H = load_hot<R>(T, true);
         if (inst != cur) {
             tb = stage_tables<R>(T, smem);
             if (a.tally_lds) {

@@ -70,3 +70,56 @@ def test_fp32_pore_lattice_with_per_row_specularity(binary):
         assert abs(x["kappa"] - ref["kappa"]) < 3.0 * ref["kappa_sigma"]
     shape = M.run(w, precision=32, block=64, refill=1)
     assert np.array_equal(shape["counts_raw"], got["counts_raw"])
+
+
+@pytest.mark.parametrize("cap", [0, 60])
+def test_fp32_specular_film_crossings_run_at_once(cap):
+    """A 20 nm film whose walls reflect specularly (d = 1; and the rows below 2 THz of a cutoff
+    film): the FP32 trace runs a phonon's wall-to-wall crossings up to the end of its free path at
+    once.  The counters match the oracle's (specular reflections and segments within 1e-4, the
+    cap's ends within a few when a cap of 60 segments cuts the longest paths), kappa within 2e-4."""
+    M = _pkg()
+    extra = {"problem.max_events": cap} if cap else {}
+    for w in (W.with_(W.film(N=200_000, d=20e-9, specularity=1.0), **extra),
+              W.with_(W.film(N=200_000, d=20e-9, spec_omega=W.OMEGA_2THZ), **extra)):
+        got = M.run(w, precision=32)
+        ref = oracle.run(w, threads=THREADS)
+        c, r = got["counts"], ref["counts"]
+        rel = abs(got["kappa"] - ref["kappa"]) / abs(ref["kappa"])
+        _say(f"[specular crossings, cap {cap}] d={w['geometry']['faces'][5][1]}: kappa rel {rel:.2e}; specular "
+             f"{c['specular']} / {r['specular']}, flights {c['flights']} / {r['flights']}, cap_end {c['cap_end']} / "
+             f"{r['cap_end']}")
+        assert r["specular"] > 0.5 * w["problem"]["N"]
+        for k in ("specular", "flights"):
+            assert abs(c[k] - r[k]) <= 1e-4 * r[k] + 2, k
+        for k in ("particles", "relaxations", "nscat_end", "diffuse"):
+            assert abs(c[k] - r[k]) <= 1e-4 * r[k] + 2, k
+        assert abs(c["cap_end"] - r["cap_end"]) <= 1e-3 * r["cap_end"] + 3
+        if cap:
+            assert r["cap_end"] > 20
+        assert rel <= 2e-4
+
+
+@pytest.mark.parametrize("d", [0.3, 0.9])
+def test_fp32_partly_specular_film_bounces_by_the_wave(d):
+    """Partly specular film walls (constant d): the FP32 trace hands a long free path's bounces to
+    the whole wave, each lane deciding its reflection by its own record and a specular one keeping
+    the last diffuse direction with the film-axis component flipped.  Against the oracle on the
+    same particles: specular and diffuse counts and segments within 1e-4, kappa within 2e-4; a cap
+    of 40 segments ends the same particles."""
+    M = _pkg()
+    for cap in (0, 40):
+        w = W.film(N=200_000, d=20e-9, specularity=d)
+        if cap:
+            w = W.with_(w, **{"problem.max_events": cap})
+        got = M.run(w, precision=32)
+        ref = oracle.run(w, threads=THREADS)
+        c, r = got["counts"], ref["counts"]
+        rel = abs(got["kappa"] - ref["kappa"]) / abs(ref["kappa"])
+        _say(f"[partly specular film d={d} cap={cap}] kappa rel {rel:.2e}; specular {c['specular']} / {r['specular']}, "
+             f"diffuse {c['diffuse']} / {r['diffuse']}, flights {c['flights']} / {r['flights']}, cap_end "
+             f"{c['cap_end']} / {r['cap_end']}")
+        for k in ("specular", "diffuse", "flights", "relaxations"):
+            assert abs(c[k] - r[k]) <= 1e-4 * r[k] + 2, k
+        assert abs(c["cap_end"] - r["cap_end"]) <= 1e-3 * r["cap_end"] + 3
+        assert rel <= 2e-4
