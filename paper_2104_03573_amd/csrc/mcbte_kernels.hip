@@ -1244,8 +1244,11 @@ template <typename R>
 __device__ __forceinline__ void fold_crossings(const Hot<R>& H, const TallyCtx& tc, Part<R>& p, LaneCounts& cnt,
                                                R vm, R sg, int fa)
 {
-    const double L = (double)H.L[fa];
-    const double oa = (double)(fa == 0 ? p.o[0] : (fa == 1 ? p.o[1] : p.o[2]));
+    // (scalars and selects only: a local array indexed at run time would live in scratch memory)
+    const R Lf = fa == 0 ? H.L[0] : (fa == 1 ? H.L[1] : H.L[2]);
+    const double L = (double)Lf;
+    const double o0 = (double)p.o[0], o1 = (double)p.o[1], o2 = (double)p.o[2];
+    const double oa = fa == 0 ? o0 : (fa == 1 ? o1 : o2);
     const double chord = L / fabs(oa);
     const double lam = (double)vm * (double)p.dtr;
     double nd = floor(lam / chord);
@@ -1255,25 +1258,26 @@ __device__ __forceinline__ void fold_crossings(const Hot<R>& H, const TallyCtx& 
     const uint32_t n = (uint32_t)nd;
     const double len = nd * chord;
     const bool odd = (n & 1u) != 0u;
-    double dq[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-        dq[a] = a == fa ? (odd ? (oa > 0.0 ? L : -L) : 0.0) : len * (double)(a == 0 ? p.o[0] : (a == 1 ? p.o[1] : p.o[2]));
+    const double dfa = odd ? (oa > 0.0 ? L : -L) : 0.0;     // net film-axis displacement
+    const double q0 = fa == 0 ? dfa : len * o0, q1 = fa == 1 ? dfa : len * o1, q2 = fa == 2 ? dfa : len * o2;
     const double s = (double)sg;
     const double tT = s * (len / (double)vm);
-    for (int q = 0; q < 4; ++q)
-        if ((H.det_mask >> q) & 1) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)p.m, q, q == 0 ? tT : s * dq[q - 1]);
+    const int mask = H.det_mask;
+    if (mask & 1) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)p.m, 0, tT);
+    if (mask & 2) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)p.m, 1, s * q0);
+    if (mask & 4) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)p.m, 2, s * q1);
+    if (mask & 8) tadd_c(tc, H.det_ncomp, H.det_slot, (int64_t)p.m, 3, s * q2);
     p.cT += tT;
-    p.cq += s * dq[H.score_axis];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (a == fa) {
-            const bool at_far = (p.x[a] > R(0.5) * H.L[a]) != odd;
-            p.x[a] = at_far ? H.L[a] : R(0);
-            if (odd) p.o[a] = -p.o[a];
-        } else {
-            p.x[a] = (R)((double)p.x[a] + dq[a]);
-        }
+    p.cq += s * (H.score_axis == 0 ? q0 : (H.score_axis == 1 ? q1 : q2));
+    const bool at_far = (fa == 0 ? p.x[0] : (fa == 1 ? p.x[1] : p.x[2])) > R(0.5) * Lf;
+    const R wall = (at_far != odd) ? Lf : R(0);
+    p.x[0] = fa == 0 ? wall : (R)((double)p.x[0] + q0);
+    p.x[1] = fa == 1 ? wall : (R)((double)p.x[1] + q1);
+    p.x[2] = fa == 2 ? wall : (R)((double)p.x[2] + q2);
+    if (odd) {
+        p.o[0] = fa == 0 ? -p.o[0] : p.o[0];
+        p.o[1] = fa == 1 ? -p.o[1] : p.o[1];
+        p.o[2] = fa == 2 ? -p.o[2] : p.o[2];
     }
     p.dtr = (R)((lam - len) / (double)vm);
     p.t = (R)((double)p.t + len / (double)vm);
