@@ -104,6 +104,8 @@ struct mcbte_tables {
     bool two = false;      // some row has a two-phonon clock
     bool spec_w = false;   // some boundary has a specular cutoff frequency
     bool walls = false;    // internal line walls
+    bool ext_film = false; // a film whose walls reflect some phonons specularly: the FP32 film paths for
+                           // specular and partly specular walls live in the kernels with the extended code
     std::vector<double> omega;
     std::vector<uint64_t> thr_ic, thr_wall, thr_rel, thr_src;
     std::vector<int32_t> src_kind, src_ref, src_sign, bin_of;
@@ -529,6 +531,9 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
             if (same) {
                 h.fold_axis = axis;
                 h.coop_min_path = 16.0 * g.L[axis];
+                for (int i = 0; i < 6; ++i)
+                    if (kFaceAxis[i] == axis && (g.face[i].data[0] > 0.0 || g.face[i].data[1] > 0.0 || g.face[i].spec_table > 0))
+                        t->ext_film = true;
             }
         }
     }
@@ -944,7 +949,7 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     }
     // FP64 film-like problems: the kernel with the exact cooperative bouncing
     if (run->precision == 64 && t->host_view.coop_axis >= 0) ft |= FT_COOP;
-    if (!t->two && !t->spec_w && !t->walls) ft |= FT_PLAIN;   // the kernel without the extended physics
+    if (!t->two && !t->spec_w && !t->walls && !t->ext_film) ft |= FT_PLAIN;   // the kernel without the extended physics
     // FP32 pore lattices: long free paths walked from pore to pore by the wave
     if (run->precision == 32 && t->host_view.lattice && !(ft & (FT_STATE | FT_LOG | FT_WIDE)) &&
         !(run->flags & MCBTE_RUN_SEGMENTS))
@@ -1006,7 +1011,7 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     // the batched kernel without the extended physics unless some instance needs it
     int ft = FT_PLAIN;
     for (int i = 0; i < n_inst; ++i)
-        if (ts[i]->two || ts[i]->spec_w || ts[i]->walls) ft = 0;
+        if (ts[i]->two || ts[i]->spec_w || ts[i]->walls || ts[i]->ext_film) ft = 0;
     int rc = plan_launch(ts, n_inst, run, 1, ft, lp);
     if (rc != MCBTE_OK) return rc;
     // chunking: items of chunk_size particles, instance-major
@@ -1081,7 +1086,7 @@ int mcbte_trace_batch_static(const mcbte_tables* const* ts, int32_t n_inst, cons
     if (queue_layout(n_inst).end > static_queue_bytes()) return MCBTE_ELIMIT;
     int ft = FT_PLAIN;
     for (int i = 0; i < n_inst; ++i)
-        if (ts[i]->two || ts[i]->spec_w || ts[i]->walls) ft = 0;
+        if (ts[i]->two || ts[i]->spec_w || ts[i]->walls || ts[i]->ext_film) ft = 0;
     LaunchPlan lp;
     int rc = plan_launch(ts, n_inst, run, 1, ft, lp);
     if (rc != MCBTE_OK) return rc;

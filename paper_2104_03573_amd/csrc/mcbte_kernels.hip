@@ -1571,7 +1571,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
     constexpr bool COOP = std::is_same<R, float>::value || (FT & FT_COOP) != 0;
     if (COOP && ev == 1 && fa >= 0 && (std::is_same<R, double>::value || !lg.row) && vm * p.dtr > H.coop_min &&
         ((cls == SURF_DIFFUSE && fa == H.coop_axis) ||
-         (std::is_same<R, float>::value && cls == SURF_PARTIAL && fa == H.fold_axis))) {
+         (std::is_same<R, float>::value && EXT && cls == SURF_PARTIAL && fa == H.fold_axis))) {
         if (AK == 2) pc.plane(fa, false);    // the chain starts with a diffuse reflection
         coop = true;
         return false;
@@ -1683,7 +1683,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         lg.put(EV_SPECULAR, hit, p.m);
         // a film whose walls reflect this phonon specularly: its next wall-to-wall crossings until
         // the free path runs out, at once (FP32 trace)
-        if constexpr (std::is_same<R, float>::value && AK == 0) {
+        if constexpr (std::is_same<R, float>::value && AK == 0 && EXT) {
             if (fa >= 0 && fa == H.fold_axis && cls == SURF_SPECULAR && !lg.row && vm * p.dtr > H.coop_min)
                 fold_crossings(H, tc, p, cnt, vm, sg, fa);
         }
@@ -1719,7 +1719,8 @@ __device__ __forceinline__ T wave_sum(T v)
 // finds the bounce during which the free path runs out, and the completed segments are scored
 // with one reduction.  The particle is handed back at the start of its last (partial) segment; the
 // sequential loop then ends that segment with the relaxation.
-template <typename R>
+// PART: partly specular walls are handled (compiled into the kernels with the extended physics)
+template <typename R, bool PART>
 __device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb, const TallyCtx& tc, Part<R>& p,
                                              const Stream& st_own, int leader, LaneCounts& cnt)
 {
@@ -1740,14 +1741,18 @@ __device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb,
     const uint32_t k0 = (uint32_t)__shfl((int)p.k, leader, 64);
     const uint32_t kcap = k0 < (uint32_t)T.max_events ? (uint32_t)T.max_events - k0 : 0u;
     // the walls' reflection class and partial threshold for this phonon (both walls read the same rule)
-    const int fid = face_id(aw, 0) - 1;
-    uint32_t cls = (T.g.face_code[Geo<R>::prec] >> (4 * fid + 2)) & 3u;
-    uint64_t thr = T.g.face_thr[fid];
-    if (T.spec_w && T.g.face_tab[fid] > 0) {
-        cls = tab_class<R>(T, T.g.face_tab[fid], m);
-        thr = T.spec_thr[(int64_t)(T.g.face_tab[fid] - 1) * T.M + m];
+    bool partial = false;
+    uint64_t thr = 0;
+    if constexpr (PART) {
+        const int fid = face_id(aw, 0) - 1;
+        uint32_t cls = (T.g.face_code[Geo<R>::prec] >> (4 * fid + 2)) & 3u;
+        thr = T.g.face_thr[fid];
+        if (T.spec_w && T.g.face_tab[fid] > 0) {
+            cls = tab_class<R>(T, T.g.face_tab[fid], m);
+            thr = T.spec_thr[(int64_t)(T.g.face_tab[fid] - 1) * T.M + m];
+        }
+        partial = cls == SURF_PARTIAL;
     }
-    const bool partial = cls == SURF_PARTIAL;
     const R vm = tb.v[m];
     double lam = (double)vm * (double)__shfl(p.dtr, leader, 64);
     const int sa = T.score_axis;
@@ -1765,7 +1770,7 @@ __device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb,
         const int sk = side ^ (lane & 1);            // wall this lane's reflection happens at
         const uint32_t rec = 2u + j + 1u + (uint32_t)lane;
         bool spec = false;
-        if (partial) {
+        if (PART && partial) {
             const W4 w0 = st.block(2u * rec);
             spec = key64(w0.x, w0.y) < thr;
         }
@@ -1778,7 +1783,7 @@ __device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb,
             for (int a = 0; a < 3; ++a) n[a] = (a == aw) ? (sk ? R(-1) : R(1)) : R(0);
             dir_cos(u1, u2, n, o);
         }
-        if (partial) {
+        if (PART && partial) {
             // a specular lane takes the direction of the last diffuse lane at or before it
             const unsigned long long dm = __ballot(!spec);
             const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
@@ -2658,7 +2663,7 @@ __global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(cons
                 if constexpr ((FT & FT_LATTICE) != 0 && std::is_same<R, float>::value)
                     lattice_walk<FT>(T, H, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
                 else if constexpr (std::is_same<R, float>::value)
-                    coop_bounces<R>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
+                    coop_bounces<R, (FT & FT_PLAIN) == 0>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
                 else if constexpr ((FT & FT_COOP) != 0)
                     coop_exact(H, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt, lg);
             }
@@ -2808,7 +2813,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
             if constexpr (TK == TALLY_STEADY_ONE) {
                 for (unsigned long long pend = __ballot(coop); pend; pend &= pend - 1ull) {
                     if constexpr (std::is_same<R, float>::value)
-                        coop_bounces<R>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
+                        coop_bounces<R, (FT & FT_PLAIN) == 0>(T, tb, tc, p, st, __ffsll((long long)pend) - 1, cnt);
                 }
             }
             if constexpr (TK == TALLY_TRANSIENT) snap_wave<R>(T, tc, tb.tmeas, p);
