@@ -435,8 +435,9 @@ int mcbte_tally(const mcbte_tables* tables, const void* tally, double* host_out,
    buffers of these tables, each filled by its own range of particles (each its own trace calls:
    disjoint ranges of one seed, or other seeds).  Each is finalized as by mcbte_tally; host_mean
    receives the particle-weighted mean over the batches (the finalized sum of all of them) and
-   host_sigma its batch-mean standard error sqrt(sum_b n_b (X_b - X)^2 / ((B - 1) N)) per element
-   (NaN when n_tallies == 1), both laid out [n_cells][n_cols][4] (n_out >= n_cells * n_cols * 4;
+   host_sigma its batch-mean standard error sqrt(sum_b n_b (X_b - X)^2 / ((B - 1) N)) per element,
+   B the buffers that traced particles (a buffer without particles weighs nothing; NaN for fewer
+   than two such buffers; with none at all the mean is 0), both laid out [n_cells][n_cols][4] (n_out >= n_cells * n_cols * 4;
    either may be NULL, not both).  Synchronizes `stream`.  Errors: MCBTE_EINVAL (a NULL buffer,
    n_tallies < 1), MCBTE_ESIZE, MCBTE_ENODEV, MCBTE_EHIP. */
 int mcbte_tally_batches(const mcbte_tables* tables, const void* const* tallies, int32_t n_tallies, double* host_mean,
@@ -452,9 +453,9 @@ int mcbte_tally_batches(const mcbte_tables* tables, const void* const* tallies, 
    flux: each row's (bin's) kappa_i = -q_score,i / gradT_score, summed in the order: kappa_cum[k] is
    the sum over the first k + 1 rows (bins), so the last entry is kappa.  keys[k] (may be NULL)
    receives the k-th row's mean free path (m) or bin's angular frequency (rad/s).  With several
-   tallies (as for mcbte_tally_batches), kappa_cum is the particle-weighted mean over them and
-   kappa_cum_sigma (may be NULL) its batch-mean standard error (NaN for one tally).  n_out >= n_modes
-   (MCBTE_CUM_MFP) or n_bins (MCBTE_CUM_OMEGA).  Synchronizes `stream`.  Errors: MCBTE_EINVAL
+   tallies (particle groups, as for mcbte_tally_batches), kappa_cum is the particle-weighted mean
+   over them and kappa_cum_sigma (may be NULL) its batch-mean standard error, both as there.
+   n_out >= n_modes (MCBTE_CUM_MFP) or n_bins (MCBTE_CUM_OMEGA).  Synchronizes `stream`.  Errors: MCBTE_EINVAL
    (transient or binned tallies, zero gradient along the score axis, flux not tallied, unknown
    order, NULL buffers), MCBTE_ESIZE, MCBTE_ENODEV, MCBTE_EHIP. */
 int mcbte_kappa_cumulative(const mcbte_tables* tables, const void* const* tallies, int32_t n_tallies, int32_t order,

@@ -361,6 +361,10 @@ def finalize(res: dict) -> dict:
     w = tb.w
     raw = res["raw"].reshape(tb.n_cells, tb.n_cols, 4)
     n = int(res["counts"][0])
+    if n == 0:                                        # no particle traced: nothing to normalise
+        z = np.zeros((tb.n_cells, tb.n_cols))
+        return {"T": z, "q": np.zeros((tb.n_cells, tb.n_cols, 3)), "e_eff": math.nan, "V_cell": math.nan,
+                "counts": dict(zip(COUNT_NAMES, [int(x) for x in res["counts"][:len(COUNT_NAMES)]]))}
     e = tb.E_tot / n                                  # effective energy (rate) per particle
     det, g = w["detectors"], w["geometry"]
     if all(k == 0 for k in det["n"]):
@@ -420,18 +424,22 @@ def batch_statistics(batches: list[dict], key=None) -> dict:
     """Particle-weighted mean over independently traced particle groups (each finalized on its
     own) and the standard error of that mean from the spread of the group values (batch means;
     trajectories are independent, section 6): mean = sum_b n_b X_b / N and
-    sigma^2 = sum_b n_b (X_b - mean)^2 / ((B - 1) N), NaN for one group.  key(batch) picks the
+    sigma^2 = sum_b n_b (X_b - mean)^2 / ((B - 1) N) over the B groups that traced particles (NaN
+    for fewer than two; a group without particles weighs nothing).  key(batch) picks the
     finalized array (default: T and q stacked as [..., 4])."""
     pick = key or (lambda b: np.concatenate([b["T"][..., None], b["q"]], axis=-1))
     X = np.stack([np.asarray(pick(b), dtype=np.float64) for b in batches])
     nb = np.array([float(b["counts"]["particles"]) for b in batches])
     N = nb.sum()
     shape = (-1,) + (1,) * (X.ndim - 1)
+    if not N > 0:                                   # no particle at all
+        return {"mean": np.zeros(X.shape[1:]), "sigma": np.full(X.shape[1:], np.nan)}
     mean = (nb.reshape(shape) * X).sum(axis=0) / N
-    if len(batches) < 2:
+    used = int((nb > 0).sum())                      # groups that traced particles
+    if used < 2:
         sigma = np.full(mean.shape, np.nan)
     else:
-        sigma = np.sqrt((nb.reshape(shape) * (X - mean) ** 2).sum(axis=0) / ((len(batches) - 1) * N))
+        sigma = np.sqrt((nb.reshape(shape) * (X - mean) ** 2).sum(axis=0) / ((used - 1) * N))
     return {"mean": mean, "sigma": sigma}
 
 

@@ -1356,25 +1356,31 @@ int64_t finalize_host(const mcbte_tables* t, const void* tally, std::vector<doub
 }
 
 // particle-weighted mean of per-batch values x[b][k] (batch b traced n[b] particles) and its
-// batch-mean standard error sqrt(sum_b n_b (x_b - mean)^2 / ((B - 1) N)) (NaN for one batch)
+// batch-mean standard error sqrt(sum_b n_b (x_b - mean)^2 / ((B - 1) N)), B the batches that traced
+// particles (a batch without particles weighs nothing; NaN for fewer than two; with no particle at
+// all the mean is 0)
 void batch_mean(const std::vector<std::vector<double>>& x, const std::vector<int64_t>& n, double* mean, double* sigma,
                 int64_t K)
 {
     const size_t B = x.size();
     double N = 0.0;
-    for (size_t b = 0; b < B; ++b) N += (double)n[b];
+    size_t used = 0;   // batches that traced particles
+    for (size_t b = 0; b < B; ++b) {
+        N += (double)n[b];
+        used += n[b] > 0 ? 1u : 0u;
+    }
     for (int64_t k = 0; k < K; ++k) {
         double m = 0.0;
         for (size_t b = 0; b < B; ++b) m += (double)n[b] * x[b][(size_t)k];
         m = N > 0.0 ? m / N : 0.0;
         if (mean) mean[k] = m;
         if (sigma) {
-            if (B < 2) {
+            if (used < 2) {
                 sigma[k] = NAN;
             } else {
                 double v = 0.0;
                 for (size_t b = 0; b < B; ++b) v += (double)n[b] * (x[b][(size_t)k] - m) * (x[b][(size_t)k] - m);
-                sigma[k] = std::sqrt(v / ((double)(B - 1) * N));
+                sigma[k] = std::sqrt(v / ((double)(used - 1) * N));
             }
         }
     }

@@ -140,3 +140,31 @@ def test_fp32_nanomesh_frequency_resolved_cumulative_kappa_against_the_oracle():
     ratio = got["kappa_cum_sigma"][-1] / ref["kappa_cum_sigma"][-1]
     _say(f"[cumulative omega, FP32 nanomesh] worst decile {worst:.2e} of kappa; sigma ratio {ratio:.3f}")
     assert 0.7 < ratio < 1.4
+
+
+def test_groups_without_particles_weigh_nothing():
+    """A tally buffer that traced no particle is a group of weight zero: the means and errors over
+    [empty, g1, g2] equal those over [g1, g2] and the oracle's; only empty buffers give mean 0 and
+    error NaN (FP64 gray slab and silicon-like film)."""
+    M = _pkg()
+    w = W.gray_slab(N=30_000)
+    t = M.Tables(w)
+    empty = t.new_tally()
+    groups = _gpu_groups(M, t, w, 2, 64)
+    a = M.tally_batches(t, [empty] + groups)
+    b = M.tally_batches(t, groups)
+    assert np.allclose(a["T"], b["T"], rtol=1e-14, atol=0.0)
+    assert np.allclose(a["T_sigma"], b["T_sigma"], rtol=1e-12, atol=0.0)
+    tb = oracle.Tables(w)
+    raw, counts, mom, _ = tb.trace_range(int(w["seed"]), 0, 0, 0)
+    e = {"raw": raw, "counts": counts, "moments": mom, "tables": tb}
+    e.update(oracle.finalize(e))
+    ref = oracle.batch_statistics([e] + oracle.run_batches(w, 2, threads=THREADS))
+    assert np.abs(a["T"] - ref["mean"][..., 0]).max() <= 1e-10 * np.abs(ref["mean"][..., 0]).max()
+    none = M.tally_batches(t, [empty, t.new_tally()])
+    assert np.all(none["T"] == 0.0) and np.isnan(none["T_sigma"]).all()
+    f = W.film(N=40_000)
+    tf = M.Tables(f)
+    cg = M.kappa_cumulative(tf, [tf.new_tally()] + _gpu_groups(M, tf, f, 2, 64), "omega")
+    ch = M.kappa_cumulative(tf, _gpu_groups(M, tf, f, 2, 64), "omega")
+    assert np.allclose(cg["kappa_cum"], ch["kappa_cum"], rtol=1e-12, atol=1e-12 * abs(ch["kappa_cum"][-1]))
