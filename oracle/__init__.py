@@ -73,8 +73,9 @@ class Problem(C.Structure):
                 ("n_ic", C.c_int32), ("n_spec_tables", C.c_int32),
                 ("t_meas", C.POINTER(C.c_double)), ("ic_edges", C.POINTER(C.c_double)),
                 ("ic_dT", C.POINTER(C.c_double)), ("spec_table", C.POINTER(C.c_double)),
-                ("n_heat", C.c_int32), ("pad_h", C.c_int32), ("heat_lo", C.c_double * 3),
-                ("heat_hi", C.c_double * 3), ("heat_t", C.POINTER(C.c_double)), ("heat_P", C.POINTER(C.c_double))]
+                ("n_heat", C.c_int32), ("n_heat_tet", C.c_int32), ("heat_lo", C.c_double * 3),
+                ("heat_hi", C.c_double * 3), ("heat_t", C.POINTER(C.c_double)), ("heat_P", C.POINTER(C.c_double)),
+                ("heat_tet", C.POINTER(C.c_double))]
 
 
 def build(force: bool = False) -> str:
@@ -245,6 +246,10 @@ class Tables:
             for a in range(3):
                 P.heat_lo[a], P.heat_hi[a] = heat["lo"][a], heat["hi"][a]
             P.heat_t, P.heat_P = self._heat_t.ctypes.data_as(dp), self._heat_P.ctypes.data_as(dp)
+            if heat.get("tets") is not None:
+                self._heat_tet = np.ascontiguousarray(heat["tets"], dtype=np.float64).reshape(-1, 12)
+                P.n_heat_tet = self._heat_tet.shape[0]
+                P.heat_tet = self._heat_tet.ctypes.data_as(dp)
         self._prob = P
         h = C.c_void_p()
         rc = L.orc_build(self._modes, len(modes), C.byref(G), C.byref(D), C.byref(P), C.byref(h))

@@ -58,6 +58,9 @@ struct orc_tables {
     orc_problem pr;
     double *t_meas, *ic_edges, *ic_dT;
     double *heat_t, *heat_P;   /* external heat source: interval edges and power densities */
+    double* heat_tet;          /* its tetrahedra (vertex 0 and the three edges from it, 12 per one) */
+    uint64_t* thr_tet;         /* choice of a tetrahedron by volume */
+    int64_t last_tet;
     int64_t n_cells;
     int32_t n_cols;
     int32_t n_bins;
@@ -202,6 +205,42 @@ double orc_dedT(double omega, double T)
 
 static double extent(const orc_geom* g, int a) { return g->unbounded[a] ? 1.0 : g->L[a]; }
 
+/* volume of the tetrahedron with vertices v[0..2], v[3..5], v[6..8], v[9..11]: |det(e1 e2 e3)| / 6 */
+static double tet_volume(const double* v)
+{
+    double e[3][3];
+    for (int q = 0; q < 3; ++q)
+        for (int a = 0; a < 3; ++a) e[q][a] = v[3 * (q + 1) + a] - v[a];
+    const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                       e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                       e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+    return fabs(det) / 6.0;
+}
+
+/* a point uniform in the tetrahedron v0 + b0 e1 + b1 e2 + b2 e3 (b >= 0, b0 + b1 + b2 <= 1) from three
+   uniforms, by folding the unit cube onto the tetrahedron (Rocchini and Cignoni, "Generating random
+   points in a tetrahedron", Journal of Graphics Tools 5(4), 2000): the cube's two halves across
+   s + t = 1 map onto each other, then the triangular prism's three parts onto the tetrahedron */
+static void tet_point(double s, double t, double u, double b[3])
+{
+    if (s + t > 1.0) {
+        s = 1.0 - s;
+        t = 1.0 - t;
+    }
+    if (t + u > 1.0) {
+        const double w = u;
+        u = 1.0 - s - t;
+        t = 1.0 - w;
+    } else if (s + t + u > 1.0) {
+        const double w = u;
+        u = s + t + u - 1.0;
+        s = 1.0 - t - w;
+    }
+    b[0] = s;
+    b[1] = t;
+    b[2] = u;
+}
+
 void orc_free(orc_tables* t)
 {
     if (!t) return;
@@ -210,6 +249,7 @@ void orc_free(orc_tables* t)
     free(t->src_kind); free(t->src_ref); free(t->src_sign); free(t->src_E); free(t->thr_src);
     free(t->t_meas); free(t->ic_edges); free(t->ic_dT);
     free(t->bin); free(t->P_bin); free(t->spec_tab); free(t->heat_t); free(t->heat_P);
+    free(t->heat_tet); free(t->thr_tet);
     free(t);
 }
 
@@ -304,6 +344,29 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
             double dx = nx - g->cyl[c].cx, dy = ny - g->cyl[c].cy;
             if (dx * dx + dy * dy < g->cyl[c].r * g->cyl[c].r) return E_INVAL;
         }
+        /* tetrahedra: vertices inside the box (bounded axes), positive volume, the x-y bounding
+           rectangle of each clear of every pore */
+        if (pr->n_heat_tet < 0 || (pr->n_heat_tet > 0 && !pr->heat_tet)) return E_INVAL;
+        for (int k = 0; k < pr->n_heat_tet; ++k) {
+            const double* v = pr->heat_tet + 12 * k;
+            double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int q = 0; q < 4; ++q)
+                for (int a = 0; a < 3; ++a) {
+                    const double x = v[3 * q + a];
+                    if (!isfinite(x) || (!g->unbounded[a] && !(x >= 0.0 && x <= g->L[a]))) return E_INVAL;
+                    lo[a] = fmin(lo[a], x);
+                    hi[a] = fmax(hi[a], x);
+                }
+            if (!(tet_volume(v) > 0.0)) return E_INVAL;
+            for (int c = 0; c < g->n_cyl; ++c) {
+                double nx = fmin(fmax(g->cyl[c].cx, lo[0]), hi[0]);
+                double ny = fmin(fmax(g->cyl[c].cy, lo[1]), hi[1]);
+                double dx = nx - g->cyl[c].cx, dy = ny - g->cyl[c].cy;
+                if (dx * dx + dy * dy < g->cyl[c].r * g->cyl[c].r) return E_INVAL;
+            }
+        }
+    } else if (pr->n_heat_tet != 0) {
+        return E_INVAL;
     }
 
     orc_tables* t = (orc_tables*)calloc(1, sizeof(orc_tables));
@@ -464,6 +527,7 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
        the interval's length */
     t->pr.heat_t = NULL;
     t->pr.heat_P = NULL;
+    t->pr.heat_tet = NULL;
     if (pr->n_heat > 0) {
         t->heat_t = (double*)malloc(sizeof(double) * (pr->n_heat + 1));
         t->heat_P = (double*)malloc(sizeof(double) * pr->n_heat);
@@ -472,6 +536,25 @@ int orc_build(const orc_mode* modes, int32_t M, const orc_geom* g, const orc_det
         memcpy(t->heat_P, pr->heat_P, sizeof(double) * pr->n_heat);
         double Vh = 1.0;
         for (int a = 0; a < 3; ++a) Vh *= g->unbounded[a] ? 1.0 : pr->heat_hi[a] - pr->heat_lo[a];
+        if (pr->n_heat_tet > 0) {        /* the union of the tetrahedra: a tetrahedron by volume */
+            const int nt = pr->n_heat_tet;
+            t->heat_tet = (double*)malloc(sizeof(double) * 12 * nt);
+            t->thr_tet = (uint64_t*)malloc(sizeof(uint64_t) * nt);
+            double* vol = (double*)malloc(sizeof(double) * nt);
+            if (!t->heat_tet || !t->thr_tet || !vol) { free(vol); orc_free(t); return E_NOMEM; }
+            Vh = 0.0;
+            for (int k = 0; k < nt; ++k) {
+                const double* v = pr->heat_tet + 12 * k;
+                for (int a = 0; a < 3; ++a) {
+                    t->heat_tet[12 * k + a] = v[a];
+                    for (int q = 1; q < 4; ++q) t->heat_tet[12 * k + 3 * q + a] = v[3 * q + a] - v[a];
+                }
+                vol[k] = tet_volume(v);
+                Vh += vol[k];
+            }
+            orc_cdf_build(vol, nt, t->thr_tet, &t->last_tet);
+            free(vol);
+        }
         for (int k = 0; k < pr->n_heat; ++k) {
             if (t->heat_P[k] == 0.0) continue;
             double E = (fabs(t->heat_P[k]) * Vh) * (t->heat_t[k + 1] - t->heat_t[k]);
@@ -768,10 +851,19 @@ static int emit(const orc_tables* t, uint64_t seed, uint32_t inst, int64_t pid, 
         if (p->s < 0) { p->o[0] = -p->o[0]; p->o[1] = -p->o[1]; p->o[2] = -p->o[2]; }
         p->m = (int32_t)orc_cdf_pick(t->thr_wall, t->M, t->last_wall, key64(R1, 0));
     } else if (kind == S_HEAT) {
-        /* the external heat source: a point of its cuboid, an isotropic direction and the row of a
-           local temperature rise (weights C, as for the initial condition) */
-        for (int a = 0; a < 3; ++a)
-            p->x[a] = g->unbounded[a] ? 0.0 : t->pr.heat_lo[a] + up[a] * (t->pr.heat_hi[a] - t->pr.heat_lo[a]);
+        /* the external heat source: a point of its cuboid (or of one of its tetrahedra, chosen by
+           volume with words W4W5 of record 2), an isotropic direction and the row of a local
+           temperature rise (weights C, as for the initial condition) */
+        if (t->pr.n_heat_tet > 0) {
+            const int64_t k = orc_cdf_pick(t->thr_tet, t->pr.n_heat_tet, t->last_tet, key64(R2, 4));
+            double b[3];
+            tet_point(up[0], up[1], up[2], b);
+            const double* v = t->heat_tet + 12 * k;
+            for (int a = 0; a < 3; ++a) p->x[a] = ((v[a] + b[0] * v[3 + a]) + b[1] * v[6 + a]) + b[2] * v[9 + a];
+        } else {
+            for (int a = 0; a < 3; ++a)
+                p->x[a] = g->unbounded[a] ? 0.0 : t->pr.heat_lo[a] + up[a] * (t->pr.heat_hi[a] - t->pr.heat_lo[a]);
+        }
         orc_dir_iso(ud1, ud2, p->o);
         p->s = t->src_sign[src];
         p->m = (int32_t)orc_cdf_pick(t->thr_ic, t->M, t->last_ic, key64(R1, 0));

@@ -57,11 +57,13 @@ typedef struct {
     const double* ic_dT;
     const double* spec_table;  /* n_spec_tables x M degrees of specularity, table-major */
     /* external heat source (transient): power density heat_P[k] (W/m^3, signed) over
-       [heat_t[k], heat_t[k+1]) in the cuboid [heat_lo, heat_hi] (bounded axes) */
-    int32_t n_heat, pad_h;
+       [heat_t[k], heat_t[k+1]) in the cuboid [heat_lo, heat_hi] (bounded axes), or, when
+       n_heat_tet > 0, in the union of the tetrahedra heat_tet (4 vertices x 3 coordinates each) */
+    int32_t n_heat, n_heat_tet;
     double heat_lo[3], heat_hi[3];
     const double* heat_t;
     const double* heat_P;
+    const double* heat_tet;
 } orc_problem;
 
 typedef struct orc_tables orc_tables;

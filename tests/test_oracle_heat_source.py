@@ -107,3 +107,66 @@ def test_heat_source_rows_are_drawn_by_heat_capacity():
         want = p[g].sum()
         got = np.isin(rows, g).sum()
         assert abs(got - n * want) <= 5.0 * math.sqrt(n * want * (1 - want)) + 1
+
+
+def _positions(w, n):
+    tb = oracle.Tables(w)
+    return tb, np.array([tb.emit_state(pid)[0][:3] for pid in range(n)])
+
+
+def _barycentric(v, x):
+    """Barycentric coordinates of points x (n, 3) in the tetrahedron v (4, 3), by solving the
+    3 x 3 system of the edges."""
+    E = np.stack([v[1] - v[0], v[2] - v[0], v[3] - v[0]], axis=1)
+    b = np.linalg.solve(E, (x - v[0]).T).T
+    return np.concatenate([1.0 - b.sum(axis=1, keepdims=True), b], axis=1)
+
+
+def test_heat_source_points_are_uniform_in_a_tetrahedron():
+    """The heat source in one tetrahedron (section 3.2: arbitrary regions built from tetrahedra):
+    every emitted point lies inside it, each barycentric coordinate follows its law for a uniform
+    point (P(b <= x) = 1 - (1 - x)^3, Kolmogorov-Smirnov), and mean and covariance are the
+    simplex's: the centroid and (1/20) sum_i (v_i - c)(v_i - c)^T."""
+    from scipy import stats
+    w = W.heated_box(N=20_000)
+    v = np.asarray(w["problem"]["heat"]["tets"][0])
+    tb, x = _positions(w, 20_000)
+    b = _barycentric(v, x)
+    assert b.min() > -1e-12 and b.max() < 1.0 + 1e-12
+    for k in range(4):
+        assert stats.kstest(b[:, k], lambda q: 1.0 - (1.0 - np.clip(q, 0, 1)) ** 3).pvalue > 1e-4, k
+    c = v.mean(axis=0)
+    cov = sum(np.outer(vi - c, vi - c) for vi in v) / 20.0
+    n = len(x)
+    se = np.sqrt(np.diag(cov) / n)
+    assert np.all(np.abs(x.mean(axis=0) - c) < 5.0 * se)
+    emp = np.cov(x.T)
+    assert np.abs(emp - cov).max() < 0.05 * np.abs(cov).max()
+
+
+def test_tetrahedra_of_a_cuboid_heat_it_as_the_cuboid_does():
+    """The cuboid region as six tetrahedra: the same energy (volumes add up to the cuboid's, 1e-12),
+    points uniform along each axis of the cuboid (Kolmogorov-Smirnov), each tetrahedron chosen
+    with its share of the volume (1/6, binomial 5 sigma); and two tetrahedra of unequal volume are
+    chosen in proportion to their volumes."""
+    from scipy import stats
+    lo, hi = np.array([50e-9, 40e-9, 30e-9]), np.array([350e-9, 240e-9, 130e-9])
+    cube = W.heated_box(N=100, tets=W.cube_tets(lo, hi))
+    box = W.with_(cube)
+    box["problem"]["heat"] = dict(box["problem"]["heat"], lo=tuple(lo), hi=tuple(hi), tets=None)
+    assert abs(oracle.Tables(cube).E_tot - oracle.Tables(box).E_tot) <= 1e-12 * oracle.Tables(box).E_tot
+    n = 12_000
+    tb, x = _positions(W.with_(cube, **{"problem.N": n}), n)
+    for a in range(3):
+        assert stats.kstest((x[:, a] - lo[a]) / (hi[a] - lo[a]), "uniform").pvalue > 1e-4, a
+    tets = W.cube_tets(lo, hi)
+    inside = np.array([[np.all(_barycentric(t, x[i:i + 1]) >= -1e-12) for t in tets] for i in range(2000)])
+    share = inside.sum(axis=0) / 2000.0
+    assert np.all(np.abs(share - 1.0 / 6.0) < 5.0 * math.sqrt((1 / 6) * (5 / 6) / 2000))
+    small = np.array([[0, 0, 0], [100e-9, 0, 0], [0, 100e-9, 0], [0, 0, 100e-9]]) + 20e-9
+    big = np.array([[0, 0, 0], [200e-9, 0, 0], [0, 200e-9, 0], [0, 0, 150e-9]]) + np.array([150e-9, 50e-9, 20e-9])
+    two = W.heated_box(N=n, tets=np.array([small, big]))
+    tb2, x2 = _positions(two, n)
+    in_small = np.all(_barycentric(small, x2) >= -1e-12, axis=1)
+    p = 1.0 / (1.0 + (2 * 2 * 1.5))          # volume ratio 1 : 6
+    assert abs(in_small.sum() - n * p) < 5.0 * math.sqrt(n * p * (1 - p))

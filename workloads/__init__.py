@@ -362,6 +362,46 @@ def heated_slab(N=10_000_000, L=1e-6, T=300.0, depth=20e-9, sigma=5e-12, peak=No
     }
 
 
+def cube_tets(lo, hi) -> np.ndarray:
+    """The cuboid [lo, hi] as six tetrahedra sharing its diagonal lo-hi (one per order of the
+    three axes: lo, lo + the first axis' edge, + the second's, hi): array (6, 4, 3)."""
+    import itertools
+    lo, hi = np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
+    out = []
+    for perm in itertools.permutations(range(3)):
+        v = [lo.copy()]
+        for a in perm:
+            nxt = v[-1].copy()
+            nxt[a] = hi[a]
+            v.append(nxt)
+        out.append(np.array(v))
+    return np.array(out)
+
+
+def heated_box(N=200_000, L=(400e-9, 300e-9, 200e-9), tets=None, modes=None, specularity=1.0, t_max=40e-12,
+               n_times=4, bins=(4, 1, 1), seed=SEED_BASE + 13):
+    """A closed box (all six faces adiabatic, of specularity `specularity`) heated over [0, 10 ps)
+    in the union of the tetrahedra `tets` (default: one tetrahedron in a corner), gray medium by
+    default; T and q in a grid of bins at n_times times."""
+    if tets is None:
+        tets = np.array([[[20e-9, 20e-9, 20e-9], [300e-9, 40e-9, 30e-9], [60e-9, 250e-9, 40e-9],
+                          [80e-9, 60e-9, 180e-9]]])
+    faces = {i: (ADIABATIC, specularity, 0, 0) for i in range(1, 7)}
+    t_meas = (np.arange(n_times) + 0.5) * (t_max / n_times)
+    prob = _problem(N, 300.0, 0, transient=True, t_max=t_max, t_meas=t_meas, score_axis=0,
+                    fmt=2 if modes is None else 1)
+    prob["heat"] = {"lo": (0.0, 0.0, 0.0), "hi": tuple(L), "t": np.array([0.0, 10e-12]), "P": np.array([1e17]),
+                    "tets": np.asarray(tets, dtype=np.float64)}
+    return {
+        "name": "heated_box",
+        "modes": gray_modes(6400.0, 50e-9 / 6400.0) if modes is None else modes,
+        "geometry": _geometry(tuple(L), (False, False, False), faces),
+        "detectors": _detectors((0, 0, 0), tuple(L), tuple(bins), MASK_ALL),
+        "problem": prob,
+        "seed": seed,
+    }
+
+
 def bulk_gradient(N=200_000, v=6400.0, Lambda=100e-9, gradT=-1.0e7, n_scat_max=1, modes=None,
                   seed=SEED_BASE + 7, T=300.0):
     """Unbounded bulk driven only by the gradient source (no boundaries at all)."""
