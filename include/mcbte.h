@@ -185,7 +185,12 @@ typedef struct {
    row drawn by heat capacity (the equilibrium distribution of a temperature rise, as for the
    initial condition) and an isotropic direction (emission record 2, words W2W3, gives the time).
    The cuboid lies inside the box and inside the solid (no pore or line wall reaches into it);
-   0 <= heat_t[0] < ... <= t_max.  n_heat = 0: none.
+   0 <= heat_t[0] < ... <= t_max.  n_heat = 0: none.  Regions of any shape (section 3.2 builds them
+   from tetrahedra): with n_heat_tet > 0 the region is instead the union of the tetrahedra heat_tet
+   (4 vertices x 3 coordinates each, inside the box, positive volume, the x-y bounding rectangle
+   of each clear of every pore); a particle's tetrahedron is drawn by volume (emission record 2,
+   words W4W5) and its point uniformly inside it from the three position uniforms (the folding of
+   the unit cube onto the tetrahedron of Rocchini and Cignoni, 2000).
    All pointers are host pointers, read during mcbte_build_tables only. */
 typedef struct {
     int64_t N, max_events;
@@ -196,10 +201,11 @@ typedef struct {
     const double* ic_edges;
     const double* ic_dT;
     const double* spec_table;
-    int32_t n_heat, reserved;
+    int32_t n_heat, n_heat_tet;
     double heat_lo[3], heat_hi[3];
     const double* heat_t;
     const double* heat_P;
+    const double* heat_tet;
 } mcbte_problem;
 
 typedef struct mcbte_tables mcbte_tables;

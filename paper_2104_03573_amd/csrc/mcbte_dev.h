@@ -131,6 +131,14 @@ struct DevTab {
     const int32_t* src_sign;
     const double* ic_edges;
     const double* heat_t;        // external heat source: interval edges (n_heat + 1), or NULL
+    // its tetrahedra (region built from them): vertex 0 and the edges to vertices 1-3, 12 values
+    // each, FP64 and FP32, and the choice of one by volume
+    const double* heat_tet64;
+    const float* heat_tet32;
+    const uint64_t* thr_tet;
+    int64_t last_tet;
+    int32_t n_heat_tet;
+    int32_t pad_t;
     const double* t_meas64;
     const float* t_meas32;
     const int32_t* bin_of;       // frequency bin of each mode (sensitivity parameters)

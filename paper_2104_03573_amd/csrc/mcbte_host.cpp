@@ -45,6 +45,20 @@ uint32_t surf_class(double d)
     return (r > R(0) && r < R(1)) ? SURF_PARTIAL : (r >= R(1) ? SURF_SPECULAR : SURF_DIFFUSE);
 }
 
+// volume of a tetrahedron (vertices at v[0..2], v[3..5], v[6..8], v[9..11]): |triple product of the
+// edges from vertex 0| / 6
+double tetra_volume(const double* v)
+{
+    double a[3], b[3], c[3];
+    for (int i = 0; i < 3; ++i) {
+        a[i] = v[3 + i] - v[i];
+        b[i] = v[6 + i] - v[i];
+        c[i] = v[9 + i] - v[i];
+    }
+    const double cx = b[1] * c[2] - b[2] * c[1], cy = b[2] * c[0] - b[0] * c[2], cz = b[0] * c[1] - b[1] * c[0];
+    return std::fabs(a[0] * cx + a[1] * cy + a[2] * cz) / 6.0;
+}
+
 // cumulative distribution as 64-bit thresholds; returns the last positive-weight index (-1 if none)
 int64_t build_thresholds(const std::vector<double>& w, std::vector<uint64_t>& thr)
 {
@@ -101,6 +115,9 @@ struct mcbte_tables {
     // host tables
     std::vector<double> C, v, tau, tau2, src_E, ic_edges, ic_dT, t_meas;   // tau2: two-phonon clock (0: none)
     std::vector<double> heat_t, heat_P;   // external heat source: interval edges and power densities
+    std::vector<double> heat_tet;         // its tetrahedra: vertex 0 and the three edges from it
+    std::vector<uint64_t> thr_tet;        // a tetrahedron by volume
+    int64_t last_tet = 0;
     bool two = false;      // some row has a two-phonon clock
     bool spec_w = false;   // some boundary has a specular cutoff frequency
     bool walls = false;    // internal line walls
@@ -281,7 +298,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         return MCBTE_EINVAL;
     }
     // external heat source: transient, ascending edges in [0, t_max], a cuboid inside the box and the solid
-    if (pr.n_heat < 0 || pr.reserved != 0) return MCBTE_EINVAL;
+    if (pr.n_heat < 0 || pr.n_heat_tet < 0 || (pr.n_heat == 0 && pr.n_heat_tet != 0)) return MCBTE_EINVAL;
     if (pr.n_heat > 0) {
         if (!pr.transient || !pr.heat_t || !pr.heat_P || g.n_walls > 0) return MCBTE_EINVAL;
         if (!(pr.heat_t[0] >= 0.0) || !(pr.heat_t[pr.n_heat] <= pr.t_max)) return MCBTE_EINVAL;
@@ -294,6 +311,27 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
             const double dx = std::max({pr.heat_lo[0] - g.pore[c].cx, 0.0, g.pore[c].cx - pr.heat_hi[0]});
             const double dy = std::max({pr.heat_lo[1] - g.pore[c].cy, 0.0, g.pore[c].cy - pr.heat_hi[1]});
             if (dx * dx + dy * dy < g.pore[c].r * g.pore[c].r) return MCBTE_EINVAL;
+        }
+        // tetrahedra: inside the box, positive volume, x-y bounding rectangle clear of the pores
+        if (pr.n_heat_tet > 0 && !pr.heat_tet) return MCBTE_EINVAL;
+        for (int k = 0; k < pr.n_heat_tet; ++k) {
+            const double* v = pr.heat_tet + 12 * (int64_t)k;
+            double lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = hi[a] = v[a];
+                for (int q = 0; q < 4; ++q) {
+                    const double x = v[3 * q + a];
+                    if (!std::isfinite(x) || (!g.unbounded[a] && !(x >= 0.0 && x <= g.L[a]))) return MCBTE_EINVAL;
+                    lo[a] = std::min(lo[a], x);
+                    hi[a] = std::max(hi[a], x);
+                }
+            }
+            if (!(tetra_volume(v) > 0.0)) return MCBTE_EINVAL;
+            for (int c = 0; c < g.n_pores; ++c) {
+                const double dx = std::max({lo[0] - g.pore[c].cx, 0.0, g.pore[c].cx - hi[0]});
+                const double dy = std::max({lo[1] - g.pore[c].cy, 0.0, g.pore[c].cy - hi[1]});
+                if (dx * dx + dy * dy < g.pore[c].r * g.pore[c].r) return MCBTE_EINVAL;
+            }
         }
     }
     if (pr.n_ic < 0 || (pr.n_ic > 0 && (!pr.ic_edges || !pr.ic_dT || pr.ic_axis < 0 || pr.ic_axis > 2 || g.n_pores > 0 ||
@@ -308,6 +346,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
     t->prob.ic_edges = nullptr;
     t->prob.heat_t = nullptr;
     t->prob.heat_P = nullptr;
+    t->prob.heat_tet = nullptr;
     t->prob.ic_dT = nullptr;
     t->prob.spec_table = nullptr;
     t->geom = g;
@@ -437,6 +476,23 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         t->heat_P.assign(pr.heat_P, pr.heat_P + pr.n_heat);
         double Vh = 1.0;
         for (int a = 0; a < 3; ++a) Vh *= g.unbounded[a] ? 1.0 : pr.heat_hi[a] - pr.heat_lo[a];
+        if (pr.n_heat_tet > 0) {   // the union of the tetrahedra: one drawn by volume
+            const int nt = pr.n_heat_tet;
+            std::vector<double> vol((size_t)nt);
+            t->heat_tet.assign(12 * (size_t)nt, 0.0);
+            Vh = 0.0;
+            for (int k = 0; k < nt; ++k) {
+                const double* v = pr.heat_tet + 12 * (int64_t)k;
+                double* o = t->heat_tet.data() + 12 * (size_t)k;
+                for (int a = 0; a < 3; ++a) {
+                    o[a] = v[a];
+                    for (int q = 1; q < 4; ++q) o[3 * q + a] = v[3 * q + a] - v[a];
+                }
+                vol[(size_t)k] = tetra_volume(v);
+                Vh += vol[(size_t)k];
+            }
+            t->last_tet = build_thresholds(vol, t->thr_tet);
+        }
         for (int k = 0; k < pr.n_heat; ++k) {
             if (t->heat_P[k] == 0.0) continue;
             t->src_kind.push_back(SRC_HEAT);
@@ -760,6 +816,11 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         add(t->spec_thr.data(), 8 * t->spec_thr.size());
         add(t->spec_cls.data(), t->spec_cls.size());
         add(t->heat_t.data(), 8 * t->heat_t.size());
+        std::vector<float> tet32(t->heat_tet.size());
+        for (size_t i = 0; i < tet32.size(); ++i) tet32[i] = (float)t->heat_tet[i];
+        add(t->heat_tet.data(), 8 * t->heat_tet.size());
+        add(tet32.data(), 4 * tet32.size());
+        add(t->thr_tet.data(), 8 * t->thr_tet.size());
         size_t total = 0;
         std::vector<size_t> off;
         for (auto& p : parts) {
@@ -797,6 +858,11 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         h.spec_thr = t->spec_thr.empty() ? nullptr : (const uint64_t*)dptr(21);
         h.spec_cls = t->spec_cls.empty() ? nullptr : (const uint8_t*)dptr(22);
         h.heat_t = t->heat_t.empty() ? nullptr : (const double*)dptr(23);
+        h.n_heat_tet = (int32_t)(t->heat_tet.size() / 12);
+        h.heat_tet64 = h.n_heat_tet ? (const double*)dptr(24) : nullptr;
+        h.heat_tet32 = h.n_heat_tet ? (const float*)dptr(25) : nullptr;
+        h.thr_tet = h.n_heat_tet ? (const uint64_t*)dptr(26) : nullptr;
+        h.last_tet = t->last_tet;
         parts[0].first = &h;
         for (size_t i = 0; i < parts.size(); ++i) {
             if (parts[i].second == 0) continue;

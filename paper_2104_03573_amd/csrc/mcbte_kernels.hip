@@ -129,6 +129,7 @@ template <> struct Geo<double> {
     static __device__ __forceinline__ const DevPore64& pore(const DevGeom& g, int i) { return g.pore64[i]; }
     static __device__ __forceinline__ double heat_lo(const DevTab& t, int a) { return t.heat_lo[a]; }
     static __device__ __forceinline__ double heat_w(const DevTab& t, int a) { return t.heat_w[a]; }
+    static __device__ __forceinline__ const double* heat_tet(const DevTab& t) { return t.heat_tet64; }
     static constexpr int prec = 1;
 };
 template <> struct Geo<float> {
@@ -151,6 +152,7 @@ template <> struct Geo<float> {
     static __device__ __forceinline__ const DevPore32& pore(const DevGeom& g, int i) { return g.pore32[i]; }
     static __device__ __forceinline__ float heat_lo(const DevTab& t, int a) { return t.heat_lo32[a]; }
     static __device__ __forceinline__ float heat_w(const DevTab& t, int a) { return t.heat_w32[a]; }
+    static __device__ __forceinline__ const float* heat_tet(const DevTab& t) { return t.heat_tet32; }
     static constexpr int prec = 0;
 };
 
@@ -391,11 +393,34 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
         }
         p.m = cdf_pick(T.thr_wall, T.M, T.last_wall, key64(r1a.x, r1a.y));
     } else if (kind == SRC_HEAT) {
-        // the external heat source: a point of its cuboid, an isotropic direction, the row drawn
-        // by heat capacity (as for the initial condition)
+        // the external heat source: a point of its cuboid, or of one of its tetrahedra (drawn by
+        // volume; the point by folding the unit cube onto the tetrahedron), an isotropic
+        // direction, the row drawn by heat capacity (as for the initial condition)
+        if (T.n_heat_tet > 0) {
+            const W4 r2b = st.block(5);
+            const int k = cdf_pick(T.thr_tet, T.n_heat_tet, T.last_tet, key64(r2b.x, r2b.y));
+            R b0 = up[0], b1 = up[1], b2 = up[2];
+            if (b0 + b1 > R(1)) {              // the cube's halves across b0 + b1 = 1 onto each other
+                b0 = R(1) - b0;
+                b1 = R(1) - b1;
+            }
+            if (b1 + b2 > R(1)) {              // then the prism's parts onto the tetrahedron
+                const R w = b2;
+                b2 = R(1) - b0 - b1;
+                b1 = R(1) - w;
+            } else if (b0 + b1 + b2 > R(1)) {
+                const R w = b2;
+                b2 = b0 + b1 + b2 - R(1);
+                b0 = R(1) - b1 - w;
+            }
+            const R* v = Geo<R>::heat_tet(T) + 12 * k;
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax)
-            p.x[ax] = g.unb[ax] ? R(0) : Geo<R>::heat_lo(T, ax) + up[ax] * Geo<R>::heat_w(T, ax);
+            for (int ax = 0; ax < 3; ++ax) p.x[ax] = ((v[ax] + b0 * v[3 + ax]) + b1 * v[6 + ax]) + b2 * v[9 + ax];
+        } else {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+                p.x[ax] = g.unb[ax] ? R(0) : Geo<R>::heat_lo(T, ax) + up[ax] * Geo<R>::heat_w(T, ax);
+        }
         dir_iso(ud1, ud2, p.o);
         p.s = T.src_sign[src];
         p.m = cdf_pick(T.thr_ic, T.M, T.last_ic, key64(r1a.x, r1a.y));

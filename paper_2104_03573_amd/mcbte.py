@@ -66,9 +66,9 @@ class ProblemC(C.Structure):
                 ("score_axis", C.c_int32), ("n_times", C.c_int32), ("ic_axis", C.c_int32), ("n_ic", C.c_int32),
                 ("n_spec_tables", C.c_int32), ("t_meas", C.POINTER(C.c_double)),
                 ("ic_edges", C.POINTER(C.c_double)), ("ic_dT", C.POINTER(C.c_double)),
-                ("spec_table", C.POINTER(C.c_double)), ("n_heat", C.c_int32), ("reserved", C.c_int32),
+                ("spec_table", C.POINTER(C.c_double)), ("n_heat", C.c_int32), ("n_heat_tet", C.c_int32),
                 ("heat_lo", C.c_double * 3), ("heat_hi", C.c_double * 3), ("heat_t", C.POINTER(C.c_double)),
-                ("heat_P", C.POINTER(C.c_double))]
+                ("heat_P", C.POINTER(C.c_double)), ("heat_tet", C.POINTER(C.c_double))]
 
 
 class Info(C.Structure):
@@ -242,6 +242,11 @@ def structs_from_workload(w: dict):
         for a in range(3):
             P.heat_lo[a], P.heat_hi[a] = heat["lo"][a], heat["hi"][a]
         P.heat_t, P.heat_P = ht.ctypes.data_as(dp), hP.ctypes.data_as(dp)
+        if heat.get("tets") is not None:
+            tets = np.ascontiguousarray(heat["tets"], dtype=np.float64).reshape(-1, 12)
+            keep.append(tets)
+            P.n_heat_tet = tets.shape[0]
+            P.heat_tet = tets.ctypes.data_as(dp)
     return modes, G, D, P, keep
 
 

@@ -38,7 +38,8 @@ def test_library_exports_every_declared_symbol():
                                   lambda: W.transient_bump(N=1000), lambda: W.porous_cell(N=1000),
                                   lambda: W.ballistic_transient(N=100), lambda: W.bulk_gradient(N=10),
                                   lambda: W.film(N=7, d=3e-8, T=100.0, specularity=0.3),
-                                  lambda: W.heated_slab(N=100, t_max=100e-12, n_times=4, n_cells=4)])
+                                  lambda: W.heated_slab(N=100, t_max=100e-12, n_times=4, n_cells=4),
+                                  lambda: W.heated_box(N=100)])
 def test_host_tables_identical_to_oracle(make):
     w = make()
     t = M.Tables(w, device=-1)
@@ -216,6 +217,33 @@ def test_heat_source_inputs():
                                                "t": np.array([0.0, 1e-12]), "P": np.array([1e16])}})
     assert _status(beside) == 0
     oracle.Tables(beside)
+    # regions built from tetrahedra: inside the box, positive volume, clear of the pores
+    box = W.heated_box(N=10)
+    assert _status(box) == 0
+    tet = np.asarray(box["problem"]["heat"]["tets"][0])
+
+    def with_tets(w, tets):
+        w = W.with_(w)
+        w["problem"]["heat"] = dict(w["problem"]["heat"], tets=np.asarray(tets, dtype=np.float64))
+        return w
+    flat = tet.copy()
+    flat[3] = flat[0]                                                               # no volume
+    outside = tet.copy()
+    outside[3, 2] = 250e-9                                                          # the box is 200 nm high
+    in_pore = np.array([[200e-9, 200e-9, 10e-9], [300e-9, 220e-9, 10e-9], [220e-9, 320e-9, 10e-9],
+                        [230e-9, 230e-9, 100e-9]])
+    nan = tet.copy()
+    nan[1, 0] = np.nan
+    for w in (with_tets(box, [flat]), with_tets(box, [outside]), with_tets(box, [nan]),
+              with_tets(W.with_(cell, **{"problem.heat": {"lo": (0.0, 0.0, 0.0), "hi": (100e-9, 500e-9, 500e-9),
+                                                          "t": np.array([0.0, 1e-12]), "P": np.array([1e16])}}),
+                        [in_pore])):
+        assert _status(w) == M.mcbte.EINVAL
+        with pytest.raises(ValueError):
+            oracle.Tables(w)
+    cubes = with_tets(box, W.cube_tets((50e-9, 40e-9, 30e-9), (350e-9, 240e-9, 130e-9)))
+    t6 = M.Tables(cubes, device=-1)
+    assert t6.info["E_tot"] == oracle.Tables(cubes).E_tot
 
 
 def test_sizes_and_messages():

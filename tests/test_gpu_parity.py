@@ -74,6 +74,14 @@ FP64_CASES = {
         "detectors.lo": (0.0, 0.0, 0.0), "detectors.hi": (500e-9, 0.0, 0.0), "detectors.n": (5, 0, 0),
         "problem.heat": {"lo": (0.0, 0.0, 0.0), "hi": (80e-9, 500e-9, 500e-9), "t": np.array([0.0, 5e-12, 20e-12]),
                          "P": np.array([2e17, -5e16])}}),
+    # heat-source regions built from tetrahedra: one in a corner of a closed box (specular and
+    # diffuse walls), and a cuboid as six tetrahedra next to a seventh (silicon-like rows)
+    "heated_box_tet": lambda: W.heated_box(N=1500),
+    "heated_box_tets_diffuse": lambda: W.heated_box(
+        N=1200, specularity=0.0, modes=W.silicon_like_modes(300.0),
+        tets=np.concatenate([W.cube_tets((50e-9, 40e-9, 30e-9), (350e-9, 240e-9, 130e-9)),
+                             [[[20e-9, 260e-9, 20e-9], [390e-9, 280e-9, 30e-9], [60e-9, 295e-9, 40e-9],
+                               [80e-9, 270e-9, 190e-9]]]])),
     # internal line walls: the paper's square pore of four walls, a channel between two walls
     "square_pore_walls": lambda: W.square_pore_cell(N=1000),
     "square_pore_walls_partial": lambda: W.square_pore_cell(N=800, specularity=0.5),
@@ -135,7 +143,7 @@ def _read_state(M, buf, precision, cap):
     return np.stack(f, 1), np.stack(i, 1)
 
 
-@pytest.mark.parametrize("name", ["gray_slab", "film", "transient_bump", "porous_cell", "ballistic_transient",
+@pytest.mark.parametrize("name", ["heated_box_tets_diffuse", "heated_slab", "gray_slab", "film", "transient_bump", "porous_cell", "ballistic_transient",
                                   "square_pore_walls", "walled_slab", "film_two_clocks"])
 def test_emission_matches_oracle(name):
     import torch

@@ -53,15 +53,17 @@ def test_fp32_partial_sums_of_the_transient_detector_against_fp64_accumulation()
     assert rel_sigma <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["transient_bump", "heated_slab"])
+@pytest.mark.parametrize("name", ["transient_bump", "heated_slab", "heated_box"])
 def test_fp32_transient_per_detector_error_against_the_oracle(name):
     """A 1e6-particle prefix in 8 groups: per bin and time, the FP32 launch against the FP64 oracle
     on the same particles, T and q_z, stated relative to the largest bin and to each bin's batch
     standard error.  Every snapshot's total over the bins is exact (a particle's sign counts once
     per time) and the bins agree far inside their statistical errors.  The transient bump starts
-    from its initial condition; the heated slab is heated by a 5 ps pulse in its top 20 nm."""
+    from its initial condition; the heated slab is heated by a 5 ps pulse in its top 20 nm; the
+    heated box by a 10 ps pulse in a tetrahedron."""
     M = _pkg()
-    w = W.transient_bump(N=1_000_000) if name == "transient_bump" else W.heated_slab(N=1_000_000)
+    w = {"transient_bump": W.transient_bump, "heated_slab": W.heated_slab,
+         "heated_box": W.heated_box}[name](N=1_000_000)
     t = M.Tables(w)
     n, G = w["problem"]["N"], 8
     bounds = [(n * i) // G for i in range(G + 1)]
