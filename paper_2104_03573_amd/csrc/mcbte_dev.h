@@ -7,7 +7,10 @@
 #define MCBTE_DEV_MAX_WALLS 16
 #define MCBTE_LDS_TABLE_BYTES (48 * 1024)   // mode tables staged in LDS (thresholds + v + tau)
 #define MCBTE_LDS_TALLY_BYTES (40 * 1024)   // per-workgroup tally privatisation budget
-#define MCBTE_LDS_GUIDE_BYTES 1024           // guide of the relaxation draw (256 packed bounds)
+#define MCBTE_GUIDE_BITS 12                  // finest guide of the relaxation draw: 2^12 + 1 bounds
+#define MCBTE_GUIDE_MIN_BITS 8               // coarsest guide staged in LDS
+// LDS bytes of a guide of 2^bits + 1 uint16 bounds (0 bits: no guide)
+__host__ __device__ inline int64_t guide_lds_bytes(int bits) { return bits > 0 ? (((int64_t(1) << bits) + 1) * 2 + 15) & ~int64_t(15) : 0; }
 #define MCBTE_TALLY_HEADER_BYTES 256
 #define MCBTE_TALLY_COUNTER_OFFSET 192
 // pore lattices: particles whose first free path is long enough to be walked for a while are
@@ -142,7 +145,8 @@ struct DevTab {
     const double* t_meas64;
     const float* t_meas32;
     const int32_t* bin_of;       // frequency bin of each mode (sensitivity parameters)
-    const uint32_t* rel_guide;   // 256 packed search bounds of the relaxation draw, or NULL
+    const uint16_t* rel_guide;   // relaxation draw: entry b = count(thr_rel <= b 2^52), b <= 2^12 (the last
+                                 // entry is M), or NULL (tables of more than 65535 rows)
     const double* tau2_64;       // two-phonon relaxation time of each row (0: no such process)
     const float* tau2_32;
     const double* omega64;       // angular frequency of each row
@@ -190,6 +194,7 @@ struct LaunchArgs {
     int32_t tally_lds;           // tallies privatised in LDS
     int32_t lds_tab_bytes;       // offset of the tally region in dynamic LDS
     int32_t lds_tmeas;           // offset of the staged measurement times in dynamic LDS (0: not staged)
+    int32_t guide_bits;          // bits of the relaxation guide staged in LDS (0: the whole table is searched)
     // sensitivity replay
     double* particle_F;          // per-particle flux score (written by the trace, read by the replay)
     double* adj;                 // n_bins sums, the relaxation-draw sum B, then a work counter

@@ -793,22 +793,20 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         add(t->t_meas.data(), 8 * t->t_meas.size());
         add(tm32.data(), 4 * tm32.size());
         add(t->bin_of.data(), 4 * (size_t)M);
-        // guide of the relaxation draw: entry b packs the number of thresholds <= b 2^56 (low 16
-        // bits) and <= (b + 1) 2^56 (high 16 bits), the bounds of the draw for keys K with top
-        // byte b (the threshold search then only runs between them); tables of more than 65535
-        // rows search the whole table
-        std::vector<uint32_t> guide(256, 0u);
+        // guide of the relaxation draw: entry b is the number of thresholds <= b 2^52 and the last
+        // entry is M, so that the draw for a key K with top 12 bits b lies between entries b and
+        // b + 1 (the threshold search then only runs between them; a launch stages every
+        // 2^(12 - bits)-th entry, a guide of the key's top bits); tables of more than 65535 rows
+        // search the whole table
+        const int n_guide = (1 << MCBTE_GUIDE_BITS) + 1;
+        std::vector<uint16_t> guide(n_guide, 0u);
         if (M <= 65535) {
-            auto count_le = [&](uint64_t K) {
-                return (uint32_t)(std::upper_bound(t->thr_rel.begin(), t->thr_rel.end(), K) - t->thr_rel.begin());
-            };
-            for (int b = 0; b < 256; ++b) {
-                const uint32_t lo = count_le((uint64_t)b << 56);
-                const uint32_t hi = b == 255 ? (uint32_t)M : count_le((uint64_t)(b + 1) << 56);
-                guide[b] = lo | (hi << 16);
-            }
+            for (int b = 0; b < n_guide - 1; ++b)
+                guide[b] = (uint16_t)(std::upper_bound(t->thr_rel.begin(), t->thr_rel.end(),
+                                                       (uint64_t)b << (64 - MCBTE_GUIDE_BITS)) - t->thr_rel.begin());
+            guide[n_guide - 1] = (uint16_t)M;
         }
-        add(guide.data(), 4 * 256);
+        add(guide.data(), 2 * (size_t)n_guide);
         add(t->tau2.data(), 8 * (size_t)M);
         add(tau2_32.data(), 4 * (size_t)M);
         add(t->omega.data(), 8 * (size_t)M);
@@ -849,7 +847,7 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         h.t_meas64 = (const double*)dptr(13);
         h.t_meas32 = (const float*)dptr(14);
         h.bin_of = (const int32_t*)dptr(15);
-        h.rel_guide = M <= 65535 ? (const uint32_t*)dptr(16) : nullptr;
+        h.rel_guide = M <= 65535 ? (const uint16_t*)dptr(16) : nullptr;
         h.tau2_64 = (const double*)dptr(17);
         h.tau2_32 = (const float*)dptr(18);
         h.omega64 = (const double*)dptr(19);
@@ -932,6 +930,7 @@ namespace {
 struct LaunchPlan {
     int block, grid, refill;
     int tally_lds;
+    int guide_bits;              // relaxation guide staged in LDS (0: none)
     int64_t lds_tab;
     int64_t lds_tmeas;           // offset of the staged measurement times (0: none)
     size_t lds;
@@ -942,44 +941,70 @@ int plan_launch(const mcbte_tables* const* ts, int n_inst, const mcbte_run* run,
     const mcbte_tables* t0 = ts[0];
     const int prec = run->precision;
     const int rb = prec / 8;
-    int64_t lds_tab = 0, lds_tally = 0;
+    int64_t lds_rows = 0, lds_tally = 0;
+    bool guided = true;
     for (int i = 0; i < n_inst; ++i) {
         const int64_t M = ts[i]->info.n_modes;
-        lds_tab = std::max<int64_t>(lds_tab, ((M * 8 + 15) & ~int64_t(15)) + 2 * ((M * rb + 15) & ~int64_t(15)) +
-                                                 MCBTE_LDS_GUIDE_BYTES);
+        lds_rows = std::max<int64_t>(lds_rows, ((M * 8 + 15) & ~int64_t(15)) + 2 * ((M * rb + 15) & ~int64_t(15)));
         lds_tally = std::max<int64_t>(lds_tally, ts[i]->info.n_cells * ts[i]->info.n_cols *
                                                      (int64_t)ts[i]->host_view.det.ncomp * 8);
+        guided = guided && ts[i]->info.n_modes <= 65535;
     }
-    if (lds_tab > MCBTE_LDS_TABLE_BYTES || lds_tab > t0->max_lds) return MCBTE_EINVAL;
-    lp.lds_tab = lds_tab;
-    if (ft & FT_WIDE) {             // wide workgroups: the FP32 tally fills the LDS, tables stay in HBM
-        lp.lds_tab = 0;
-        lp.tally_lds = 1;
-        lp.lds = (size_t)(lds_tally / 2);
-        if ((int64_t)lp.lds > t0->max_lds) return MCBTE_EINVAL;
-    } else if (mode >= 2 && mode <= 4) {   // sensitivity replay: the per-bin sums take the place of the tallies
-        const int64_t bins = 8 * t0->info.n_bins;
-        if (lds_tab + bins > t0->max_lds) return MCBTE_EINVAL;
-        lp.tally_lds = 0;
-        lp.lds = (size_t)(lds_tab + bins);
-    } else {
-        lp.tally_lds = (lds_tally <= MCBTE_LDS_TALLY_BYTES && lds_tab + lds_tally <= t0->max_lds) ? 1 : 0;
-        lp.lds = (size_t)(lds_tab + (lp.tally_lds ? lds_tally : 0));
-    }
-    // a solo transient trace also stages its measurement times after the tally where they fit
-    lp.lds_tmeas = 0;
-    if (mode == 0 && n_inst == 1 && t0->host_view.tally_kind == TALLY_TRANSIENT) {
-        const int64_t off = ((int64_t)lp.lds + 15) & ~int64_t(15);
-        const int64_t end = off + (int64_t)t0->host_view.n_times * rb;
-        if (off > 0 && end <= t0->max_lds) {
-            lp.lds_tmeas = off;
-            lp.lds = (size_t)end;
-        }
-    }
+    const int min_bits = guided ? MCBTE_GUIDE_MIN_BITS : 0;
+    if (lds_rows + guide_lds_bytes(min_bits) > MCBTE_LDS_TABLE_BYTES ||
+        lds_rows + guide_lds_bytes(min_bits) > t0->max_lds)
+        return MCBTE_EINVAL;
     const int max_block = (ft & FT_WIDE) ? 1024 : 256;
     lp.block = run->block > 0 ? run->block : max_block;
     if (lp.block % 64 != 0 || lp.block > max_block) return MCBTE_EINVAL;
     lp.refill = run->refill > 0 ? run->refill : 4;
+    // the LDS layout for a guide of `bits`: tables, guide, tallies, measurement times
+    auto layout = [&](int bits) -> bool {
+        const int64_t lds_tab = lds_rows + guide_lds_bytes(bits);
+        lp.guide_bits = bits;
+        lp.lds_tab = lds_tab;
+        if (ft & FT_WIDE) {             // wide workgroups: the FP32 tally fills the LDS, tables stay in HBM
+            lp.guide_bits = 0;        // wide workgroups: the FP32 tally fills the LDS, tables stay in HBM
+            lp.lds_tab = 0;
+            lp.tally_lds = 1;
+            lp.lds = (size_t)(lds_tally / 2);
+            if ((int64_t)lp.lds > t0->max_lds) return false;
+        } else if (mode >= 2 && mode <= 4) {   // sensitivity replay: the per-bin sums take the place of the tallies
+            const int64_t bins = 8 * t0->info.n_bins;
+            if (lds_tab + bins > t0->max_lds) return false;
+            lp.tally_lds = 0;
+            lp.lds = (size_t)(lds_tab + bins);
+        } else {
+            lp.tally_lds = (lds_tally <= MCBTE_LDS_TALLY_BYTES && lds_tab + lds_tally <= t0->max_lds) ? 1 : 0;
+            lp.lds = (size_t)(lds_tab + (lp.tally_lds ? lds_tally : 0));
+        }
+        // a solo transient trace also stages its measurement times after the tally where they fit
+        lp.lds_tmeas = 0;
+        if (mode == 0 && n_inst == 1 && t0->host_view.tally_kind == TALLY_TRANSIENT) {
+            const int64_t off = ((int64_t)lp.lds + 15) & ~int64_t(15);
+            const int64_t end = off + (int64_t)t0->host_view.n_times * rb;
+            if (off > 0 && end <= t0->max_lds) {
+                lp.lds_tmeas = off;
+                lp.lds = (size_t)end;
+            }
+        }
+        return true;
+    };
+    if (!layout(min_bits)) return MCBTE_EINVAL;
+    // the finest guide that leaves as many workgroups per compute unit as the coarsest (a finer
+    // guide shortens the relaxation draw's search, which otherwise idles most lanes of a wave
+    // while a few search the crowded stretches of the table)
+    if (guided && !(ft & FT_WIDE)) {
+        const LaunchPlan coarse = lp;
+        const int occ0 = trace_occupancy(mode, prec, t0->host_view.tally_kind, ft, lp.block, lp.lds);
+        bool found = false;
+        for (int bits = MCBTE_GUIDE_BITS; bits > min_bits && !found; --bits) {
+            const bool same_tally = layout(bits) && lp.tally_lds == coarse.tally_lds &&
+                                    (lp.lds_tmeas > 0) == (coarse.lds_tmeas > 0);
+            found = same_tally && trace_occupancy(mode, prec, t0->host_view.tally_kind, ft, lp.block, lp.lds) >= occ0;
+        }
+        if (!found) lp = coarse;
+    }
     if (run->grid > 0) {
         lp.grid = run->grid;
     } else {
@@ -1009,7 +1034,8 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     if (ft == 0 && run->precision == 32) {
         const int64_t t64 = t->info.n_cells * t->info.n_cols * (int64_t)t->host_view.det.ncomp * 8;
         const int64_t M = t->info.n_modes;
-        const int64_t tab = ((M * 8 + 15) & ~int64_t(15)) + 2 * ((M * 4 + 15) & ~int64_t(15)) + MCBTE_LDS_GUIDE_BYTES;
+        const int64_t tab = ((M * 8 + 15) & ~int64_t(15)) + 2 * ((M * 4 + 15) & ~int64_t(15)) +
+                            guide_lds_bytes(M <= 65535 ? MCBTE_GUIDE_MIN_BITS : 0);
         const bool fits64 = t64 <= MCBTE_LDS_TALLY_BYTES && tab + t64 <= t->max_lds;
         if (!fits64 && t64 / 2 <= t->max_lds) ft = FT_WIDE;
     }
@@ -1039,6 +1065,7 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     a.n_log = run->event_log ? run->n_log : 0;
     a.tally_lds = lp.tally_lds;
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
+    a.guide_bits = lp.guide_bits;
     a.lds_tmeas = (int32_t)lp.lds_tmeas;
     a.particle_F = run->particle_F;
     const hipError_t e = launch_trace(a, 0, run->precision, t->host_view.tally_kind, ft, lp.block, lp.grid, lp.lds,
@@ -1124,6 +1151,7 @@ int mcbte_trace_batch(const mcbte_tables* const* ts, int32_t n_inst, const int64
     a.n_chunks = cstart[n_inst];
     a.tally_lds = lp.tally_lds;
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
+    a.guide_bits = lp.guide_bits;
     const hipError_t e = launch_trace(a, 1, run->precision, t0->host_view.tally_kind, ft, lp.block, lp.grid, lp.lds, s);
     return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
 }
@@ -1188,6 +1216,7 @@ int mcbte_trace_batch_static(const mcbte_tables* const* ts, int32_t n_inst, cons
     a.n_chunks = sa.cstart[n_inst];
     a.tally_lds = lp.tally_lds;
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
+    a.guide_bits = lp.guide_bits;
     const hipError_t e = launch_trace(a, 1, run->precision, t0->host_view.tally_kind, ft, lp.block, lp.grid, lp.lds, s);
     return e == hipSuccess ? MCBTE_OK : MCBTE_EHIP;
 }
@@ -1312,6 +1341,7 @@ int mcbte_adjoint(const mcbte_tables* t, const mcbte_run* run, int32_t estimator
     a.n = n;
     a.capacity = n;
     a.lds_tab_bytes = (int32_t)lp.lds_tab;
+    a.guide_bits = lp.guide_bits;
     a.particle_F = const_cast<double*>(particle_F);
     a.adj = adj;
     // local form: the split given, else the smallest bounded extent or pore diameter (every mode

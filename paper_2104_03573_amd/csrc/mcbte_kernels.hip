@@ -171,12 +171,13 @@ __device__ __forceinline__ int cdf_pick(const uint64_t* thr, int n, int64_t last
 }
 
 // the same choice as cdf_pick for a non-decreasing table, searching only between the bounds the
-// guide gives for the key's top byte (guide[b] = count(thr <= b 2^56) | count(thr <= (b+1) 2^56) << 16)
-__device__ __forceinline__ int cdf_pick_guided(const uint64_t* thr, const uint32_t* guide, int n, int64_t last,
-                                               uint64_t K)
+// guide gives for the key's top 64 - shift bits (guide[b] = count(thr <= b 2^shift), b <= 2^(64 - shift));
+// a guide as fine as the table's spread keeps the search at a step or two for every lane
+__device__ __forceinline__ int cdf_pick_guided(const uint64_t* thr, const uint16_t* guide, int shift, int n,
+                                               int64_t last, uint64_t K)
 {
-    const uint32_t g = guide[(uint32_t)(K >> 56)];
-    int lo = (int)(g & 0xFFFFu), hi = (int)(g >> 16);          // count(thr <= K) lies in [lo, hi]
+    const uint32_t b = (uint32_t)(K >> shift);
+    int lo = guide[b], hi = guide[b + 1];                        // count(thr <= K) lies in [lo, hi]
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (thr[mid] <= K) lo = mid + 1;
@@ -210,6 +211,19 @@ template <typename R> struct Part {
 template <typename R>
 __device__ __forceinline__ void dir_about(R mu, R a, R b, const R n[3], R o[3])
 {
+    if (n[2] == R(0) && n[0] != R(0) && n[1] != R(0)) {
+        // a normal in the x-y plane with both components nonzero (a pore's, a line wall's): the
+        // frame below takes j = 2, so t1 = (-n1, n0, 0) / |n|, t2 = (0, 0, n0 t1_1 - n1 t1_0); the
+        // same roundings without the products and sums that are exact zeros (only the sign of an
+        // exactly zero component can differ)
+        const R len = r_sqrt(n[1] * n[1] + n[0] * n[0]);
+        const R t10 = r_div(-n[1], len), t11 = r_div(n[0], len);
+        const R t22 = n[0] * t11 - n[1] * t10;
+        o[0] = mu * n[0] + a * t10;
+        o[1] = mu * n[1] + a * t11;
+        o[2] = b * t22;
+        return;
+    }
     int j = 0;
     R m0 = fabs(n[0]);
     if (fabs(n[1]) < m0) { j = 1; m0 = fabs(n[1]); }
@@ -770,8 +784,9 @@ struct Tabs {
     const uint64_t* thr_rel;   // LDS
     const R* v;                // LDS
     const R* tau;              // LDS
-    const uint32_t* guide;     // LDS: bounds of the relaxation draw, or NULL (search the whole table)
+    const uint16_t* guide;     // bounds of the relaxation draw (LDS when staged), or NULL (search the whole table)
     const R* tmeas;            // measurement times (transient tallies): LDS where staged, else the table block
+    int gshift;                // key bits below the guide's index
 };
 
 // The launch-uniform values the flight loop reads, loaded once before it so that they stay in
@@ -1632,7 +1647,7 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         if (relax) {
             // three-phonon relaxation: frequency from the post-scattering distribution
             // (weights C/tau), isotropic direction, new free flight, sign kept
-            p.m = tb.guide ? cdf_pick_guided(tb.thr_rel, tb.guide, H.M, H.last_rel, key64(w0.x, w0.y))
+            p.m = tb.guide ? cdf_pick_guided(tb.thr_rel, tb.guide, tb.gshift, H.M, H.last_rel, key64(w0.x, w0.y))
                            : cdf_pick(tb.thr_rel, H.M, H.last_rel, key64(w0.x, w0.y));
             p.o[0] = sth * cs;
             p.o[1] = sth * sn;
@@ -2417,15 +2432,16 @@ __global__ void __launch_bounds__(256) k_emit(const DevTab* __restrict__ tabs, u
 // persistent trace kernels
 // ------------------------------------------------------------------------------------------
 
-// stage the relaxation table, velocities and relaxation times of one instance into LDS
+// stage the relaxation table, velocities and relaxation times of one instance into LDS, with the
+// relaxation guide coarsened to 2^bits + 1 bounds (entry i of the finest guide every 2^(12 - bits))
 template <typename R>
-__device__ __forceinline__ Tabs<R> stage_tables(const DevTab& T, unsigned char* smem)
+__device__ __forceinline__ Tabs<R> stage_tables(const DevTab& T, unsigned char* smem, int bits)
 {
     const int M = T.M;
     uint64_t* s_thr = (uint64_t*)smem;
     R* s_v = (R*)(smem + align16((int64_t)M * 8));
     R* s_tau = (R*)(smem + align16((int64_t)M * 8) + align16((int64_t)M * sizeof(R)));
-    uint32_t* s_guide = (uint32_t*)(smem + align16((int64_t)M * 8) + 2 * align16((int64_t)M * sizeof(R)));
+    uint16_t* s_guide = (uint16_t*)(smem + align16((int64_t)M * 8) + 2 * align16((int64_t)M * sizeof(R)));
     const R* gv = Geo<R>::v(T);
     const R* gt = Geo<R>::tau(T);
     for (int i = threadIdx.x; i < M; i += blockDim.x) {
@@ -2433,9 +2449,10 @@ __device__ __forceinline__ Tabs<R> stage_tables(const DevTab& T, unsigned char* 
         s_v[i] = gv[i];
         s_tau[i] = gt[i];
     }
-    if (T.rel_guide)
-        for (int i = threadIdx.x; i < 256; i += blockDim.x) s_guide[i] = T.rel_guide[i];
-    return Tabs<R>{s_thr, s_v, s_tau, T.rel_guide ? s_guide : nullptr, Geo<R>::tmeas_ptr(T)};
+    const bool guided = T.rel_guide && bits >= MCBTE_GUIDE_MIN_BITS && bits <= MCBTE_GUIDE_BITS;
+    if (guided)
+        for (int i = threadIdx.x; i <= (1 << bits); i += blockDim.x) s_guide[i] = T.rel_guide[i << (MCBTE_GUIDE_BITS - bits)];
+    return Tabs<R>{s_thr, s_v, s_tau, guided ? s_guide : nullptr, Geo<R>::tmeas_ptr(T), 64 - bits};
 }
 
 __device__ __forceinline__ int64_t lds_tally_size(const DevTab& T) { return T.det.n_cells * T.det.n_cols * T.det.ncomp; }
@@ -2553,14 +2570,18 @@ __device__ __forceinline__ void end_particle(const Part<R>& p, int transient, do
 // AK = 1 (likelihood ratio), 2 (pathwise) or 3 (local pathwise): the sensitivity replay of the same particles: no
 // tallies; the per-bin sums go to LDS and then to a.adj; the work counter lives after the sums.
 template <typename R, int TK, int AK, int FT>
-__global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256) k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
+// (the plain pore-lattice kernel is held to 128 VGPRs, four waves per SIMD, which it fits without
+// spilling; the others keep what their register use allows)
+__global__ void __launch_bounds__((FT & FT_WIDE) ? 1024 : 256, (FT & (FT_LATTICE | FT_PLAIN)) == (FT_LATTICE | FT_PLAIN) ? 4 : 1)
+k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const DevTab& T = tabs[0];
     const Hot<R> H = load_hot<R>(T, AK == 0 && a.particle_F == nullptr);
     constexpr bool WIDE = (FT & FT_WIDE) != 0;
-    Tabs<R> tb = WIDE ? Tabs<R>{T.thr_rel, Geo<R>::v(T), Geo<R>::tau(T), T.rel_guide, Geo<R>::tmeas_ptr(T)}
-                      : stage_tables<R>(T, smem);
+    Tabs<R> tb = WIDE ? Tabs<R>{T.thr_rel, Geo<R>::v(T), Geo<R>::tau(T), T.rel_guide, Geo<R>::tmeas_ptr(T),
+                                64 - MCBTE_GUIDE_BITS}
+                      : stage_tables<R>(T, smem, a.guide_bits);
     if (TK == TALLY_TRANSIENT && a.lds_tmeas > 0) {     // the measurement times, where the LDS has room
         R* s_tm = (R*)(smem + a.lds_tmeas);
         for (int i = threadIdx.x; i < T.n_times; i += blockDim.x) s_tm[i] = tb.tmeas[i];
@@ -2762,7 +2783,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
         const DevTab& T = tabs[inst];
         const Hot<R> H = load_hot<R>(T, true);
         if (inst != cur) {
-            tb = stage_tables<R>(T, smem);
+            tb = stage_tables<R>(T, smem, a.guide_bits);
             if (a.tally_lds) {
                 const int64_t n = lds_tally_size(T);
                 for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s_tally[i] = 0.0;
