@@ -140,6 +140,9 @@ struct DevTab {
     const float* heat_tet32;
     const uint64_t* thr_tet;
     int64_t last_tet;
+    // emission row draws: guides of thr_wall and thr_ic in the form of rel_guide, or NULL
+    const uint16_t* wall_guide;
+    const uint16_t* ic_guide;
     int32_t n_heat_tet;
     int32_t pad_t;
     const double* t_meas64;

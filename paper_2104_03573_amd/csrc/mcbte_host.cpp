@@ -799,13 +799,17 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         // 2^(12 - bits)-th entry, a guide of the key's top bits); tables of more than 65535 rows
         // search the whole table
         const int n_guide = (1 << MCBTE_GUIDE_BITS) + 1;
-        std::vector<uint16_t> guide(n_guide, 0u);
-        if (M <= 65535) {
-            for (int b = 0; b < n_guide - 1; ++b)
-                guide[b] = (uint16_t)(std::upper_bound(t->thr_rel.begin(), t->thr_rel.end(),
-                                                       (uint64_t)b << (64 - MCBTE_GUIDE_BITS)) - t->thr_rel.begin());
-            guide[n_guide - 1] = (uint16_t)M;
-        }
+        auto make_guide = [&](const std::vector<uint64_t>& thr) {
+            std::vector<uint16_t> gd(n_guide, 0u);
+            if (M <= 65535) {
+                for (int b = 0; b < n_guide - 1; ++b)
+                    gd[b] = (uint16_t)(std::upper_bound(thr.begin(), thr.end(), (uint64_t)b << (64 - MCBTE_GUIDE_BITS)) -
+                                       thr.begin());
+                gd[n_guide - 1] = (uint16_t)M;
+            }
+            return gd;
+        };
+        const std::vector<uint16_t> guide = make_guide(t->thr_rel);
         add(guide.data(), 2 * (size_t)n_guide);
         add(t->tau2.data(), 8 * (size_t)M);
         add(tau2_32.data(), 4 * (size_t)M);
@@ -819,6 +823,10 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         add(t->heat_tet.data(), 8 * t->heat_tet.size());
         add(tet32.data(), 4 * tet32.size());
         add(t->thr_tet.data(), 8 * t->thr_tet.size());
+        // the emission draws' guides (the same form as the relaxation draw's)
+        const std::vector<uint16_t> wall_guide = make_guide(t->thr_wall), ic_guide = make_guide(t->thr_ic);
+        add(wall_guide.data(), 2 * (size_t)n_guide);
+        add(ic_guide.data(), 2 * (size_t)n_guide);
         size_t total = 0;
         std::vector<size_t> off;
         for (auto& p : parts) {
@@ -861,6 +869,8 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         h.heat_tet32 = h.n_heat_tet ? (const float*)dptr(25) : nullptr;
         h.thr_tet = h.n_heat_tet ? (const uint64_t*)dptr(26) : nullptr;
         h.last_tet = t->last_tet;
+        h.wall_guide = M <= 65535 ? (const uint16_t*)dptr(27) : nullptr;
+        h.ic_guide = M <= 65535 ? (const uint16_t*)dptr(28) : nullptr;
         parts[0].first = &h;
         for (size_t i = 0; i < parts.size(); ++i) {
             if (parts[i].second == 0) continue;

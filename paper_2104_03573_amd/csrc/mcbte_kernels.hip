@@ -186,6 +186,12 @@ __device__ __forceinline__ int cdf_pick_guided(const uint64_t* thr, const uint16
     return lo < n ? lo : (int)last;
 }
 
+// an emission row draw: guided where the table has a guide (global memory), the same choice
+__device__ __forceinline__ int cdf_pick_rows(const uint64_t* thr, const uint16_t* guide, int n, int64_t last, uint64_t K)
+{
+    return guide ? cdf_pick_guided(thr, guide, 64 - MCBTE_GUIDE_BITS, n, last, K) : cdf_pick(thr, n, last, K);
+}
+
 template <typename R> struct Part {
     R x[3], o[3];
     R t, dtr;            // time, time left until the next scattering event
@@ -365,7 +371,7 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
         }
         dir_cos(ud1, ud2, n, p.o);
         p.s = T.src_sign[src];
-        p.m = cdf_pick(T.thr_wall, T.M, T.last_wall, key64(r1a.x, r1a.y));
+        p.m = cdf_pick_rows(T.thr_wall, T.wall_guide, T.M, T.last_wall, key64(r1a.x, r1a.y));
     } else if (kind == SRC_IWALL) {
         // a point of the isothermal line wall (along the segment, through the thickness),
         // directions cosine-weighted about its normal
@@ -376,7 +382,7 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
         const R n[3] = {w.nx, w.ny, R(0)};
         dir_cos(ud1, ud2, n, p.o);
         p.s = T.src_sign[src];
-        p.m = cdf_pick(T.thr_wall, T.M, T.last_wall, key64(r1a.x, r1a.y));
+        p.m = cdf_pick_rows(T.thr_wall, T.wall_guide, T.M, T.last_wall, key64(r1a.x, r1a.y));
     } else if (kind == SRC_GRAD) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) p.x[ax] = g.unb[ax] ? R(0) : up[ax] * Geo<R>::L(g, ax);
@@ -405,7 +411,7 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
             p.o[1] = -p.o[1];
             p.o[2] = -p.o[2];
         }
-        p.m = cdf_pick(T.thr_wall, T.M, T.last_wall, key64(r1a.x, r1a.y));
+        p.m = cdf_pick_rows(T.thr_wall, T.wall_guide, T.M, T.last_wall, key64(r1a.x, r1a.y));
     } else if (kind == SRC_HEAT) {
         // the external heat source: a point of its cuboid, or of one of its tetrahedra (drawn by
         // volume; the point by folding the unit cube onto the tetrahedron), an isotropic
@@ -437,7 +443,7 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
         }
         dir_iso(ud1, ud2, p.o);
         p.s = T.src_sign[src];
-        p.m = cdf_pick(T.thr_ic, T.M, T.last_ic, key64(r1a.x, r1a.y));
+        p.m = cdf_pick_rows(T.thr_ic, T.ic_guide, T.M, T.last_ic, key64(r1a.x, r1a.y));
     } else {
         const int c = T.src_ref[src];
         const int ia = T.ic_axis;
@@ -448,7 +454,7 @@ __device__ __forceinline__ void emit_particle(const DevTab& T, const Stream& st,
             p.x[ax] = (ax == ia) ? e0 + up[ax] * width : (g.unb[ax] ? R(0) : up[ax] * Geo<R>::L(g, ax));
         dir_iso(ud1, ud2, p.o);
         p.s = T.src_sign[src];
-        p.m = cdf_pick(T.thr_ic, T.M, T.last_ic, key64(r1a.x, r1a.y));
+        p.m = cdf_pick_rows(T.thr_ic, T.ic_guide, T.M, T.last_ic, key64(r1a.x, r1a.y));
     }
     if (kind == SRC_HEAT) {   // a time uniform in the source's interval
         const int k = T.src_ref[src];
@@ -2545,8 +2551,9 @@ __global__ void __launch_bounds__(256) k_prio_scan(const DevTab* __restrict__ ta
         const Stream st{(uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)pid, (uint32_t)(pid >> 32), inst};
         const W4 r0a = st.block(0), r1a = st.block(2);
         const int src = T.S == 1 ? 0 : cdf_pick(T.thr_src, T.S, T.last_src, key64(r0a.x, r0a.y));
-        const int m = T.src_kind[src] == SRC_IC ? cdf_pick(T.thr_ic, T.M, T.last_ic, key64(r1a.x, r1a.y))
-                                                : cdf_pick(T.thr_wall, T.M, T.last_wall, key64(r1a.x, r1a.y));
+        const int m = T.src_kind[src] == SRC_IC || T.src_kind[src] == SRC_HEAT
+                          ? cdf_pick_rows(T.thr_ic, T.ic_guide, T.M, T.last_ic, key64(r1a.x, r1a.y))
+                          : cdf_pick_rows(T.thr_wall, T.wall_guide, T.M, T.last_wall, key64(r1a.x, r1a.y));
         if ((key64(r0a.z, r0a.w) >> 11) >= T.prio_thr[m]) {
             const unsigned long long k = atomicAdd(count, 1ull);
             if (k < MCBTE_PRIO_CAP) list[k] = (int64_t)pid;
