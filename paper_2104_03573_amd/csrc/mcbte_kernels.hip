@@ -45,9 +45,16 @@ __host__ __device__ __forceinline__ int64_t align16(int64_t x) { return (x + 15)
 struct W4 { uint32_t x, y, z, w; };
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64 products
-// (v_mad_u64_u32) and two three-way XORs; the key schedule is wave-uniform.
+// (v_mad_u64_u32) and two three-way XORs; the key schedule is wave-uniform.  Every stream of a
+// launch has the same key (the seed), so the key lives in scalar registers; the empty asm keeps
+// its schedule inside each call (two scalar adds a round) instead of twenty round keys held, and
+// spilled, across the whole persistent kernel.  (Every lane holds the key, so the first active
+// lane's copy is the wave's.)
 __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
 {
+    k0 = __builtin_amdgcn_readfirstlane(k0);
+    k1 = __builtin_amdgcn_readfirstlane(k1);
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
@@ -1775,7 +1782,7 @@ __device__ __forceinline__ void coop_bounces(const DevTab& T, const Tabs<R>& tb,
     const R L = Geo<R>::L(T.g, aw);
     const int m = __shfl(p.m, leader, 64);
     const R sg = (R)__shfl(p.s, leader, 64);
-    // the owner's random stream (a lane that never started a particle holds no valid key)
+    // the owner's random stream
     const Stream st{(uint32_t)__shfl((int)st_own.k0, leader, 64), (uint32_t)__shfl((int)st_own.k1, leader, 64),
                     (uint32_t)__shfl((int)st_own.plo, leader, 64), (uint32_t)__shfl((int)st_own.phi, leader, 64),
                     (uint32_t)__shfl((int)st_own.inst, leader, 64)};
@@ -2619,7 +2626,7 @@ k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
     Part<R> p;
     p.sn = 0;                          // no pending snapshots (lanes that never hold a particle too)
     p.tk = -1;
-    Stream st{0u, 0u, 0u, 0u, 0u};
+    Stream st{(uint32_t)a.seed, (uint32_t)(a.seed >> 32), 0u, 0u, 0u};   // the launch's key in every lane
     LaneCounts cnt;
 #pragma unroll
     for (int q = 0; q < LaneCounts::N; ++q) cnt.c[q] = 0;
@@ -2811,7 +2818,7 @@ __global__ void __launch_bounds__(256) k_trace_batch(const DevTab* __restrict__ 
         Part<R> p;
         p.sn = 0;
         p.tk = -1;
-        Stream st{0u, 0u, 0u, 0u, 0u};
+        Stream st{(uint32_t)a.seed, (uint32_t)(a.seed >> 32), 0u, 0u, 0u};
         LogRow lg{nullptr, 0, 2};
         AdjCtx adj{nullptr, 0.0, 0.0, 0u, 0.0};
         PathCtx<R> pc;            // unused by the trace
