@@ -143,6 +143,12 @@ struct DevTab {
     // emission row draws: guides of thr_wall and thr_ic in the form of rel_guide, or NULL
     const uint16_t* wall_guide;
     const uint16_t* ic_guide;
+    // measurement times: entry b = count(t_k < b t_max / 256) for b < 256, entry 256 = n_times (a
+    // time t lies in bucket floor(t 256 / t_max)); NULL: not transient or more than 65535 times
+    const uint16_t* tm_guide;
+    double tm_gs64;              // 256 / t_max
+    float tm_gs32;
+    int32_t pad_tg;
     int32_t n_heat_tet;
     int32_t pad_t;
     const double* t_meas64;

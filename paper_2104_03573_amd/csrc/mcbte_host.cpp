@@ -827,6 +827,17 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         const std::vector<uint16_t> wall_guide = make_guide(t->thr_wall), ic_guide = make_guide(t->thr_ic);
         add(wall_guide.data(), 2 * (size_t)n_guide);
         add(ic_guide.data(), 2 * (size_t)n_guide);
+        // the measurement times' guide (snapshot ranges of transient segments)
+        std::vector<uint16_t> tm_guide;
+        const bool tm_guided = pr.transient && !t->t_meas.empty() && t->t_meas.size() <= 65535;
+        if (tm_guided) {
+            tm_guide.resize(257);
+            for (int b = 0; b < 256; ++b)
+                tm_guide[b] = (uint16_t)(std::lower_bound(t->t_meas.begin(), t->t_meas.end(), b * (pr.t_max / 256.0)) -
+                                         t->t_meas.begin());
+            tm_guide[256] = (uint16_t)t->t_meas.size();
+        }
+        add(tm_guide.data(), 2 * tm_guide.size());
         size_t total = 0;
         std::vector<size_t> off;
         for (auto& p : parts) {
@@ -871,6 +882,9 @@ int mcbte_build_tables(const mcbte_mode* modes, int32_t M, const mcbte_geometry*
         h.last_tet = t->last_tet;
         h.wall_guide = M <= 65535 ? (const uint16_t*)dptr(27) : nullptr;
         h.ic_guide = M <= 65535 ? (const uint16_t*)dptr(28) : nullptr;
+        h.tm_guide = tm_guided ? (const uint16_t*)dptr(29) : nullptr;
+        h.tm_gs64 = tm_guided ? 256.0 / pr.t_max : 0.0;
+        h.tm_gs32 = (float)h.tm_gs64;
         parts[0].first = &h;
         for (size_t i = 0; i < parts.size(); ++i) {
             if (parts[i].second == 0) continue;

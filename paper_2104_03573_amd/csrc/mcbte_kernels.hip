@@ -626,8 +626,19 @@ __device__ __forceinline__ void tally_grid(const DevTab& T, const TallyCtx& tc, 
 // t_k with t0 <= t_k < t1; the step only records them (snap_pend) and the whole wave then scores
 // the records of all its lanes together (snap_wave), 64 snapshots per pass however they are
 // spread over the lanes (a per-lane loop ran at 9 % lane efficiency: few lanes have many).
+// bounds of count(t_k < t) from the measurement-time guide gd: one bucket of slack on each side
+// covers the rounding of t's bucket and of the times' copies in the trajectories' precision
 template <typename R>
-__device__ __forceinline__ void snap_pend(const R* tmeas, int nt, Part<R>& p, R t1, R vm)
+__device__ __forceinline__ void tm_bounds(const uint16_t* gd, R gs, R t, int& lo, int& hi)
+{
+    int b = (int)(t * gs);
+    b = b < 0 ? 0 : (b > 255 ? 255 : b);
+    lo = gd[b > 0 ? b - 1 : 0];
+    hi = gd[b + 2 < 256 ? b + 2 : 256];
+}
+
+template <typename R>
+__device__ __forceinline__ void snap_pend(const R* tmeas, int nt, const uint16_t* gd, R gs, Part<R>& p, R t1, R vm)
 {
     // first k with t_k >= t0: found once per particle, then carried from segment to segment (a
     // particle's time only grows, and each segment starts where the previous one ended)
@@ -635,6 +646,7 @@ __device__ __forceinline__ void snap_pend(const R* tmeas, int nt, Part<R>& p, R 
     if (k0 < 0) {
         int hi = nt;
         k0 = 0;
+        if (gd) tm_bounds<R>(gd, gs, p.t, k0, hi);
         while (k0 < hi) {
             const int mid = (k0 + hi) >> 1;
             if (tmeas[mid] < p.t) k0 = mid + 1;
@@ -645,6 +657,11 @@ __device__ __forceinline__ void snap_pend(const R* tmeas, int nt, Part<R>& p, R 
     if (k1 < nt && tmeas[k1] < t1) {
         int hi = nt;
         ++k1;
+        if (gd) {
+            int lo;
+            tm_bounds<R>(gd, gs, t1, lo, hi);
+            k1 = k1 > lo ? k1 : lo;
+        }
         while (k1 < hi) {
             const int mid = (k1 + hi) >> 1;
             if (tmeas[mid] < t1) k1 = mid + 1;
@@ -666,18 +683,54 @@ __device__ __forceinline__ void snap_pend(const R* tmeas, int nt, Part<R>& p, R 
 template <typename R>
 __device__ __forceinline__ R lane_r(R v, int src) { return __shfl(v, src, 64); }
 
+// Wave-wide scans by DPP (all 64 lanes active): within each row of 16 lanes the partial results
+// move right by 1, 2, 4 and 8 lanes, then the last lane of a row is broadcast into the next rows
+// (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3).  Register-to-register moves,
+// with none of the LDS round trip a cross-lane shuffle takes.
+__device__ __forceinline__ int dpp_incl_sum(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return v;
+}
+
+// the OR of every lane's v (in every lane)
+__device__ __forceinline__ uint32_t dpp_or_all(uint32_t v)
+{
+    int x = (int)v;
+    x |= __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);
+    x |= __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);
+    x |= __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);
+    x |= __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);
+    x |= __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);
+    x |= __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_readlane(x, 63);
+}
+
+// the position of the set bit of L that has r set bits below it (L holds more than r)
+__device__ __forceinline__ int nth_set_bit(unsigned long long L, int r)
+{
+    int pos = 0;                     // the largest pos with popcount(L below pos) <= r
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (__popcll(L & ((1ull << (pos + step)) - 1ull)) <= r) pos += step;
+    return pos;
+}
+
 template <typename R>
 __device__ __forceinline__ void snap_wave(const DevTab& T, const TallyCtx& tc, const R* tmeas, Part<R>& p)
 {
-    if (__ballot(p.sn > 0) == 0ull) return;
+    const unsigned long long L = __ballot(p.sn > 0);   // the lanes holding snapshots
+    if (L == 0ull) return;
     const int lane = threadIdx.x & 63;
-    int S = p.sn;                    // inclusive prefix sum of the lanes' snapshot counts
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(S, off, 64);
-        if (lane >= off) S += t;
-    }
-    const int total = __shfl(S, 63, 64);
+    const int S = dpp_incl_sum(p.sn);   // inclusive prefix sum of the lanes' snapshot counts
+    const int total = __builtin_amdgcn_readlane(S, 63);
+    const int kb = p.sk0 - (S - p.sn);  // measurement index of snapshot g of this lane: kb + g
+    const R sv = p.s < 0 ? -p.svm : p.svm;
     const DevDet& D = T.det;
     int gn[3];
     R glo[3], ghi[3], gsc[3];
@@ -694,23 +747,30 @@ __device__ __forceinline__ void snap_wave(const DevTab& T, const TallyCtx& tc, c
     for (int q = 0; q < 4; ++q) slots |= ((uint32_t)D.slot[q] & 0xFFu) << (8 * q);
     for (int base = 0; base < total; base += 64) {
         const int g = base + lane;
-        int own = 0;                 // the lane whose records hold snapshot g: count of S_i <= g
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1) {
-            const int c = own + step - 1;
-            if (__shfl(S, c < 63 ? c : 63, 64) <= g) own += step;
-        }
-        own = own < 63 ? own : 63;
-        const int first = __shfl(S, own, 64) - __shfl(p.sn, own, 64);
-        const int k = __shfl(p.sk0, own, 64) + (g - first);
-        R x0[3], o[3];
+        // the lane whose records hold snapshot g: among the lanes with snapshots (L), the one
+        // after the rank(g) = #{i in L : S_i <= g} whose ranges end at or before g.  Ranges ending
+        // in this pass's window (1 <= S_i - base <= 63) are distinct bits of W; those ending before
+        // it are counted by one ballot.
+        const int e = S - base;
+        const bool ends_in = ((L >> lane) & 1ull) && e >= 1 && e <= 63;
+        const uint32_t wlo = dpp_or_all(ends_in && e < 32 ? 1u << e : 0u);
+        const uint32_t whi = dpp_or_all(ends_in && e >= 32 ? 1u << (e - 32) : 0u);
+        const unsigned long long W = ((unsigned long long)whi << 32) | wlo;
+        const int c0 = __popcll(__ballot(((L >> lane) & 1ull) && e <= 0));
+        const unsigned long long upto = lane == 63 ? ~0ull : (2ull << lane) - 1ull;
+        const int rank = c0 + __popcll(W & upto);
+        const int own = rank < __popcll(L) ? nth_set_bit(L, rank) : 63;
+        const int k = __shfl(kb, own, 64) + g;
+        // the owner's segment: positions along the binned axes, direction components those axes
+        // and the scored flux components need, start time, and speed with the particle's sign
+        R x0[3] = {R(0), R(0), R(0)}, o[3] = {R(0), R(0), R(0)};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            x0[a] = lane_r<R>(p.sx[a], own);
-            o[a] = lane_r<R>(p.so[a], own);
+            if (gn[a] > 0) x0[a] = lane_r<R>(p.sx[a], own);
+            if (gn[a] > 0 || (mask & (2 << a))) o[a] = lane_r<R>(p.so[a], own);
         }
-        const R t0 = lane_r<R>(p.st0, own), vm = lane_r<R>(p.svm, own);
-        const R sg = (R)__shfl(p.s, own, 64);
+        const R t0 = lane_r<R>(p.st0, own), svm = lane_r<R>(sv, own);
+        const R vm = fabs(svm), sg = copysign(R(1), svm);
         if (g < total) {
             const R dist = vm * (tmeas[k] - t0);
             int64_t cell = 0;
@@ -1469,7 +1529,8 @@ __device__ __forceinline__ bool flight(const DevTab& T, const Hot<R>& H, const T
         const R dt = (ev == 0) ? p.dtr : (ev == 1 ? r_div(d, vm) : tmax - p.t);
         const R t_end = (ev == 2) ? tmax : p.t + dt;
         if (TK == TALLY_TRANSIENT) {
-            snap_pend<R>(tb.tmeas, T.n_times, p, t_end, vm);
+            snap_pend<R>(tb.tmeas, T.n_times, T.tm_guide, std::is_same<R, float>::value ? (R)T.tm_gs32 : (R)T.tm_gs64,
+                         p, t_end, vm);
         } else {
             if (TK == TALLY_STEADY_ONE) {
                 if (d > R(0)) add4_c(tc, H.det_mask, H.det_ncomp, H.det_slot, (int64_t)p.m, sg, d, vm, p.o);

@@ -34,6 +34,10 @@ FP64_CASES = {
     "film_partial_specular": lambda: W.film(N=2000, d=30e-9, specularity=0.4),
     "film_zbins": lambda: W.film(N=1500, z_bins=7),
     "transient_bump": lambda: W.transient_bump(N=400),
+    # uneven measurement times: log-spaced, a tight cluster, repeats, one at the time horizon
+    "transient_uneven_times": lambda: W.with_(W.transient_bump(N=600, n_times=8), **{
+        "problem.t_max": 2e-9, "problem.t_meas": np.sort(np.concatenate([np.geomspace(1e-14, 1.5e-9, 40), 7.3e-10 + 1e-15 * np.arange(12),
+                                                  [3e-10, 3e-10, 3e-10, 2e-9]]))}),
     "porous_cell": lambda: W.porous_cell(N=2000),
     "porous_cell_specular": lambda: W.porous_cell(N=1000, specularity=0.5),
     # the same lattice driven along x, and with the pore moved off the cell's centre
@@ -404,14 +408,17 @@ def test_event_cap_fp64_bit_exact_and_in_the_lone_lane_walk(cap):
     assert np.array_equal(plain["counts_raw"], logged["counts_raw"])
 
 
-def test_fp32_transient_wide_kernel_against_fp64_oracle():
+@pytest.mark.parametrize("name", ["transient_bump", "transient_uneven_times"])
+def test_fp32_transient_wide_kernel_against_fp64_oracle(name):
     """The transient bump with its full snapshot detector (100 bins x 200 times, too large for a
     per-workgroup FP64 copy): the FP32 kernel sums it per workgroup in FP32 in LDS.  Each particle
     adds its sign once per measurement time, so the total of every snapshot equals the oracle's
     exactly, and every cell agrees within two particles moved to a neighbouring bin by FP32
-    rounding (a particle adds s to T and s v Omega_z to q_z of one bin per time)."""
+    rounding (a particle adds s to T and s v Omega_z to q_z of one bin per time).  Also on uneven
+    measurement times (clusters, repeats, log spacing), where a segment's snapshot range comes
+    from the guided search of the times."""
     M = _pkg()
-    w = W.transient_bump(N=20000)
+    w = W.transient_bump(N=20000) if name == "transient_bump" else W.with_(FP64_CASES[name](), **{"problem.N": 20000})
     got = M.run(w, precision=32)
     ref = _oracle_full(w)
     rg = np.asarray(got["raw"])
