@@ -721,80 +721,104 @@ __device__ __forceinline__ int nth_set_bit(unsigned long long L, int r)
     return pos;
 }
 
+// the detector layout snapshot scoring reads (launch-uniform)
+template <typename R>
+struct SnapDet {
+    int gn[3];
+    R glo[3], ghi[3], gsc[3];
+    int mask, ncomp, n_cols;
+    uint32_t slots;
+    __device__ __forceinline__ explicit SnapDet(const DevDet& D)
+    {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            gn[a] = D.n[a];
+            glo[a] = Geo<R>::dlo(D, a);
+            ghi[a] = Geo<R>::dhi(D, a);
+            gsc[a] = Geo<R>::cell_scale(D, a);
+        }
+        mask = D.mask;
+        ncomp = D.ncomp;
+        n_cols = D.n_cols;
+        slots = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) slots |= ((uint32_t)D.slot[q] & 0xFFu) << (8 * q);
+    }
+};
+
+// one snapshot: the particle of sign sg that left x0 along o at t0 with speed vm, at measurement
+// time k, scores sg and sg vm Omega into the cell holding its position then
+template <typename R>
+__device__ __forceinline__ void snap_score(const SnapDet<R>& G, const TallyCtx& tc, const R* tmeas, const R x0[3],
+                                           const R o[3], R t0, R vm, R sg, int k)
+{
+    const R dist = vm * (tmeas[k] - t0);
+    int64_t cell = 0;
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int n = G.gn[a] > 0 ? G.gn[a] : 1;
+        int64_t ci = 0;
+        if (G.gn[a] > 0) {
+            const R xa = x0[a] + o[a] * dist;
+            if (xa < G.glo[a] || xa > G.ghi[a]) inside = false;
+            const R f = Geo<R>::cellf_of(xa, G.glo[a], G.gsc[a]);
+            ci = (int64_t)f;
+            ci = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
+        }
+        cell = cell * n + ci;
+    }
+    if (inside) {
+        const int64_t cc = cell * G.n_cols + k;
+        if (G.mask & 1) tadd_c(tc, G.ncomp, G.slots, cc, 0, (double)sg);
+        if (G.mask & 2) tadd_c(tc, G.ncomp, G.slots, cc, 1, (double)(sg * (vm * o[0])));
+        if (G.mask & 4) tadd_c(tc, G.ncomp, G.slots, cc, 2, (double)(sg * (vm * o[1])));
+        if (G.mask & 8) tadd_c(tc, G.ncomp, G.slots, cc, 3, (double)(sg * (vm * o[2])));
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ void snap_wave(const DevTab& T, const TallyCtx& tc, const R* tmeas, Part<R>& p)
 {
-    const unsigned long long L = __ballot(p.sn > 0);   // the lanes holding snapshots
-    if (L == 0ull) return;
+    if (__ballot(p.sn > 0) == 0ull) return;
     const int lane = threadIdx.x & 63;
-    const int S = dpp_incl_sum(p.sn);   // inclusive prefix sum of the lanes' snapshot counts
-    const int total = __builtin_amdgcn_readlane(S, 63);
-    const int kb = p.sk0 - (S - p.sn);  // measurement index of snapshot g of this lane: kb + g
-    const R sv = p.s < 0 ? -p.svm : p.svm;
-    const DevDet& D = T.det;
-    int gn[3];
-    R glo[3], ghi[3], gsc[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        gn[a] = D.n[a];
-        glo[a] = Geo<R>::dlo(D, a);
-        ghi[a] = Geo<R>::dhi(D, a);
-        gsc[a] = Geo<R>::cell_scale(D, a);
-    }
-    const int mask = D.mask, ncomp = D.ncomp, n_cols = D.n_cols;
-    uint32_t slots = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) slots |= ((uint32_t)D.slot[q] & 0xFFu) << (8 * q);
-    for (int base = 0; base < total; base += 64) {
-        const int g = base + lane;
-        // the lane whose records hold snapshot g: among the lanes with snapshots (L), the one
-        // after the rank(g) = #{i in L : S_i <= g} whose ranges end at or before g.  Ranges ending
-        // in this pass's window (1 <= S_i - base <= 63) are distinct bits of W; those ending before
-        // it are counted by one ballot.
-        const int e = S - base;
-        const bool ends_in = ((L >> lane) & 1ull) && e >= 1 && e <= 63;
-        const uint32_t wlo = dpp_or_all(ends_in && e < 32 ? 1u << e : 0u);
-        const uint32_t whi = dpp_or_all(ends_in && e >= 32 ? 1u << (e - 32) : 0u);
-        const unsigned long long W = ((unsigned long long)whi << 32) | wlo;
-        const int c0 = __popcll(__ballot(((L >> lane) & 1ull) && e <= 0));
-        const unsigned long long upto = lane == 63 ? ~0ull : (2ull << lane) - 1ull;
-        const int rank = c0 + __popcll(W & upto);
-        const int own = rank < __popcll(L) ? nth_set_bit(L, rank) : 63;
-        const int k = __shfl(kb, own, 64) + g;
-        // the owner's segment: positions along the binned axes, direction components those axes
-        // and the scored flux components need, start time, and speed with the particle's sign
-        R x0[3] = {R(0), R(0), R(0)}, o[3] = {R(0), R(0), R(0)};
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (gn[a] > 0) x0[a] = lane_r<R>(p.sx[a], own);
-            if (gn[a] > 0 || (mask & (2 << a))) o[a] = lane_r<R>(p.so[a], own);
-        }
-        const R t0 = lane_r<R>(p.st0, own), svm = lane_r<R>(sv, own);
-        const R vm = fabs(svm), sg = copysign(R(1), svm);
-        if (g < total) {
-            const R dist = vm * (tmeas[k] - t0);
-            int64_t cell = 0;
-            bool inside = true;
+    const SnapDet<R> G(T.det);
+    // every lane scores the first snapshot of its segment itself (most segments hold at most one)
+    if (p.sn > 0) snap_score<R>(G, tc, tmeas, p.sx, p.so, p.st0, p.svm, (R)p.s, p.sk0);
+    // the rest, 64 per pass however they are spread over the lanes
+    const int rest = p.sn > 0 ? p.sn - 1 : 0;
+    const unsigned long long L = __ballot(rest > 0);   // the lanes holding more snapshots
+    if (L != 0ull) {
+        const int S = dpp_incl_sum(rest);   // inclusive prefix sum of the lanes' remaining counts
+        const int total = __builtin_amdgcn_readlane(S, 63);
+        const int kb = (p.sk0 + 1) - (S - rest);   // measurement index of snapshot g of this lane: kb + g
+        const R sv = p.s < 0 ? -p.svm : p.svm;
+        for (int base = 0; base < total; base += 64) {
+            const int g = base + lane;
+            // the lane whose records hold snapshot g: among the lanes with snapshots (L), the one
+            // after the rank(g) = #{i in L : S_i <= g} whose ranges end at or before g.  Ranges
+            // ending in this pass's window (1 <= S_i - base <= 63) are distinct bits of W; those
+            // ending before it are counted by one ballot.
+            const int e = S - base;
+            const bool ends_in = ((L >> lane) & 1ull) && e >= 1 && e <= 63;
+            const uint32_t wlo = dpp_or_all(ends_in && e < 32 ? 1u << e : 0u);
+            const uint32_t whi = dpp_or_all(ends_in && e >= 32 ? 1u << (e - 32) : 0u);
+            const unsigned long long W = ((unsigned long long)whi << 32) | wlo;
+            const int c0 = __popcll(__ballot(((L >> lane) & 1ull) && e <= 0));
+            const unsigned long long upto = lane == 63 ? ~0ull : (2ull << lane) - 1ull;
+            const int rank = c0 + __popcll(W & upto);
+            const int own = rank < __popcll(L) ? nth_set_bit(L, rank) : 63;
+            const int k = __shfl(kb, own, 64) + g;
+            // the owner's segment: positions along the binned axes, direction components those
+            // axes and the scored flux components need, start time, speed with the particle's sign
+            R x0[3] = {R(0), R(0), R(0)}, o[3] = {R(0), R(0), R(0)};
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const int n = gn[a] > 0 ? gn[a] : 1;
-                int64_t ci = 0;
-                if (gn[a] > 0) {
-                    const R xa = x0[a] + o[a] * dist;
-                    if (xa < glo[a] || xa > ghi[a]) inside = false;
-                    const R f = Geo<R>::cellf_of(xa, glo[a], gsc[a]);
-                    ci = (int64_t)f;
-                    ci = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
-                }
-                cell = cell * n + ci;
+                if (G.gn[a] > 0) x0[a] = lane_r<R>(p.sx[a], own);
+                if (G.gn[a] > 0 || (G.mask & (2 << a))) o[a] = lane_r<R>(p.so[a], own);
             }
-            if (inside) {
-                const int64_t cc = cell * n_cols + k;
-                if (mask & 1) tadd_c(tc, ncomp, slots, cc, 0, (double)sg);
-                if (mask & 2) tadd_c(tc, ncomp, slots, cc, 1, (double)(sg * (vm * o[0])));
-                if (mask & 4) tadd_c(tc, ncomp, slots, cc, 2, (double)(sg * (vm * o[1])));
-                if (mask & 8) tadd_c(tc, ncomp, slots, cc, 3, (double)(sg * (vm * o[2])));
-            }
+            const R t0 = lane_r<R>(p.st0, own), svm = lane_r<R>(sv, own);
+            if (g < total) snap_score<R>(G, tc, tmeas, x0, o, t0, fabs(svm), copysign(R(1), svm), k);
         }
     }
     p.sn = 0;
