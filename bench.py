@@ -362,7 +362,7 @@ def measure_sensitivity(args, w, M, torch, estimators, steps: int):
     it adds are a few operations per relaxation and flight end) and its roofline fraction is that
     work over the replay's time."""
     tabs = M.Tables(w, 0)
-    lc = launch_config(args, tabs, w, M, 32, 1_000_000, 1)
+    lc = launch_config(args, tabs, w, M, 32)
     N = w["problem"]["N"]
     ncomp = bin(w["detectors"]["mask"]).count("1")
     F = torch.zeros(N, dtype=torch.float64, device="cuda")

@@ -2722,7 +2722,11 @@ k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
     pc.nt = 0;
     int64_t my_pid = 0;
     bool alive = false;
-    bool exhausted = false;        // wave-uniform: the particle counter has run past n
+    bool exhausted = false;        // wave-uniform: the particle counter has run past n, the pool is empty
+    bool counter_done = false;     // wave-uniform: the counter has run past n
+    bool near_end = false;         // wave-uniform: few ids left, the pool takes only what it needs
+    unsigned long long pool_next = 0, pool_end = 0;   // the wave's unused ids [pool_next, pool_end)
+    const unsigned long long tail_ids = 256ull * gridDim.x * (blockDim.x / 64);
     int since_refill = 0;
     // pore lattices: the listed particles (long first flights) are taken first, one per refill of a
     // wave, and skipped when the counter reaches them; a list that overflowed is not used
@@ -2758,14 +2762,29 @@ k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
                 }
             }
             if (need && !exhausted) {
+                // ids from the wave's pool, topped up from the global counter 64 at a time (exactly
+                // what is needed once the counter nears n), so that thousands of waves refilling
+                // every few steps do not queue on one atomic
                 const uint32_t cnt_need = (uint32_t)__popcll(need);
-                const int leader = __ffsll((long long)need) - 1;
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(counter, (unsigned long long)cnt_need);
-                base = __shfl(base, leader, 64);
-                if (base + cnt_need >= n) exhausted = true;
+                const unsigned long long avail = pool_end - pool_next;
+                unsigned long long fresh = 0;
+                if (avail < cnt_need) {
+                    const int leader = __ffsll((long long)need) - 1;
+                    const unsigned long long chunk = near_end ? cnt_need - avail : (unsigned long long)64;
+                    unsigned long long b0 = 0;
+                    if (lane == leader) b0 = atomicAdd(counter, chunk);
+                    b0 = __shfl(b0, leader, 64);
+                    fresh = b0;
+                    if (b0 + chunk >= n) counter_done = true;
+                    if (n - (b0 < n ? b0 : n) < tail_ids) near_end = true;
+                    pool_end = b0 + chunk < n ? b0 + chunk : (b0 < n ? n : b0);
+                }
+                const uint32_t rank = wave_rank(need);
+                const unsigned long long idx = rank < avail ? pool_next + rank : fresh + (rank - avail);
+                pool_next = avail < cnt_need ? fresh + (cnt_need - avail) : pool_next + cnt_need;
+                if (pool_next > pool_end) pool_next = pool_end;
+                if (counter_done && pool_next >= pool_end) exhausted = true;
                 if ((need >> lane) & 1ull) {
-                    const unsigned long long idx = base + wave_rank(need);
                     if (idx < n) {
                         my_pid = a.first_pid + (int64_t)idx;
                         uint64_t kf = 0;
