@@ -298,6 +298,32 @@ def test_batched_launch_equals_solo_runs():
             assert np.abs(t.raw(tl) - s["raw"]).max() <= 1e-12 * np.abs(s["raw"]).max()
 
 
+def test_batched_transient_launch_equals_solo_runs():
+    """Transient instances (a bump with uneven measurement times, a pulse-heated slab, the bump
+    on its regular grid) in one batched launch: the batched kernel's snapshot scoring gives each
+    instance the solo run's counters exactly and its sums to rounding (FP64), and the same counters
+    in FP32 (the solo FP32 launch sums snapshots in FP32 per workgroup, the batched one in FP64)."""
+    import torch
+    M = _pkg()
+    ws = [FP64_CASES["transient_uneven_times"](), W.heated_slab(N=700, t_max=100e-12, n_times=20, n_cells=10),
+          W.transient_bump(N=900, n_times=40)]
+    for i, w in enumerate(ws):
+        w["instance"] = 11 + i
+        w["seed"] = ws[0]["seed"]            # one launch, one key: instances differ by their ids
+    for prec in (64, 32):
+        tabs = [M.Tables(w) for w in ws]
+        tallies = [t.new_tally() for t in tabs]
+        queue = torch.zeros(M.batch_queue_bytes(len(ws)), dtype=torch.uint8, device="cuda")
+        run = M.make_run(int(ws[0]["seed"]), prec)
+        M.trace_batch(tabs, [w["problem"]["N"] for w in ws], [w["instance"] for w in ws], tallies, run, queue)
+        for w, t, tl in zip(ws, tabs, tallies):
+            b = M.tally(t, tl)
+            s = M.run(w, precision=prec, tables=t)
+            assert np.array_equal(b["counts_raw"], s["counts_raw"]), (prec, w["name"], b["counts"], s["counts"])
+            scale = np.abs(s["raw"]).max()
+            assert np.abs(t.raw(tl) - s["raw"]).max() <= (1e-12 if prec == 64 else 1e-5) * scale, (prec, w["name"])
+
+
 def test_full_size_film_fp32_against_oracle():
     """The benchmark workload at full size (1e6 particles, FP32, default launch shape) against
     the FP64 oracle on the same particles."""
