@@ -1054,7 +1054,9 @@ int mcbte_trace(const mcbte_tables* t, const mcbte_run* run, int64_t first_pid, 
     LaunchPlan lp;
     // the plain kernel has neither a state buffer nor an event log compiled in; an FP32 trace whose
     // FP64 tally is too large for the LDS copy but whose FP32 tally fits runs wide workgroups
+    // (FP32 steady traces from pre-emitted states have a kernel without the event log compiled in)
     int ft = (state || run->event_log) ? (FT_STATE | FT_LOG) : 0;
+    if (state && !run->event_log && run->precision == 32 && t->host_view.tally_kind == TALLY_STEADY_ONE) ft = FT_STATE;
     if (ft == 0 && run->precision == 32) {
         const int64_t t64 = t->info.n_cells * t->info.n_cols * (int64_t)t->host_view.det.ncomp * 8;
         const int64_t M = t->info.n_modes;

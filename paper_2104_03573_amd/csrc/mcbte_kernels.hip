@@ -2724,9 +2724,9 @@ k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
     bool alive = false;
     bool exhausted = false;        // wave-uniform: the particle counter has run past n, the pool is empty
     bool counter_done = false;     // wave-uniform: the counter has run past n
-    bool near_end = false;         // wave-uniform: few ids left, the pool takes only what it needs
     unsigned long long pool_next = 0, pool_end = 0;   // the wave's unused ids [pool_next, pool_end)
-    const unsigned long long tail_ids = 256ull * gridDim.x * (blockDim.x / 64);
+    unsigned long long seen = 0;   // the counter's value after this wave's last grab
+    const unsigned long long n_waves = (unsigned long long)gridDim.x * (blockDim.x / 64);
     int since_refill = 0;
     // pore lattices: the listed particles (long first flights) are taken first, one per refill of a
     // wave, and skipped when the counter reaches them; a list that overflowed is not used
@@ -2762,21 +2762,24 @@ k_trace_solo(const DevTab* __restrict__ tabs, LaunchArgs a)
                 }
             }
             if (need && !exhausted) {
-                // ids from the wave's pool, topped up from the global counter 64 at a time (exactly
-                // what is needed once the counter nears n), so that thousands of waves refilling
-                // every few steps do not queue on one atomic
+                // ids from the wave's pool, topped up from the global counter in chunks of up to 64
+                // (half the ids left per wave when the counter was last read, at least what is
+                // needed), so that thousands of waves refilling every few steps do not queue on
+                // one atomic and no wave hoards ids at the end
                 const uint32_t cnt_need = (uint32_t)__popcll(need);
                 const unsigned long long avail = pool_end - pool_next;
                 unsigned long long fresh = 0;
                 if (avail < cnt_need) {
                     const int leader = __ffsll((long long)need) - 1;
-                    const unsigned long long chunk = near_end ? cnt_need - avail : (unsigned long long)64;
+                    const unsigned long long short_by = cnt_need - avail;
+                    const unsigned long long share = (n > seen ? n - seen : 0ull) / (2ull * n_waves);
+                    const unsigned long long chunk = share > 64ull ? 64ull : (share > short_by ? share : short_by);
                     unsigned long long b0 = 0;
                     if (lane == leader) b0 = atomicAdd(counter, chunk);
                     b0 = __shfl(b0, leader, 64);
                     fresh = b0;
+                    seen = b0 + chunk;
                     if (b0 + chunk >= n) counter_done = true;
-                    if (n - (b0 < n ? b0 : n) < tail_ids) near_end = true;
                     pool_end = b0 + chunk < n ? b0 + chunk : (b0 < n ? n : b0);
                 }
                 const uint32_t rank = wave_rank(need);
@@ -3044,6 +3047,8 @@ static const void* pick_solo(int mode, int ft)
         }
     }
     if constexpr (std::is_same<R, float>::value && TK == TALLY_STEADY_ONE) {
+        // pre-emitted states without an event log: refills load states instead of emitting
+        if (mode == 0 && (ft & FT_STATE) && !(ft & FT_LOG)) return (const void*)k_trace_solo<R, TK, 0, FT_STATE | PLAIN>;
         if (ft & FT_LATTICE) {   // (never with a state buffer or an event log)
             if (mode == 2) return (const void*)k_trace_solo<R, TK, 1, FT_LATTICE | FT_PLAIN>;
             if (mode == 4) return (const void*)k_trace_solo<R, TK, 3, FT_LATTICE | FT_PLAIN>;

@@ -298,6 +298,27 @@ def test_batched_launch_equals_solo_runs():
             assert np.abs(t.raw(tl) - s["raw"]).max() <= 1e-12 * np.abs(s["raw"]).max()
 
 
+@pytest.mark.parametrize("name", ["film", "film_two_clocks"])
+def test_fp32_trace_from_emitted_states_equals_the_inline_trace(name):
+    """FP32 steady traces from states written by mcbte_emit run a kernel without the event log; the
+    particles and every counter are those of the trace that emits inline (FP64 sums to rounding)."""
+    import torch
+    M = _pkg()
+    w = W.film(N=50_000) if name == "film" else W.film(N=50_000, modes=W.silicon_like_modes(300.0, impurity_clock=True))
+    t = M.Tables(w)
+    n = w["problem"]["N"]
+    for block, refill in ((0, 0), (64, 1)):
+        run = M.make_run(int(w["seed"]), 32, block=block, refill=refill)
+        st = torch.zeros(M.state_bytes(32, n), dtype=torch.uint8, device="cuda")
+        M.emit(t, run, 0, n, st, n)
+        a_tl, b_tl = t.new_tally(), t.new_tally()
+        M.trace(t, run, 0, n, st, a_tl)
+        M.trace(t, run, 0, n, None, b_tl)
+        a, b = M.tally(t, a_tl), M.tally(t, b_tl)
+        assert np.array_equal(a["counts_raw"], b["counts_raw"]), (block, refill, a["counts"], b["counts"])
+        assert np.abs(t.raw(a_tl) - t.raw(b_tl)).max() <= 1e-6 * np.abs(t.raw(b_tl)).max()
+
+
 def test_batched_transient_launch_equals_solo_runs():
     """Transient instances (a bump with uneven measurement times, a pulse-heated slab, the bump
     on its regular grid) in one batched launch: the batched kernel's snapshot scoring gives each
