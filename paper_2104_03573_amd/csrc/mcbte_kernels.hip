@@ -2283,13 +2283,18 @@ __device__ void lattice_walk(const DevTab& T, const Hot<float>& H, const Tabs<fl
         // the segment cap: one step below crosses at most 32 columns, 33 rows and the z cells
         // within the free path; closer to the cap the one-segment step goes on (and ends it there)
         const float zcap = zper ? fminf(D * fabsf(o2) * iWz, 1.0e9f) : 0.0f;
-        if (!__builtin_amdgcn_readfirstlane((int)((double)k + 67.0 + (double)zcap <= (double)kmax))) {
+        // (every lane holds the same values, so a ballot is the wave's decision; below 2^24 events
+        // of budget the integer is exact in FP32, and one event of margin covers zcap + 68's rounding)
+        const uint32_t budget = kmax - k;
+        const bool room = budget < (1u << 24) ? zcap + 68.0f <= (float)budget
+                                             : (double)k + 67.0 + (double)zcap <= (double)kmax;
+        if (__ballot(room) == 0ull) {
             finish = false;
             break;
         }
         const float ax = fabsf(o0), ay = fabsf(o1);
-        if (!__builtin_amdgcn_readfirstlane((int)(ax > 0.0f || ay > 0.0f))) break;   // along z: no pore ahead
-        const bool xm = __builtin_amdgcn_readfirstlane((int)(ax >= ay)) != 0;
+        if (__ballot(ax > 0.0f || ay > 0.0f) == 0ull) break;   // along z: no pore ahead
+        const bool xm = __ballot(ax >= ay) != 0ull;
         const float oM = xm ? o0 : o1, om = xm ? o1 : o0;
         const float pM = xm ? x0 : x1, pm = xm ? x1 : x0;
         const float WM = xm ? Wx : Wy, Wm = xm ? Wy : Wx, iWm = xm ? iWy : iWx;
@@ -2324,7 +2329,7 @@ __device__ void lattice_walk(const DevTab& T, const Hot<float>& H, const Tabs<fl
             // entry of the next column (32 column boundaries crossed, the last on a face as after a
             // transfer)
             const float u = e0 + 31.0f * WM;
-            if (!__builtin_amdgcn_readfirstlane((int)(D * aM > u))) break;   // the free path ends first
+            if (__ballot(D * aM > u) == 0ull) break;   // the free path ends first
             const float s = r_div(u, aM);
             const float ym = pm + u * tmin;
             const float km = floorf(ym * iWm);
