@@ -47,14 +47,34 @@ OPS = {
     "cos_dir": 36,            # cosine-weighted direction about a normal
     "search_step": 5,         # one step of the 64-bit threshold search
     "emit_misc": 20,          # source pick, position, sign, start time
+    "snapshot_axis": 9,       # one snapshot: position along a binned axis at t_k, its cell index
 }
 
 
+def exact_snapshots(w: dict, counts: dict) -> int:
+    """Snapshot scorings (Eq. sampling) of a transient launch where their number is fixed: every
+    particle starts at t = 0 (initial-condition sources only: no heat source, no gradient, no
+    isothermal face or line wall) and lives to t_max, so it scores each measurement time below t_max
+    once; 0 (not counted) otherwise."""
+    import numpy as np
+    import workloads as W
+    p, g = w["problem"], w["geometry"]
+    if not p.get("transient") or p.get("heat") is not None or any(x != 0 for x in g.get("gradT", (0, 0, 0))):
+        return 0
+    if g.get("walls") or any(f[0] == W.ISOTHERMAL for f in g["faces"].values()):
+        return 0
+    if counts["timeouts"] != counts["particles"]:
+        return 0
+    return int(counts["particles"]) * int(np.sum(np.asarray(p["t_meas"]) < p["t_max"]))
+
+
 def algorithmic_lane_ops(counts: dict, info: dict, geom: dict, ncomp: int, transient: bool,
-                         two_clocks: bool = False) -> float:
+                         two_clocks: bool = False, snapshots: int = 0, binned_axes: int = 0) -> float:
     """Lane-operations the method requires for the events of one launch (see OPS).  With a
     two-phonon clock every emission and three-phonon relaxation also draws that clock, and a
-    two-phonon event draws a direction and the clock again."""
+    two-phonon event draws a direction and the clock again.  A transient launch adds its snapshot
+    scorings where their number is known (exact_snapshots): per snapshot the position and cell on
+    each binned axis and the scored components."""
     M = int(info["n_modes"])
     S = int(info["n_sources"])
     steps_M = max(1, math.ceil(math.log2(M + 1)))
@@ -73,7 +93,8 @@ def algorithmic_lane_ops(counts: dict, info: dict, geom: dict, ncomp: int, trans
             + relax_draws * (2 * OPS["philox_block"] + steps_M * OPS["search_step"] + OPS["iso_dir"]
                              + OPS["free_flight"])
             + diffuse * (OPS["philox_block"] + OPS["cos_dir"])
-            + counts["rejections"] * 2 * OPS["philox_block"] + two)
+            + counts["rejections"] * 2 * OPS["philox_block"] + two
+            + snapshots * (binned_axes * OPS["snapshot_axis"] + ncomp * OPS["tally_comp"]))
 
 
 def profiled_traffic(kernel_tag: str):
@@ -274,7 +295,9 @@ def measure(args, w, M, torch, precision: int, steps: int, warmup: int, streams:
     wall = time.perf_counter() - t0
     kernel_ms = [a.elapsed_time(b) for a, b in events]
     two = bool((w["modes"]["tau_imp"] > 0).any())
-    ops = sum(algorithmic_lane_ops(r["counts"], tabs.info, w["geometry"], ncomp, w["problem"]["transient"], two)
+    binned = sum(1 for x in w["detectors"]["n"] if x > 0)
+    ops = sum(algorithmic_lane_ops(r["counts"], tabs.info, w["geometry"], ncomp, w["problem"]["transient"], two,
+                                   exact_snapshots(w, r["counts"]), binned)
               for r in results)
     achieved = ops / (sum(kernel_ms) / 1e3)
     flights = sum(r["counts"]["flights"] for r in results)

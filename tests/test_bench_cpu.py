@@ -53,3 +53,23 @@ def test_work_model_adds_the_two_phonon_clock_draws():
     two = bench.algorithmic_lane_ops(counts, info, geom, ncomp=2, transient=False, two_clocks=True)
     clock = O["philox_block"] + O["free_flight"]
     assert two - one == 7 * (O["philox_block"] + O["iso_dir"] + clock) + (10 + 50) * clock
+
+
+def test_snapshot_count_only_where_it_is_fixed():
+    """The transient bump (initial condition only, specular walls): every particle that reaches
+    t_max scores each of the 200 measurement times once.  A heat source, a steady problem, or a
+    particle that did not reach t_max leave the snapshots uncounted."""
+    import bench
+    import workloads as W
+    w = W.transient_bump(N=1000)
+    assert bench.exact_snapshots(w, {"timeouts": 1000, "particles": 1000}) == 1000 * 200
+    assert bench.exact_snapshots(w, {"timeouts": 999, "particles": 1000}) == 0
+    assert bench.exact_snapshots(W.heated_slab(N=10), {"timeouts": 10, "particles": 10}) == 0
+    assert bench.exact_snapshots(W.film(N=10), {"timeouts": 0, "particles": 10}) == 0
+    base = bench.algorithmic_lane_ops({"particles": 10, "flights": 100, "relaxations": 50, "nscat_end": 0,
+                                       "diffuse": 0, "rejections": 0}, {"n_modes": 1400, "n_sources": 100},
+                                      w["geometry"], 2, True)
+    more = bench.algorithmic_lane_ops({"particles": 10, "flights": 100, "relaxations": 50, "nscat_end": 0,
+                                       "diffuse": 0, "rejections": 0}, {"n_modes": 1400, "n_sources": 100},
+                                      w["geometry"], 2, True, snapshots=2000, binned_axes=1)
+    assert more - base == 2000 * (bench.OPS["snapshot_axis"] + 2 * bench.OPS["tally_comp"])
