@@ -711,6 +711,19 @@ __device__ __forceinline__ uint32_t dpp_or_all(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readlane(x, 63);
 }
 
+// the minimum of every lane's v (in every lane; all 64 lanes active), the same DPP pattern
+__device__ __forceinline__ float dpp_min_all(float v)
+{
+    const int inf = __float_as_int(INFINITY);
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x111, 0xF, 0xF, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x112, 0xF, 0xF, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x114, 0xF, 0xF, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x118, 0xF, 0xF, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x142, 0xA, 0xF, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x143, 0xC, 0xF, false)));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // the position of the set bit of L that has r set bits below it (L holds more than r)
 __device__ __forceinline__ int nth_set_bit(unsigned long long L, int r)
 {
@@ -2207,12 +2220,13 @@ __device__ __forceinline__ float lane_f(float v, int k)
 // reinserted unchanged at the partner face (Eq. periodic_lin_final) -- is the same as flying on
 // through that lattice.  The particle of lane `leader`, with a free path of many cells ahead, is
 // followed by the whole wave from pore to pore in these unfolded coordinates:
-//   - the lanes test the pores of the next 32 lattice columns along the ray, two rows per column
-//     (along the axis the ray moves fastest on, one column spans at most two rows), and a ballot
-//     finds the first column with a pore met before the free path runs out; a pore lies inside
-//     its cell, so the order of the columns is the order along the ray;
+//   - the lanes test the pores of a window of 64 cells ahead of the ray (32 x 2, 16 x 4 or 8 x 8
+//     along the axis it moves fastest on, by its slope), and the nearest entry into a pore within
+//     the free path (a DPP minimum) is the first pore met: a pore lies inside its cell and the
+//     cells the ray passes form a staircase in its direction, so any pore met before the ray
+//     leaves the window is in it; with none, the walk moves on to the window's far edge;
 //   - a pore's discriminant is taken in Lagrange's form, qa r^2 - (dP x o)^2 (dP the pore's offset,
-//     o the direction, in the x-y plane), so that a pore 32 cells away is decided from the cross
+//     o the direction, in the x-y plane), so that a pore many cells away is decided from the cross
 //     product's rounding rather than from a difference of squares of its distance;
 //   - the transfers on the way are the cell boundaries crossed, counted per axis;
 //   - the reflection uses the unit normal at the hit point (the hit point's offset from the axis,
@@ -2273,15 +2287,12 @@ __device__ void lattice_walk(const DevTab& T, const Hot<float>& H, const Tabs<fl
     // record 2 + jb + 1 + lane, jb the draws made before the batch
     float dmu = 0.0f, dca = 0.0f, dcb = 0.0f;
     uint32_t used = 64;
-    const int col = lane & 31;
-    const bool hi_row = lane >= 32;
-    const float cWx = (float)col * Wx, cWy = (float)col * Wy;   // this lane's column offset, per axis
     const float r2 = rr * rr;
     bool finish = true;          // false: stopped ahead of the segment cap (left to the one-segment step)
     for (int guard = 0; guard < (1 << 24); ++guard) {
         const float D = vm * dtr;
-        // the segment cap: one step below crosses at most 32 columns, 33 rows and the z cells
-        // within the free path; closer to the cap the one-segment step goes on (and ends it there)
+        // the segment cap: one step below crosses at most 65 cell boundaries in x and y and the z
+        // cells within the free path; closer to the cap the one-segment step goes on (and ends it)
         const float zcap = zper ? fminf(D * fabsf(o2) * iWz, 1.0e9f) : 0.0f;
         // (every lane holds the same values, so a ballot is the wave's decision; below 2^24 events
         // of budget the integer is exact in FP32, and one event of margin covers zcap + 68's rounding)
@@ -2294,76 +2305,72 @@ __device__ void lattice_walk(const DevTab& T, const Hot<float>& H, const Tabs<fl
         }
         const float ax = fabsf(o0), ay = fabsf(o1);
         if (__ballot(ax > 0.0f || ay > 0.0f) == 0ull) break;   // along z: no pore ahead
-        const bool xm = __ballot(ax >= ay) != 0ull;
-        const float oM = xm ? o0 : o1, om = xm ? o1 : o0;
-        const float pM = xm ? x0 : x1, pm = xm ? x1 : x0;
-        const float WM = xm ? Wx : Wy, Wm = xm ? Wy : Wx, iWm = xm ? iWy : iWx;
-        const float cM = xm ? cx : cy, cm = xm ? cy : cx;
-        const float aM = xm ? ax : ay;
-        const bool up = oM > 0.0f;
-        const float qa = oM * oM + om * om;
+        // the window of cells the lanes test: A cells along x by B along y (A B = 64), counted in
+        // the ray's direction from the particle's cell and shaped by its slope (32 x 2, 16 x 4 or
+        // 8 x 8 along the axis it moves fastest on), lane (i, j) = (lane mod A, lane / A)
+        const bool xmaj = __ballot(ax >= ay) != 0ull;
+        const float amaj = xmaj ? ax : ay, amin = xmaj ? ay : ax;
+        const int lgM = __ballot(amin * 32.0f < amaj) != 0ull ? 5 : (__ballot(amin * 16.0f < 3.0f * amaj) != 0ull ? 4 : 3);
+        const int lgA = xmaj ? lgM : 6 - lgM;
+        const int A = 1 << lgA, B = 64 >> lgA;
+        const bool sxp = __ballot(o0 >= 0.0f) != 0ull, syp = __ballot(o1 >= 0.0f) != 0ull;
+        const float fi = (float)(lane & (A - 1)) * Wx, fj = (float)(lane >> lgA) * Wy;
+        const float qa = o0 * o0 + o1 * o1;
         const float iqa = r_div(1.0f, qa), qar2 = qa * r2;
-        // distance along the column axis to the column boundary ahead, then column `col`'s range
-        const float e0 = up ? WM - pM : pM;
-        const float tmin = r_div(om, aM);            // minor displacement per unit of column-axis travel
-        const float cW = xm ? cWx : cWy;
-        const float ua = col == 0 ? 0.0f : e0 + (cW - WM);
-        const float ub = e0 + cW;
-        const float ya = pm + ua * tmin, yb = pm + ub * tmin;
-        const float rlo = floorf((ya < yb ? ya : yb) * iWm), rhi = floorf((ya < yb ? yb : ya) * iWm);
-        const float row = hi_row ? rhi : rlo;
-        // the pore of that column and row relative to the particle, and the ray's entry into it:
-        // the discriminant in Lagrange's form qa r^2 - (dP x o)^2, which keeps the precision of the
+        // the pore of cell (i, j) relative to the particle, and the ray's entry into it: the
+        // discriminant in Lagrange's form qa r^2 - (dP x o)^2, which keeps the precision of the
         // cross product for a distant pore (no difference of squares of the distance)
-        const float dM = pM - ((up ? cW : -cW) + cM);
-        const float dm = pm - (row * Wm + cm);
-        const float qb = dM * oM + dm * om;
-        const float cr = dM * om - dm * oM;
+        const float dX = x0 - ((sxp ? fi : -fi) + cx);
+        const float dY = x1 - ((syp ? fj : -fj) + cy);
+        const float qb = dX * o0 + dY * o1;
+        const float cr = dX * o1 - dY * o0;
         const float disc = qar2 - cr * cr;
         const float dd = (-qb - r_sqrt(disc > 0.0f ? disc : 0.0f)) * iqa;
         const float d = dd > 0.0f ? dd : 0.0f;
-        const unsigned long long bal = __ballot((qb < 0.0f) & (disc >= 0.0f) & !(hi_row & (rhi == rlo)) & (d <= D));
-        const uint32_t cols = (uint32_t)bal | (uint32_t)(bal >> 32);
-        if (cols == 0u) {
-            // no pore met in the 32 columns: the free path ends in them, or the walk moves on to the
-            // entry of the next column (32 column boundaries crossed, the last on a face as after a
-            // transfer)
-            const float u = e0 + 31.0f * WM;
-            if (__ballot(D * aM > u) == 0ull) break;   // the free path ends first
-            const float s = r_div(u, aM);
-            const float ym = pm + u * tmin;
-            const float km = floorf(ym * iWm);
+        const bool met = (qb < 0.0f) & (disc >= 0.0f) & (d <= D);
+        // the first pore met is the nearest entry: a pore lies inside its cell and the cells the
+        // ray passes form a staircase in its direction, so every pore it meets before leaving the
+        // window is in the window
+        const float dh = dpp_min_all(met ? d : INFINITY);
+        const unsigned long long bal = __ballot(met & (d == dh));
+        if (bal == 0ull) {
+            // no pore met in the window: the free path ends in it, or the walk moves on to the
+            // window's far edge (the cell boundaries crossed counted per axis, the particle placed
+            // on the partner face of the edge it leaves through, as after a transfer)
+            const float gx = sxp ? (float)A * Wx - x0 : x0 + (float)(A - 1) * Wx;
+            const float gy = syp ? (float)B * Wy - x1 : x1 + (float)(B - 1) * Wy;
+            const float sxe = ax > 0.0f ? r_div(gx, ax) : INFINITY;
+            const float sye = ay > 0.0f ? r_div(gy, ay) : INFINITY;
+            const bool ex = __ballot(sxe <= sye) != 0ull;
+            const float s = ex ? sxe : sye;
+            if (__ballot(D > s) == 0ull) break;   // the free path ends first
+            const float X = x0 + s * o0, Y = x1 + s * o1;
+            const float kx = ex ? 0.0f : floorf(X * iWx), ky = ex ? floorf(Y * iWy) : 0.0f;
             float z = x2 + s * o2, kz = 0.0f;
             if (zper) kz = floorf(z * iWz);
-            const uint32_t nx = 32u + (uint32_t)fabsf(km) + (uint32_t)fabsf(kz);
+            const uint32_t nx = (uint32_t)(ex ? A : B) + (uint32_t)fabsf(ex ? ky : kx) + (uint32_t)fabsf(kz);
             advance_time(s);
-            const float pm2 = ym - km * Wm;
-            const float pM2 = up ? 0.0f : WM;
             if (zper) z = z - kz * Wz;
-            x0 = xm ? pM2 : pm2;
-            x1 = xm ? pm2 : pM2;
+            x0 = ex ? (sxp ? 0.0f : Wx) : X - kx * Wx;
+            x1 = ex ? Y - ky * Wy : (syp ? 0.0f : Wy);
             x2 = zper ? (z < 0.0f ? 0.0f : (z > Wz ? Wz : z)) : z;
             k += nx;
             nf += nx;
             np += nx;
             continue;
         }
-        // the first column with a pore met; of its two rows, the nearer
-        const int kc = __builtin_ctz(cols);
-        const bool v0 = ((bal >> kc) & 1ull) != 0ull, v1 = ((bal >> (kc + 32)) & 1ull) != 0ull;
-        const float d0 = lane_f(d, kc), d1 = lane_f(d, kc + 32);
-        const bool pick1 = v1 && (!v0 || d1 < d0);
-        const int wl = pick1 ? kc + 32 : kc;
-        const float dh = pick1 ? d1 : d0;
-        const float rowh = lane_f(row, wl);
-        // hit point relative to the pore's centre, and the cells crossed on the way
-        const float relM = lane_f(dM, wl) + dh * oM, relm = lane_f(dm, wl) + dh * om;
+        // the hit: the winning lane's cell (the lowest lane among equal entries) and its offsets,
+        // recomputed as that lane computed them; the cells crossed on the way
+        const int wl = __ffsll((long long)bal) - 1;
+        const int wi = wl & (A - 1), wj = wl >> lgA;
+        const float wfi = (float)wi * Wx, wfj = (float)wj * Wy;
+        const float rx = (x0 - ((sxp ? wfi : -wfi) + cx)) + dh * o0;
+        const float ry = (x1 - ((syp ? wfj : -wfj) + cy)) + dh * o1;
         float z = x2 + dh * o2, kz = 0.0f;
         if (zper) kz = floorf(z * iWz);
-        const uint32_t nx = (uint32_t)kc + (uint32_t)fabsf(rowh) + (uint32_t)fabsf(kz);
+        const uint32_t nx = (uint32_t)wi + (uint32_t)wj + (uint32_t)fabsf(kz);
         advance_time(dh);
         if (zper) z = z - kz * Wz;
-        const float rx = xm ? relM : relm, ry = xm ? relm : relM;
         x0 = cx + rx;
         x1 = cy + ry;
         x2 = zper ? (z < 0.0f ? 0.0f : (z > Wz ? Wz : z)) : z;
