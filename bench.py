@@ -110,7 +110,7 @@ def profiled_traffic(kernel_tag: str):
     if not os.path.exists(path):
         return None
     kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
-    if kv.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+    if kv.get("kernel_source_sha256_16") != h.hexdigest()[:16] or "hbm_bytes_per_launch" not in kv:
         return None
     return float(kv["hbm_bytes_per_launch"])
 
@@ -132,6 +132,12 @@ def workload(name: str, scale: float = 1.0):
         # the pore reflects the phonons below 2 THz specularly (the paper's nanomesh variant)
         return (W.porous_cell(N=int(100_000_000 * scale), spec_omega=W.OMEGA_2THZ, n_scat_max=W.C5_NSCAT),
                 f"porous_cell_500nm_phi0.25_N1e8_nscat{W.C5_NSCAT}_specular_below_2THz")
+    if name == "lone_walker":
+        # one phonon of the pore cell with a 10 cm gray free path and N_scat^max 1: a single wave walks
+        # ~1e5 pore reflections (the cost of the long-free-path tail of the cell, one reflection at a time)
+        w = W.porous_cell(N=max(1, int(scale)), modes=W.gray_modes(6400.0, 0.1 / 6400.0), n_scat_max=1)
+        w["problem"]["format"] = 2   # the gray row gives C directly
+        return w, "porous_cell_500nm_phi0.25_gray_Lambda10cm_N1_nscat1"
     if name == "gray_slab":
         return W.gray_slab(N=int(100_000 * scale)), "gray_slab_L100nm_Kn1_N1e5_50bins"
     if name == "porous_cell":
@@ -306,7 +312,7 @@ def measure(args, w, M, torch, precision: int, steps: int, warmup: int, streams:
            "frac": achieved / PEAK_LANE_OPS, "flights_per_step": flights / steps,
            "particles_per_s": N * steps / wall,
            "relaxations_per_s": sum(r["counts"]["relaxations"] for r in results) / wall,
-           "table_build_s": t_tables, "launch": lc, "tables": tabs, "last": results[-1], "N": N,
+           "table_build_s": t_tables, "launch": lc, "tables": tabs, "last": results[-1], "results": results, "N": N,
            "pore_walk": precision == 32 and not args.segments and is_pore_lattice(w)}
     last = results[-1]
     if not w["problem"]["transient"] and last.get("kappa"):
@@ -526,6 +532,11 @@ def main():
     for k in ("kappa_eff", "kappa_sigma", "time_to_sigma_0p5pct_s"):
         if k in m:
             out[k] = m[k]
+    if args.workload == "lone_walker" and S == 1:
+        # per launch: the walked pore reflections and periodic transfers, and the launch time per reflection
+        refl = [r["counts"]["diffuse"] + r["counts"]["specular"] for r in m["results"]]
+        out["walk"] = {"reflections": refl, "periodic": [r["counts"]["periodic"] for r in m["results"]],
+                       "ns_per_reflection": [t * 1e6 / max(n, 1) for t, n in zip(m["kernel_ms"], refl)]}
     if not args.no_forms and args.workload == "porous_cell" and args.precision == 32 and S == 1:
         out["forms"] = other_forms(args, M, torch)
     if not args.no_cpu_baseline:

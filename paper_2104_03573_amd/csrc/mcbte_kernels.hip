@@ -711,17 +711,20 @@ __device__ __forceinline__ uint32_t dpp_or_all(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readlane(x, 63);
 }
 
-// the minimum of every lane's v (in every lane; all 64 lanes active), the same DPP pattern
-__device__ __forceinline__ float dpp_min_all(float v)
+// the minimum of every lane's v (in every lane; all 64 lanes active), the same DPP pattern; v
+// non-negative or +inf, whose order is that of their bit patterns as unsigned integers (the
+// unsigned minimum's identity, all ones, fills the lanes a shift leaves without a source, so each
+// step is one v_min_u32 with its DPP operand)
+__device__ __forceinline__ float dpp_min_nonneg(float v)
 {
-    const int inf = __float_as_int(INFINITY);
-    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x111, 0xF, 0xF, false)));
-    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x112, 0xF, 0xF, false)));
-    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x114, 0xF, 0xF, false)));
-    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x118, 0xF, 0xF, false)));
-    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x142, 0xA, 0xF, false)));
-    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x143, 0xC, 0xF, false)));
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    uint32_t x = (uint32_t)__float_as_int(v);
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, 0x111, 0xF, 0xF, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, 0x112, 0xF, 0xF, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, 0x114, 0xF, 0xF, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, 0x118, 0xF, 0xF, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, 0x142, 0xA, 0xF, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, 0x143, 0xC, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_readlane((int)x, 63));
 }
 
 // the position of the set bit of L that has r set bits below it (L holds more than r)
@@ -2215,6 +2218,9 @@ __device__ __forceinline__ float lane_f(float v, int k)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
 
+// a wave-uniform decision from a condition every active lane evaluates alike
+__device__ __forceinline__ bool wave_any(bool c) { return __builtin_amdgcn_ballot_w64(c) != 0ull; }
+
 // A cell periodic in x and y (periodic or without faces in z) holding one z-axis pore tiles an
 // infinite square lattice of pores, and a transfer through a periodic face -- the particle
 // reinserted unchanged at the partner face (Eq. periodic_lin_final) -- is the same as flying on
@@ -2288,32 +2294,40 @@ __device__ void lattice_walk(const DevTab& T, const Hot<float>& H, const Tabs<fl
     float dmu = 0.0f, dca = 0.0f, dcb = 0.0f;
     uint32_t used = 64;
     const float r2 = rr * rr;
+    // the free path only shrinks along the walk and |o2| <= 1, so no later step's z cells (zcap
+    // below) exceed those of the whole free path at the start (a 0.1 % margin covers rounding and
+    // the last bits of a unit direction): while k <= k_safe the cap test holds without evaluation
+    const double need = (double)(zper ? fminf(vm * dtr * iWz, 1.0e9f) : 0.0f) * 1.001 + 70.0;
+    const bool safe_ok = need < (double)kmax;
+    const uint32_t k_safe = __builtin_amdgcn_readfirstlane(safe_ok ? (uint32_t)((double)kmax - need) : 0u);
     bool finish = true;          // false: stopped ahead of the segment cap (left to the one-segment step)
     for (int guard = 0; guard < (1 << 24); ++guard) {
         const float D = vm * dtr;
-        // the segment cap: one step below crosses at most 65 cell boundaries in x and y and the z
-        // cells within the free path; closer to the cap the one-segment step goes on (and ends it)
-        const float zcap = zper ? fminf(D * fabsf(o2) * iWz, 1.0e9f) : 0.0f;
-        // (every lane holds the same values, so a ballot is the wave's decision; below 2^24 events
-        // of budget the integer is exact in FP32, and one event of margin covers zcap + 68's rounding)
-        const uint32_t budget = kmax - k;
-        const bool room = budget < (1u << 24) ? zcap + 68.0f <= (float)budget
-                                             : (double)k + 67.0 + (double)zcap <= (double)kmax;
-        if (__ballot(room) == 0ull) {
-            finish = false;
-            break;
+        if (!(safe_ok && k <= k_safe)) {
+            // the segment cap: one step below crosses at most 65 cell boundaries in x and y and the z
+            // cells within the free path; closer to the cap the one-segment step goes on (and ends it)
+            const float zcap = zper ? fminf(D * fabsf(o2) * iWz, 1.0e9f) : 0.0f;
+            // (every lane holds the same values, so a ballot is the wave's decision; below 2^24 events
+            // of budget the integer is exact in FP32, and one event of margin covers zcap + 68's rounding)
+            const uint32_t budget = kmax - k;
+            const bool room = budget < (1u << 24) ? zcap + 68.0f <= (float)budget
+                                                 : (double)k + 67.0 + (double)zcap <= (double)kmax;
+            if (!wave_any(room)) {
+                finish = false;
+                break;
+            }
         }
         const float ax = fabsf(o0), ay = fabsf(o1);
-        if (__ballot(ax > 0.0f || ay > 0.0f) == 0ull) break;   // along z: no pore ahead
         // the window of cells the lanes test: A cells along x by B along y (A B = 64), counted in
         // the ray's direction from the particle's cell and shaped by its slope (32 x 2, 16 x 4 or
         // 8 x 8 along the axis it moves fastest on), lane (i, j) = (lane mod A, lane / A)
-        const bool xmaj = __ballot(ax >= ay) != 0ull;
+        const bool xmaj = wave_any(ax >= ay);
         const float amaj = xmaj ? ax : ay, amin = xmaj ? ay : ax;
-        const int lgM = __ballot(amin * 32.0f < amaj) != 0ull ? 5 : (__ballot(amin * 16.0f < 3.0f * amaj) != 0ull ? 4 : 3);
+        if (!wave_any(amaj > 0.0f)) break;   // along z: no pore ahead
+        const int lgM = wave_any(amin * 32.0f < amaj) ? 5 : (wave_any(amin * 16.0f < 3.0f * amaj) ? 4 : 3);
         const int lgA = xmaj ? lgM : 6 - lgM;
         const int A = 1 << lgA, B = 64 >> lgA;
-        const bool sxp = __ballot(o0 >= 0.0f) != 0ull, syp = __ballot(o1 >= 0.0f) != 0ull;
+        const bool sxp = wave_any(o0 >= 0.0f), syp = wave_any(o1 >= 0.0f);
         const float fi = (float)(lane & (A - 1)) * Wx, fj = (float)(lane >> lgA) * Wy;
         const float qa = o0 * o0 + o1 * o1;
         const float iqa = r_div(1.0f, qa), qar2 = qa * r2;
@@ -2328,12 +2342,13 @@ __device__ void lattice_walk(const DevTab& T, const Hot<float>& H, const Tabs<fl
         const float dd = (-qb - r_sqrt(disc > 0.0f ? disc : 0.0f)) * iqa;
         const float d = dd > 0.0f ? dd : 0.0f;
         const bool met = (qb < 0.0f) & (disc >= 0.0f) & (d <= D);
+        const float rxl = dX + d * o0, ryl = dY + d * o1;   // the entry point relative to the pore
         // the first pore met is the nearest entry: a pore lies inside its cell and the cells the
         // ray passes form a staircase in its direction, so every pore it meets before leaving the
         // window is in the window
-        const float dh = dpp_min_all(met ? d : INFINITY);
-        const unsigned long long bal = __ballot(met & (d == dh));
-        if (bal == 0ull) {
+        const float dm = met ? d : INFINITY;
+        const float dh = dpp_min_nonneg(dm);          // +inf: no pore met (a met entry is <= D)
+        if (__float_as_uint(dh) == 0x7f800000u) {
             // no pore met in the window: the free path ends in it, or the walk moves on to the
             // window's far edge (the cell boundaries crossed counted per axis, the particle placed
             // on the partner face of the edge it leaves through, as after a transfer)
@@ -2341,9 +2356,9 @@ __device__ void lattice_walk(const DevTab& T, const Hot<float>& H, const Tabs<fl
             const float gy = syp ? (float)B * Wy - x1 : x1 + (float)(B - 1) * Wy;
             const float sxe = ax > 0.0f ? r_div(gx, ax) : INFINITY;
             const float sye = ay > 0.0f ? r_div(gy, ay) : INFINITY;
-            const bool ex = __ballot(sxe <= sye) != 0ull;
+            const bool ex = wave_any(sxe <= sye);
             const float s = ex ? sxe : sye;
-            if (__ballot(D > s) == 0ull) break;   // the free path ends first
+            if (!wave_any(D > s)) break;   // the free path ends first
             const float X = x0 + s * o0, Y = x1 + s * o1;
             const float kx = ex ? 0.0f : floorf(X * iWx), ky = ex ? floorf(Y * iWy) : 0.0f;
             float z = x2 + s * o2, kz = 0.0f;
@@ -2359,13 +2374,11 @@ __device__ void lattice_walk(const DevTab& T, const Hot<float>& H, const Tabs<fl
             np += nx;
             continue;
         }
-        // the hit: the winning lane's cell (the lowest lane among equal entries) and its offsets,
-        // recomputed as that lane computed them; the cells crossed on the way
-        const int wl = __ffsll((long long)bal) - 1;
+        // the hit: the winning lane's cell (the lowest lane among equal entries) and its entry
+        // point; the cells crossed on the way
+        const int wl = __ffsll((long long)__builtin_amdgcn_ballot_w64(dm == dh)) - 1;
         const int wi = wl & (A - 1), wj = wl >> lgA;
-        const float wfi = (float)wi * Wx, wfj = (float)wj * Wy;
-        const float rx = (x0 - ((sxp ? wfi : -wfi) + cx)) + dh * o0;
-        const float ry = (x1 - ((syp ? wfj : -wfj) + cy)) + dh * o1;
+        const float rx = lane_f(rxl, wl), ry = lane_f(ryl, wl);
         float z = x2 + dh * o2, kz = 0.0f;
         if (zper) kz = floorf(z * iWz);
         const uint32_t nx = (uint32_t)wi + (uint32_t)wj + (uint32_t)fabsf(kz);
