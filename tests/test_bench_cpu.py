@@ -73,3 +73,23 @@ def test_snapshot_count_only_where_it_is_fixed():
                                        "diffuse": 0, "rejections": 0}, {"n_modes": 1400, "n_sources": 100},
                                       w["geometry"], 2, True, snapshots=2000, binned_axes=1)
     assert more - base == 2000 * (bench.OPS["snapshot_axis"] + 2 * bench.OPS["tally_comp"])
+
+
+def test_lone_walker_is_one_long_walk_through_the_pore_lattice():
+    """The lone-walker workload: one phonon of the pore cell whose free path (10 cm) spans ~1e5
+    pore reflections, in the geometry the pore-lattice walk takes (periodic in x and y, one pore,
+    no line walls), traced by the oracle on the CPU: a single relaxation ends it, and its pore
+    reflections and periodic transfers number in the tens of thousands."""
+    import bench
+    import oracle
+    w, name = bench.workload("lone_walker")
+    assert w["problem"]["N"] == 1 and w["problem"]["n_scat_max"] == 1
+    assert bench.is_pore_lattice(w)
+    assert "Lambda10cm" in name
+    lam = float(w["modes"]["v"][0] * w["modes"]["tau"][0])
+    assert abs(lam - 0.1) < 1e-12
+    c = oracle.trace(w)["counts"]
+    particles, flights, relax, spec, diffuse, periodic = (int(x) for x in c[:6])
+    assert particles == 1 and relax == 1 and spec == 0
+    assert diffuse > 10_000 and periodic > diffuse
+    assert flights == diffuse + periodic + relax
